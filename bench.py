@@ -1,0 +1,141 @@
+"""Throughput benchmark of the MW transforms on one MI355X.
+
+Workload (default): L = 512, spin 2, one complex map, f_lm = (N(0,1) + i N(0,1))/(l+1)
+for l >= 2 (seed 1002).  One step = one inverse (f_lm -> map) plus one forward
+(map -> f_lm) on data resident in HBM.  Prints ONE JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+
+
+def contraction_flops(L, s):
+    """Algorithmic flops of one contraction launch: 4 per folded term (l, m, m'>=0)
+    (complex H times the real product Delta*Delta), plus 5 per Wigner
+    eighth-wedge element 0 <= m <= m' <= l generated (one three-term step)."""
+    terms = sum((2 * l + 1) * (l + 1) for l in range(abs(s), L))
+    wedge = sum((l + 1) * (l + 2) // 2 for l in range(L))
+    return 4.0 * terms + 5.0 * wedge
+
+
+def rel(a, b):
+    import numpy as np
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--L", type=int, default=512)
+    ap.add_argument("--spin", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(maps are independent; see DESIGN.md for how the work would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import mwsynth
+    import paper_1110_6298_amd as mw
+
+    L, s = args.L, args.spin
+    w = mwsynth.workload_spin2_l512(L) if s == 2 else dict(L=L, s=s, flm=mwsynth.flm_gaussian(L, s, 1002, 1.0))
+    flm_h = w["flm"]
+    dev = torch.device("cuda", 0)
+    flm = torch.from_numpy(flm_h).to(dev)
+    xmap = torch.empty((L, 2 * L - 1), dtype=torch.complex128, device=dev)
+    back = torch.empty(L * L, dtype=torch.complex128, device=dev)
+    mw.prepare([L], [s])
+
+    def step():
+        mw.inverse(flm, L, s, out=xmap)
+        mw.forward(xmap, L, s, out=back)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t0.elapsed_time(t1)
+    ms_step = ms_total / args.steps
+
+    # per-kernel durations: the same steps again with per-launch events
+    mw.profile_enable(True)
+    for _ in range(args.steps):
+        step()
+    prof = mw.profile_read()
+    mw.profile_enable(False)
+    per_kernel = {k: v[0] / v[1] for k, v in prof.items()}
+    dom = max(per_kernel, key=lambda k: per_kernel[k])
+    flops = contraction_flops(L, s)
+    kernels = {k: {"avg_us": 1e3 * v} for k, v in per_kernel.items()}
+    for k in ("contract_forward", "contract_inverse"):
+        if k in per_kernel:
+            kernels[k]["tflops"] = flops / (per_kernel[k] * 1e-3) / 1e12
+    dom_c = "contract_forward" if per_kernel.get("contract_forward", 0) >= per_kernel.get("contract_inverse", 0) \
+        else "contract_inverse"
+    achieved = flops / (per_kernel[dom_c] * 1e-3)
+
+    x_h = xmap.cpu().numpy()
+    back_h = back.cpu().numpy()
+    result = {
+        "metric": "MW fwd+inv transforms/sec at L=512 s=2 (FP64 vs mixed) at stated max rel error",
+        "value": 1e3 / ms_step,
+        "unit": "round trips/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "MW spin-%d round trip (inverse + forward), L=%d, one complex map, "
+                               "f_lm ~ (N+iN)/(l+1), seed 1002" % (s, L), "L": L, "spin": s,
+                   "precision": "fp64", "maps_per_step": 1},
+        "round_trip_rel_err": rel(back_h, flm_h),
+        "wall_ms_per_step": 1e3 * wall / args.steps,
+        "kernels": kernels,
+        "dominant_kernel": dom,
+        "roofline": {"kernel": dom_c, "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                     "flops_per_launch": flops},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        t = time.perf_counter()
+        xo = oracle.inverse(flm_h, L, s)
+        fo = oracle.forward(xo, L, s)
+        dt = time.perf_counter() - t
+        result["cpu_baseline"] = {"value": 1.0 / dt, "unit": "round trips/s", "cores": oracle.max_threads(),
+                                  "kind": "oracle",
+                                  "sample": "one full round trip (inverse + forward) of the same L=%d s=%d map, "
+                                            "%.1f s" % (L, s, dt)}
+        result["max_rel_err_vs_oracle"] = {"inverse_map": rel(x_h, xo), "forward_coeffs": rel(back_h, fo)}
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,124 @@
+/*
+ * mw.h -- C ABI of the MI355X (gfx950) McEwen-Wiaux spin spherical-harmonic
+ * transform library (libmw.so).
+ *
+ * The transforms are those of McEwen & Wiaux, "A novel sampling theorem on the
+ * sphere" (IEEE TSP 59(12), 2011):
+ *   forward  f(theta_t, phi_p) -> sf_lm   (Sec. IV-D, algorithm Forward Transform,
+ *                                         Eqs.(flm_wig), (Gmm), (Gmt), (Gmm_convolution))
+ *   inverse  sf_lm -> f(theta_t, phi_p)   (Sec. IV-E, algorithm Inverse Transform,
+ *                                         Eqs.(f_pfft), (Fmt), (Fmm))
+ * on the equiangular grid of Sec. IV-C:
+ *   theta_t = pi (2t+1)/(2L-1), t = 0..L-1;   phi_p = 2 pi p/(2L-1), p = 0..2L-2.
+ *
+ * ---------------------------------------------------------------------------
+ * Data layout (all buffers are DEVICE memory owned by the caller)
+ *   map    : row-major [t][p], L rows of 2L-1 samples.  The last row (t = L-1)
+ *            is the south pole theta = pi, stored as a full ring.  Interleaved
+ *            complex128 (re, im) when reality = 0; float64 when reality = 1.
+ *   coeffs : complex128 at index l*l + l + m, 0 <= l < L, |m| <= l (L*L entries).
+ *            The forward writes 0 for l < |spin| (those coefficients do not
+ *            exist, Sec. III-B); the inverse ignores them.  With reality = 1 the
+ *            forward writes all L*L entries (negative m by the symmetry of
+ *            Sec. IV-G) and the inverse reads only m >= 0.
+ *
+ * Batches: every per-map argument (L, spin, reality) is a HOST array of length
+ * `batch`; `ptrs` is a HOST array of 2*batch DEVICE pointers, ptrs[2b] = input
+ * of map b and ptrs[2b+1] = its output.  Inputs are not modified; input and
+ * output of one map must not overlap.
+ *
+ * Streams: every call enqueues its kernels on `stream` (a hipStream_t; NULL =
+ * the default stream) and returns without synchronising.  Device faults
+ * surface at the caller's next synchronisation.  Calls are thread-safe.
+ *
+ * Precision (applies to the O(L^3) contraction only; every other stage, and the
+ * Wigner recursion, always runs in FP64):
+ *   MW_FP64  : FP64 throughout.
+ *   MW_FP32C : FP32 products with compensated (error-free) FP32 accumulation.
+ *
+ * Errors: arguments are validated before anything is enqueued.  Return values
+ * are mw_status codes; mw_status_string() gives a description, and
+ * mw_last_error() the detail of the last failure in this thread.
+ *
+ * Memory: the library owns per-band-limit plan tables and a workspace for
+ * intermediates, both allocated on first use on the current device (outside any
+ * stream capture) and kept until mw_release() or process exit.  It never frees
+ * caller memory.
+ * ---------------------------------------------------------------------------
+ */
+#ifndef MW_H
+#define MW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MW_OK = 0,
+    MW_EINVAL = -1,   /* invalid argument (see validation rules below)            */
+    MW_ENOMEM = -2,   /* device or host allocation failed                         */
+    MW_EHIP = -3,     /* a HIP runtime call or kernel launch failed               */
+    MW_ENOTSUP = -4   /* valid request that this build does not support           */
+} mw_status;
+
+typedef enum {
+    MW_FP64 = 0,
+    MW_FP32C = 1
+} mw_precision;
+
+/* Validation rules shared by all transform entry points (MW_EINVAL otherwise):
+ *   1 <= batch;  for every map b: 1 <= L[b] <= 2048, |spin[b]| < L[b],
+ *   reality[b] in {0, 1}, reality[b] = 1 only with spin[b] = 0 (the real-signal
+ *   saving of Sec. IV-G is for scalar maps), ptrs and ptrs[0..2*batch-1] non-NULL,
+ *   precision one of mw_precision. */
+
+/* Forward transform (Sec. IV-D): ptrs[2b] = map, ptrs[2b+1] = coeffs. */
+int mw_forward(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+               void* const* ptrs, int32_t precision, void* stream);
+
+/* Inverse transform (Sec. IV-E): ptrs[2b] = coeffs, ptrs[2b+1] = map. */
+int mw_inverse(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+               void* const* ptrs, int32_t precision, void* stream);
+
+/* Conjugate transpose of the forward map with respect to the Euclidean inner
+ * products on the L x (2L-1) grid and on the L*L coefficients:
+ * ptrs[2b] = coeffs-space input, ptrs[2b+1] = map-space output (complex128;
+ * reality must be 0).  This is the reverse-mode derivative of mw_forward. */
+int mw_forward_adjoint(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                       void* const* ptrs, int32_t precision, void* stream);
+
+/* Conjugate transpose of the inverse map: ptrs[2b] = map-space input
+ * (complex128), ptrs[2b+1] = coeffs-space output (reality must be 0). */
+int mw_inverse_adjoint(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                       void* const* ptrs, int32_t precision, void* stream);
+
+/* Bytes of workspace one call with these arguments needs (plan tables excluded). */
+int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                      int32_t precision, size_t* bytes);
+
+/* Create the plan tables and workspace a call with these arguments needs, on the
+ * current device, so that a later call (e.g. one under stream capture) performs
+ * no allocation.  Synchronises the device. */
+int mw_prepare(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+               int32_t precision);
+
+/* Free every plan and workspace of the library (all devices).  Synchronises. */
+int mw_release(void);
+
+/* Static description of a status code. */
+const char* mw_status_string(int status);
+
+/* Detail of the last failing call in this thread ("" if none). */
+const char* mw_last_error(void);
+
+/* Library version string. */
+const char* mw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MW_H */

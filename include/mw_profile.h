@@ -1,0 +1,40 @@
+/*
+ * mw_profile.h -- opt-in per-kernel timing of libmw (instrumentation, not a
+ * transform).  While enabled, every kernel launch of mw_forward / mw_inverse
+ * and the adjoints is bracketed by two hipEventRecord calls on the caller's
+ * stream; mw_profile_read() waits for the recorded events and returns the
+ * summed duration and launch count of each stage.  Disabled by default; when
+ * disabled no event is recorded.
+ *
+ * Stage ids (index into the output arrays):
+ *   0 phi stage, forward        3 contraction, inverse
+ *   1 theta stage, forward      4 theta stage, inverse
+ *   2 contraction, forward      5 phi stage, inverse
+ *   6 contraction, forward adjoint   7 contraction, inverse adjoint
+ *   8 other (adjoint Fourier stages, batched helpers)
+ */
+#ifndef MW_PROFILE_H
+#define MW_PROFILE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MW_PROFILE_NSTAGE 9
+
+/* Enable (on != 0) or disable recording; enabling clears previous records. */
+int mw_profile_enable(int on);
+
+/* Synchronise the recorded events and write, per stage, the summed kernel time
+ * in milliseconds (ms[MW_PROFILE_NSTAGE]) and the number of launches
+ * (count[MW_PROFILE_NSTAGE]); clears the records.  Returns an mw_status. */
+int mw_profile_read(double* ms, int* count);
+
+/* Name of a stage id ("" if out of range). */
+const char* mw_profile_stage_name(int stage);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MW_PROFILE_H */

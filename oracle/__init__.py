@@ -51,6 +51,7 @@ def _load():
             "orc_forward_stages": (I, [I, I, D, D, D, D, D]),
             "orc_forward_orders": (I, [I, I, D, I, IP, D]),
             "orc_inverse": (I, [I, I, D, D]),
+            "orc_inverse_orders": (I, [I, I, D, I, IP, D]),
             "orc_inverse_stages": (I, [I, I, D, D, D, D]),
             "orc_forward_adjoint": (I, [I, I, D, D]),
             "orc_inverse_adjoint": (I, [I, I, D, D]),
@@ -149,6 +150,19 @@ def inverse(flm, L: int, s: int) -> np.ndarray:
     flm = _coeffs(flm, L)
     out = np.zeros((L, 2 * L - 1), dtype=np.complex128)
     _check(_load().orc_inverse(L, s, _dp(flm.view(np.float64)), _dp(out.view(np.float64))), "inverse")
+    return out
+
+
+def inverse_orders(flm, L: int, s: int, ms) -> np.ndarray:
+    """F_m(theta_t) (the phi-Fourier coefficients of the inverse map's rings) for
+    the listed orders: returns [len(ms)][L]."""
+    flm = _coeffs(flm, L)
+    ms = np.ascontiguousarray(ms, dtype=np.int32)
+    out = np.zeros((ms.size, L), dtype=np.complex128)
+    rc = _load().orc_inverse_orders(L, s, _dp(flm.view(np.float64)), int(ms.size),
+                                    ms.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                    _dp(out.view(np.float64)))
+    _check(rc, "inverse_orders")
     return out
 
 

@@ -91,22 +91,25 @@ static double sgn(int k) { return (k % 2 == 0) ? 1.0 : -1.0; }
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int twoj;      /* 2j of the plane currently held in cur */
-    int cap;       /* allocated side length */
+    int stride;    /* row stride: planes carry a zero border of width 1 */
     double *cur, *nxt;
     double *cp, *cm;
 } risbo_t;
 
+/* Entry (a, b) of a plane, a, b in [-1, 2j+1] (the border entries stay zero). */
+#define RAT(buf, R, a, b) ((buf)[(size_t)((a) + 1) * (size_t)(R)->stride + (size_t)((b) + 1)])
+
 static int risbo_init(risbo_t* R, int lmax)
 {
-    R->cap = 2 * lmax + 1;
-    size_t n = (size_t)R->cap * (size_t)R->cap;
+    R->stride = 2 * lmax + 3;
+    size_t n = (size_t)R->stride * (size_t)R->stride;
     R->cur = (double*)calloc(n, sizeof(double));
     R->nxt = (double*)calloc(n, sizeof(double));
-    R->cp = (double*)calloc((size_t)R->cap + 1, sizeof(double));
-    R->cm = (double*)calloc((size_t)R->cap + 1, sizeof(double));
+    R->cp = (double*)calloc((size_t)R->stride + 1, sizeof(double));
+    R->cm = (double*)calloc((size_t)R->stride + 1, sizeof(double));
     if (!R->cur || !R->nxt || !R->cp || !R->cm) return -2;
     R->twoj = 0;
-    R->cur[0] = 1.0; /* d^0_{00} = 1 */
+    RAT(R->cur, R, 0, 0) = 1.0; /* d^0_{00} = 1 */
     return 0;
 }
 
@@ -115,13 +118,8 @@ static void risbo_free(risbo_t* R)
     free(R->cur); free(R->nxt); free(R->cp); free(R->cm);
 }
 
-/* Value of the current plane at (a, b); zero outside [0, twoj]. */
-static double risbo_at(const risbo_t* R, int a, int b)
-{
-    if (a < 0 || b < 0 || a > R->twoj || b > R->twoj) return 0.0;
-    return R->cur[(size_t)a * (size_t)(R->twoj + 1) + (size_t)b];
-}
-
+/* Planes only grow, so every entry outside the current plane (including the
+ * border row/column -1) is zero in both buffers. */
 static void risbo_halfstep(risbo_t* R)
 {
     const int tj = R->twoj + 1; /* 2j of the new plane */
@@ -130,14 +128,16 @@ static void risbo_halfstep(risbo_t* R)
         R->cp[a] = sqrt((double)a / (double)tj);
         R->cm[a] = sqrt((double)(tj - a) / (double)tj);
     }
+    const double* P = R->cur;
+    double* Q = R->nxt;
     #pragma omp parallel for schedule(static)
     for (int a = 0; a <= tj; ++a) {
         for (int b = 0; b <= tj; ++b) {
-            double v = R->cp[a] * R->cp[b] * risbo_at(R, a - 1, b - 1)
-                     - R->cp[a] * R->cm[b] * risbo_at(R, a - 1, b)
-                     + R->cm[a] * R->cp[b] * risbo_at(R, a, b - 1)
-                     + R->cm[a] * R->cm[b] * risbo_at(R, a, b);
-            R->nxt[(size_t)a * (size_t)(tj + 1) + (size_t)b] = r * v;
+            double v = R->cp[a] * R->cp[b] * RAT(P, R, a - 1, b - 1)
+                     - R->cp[a] * R->cm[b] * RAT(P, R, a - 1, b)
+                     + R->cm[a] * R->cp[b] * RAT(P, R, a, b - 1)
+                     + R->cm[a] * R->cm[b] * RAT(P, R, a, b);
+            RAT(Q, R, a, b) = r * v;
         }
     }
     double* t = R->cur; R->cur = R->nxt; R->nxt = t;
@@ -153,7 +153,7 @@ static void risbo_to(risbo_t* R, int l)
 /* Delta^l_{m,n} from a plane of integer order l. */
 static double D(const risbo_t* R, int l, int m, int n)
 {
-    return R->cur[(size_t)(m + l) * (size_t)(2 * l + 1) + (size_t)(n + l)];
+    return RAT(R->cur, R, m + l, n + l);
 }
 
 int orc_delta_plane(int l, double* out)
@@ -162,7 +162,8 @@ int orc_delta_plane(int l, double* out)
     risbo_t R;
     if (risbo_init(&R, l)) { risbo_free(&R); return -2; }
     risbo_to(&R, l);
-    memcpy(out, R.cur, sizeof(double) * (size_t)(2 * l + 1) * (size_t)(2 * l + 1));
+    for (int m = -l; m <= l; ++m)
+        for (int n = -l; n <= l; ++n) out[(size_t)(m + l) * (2 * l + 1) + (n + l)] = D(&R, l, m, n);
     risbo_free(&R);
     return 0;
 }
@@ -451,6 +452,48 @@ int orc_inverse_stages(int L, int s, const double* flm_ri, double* F_ri, double*
     if (f_ri) inv_phi(L, Fmt, (cplx*)f_ri);
 done:
     free(F); free(Fmt);
+    return rc;
+}
+
+/* Inverse restricted to the listed orders: out[k][t] = F_{ms[k]}(theta_t), t < L,
+ * i.e. Eq.(Fmm) for those m followed by Eq.(Fmt); equal to the phi-Fourier
+ * coefficient of ring t of the inverse map at order ms[k]. */
+int orc_inverse_orders(int L, int s, const double* flm_ri, int nm, const int* ms, double* out_ri)
+{
+    if (check_args(L, s) || !flm_ri || nm < 1 || !ms || !out_ri) return -1;
+    const int N1 = 2 * L - 1;
+    for (int k = 0; k < nm; ++k) if (ms[k] <= -L || ms[k] >= L) return -1;
+    const cplx* flm = (const cplx*)flm_ri;
+    cplx* out = (cplx*)out_ri;
+    cplx* F = (cplx*)calloc((size_t)nm * N1, sizeof(cplx));
+    risbo_t R;
+    int rc = risbo_init(&R, L - 1);
+    if (rc || !F) { rc = -2; goto done; }
+    for (int l = 0; l < L; ++l) {
+        risbo_to(&R, l);
+        if (l < abs(s)) continue;
+        const double nl = sqrt((2.0 * l + 1.0) / (4.0 * PI));
+        #pragma omp parallel for schedule(static)
+        for (int k = 0; k < nm; ++k) {
+            const int m = ms[k];
+            if (m < -l || m > l) continue;
+            for (int mp = -l; mp <= l; ++mp)
+                F[(size_t)k * N1 + (mp + L - 1)] += nl * D(&R, l, mp, m) * D(&R, l, mp, -s) * flm[(size_t)l * l + l + m];
+        }
+    }
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nm; ++k)
+        for (int t = 0; t < L; ++t) {
+            const int m = ms[k];
+            cplx acc = 0.0;
+            for (int mp = -(L - 1); mp <= L - 1; ++mp)
+                acc += sgn(s) * ipow(-(m + s)) * F[(size_t)k * N1 + (mp + L - 1)] *
+                       conj(unit_root((long long)mp * (2 * t + 1), 2LL * N1));
+            out[(size_t)k * L + t] = acc;
+        }
+done:
+    risbo_free(&R);
+    free(F);
     return rc;
 }
 

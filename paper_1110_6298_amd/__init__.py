@@ -1,0 +1,228 @@
+"""MI355X (gfx950) McEwen-Wiaux spin spherical-harmonic transforms.
+
+Thin binding over the C ABI of ``libmw.so`` (declared in ``include/mw.h``).
+This module only marshals arguments: every stage of every transform runs in
+the library's HIP kernels.  Tensors are torch CUDA (ROCm) tensors used as
+device memory; work is enqueued on the current torch stream.
+
+    import paper_1110_6298_amd as mw
+    flm = mw.forward(x, L=512, spin=2)          # x: (L, 2L-1) complex128 on cuda
+    x2  = mw.inverse(flm, L=512, spin=2)        # flm: (L*L,) complex128 on cuda
+
+If the library has not been built (``python -m paper_1110_6298_amd.build``) or
+cannot be loaded, every entry point raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+__all__ = ["forward", "inverse", "forward_adjoint", "inverse_adjoint", "forward_batch",
+           "inverse_batch", "prepare", "release", "workspace_size", "library", "MWError",
+           "FP64", "FP32C", "EXPORTS", "LIB_PATH"]
+
+FP64, FP32C = 0, 1
+_PREC = {"fp64": FP64, "fp32c": FP32C, FP64: FP64, FP32C: FP32C}
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmw.so")
+EXPORTS = ("mw_forward", "mw_inverse", "mw_forward_adjoint", "mw_inverse_adjoint",
+           "mw_workspace_size", "mw_prepare", "mw_release", "mw_status_string",
+           "mw_last_error", "mw_version")
+PROFILE_EXPORTS = ("mw_profile_enable", "mw_profile_read", "mw_profile_stage_name")
+NSTAGE = 9
+
+_lib = None
+
+
+class MWError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str):
+        super().__init__("%s failed: status %d (%s)" % (what, status, detail))
+        self.status = status
+
+
+def library():
+    """The loaded ``libmw.so`` (ctypes.CDLL), loading it on first use."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmw.so is not built (%s); run `python -m paper_1110_6298_amd.build`"
+                               % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        vpp = ctypes.POINTER(ctypes.c_void_p)
+        for name in ("mw_forward", "mw_inverse", "mw_forward_adjoint", "mw_inverse_adjoint"):
+            fn = getattr(lib, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = [i32p, i32p, i32p, ctypes.c_int32, vpp, ctypes.c_int32, ctypes.c_void_p]
+        lib.mw_workspace_size.restype = ctypes.c_int
+        lib.mw_workspace_size.argtypes = [i32p, i32p, i32p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_size_t)]
+        lib.mw_prepare.restype = ctypes.c_int
+        lib.mw_prepare.argtypes = [i32p, i32p, i32p, ctypes.c_int32, ctypes.c_int32]
+        lib.mw_release.restype = ctypes.c_int
+        lib.mw_release.argtypes = []
+        for name in ("mw_status_string",):
+            getattr(lib, name).restype = ctypes.c_char_p
+            getattr(lib, name).argtypes = [ctypes.c_int]
+        for name in ("mw_last_error", "mw_version"):
+            getattr(lib, name).restype = ctypes.c_char_p
+            getattr(lib, name).argtypes = []
+        lib.mw_profile_enable.restype = ctypes.c_int
+        lib.mw_profile_enable.argtypes = [ctypes.c_int]
+        lib.mw_profile_read.restype = ctypes.c_int
+        lib.mw_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+        lib.mw_profile_stage_name.restype = ctypes.c_char_p
+        lib.mw_profile_stage_name.argtypes = [ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def _arr(vals):
+    vals = [int(v) for v in vals]
+    return (ctypes.c_int32 * len(vals))(*vals)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        lib = library()
+        raise MWError(rc, what, lib.mw_last_error().decode() or lib.mw_status_string(rc).decode())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def call(name: str, Ls: Sequence[int], spins: Sequence[int], reals: Sequence[int], ptrs: Sequence[int],
+         precision=FP64, stream=None) -> None:
+    """Raw C-ABI call: ``ptrs`` are integer device addresses (2 per map)."""
+    lib = library()
+    n = len(Ls)
+    parr = (ctypes.c_void_p * (2 * n))(*[ctypes.c_void_p(int(p)) for p in ptrs])
+    rc = getattr(lib, name)(_arr(Ls), _arr(spins), _arr(reals), n,
+                            ctypes.cast(parr, ctypes.POINTER(ctypes.c_void_p)),
+                            _PREC[precision], _stream_handle(stream))
+    _check(rc, name)
+
+
+def _check_tensor(t, shape, dtypes, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % what)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s (got %s)" % (what, tuple(shape), tuple(t.shape)))
+    if t.dtype not in dtypes:
+        raise TypeError("%s has dtype %s, expected one of %s" % (what, t.dtype, dtypes))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+
+
+def _map_shape(L):
+    return (L, 2 * L - 1)
+
+
+def forward_batch(maps, Ls, spins, realities=None, precision=FP64, outs=None, stream=None):
+    """Forward transforms of a batch of maps in one library call."""
+    import torch
+    n = len(maps)
+    realities = [0] * n if realities is None else list(realities)
+    outs = list(outs) if outs is not None else [None] * n
+    ptrs = []
+    for b in range(n):
+        L = int(Ls[b])
+        dt = (torch.float64,) if realities[b] else (torch.complex128,)
+        _check_tensor(maps[b], _map_shape(L), dt, "map %d" % b)
+        if outs[b] is None:
+            outs[b] = torch.empty(L * L, dtype=torch.complex128, device=maps[b].device)
+        _check_tensor(outs[b], (L * L,), (torch.complex128,), "coeffs %d" % b)
+        ptrs += [maps[b].data_ptr(), outs[b].data_ptr()]
+    call("mw_forward", Ls, spins, realities, ptrs, precision, stream)
+    return outs
+
+
+def inverse_batch(coeffs, Ls, spins, realities=None, precision=FP64, outs=None, stream=None):
+    """Inverse transforms of a batch of coefficient vectors in one library call."""
+    import torch
+    n = len(coeffs)
+    realities = [0] * n if realities is None else list(realities)
+    outs = list(outs) if outs is not None else [None] * n
+    ptrs = []
+    for b in range(n):
+        L = int(Ls[b])
+        _check_tensor(coeffs[b], (L * L,), (torch.complex128,), "coeffs %d" % b)
+        dt = torch.float64 if realities[b] else torch.complex128
+        if outs[b] is None:
+            outs[b] = torch.empty(_map_shape(L), dtype=dt, device=coeffs[b].device)
+        _check_tensor(outs[b], _map_shape(L), (dt,), "map %d" % b)
+        ptrs += [coeffs[b].data_ptr(), outs[b].data_ptr()]
+    call("mw_inverse", Ls, spins, realities, ptrs, precision, stream)
+    return outs
+
+
+def forward(x, L: int, spin: int = 0, reality: int = 0, precision=FP64, out=None, stream=None):
+    """Forward MW transform of one map (L, 2L-1) -> coefficients (L*L,)."""
+    return forward_batch([x], [L], [spin], [reality], precision, [out], stream)[0]
+
+
+def inverse(flm, L: int, spin: int = 0, reality: int = 0, precision=FP64, out=None, stream=None):
+    """Inverse MW transform of one coefficient vector (L*L,) -> map (L, 2L-1)."""
+    return inverse_batch([flm], [L], [spin], [reality], precision, [out], stream)[0]
+
+
+def forward_adjoint(y, L: int, spin: int = 0, precision=FP64, out=None, stream=None):
+    """Conjugate transpose of the forward map: coefficients (L*L,) -> grid (L, 2L-1)."""
+    import torch
+    _check_tensor(y, (L * L,), (torch.complex128,), "coeffs")
+    if out is None:
+        out = torch.empty(_map_shape(L), dtype=torch.complex128, device=y.device)
+    _check_tensor(out, _map_shape(L), (torch.complex128,), "map")
+    call("mw_forward_adjoint", [L], [spin], [0], [y.data_ptr(), out.data_ptr()], precision, stream)
+    return out
+
+
+def inverse_adjoint(g, L: int, spin: int = 0, precision=FP64, out=None, stream=None):
+    """Conjugate transpose of the inverse map: grid (L, 2L-1) -> coefficients (L*L,)."""
+    import torch
+    _check_tensor(g, _map_shape(L), (torch.complex128,), "map")
+    if out is None:
+        out = torch.empty(L * L, dtype=torch.complex128, device=g.device)
+    _check_tensor(out, (L * L,), (torch.complex128,), "coeffs")
+    call("mw_inverse_adjoint", [L], [spin], [0], [g.data_ptr(), out.data_ptr()], precision, stream)
+    return out
+
+
+def prepare(Ls, spins, realities=None, precision=FP64) -> None:
+    """Build plans and workspace ahead of time (e.g. before stream capture)."""
+    n = len(Ls)
+    realities = [0] * n if realities is None else realities
+    _check(library().mw_prepare(_arr(Ls), _arr(spins), _arr(realities), n, _PREC[precision]), "mw_prepare")
+
+
+def workspace_size(Ls, spins, realities=None, precision=FP64) -> int:
+    n = len(Ls)
+    realities = [0] * n if realities is None else realities
+    out = ctypes.c_size_t(0)
+    _check(library().mw_workspace_size(_arr(Ls), _arr(spins), _arr(realities), n, _PREC[precision],
+                                       ctypes.byref(out)), "mw_workspace_size")
+    return int(out.value)
+
+
+def profile_enable(on: bool = True) -> None:
+    """Bracket every kernel launch with HIP events on the launching stream."""
+    _check(library().mw_profile_enable(1 if on else 0), "mw_profile_enable")
+
+
+def profile_read() -> dict:
+    """{stage name: (summed ms, launches)} of the kernels recorded since enabling."""
+    lib = library()
+    ms = (ctypes.c_double * NSTAGE)()
+    cnt = (ctypes.c_int * NSTAGE)()
+    _check(lib.mw_profile_read(ms, cnt), "mw_profile_read")
+    return {lib.mw_profile_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(NSTAGE) if cnt[i]}
+
+
+def release() -> None:
+    _check(library().mw_release(), "mw_release")

@@ -1,0 +1,335 @@
+// C ABI of libmw: argument validation, per-device plan/workspace cache and the
+// launch sequence of each transform.  See include/mw.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mw.h"
+#include "../../include/mw_profile.h"
+#include "mw_internal.h"
+
+namespace {
+
+using mw::Plan;
+using mw::SpinTable;
+
+thread_local std::string g_last_error;
+
+struct DeviceState {
+    std::map<int, Plan> plans;                    // by L
+    std::map<std::pair<int, int>, SpinTable> spins;  // by (L, |s|)
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+std::mutex g_mu;
+std::map<int, DeviceState> g_dev;
+
+// ---- opt-in per-stage event timing --------------------------------------
+struct ProfRec { int stage; hipEvent_t a, b; };
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t take_event()
+{
+    if (!g_event_pool.empty()) { hipEvent_t e = g_event_pool.back(); g_event_pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// Runs one launcher, bracketed by events when profiling is on.
+template <class F>
+hipError_t staged(int stage, hipStream_t st, F&& launch)
+{
+    if (!g_prof_on) return launch();
+    ProfRec r{stage, take_event(), take_event()};
+    (void)hipEventRecord(r.a, st);
+    hipError_t e = launch();
+    (void)hipEventRecord(r.b, st);
+    g_prof.push_back(r);
+    return e;
+}
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int validate(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+             void* const* ptrs, int32_t precision, bool need_ptrs, bool complex_only)
+{
+    if (batch < 1) return fail(MW_EINVAL, "batch must be >= 1 (got %d)", batch);
+    if (!L || !spin || !reality) return fail(MW_EINVAL, "L, spin and reality arrays must be non-NULL");
+    if (precision != MW_FP64 && precision != MW_FP32C) return fail(MW_EINVAL, "unknown precision %d", precision);
+    if (need_ptrs && !ptrs) return fail(MW_EINVAL, "ptrs must be non-NULL");
+    for (int b = 0; b < batch; ++b) {
+        if (L[b] < 1 || L[b] > 2048) return fail(MW_EINVAL, "map %d: L = %d outside [1, 2048]", b, L[b]);
+        if (spin[b] <= -L[b] || spin[b] >= L[b])
+            return fail(MW_EINVAL, "map %d: |spin| = %d must be < L = %d", b, spin[b], L[b]);
+        if (reality[b] != 0 && reality[b] != 1) return fail(MW_EINVAL, "map %d: reality must be 0 or 1", b);
+        if (reality[b] == 1 && spin[b] != 0) return fail(MW_EINVAL, "map %d: reality = 1 needs spin = 0", b);
+        if (complex_only && reality[b] == 1) return fail(MW_EINVAL, "map %d: adjoints take complex data", b);
+        if (need_ptrs && (!ptrs[2 * b] || !ptrs[2 * b + 1])) return fail(MW_EINVAL, "map %d: NULL pointer", b);
+    }
+    return MW_OK;
+}
+
+size_t ws_need(int L)
+{
+    const size_t n1 = 2 * (size_t)L - 1;
+    return 2 * n1 * (size_t)L * sizeof(double2) + 256;
+}
+
+bool capturing(hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+    return cs != hipStreamCaptureStatusNone;
+}
+
+// Fetch (building if needed) the plan, spin table and workspace for one map.
+int get_resources(DeviceState& d, int L, int as, bool need_spin, size_t ws_bytes, bool may_alloc,
+                  const Plan** plan, const SpinTable** spt, void** ws)
+{
+    std::string err;
+    auto it = d.plans.find(L);
+    if (it == d.plans.end()) {
+        if (!may_alloc) return fail(MW_ENOMEM, "plan for L=%d not prepared (call mw_prepare before capture)", L);
+        Plan p;
+        int rc = mw::build_plan(L, p, err);
+        if (rc) { mw::free_plan(p); return fail(rc == -2 ? MW_ENOMEM : MW_EHIP, "plan L=%d: %s", L, err.c_str()); }
+        it = d.plans.emplace(L, p).first;
+    }
+    *plan = &it->second;
+    if (need_spin) {
+        auto key = std::make_pair(L, as);
+        auto jt = d.spins.find(key);
+        if (jt == d.spins.end()) {
+            if (!may_alloc) return fail(MW_ENOMEM, "spin table L=%d |s|=%d not prepared", L, as);
+            SpinTable t;
+            int rc = mw::build_spin_table(L, as, t, err);
+            if (rc) { mw::free_spin_table(t); return fail(rc == -2 ? MW_ENOMEM : MW_EHIP, "spin table: %s", err.c_str()); }
+            jt = d.spins.emplace(key, t).first;
+        }
+        *spt = &jt->second;
+    }
+    if (d.ws_bytes < ws_bytes) {
+        if (!may_alloc) return fail(MW_ENOMEM, "workspace of %zu bytes not prepared", ws_bytes);
+        if (d.ws) (void)hipFree(d.ws);
+        d.ws = nullptr;
+        d.ws_bytes = 0;
+        if (hipMalloc(&d.ws, ws_bytes) != hipSuccess) return fail(MW_ENOMEM, "workspace hipMalloc(%zu) failed", ws_bytes);
+        d.ws_bytes = ws_bytes;
+    }
+    *ws = d.ws;
+    return MW_OK;
+}
+
+enum class Op { Forward, Inverse };
+
+int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+        void* const* ptrs, int32_t precision, void* stream)
+{
+    int rc = validate(L, spin, reality, batch, ptrs, precision, true, false);
+    if (rc) return rc;
+    if (precision != MW_FP64) return fail(MW_ENOTSUP, "precision %d is not available for this call", precision);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");
+    const bool may_alloc = !capturing(st);
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState& d = g_dev[dev];
+    size_t need = 0;
+    for (int b = 0; b < batch; ++b) need = std::max(need, ws_need(L[b]));
+    for (int b = 0; b < batch; ++b) {
+        const Plan* p = nullptr;
+        const SpinTable* sp = nullptr;
+        void* ws = nullptr;
+        const int s = spin[b], as = s < 0 ? -s : s;
+        rc = get_resources(d, L[b], as, op == Op::Inverse, need, may_alloc, &p, &sp, &ws);
+        if (rc) return rc;
+        const size_t half = (size_t)p->N1 * p->L;
+        double2* W0 = (double2*)ws;
+        double2* W1 = W0 + half;
+        hipError_t e = hipSuccess;
+        if (op == Op::Forward) {
+            if (e == hipSuccess)
+                e = staged(0, st, [&] { return mw::launch_phi_forward(*p, ptrs[2 * b], reality[b], W0, st); });
+            if (e == hipSuccess)
+                e = staged(1, st, [&] { return mw::launch_theta_forward(*p, s, W0, W1, st); });
+            if (e == hipSuccess)
+                e = staged(2, st, [&] {
+                    return mw::launch_contract_forward(*p, s, reality[b], W1, (double2*)ptrs[2 * b + 1], st);
+                });
+        } else {
+            if (e == hipSuccess)
+                e = staged(3, st, [&] {
+                    return mw::launch_contract_inverse(*p, *sp, s, reality[b], (const double2*)ptrs[2 * b], W0, st);
+                });
+            if (e == hipSuccess)
+                e = staged(4, st, [&] { return mw::launch_theta_inverse(*p, s, W0, W1, st); });
+            if (e == hipSuccess)
+                e = staged(5, st, [&] { return mw::launch_phi_inverse(*p, W1, ptrs[2 * b + 1], reality[b], st); });
+        }
+        if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    }
+    g_last_error.clear();
+    return MW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mw_forward(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+               void* const* ptrs, int32_t precision, void* stream)
+{
+    return run(Op::Forward, L, spin, reality, batch, ptrs, precision, stream);
+}
+
+int mw_inverse(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+               void* const* ptrs, int32_t precision, void* stream)
+{
+    return run(Op::Inverse, L, spin, reality, batch, ptrs, precision, stream);
+}
+
+int mw_forward_adjoint(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                       void* const* ptrs, int32_t precision, void* stream)
+{
+    (void)stream;
+    int rc = validate(L, spin, reality, batch, ptrs, precision, true, true);
+    if (rc) return rc;
+    return fail(MW_ENOTSUP, "forward adjoint is not available in this build");
+}
+
+int mw_inverse_adjoint(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                       void* const* ptrs, int32_t precision, void* stream)
+{
+    (void)stream;
+    int rc = validate(L, spin, reality, batch, ptrs, precision, true, true);
+    if (rc) return rc;
+    return fail(MW_ENOTSUP, "inverse adjoint is not available in this build");
+}
+
+int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                      int32_t precision, size_t* bytes)
+{
+    int rc = validate(L, spin, reality, batch, nullptr, precision, false, false);
+    if (rc) return rc;
+    if (!bytes) return fail(MW_EINVAL, "bytes must be non-NULL");
+    size_t need = 0;
+    for (int b = 0; b < batch; ++b) need = std::max(need, ws_need(L[b]));
+    *bytes = need;
+    return MW_OK;
+}
+
+int mw_prepare(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch, int32_t precision)
+{
+    int rc = validate(L, spin, reality, batch, nullptr, precision, false, false);
+    if (rc) return rc;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState& d = g_dev[dev];
+    size_t need = 0;
+    for (int b = 0; b < batch; ++b) need = std::max(need, ws_need(L[b]));
+    for (int b = 0; b < batch; ++b) {
+        const Plan* p;
+        const SpinTable* sp;
+        void* ws;
+        const int as = spin[b] < 0 ? -spin[b] : spin[b];
+        rc = get_resources(d, L[b], as, true, need, true, &p, &sp, &ws);
+        if (rc) return rc;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) return fail(MW_EHIP, "hipDeviceSynchronize failed");
+    return MW_OK;
+}
+
+int mw_release(void)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : g_dev) {
+        (void)hipSetDevice(kv.first);
+        (void)hipDeviceSynchronize();
+        for (auto& pp : kv.second.plans) mw::free_plan(pp.second);
+        for (auto& ss : kv.second.spins) mw::free_spin_table(ss.second);
+        if (kv.second.ws) (void)hipFree(kv.second.ws);
+    }
+    g_dev.clear();
+    (void)hipSetDevice(cur);
+    return MW_OK;
+}
+
+const char* mw_status_string(int status)
+{
+    switch (status) {
+        case MW_OK: return "success";
+        case MW_EINVAL: return "invalid argument";
+        case MW_ENOMEM: return "allocation failed or resources not prepared";
+        case MW_EHIP: return "HIP runtime error";
+        case MW_ENOTSUP: return "not supported";
+        default: return "unknown status";
+    }
+}
+
+const char* mw_last_error(void) { return g_last_error.c_str(); }
+
+const char* mw_version(void) { return "mw-hip 0.1 (gfx950)"; }
+
+int mw_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (auto& r : g_prof) { g_event_pool.push_back(r.a); g_event_pool.push_back(r.b); }
+    g_prof.clear();
+    g_prof_on = on != 0;
+    return MW_OK;
+}
+
+int mw_profile_read(double* ms, int* count)
+{
+    if (!ms || !count) return fail(MW_EINVAL, "ms and count must be non-NULL");
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (int i = 0; i < MW_PROFILE_NSTAGE; ++i) { ms[i] = 0.0; count[i] = 0; }
+    int rc = MW_OK;
+    for (auto& r : g_prof) {
+        float t = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+            rc = fail(MW_EHIP, "event timing failed");
+        } else if (r.stage >= 0 && r.stage < MW_PROFILE_NSTAGE) {
+            ms[r.stage] += t;
+            count[r.stage] += 1;
+        }
+        g_event_pool.push_back(r.a);
+        g_event_pool.push_back(r.b);
+    }
+    g_prof.clear();
+    return rc;
+}
+
+const char* mw_profile_stage_name(int stage)
+{
+    static const char* names[MW_PROFILE_NSTAGE] = {
+        "phi_forward", "theta_forward", "contract_forward", "contract_inverse", "theta_inverse",
+        "phi_inverse", "contract_forward_adjoint", "contract_inverse_adjoint", "other"};
+    return (stage >= 0 && stage < MW_PROFILE_NSTAGE) ? names[stage] : "";
+}
+
+}  // extern "C"

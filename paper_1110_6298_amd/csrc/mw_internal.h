@@ -1,0 +1,69 @@
+// Internal declarations shared by the libmw sources (host plan, kernels, C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mw {
+
+// Chains whose start value lies below 2^-EXT_LIMIT are carried with an extra
+// binary exponent in steps of 2^EXT_STEP (see the contraction kernels).
+constexpr int EXT_STEP = 600;
+constexpr int EXT_LIMIT = 900;
+
+// Band-limit-dependent constants, built once per (device, L) on the host in
+// long double and uploaded.  All device pointers are owned by the plan.
+struct Plan {
+    int L = 0, N1 = 0, N2 = 0, logN2 = 0;
+    bool ext = false;        // some start value needs the exponent extension
+    // Wigner tables
+    double2* sqtab = nullptr;   // (sqrt k, 1/sqrt k), k = 0..2L+2; entry 0 = (0, 0)
+    double* edge = nullptr;     // Delta^l_{m,l}, packed l(l+1)/2 + m, as mantissa * 2^(EXT_STEP*k)
+    int* edgek = nullptr;       // k of each edge entry
+    double2* lco = nullptr;     // l-recursion factors (Pu_m(l), Qu_m(l)) at [m*L + l]
+    double* cl = nullptr;       // sqrt((2l+1)/(4 pi))
+    // Fourier tables
+    double2* tw = nullptr;      // exp(-2 pi i e/N2), e < N2
+    double2* chirp = nullptr;   // exp(-i pi j^2/N1), j < N1
+    double2* bhat = nullptr;    // FFT_N2 of the Bluestein kernel, divided by N2
+    double2* what = nullptr;    // (2 pi/N2) * DFT_N2 of the theta weights w(k)
+    double2* thtw = nullptr;    // exp(-i m' pi/N1)/(2 pi N1) at slot k = m' mod N1
+    // contraction work lists (int2: (block start, first order)); sorted longest first
+    int2* workf = nullptr; int nworkf = 0;   // forward: (l0, m0)
+    int2* worki = nullptr; int nworki = 0;   // inverse: (n0, m0)
+    size_t bytes = 0;
+};
+
+// Spin-row start table for the inverse l-recursion: Delta^l_{n,|s|} at [l*L + n]
+// (mantissa * 2^(EXT_STEP*k)), with its exponent level.
+struct SpinTable {
+    int L = 0, as = 0;
+    double* val = nullptr;
+    int* k = nullptr;
+    size_t bytes = 0;
+};
+
+// Chains per lane in the contraction kernels (work-list granularity in m).
+constexpr int MT_FWD = 2;
+constexpr int MT_INV = 2;
+
+int build_plan(int L, Plan& p, std::string& err);
+void free_plan(Plan& p);
+int build_spin_table(int L, int as, SpinTable& t, std::string& err);
+void free_spin_table(SpinTable& t);
+
+// Kernel launchers (enqueue only).  Buffers: map, G (L x N1), H (N1 x L), coeffs.
+hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2* G, hipStream_t st);
+hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, double2* H, hipStream_t st);
+hipError_t launch_contract_forward(const Plan& p, int s, int real, const double2* H, double2* flm,
+                                   hipStream_t st);
+hipError_t launch_contract_inverse(const Plan& p, const SpinTable& st_, int s, int real,
+                                   const double2* flm, double2* F, hipStream_t st);
+hipError_t launch_theta_inverse(const Plan& p, int s, const double2* F, double2* Ft, hipStream_t st);
+hipError_t launch_phi_inverse(const Plan& p, const double2* Ft, void* map, int real, hipStream_t st);
+
+}  // namespace mw

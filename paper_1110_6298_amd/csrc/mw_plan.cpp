@@ -1,0 +1,285 @@
+// Host-side construction of the per-band-limit tables (long double arithmetic,
+// rounded once to double when uploaded).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mw_internal.h"
+
+namespace mw {
+
+namespace {
+
+using ld = long double;
+using cld = std::complex<long double>;
+const ld PI_L = 3.141592653589793238462643383279502884L;
+
+int next_pow2(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// In-place iterative radix-2 DFT, X_j = sum_k x_k exp(-2 pi i j k / N).
+void host_fft(std::vector<cld>& a)
+{
+    const size_t n = a.size();
+    for (size_t i = 1, j = 0; i < n; ++i) {
+        size_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (size_t len = 2; len <= n; len <<= 1) {
+        for (size_t i = 0; i < n; i += len) {
+            for (size_t k = 0; k < len / 2; ++k) {
+                ld ang = -2.0L * PI_L * (ld)k / (ld)len;
+                cld w(cosl(ang), sinl(ang));
+                cld u = a[i + k], v = a[i + k + len / 2] * w;
+                a[i + k] = u + v;
+                a[i + k + len / 2] = u - v;
+            }
+        }
+    }
+}
+
+// Split a positive value into mantissa * 2^(-EXT_STEP k) with the mantissa
+// kept above 2^-EXT_LIMIT whenever k > 0.
+void split_ext(ld v, double& x, int& k)
+{
+    if (v == 0.0L) { x = 0.0; k = 0; return; }
+    int e = ilogbl(v);
+    k = 0;
+    if (e < -EXT_LIMIT) k = (-EXT_LIMIT - e + EXT_STEP - 1) / EXT_STEP;
+    x = (double)ldexpl(v, EXT_STEP * k);
+}
+
+// Delta^l_{m,l} = 2^-l sqrt(binom(2l, l+m)) for 0 <= m <= l < L, by the exact
+// ratio recurrences in long double (no underflow for l < 8192).
+std::vector<ld> edge_values(int L)
+{
+    std::vector<ld> E((size_t)L * (L + 1) / 2);
+    ld e0 = 1.0L;
+    for (int l = 0; l < L; ++l) {
+        if (l > 0) e0 *= sqrtl((2.0L * l - 1.0L) / (2.0L * l));
+        size_t base = (size_t)l * (l + 1) / 2;
+        ld v = e0;
+        E[base] = v;
+        for (int m = 1; m <= l; ++m) {
+            v *= sqrtl((ld)(l - m + 1) / (ld)(l + m));
+            E[base + m] = v;
+        }
+    }
+    return E;
+}
+
+template <class T>
+int upload(const std::vector<T>& h, T** d, size_t& bytes, std::string& err)
+{
+    size_t nb = h.size() * sizeof(T);
+    if (nb == 0) nb = sizeof(T);
+    if (hipMalloc((void**)d, nb) != hipSuccess) { err = "hipMalloc of plan table failed"; return -2; }
+    if (!h.empty() && hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+        err = "hipMemcpy of plan table failed";
+        return -3;
+    }
+    bytes += nb;
+    return 0;
+}
+
+}  // namespace
+
+int build_plan(int L, Plan& p, std::string& err)
+{
+    p = Plan();
+    p.L = L;
+    p.N1 = 2 * L - 1;
+    p.N2 = std::max(16, next_pow2(4 * L - 3));
+    p.logN2 = 0;
+    while ((1 << p.logN2) < p.N2) ++p.logN2;
+    const int N1 = p.N1, N2 = p.N2;
+    int rc;
+
+    // sqrt table
+    std::vector<double2> sq(2 * L + 3);
+    for (int k = 0; k < (int)sq.size(); ++k) {
+        ld r = sqrtl((ld)k);
+        sq[k] = make_double2((double)r, k ? (double)(1.0L / r) : 0.0);
+    }
+    if ((rc = upload(sq, &p.sqtab, p.bytes, err))) return rc;
+
+    // edge table
+    std::vector<ld> E = edge_values(L);
+    std::vector<double> ex(E.size());
+    std::vector<int> ek(E.size());
+    for (size_t i = 0; i < E.size(); ++i) {
+        split_ext(E[i], ex[i], ek[i]);
+        if (ek[i]) p.ext = true;
+    }
+    if ((rc = upload(ex, &p.edge, p.bytes, err))) return rc;
+    if ((rc = upload(ek, &p.edgek, p.bytes, err))) return rc;
+
+    // l-recursion factors at beta = pi/2, split into an m part (this table) and an
+    // n part formed in the kernel:
+    //  Delta^{l+1} = Pu_m(l) X_n(l) Delta^l + Qu_m(l) Y_n(l) Delta^{l-1}
+    //  Pu_m(l) = -(2l+1) m / (l sqrt((l+1)^2 - m^2)),  Qu_m(l) = -(l+1)/l sqrt((l^2-m^2)/((l+1)^2-m^2))
+    std::vector<double2> lco((size_t)L * L, make_double2(0.0, 0.0));
+    for (int m = 0; m < L; ++m)
+        for (int l = std::max(1, m); l < L; ++l) {
+            ld a = (ld)(l + 1) * (l + 1) - (ld)m * m;
+            ld b = (ld)l * l - (ld)m * m;
+            ld pu = -(2.0L * l + 1.0L) * (ld)m / ((ld)l * sqrtl(a));
+            ld qu = -((ld)(l + 1) / (ld)l) * sqrtl(b / a);
+            lco[(size_t)m * L + l] = make_double2((double)pu, (double)qu);
+        }
+    if ((rc = upload(lco, &p.lco, p.bytes, err))) return rc;
+
+    std::vector<double> cl(L);
+    for (int l = 0; l < L; ++l) cl[l] = (double)sqrtl((2.0L * l + 1.0L) / (4.0L * PI_L));
+    if ((rc = upload(cl, &p.cl, p.bytes, err))) return rc;
+
+    // Fourier tables
+    std::vector<double2> tw(N2);
+    for (int e = 0; e < N2; ++e) {
+        ld a = -2.0L * PI_L * (ld)e / (ld)N2;
+        tw[e] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    if ((rc = upload(tw, &p.tw, p.bytes, err))) return rc;
+
+    std::vector<cld> c(N1);
+    std::vector<double2> chirp(N1);
+    for (int j = 0; j < N1; ++j) {
+        long long r = ((long long)j * j) % (2LL * N1);
+        ld a = -PI_L * (ld)r / (ld)N1;
+        c[j] = cld(cosl(a), sinl(a));
+        chirp[j] = make_double2((double)c[j].real(), (double)c[j].imag());
+    }
+    if ((rc = upload(chirp, &p.chirp, p.bytes, err))) return rc;
+
+    std::vector<cld> bv(N2, cld(0, 0));
+    for (int k = 0; k < N1; ++k) {
+        bv[k] = std::conj(c[k]);
+        if (k) bv[N2 - k] = std::conj(c[k]);
+    }
+    host_fft(bv);
+    std::vector<double2> bh(N2);
+    for (int j = 0; j < N2; ++j) {
+        cld v = bv[j] / (ld)N2;
+        bh[j] = make_double2((double)v.real(), (double)v.imag());
+    }
+    if ((rc = upload(bh, &p.bhat, p.bytes, err))) return rc;
+
+    // weights of the theta convolution (Sec. IV-D): w(+-1) = +-i pi/2, 0 for other
+    // odd k, 2/(1-k^2) for even k; placed at k mod N2 for |k| <= 2(L-1).
+    std::vector<cld> wv(N2, cld(0, 0));
+    for (int k = -2 * (L - 1); k <= 2 * (L - 1); ++k) {
+        cld w;
+        if (k == 1) w = cld(0, PI_L / 2);
+        else if (k == -1) w = cld(0, -PI_L / 2);
+        else if (k % 2 != 0) w = cld(0, 0);
+        else w = cld(2.0L / (1.0L - (ld)k * (ld)k), 0);
+        wv[((k % N2) + N2) % N2] += w;
+    }
+    host_fft(wv);
+    std::vector<double2> wh(N2);
+    for (int j = 0; j < N2; ++j) {
+        cld v = wv[j] * (2.0L * PI_L / (ld)N2);
+        wh[j] = make_double2((double)v.real(), (double)v.imag());
+    }
+    if ((rc = upload(wh, &p.what, p.bytes, err))) return rc;
+
+    std::vector<double2> th(N1);
+    for (int k = 0; k < N1; ++k) {
+        int mp = (k <= L - 1) ? k : k - N1;
+        ld a = -PI_L * (ld)mp / (ld)N1;
+        ld sc = 1.0L / (2.0L * PI_L * (ld)N1);
+        th[k] = make_double2((double)(cosl(a) * sc), (double)(sinl(a) * sc));
+    }
+    if ((rc = upload(th, &p.thtw, p.bytes, err))) return rc;
+
+    // work lists, longest chains first
+    {
+        std::vector<int2> wf;
+        for (int l0 = 0; l0 < L; l0 += 64)
+            for (int m0 = 0; m0 <= std::min(l0 + 63, L - 1); m0 += MT_FWD) wf.push_back(make_int2(l0, m0));
+        std::stable_sort(wf.begin(), wf.end(), [](int2 a, int2 b) { return a.x > b.x; });
+        p.nworkf = (int)wf.size();
+        if ((rc = upload(wf, &p.workf, p.bytes, err))) return rc;
+        std::vector<int2> wi;
+        for (int n0 = 0; n0 < L; n0 += 64)
+            for (int m0 = 0; m0 < L; m0 += MT_INV) wi.push_back(make_int2(n0, m0));
+        std::stable_sort(wi.begin(), wi.end(), [L](int2 a, int2 b) {
+            return (L - std::max(a.x, a.y)) > (L - std::max(b.x, b.y));
+        });
+        p.nworki = (int)wi.size();
+        if ((rc = upload(wi, &p.worki, p.bytes, err))) return rc;
+    }
+    return 0;
+}
+
+void free_plan(Plan& p)
+{
+    void* ptrs[] = {p.sqtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.thtw,
+                    p.workf, p.worki};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    p = Plan();
+}
+
+// Delta^l_{n,|s|} for n <= l < L by the upward l-recursion in long double,
+// started at l0 = max(n, |s|) from the edge value.
+int build_spin_table(int L, int as, SpinTable& t, std::string& err)
+{
+    t = SpinTable();
+    t.L = L;
+    t.as = as;
+    std::vector<ld> E = edge_values(L);
+    auto edge = [&](int l, int m) { return E[(size_t)l * (l + 1) / 2 + m]; };
+    std::vector<double> val((size_t)L * L, 0.0);
+    std::vector<int> kk((size_t)L * L, 0);
+    for (int n = 0; n < L; ++n) {
+        int l0 = std::max(n, as);
+        if (l0 >= L) continue;
+        ld dcur = (n >= as) ? (((n - as) % 2) ? -edge(n, as) : edge(n, as)) : edge(as, n);
+        ld dprev = 0.0L;
+        for (int l = l0; l < L; ++l) {
+            double x;
+            int k;
+            ld a = fabsl(dcur);
+            split_ext(a, x, k);
+            val[(size_t)l * L + n] = (dcur < 0) ? -x : x;
+            kk[(size_t)l * L + n] = k;
+            if (l + 1 >= L) break;
+            ld dnext;
+            if (l == 0) {
+                dnext = 0.0L;
+            } else {
+                ld num = -(2.0L * l + 1.0L) * (ld)as * (ld)n * dcur -
+                         (ld)(l + 1) * sqrtl(((ld)l * l - (ld)as * as) * ((ld)l * l - (ld)n * n)) * dprev;
+                ld den = (ld)l * sqrtl(((ld)(l + 1) * (l + 1) - (ld)as * as) * ((ld)(l + 1) * (l + 1) - (ld)n * n));
+                dnext = num / den;
+            }
+            dprev = dcur;
+            dcur = dnext;
+        }
+    }
+    int rc;
+    if ((rc = upload(val, &t.val, t.bytes, err))) return rc;
+    if ((rc = upload(kk, &t.k, t.bytes, err))) return rc;
+    return 0;
+}
+
+void free_spin_table(SpinTable& t)
+{
+    if (t.val) (void)hipFree(t.val);
+    if (t.k) (void)hipFree(t.k);
+    t = SpinTable();
+}
+
+}  // namespace mw

@@ -1,0 +1,186 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+FP64 path tolerance: infinity-norm relative error <= 1e-12, i.e.
+max |gpu - oracle| / max |oracle| over the whole output.
+"""
+import numpy as np
+import pytest
+
+import mwsynth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mw(tc):
+    import paper_1110_6298_amd as m
+    m.library()
+    return m
+
+
+def dev(tc, x):
+    return tc.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(tc, t):
+    tc.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+SMALL = [(1, 0), (2, 0), (2, 1), (3, -2), (5, 2), (8, 0), (17, 16), (31, -3), (64, 0), (65, 2),
+         (100, -1), (129, 7), (200, 30), (257, -2)]
+
+
+@pytest.mark.parametrize("L,s", SMALL)
+def test_inverse_parity(orc, tc, mw, L, s):
+    print("inverse parity L=%d s=%d" % (L, s), flush=True)
+    flm = mwsynth.flm_gaussian(L, s, seed=1000 + L + s)
+    ref = orc.inverse(flm, L, s)
+    got = host(tc, mw.inverse(dev(tc, flm), L, s))
+    assert rel(got, ref) < TOL
+
+
+@pytest.mark.parametrize("L,s", SMALL)
+def test_forward_parity(orc, tc, mw, L, s):
+    print("forward parity L=%d s=%d" % (L, s), flush=True)
+    flm = mwsynth.flm_gaussian(L, s, seed=2000 + L + s)
+    # band-limited map plus a non-band-limited perturbation: the forward is the
+    # paper's algorithm on any grid values
+    x = orc.inverse(flm, L, s) + 0.5 * mwsynth.grid_gaussian(L, seed=3000 + L)
+    ref = orc.forward(x, L, s)
+    got = host(tc, mw.forward(dev(tc, x), L, s))
+    assert rel(got, ref) < TOL
+
+
+def test_config_scalar_l64(orc, tc, mw):
+    w = mwsynth.workload_scalar_l64()
+    L, s, flm = w["L"], w["s"], w["flm"]
+    x = orc.inverse(flm, L, s)
+    got_f = host(tc, mw.forward(dev(tc, x), L, s))
+    assert rel(got_f, orc.forward(x, L, s)) < TOL
+    assert rel(got_f, flm) < TOL                      # the sampling theorem
+    got_x = host(tc, mw.inverse(dev(tc, flm), L, s))
+    assert rel(got_x, x) < TOL
+
+
+@pytest.fixture(scope="module")
+def spin2_l512(orc):
+    w = mwsynth.workload_spin2_l512()
+    L, s, flm = w["L"], w["s"], w["flm"]
+    x = orc.inverse(flm, L, s)
+    return L, s, flm, x, orc.forward(x, L, s)
+
+
+def test_config_spin2_l512_fp64(tc, mw, spin2_l512):
+    L, s, flm, x, fref = spin2_l512
+    got_x = host(tc, mw.inverse(dev(tc, flm), L, s))
+    assert rel(got_x, x) < TOL
+    got_f = host(tc, mw.forward(dev(tc, x), L, s))
+    assert rel(got_f, fref) < TOL
+    assert rel(got_f, flm) < TOL
+
+
+@pytest.mark.parametrize("L", [7, 64, 130])
+def test_real_maps(orc, tc, mw, L):
+    flm = mwsynth.make_real_symmetric(mwsynth.flm_gaussian(L, 0, seed=50 + L), L)
+    xr = orc.inverse(flm, L, 0)
+    assert np.abs(xr.imag).max() < 1e-12 * np.abs(xr).max()
+    got_x = host(tc, mw.inverse(dev(tc, flm), L, 0, reality=1))
+    assert got_x.dtype == np.float64
+    assert rel(got_x, xr.real) < TOL
+    xin = xr.real + 0.3 * mwsynth.grid_gaussian(L, seed=60 + L, real=True)
+    ref = orc.forward(xin.astype(np.complex128), L, 0)
+    got_f = host(tc, mw.forward(dev(tc, xin), L, 0, reality=1))
+    assert rel(got_f, ref) < TOL
+    l, m = mwsynth.lm_arrays(L)
+    assert np.abs(np.conj(got_f) - (-1.0) ** m * got_f[l * l + l - m]).max() < 1e-12 * np.abs(got_f).max()
+
+
+def test_batched_call_equals_single_calls(orc, tc, mw):
+    specs = [(16, 0, 0), (40, 2, 0), (33, 0, 1), (64, -1, 0)]
+    maps, flms = [], []
+    for i, (L, s, r) in enumerate(specs):
+        flm = mwsynth.flm_gaussian(L, s, seed=70 + i)
+        if r:
+            flm = mwsynth.make_real_symmetric(flm, L)
+        flms.append(dev(tc, flm))
+        x = orc.inverse(flm, L, s)
+        maps.append(dev(tc, x.real.copy() if r else x))
+    Ls = [a for a, _, _ in specs]
+    ss = [b for _, b, _ in specs]
+    rs = [c for _, _, c in specs]
+    fb = [host(tc, t) for t in mw.forward_batch(maps, Ls, ss, rs)]
+    ib = [host(tc, t) for t in mw.inverse_batch(flms, Ls, ss, rs)]
+    for i in range(len(specs)):
+        f1 = host(tc, mw.forward(maps[i], Ls[i], ss[i], rs[i]))
+        i1 = host(tc, mw.inverse(flms[i], Ls[i], ss[i], rs[i]))
+        assert np.array_equal(fb[i], f1)
+        assert np.array_equal(ib[i], i1)
+
+
+def test_deterministic(tc, mw):
+    L, s = 96, 2
+    flm = dev(tc, mwsynth.flm_gaussian(L, s, seed=81))
+    a = host(tc, mw.inverse(flm, L, s))
+    b = host(tc, mw.inverse(flm, L, s))
+    assert np.array_equal(a, b)
+    xa = host(tc, mw.forward(dev(tc, a), L, s))
+    xb = host(tc, mw.forward(dev(tc, a), L, s))
+    assert np.array_equal(xa, xb)
+
+
+def test_nan_propagates(tc, mw):
+    L, s = 12, 0
+    x = mwsynth.grid_gaussian(L, seed=90)
+    x[3, 5] = np.nan
+    out = host(tc, mw.forward(dev(tc, x), L, s))
+    assert np.isnan(out).any()
+
+
+@pytest.mark.parametrize("L,s,real", [(1024, 0, 1), (2048, 0, 1), (2048, 3, 0)])
+def test_large_l_sampled_and_round_trip(orc, tc, mw, L, s, real):
+    """Full band-limits: the forward on sampled orders against the oracle, the
+    inverse on sampled orders of its rings' phi-spectra, and the round trip."""
+    print("large L=%d s=%d real=%d" % (L, s, real), flush=True)
+    if real:
+        flm = mwsynth.flm_cl_real(L, seed=1004)
+    else:
+        flm = mwsynth.flm_gaussian(L, s, seed=1104, decay=1.0)
+    ms = [0, 1, 2, 5, L // 2, L - 2, L - 1]
+    if not real:
+        ms += [-1, -(L - 1), -(L // 3)]
+    x = host(tc, mw.inverse(dev(tc, flm), L, s, reality=real))
+    # inverse: phi-Fourier coefficients of the GPU map's rings at the sampled orders
+    xc = x.astype(np.complex128)
+    spec = np.fft.fft(xc, axis=1) / (2 * L - 1)
+    got_inv = spec[:, np.array(ms) % (2 * L - 1)].T
+    ref_inv = orc.inverse_orders(flm, L, s, ms)
+    assert rel(got_inv, ref_inv) < TOL
+    # forward on a perturbed (non band-limited) map, sampled orders
+    pert = mwsynth.grid_gaussian(L, seed=1200 + L, real=bool(real))
+    xin = x + 0.25 * pert
+    got_f = host(tc, mw.forward(dev(tc, xin), L, s, reality=real))
+    ref_f = orc.forward_orders(xin.astype(np.complex128), L, s, ms)
+    l, m = mwsynth.lm_arrays(L)
+    got_rows = np.zeros_like(ref_f)
+    for k, mm in enumerate(ms):
+        for ll in range(abs(mm), L):
+            got_rows[k, ll] = got_f[ll * ll + ll + mm]
+    assert rel(got_rows, ref_f) < TOL
+    # round trip on the band-limited map
+    back = host(tc, mw.forward(dev(tc, x), L, s, reality=real))
+    assert rel(back, flm) < TOL
