@@ -90,11 +90,20 @@ int validate(const int32_t* L, const int32_t* spin, const int32_t* reality, int3
     return MW_OK;
 }
 
-size_t ws_need(int L)
+// Three regions: W0 = N1 x L complex (G, or the inverse's F); W1 = max(N1 x L
+// complex, forward Hp records of L x Lp x 4 doubles); W2 = the inverse's
+// coefficient stream (L x Lp x 4 doubles).  Each starts 256-byte aligned.
+size_t ws_region(int L, int which)
 {
     const size_t n1 = 2 * (size_t)L - 1;
-    return 2 * n1 * (size_t)L * sizeof(double2) + 256;
+    const size_t lp = (size_t)L + (L & 1);
+    const size_t a = n1 * (size_t)L * sizeof(double2);
+    const size_t rec = (size_t)L * lp * 4 * sizeof(double);
+    const size_t r = which == 0 ? a : which == 1 ? std::max(a, rec) : rec;
+    return (r + 255) & ~(size_t)255;
 }
+
+size_t ws_need(int L) { return ws_region(L, 0) + ws_region(L, 1) + ws_region(L, 2) + 256; }
 
 bool capturing(hipStream_t st)
 {
@@ -164,23 +173,26 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
         const int s = spin[b], as = s < 0 ? -s : s;
         rc = get_resources(d, L[b], as, op == Op::Inverse, need, may_alloc, &p, &sp, &ws);
         if (rc) return rc;
-        const size_t half = (size_t)p->N1 * p->L;
-        double2* W0 = (double2*)ws;
-        double2* W1 = W0 + half;
+        char* base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+        double2* W0 = (double2*)base;
+        double2* W1 = (double2*)(base + ws_region(p->L, 0));
+        double* W2 = (double*)(base + ws_region(p->L, 0) + ws_region(p->L, 1));
         hipError_t e = hipSuccess;
         if (op == Op::Forward) {
             if (e == hipSuccess)
                 e = staged(0, st, [&] { return mw::launch_phi_forward(*p, ptrs[2 * b], reality[b], W0, st); });
             if (e == hipSuccess)
-                e = staged(1, st, [&] { return mw::launch_theta_forward(*p, s, W0, W1, st); });
+                e = staged(1, st, [&] { return mw::launch_theta_forward(*p, s, W0, (double*)W1, st); });
             if (e == hipSuccess)
                 e = staged(2, st, [&] {
-                    return mw::launch_contract_forward(*p, s, reality[b], W1, (double2*)ptrs[2 * b + 1], st);
+                    return mw::launch_contract_forward(*p, s, reality[b], (const double*)W1,
+                                                       (double2*)ptrs[2 * b + 1], st);
                 });
         } else {
             if (e == hipSuccess)
                 e = staged(3, st, [&] {
-                    return mw::launch_contract_inverse(*p, *sp, s, reality[b], (const double2*)ptrs[2 * b], W0, st);
+                    return mw::launch_contract_inverse(*p, *sp, s, reality[b], (const double2*)ptrs[2 * b], W2,
+                                                       W0, st);
                 });
             if (e == hipSuccess)
                 e = staged(4, st, [&] { return mw::launch_theta_inverse(*p, s, W0, W1, st); });

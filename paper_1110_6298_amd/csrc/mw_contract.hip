@@ -5,20 +5,26 @@
 //   f_{l,+-m} = (-1)^s i^{+-m+s} sqrt((2l+1)/4pi) sum_{n>=0} Delta^l_{n,+-m} Delta^l_{n,-s} H_{+-m,n}
 // A wavefront owns 64 consecutive degrees l (one per lane) and MT orders m.
 // Each lane runs the three-term recursion of row m of Delta^l along the second
-// index n = l .. 0 (beta = pi/2 member of the recursion family of Trapani &
-// Navaza, Sec. V-C):
+// index n = l .. 0 (the beta = pi/2 recursion family of Trapani & Navaza that
+// the paper compares with Risbo's, Sec. V-C):
 //   sqrt((l+n)(l-n+1)) D_{m,n-1} = -2m D_{m,n} - sqrt((l-n)(l+n+1)) D_{m,n+1},
-// started from the edge value D_{m,l} = 2^-l sqrt(binom(2l, l+m)).  The row |s|
-// (the spin factor) runs as one more chain in the same lane.  H_{+-m,n} is the
-// same for all lanes (scalar loads), the sqrt factors come from an LDS table,
-// and the sum over n accumulates in registers.
+// started from the edge value D_{m,l} = 2^-l sqrt(binom(2l, l+m)).  Row |s| (the
+// spin factor) runs as one more chain in the same lane.  H_{+-m,n} is the same
+// for every lane and arrives through scalar loads; the sum over n accumulates
+// in registers.
 //
 // Inverse, Eq.(Fmm):
 //   F_{+-m,n} = (-1)^s i^{-(+-m+s)} sum_l sqrt((2l+1)/4pi) Delta^l_{n,+-m} Delta^l_{n,-s} f_{l,+-m}
-// A wavefront owns 64 consecutive n (one per lane) and MT orders m.  Each lane
-// runs the three-term recursion of Delta^l_{n,m} in the degree l (upward from
-// l0 = max(n, m)), so the sum over l again accumulates in registers; the spin
-// factor Delta^l_{n,|s|} runs as one more chain, started from a table.
+// A wavefront owns 64 consecutive n (one per lane) and one order m.  Each lane
+// runs the three-term recursion of Delta^l_{n,m} upward in the degree l from
+// l0 = max(n, m), so the sum over l again accumulates in registers; the spin
+// factor Delta^l_{n,|s|} runs as a second chain, started from a table.
+//
+// Pipelining: steps run in pairs; the uniform data of pair k-1 (scalar loads)
+// and the per-lane 1/sqrt factors of pair k-1 (vector loads from a small table)
+// are issued before pair k is computed, after an explicit wait on pair k's data.
+// Nothing in the loop touches LDS, so the scalar-load counter only tracks the
+// scalar stream.
 //
 // Chains whose start value is below 2^-900 (only for L > ~900) carry an extra
 // exponent: the stored value is x = D * 2^(600k); while k > 0 the chain's
@@ -40,47 +46,76 @@ __device__ __forceinline__ double2 mul_ipow(double2 z, int k)
 __device__ __forceinline__ double sgn(int k) { return (k & 1) ? -1.0 : 1.0; }
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Makes the compiler wait for a scalar-loaded value here (and, scalar loads
+// returning out of order, for every scalar load issued before it).
+__device__ __forceinline__ void wait_scalar(double v) { asm volatile("" ::"s"(v)); }
+
 constexpr double EXT_UP = 0x1p300;
 constexpr double EXT_DOWN = 0x1p-600;
+
+struct alignas(64) Rec8 { double v[8]; };    // 64-byte scalar-load unit
+
+// 1/sqrt(i) for i = j-1 .. j, read from the shifted table Rt (Rt[j] = 1/sqrt(j-1),
+// Rt[0] = Rt[1] = 0), so that indices below 0 read zeros.
+__device__ __forceinline__ double2 rpair(const double* __restrict__ Rt, int j)
+{
+    double2 r;
+    r.x = Rt[j];
+    r.y = Rt[j + 1];
+    return r;
+}
 
 // ===========================================================================
 // Forward contraction
 // ===========================================================================
 template <int MT, bool EXT>
 struct FwdLane {
-    double dc[MT], dn[MT];      // D_{m,n} and D_{m,n+1}
-    double sc, sn;              // spin row |s|
+    double dc[MT], dn[MT];         // D_{m,n} and D_{m,n+1}
+    double sc, sn;                 // spin row |s|
     double2 ap[MT][2], am[MT][2];  // accumulators for +m / -m, split by parity of n
-    int k[MT], ks;              // exponent levels (EXT)
-    double anext;               // sqrt((l-n)(l+n+1)) of the current step
+    int k[MT], ks;                 // exponent levels (EXT)
+    double anext;                  // sqrt((l-n)(l+n+1)) of the current step
+    double q, dq;                  // Q_n = (l+n)(l-n+1) and 2(n-1), exact in FP64
+    double start[MT], starts;
+    int startk[MT], startks;
 };
 
-template <int MT, bool EXT, int PAR>
-__device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int le, int L, int mb, int as,
-                                         const double2* __restrict__ H, const double2* sq, bool& anyscaled)
+// One step n: contributions of D_{.,n} (h = the four doubles of H at n for
+// each chain), then the recursion to n-1 with ra = 1/sqrt(Q_n).
+template <int MT, bool EXT, int PAR, bool INJ>
+__device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int mb, int as,
+                                         const Rec8 (&h)[MT], double ra, bool& anyscaled)
 {
-    // contributions of D_{.,n}
+    if (INJ) {
+        if (n == l) {
+#pragma unroll
+            for (int c = 0; c < MT; ++c) { st.dc[c] = st.start[c]; if (EXT) st.k[c] = st.startk[c]; }
+            st.sc = st.starts;
+            if (EXT) st.ks = st.startks;
+        }
+        if (EXT) {
+            bool sc = st.ks > 0;
+#pragma unroll
+            for (int c = 0; c < MT; ++c) sc |= st.k[c] > 0;
+            anyscaled = __any(sc);
+        }
+    }
     double seff = st.sc;
     if (EXT) seff = (st.ks == 0) ? seff : 0.0;
 #pragma unroll
     for (int c = 0; c < MT; ++c) {
-        const int mrow = min(mb + c, L - 1);
-        const double2 hp = H[(size_t)(L - 1 + mrow) * L + n];
-        const double2 hm = H[(size_t)(L - 1 - mrow) * L + n];
+        const double* hc = h[c].v + 4 * PAR;
         double d = st.dc[c];
         if (EXT) d = (st.k[c] == 0) ? d : 0.0;
         const double pr = d * seff;
-        st.ap[c][PAR].x = fma(pr, hp.x, st.ap[c][PAR].x);
-        st.ap[c][PAR].y = fma(pr, hp.y, st.ap[c][PAR].y);
-        st.am[c][PAR].x = fma(pr, hm.x, st.am[c][PAR].x);
-        st.am[c][PAR].y = fma(pr, hm.y, st.am[c][PAR].y);
+        st.ap[c][PAR].x = fma(pr, hc[0], st.ap[c][PAR].x);
+        st.ap[c][PAR].y = fma(pr, hc[1], st.ap[c][PAR].y);
+        st.am[c][PAR].x = fma(pr, hc[2], st.am[c][PAR].x);
+        st.am[c][PAR].y = fma(pr, hc[3], st.am[c][PAR].y);
     }
-    if (n == 0) return;
-    // advance every chain from (n, n+1) to (n-1, n)
-    const double2 t1 = sq[le + n];
-    const double2 t2 = sq[max(le - n + 1, 0)];
-    const double an = t1.x * t2.x;
-    const double nra = -(t1.y * t2.y);
+    // D_{n-1} = -(2m D_n + a_{n+1} D_{n+1}) / a_n,  a_n = sqrt(Q_n); harmless at n = 0
+    const double an = st.q * ra;
+    const double nra = -ra;
 #pragma unroll
     for (int c = 0; c < MT; ++c) {
         const double tm = 2.0 * (double)(mb + c);
@@ -94,6 +129,8 @@ __device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int le, in
         st.sc = d;
     }
     st.anext = an;
+    st.q += st.dq;          // Q_{n-1} = Q_n + 2(n-1)
+    st.dq -= 2.0;
     if (EXT && anyscaled) {
         bool still = false;
 #pragma unroll
@@ -109,72 +146,213 @@ __device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int le, in
     }
 }
 
-template <int MT, bool EXT>
-__global__ __launch_bounds__(256) void k_contract_forward(
-    const double2* __restrict__ H, double2* __restrict__ flm, const double2* __restrict__ sqtab,
-    const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,
-    const int2* __restrict__ work, int nwork, int L, int s)
+template <int MT>
+__device__ __forceinline__ void fwd_load_h(Rec8 (&h)[MT], const double* __restrict__ Hp, int mb, int Lp, int L,
+                                           int k)
 {
-    extern __shared__ double2 sq[];
-    for (int i = threadIdx.x; i < 2 * L + 3; i += blockDim.x) sq[i] = sqtab[i];
-    __syncthreads();
-    const int wv = uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-    if (wv >= nwork) return;
+#pragma unroll
+    for (int c = 0; c < MT; ++c) {
+        const int m = min(mb + c, L - 1);
+        h[c] = *(const Rec8*)(Hp + ((size_t)m * Lp + 2 * k) * 4);
+    }
+}
+
+// 1/sqrt factors of the pair (n = 2k+1, 2k): ra(n) = Rt'[le+n] * Rt'[le-n+1]
+struct FwdR { double2 hi, lo; };
+__device__ __forceinline__ FwdR fwd_load_r(const double* __restrict__ Rt, int le, int k)
+{
+    FwdR r;
+    r.hi = rpair(Rt, le + 2 * k + 1);              // 1/sqrt(le+2k), 1/sqrt(le+2k+1)
+    r.lo = rpair(Rt, max(le - 2 * k, -1) + 1);     // 1/sqrt(le-2k-1), 1/sqrt(le-2k)  (0 below 0)
+    return r;
+}
+
+template <int MT, bool EXT, bool INJ>
+__device__ __forceinline__ void fwd_pair(FwdLane<MT, EXT>& st, int k, int l, int mb, int as,
+                                         const Rec8 (&h)[MT], const FwdR& r, bool& anyscaled)
+{
+    // n = 2k+1: 1/sqrt(l+n) = hi.y, 1/sqrt(l-n+1) = lo.x;  n = 2k: hi.x, lo.y
+    fwd_step<MT, EXT, 1, INJ>(st, 2 * k + 1, l, mb, as, h, r.hi.y * r.lo.x, anyscaled);
+    fwd_step<MT, EXT, 0, INJ>(st, 2 * k, l, mb, as, h, r.hi.x * r.lo.y, anyscaled);
+}
+
+// Pairs kfrom, kfrom-1, ..., kto+1 (an even count); on entry A holds pair kfrom,
+// on exit A holds pair kto (pair 0 when kto < 0).
+template <int MT, bool EXT, bool INJ>
+__device__ __forceinline__ void fwd_phase(FwdLane<MT, EXT>& st, int kfrom, int kto, int l, int le, int mb,
+                                          int as, const double* __restrict__ Hp, const double* __restrict__ Rt,
+                                          int Lp, int L, Rec8 (&hA)[MT], Rec8 (&hB)[MT], FwdR& rA, FwdR& rB,
+                                          bool& anyscaled)
+{
+    for (int k = kfrom; k > kto; k -= 2) {
+        wait_scalar(hA[0].v[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        fwd_load_h<MT>(hB, Hp, mb, Lp, L, k - 1);
+        rB = fwd_load_r(Rt, le, k - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        fwd_pair<MT, EXT, INJ>(st, k, l, mb, as, hA, rA, anyscaled);
+        wait_scalar(hB[0].v[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        const int k2 = max(k - 2, 0);
+        fwd_load_h<MT>(hA, Hp, mb, Lp, L, k2);
+        rA = fwd_load_r(Rt, le, k2);
+        __builtin_amdgcn_sched_barrier(0);
+        fwd_pair<MT, EXT, INJ>(st, k - 1, l, mb, as, hB, rB, anyscaled);
+    }
+}
+
+// Pairs ktop .. klo of one segment; pairs >= kA (kA in [klo, ktop+1]) contain
+// lane starts.  Phase loops cover even pair counts; a leftover pair is peeled.
+template <int MT, bool EXT>
+__device__ __forceinline__ void fwd_segment(FwdLane<MT, EXT>& st, int ktop, int kA, int klo, int l, int le, int mb,
+                                            int as, const double* __restrict__ Hp, const double* __restrict__ Rt,
+                                            int Lp, int L, bool& anyscaled)
+{
+    Rec8 hA[MT], hB[MT];
+    FwdR rA, rB;
+    fwd_load_h<MT>(hA, Hp, mb, Lp, L, ktop);
+    rA = fwd_load_r(Rt, le, ktop);
+    int cntA = ktop - kA + 1;
+    if ((cntA & 1) && kA > klo) { --kA; ++cntA; }
+    if (cntA > 0) {
+        const int klastA = (cntA & 1) ? kA + 1 : kA;
+        fwd_phase<MT, EXT, true>(st, ktop, klastA - 1, l, le, mb, as, Hp, Rt, Lp, L, hA, hB, rA, rB, anyscaled);
+        if (cntA & 1) {            // kA = klo, in A
+            wait_scalar(hA[0].v[0]);
+            fwd_pair<MT, EXT, true>(st, kA, l, mb, as, hA, rA, anyscaled);
+            return;
+        }
+    }
+    const int cntB = kA - klo;     // pairs kA-1 .. klo, A holds kA-1
+    if (cntB > 0) {
+        const int klastB = (cntB & 1) ? klo + 1 : klo;
+        fwd_phase<MT, EXT, false>(st, kA - 1, klastB - 1, l, le, mb, as, Hp, Rt, Lp, L, hA, hB, rA, rB, anyscaled);
+        if (cntB & 1) {
+            wait_scalar(hA[0].v[0]);
+            fwd_pair<MT, EXT, false>(st, klo, l, mb, as, hA, rA, anyscaled);
+        }
+    }
+}
+
+// Bring a (D_{n-1}, D_n) checkpoint pair with levels (k0, k1) to one level.
+template <bool EXT>
+__device__ __forceinline__ void ck_level(double& v0, double& v1, int k0, int k1, int& k)
+{
+    if (!EXT) { k = 0; return; }
+    k = max(k0, k1);
+    v0 = ldexp(v0, EXT_STEP * (k - k0));
+    v1 = ldexp(v1, EXT_STEP * (k - k1));
+}
+
+// One workgroup per chain group (64 degrees l0.., MT orders mb..); wave w runs
+// segment w of the row recursions (n in [w*segf, (w+1)*segf) below the top
+// segment, which holds the edge starts).  Partial sums are added in LDS in
+// segment order.
+template <int MT, bool EXT>
+__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
+    const double* __restrict__ Hp, double2* __restrict__ flm, const double* __restrict__ Rt,
+    const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,
+    const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int2* __restrict__ work, int L, int Lp,
+    int s, int segf)
+{
+    __shared__ double2 red[SEG_MAX - 1][MT][4][64];
+    const int grp = blockIdx.x;
+    const int w = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int l0 = uniform(work[wv].x), mb = uniform(work[wv].y);
+    const int l0 = uniform(work[grp].x), mb = uniform(work[grp].y);
     const int l = l0 + lane;
     const bool valid = l < L;
     const int le = valid ? l : L - 1;
     const int as = s < 0 ? -s : s;
+    const int nmax = min(l0 + 63, L - 1);
+    const int jtop = nmax / segf;
+    const size_t T = (size_t)L * (L + 1) / 2;
 
     FwdLane<MT, EXT> st;
-    double start[MT];
-    int startk[MT];
 #pragma unroll
     for (int c = 0; c < MT; ++c) {
-        const int m = mb + c;
-        const bool ok = valid && m <= l;
-        start[c] = ok ? edge[(size_t)l * (l + 1) / 2 + m] : 0.0;
-        startk[c] = (EXT && ok) ? edgek[(size_t)l * (l + 1) / 2 + m] : 0;
-        st.dc[c] = 0.0; st.dn[c] = 0.0; st.k[c] = 0;
+        st.dc[c] = 0.0; st.dn[c] = 0.0; st.k[c] = 0; st.start[c] = 0.0; st.startk[c] = 0;
         st.ap[c][0] = st.ap[c][1] = st.am[c][0] = st.am[c][1] = make_double2(0.0, 0.0);
     }
-    const bool oks = valid && as <= l;
-    const double starts = oks ? edge[(size_t)le * (le + 1) / 2 + as] : 0.0;
-    const int startks = (EXT && oks) ? edgek[(size_t)le * (le + 1) / 2 + as] : 0;
-    st.sc = 0.0; st.sn = 0.0; st.ks = 0; st.anext = 0.0;
+    st.sc = 0.0; st.sn = 0.0; st.ks = 0; st.anext = 0.0; st.starts = 0.0; st.startks = 0;
     bool anyscaled = EXT;
 
-    const int nmax = min(l0 + 63, L - 1);
-    int n = nmax;
-    // phase A: lanes start at their own n = l
-    for (; n >= l0; --n) {
-        if (n == l) {
+    if (w == jtop) {
+        // top segment: lanes start at their own n = l from the edge
 #pragma unroll
-            for (int c = 0; c < MT; ++c) { st.dc[c] = start[c]; st.k[c] = startk[c]; }
-            st.sc = starts; st.ks = startks;
+        for (int c = 0; c < MT; ++c) {
+            const int m = mb + c;
+            const bool ok = valid && m <= l;
+            st.start[c] = ok ? edge[(size_t)l * (l + 1) / 2 + m] : 0.0;
+            st.startk[c] = (EXT && ok) ? edgek[(size_t)l * (l + 1) / 2 + m] : 0;
         }
+        const bool oks = valid && as <= l;
+        st.starts = oks ? edge[(size_t)le * (le + 1) / 2 + as] : 0.0;
+        st.startks = (EXT && oks) ? edgek[(size_t)le * (le + 1) / 2 + as] : 0;
+        const int ktop = nmax >> 1, ntop = 2 * ktop + 1;   // n = L (odd L) is a zero pad step
+        st.q = (double)(le + ntop) * (double)(le - ntop + 1);
+        st.dq = 2.0 * (double)(ntop - 1);
+        fwd_segment<MT, EXT>(st, ktop, l0 >> 1, (jtop * segf) >> 1, l, le, mb, as, Hp, Rt, Lp, L, anyscaled);
+    } else if (w < jtop) {
+        // lower segment: n from (w+1)*segf - 1 down to w*segf, started from the
+        // checkpoint pair at n_c = (w+1)*segf (every lane has l >= n_c)
+        const int nc = (w + 1) * segf;
+        const size_t base = (size_t)w * T + (size_t)le * (le + 1) / 2;
+#pragma unroll
+        for (int c = 0; c < MT; ++c) {
+            const int m = mb + c;
+            if (valid && m <= l) {
+                double2 v = ckf[base + m];
+                int kk = 0;
+                if (EXT) { const int2 kv = ckfk[base + m]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
+                st.dc[c] = v.x; st.dn[c] = v.y; st.k[c] = kk;
+            }
+        }
+        if (valid && as <= l) {
+            double2 v = ckf[base + as];
+            int kk = 0;
+            if (EXT) { const int2 kv = ckfk[base + as]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
+            st.sc = v.x; st.sn = v.y; st.ks = kk;
+        }
+        st.anext = sqrt(fmax(0.0, (double)(le + nc) * (double)(le - nc + 1)));
+        const int ntop = nc - 1;
+        st.q = (double)(le + ntop) * (double)(le - ntop + 1);
+        st.dq = 2.0 * (double)(ntop - 1);
         if (EXT) {
-            bool sc = false;
+            bool sc = st.ks > 0;
 #pragma unroll
             for (int c = 0; c < MT; ++c) sc |= st.k[c] > 0;
-            sc |= st.ks > 0;
-            anyscaled = __any(sc) || (n > l0);
+            anyscaled = __any(sc);
         }
-        if (n & 1) fwd_step<MT, EXT, 1>(st, n, le, L, mb, as, H, sq, anyscaled);
-        else fwd_step<MT, EXT, 0>(st, n, le, L, mb, as, H, sq, anyscaled);
+        fwd_segment<MT, EXT>(st, ntop >> 1, (ntop >> 1) + 1, (w * segf) >> 1, l, le, mb, as, Hp, Rt, Lp, L,
+                             anyscaled);
     }
-    // phase B: every lane running
-    for (; n >= 1; n -= 2) {
-        if (n & 1) {
-            fwd_step<MT, EXT, 1>(st, n, le, L, mb, as, H, sq, anyscaled);
-            fwd_step<MT, EXT, 0>(st, n - 1, le, L, mb, as, H, sq, anyscaled);
-        } else {
-            fwd_step<MT, EXT, 0>(st, n, le, L, mb, as, H, sq, anyscaled);
-            fwd_step<MT, EXT, 1>(st, n - 1, le, L, mb, as, H, sq, anyscaled);
+
+    if (jtop > 0) {
+        if (w > 0 && w <= jtop) {
+#pragma unroll
+            for (int c = 0; c < MT; ++c) {
+                red[w - 1][c][0][lane] = st.ap[c][0];
+                red[w - 1][c][1][lane] = st.ap[c][1];
+                red[w - 1][c][2][lane] = st.am[c][0];
+                red[w - 1][c][3][lane] = st.am[c][1];
+            }
         }
+        __syncthreads();
+        if (w != 0) return;
+        for (int j = 1; j <= jtop; ++j) {
+#pragma unroll
+            for (int c = 0; c < MT; ++c) {
+                double2 v;
+                v = red[j - 1][c][0][lane]; st.ap[c][0].x += v.x; st.ap[c][0].y += v.y;
+                v = red[j - 1][c][1][lane]; st.ap[c][1].x += v.x; st.ap[c][1].y += v.y;
+                v = red[j - 1][c][2][lane]; st.am[c][0].x += v.x; st.am[c][0].y += v.y;
+                v = red[j - 1][c][3][lane]; st.am[c][1].x += v.x; st.am[c][1].y += v.y;
+            }
+        }
+    } else if (w != 0) {
+        return;
     }
-    if (n == 0) fwd_step<MT, EXT, 0>(st, 0, le, L, mb, as, H, sq, anyscaled);
 
     if (!valid) return;
     const double c_l = cl[l];
@@ -208,254 +386,338 @@ __global__ __launch_bounds__(256) void k_contract_forward(
 // ===========================================================================
 // Inverse contraction
 // ===========================================================================
-template <int MT, bool EXT>
+
+// Per-map stream of the inverse: record (m, l) = (c_l sp(l) f_{l,m}, c_l sm(l) f_{l,-m})
+// for l < Lp (zero where l < m or l >= L), where sp/sm fold the (-1)^l factors of
+// Delta^l_{n,-m} and Delta^l_{n,-s}: sp = (-1)^l for s >= 0 (else 1), sm = (-1)^l
+// for s < 0 (else 1).  Real maps read only m >= 0: f_{l,-m} = (-1)^m conj(f_{l,m}).
+__global__ void k_inverse_stream(const double2* __restrict__ flm, double* __restrict__ fs,
+                                 const double* __restrict__ cl, int L, int Lp, int s, int real)
+{
+    const int m = blockIdx.y;
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= Lp) return;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (l < L && m <= l) {
+        const double c = cl[l];
+        const double par = (l & 1) ? -1.0 : 1.0;
+        const double sp = (s >= 0) ? par : 1.0;
+        const double sm = (s >= 0) ? 1.0 : par;
+        const double2 fp = flm[(size_t)l * l + l + m];
+        double2 fm;
+        if (real) fm = (m & 1) ? make_double2(-fp.x, fp.y) : make_double2(fp.x, -fp.y);
+        else fm = flm[(size_t)l * l + l - m];
+        a = make_double2(c * sp * fp.x, c * sp * fp.y);
+        b = make_double2(c * sm * fm.x, c * sm * fm.y);
+    }
+    double* rec = fs + ((size_t)m * Lp + l) * 4;
+    rec[0] = a.x; rec[1] = a.y; rec[2] = b.x; rec[3] = b.y;
+}
+
+template <bool EXT>
 struct InvLane {
-    double dc[MT], dp[MT];     // Delta^l_{n,m}, Delta^{l-1}_{n,m}
+    double dc, dp;             // Delta^l_{n,m}, Delta^{l-1}_{n,m}
     double sc, sp;             // Delta^l_{n,|s|}, Delta^{l-1}_{n,|s|}
-    double2 ap[MT], am[MT];
-    int k[MT], ks;
-    double sprev;              // sqrt(l^2 - n^2) of the current step
+    double2 ap, am;
+    int k, ks;
+    double q, dq;              // (l+1)^2 - n^2 and 2l+3 of the current step (exact)
+    double sprev;              // sqrt(l^2 - n^2)
+    double start, starts;
+    int startk, startks, lz, l0s;
 };
 
-template <int MT, bool EXT, int PAR>
-__device__ __forceinline__ void inv_step(InvLane<MT, EXT>& st, int l, int ne, int L, int mb, int as,
-                                         int s, int real, const double2* __restrict__ flm,
-                                         const double2* __restrict__ lco, const double* __restrict__ cl,
-                                         const double2* sq, bool& anyscaled)
+// uniform data of one step: stream record (4 doubles), (Pu_m, Qu_m), (Pu_s, Qu_s)
+template <bool EXT, bool INJ>
+__device__ __forceinline__ void inv_step(InvLane<EXT>& st, int l, int lstart, double nd, const double* f,
+                                         double pum, double qum, double pus, double qus, double rs,
+                                         bool& anyscaled)
 {
-    // contributions at degree l
-    double seff = st.sc * cl[l];
-    if (EXT) seff = (st.ks == 0) ? seff : 0.0;
-#pragma unroll
-    for (int c = 0; c < MT; ++c) {
-        const int m = min(mb + c, l);   // orders above l contribute nothing (chain is 0)
-        double2 fpv = flm[(size_t)l * l + l + m];
-        double2 fmv;
-        if (real) fmv = (m & 1) ? make_double2(-fpv.x, fpv.y) : make_double2(fpv.x, -fpv.y);
-        else fmv = flm[(size_t)l * l + l - m];
-        // (-1)^l on the +m sum for s >= 0, on the -m sum for s < 0
-        if (PAR) {
-            if (s >= 0) fpv = make_double2(-fpv.x, -fpv.y);
-            else fmv = make_double2(-fmv.x, -fmv.y);
-        }
-        double d = st.dc[c];
-        if (EXT) d = (st.k[c] == 0) ? d : 0.0;
-        const double pr = d * seff;
-        st.ap[c].x = fma(pr, fpv.x, st.ap[c].x);
-        st.ap[c].y = fma(pr, fpv.y, st.ap[c].y);
-        st.am[c].x = fma(pr, fmv.x, st.am[c].x);
-        st.am[c].y = fma(pr, fmv.y, st.am[c].y);
+    if (INJ) {
+        if (l == st.lz) { st.dc = st.start; if (EXT) st.k = st.startk; }
+        if (l == st.l0s && st.l0s > lstart) { st.sc = st.starts; if (EXT) st.ks = st.startks; }
+        if (EXT) anyscaled = __any(st.k > 0 || st.ks > 0);
     }
-    if (l + 1 >= L) return;
-    // n-dependent factors X_n(l) = n / sqrt((l+1)^2 - n^2), Y_n(l) = sqrt(l^2-n^2)/sqrt((l+1)^2-n^2)
-    const double2 t1 = sq[max(l + 1 - ne, 0)];
-    const double2 t2 = sq[l + 1 + ne];
-    const double rs = t1.y * t2.y;
-    const double snew = t1.x * t2.x;
-    const double xn = (double)ne * rs;
+    double d = st.dc, sv = st.sc;
+    if (EXT) { d = (st.k == 0) ? d : 0.0; sv = (st.ks == 0) ? sv : 0.0; }
+    const double pr = d * sv;
+    st.ap.x = fma(pr, f[0], st.ap.x);
+    st.ap.y = fma(pr, f[1], st.ap.y);
+    st.am.x = fma(pr, f[2], st.am.x);
+    st.am.y = fma(pr, f[3], st.am.y);
+    // X_n(l) = n/sqrt((l+1)^2-n^2), Y_n(l) = sqrt(l^2-n^2)/sqrt((l+1)^2-n^2); harmless at l = L-1
+    const double xn = nd * rs;
     const double yn = st.sprev * rs;
-    st.sprev = snew;
-#pragma unroll
-    for (int c = 0; c < MT; ++c) {
-        const double2 pq = lco[(size_t)min(mb + c, L - 1) * L + l];
-        const double d = fma(pq.x * xn, st.dc[c], (pq.y * yn) * st.dp[c]);
-        st.dp[c] = st.dc[c];
-        st.dc[c] = d;
+    st.sprev = st.q * rs;
+    st.q += st.dq;
+    st.dq += 2.0;
+    {
+        const double dn = fma(pum * xn, st.dc, (qum * yn) * st.dp);
+        st.dp = st.dc;
+        st.dc = dn;
     }
     {
-        const double2 pq = lco[(size_t)as * L + l];
-        const double d = fma(pq.x * xn, st.sc, (pq.y * yn) * st.sp);
+        const double sn = fma(pus * xn, st.sc, (qus * yn) * st.sp);
         st.sp = st.sc;
-        st.sc = d;
+        st.sc = sn;
     }
     if (EXT && anyscaled) {
-        bool still = false;
-#pragma unroll
-        for (int c = 0; c < MT; ++c) {
-            if (st.k[c] > 0 && fabs(st.dc[c]) > EXT_UP) {
-                st.dc[c] *= EXT_DOWN; st.dp[c] *= EXT_DOWN; st.k[c] -= 1;
-            }
-            still |= st.k[c] > 0;
-        }
+        if (st.k > 0 && fabs(st.dc) > EXT_UP) { st.dc *= EXT_DOWN; st.dp *= EXT_DOWN; st.k -= 1; }
         if (st.ks > 0 && fabs(st.sc) > EXT_UP) { st.sc *= EXT_DOWN; st.sp *= EXT_DOWN; st.ks -= 1; }
-        still |= st.ks > 0;
-        anyscaled = __any(still);
+        anyscaled = __any(st.k > 0 || st.ks > 0);
     }
 }
 
-template <int MT, bool EXT>
-__global__ __launch_bounds__(256) void k_contract_inverse(
-    const double2* __restrict__ flm, double2* __restrict__ F, const double2* __restrict__ sqtab,
-    const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
-    const double* __restrict__ cl, const double* __restrict__ stab, const int* __restrict__ stabk,
-    const int2* __restrict__ work, int nwork, int L, int s, int real)
+struct InvU { Rec8 f; double4 cm, cs; };   // pair (l, l+1): stream, (Pu,Qu)_m, (Pu,Qu)_s
+struct InvR { double2 a, b; };             // 1/sqrt of l+1-n .. l+2-n and l+1+n .. l+2+n
+
+__device__ __forceinline__ void inv_load_u(InvU& u, const double* __restrict__ fs, const double2* __restrict__ lco,
+                                           int m, int as, int Lp, int L, int j)
 {
-    extern __shared__ double2 sq[];
-    for (int i = threadIdx.x; i < 2 * L + 3; i += blockDim.x) sq[i] = sqtab[i];
-    __syncthreads();
-    const int wv = uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-    if (wv >= nwork) return;
+    u.f = *(const Rec8*)(fs + ((size_t)m * Lp + 2 * j) * 4);
+    u.cm = *(const double4*)(lco + (size_t)m * Lp + 2 * j);
+    u.cs = *(const double4*)(lco + (size_t)as * Lp + 2 * j);
+}
+
+__device__ __forceinline__ InvR inv_load_r(const double* __restrict__ Rt, int ne, int j)
+{
+    InvR r;
+    const int l = 2 * j;
+    r.a = rpair(Rt, max(l + 1 - ne, -1) + 1);   // 1/sqrt(l+1-n), 1/sqrt(l+2-n)  (0 below 0)
+    r.b = rpair(Rt, l + 2 + ne);                // 1/sqrt(l+1+n), 1/sqrt(l+2+n)
+    return r;
+}
+
+template <bool EXT, bool INJ>
+__device__ __forceinline__ void inv_pair(InvLane<EXT>& st, int j, int lstart, double nd, const InvU& u,
+                                         const InvR& r, bool& anyscaled)
+{
+    const int l = 2 * j;
+    inv_step<EXT, INJ>(st, l, lstart, nd, u.f.v, u.cm.x, u.cm.y, u.cs.x, u.cs.y, r.a.x * r.b.x, anyscaled);
+    inv_step<EXT, INJ>(st, l + 1, lstart, nd, u.f.v + 4, u.cm.z, u.cm.w, u.cs.z, u.cs.w, r.a.y * r.b.y, anyscaled);
+}
+
+// Pairs jfrom .. jlast (ascending, an even count); on entry A holds pair jfrom,
+// on exit A holds pair min(jlast + 1, jend).
+template <bool EXT, bool INJ>
+__device__ __forceinline__ void inv_phase(InvLane<EXT>& st, int jfrom, int jlast, int jend, int lstart, int ne,
+                                          double nd, int m, int as, int Lp, int L, const double* __restrict__ fs,
+                                          const double2* __restrict__ lco, const double* __restrict__ Rt, InvU& uA,
+                                          InvU& uB, InvR& rA, InvR& rB, bool& anyscaled)
+{
+    for (int j = jfrom; j < jlast; j += 2) {
+        wait_scalar(uA.f.v[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        inv_load_u(uB, fs, lco, m, as, Lp, L, j + 1);
+        rB = inv_load_r(Rt, ne, j + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        inv_pair<EXT, INJ>(st, j, lstart, nd, uA, rA, anyscaled);
+        wait_scalar(uB.f.v[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        const int j2 = min(j + 2, jend);
+        inv_load_u(uA, fs, lco, m, as, Lp, L, j2);
+        rA = inv_load_r(Rt, ne, j2);
+        __builtin_amdgcn_sched_barrier(0);
+        inv_pair<EXT, INJ>(st, j + 1, lstart, nd, uB, rB, anyscaled);
+    }
+}
+
+// Pairs jfrom .. jlast of one segment (ascending); pairs <= jA (jA in
+// [jfrom-1, jlast]) contain chain starts.  Phase loops cover even pair counts; a
+// leftover pair is peeled.
+template <bool EXT>
+__device__ __forceinline__ void inv_segment(InvLane<EXT>& st, int jfrom, int jA, int jlast, int jend, int lstart,
+                                            int ne, double nd, int m, int as, int Lp, int L,
+                                            const double* __restrict__ fs, const double2* __restrict__ lco,
+                                            const double* __restrict__ Rt, bool& anyscaled)
+{
+    InvU uA, uB;
+    InvR rA, rB;
+    inv_load_u(uA, fs, lco, m, as, Lp, L, jfrom);
+    rA = inv_load_r(Rt, ne, jfrom);
+    int cntA = jA - jfrom + 1;
+    if ((cntA & 1) && jA < jlast) { ++jA; ++cntA; }
+    if (cntA > 0) {
+        const int jlastA = (cntA & 1) ? jA - 1 : jA;
+        inv_phase<EXT, true>(st, jfrom, jlastA, jend, lstart, ne, nd, m, as, Lp, L, fs, lco, Rt, uA, uB, rA, rB,
+                             anyscaled);
+        if (cntA & 1) {             // jA = jlast, in A
+            wait_scalar(uA.f.v[0]);
+            inv_pair<EXT, true>(st, jA, lstart, nd, uA, rA, anyscaled);
+            return;
+        }
+    }
+    const int cntB = jlast - jA;    // pairs jA+1 .. jlast, A holds jA+1
+    if (cntB > 0) {
+        const int jlastB = (cntB & 1) ? jlast - 1 : jlast;
+        inv_phase<EXT, false>(st, jA + 1, jlastB, jend, lstart, ne, nd, m, as, Lp, L, fs, lco, Rt, uA, uB, rA, rB,
+                              anyscaled);
+        if (cntB & 1) {
+            wait_scalar(uA.f.v[0]);
+            inv_pair<EXT, false>(st, jlast, lstart, nd, uA, rA, anyscaled);
+        }
+    }
+}
+
+struct CkOff { size_t off[SEG_MAX]; };
+
+// One workgroup per chain group (64 orders n0.., one order m); wave 0 runs the
+// degrees from lstart (with every chain start) up to the first boundary
+// j*segi >= max(lA, lstart+2), wave w >= 1 runs the w-th following segment from
+// the checkpoint planes.  Partial sums are added in LDS in segment order.
+template <bool EXT>
+__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
+    const double* __restrict__ fs, double2* __restrict__ F, const double* __restrict__ Rt,
+    const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
+    const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,
+    const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work, int L, int Lp, int s, int segi,
+    int nsegi)
+{
+    __shared__ double2 red[SEG_MAX - 1][2][64];
+    const int grp = blockIdx.x;
+    const int w = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int n0 = uniform(work[wv].x), mb = uniform(work[wv].y);
+    const int n0 = uniform(work[grp].x), m = uniform(work[grp].y);
     const int n = n0 + lane;
     const bool valid = n < L;
     const int ne = valid ? n : L - 1;
     const int as = s < 0 ? -s : s;
-    const int lstart = max(n0, mb);
+    const double nd = (double)ne;
+    // pairs (l, l+1) start at an even l; the step before max(n0, m) is skipped
+    const int lstart = max(n0, m) & ~1;
+    const int jend = (Lp >> 1) - 1;
+    // every chain start lies below lA
+    const int lA = max(max(n0 + 64, m + 1), as + 1);
+    int jb = (max(lA, lstart + 2) + segi - 1) / segi;
+    const int nseg = (jb < nsegi) ? 1 + nsegi - jb : 1;
 
-    InvLane<MT, EXT> st;
-    double start[MT];
-    int startk[MT], lz[MT];
-#pragma unroll
-    for (int c = 0; c < MT; ++c) {
-        const int m = mb + c;
-        const bool ok = valid && m < L;
-        lz[c] = max(n, m);
-        double v = 0.0;
-        int kk = 0;
-        if (ok) {
+    InvLane<EXT> st;
+    st.dc = 0.0; st.dp = 0.0; st.k = 0;
+    st.sc = 0.0; st.sp = 0.0; st.ks = 0; st.starts = 0.0; st.startks = 0;
+    st.start = 0.0; st.startk = 0;
+    st.ap = st.am = make_double2(0.0, 0.0);
+    st.lz = max(n, m);
+    st.l0s = max(n, as);
+    bool anyscaled = EXT;
+
+    if (w == 0) {
+        if (valid) {
             if (n >= m) {
                 const size_t i = (size_t)n * (n + 1) / 2 + m;
-                v = ((n - m) & 1) ? -edge[i] : edge[i];
-                if (EXT) kk = edgek[i];
+                st.start = ((n - m) & 1) ? -edge[i] : edge[i];
+                if (EXT) st.startk = edgek[i];
             } else {
                 const size_t i = (size_t)m * (m + 1) / 2 + n;
-                v = edge[i];
-                if (EXT) kk = edgek[i];
+                st.start = edge[i];
+                if (EXT) st.startk = edgek[i];
+            }
+            // spin chain: from the table at lstart when already running, else injected
+            if (st.l0s <= lstart) {
+                double v1 = stab[(size_t)lstart * L + n], v0 = 0.0;
+                int k1 = EXT ? stabk[(size_t)lstart * L + n] : 0, k0 = k1;
+                if (lstart >= 1) {
+                    v0 = stab[(size_t)(lstart - 1) * L + n];
+                    k0 = EXT ? stabk[(size_t)(lstart - 1) * L + n] : 0;
+                }
+                int kk;
+                ck_level<EXT>(v0, v1, k0, k1, kk);
+                st.sc = v1; st.sp = v0; st.ks = kk;
+            } else if (st.l0s < L) {
+                st.starts = stab[(size_t)st.l0s * L + n];
+                st.startks = EXT ? stabk[(size_t)st.l0s * L + n] : 0;
             }
         }
-        start[c] = v; startk[c] = kk;
-        st.dc[c] = 0.0; st.dp[c] = 0.0; st.k[c] = 0;
-        st.ap[c] = st.am[c] = make_double2(0.0, 0.0);
-    }
-    // spin chain: from the table at lstart (and lstart-1) when already running,
-    // else injected at its own start l0s = max(n, |s|)
-    const int l0s = max(n, as);
-    st.sc = 0.0; st.sp = 0.0; st.ks = 0;
-    double starts = 0.0;
-    int startks = 0;
-    if (valid) {
-        if (l0s <= lstart) {
-            double v1 = stab[(size_t)lstart * L + n];
-            int k1 = EXT ? stabk[(size_t)lstart * L + n] : 0;
-            double v0 = 0.0;
-            int k0 = k1;
-            if (lstart >= 1) {
-                v0 = stab[(size_t)(lstart - 1) * L + n];
-                k0 = EXT ? stabk[(size_t)(lstart - 1) * L + n] : 0;
-            }
-            if (EXT) {
-                // bring both to the deeper scale level
-                const int kk = max(k0, k1);
-                v1 = ldexp(v1, 600 * (kk - k1));
-                v0 = ldexp(v0, 600 * (kk - k0));
-                st.ks = kk;
-            }
-            st.sc = v1; st.sp = v0;
-        } else if (l0s < L) {
-            starts = stab[(size_t)l0s * L + n];
-            startks = EXT ? stabk[(size_t)l0s * L + n] : 0;
+        // sqrt(l^2 - n^2) at l = lstart, and q = (l+1)^2 - n^2 of the first step
+        st.sprev = (lstart >= ne) ? sqrt((double)(lstart - ne) * (double)(lstart + ne)) : 0.0;
+        st.q = (double)(lstart + 1 - ne) * (double)(lstart + 1 + ne);
+        st.dq = 2.0 * (double)lstart + 3.0;
+        const int jlast = (nseg > 1) ? ((jb * segi) >> 1) - 1 : jend;
+        const int jA = min(jlast, (lA - 1) >> 1);
+        inv_segment<EXT>(st, lstart >> 1, jA, jlast, jend, lstart, ne, nd, m, as, Lp, L, fs, lco, Rt, anyscaled);
+    } else if (w < nseg) {
+        // segment from degree c = (jb+w-1)*segi, started from the checkpoint plane
+        const int jj = jb + w - 1;
+        const int c = jj * segi;
+        if (valid) {
+            const size_t i = ckoff.off[jj] + (size_t)n * (c + 1) + m;
+            double2 v = cki[i];
+            int kk = 0;
+            if (EXT) { const int2 kv = ckik[i]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
+            st.dp = v.x; st.dc = v.y; st.k = kk;
+            double v1 = stab[(size_t)c * L + n], v0 = stab[(size_t)(c - 1) * L + n];
+            int k1 = EXT ? stabk[(size_t)c * L + n] : 0, k0 = EXT ? stabk[(size_t)(c - 1) * L + n] : 0;
+            ck_level<EXT>(v0, v1, k0, k1, kk);
+            st.sc = v1; st.sp = v0; st.ks = kk;
         }
+        st.sprev = sqrt(fmax(0.0, (double)(c - ne) * (double)(c + ne)));
+        st.q = (double)(c + 1 - ne) * (double)(c + 1 + ne);
+        st.dq = 2.0 * (double)c + 3.0;
+        if (EXT) anyscaled = __any(st.k > 0 || st.ks > 0);
+        const int jlast = (w < nseg - 1) ? (((jj + 1) * segi) >> 1) - 1 : jend;
+        inv_segment<EXT>(st, c >> 1, (c >> 1) - 1, jlast, jend, lstart, ne, nd, m, as, Lp, L, fs, lco, Rt,
+                         anyscaled);
     }
-    st.sprev = sq[max(lstart - ne, 0)].x * sq[lstart + ne].x;
-    bool anyscaled = EXT;
-    // phase A: injections happen while l < lA
-    const int lA = min(L, max(max(n0 + 64, mb + MT), as + 1));
-    int l = lstart;
-    for (; l < lA; ++l) {
-#pragma unroll
-        for (int c = 0; c < MT; ++c)
-            if (l == lz[c]) { st.dc[c] = start[c]; st.k[c] = startk[c]; }
-        if (l == l0s && l0s > lstart) { st.sc = starts; st.ks = startks; }
-        if (EXT) {
-            bool sc = false;
-#pragma unroll
-            for (int c = 0; c < MT; ++c) sc |= st.k[c] > 0;
-            sc |= st.ks > 0;
-            anyscaled = __any(sc) || true;
+
+    if (nseg > 1) {
+        if (w > 0 && w < nseg) {
+            red[w - 1][0][lane] = st.ap;
+            red[w - 1][1][lane] = st.am;
         }
-        if (l & 1) inv_step<MT, EXT, 1>(st, l, ne, L, mb, as, s, real, flm, lco, cl, sq, anyscaled);
-        else inv_step<MT, EXT, 0>(st, l, ne, L, mb, as, s, real, flm, lco, cl, sq, anyscaled);
-    }
-    for (; l + 1 < L; l += 2) {
-        if (l & 1) {
-            inv_step<MT, EXT, 1>(st, l, ne, L, mb, as, s, real, flm, lco, cl, sq, anyscaled);
-            inv_step<MT, EXT, 0>(st, l + 1, ne, L, mb, as, s, real, flm, lco, cl, sq, anyscaled);
-        } else {
-            inv_step<MT, EXT, 0>(st, l, ne, L, mb, as, s, real, flm, lco, cl, sq, anyscaled);
-            inv_step<MT, EXT, 1>(st, l + 1, ne, L, mb, as, s, real, flm, lco, cl, sq, anyscaled);
+        __syncthreads();
+        if (w != 0) return;
+        for (int j = 1; j < nseg; ++j) {
+            const double2 a = red[j - 1][0][lane], b = red[j - 1][1][lane];
+            st.ap.x += a.x; st.ap.y += a.y;
+            st.am.x += b.x; st.am.y += b.y;
         }
-    }
-    if (l < L) {
-        if (l & 1) inv_step<MT, EXT, 1>(st, l, ne, L, mb, as, s, real, flm, lco, cl, sq, anyscaled);
-        else inv_step<MT, EXT, 0>(st, l, ne, L, mb, as, s, real, flm, lco, cl, sq, anyscaled);
+    } else if (w != 0) {
+        return;
     }
 
     if (!valid) return;
-#pragma unroll
-    for (int c = 0; c < MT; ++c) {
-        const int m = mb + c;
-        if (m >= L) continue;
-        const double fsp = sgn(s) * ((s >= 0) ? sgn(n) : 1.0);
-        const double fsm = sgn(s) * ((s < 0) ? sgn(n) : 1.0);
-        double2 op = mul_ipow(st.ap[c], ((-(m + s)) % 4 + 4) % 4);
-        F[(size_t)(L - 1 + m) * L + n] = make_double2(op.x * fsp, op.y * fsp);
-        if (m > 0) {
-            double2 om = mul_ipow(st.am[c], ((m - s) % 4 + 4) % 4);
-            F[(size_t)(L - 1 - m) * L + n] = make_double2(om.x * fsm, om.y * fsm);
-        }
+    const double fsp = sgn(s) * ((s >= 0) ? sgn(n) : 1.0);
+    const double fsm = sgn(s) * ((s < 0) ? sgn(n) : 1.0);
+    double2 op = mul_ipow(st.ap, ((-(m + s)) % 4 + 4) % 4);
+    F[(size_t)(L - 1 + m) * L + n] = make_double2(op.x * fsp, op.y * fsp);
+    if (m > 0) {
+        double2 om = mul_ipow(st.am, ((m - s) % 4 + 4) % 4);
+        F[(size_t)(L - 1 - m) * L + n] = make_double2(om.x * fsm, om.y * fsm);
     }
-}
-
-template <class K>
-hipError_t set_lds(K kernel, size_t bytes)
-{
-    if (bytes <= 65536) return hipSuccess;
-    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 }  // namespace
 
-hipError_t launch_contract_forward(const Plan& p, int s, int real, const double2* H, double2* flm,
+hipError_t launch_contract_forward(const Plan& p, int s, int real, const double* Hp, double2* flm,
                                    hipStream_t st)
 {
     (void)real;
-    const size_t lds = (size_t)(2 * p.L + 3) * sizeof(double2);
-    const int threads = 256, wpb = threads / 64;
-    const dim3 grid((p.nworkf + wpb - 1) / wpb);
-    hipError_t e;
-    if (p.ext) {
-        auto k = k_contract_forward<MT_FWD, true>;
-        if ((e = set_lds(k, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k, grid, dim3(threads), lds, st, H, flm, p.sqtab, p.edge, p.edgek, p.cl,
-                           p.workf, p.nworkf, p.L, s);
-    } else {
-        auto k = k_contract_forward<MT_FWD, false>;
-        if ((e = set_lds(k, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k, grid, dim3(threads), lds, st, H, flm, p.sqtab, p.edge, p.edgek, p.cl,
-                           p.workf, p.nworkf, p.L, s);
-    }
+    const dim3 grid(p.nworkf), block(64 * SEG_MAX);
+    if (p.ext)
+        hipLaunchKernelGGL((k_contract_forward<MT_FWD, true>), grid, block, 0, st, Hp, flm, p.rtab, p.edge, p.edgek,
+                           p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
+    else
+        hipLaunchKernelGGL((k_contract_forward<MT_FWD, false>), grid, block, 0, st, Hp, flm, p.rtab, p.edge,
+                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
     return hipGetLastError();
 }
 
-hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, int real,
-                                   const double2* flm, double2* F, hipStream_t st)
+hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, int real, const double2* flm,
+                                   double* fs, double2* F, hipStream_t st)
 {
-    const size_t lds = (size_t)(2 * p.L + 3) * sizeof(double2);
-    const int threads = 256, wpb = threads / 64;
-    const dim3 grid((p.nworki + wpb - 1) / wpb);
-    hipError_t e;
-    if (p.ext) {
-        auto k = k_contract_inverse<MT_INV, true>;
-        if ((e = set_lds(k, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k, grid, dim3(threads), lds, st, flm, F, p.sqtab, p.edge, p.edgek, p.lco,
-                           p.cl, sp.val, sp.k, p.worki, p.nworki, p.L, s, real);
-    } else {
-        auto k = k_contract_inverse<MT_INV, false>;
-        if ((e = set_lds(k, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k, grid, dim3(threads), lds, st, flm, F, p.sqtab, p.edge, p.edgek, p.lco,
-                           p.cl, sp.val, sp.k, p.worki, p.nworki, p.L, s, real);
+    {
+        const dim3 grid((p.Lp + 255) / 256, p.L);
+        hipLaunchKernelGGL(k_inverse_stream, grid, dim3(256), 0, st, flm, fs, p.cl, p.L, p.Lp, s, real);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
+    CkOff off;
+    for (int j = 0; j < SEG_MAX; ++j) off.off[j] = p.cki_off[j];
+    const dim3 grid(p.nworki), block(64 * SEG_MAX);
+    if (p.ext)
+        hipLaunchKernelGGL((k_contract_inverse<true>), grid, block, 0, st, fs, F, p.rtab, p.edge, p.edgek, p.lco,
+                           sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
+    else
+        hipLaunchKernelGGL((k_contract_inverse<false>), grid, block, 0, st, fs, F, p.rtab, p.edge, p.edgek, p.lco,
+                           sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
     return hipGetLastError();
 }
 

@@ -147,8 +147,9 @@ __global__ void k_phi_forward(Plan p, const void* __restrict__ map, double2* __r
 //   F_{m m'} = 1/(2 pi N1) sum_t Gext(theta_t) e^{-i m' theta_t},
 //   G_{m m'} = 2 pi sum_{m''} F_{m m''} w(m'' - m')  (product on the N2 grid),
 //   fold     H_{m,0} = G_{m,0},  H_{m,n} = G_{m,n} + (-1)^{m+s} G_{m,-n}  (Eq.(Fmm_sym1)).
-// Output H[m + L-1][n], n < L.
-__global__ void k_theta_forward(Plan p, int s, const double2* __restrict__ G, double2* __restrict__ H)
+// Output: Hp records (see mw_internal.h); order m writes its slot of row |m|,
+// including the zero pad entry n = L when L is odd.
+__global__ void k_theta_forward(Plan p, int s, const double2* __restrict__ G, double* __restrict__ Hp)
 {
     extern __shared__ double2 A[];
     const int L = p.L, N1 = p.N1, N2 = p.N2;
@@ -186,10 +187,16 @@ __global__ void k_theta_forward(Plan p, int s, const double2* __restrict__ G, do
     block_fft<+1>(A, N2, p.logN2, p.tw);
     for (int j = threadIdx.x; j < N2; j += blockDim.x) A[j] = cmul(A[j], p.what[j]);
     block_fft<-1>(A, N2, p.logN2, p.tw);
-    for (int n = threadIdx.x; n < L; n += blockDim.x) {
-        double2 v = A[n];
-        if (n > 0) v = cadd(v, cscale(A[N2 - n], sig));
-        H[(size_t)mi * L + n] = v;
+    const int am = m < 0 ? -m : m;
+    for (int n = threadIdx.x; n < p.Lp; n += blockDim.x) {
+        double2 v = make_double2(0.0, 0.0);
+        if (n < L) {
+            v = A[n];
+            if (n > 0) v = cadd(v, cscale(A[N2 - n], sig));
+        }
+        double* rec = Hp + ((size_t)am * p.Lp + n) * 4;
+        if (m >= 0) { rec[0] = v.x; rec[1] = v.y; }
+        if (m <= 0) { rec[2] = v.x; rec[3] = v.y; }
     }
 }
 
@@ -278,12 +285,12 @@ hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2*
     return hipGetLastError();
 }
 
-hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, double2* H, hipStream_t st)
+hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, double* Hp, hipStream_t st)
 {
     const size_t lds = (size_t)p.N2 * sizeof(double2);
     hipError_t e;
     if ((e = set_lds(k_theta_forward, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_theta_forward, dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s, G, H);
+    hipLaunchKernelGGL(k_theta_forward, dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s, G, Hp);
     return hipGetLastError();
 }
 

@@ -15,16 +15,21 @@ namespace mw {
 constexpr int EXT_STEP = 600;
 constexpr int EXT_LIMIT = 900;
 
+// Waves per contraction workgroup = maximum number of segments of one chain.
+constexpr int SEG_MAX = 4;
+
 // Band-limit-dependent constants, built once per (device, L) on the host in
 // long double and uploaded.  All device pointers are owned by the plan.
 struct Plan {
     int L = 0, N1 = 0, N2 = 0, logN2 = 0;
+    int Lp = 0;              // L rounded up to even (row length of the forward H layout)
     bool ext = false;        // some start value needs the exponent extension
     // Wigner tables
     double2* sqtab = nullptr;   // (sqrt k, 1/sqrt k), k = 0..2L+2; entry 0 = (0, 0)
+    double* rtab = nullptr;     // rtab[j] = 1/sqrt(j-1) for j >= 2, rtab[0] = rtab[1] = 0; 2L+8 entries
     double* edge = nullptr;     // Delta^l_{m,l}, packed l(l+1)/2 + m, as mantissa * 2^(EXT_STEP*k)
     int* edgek = nullptr;       // k of each edge entry
-    double2* lco = nullptr;     // l-recursion factors (Pu_m(l), Qu_m(l)) at [m*L + l]
+    double2* lco = nullptr;     // l-recursion factors (Pu_m(l), Qu_m(l)) at [m*Lp + l] (0 for l >= L)
     double* cl = nullptr;       // sqrt((2l+1)/(4 pi))
     // Fourier tables
     double2* tw = nullptr;      // exp(-2 pi i e/N2), e < N2
@@ -35,6 +40,17 @@ struct Plan {
     // contraction work lists (int2: (block start, first order)); sorted longest first
     int2* workf = nullptr; int nworkf = 0;   // forward: (l0, m0)
     int2* worki = nullptr; int nworki = 0;   // inverse: (n0, m0)
+    // Chain segmentation.  The forward splits every row recursion at the global
+    // boundaries n = j*segf (j = 1..nsegf-1); ckf holds, for boundary j at
+    // [(j-1)*L(L+1)/2 + l(l+1)/2 + m], the pair (Delta^l_{m,n-1}, Delta^l_{m,n})
+    // as mantissas with exponent levels ckfk.  The inverse splits every degree
+    // recursion at l = j*segi; cki holds, for boundary j, the pair
+    // (Delta^{c-1}_{n,m}, Delta^{c}_{n,m}), c = j*segi, at cki_off[j] + n*(c+1) + m
+    // (n, m <= c), with levels ckik.
+    int segf = 0, nsegf = 1, segi = 0, nsegi = 1;
+    double2* ckf = nullptr; int2* ckfk = nullptr;
+    double2* cki = nullptr; int2* ckik = nullptr;
+    size_t cki_off[SEG_MAX] = {0};
     size_t bytes = 0;
 };
 
@@ -49,20 +65,23 @@ struct SpinTable {
 
 // Chains per lane in the contraction kernels (work-list granularity in m).
 constexpr int MT_FWD = 2;
-constexpr int MT_INV = 2;
+constexpr int MT_INV = 1;
 
 int build_plan(int L, Plan& p, std::string& err);
 void free_plan(Plan& p);
 int build_spin_table(int L, int as, SpinTable& t, std::string& err);
 void free_spin_table(SpinTable& t);
 
-// Kernel launchers (enqueue only).  Buffers: map, G (L x N1), H (N1 x L), coeffs.
+// Kernel launchers (enqueue only).  Buffers: map, G (L x N1), F (N1 x L), coeffs.
 hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2* G, hipStream_t st);
-hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, double2* H, hipStream_t st);
-hipError_t launch_contract_forward(const Plan& p, int s, int real, const double2* H, double2* flm,
+// Hp: forward Fourier coefficients H_{+-m,n} as records (Re H_{m,n}, Im H_{m,n},
+// Re H_{-m,n}, Im H_{-m,n}) at [(m * Lp + n) * 4], m < L, n < Lp (pad rows zero).
+hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, double* Hp, hipStream_t st);
+hipError_t launch_contract_forward(const Plan& p, int s, int real, const double* Hp, double2* flm,
                                    hipStream_t st);
+// fs: per-map scratch of L x Lp x 4 doubles (the inverse's scaled coefficient stream).
 hipError_t launch_contract_inverse(const Plan& p, const SpinTable& st_, int s, int real,
-                                   const double2* flm, double2* F, hipStream_t st);
+                                   const double2* flm, double* fs, double2* F, hipStream_t st);
 hipError_t launch_theta_inverse(const Plan& p, int s, const double2* F, double2* Ft, hipStream_t st);
 hipError_t launch_phi_inverse(const Plan& p, const double2* Ft, void* map, int real, hipStream_t st);
 

@@ -79,6 +79,54 @@ std::vector<ld> edge_values(int L)
     return E;
 }
 
+// Delta^l_{a,b} for l = max(a,b) .. L-1 by the upward degree recursion at beta = pi/2
+// (symmetric in a, b), started from the edge value; out[l] (0 for l < max(a,b)).
+void degree_chain(const std::vector<ld>& E, int L, int a, int b, std::vector<ld>& out)
+{
+    out.assign(L, 0.0L);
+    const int l0 = std::max(a, b);
+    if (l0 >= L) return;
+    auto edge = [&](int l, int k) { return E[(size_t)l * (l + 1) / 2 + k]; };
+    ld dcur = (a >= b) ? ((((a - b) & 1) ? -1.0L : 1.0L) * edge(a, b)) : edge(b, a);
+    ld dprev = 0.0L;
+    for (int l = l0; l < L; ++l) {
+        out[l] = dcur;
+        if (l + 1 >= L) break;
+        ld dnext = 0.0L;
+        if (l > 0) {
+            ld num = -(2.0L * l + 1.0L) * (ld)a * (ld)b * dcur -
+                     (ld)(l + 1) * sqrtl(((ld)l * l - (ld)a * a) * ((ld)l * l - (ld)b * b)) * dprev;
+            ld den = (ld)l * sqrtl(((ld)(l + 1) * (l + 1) - (ld)a * a) * ((ld)(l + 1) * (l + 1) - (ld)b * b));
+            dnext = num / den;
+        }
+        dprev = dcur;
+        dcur = dnext;
+    }
+}
+
+// Row m of Delta^c by the three-term recursion in the second index from the edge:
+// out[n] = Delta^c_{m,n}, n = 0..c.
+void row_chain(const std::vector<ld>& E, int c, int m, std::vector<ld>& out)
+{
+    out.assign(c + 1, 0.0L);
+    ld dn = E[(size_t)c * (c + 1) / 2 + m], dn1 = 0.0L;
+    out[c] = dn;
+    for (int n = c; n >= 1; --n) {
+        ld an = sqrtl((ld)(c + n) * (ld)(c - n + 1));
+        ld an1 = sqrtl((ld)(c - n) * (ld)(c + n + 1));
+        ld dm1 = -(2.0L * m * dn + an1 * dn1) / an;
+        dn1 = dn;
+        dn = dm1;
+        out[n - 1] = dn;
+    }
+}
+
+void split_signed(ld v, double& x, int& k)
+{
+    split_ext(fabsl(v), x, k);
+    if (v < 0) x = -x;
+}
+
 template <class T>
 int upload(const std::vector<T>& h, T** d, size_t& bytes, std::string& err)
 {
@@ -100,6 +148,7 @@ int build_plan(int L, Plan& p, std::string& err)
     p = Plan();
     p.L = L;
     p.N1 = 2 * L - 1;
+    p.Lp = L + (L & 1);
     p.N2 = std::max(16, next_pow2(4 * L - 3));
     p.logN2 = 0;
     while ((1 << p.logN2) < p.N2) ++p.logN2;
@@ -113,6 +162,9 @@ int build_plan(int L, Plan& p, std::string& err)
         sq[k] = make_double2((double)r, k ? (double)(1.0L / r) : 0.0);
     }
     if ((rc = upload(sq, &p.sqtab, p.bytes, err))) return rc;
+    std::vector<double> rt(2 * L + 8, 0.0);
+    for (int j = 2; j < (int)rt.size(); ++j) rt[j] = (double)(1.0L / sqrtl((ld)(j - 1)));
+    if ((rc = upload(rt, &p.rtab, p.bytes, err))) return rc;
 
     // edge table
     std::vector<ld> E = edge_values(L);
@@ -129,14 +181,14 @@ int build_plan(int L, Plan& p, std::string& err)
     // n part formed in the kernel:
     //  Delta^{l+1} = Pu_m(l) X_n(l) Delta^l + Qu_m(l) Y_n(l) Delta^{l-1}
     //  Pu_m(l) = -(2l+1) m / (l sqrt((l+1)^2 - m^2)),  Qu_m(l) = -(l+1)/l sqrt((l^2-m^2)/((l+1)^2-m^2))
-    std::vector<double2> lco((size_t)L * L, make_double2(0.0, 0.0));
+    std::vector<double2> lco((size_t)L * p.Lp, make_double2(0.0, 0.0));
     for (int m = 0; m < L; ++m)
         for (int l = std::max(1, m); l < L; ++l) {
             ld a = (ld)(l + 1) * (l + 1) - (ld)m * m;
             ld b = (ld)l * l - (ld)m * m;
             ld pu = -(2.0L * l + 1.0L) * (ld)m / ((ld)l * sqrtl(a));
             ld qu = -((ld)(l + 1) / (ld)l) * sqrtl(b / a);
-            lco[(size_t)m * L + l] = make_double2((double)pu, (double)qu);
+            lco[(size_t)m * p.Lp + l] = make_double2((double)pu, (double)qu);
         }
     if ((rc = upload(lco, &p.lco, p.bytes, err))) return rc;
 
@@ -203,7 +255,71 @@ int build_plan(int L, Plan& p, std::string& err)
     }
     if ((rc = upload(th, &p.thtw, p.bytes, err))) return rc;
 
-    // work lists, longest chains first
+    // chain segmentation (only where a chain is long relative to the parallelism)
+    {
+        const int seg = (L <= 1024) ? 64 * std::max(1, (L + 64 * SEG_MAX - 1) / (64 * SEG_MAX)) : 0;
+        p.segf = p.segi = (seg > 0 && seg < L) ? seg : (L + 63) / 64 * 64 + 64;
+        p.nsegf = p.nsegi = (p.segf < L) ? (L + p.segf - 1) / p.segf : 1;
+        if (p.nsegf > SEG_MAX) { err = "segmentation exceeds SEG_MAX"; return -3; }
+        const size_t T = (size_t)L * (L + 1) / 2;
+        if (p.nsegf > 1) {
+            std::vector<double2> ck((size_t)(p.nsegf - 1) * T, make_double2(0.0, 0.0));
+            std::vector<int2> ckk((size_t)(p.nsegf - 1) * T, make_int2(0, 0));
+            std::vector<ld> c0, c1;
+            for (int j = 1; j < p.nsegf; ++j) {
+                const int nc = j * p.segf;
+                for (int m = 0; m < L; ++m) {
+                    degree_chain(E, L, m, nc - 1, c0);
+                    degree_chain(E, L, m, nc, c1);
+                    for (int l = std::max(m, nc - 1); l < L; ++l) {
+                        double x0, x1;
+                        int k0, k1;
+                        split_signed(c0[l], x0, k0);
+                        split_signed(c1[l], x1, k1);
+                        const size_t i = (size_t)(j - 1) * T + (size_t)l * (l + 1) / 2 + m;
+                        ck[i] = make_double2(x0, x1);
+                        ckk[i] = make_int2(k0, k1);
+                    }
+                }
+            }
+            if ((rc = upload(ck, &p.ckf, p.bytes, err))) return rc;
+            if ((rc = upload(ckk, &p.ckfk, p.bytes, err))) return rc;
+        }
+        if (p.nsegi > 1) {
+            size_t tot = 0;
+            for (int j = 1; j < p.nsegi; ++j) {
+                const int c = j * p.segi;
+                p.cki_off[j] = tot;
+                tot += (size_t)(c + 1) * (c + 1);
+            }
+            std::vector<double2> ck(tot, make_double2(0.0, 0.0));
+            std::vector<int2> ckk(tot, make_int2(0, 0));
+            std::vector<ld> r0, r1;
+            for (int j = 1; j < p.nsegi; ++j) {
+                const int c = j * p.segi;
+                for (int m = 0; m <= c; ++m) {
+                    row_chain(E, c, m, r1);                    // Delta^c_{m,n}
+                    if (m <= c - 1) row_chain(E, c - 1, m, r0);  // Delta^{c-1}_{m,n}
+                    for (int n = 0; n <= c; ++n) {
+                        // Delta_{n,m} = (-1)^{n-m} Delta_{m,n}
+                        const ld sg = ((n - m) & 1) ? -1.0L : 1.0L;
+                        const ld v1 = sg * r1[n];
+                        const ld v0 = (m <= c - 1 && n <= c - 1) ? sg * r0[n] : 0.0L;
+                        double x0, x1;
+                        int k0, k1;
+                        split_signed(v0, x0, k0);
+                        split_signed(v1, x1, k1);
+                        ck[p.cki_off[j] + (size_t)n * (c + 1) + m] = make_double2(x0, x1);
+                        ckk[p.cki_off[j] + (size_t)n * (c + 1) + m] = make_int2(k0, k1);
+                    }
+                }
+            }
+            if ((rc = upload(ck, &p.cki, p.bytes, err))) return rc;
+            if ((rc = upload(ckk, &p.ckik, p.bytes, err))) return rc;
+        }
+    }
+
+    // work lists (one entry per chain group; a workgroup runs its segments), longest first
     {
         std::vector<int2> wf;
         for (int l0 = 0; l0 < L; l0 += 64)
@@ -225,8 +341,8 @@ int build_plan(int L, Plan& p, std::string& err)
 
 void free_plan(Plan& p)
 {
-    void* ptrs[] = {p.sqtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.thtw,
-                    p.workf, p.worki};
+    void* ptrs[] = {p.sqtab, p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.thtw,
+                    p.workf, p.worki, p.ckf, p.ckfk, p.cki, p.ckik};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p = Plan();
