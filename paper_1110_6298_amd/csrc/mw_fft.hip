@@ -26,81 +26,180 @@ __device__ __forceinline__ double2 mul_dir_i(double2 a)
     return DIR < 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
 }
 
-// Block-wide in-place FFT of length N = 2^logN in LDS (Stockham indexing,
-// radix-4 stages preceded by one radix-2 stage when logN is odd; each stage
-// reads into registers, synchronises, writes).  Requires blockDim.x >= N/8.
+// In-place DFT of 4 values: a_k <- sum_j a_j w^{jk}, w = exp(DIR 2 pi i/4).
+template <int DIR>
+__device__ __forceinline__ void bf4(double2& a0, double2& a1, double2& a2, double2& a3)
+{
+    const double2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3);
+    const double2 t3 = mul_dir_i<DIR>(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a1 = cadd(t1, t3);
+    a2 = csub(t0, t2);
+    a3 = csub(t1, t3);
+}
+
+// exp(DIR 2 pi i e/16) for a compile-time e
+template <int DIR, int E>
+__device__ __forceinline__ double2 w16()
+{
+    constexpr double C[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                              0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                              -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                              0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+    constexpr double S[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                              1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                              0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                              -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+    return make_double2(C[E & 15], DIR * S[E & 15]);
+}
+
+// DFT of 16 values in registers as 4 x 4: inner DFT4 over j of x[a + 4j], twiddle
+// w16^{ab}, outer DFT4 over a; X[b + 4c] ends in v[4b + c] and is moved to v[b + 4c].
+template <int DIR>
+__device__ __forceinline__ void dft16(double2 (&v)[16])
+{
+#pragma unroll
+    for (int a = 0; a < 4; ++a) bf4<DIR>(v[a], v[a + 4], v[a + 8], v[a + 12]);
+    // now v[a + 4b] = inner result b of column a
+    v[1 + 4] = cmul(v[1 + 4], w16<DIR, 1>());
+    v[1 + 8] = cmul(v[1 + 8], w16<DIR, 2>());
+    v[1 + 12] = cmul(v[1 + 12], w16<DIR, 3>());
+    v[2 + 4] = cmul(v[2 + 4], w16<DIR, 2>());
+    v[2 + 8] = cmul(v[2 + 8], w16<DIR, 4>());
+    v[2 + 12] = cmul(v[2 + 12], w16<DIR, 6>());
+    v[3 + 4] = cmul(v[3 + 4], w16<DIR, 3>());
+    v[3 + 8] = cmul(v[3 + 8], w16<DIR, 6>());
+    v[3 + 12] = cmul(v[3 + 12], w16<DIR, 9>());
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bf4<DIR>(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]);
+    // v[4b + c] = X[b + 4c]: transpose the 4 x 4 block
+    double2 t;
+    t = v[1]; v[1] = v[4]; v[4] = t;
+    t = v[2]; v[2] = v[8]; v[8] = t;
+    t = v[3]; v[3] = v[12]; v[12] = t;
+    t = v[6]; v[6] = v[9]; v[9] = t;
+    t = v[7]; v[7] = v[13]; v[13] = t;
+    t = v[11]; v[11] = v[14]; v[14] = t;
+}
+
+// u_t *= w^t for t = 1..15, each power formed from w, w^2, w^4, w^8 (bits of t),
+// i.e. a product of at most four factors.
+template <int R>
+__device__ __forceinline__ void twiddle_powers(double2* u, double2 w)
+{
+    const double2 w2 = cmul(w, w);
+    const double2 w4 = cmul(w2, w2);
+    const double2 w8 = cmul(w4, w4);
+#pragma unroll
+    for (int t = 1; t < R; ++t) {
+        double2 f;
+        bool have = false;
+        if (t & 1) { f = w; have = true; }
+        if (t & 2) { f = have ? cmul(f, w2) : w2; have = true; }
+        if (t & 4) { f = have ? cmul(f, w4) : w4; have = true; }
+        if (t & 8) { f = have ? cmul(f, w8) : w8; }
+        u[t] = cmul(u[t], f);
+    }
+}
+
+// Final Stockham pass of radix R = 2, 4 or 8 (the factor left after the radix-16
+// passes): each thread holds up to 16/R butterflies in one 16-value register set.
+template <int DIR, int R>
+__device__ __forceinline__ void last_pass(double2* x, int N, int logN, int p, int logp,
+                                          const double2* __restrict__ tw)
+{
+    constexpr int r = (R == 2) ? 1 : (R == 4) ? 2 : 3;
+    constexpr int QM = 16 / R;
+    const int NB = N >> r;
+    double2 u[16];
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int i = threadIdx.x + q * blockDim.x;
+        if (i < NB) {
+            const int k = i & (p - 1);
+#pragma unroll
+            for (int t = 0; t < R; ++t) u[q * R + t] = x[i + t * NB];
+            double2 w = tw[k << (logN - logp - r)];
+            if (DIR > 0) w = cconj(w);
+            twiddle_powers<R>(u + q * R, w);
+            double2* v = u + q * R;
+            if (R == 2) {
+                const double2 a = v[0], b = v[1];
+                v[0] = cadd(a, b); v[1] = csub(a, b);
+            } else if (R == 4) {
+                bf4<DIR>(v[0], v[1], v[2], v[3]);
+            } else {
+                // radix 8 = 2 x 4: DFT4 of even and odd inputs, twiddle w8^c, combine
+                double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+                double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+                bf4<DIR>(e0, e1, e2, e3);
+                bf4<DIR>(o0, o1, o2, o3);
+                o1 = cmul(o1, w16<DIR, 2>());
+                o2 = cmul(o2, w16<DIR, 4>());
+                o3 = cmul(o3, w16<DIR, 6>());
+                v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+                v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+                v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+                v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int i = threadIdx.x + q * blockDim.x;
+        if (i < NB) {
+            const int k = i & (p - 1);
+            const int j = ((i - k) << r) + k;
+#pragma unroll
+            for (int t = 0; t < R; ++t) x[j + t * p] = u[q * R + t];
+        }
+    }
+    __syncthreads();
+}
+
+// Block-wide in-place FFT of length N = 2^logN (16 <= N <= 8192) held in LDS:
+// Stockham radix-16 passes, one butterfly per thread in registers, then one
+// radix-2/4/8 pass for the remaining factor.  Needs blockDim.x >= N/16.
 //   DIR = -1:  X_j = sum_k x_k exp(-2 pi i j k / N)
 //   DIR = +1:  X_j = sum_k x_k exp(+2 pi i j k / N)   (no 1/N)
-// tw[e] = exp(-2 pi i e / N2) of the plan; N divides N2 = N here.
+// tw[e] = exp(-2 pi i e / N).
 template <int DIR>
-__device__ void block_fft(double2* x, int N, int logN, const double2* __restrict__ tw)
+__device__ __forceinline__ void block_fft(double2* x, int N, int logN, const double2* __restrict__ tw)
 {
-    const int T = blockDim.x, tid = threadIdx.x;
+    const int i = threadIdx.x;
     int p = 1, logp = 0;
     __syncthreads();
-    if (logN & 1) {
-        const int NB = N >> 1;
-        double2 u[4][2];
+    while (logN - logp >= 4) {
+        const int NB = N >> 4;
+        double2 u[16];
+        const int k = i & (p - 1);
+        if (i < NB) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int i = tid + q * T;
-            if (i < NB) { u[q][0] = x[i]; u[q][1] = x[i + NB]; }
+            for (int t = 0; t < 16; ++t) u[t] = x[i + t * NB];
+            double2 w = tw[k << (logN - logp - 4)];
+            if (DIR > 0) w = cconj(w);
+            twiddle_powers<16>(u, w);
+            dft16<DIR>(u);
         }
         __syncthreads();
+        if (i < NB) {
+            const int j = ((i - k) << 4) + k;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int i = tid + q * T;
-            if (i < NB) {
-                x[2 * i] = cadd(u[q][0], u[q][1]);
-                x[2 * i + 1] = csub(u[q][0], u[q][1]);
-            }
+            for (int t = 0; t < 16; ++t) x[j + t * p] = u[t];
         }
-        p = 2; logp = 1;
-        __syncthreads();
-    }
-    const int NB = N >> 2;
-    while (p < N) {
-        double2 u[2][4];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            int i = tid + q * T;
-            if (i < NB) {
-#pragma unroll
-                for (int t = 0; t < 4; ++t) u[q][t] = x[i + t * NB];
-            }
-        }
-        __syncthreads();
-        const int sh = logN - logp - 2;  // log2(N / (4p))
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            int i = tid + q * T;
-            if (i < NB) {
-                const int k = i & (p - 1);
-#pragma unroll
-                for (int t = 1; t < 4; ++t) {
-                    double2 w = tw[(t * k) << sh];
-                    if (DIR > 0) w = cconj(w);
-                    u[q][t] = cmul(u[q][t], w);
-                }
-                double2 a0 = cadd(u[q][0], u[q][2]);
-                double2 a1 = csub(u[q][0], u[q][2]);
-                double2 a2 = cadd(u[q][1], u[q][3]);
-                double2 a3 = mul_dir_i<DIR>(csub(u[q][1], u[q][3]));
-                const int j = ((i - k) << 2) + k;
-                x[j] = cadd(a0, a2);
-                x[j + p] = cadd(a1, a3);
-                x[j + 2 * p] = csub(a0, a2);
-                x[j + 3 * p] = csub(a1, a3);
-            }
-        }
-        p <<= 2; logp += 2;
+        p <<= 4; logp += 4;
         __syncthreads();
     }
+    const int r = logN - logp;
+    if (r == 1) last_pass<DIR, 2>(x, N, logN, p, logp, tw);
+    else if (r == 2) last_pass<DIR, 4>(x, N, logN, p, logp, tw);
+    else if (r == 3) last_pass<DIR, 8>(x, N, logN, p, logp, tw);
 }
 
 // Bluestein DFT of length N1 of the chirped, zero-padded sequence already in
 // x[0..N2): on return x[k] * chirp[k] = sum_j a_j exp(-2 pi i j k / N1), k < N1.
-__device__ void bluestein_core(double2* x, const Plan& p)
+__device__ __forceinline__ void bluestein_core(double2* x, const Plan& p)
 {
     block_fft<-1>(x, p.N2, p.logN2, p.tw);
     for (int j = threadIdx.x; j < p.N2; j += blockDim.x) x[j] = cmul(x[j], p.bhat[j]);
@@ -121,7 +220,7 @@ __device__ __forceinline__ int xcd_column(int ncol)
 // Forward phi stage (Sec. IV-D): G_m(theta_t) = 2pi/N1 sum_p f(t, p) e^{-i m phi_p}.
 // Output G[t][m + L-1].
 template <int REAL>
-__global__ void k_phi_forward(Plan p, const void* __restrict__ map, double2* __restrict__ G)
+__global__ __launch_bounds__(512) void k_phi_forward(Plan p, const void* __restrict__ map, double2* __restrict__ G)
 {
     extern __shared__ double2 A[];
     const int t = blockIdx.x, L = p.L, N1 = p.N1;
@@ -149,7 +248,7 @@ __global__ void k_phi_forward(Plan p, const void* __restrict__ map, double2* __r
 //   fold     H_{m,0} = G_{m,0},  H_{m,n} = G_{m,n} + (-1)^{m+s} G_{m,-n}  (Eq.(Fmm_sym1)).
 // Output: Hp records (see mw_internal.h); order m writes its slot of row |m|,
 // including the zero pad entry n = L when L is odd.
-__global__ void k_theta_forward(Plan p, int s, const double2* __restrict__ G, double* __restrict__ Hp)
+__global__ __launch_bounds__(512) void k_theta_forward(Plan p, int s, const double2* __restrict__ G, double* __restrict__ Hp)
 {
     extern __shared__ double2 A[];
     const int L = p.L, N1 = p.N1, N2 = p.N2;
@@ -166,7 +265,7 @@ __global__ void k_theta_forward(Plan p, int s, const double2* __restrict__ G, do
         A[j] = v;
     }
     bluestein_core(A, p);
-    // F_{m'} into registers (N1 <= 8 * blockDim.x), then scatter to slot m' mod N2.
+    // F_{m'} into registers (N1 <= N2/2 <= 8 * blockDim.x), then scatter to slot m' mod N2.
     double2 r[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -204,7 +303,7 @@ __global__ void k_theta_forward(Plan p, int s, const double2* __restrict__ G, do
 //   F_m(theta_t) = sum_{m'} F_{m m'} e^{i m' theta_t}, t < L only,
 // from the folded F[m + L-1][n] (n >= 0) with F_{m,-n} = (-1)^{m+s} F_{m,n}.
 // Output Ft[t][m + L-1].
-__global__ void k_theta_inverse(Plan p, int s, const double2* __restrict__ F, double2* __restrict__ Ft)
+__global__ __launch_bounds__(512) void k_theta_inverse(Plan p, int s, const double2* __restrict__ F, double2* __restrict__ Ft)
 {
     extern __shared__ double2 A[];
     const int L = p.L, N1 = p.N1, N2 = p.N2;
@@ -232,7 +331,7 @@ __global__ void k_theta_inverse(Plan p, int s, const double2* __restrict__ F, do
 
 // Inverse phi stage (Eq.(f_pfft)): f(t, p) = sum_m F_m(theta_t) e^{i m phi_p}.
 template <int REAL>
-__global__ void k_phi_inverse(Plan p, const double2* __restrict__ Ft, void* __restrict__ map)
+__global__ __launch_bounds__(512) void k_phi_inverse(Plan p, const double2* __restrict__ Ft, void* __restrict__ map)
 {
     extern __shared__ double2 A[];
     const int t = blockIdx.x, L = p.L, N1 = p.N1;
@@ -254,7 +353,7 @@ __global__ void k_phi_inverse(Plan p, const double2* __restrict__ Ft, void* __re
 
 int fft_threads(const Plan& p)
 {
-    int t = p.N2 / 8;
+    int t = p.N2 / 16;
     if (t < 64) t = 64;
     if (t > 1024) t = 1024;
     return t;
