@@ -5,6 +5,7 @@ for l >= 2 (seed 1002).  One step = one inverse (f_lm -> map) plus one forward
 (map -> f_lm) on data resident in HBM.  Prints ONE JSON line.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -16,6 +17,21 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+
+# HBM traffic of the contraction kernels per launch at L=512 s=2, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters
+# read for a plain copy of known size (profiles/traffic_contract_L512_s2.md).
+# Valid only while the kernel source is unchanged: keyed by its SHA-256.
+TRAFFIC = {}
+KERNEL_SOURCES = ("paper_1110_6298_amd/csrc/mw_contract.hip", "paper_1110_6298_amd/csrc/mw_internal.h")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def contraction_flops(L, s):
@@ -40,6 +56,11 @@ def main():
     ap.add_argument("--L", type=int, default=512)
     ap.add_argument("--spin", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum CPU time of the oracle baseline sample (whole round trips)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the timed work, negate a float64 buffer of this many MiB once "
+                         "(a plain read+write kernel of known size, for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -97,6 +118,15 @@ def main():
         else "contract_inverse"
     achieved = flops / (per_kernel[dom_c] * 1e-3)
 
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
     x_h = xmap.cpu().numpy()
     back_h = back.cpu().numpy()
     result = {
@@ -121,18 +151,26 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
                      "flops_per_launch": flops},
     }
+    tr = TRAFFIC.get((dom_c, L, s))
+    if tr is not None and tr["source_sha256"] == kernel_source_hash():
+        result["roofline"]["traffic"] = tr["bytes"]
 
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
         t = time.perf_counter()
-        xo = oracle.inverse(flm_h, L, s)
-        fo = oracle.forward(xo, L, s)
-        dt = time.perf_counter() - t
-        result["cpu_baseline"] = {"value": 1.0 / dt, "unit": "round trips/s", "cores": oracle.max_threads(),
+        count = 0
+        while True:
+            xo = oracle.inverse(flm_h, L, s)
+            fo = oracle.forward(xo, L, s)
+            count += 1
+            dt = time.perf_counter() - t
+            if dt >= args.cpu_seconds:
+                break
+        result["cpu_baseline"] = {"value": count / dt, "unit": "round trips/s", "cores": oracle.max_threads(),
                                   "kind": "oracle",
-                                  "sample": "one full round trip (inverse + forward) of the same L=%d s=%d map, "
-                                            "%.1f s" % (L, s, dt)}
+                                  "sample": "%d full round trips (inverse + forward) of the same L=%d s=%d map, "
+                                            "%.1f s" % (count, L, s, dt)}
         result["max_rel_err_vs_oracle"] = {"inverse_map": rel(x_h, xo), "forward_coeffs": rel(back_h, fo)}
     print(json.dumps(result))
 

@@ -11,7 +11,8 @@
  *   1 theta stage, forward      4 theta stage, inverse
  *   2 contraction, forward      5 phi stage, inverse
  *   6 contraction, forward adjoint   7 contraction, inverse adjoint
- *   8 other (adjoint Fourier stages, batched helpers)
+ *   8 other: the inverse's coefficient staging kernel, adjoint Fourier stages,
+ *     batched helpers
  */
 #ifndef MW_PROFILE_H
 #define MW_PROFILE_H

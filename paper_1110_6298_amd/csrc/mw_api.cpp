@@ -190,10 +190,11 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
                 });
         } else {
             if (e == hipSuccess)
-                e = staged(3, st, [&] {
-                    return mw::launch_contract_inverse(*p, *sp, s, reality[b], (const double2*)ptrs[2 * b], W2,
-                                                       W0, st);
+                e = staged(8, st, [&] {
+                    return mw::launch_inverse_stream(*p, s, reality[b], (const double2*)ptrs[2 * b], W2, st);
                 });
+            if (e == hipSuccess)
+                e = staged(3, st, [&] { return mw::launch_contract_inverse(*p, *sp, s, W2, W0, st); });
             if (e == hipSuccess)
                 e = staged(4, st, [&] { return mw::launch_theta_inverse(*p, s, W0, W1, st); });
             if (e == hipSuccess)

@@ -250,16 +250,20 @@ __device__ __forceinline__ void ck_level(double& v0, double& v1, int k0, int k1,
 // segment order.
 template <int MT, bool EXT>
 __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
-    const double* __restrict__ Hp, double2* __restrict__ flm, const double* __restrict__ Rt,
+    const double* __restrict__ Hp, double2* __restrict__ flm, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,
     const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int2* __restrict__ work, int L, int Lp,
     int s, int segf)
 {
     __shared__ double2 red[SEG_MAX - 1][MT][4][64];
+    extern __shared__ double Rt[];   // copy of the 1/sqrt table (2L+8 entries)
     const int grp = blockIdx.x;
     const int w = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int l0 = uniform(work[grp].x), mb = uniform(work[grp].y);
+    if (l0 < 0) return;   // padding entry of the work list
+    for (int i = threadIdx.x; i < 2 * L + 8; i += blockDim.x) Rt[i] = Rtg[i];
+    __syncthreads();
     const int l = l0 + lane;
     const bool valid = l < L;
     const int le = valid ? l : L - 1;
@@ -391,27 +395,45 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
 // for l < Lp (zero where l < m or l >= L), where sp/sm fold the (-1)^l factors of
 // Delta^l_{n,-m} and Delta^l_{n,-s}: sp = (-1)^l for s >= 0 (else 1), sm = (-1)^l
 // for s < 0 (else 1).  Real maps read only m >= 0: f_{l,-m} = (-1)^m conj(f_{l,m}).
-__global__ void k_inverse_stream(const double2* __restrict__ flm, double* __restrict__ fs,
-                                 const double* __restrict__ cl, int L, int Lp, int s, int real)
+// Inverse coefficient stream: record (c_l sp(l) f_{l,m}, c_l sm(l) f_{l,-m}) at
+// [(m*Lp + l)*4] for 0 <= m <= l < L (zero elsewhere, l < Lp), where sp and sm
+// are the degree-parity factors of the +m and -m terms (Eq. for F_{m m'} with
+// the order symmetries of Delta).  A 32(l) x 8(m) tile is read along m (rows of
+// f_lm are contiguous in m) and written along l through LDS.
+constexpr int STR_L = 32, STR_M = 8;
+
+__global__ __launch_bounds__(256) void k_inverse_stream(const double2* __restrict__ flm, double* __restrict__ fs,
+                                                        const double* __restrict__ cl, int L, int Lp, int s,
+                                                        int real)
 {
-    const int m = blockIdx.y;
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= Lp) return;
-    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-    if (l < L && m <= l) {
-        const double c = cl[l];
-        const double par = (l & 1) ? -1.0 : 1.0;
-        const double sp = (s >= 0) ? par : 1.0;
-        const double sm = (s >= 0) ? 1.0 : par;
-        const double2 fp = flm[(size_t)l * l + l + m];
-        double2 fm;
-        if (real) fm = (m & 1) ? make_double2(-fp.x, fp.y) : make_double2(fp.x, -fp.y);
-        else fm = flm[(size_t)l * l + l - m];
-        a = make_double2(c * sp * fp.x, c * sp * fp.y);
-        b = make_double2(c * sm * fm.x, c * sm * fm.y);
+    __shared__ double2 ta[STR_L][STR_M + 1], tb[STR_L][STR_M + 1];
+    const int l0 = blockIdx.x * STR_L, m0 = blockIdx.y * STR_M;
+    {
+        const int i = threadIdx.x / STR_M, k = threadIdx.x % STR_M;   // read: l = l0+i, m = m0+k
+        const int l = l0 + i, m = m0 + k;
+        double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+        if (l < L && m <= l) {
+            const size_t c = (size_t)l * l + l;
+            a = flm[c + m];
+            if (real) b = (m & 1) ? make_double2(-a.x, a.y) : make_double2(a.x, -a.y);
+            else b = flm[c - m];
+        }
+        ta[i][k] = a;
+        tb[i][k] = b;
     }
-    double* rec = fs + ((size_t)m * Lp + l) * 4;
-    rec[0] = a.x; rec[1] = a.y; rec[2] = b.x; rec[3] = b.y;
+    __syncthreads();
+    {
+        const int i = threadIdx.x % STR_L, k = threadIdx.x / STR_L;   // write: l = l0+i, m = m0+k
+        const int l = l0 + i, m = m0 + k;
+        if (m >= L || l >= Lp) return;
+        const double c = (l < L) ? cl[l] : 0.0;
+        const double par = (l & 1) ? -c : c;
+        const double sp = (s >= 0) ? par : c;
+        const double sm = (s >= 0) ? c : par;
+        const double2 a = ta[i][k], b = tb[i][k];
+        double4* rec = (double4*)(fs + ((size_t)m * Lp + l) * 4);
+        *rec = make_double4(sp * a.x, sp * a.y, sm * b.x, sm * b.y);
+    }
 }
 
 template <bool EXT>
@@ -566,17 +588,21 @@ struct CkOff { size_t off[SEG_MAX]; };
 // the checkpoint planes.  Partial sums are added in LDS in segment order.
 template <bool EXT>
 __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
-    const double* __restrict__ fs, double2* __restrict__ F, const double* __restrict__ Rt,
+    const double* __restrict__ fs, double2* __restrict__ F, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
     const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,
     const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work, int L, int Lp, int s, int segi,
     int nsegi)
 {
     __shared__ double2 red[SEG_MAX - 1][2][64];
+    extern __shared__ double Rt[];   // copy of the 1/sqrt table (2L+8 entries)
     const int grp = blockIdx.x;
     const int w = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int n0 = uniform(work[grp].x), m = uniform(work[grp].y);
+    if (n0 < 0) return;   // padding entry of the work list
+    for (int i = threadIdx.x; i < 2 * L + 8; i += blockDim.x) Rt[i] = Rtg[i];
+    __syncthreads();
     const int n = n0 + lane;
     const bool valid = n < L;
     const int ne = valid ? n : L - 1;
@@ -691,32 +717,35 @@ hipError_t launch_contract_forward(const Plan& p, int s, int real, const double*
 {
     (void)real;
     const dim3 grid(p.nworkf), block(64 * SEG_MAX);
+    const size_t lds = (size_t)(2 * p.L + 8) * sizeof(double);
     if (p.ext)
-        hipLaunchKernelGGL((k_contract_forward<MT_FWD, true>), grid, block, 0, st, Hp, flm, p.rtab, p.edge, p.edgek,
+        hipLaunchKernelGGL((k_contract_forward<MT_FWD, true>), grid, block, lds, st, Hp, flm, p.rtab, p.edge, p.edgek,
                            p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
     else
-        hipLaunchKernelGGL((k_contract_forward<MT_FWD, false>), grid, block, 0, st, Hp, flm, p.rtab, p.edge,
+        hipLaunchKernelGGL((k_contract_forward<MT_FWD, false>), grid, block, lds, st, Hp, flm, p.rtab, p.edge,
                            p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
     return hipGetLastError();
 }
 
-hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, int real, const double2* flm,
-                                   double* fs, double2* F, hipStream_t st)
+hipError_t launch_inverse_stream(const Plan& p, int s, int real, const double2* flm, double* fs, hipStream_t st)
 {
-    {
-        const dim3 grid((p.Lp + 255) / 256, p.L);
-        hipLaunchKernelGGL(k_inverse_stream, grid, dim3(256), 0, st, flm, fs, p.cl, p.L, p.Lp, s, real);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+    const dim3 grid((p.Lp + STR_L - 1) / STR_L, (p.L + STR_M - 1) / STR_M);
+    hipLaunchKernelGGL(k_inverse_stream, grid, dim3(256), 0, st, flm, fs, p.cl, p.L, p.Lp, s, real);
+    return hipGetLastError();
+}
+
+hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, const double* fs, double2* F,
+                                   hipStream_t st)
+{
     CkOff off;
     for (int j = 0; j < SEG_MAX; ++j) off.off[j] = p.cki_off[j];
     const dim3 grid(p.nworki), block(64 * SEG_MAX);
+    const size_t lds = (size_t)(2 * p.L + 8) * sizeof(double);
     if (p.ext)
-        hipLaunchKernelGGL((k_contract_inverse<true>), grid, block, 0, st, fs, F, p.rtab, p.edge, p.edgek, p.lco,
+        hipLaunchKernelGGL((k_contract_inverse<true>), grid, block, lds, st, fs, F, p.rtab, p.edge, p.edgek, p.lco,
                            sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
     else
-        hipLaunchKernelGGL((k_contract_inverse<false>), grid, block, 0, st, fs, F, p.rtab, p.edge, p.edgek, p.lco,
+        hipLaunchKernelGGL((k_contract_inverse<false>), grid, block, lds, st, fs, F, p.rtab, p.edge, p.edgek, p.lco,
                            sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
     return hipGetLastError();
 }

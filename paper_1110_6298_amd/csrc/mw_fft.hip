@@ -26,6 +26,10 @@ __device__ __forceinline__ double2 mul_dir_i(double2 a)
     return DIR < 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
 }
 
+// LDS index with one pad slot per 16 entries: the stride-16 stores of a
+// radix-16 pass then fall on distinct banks.
+__device__ __forceinline__ int P(int i) { return i + (i >> 4); }
+
 // In-place DFT of 4 values: a_k <- sum_j a_j w^{jk}, w = exp(DIR 2 pi i/4).
 template <int DIR>
 __device__ __forceinline__ void bf4(double2& a0, double2& a1, double2& a2, double2& a3)
@@ -104,9 +108,10 @@ __device__ __forceinline__ void twiddle_powers(double2* u, double2 w)
 
 // Final Stockham pass of radix R = 2, 4 or 8 (the factor left after the radix-16
 // passes): each thread holds up to 16/R butterflies in one 16-value register set.
+// With post != nullptr every output X_j is stored as X_j * post[j].
 template <int DIR, int R>
 __device__ __forceinline__ void last_pass(double2* x, int N, int logN, int p, int logp,
-                                          const double2* __restrict__ tw)
+                                          const double2* __restrict__ tw, const double2* __restrict__ post)
 {
     constexpr int r = (R == 2) ? 1 : (R == 4) ? 2 : 3;
     constexpr int QM = 16 / R;
@@ -118,7 +123,7 @@ __device__ __forceinline__ void last_pass(double2* x, int N, int logN, int p, in
         if (i < NB) {
             const int k = i & (p - 1);
 #pragma unroll
-            for (int t = 0; t < R; ++t) u[q * R + t] = x[i + t * NB];
+            for (int t = 0; t < R; ++t) u[q * R + t] = x[P(i + t * NB)];
             double2 w = tw[k << (logN - logp - r)];
             if (DIR > 0) w = cconj(w);
             twiddle_powers<R>(u + q * R, w);
@@ -151,21 +156,28 @@ __device__ __forceinline__ void last_pass(double2* x, int N, int logN, int p, in
         if (i < NB) {
             const int k = i & (p - 1);
             const int j = ((i - k) << r) + k;
+            if (post) {
 #pragma unroll
-            for (int t = 0; t < R; ++t) x[j + t * p] = u[q * R + t];
+                for (int t = 0; t < R; ++t) x[P(j + t * p)] = cmul(u[q * R + t], post[j + t * p]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < R; ++t) x[P(j + t * p)] = u[q * R + t];
+            }
         }
     }
     __syncthreads();
 }
 
-// Block-wide in-place FFT of length N = 2^logN (16 <= N <= 8192) held in LDS:
-// Stockham radix-16 passes, one butterfly per thread in registers, then one
-// radix-2/4/8 pass for the remaining factor.  Needs blockDim.x >= N/16.
+// Block-wide in-place FFT of length N = 2^logN (16 <= N <= 8192) held in LDS
+// at padded positions P(j): Stockham radix-16 passes, one butterfly per thread
+// in registers, then one radix-2/4/8 pass for the remaining factor.  Needs
+// blockDim.x >= N/16.
 //   DIR = -1:  X_j = sum_k x_k exp(-2 pi i j k / N)
 //   DIR = +1:  X_j = sum_k x_k exp(+2 pi i j k / N)   (no 1/N)
-// tw[e] = exp(-2 pi i e / N).
+// tw[e] = exp(-2 pi i e / N).  With post != nullptr the result is X_j * post[j].
 template <int DIR>
-__device__ __forceinline__ void block_fft(double2* x, int N, int logN, const double2* __restrict__ tw)
+__device__ __forceinline__ void block_fft(double2* x, int N, int logN, const double2* __restrict__ tw,
+                                          const double2* __restrict__ post = nullptr)
 {
     const int i = threadIdx.x;
     int p = 1, logp = 0;
@@ -176,7 +188,7 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const dou
         const int k = i & (p - 1);
         if (i < NB) {
 #pragma unroll
-            for (int t = 0; t < 16; ++t) u[t] = x[i + t * NB];
+            for (int t = 0; t < 16; ++t) u[t] = x[P(i + t * NB)];
             double2 w = tw[k << (logN - logp - 4)];
             if (DIR > 0) w = cconj(w);
             twiddle_powers<16>(u, w);
@@ -186,23 +198,26 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const dou
         if (i < NB) {
             const int j = ((i - k) << 4) + k;
 #pragma unroll
-            for (int t = 0; t < 16; ++t) x[j + t * p] = u[t];
+            for (int t = 0; t < 16; ++t) x[P(j + t * p)] = u[t];
         }
         p <<= 4; logp += 4;
         __syncthreads();
     }
     const int r = logN - logp;
-    if (r == 1) last_pass<DIR, 2>(x, N, logN, p, logp, tw);
-    else if (r == 2) last_pass<DIR, 4>(x, N, logN, p, logp, tw);
-    else if (r == 3) last_pass<DIR, 8>(x, N, logN, p, logp, tw);
+    if (r == 1) last_pass<DIR, 2>(x, N, logN, p, logp, tw, post);
+    else if (r == 2) last_pass<DIR, 4>(x, N, logN, p, logp, tw, post);
+    else if (r == 3) last_pass<DIR, 8>(x, N, logN, p, logp, tw, post);
+    else if (post) {
+        for (int j = threadIdx.x; j < N; j += blockDim.x) x[P(j)] = cmul(x[P(j)], post[j]);
+        __syncthreads();
+    }
 }
 
-// Bluestein DFT of length N1 of the chirped, zero-padded sequence already in
-// x[0..N2): on return x[k] * chirp[k] = sum_j a_j exp(-2 pi i j k / N1), k < N1.
+// Bluestein DFT of length N1 of the chirped, zero-padded sequence a_j already in
+// x[P(j)], j < N2: on return x[P(k)] * chirp[k] = sum_j a_j exp(-2 pi i j k / N1), k < N1.
 __device__ __forceinline__ void bluestein_core(double2* x, const Plan& p)
 {
-    block_fft<-1>(x, p.N2, p.logN2, p.tw);
-    for (int j = threadIdx.x; j < p.N2; j += blockDim.x) x[j] = cmul(x[j], p.bhat[j]);
+    block_fft<-1>(x, p.N2, p.logN2, p.tw, p.bhat);
     block_fft<+1>(x, p.N2, p.logN2, p.tw);
 }
 
@@ -231,13 +246,13 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, const void* __restr
                              : ((const double2*)map)[(size_t)t * N1 + j];
             v = cmul(f, p.chirp[j]);
         }
-        A[j] = v;
+        A[P(j)] = v;
     }
     bluestein_core(A, p);
     const double sc = 2.0 * 3.14159265358979323846 / (double)N1;
     for (int k = threadIdx.x; k < N1; k += blockDim.x) {
         const int m = (k <= L - 1) ? k : k - N1;
-        G[(size_t)t * N1 + (m + L - 1)] = cscale(cmul(A[k], p.chirp[k]), sc);
+        G[(size_t)t * N1 + (m + L - 1)] = cscale(cmul(A[P(k)], p.chirp[k]), sc);
     }
 }
 
@@ -262,7 +277,7 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, int s, const doub
             double2 g = (j < L) ? G[(size_t)j * N1 + mi] : cscale(G[(size_t)(2 * L - 2 - j) * N1 + mi], sig);
             v = cmul(g, p.chirp[j]);
         }
-        A[j] = v;
+        A[P(j)] = v;
     }
     bluestein_core(A, p);
     // F_{m'} into registers (N1 <= N2/2 <= 8 * blockDim.x), then scatter to slot m' mod N2.
@@ -270,28 +285,27 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, int s, const doub
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int k = threadIdx.x + q * blockDim.x;
-        if (k < N1) r[q] = cmul(cmul(A[k], p.chirp[k]), p.thtw[k]);
+        if (k < N1) r[q] = cmul(cmul(A[P(k)], p.chirp[k]), p.thtw[k]);
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < N2; j += blockDim.x) A[j] = make_double2(0.0, 0.0);
+    for (int j = threadIdx.x; j < N2; j += blockDim.x) A[P(j)] = make_double2(0.0, 0.0);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int k = threadIdx.x + q * blockDim.x;
         if (k < N1) {
             const int mp = (k <= L - 1) ? k : k - N1;
-            A[(mp + N2) & (N2 - 1)] = r[q];
+            A[P((mp + N2) & (N2 - 1))] = r[q];
         }
     }
-    block_fft<+1>(A, N2, p.logN2, p.tw);
-    for (int j = threadIdx.x; j < N2; j += blockDim.x) A[j] = cmul(A[j], p.what[j]);
+    block_fft<+1>(A, N2, p.logN2, p.tw, p.what);
     block_fft<-1>(A, N2, p.logN2, p.tw);
     const int am = m < 0 ? -m : m;
     for (int n = threadIdx.x; n < p.Lp; n += blockDim.x) {
         double2 v = make_double2(0.0, 0.0);
         if (n < L) {
-            v = A[n];
-            if (n > 0) v = cadd(v, cscale(A[N2 - n], sig));
+            v = A[P(n)];
+            if (n > 0) v = cadd(v, cscale(A[P(N2 - n)], sig));
         }
         double* rec = Hp + ((size_t)am * p.Lp + n) * 4;
         if (m >= 0) { rec[0] = v.x; rec[1] = v.y; }
@@ -322,11 +336,11 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, int s, const doub
             double2 y = cmul(f, cscale(cconj(p.thtw[j]), unscale));
             v = cmul(cconj(y), p.chirp[j]);
         }
-        A[j] = v;
+        A[P(j)] = v;
     }
     bluestein_core(A, p);
     for (int t = threadIdx.x; t < L; t += blockDim.x)
-        Ft[(size_t)t * N1 + mi] = cconj(cmul(A[t], p.chirp[t]));
+        Ft[(size_t)t * N1 + mi] = cconj(cmul(A[P(t)], p.chirp[t]));
 }
 
 // Inverse phi stage (Eq.(f_pfft)): f(t, p) = sum_m F_m(theta_t) e^{i m phi_p}.
@@ -341,11 +355,11 @@ __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, const double2* __re
             const int m = (j <= L - 1) ? j : j - N1;
             v = cmul(cconj(Ft[(size_t)t * N1 + (m + L - 1)]), p.chirp[j]);
         }
-        A[j] = v;
+        A[P(j)] = v;
     }
     bluestein_core(A, p);
     for (int k = threadIdx.x; k < N1; k += blockDim.x) {
-        double2 out = cconj(cmul(A[k], p.chirp[k]));
+        double2 out = cconj(cmul(A[P(k)], p.chirp[k]));
         if (REAL) ((double*)map)[(size_t)t * N1 + k] = out.x;
         else ((double2*)map)[(size_t)t * N1 + k] = out;
     }
@@ -372,7 +386,7 @@ int xcd_grid(int ncol) { return 8 * ((ncol + 7) >> 3); }
 
 hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2* G, hipStream_t st)
 {
-    const size_t lds = (size_t)p.N2 * sizeof(double2);
+    const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     hipError_t e;
     if (real) {
         if ((e = set_lds(k_phi_forward<1>, lds)) != hipSuccess) return e;
@@ -386,7 +400,7 @@ hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2*
 
 hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, double* Hp, hipStream_t st)
 {
-    const size_t lds = (size_t)p.N2 * sizeof(double2);
+    const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     hipError_t e;
     if ((e = set_lds(k_theta_forward, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_theta_forward, dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s, G, Hp);
@@ -395,7 +409,7 @@ hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, double* 
 
 hipError_t launch_theta_inverse(const Plan& p, int s, const double2* F, double2* Ft, hipStream_t st)
 {
-    const size_t lds = (size_t)p.N2 * sizeof(double2);
+    const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     hipError_t e;
     if ((e = set_lds(k_theta_inverse, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_theta_inverse, dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s, F, Ft);
@@ -404,7 +418,7 @@ hipError_t launch_theta_inverse(const Plan& p, int s, const double2* F, double2*
 
 hipError_t launch_phi_inverse(const Plan& p, const double2* Ft, void* map, int real, hipStream_t st)
 {
-    const size_t lds = (size_t)p.N2 * sizeof(double2);
+    const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     hipError_t e;
     if (real) {
         if ((e = set_lds(k_phi_inverse<1>, lds)) != hipSuccess) return e;

@@ -37,7 +37,8 @@ struct Plan {
     double2* bhat = nullptr;    // FFT_N2 of the Bluestein kernel, divided by N2
     double2* what = nullptr;    // (2 pi/N2) * DFT_N2 of the theta weights w(k)
     double2* thtw = nullptr;    // exp(-i m' pi/N1)/(2 pi N1) at slot k = m' mod N1
-    // contraction work lists (int2: (block start, first order)); sorted longest first
+    // contraction work lists (int2: (block start, first order)), dealt over the 8
+    // XCDs by order and longest first; (-1, -1) entries are padding
     int2* workf = nullptr; int nworkf = 0;   // forward: (l0, m0)
     int2* worki = nullptr; int nworki = 0;   // inverse: (n0, m0)
     // Chain segmentation.  The forward splits every row recursion at the global
@@ -79,9 +80,11 @@ hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2*
 hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, double* Hp, hipStream_t st);
 hipError_t launch_contract_forward(const Plan& p, int s, int real, const double* Hp, double2* flm,
                                    hipStream_t st);
-// fs: per-map scratch of L x Lp x 4 doubles (the inverse's scaled coefficient stream).
-hipError_t launch_contract_inverse(const Plan& p, const SpinTable& st_, int s, int real,
-                                   const double2* flm, double* fs, double2* F, hipStream_t st);
+// fs: per-map scratch of L x Lp x 4 doubles (the inverse's scaled coefficient stream),
+// written by launch_inverse_stream and read by launch_contract_inverse.
+hipError_t launch_inverse_stream(const Plan& p, int s, int real, const double2* flm, double* fs, hipStream_t st);
+hipError_t launch_contract_inverse(const Plan& p, const SpinTable& st_, int s, const double* fs, double2* F,
+                                   hipStream_t st);
 hipError_t launch_theta_inverse(const Plan& p, int s, const double2* F, double2* Ft, hipStream_t st);
 hipError_t launch_phi_inverse(const Plan& p, const double2* Ft, void* map, int real, hipStream_t st);
 

@@ -319,20 +319,38 @@ int build_plan(int L, Plan& p, std::string& err)
         }
     }
 
-    // work lists (one entry per chain group; a workgroup runs its segments), longest first
+    // Work lists (one entry per chain group; a workgroup runs its segments).
+    // Workgroups are dealt round-robin over the 8 XCDs, so entry i runs on XCD
+    // i mod 8.  All groups of one order (block) go to the same XCD, where its L2
+    // serves the rows they share; within an XCD the longest groups go first.
+    // Shorter XCD lists are padded with (-1, -1) entries, which exit at once.
     {
-        std::vector<int2> wf;
+        auto deal = [](std::vector<std::vector<int2>>& per, std::vector<int2>& out) {
+            size_t n = 0;
+            for (auto& v : per) n = std::max(n, v.size());
+            out.clear();
+            for (size_t i = 0; i < n; ++i)
+                for (auto& v : per) out.push_back(i < v.size() ? v[i] : make_int2(-1, -1));
+        };
+        std::vector<std::vector<int2>> per(8);
         for (int l0 = 0; l0 < L; l0 += 64)
-            for (int m0 = 0; m0 <= std::min(l0 + 63, L - 1); m0 += MT_FWD) wf.push_back(make_int2(l0, m0));
-        std::stable_sort(wf.begin(), wf.end(), [](int2 a, int2 b) { return a.x > b.x; });
+            for (int m0 = 0; m0 <= std::min(l0 + 63, L - 1); m0 += MT_FWD)
+                per[(m0 / MT_FWD) & 7].push_back(make_int2(l0, m0));
+        for (auto& v : per)
+            std::stable_sort(v.begin(), v.end(), [](int2 a, int2 b) { return a.x > b.x; });
+        std::vector<int2> wf;
+        deal(per, wf);
         p.nworkf = (int)wf.size();
         if ((rc = upload(wf, &p.workf, p.bytes, err))) return rc;
-        std::vector<int2> wi;
+        for (auto& v : per) v.clear();
         for (int n0 = 0; n0 < L; n0 += 64)
-            for (int m0 = 0; m0 < L; m0 += MT_INV) wi.push_back(make_int2(n0, m0));
-        std::stable_sort(wi.begin(), wi.end(), [L](int2 a, int2 b) {
-            return (L - std::max(a.x, a.y)) > (L - std::max(b.x, b.y));
-        });
+            for (int m0 = 0; m0 < L; m0 += MT_INV) per[(m0 / MT_INV) & 7].push_back(make_int2(n0, m0));
+        for (auto& v : per)
+            std::stable_sort(v.begin(), v.end(), [L](int2 a, int2 b) {
+                return (L - std::max(a.x, a.y)) > (L - std::max(b.x, b.y));
+            });
+        std::vector<int2> wi;
+        deal(per, wi);
         p.nworki = (int)wi.size();
         if ((rc = upload(wi, &p.worki, p.bytes, err))) return rc;
     }
