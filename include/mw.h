@@ -83,15 +83,29 @@ int mw_forward(const int32_t* L, const int32_t* spin, const int32_t* reality, in
 int mw_inverse(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                void* const* ptrs, int32_t precision, void* stream);
 
-/* Conjugate transpose of the forward map with respect to the Euclidean inner
- * products on the L x (2L-1) grid and on the L*L coefficients:
- * ptrs[2b] = coeffs-space input, ptrs[2b+1] = map-space output (complex128;
- * reality must be 0).  This is the reverse-mode derivative of mw_forward. */
+/* Adjoint (conjugate transpose) of the forward map with respect to the Euclidean
+ * inner products on the full L x (2L-1) grid and on the L*L coefficients: the
+ * forward's stages (Sec. IV-D) transposed and conjugated in reverse order, i.e.
+ * contraction^H (= the inverse's contraction, Eq.(Fmm)), unfold, correlation with
+ * the conjugate weights (Eq.(Gmm_convolution)^H), positive-exponent theta DFT over
+ * the whole period (Eq.(Gmm)^H), fold of the periodic extension back onto
+ * t < L (Eq.(Gmt)^H) and (2 pi/N1) x the inverse phi DFT (Eq.(Gmt)^H).  It is not
+ * the inverse transform.  ptrs[2b] = coeffs-space input (complex128, all L*L
+ * entries used, entries with l < |spin| ignored), ptrs[2b+1] = map-space output.
+ * With reality = 1 the output is the float64 map Re(A^H y), the adjoint of the
+ * forward restricted to real maps.  This is the reverse-mode derivative of
+ * mw_forward: for a real loss, grad_map = A^H grad_coeffs. */
 int mw_forward_adjoint(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                        void* const* ptrs, int32_t precision, void* stream);
 
-/* Conjugate transpose of the inverse map: ptrs[2b] = map-space input
- * (complex128), ptrs[2b+1] = coeffs-space output (reality must be 0). */
+/* Adjoint of the inverse map (Sec. IV-E transposed): Y^H g = contraction^H of
+ * Z_{m m'} = sum_{t<L} e^{-i m' theta_t} sum_p e^{-i m phi_p} g(t, p), where the
+ * contraction^H is the forward's Eq.(flm_wig) with the fold of Eq.(Fmm_sym1)
+ * (no weights, no extension, no 1/(2 pi N1)).  ptrs[2b] = map-space input,
+ * ptrs[2b+1] = coeffs-space output (complex128, L*L entries, 0 for l < |spin|).
+ * With reality = 1 the input is a float64 map and the output is the adjoint of
+ * the real inverse (which reads only m >= 0): y_{l,m} + (-1)^m conj(y_{l,-m})
+ * for m > 0, y_{l,0} unchanged, and 0 for m < 0. */
 int mw_inverse_adjoint(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                        void* const* ptrs, int32_t precision, void* stream);
 

@@ -19,8 +19,8 @@ import os
 from typing import Sequence
 
 __all__ = ["forward", "inverse", "forward_adjoint", "inverse_adjoint", "forward_batch",
-           "inverse_batch", "prepare", "release", "workspace_size", "library", "MWError",
-           "FP64", "FP32C", "EXPORTS", "LIB_PATH"]
+           "inverse_batch", "forward_adjoint_batch", "inverse_adjoint_batch", "prepare", "release",
+           "workspace_size", "library", "MWError", "FP64", "FP32C", "EXPORTS", "LIB_PATH"]
 
 FP64, FP32C = 0, 1
 _PREC = {"fp64": FP64, "fp32c": FP32C, FP64: FP64, FP32C: FP32C}
@@ -124,42 +124,63 @@ def _map_shape(L):
     return (L, 2 * L - 1)
 
 
-def forward_batch(maps, Ls, spins, realities=None, precision=FP64, outs=None, stream=None):
-    """Forward transforms of a batch of maps in one library call."""
+_MAP, _COEF = "map", "coeffs"
+_OPS = {  # name: (input kind, output kind)
+    "mw_forward": (_MAP, _COEF),
+    "mw_inverse": (_COEF, _MAP),
+    "mw_forward_adjoint": (_COEF, _MAP),
+    "mw_inverse_adjoint": (_MAP, _COEF),
+}
+
+
+def _kind_spec(kind, L, real):
     import torch
-    n = len(maps)
+    if kind == _MAP:
+        return _map_shape(L), (torch.float64 if real else torch.complex128)
+    return (L * L,), torch.complex128
+
+
+def _batch(name, inputs, Ls, spins, realities, precision, outs, stream):
+    n = len(inputs)
+    if not (len(Ls) == len(spins) == n):
+        raise ValueError("inputs, Ls and spins must have the same length")
     realities = [0] * n if realities is None else list(realities)
     outs = list(outs) if outs is not None else [None] * n
+    kin, kout = _OPS[name]
+    import torch
     ptrs = []
     for b in range(n):
         L = int(Ls[b])
-        dt = (torch.float64,) if realities[b] else (torch.complex128,)
-        _check_tensor(maps[b], _map_shape(L), dt, "map %d" % b)
+        shp, dt = _kind_spec(kin, L, realities[b])
+        _check_tensor(inputs[b], shp, (dt,), "%s %d" % (kin, b))
+        shp, dt = _kind_spec(kout, L, realities[b])
         if outs[b] is None:
-            outs[b] = torch.empty(L * L, dtype=torch.complex128, device=maps[b].device)
-        _check_tensor(outs[b], (L * L,), (torch.complex128,), "coeffs %d" % b)
-        ptrs += [maps[b].data_ptr(), outs[b].data_ptr()]
-    call("mw_forward", Ls, spins, realities, ptrs, precision, stream)
+            outs[b] = torch.empty(shp, dtype=dt, device=inputs[b].device)
+        _check_tensor(outs[b], shp, (dt,), "%s %d" % (kout, b))
+        ptrs += [inputs[b].data_ptr(), outs[b].data_ptr()]
+    call(name, Ls, spins, realities, ptrs, precision, stream)
     return outs
+
+
+def forward_batch(maps, Ls, spins, realities=None, precision=FP64, outs=None, stream=None):
+    """Forward transforms of a batch of maps in one library call (maps of
+    reality 1 are float64, the others complex128)."""
+    return _batch("mw_forward", maps, Ls, spins, realities, precision, outs, stream)
 
 
 def inverse_batch(coeffs, Ls, spins, realities=None, precision=FP64, outs=None, stream=None):
     """Inverse transforms of a batch of coefficient vectors in one library call."""
-    import torch
-    n = len(coeffs)
-    realities = [0] * n if realities is None else list(realities)
-    outs = list(outs) if outs is not None else [None] * n
-    ptrs = []
-    for b in range(n):
-        L = int(Ls[b])
-        _check_tensor(coeffs[b], (L * L,), (torch.complex128,), "coeffs %d" % b)
-        dt = torch.float64 if realities[b] else torch.complex128
-        if outs[b] is None:
-            outs[b] = torch.empty(_map_shape(L), dtype=dt, device=coeffs[b].device)
-        _check_tensor(outs[b], _map_shape(L), (dt,), "map %d" % b)
-        ptrs += [coeffs[b].data_ptr(), outs[b].data_ptr()]
-    call("mw_inverse", Ls, spins, realities, ptrs, precision, stream)
-    return outs
+    return _batch("mw_inverse", coeffs, Ls, spins, realities, precision, outs, stream)
+
+
+def forward_adjoint_batch(coeffs, Ls, spins, realities=None, precision=FP64, outs=None, stream=None):
+    """Adjoints of the forward map (coefficients -> grid) for a batch."""
+    return _batch("mw_forward_adjoint", coeffs, Ls, spins, realities, precision, outs, stream)
+
+
+def inverse_adjoint_batch(maps, Ls, spins, realities=None, precision=FP64, outs=None, stream=None):
+    """Adjoints of the inverse map (grid -> coefficients) for a batch."""
+    return _batch("mw_inverse_adjoint", maps, Ls, spins, realities, precision, outs, stream)
 
 
 def forward(x, L: int, spin: int = 0, reality: int = 0, precision=FP64, out=None, stream=None):
@@ -172,26 +193,15 @@ def inverse(flm, L: int, spin: int = 0, reality: int = 0, precision=FP64, out=No
     return inverse_batch([flm], [L], [spin], [reality], precision, [out], stream)[0]
 
 
-def forward_adjoint(y, L: int, spin: int = 0, precision=FP64, out=None, stream=None):
-    """Conjugate transpose of the forward map: coefficients (L*L,) -> grid (L, 2L-1)."""
-    import torch
-    _check_tensor(y, (L * L,), (torch.complex128,), "coeffs")
-    if out is None:
-        out = torch.empty(_map_shape(L), dtype=torch.complex128, device=y.device)
-    _check_tensor(out, _map_shape(L), (torch.complex128,), "map")
-    call("mw_forward_adjoint", [L], [spin], [0], [y.data_ptr(), out.data_ptr()], precision, stream)
-    return out
+def forward_adjoint(y, L: int, spin: int = 0, reality: int = 0, precision=FP64, out=None, stream=None):
+    """Conjugate transpose of the forward map: coefficients (L*L,) -> grid (L, 2L-1)
+    (float64 Re(A^H y) when reality = 1)."""
+    return forward_adjoint_batch([y], [L], [spin], [reality], precision, [out], stream)[0]
 
 
-def inverse_adjoint(g, L: int, spin: int = 0, precision=FP64, out=None, stream=None):
+def inverse_adjoint(g, L: int, spin: int = 0, reality: int = 0, precision=FP64, out=None, stream=None):
     """Conjugate transpose of the inverse map: grid (L, 2L-1) -> coefficients (L*L,)."""
-    import torch
-    _check_tensor(g, _map_shape(L), (torch.complex128,), "map")
-    if out is None:
-        out = torch.empty(L * L, dtype=torch.complex128, device=g.device)
-    _check_tensor(out, (L * L,), (torch.complex128,), "coeffs")
-    call("mw_inverse_adjoint", [L], [spin], [0], [g.data_ptr(), out.data_ptr()], precision, stream)
-    return out
+    return inverse_adjoint_batch([g], [L], [spin], [reality], precision, [out], stream)[0]
 
 
 def prepare(Ls, spins, realities=None, precision=FP64) -> None:

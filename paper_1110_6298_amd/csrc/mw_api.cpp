@@ -72,7 +72,7 @@ int fail(int code, const char* fmt, ...)
 }
 
 int validate(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
-             void* const* ptrs, int32_t precision, bool need_ptrs, bool complex_only)
+             void* const* ptrs, int32_t precision, bool need_ptrs)
 {
     if (batch < 1) return fail(MW_EINVAL, "batch must be >= 1 (got %d)", batch);
     if (!L || !spin || !reality) return fail(MW_EINVAL, "L, spin and reality arrays must be non-NULL");
@@ -84,7 +84,6 @@ int validate(const int32_t* L, const int32_t* spin, const int32_t* reality, int3
             return fail(MW_EINVAL, "map %d: |spin| = %d must be < L = %d", b, spin[b], L[b]);
         if (reality[b] != 0 && reality[b] != 1) return fail(MW_EINVAL, "map %d: reality must be 0 or 1", b);
         if (reality[b] == 1 && spin[b] != 0) return fail(MW_EINVAL, "map %d: reality = 1 needs spin = 0", b);
-        if (complex_only && reality[b] == 1) return fail(MW_EINVAL, "map %d: adjoints take complex data", b);
         if (need_ptrs && (!ptrs[2 * b] || !ptrs[2 * b + 1])) return fail(MW_EINVAL, "map %d: NULL pointer", b);
     }
     return MW_OK;
@@ -150,18 +149,65 @@ int get_resources(DeviceState& d, int L, int as, bool need_spin, size_t ws_bytes
     return MW_OK;
 }
 
-enum class Op { Forward, Inverse };
+enum class Op { Forward, Inverse, ForwardAdjoint, InverseAdjoint };
+
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+
+// Launch sequence of one map.  Workspace: W0 (N1 x L complex), W1 (max of
+// N1 x L complex and the Hp records), W2 (the inverse's coefficient stream).
+hipError_t run_map(Op op, const Plan& p, const SpinTable* sp, int s, int real, const void* in, void* out,
+                   double2* W0, double2* W1, double* W2, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    const double phi_sc = TWO_PI / (double)p.N1;
+    switch (op) {
+    case Op::Forward:
+        e = staged(0, st, [&] { return mw::launch_phi_forward(p, in, real, W0, phi_sc, st); });
+        if (e == hipSuccess) e = staged(1, st, [&] { return mw::launch_theta_forward(p, s, W0, (double*)W1, st); });
+        if (e == hipSuccess)
+            e = staged(2, st, [&] { return mw::launch_contract_forward(p, s, real, (const double*)W1, (double2*)out, st); });
+        break;
+    case Op::Inverse:
+        e = staged(8, st, [&] { return mw::launch_inverse_stream(p, s, real, (const double2*)in, W2, st); });
+        if (e == hipSuccess) e = staged(3, st, [&] { return mw::launch_contract_inverse(p, *sp, s, W2, W0, st); });
+        if (e == hipSuccess) e = staged(4, st, [&] { return mw::launch_theta_inverse(p, s, W0, W1, st); });
+        if (e == hipSuccess) e = staged(5, st, [&] { return mw::launch_phi_inverse(p, W1, out, real, 1.0, st); });
+        break;
+    case Op::ForwardAdjoint:
+        // coefficients -> grid: the inverse's contraction is the conjugate transpose
+        // of the forward's contraction and fold; then the theta and phi adjoints.
+        // The coefficients are used as given (no real-map expansion): with real = 1
+        // the result is Re(A^H y), the adjoint of the forward restricted to real maps.
+        e = staged(8, st, [&] { return mw::launch_inverse_stream(p, s, 0, (const double2*)in, W2, st); });
+        if (e == hipSuccess) e = staged(6, st, [&] { return mw::launch_contract_inverse(p, *sp, s, W2, W0, st); });
+        if (e == hipSuccess) e = staged(8, st, [&] { return mw::launch_theta_forward_adjoint(p, s, W0, W1, st); });
+        if (e == hipSuccess) e = staged(8, st, [&] { return mw::launch_phi_inverse(p, W1, out, real, phi_sc, st); });
+        break;
+    case Op::InverseAdjoint:
+        // grid -> coefficients: phi and theta adjoints, then the forward's
+        // contraction (the conjugate transpose of the inverse's).  With real = 1
+        // the real-map coefficient expansion is adjoined last.
+        e = staged(8, st, [&] { return mw::launch_phi_forward(p, in, real, W0, 1.0, st); });
+        if (e == hipSuccess) e = staged(8, st, [&] { return mw::launch_theta_inverse_adjoint(p, s, W0, (double*)W1, st); });
+        if (e == hipSuccess)
+            e = staged(7, st, [&] { return mw::launch_contract_forward(p, s, 0, (const double*)W1, (double2*)out, st); });
+        if (e == hipSuccess && real) e = staged(8, st, [&] { return mw::launch_real_fold(p.L, (double2*)out, st); });
+        break;
+    }
+    return e;
+}
 
 int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
         void* const* ptrs, int32_t precision, void* stream)
 {
-    int rc = validate(L, spin, reality, batch, ptrs, precision, true, false);
+    int rc = validate(L, spin, reality, batch, ptrs, precision, true);
     if (rc) return rc;
     if (precision != MW_FP64) return fail(MW_ENOTSUP, "precision %d is not available for this call", precision);
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");
     const bool may_alloc = !capturing(st);
+    const bool need_spin = (op == Op::Inverse || op == Op::ForwardAdjoint);
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceState& d = g_dev[dev];
     size_t need = 0;
@@ -171,35 +217,13 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
         const SpinTable* sp = nullptr;
         void* ws = nullptr;
         const int s = spin[b], as = s < 0 ? -s : s;
-        rc = get_resources(d, L[b], as, op == Op::Inverse, need, may_alloc, &p, &sp, &ws);
+        rc = get_resources(d, L[b], as, need_spin, need, may_alloc, &p, &sp, &ws);
         if (rc) return rc;
         char* base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
         double2* W0 = (double2*)base;
         double2* W1 = (double2*)(base + ws_region(p->L, 0));
         double* W2 = (double*)(base + ws_region(p->L, 0) + ws_region(p->L, 1));
-        hipError_t e = hipSuccess;
-        if (op == Op::Forward) {
-            if (e == hipSuccess)
-                e = staged(0, st, [&] { return mw::launch_phi_forward(*p, ptrs[2 * b], reality[b], W0, st); });
-            if (e == hipSuccess)
-                e = staged(1, st, [&] { return mw::launch_theta_forward(*p, s, W0, (double*)W1, st); });
-            if (e == hipSuccess)
-                e = staged(2, st, [&] {
-                    return mw::launch_contract_forward(*p, s, reality[b], (const double*)W1,
-                                                       (double2*)ptrs[2 * b + 1], st);
-                });
-        } else {
-            if (e == hipSuccess)
-                e = staged(8, st, [&] {
-                    return mw::launch_inverse_stream(*p, s, reality[b], (const double2*)ptrs[2 * b], W2, st);
-                });
-            if (e == hipSuccess)
-                e = staged(3, st, [&] { return mw::launch_contract_inverse(*p, *sp, s, W2, W0, st); });
-            if (e == hipSuccess)
-                e = staged(4, st, [&] { return mw::launch_theta_inverse(*p, s, W0, W1, st); });
-            if (e == hipSuccess)
-                e = staged(5, st, [&] { return mw::launch_phi_inverse(*p, W1, ptrs[2 * b + 1], reality[b], st); });
-        }
+        hipError_t e = run_map(op, *p, sp, s, reality[b], ptrs[2 * b], ptrs[2 * b + 1], W0, W1, W2, st);
         if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     }
     g_last_error.clear();
@@ -225,25 +249,19 @@ int mw_inverse(const int32_t* L, const int32_t* spin, const int32_t* reality, in
 int mw_forward_adjoint(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                        void* const* ptrs, int32_t precision, void* stream)
 {
-    (void)stream;
-    int rc = validate(L, spin, reality, batch, ptrs, precision, true, true);
-    if (rc) return rc;
-    return fail(MW_ENOTSUP, "forward adjoint is not available in this build");
+    return run(Op::ForwardAdjoint, L, spin, reality, batch, ptrs, precision, stream);
 }
 
 int mw_inverse_adjoint(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                        void* const* ptrs, int32_t precision, void* stream)
 {
-    (void)stream;
-    int rc = validate(L, spin, reality, batch, ptrs, precision, true, true);
-    if (rc) return rc;
-    return fail(MW_ENOTSUP, "inverse adjoint is not available in this build");
+    return run(Op::InverseAdjoint, L, spin, reality, batch, ptrs, precision, stream);
 }
 
 int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                       int32_t precision, size_t* bytes)
 {
-    int rc = validate(L, spin, reality, batch, nullptr, precision, false, false);
+    int rc = validate(L, spin, reality, batch, nullptr, precision, false);
     if (rc) return rc;
     if (!bytes) return fail(MW_EINVAL, "bytes must be non-NULL");
     size_t need = 0;
@@ -254,7 +272,7 @@ int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* real
 
 int mw_prepare(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch, int32_t precision)
 {
-    int rc = validate(L, spin, reality, batch, nullptr, precision, false, false);
+    int rc = validate(L, spin, reality, batch, nullptr, precision, false);
     if (rc) return rc;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");

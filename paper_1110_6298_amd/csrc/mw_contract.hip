@@ -436,6 +436,21 @@ __global__ __launch_bounds__(256) void k_inverse_stream(const double2* __restric
     }
 }
 
+// Adjoint of the real-map coefficient expansion f_{l,-m} = (-1)^m conj(f_{l,m})
+// (Sec. IV-G): y_{l,m} += (-1)^m conj(y_{l,-m}) and y_{l,-m} = 0 for m > 0.
+// One thread per (l, m > 0).
+__global__ __launch_bounds__(256) void k_real_fold(double2* __restrict__ y, int L)
+{
+    const int l = blockIdx.y;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (l >= L || m > l) return;
+    const size_t c = (size_t)l * l + l;
+    const double2 a = y[c + m], b = y[c - m];
+    const double sg = (m & 1) ? -1.0 : 1.0;
+    y[c + m] = make_double2(a.x + sg * b.x, a.y - sg * b.y);
+    y[c - m] = make_double2(0.0, 0.0);
+}
+
 template <bool EXT>
 struct InvLane {
     double dc, dp;             // Delta^l_{n,m}, Delta^{l-1}_{n,m}
@@ -724,6 +739,13 @@ hipError_t launch_contract_forward(const Plan& p, int s, int real, const double*
     else
         hipLaunchKernelGGL((k_contract_forward<MT_FWD, false>), grid, block, lds, st, Hp, flm, p.rtab, p.edge,
                            p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
+    return hipGetLastError();
+}
+
+hipError_t launch_real_fold(int L, double2* y, hipStream_t st)
+{
+    const dim3 grid((L + 255) / 256, L);
+    hipLaunchKernelGGL(k_real_fold, grid, dim3(256), 0, st, y, L);
     return hipGetLastError();
 }
 

@@ -232,10 +232,12 @@ __device__ __forceinline__ int xcd_column(int ncol)
 }
 
 // ---------------------------------------------------------------------------
-// Forward phi stage (Sec. IV-D): G_m(theta_t) = 2pi/N1 sum_p f(t, p) e^{-i m phi_p}.
+// Forward phi stage (Sec. IV-D): G_m(theta_t) = sc sum_p f(t, p) e^{-i m phi_p}, with
+// sc = 2pi/N1 for the forward transform and sc = 1 for the adjoint of the inverse.
 // Output G[t][m + L-1].
 template <int REAL>
-__global__ __launch_bounds__(512) void k_phi_forward(Plan p, const void* __restrict__ map, double2* __restrict__ G)
+__global__ __launch_bounds__(512) void k_phi_forward(Plan p, const void* __restrict__ map, double2* __restrict__ G,
+                                                     double sc)
 {
     extern __shared__ double2 A[];
     const int t = blockIdx.x, L = p.L, N1 = p.N1;
@@ -249,7 +251,6 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, const void* __restr
         A[P(j)] = v;
     }
     bluestein_core(A, p);
-    const double sc = 2.0 * 3.14159265358979323846 / (double)N1;
     for (int k = threadIdx.x; k < N1; k += blockDim.x) {
         const int m = (k <= L - 1) ? k : k - N1;
         G[(size_t)t * N1 + (m + L - 1)] = cscale(cmul(A[P(k)], p.chirp[k]), sc);
@@ -263,7 +264,13 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, const void* __restr
 //   fold     H_{m,0} = G_{m,0},  H_{m,n} = G_{m,n} + (-1)^{m+s} G_{m,-n}  (Eq.(Fmm_sym1)).
 // Output: Hp records (see mw_internal.h); order m writes its slot of row |m|,
 // including the zero pad entry n = L when L is odd.
-__global__ __launch_bounds__(512) void k_theta_forward(Plan p, int s, const double2* __restrict__ G, double* __restrict__ Hp)
+// ADJ_INV = 1 gives the theta step of the adjoint of the inverse transform
+// instead: Z_{m m'} = sum_{t<L} G_m(theta_t) e^{-i m' theta_t} (the conjugate
+// transpose of Eq.(Fmt): no extension, no 1/(2 pi N1), no weights), folded the
+// same way, because the adjoint's contraction is the forward's.
+template <int ADJ_INV>
+__global__ __launch_bounds__(512) void k_theta_forward(Plan p, int s, const double2* __restrict__ G,
+                                                       double* __restrict__ Hp)
 {
     extern __shared__ double2 A[];
     const int L = p.L, N1 = p.N1, N2 = p.N2;
@@ -274,7 +281,9 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, int s, const doub
     for (int j = threadIdx.x; j < N2; j += blockDim.x) {
         double2 v = make_double2(0.0, 0.0);
         if (j < N1) {
-            double2 g = (j < L) ? G[(size_t)j * N1 + mi] : cscale(G[(size_t)(2 * L - 2 - j) * N1 + mi], sig);
+            double2 g;
+            if (j < L) g = G[(size_t)j * N1 + mi];
+            else g = ADJ_INV ? make_double2(0.0, 0.0) : cscale(G[(size_t)(2 * L - 2 - j) * N1 + mi], sig);
             v = cmul(g, p.chirp[j]);
         }
         A[P(j)] = v;
@@ -282,34 +291,105 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, int s, const doub
     bluestein_core(A, p);
     // F_{m'} into registers (N1 <= N2/2 <= 8 * blockDim.x), then scatter to slot m' mod N2.
     double2 r[8];
+    const double unscale = ADJ_INV ? 2.0 * 3.14159265358979323846 * (double)N1 : 1.0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int k = threadIdx.x + q * blockDim.x;
-        if (k < N1) r[q] = cmul(cmul(A[P(k)], p.chirp[k]), p.thtw[k]);
+        if (k < N1) r[q] = cscale(cmul(cmul(A[P(k)], p.chirp[k]), p.thtw[k]), unscale);
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < N2; j += blockDim.x) A[P(j)] = make_double2(0.0, 0.0);
-    __syncthreads();
+    int wrap;   // index of -n is wrap - n
+    if (ADJ_INV) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int k = threadIdx.x + q * blockDim.x;
-        if (k < N1) {
-            const int mp = (k <= L - 1) ? k : k - N1;
-            A[P((mp + N2) & (N2 - 1))] = r[q];
+        for (int q = 0; q < 8; ++q) {
+            const int k = threadIdx.x + q * blockDim.x;
+            if (k < N1) A[P(k)] = r[q];
         }
+        __syncthreads();
+        wrap = N1;
+    } else {
+        for (int j = threadIdx.x; j < N2; j += blockDim.x) A[P(j)] = make_double2(0.0, 0.0);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int k = threadIdx.x + q * blockDim.x;
+            if (k < N1) {
+                const int mp = (k <= L - 1) ? k : k - N1;
+                A[P((mp + N2) & (N2 - 1))] = r[q];
+            }
+        }
+        block_fft<+1>(A, N2, p.logN2, p.tw, p.what);
+        block_fft<-1>(A, N2, p.logN2, p.tw);
+        wrap = N2;
     }
-    block_fft<+1>(A, N2, p.logN2, p.tw, p.what);
-    block_fft<-1>(A, N2, p.logN2, p.tw);
     const int am = m < 0 ? -m : m;
     for (int n = threadIdx.x; n < p.Lp; n += blockDim.x) {
         double2 v = make_double2(0.0, 0.0);
         if (n < L) {
             v = A[P(n)];
-            if (n > 0) v = cadd(v, cscale(A[P(N2 - n)], sig));
+            if (n > 0) v = cadd(v, cscale(A[P(wrap - n)], sig));
         }
         double* rec = Hp + ((size_t)am * p.Lp + n) * 4;
         if (m >= 0) { rec[0] = v.x; rec[1] = v.y; }
         if (m <= 0) { rec[2] = v.x; rec[3] = v.y; }
+    }
+}
+
+// Theta step of the adjoint of the forward transform, for order m: the
+// conjugate transposes of the forward's theta stages in reverse order.
+//   unfold   Y_{m,-n} = (-1)^{m+s} Y_{m,n}     (input: folded Y[m + L-1][n], n >= 0)
+//   weights  Z_{m m''} = 2 pi sum_{m'} conj(w(m'' - m')) Y_{m m'}
+//            (the forward's N2-grid product with conj of its weight spectrum)
+//   DFT^H    Gext(theta_t) = 1/(2 pi N1) sum_{m''} Z_{m m''} e^{+i m'' theta_t}, t < N1
+//   fold     G_m(theta_t) = Gext(theta_t) + (-1)^{m+s} Gext(theta_{2L-2-t}), t < L-1;
+//            G_m(theta_{L-1}) = Gext(theta_{L-1})
+// Output G[t][m + L-1] (the layout the inverse phi stage reads).
+__global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, int s, const double2* __restrict__ Y,
+                                                               double2* __restrict__ Gt)
+{
+    extern __shared__ double2 A[];
+    const int L = p.L, N1 = p.N1, N2 = p.N2;
+    const int mi = xcd_column(N1);
+    if (mi >= N1) return;
+    const int m = mi - (L - 1);
+    const double sig = ((m + s) & 1) ? -1.0 : 1.0;
+    for (int j = threadIdx.x; j < N2; j += blockDim.x) A[P(j)] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int k = threadIdx.x; k < N1; k += blockDim.x) {
+        const int mp = (k <= L - 1) ? k : k - N1;
+        double2 y = Y[(size_t)mi * L + (mp < 0 ? -mp : mp)];
+        if (mp < 0) y = cscale(y, sig);
+        A[P((mp + N2) & (N2 - 1))] = y;
+    }
+    block_fft<+1>(A, N2, p.logN2, p.tw, p.whatc);
+    block_fft<-1>(A, N2, p.logN2, p.tw);
+    // Z_{m''} e^{+i m'' pi/N1}/(2 pi N1) = Z conj(thtw), conjugated and chirped for the
+    // Bluestein evaluation of the positive-exponent DFT
+    double2 r[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int k = threadIdx.x + q * blockDim.x;
+        if (k < N1) {
+            const int mp = (k <= L - 1) ? k : k - N1;
+            const double2 y = cmul(A[P((mp + N2) & (N2 - 1))], cconj(p.thtw[k]));
+            r[q] = cmul(cconj(y), p.chirp[k]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int k = threadIdx.x + q * blockDim.x;
+        if (k < N2) A[P(k)] = (k < N1) ? r[q] : make_double2(0.0, 0.0);
+    }
+    for (int j = threadIdx.x + 8 * blockDim.x; j < N2; j += blockDim.x) A[P(j)] = make_double2(0.0, 0.0);
+    bluestein_core(A, p);
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        double2 v = cconj(cmul(A[P(t)], p.chirp[t]));
+        if (t <= L - 2) {
+            const int u = 2 * L - 2 - t;
+            v = cadd(v, cscale(cconj(cmul(A[P(u)], p.chirp[u])), sig));
+        }
+        Gt[(size_t)t * N1 + mi] = v;
     }
 }
 
@@ -343,9 +423,12 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, int s, const doub
         Ft[(size_t)t * N1 + mi] = cconj(cmul(A[P(t)], p.chirp[t]));
 }
 
-// Inverse phi stage (Eq.(f_pfft)): f(t, p) = sum_m F_m(theta_t) e^{i m phi_p}.
+// Inverse phi stage (Eq.(f_pfft)): f(t, p) = sc sum_m F_m(theta_t) e^{i m phi_p}, with
+// sc = 1 for the inverse transform and sc = 2pi/N1 for the adjoint of the forward
+// (whose phi step is the conjugate transpose of the forward's).  REAL stores Re f.
 template <int REAL>
-__global__ __launch_bounds__(512) void k_phi_inverse(Plan p, const double2* __restrict__ Ft, void* __restrict__ map)
+__global__ __launch_bounds__(512) void k_phi_inverse(Plan p, const double2* __restrict__ Ft, void* __restrict__ map,
+                                                     double sc)
 {
     extern __shared__ double2 A[];
     const int t = blockIdx.x, L = p.L, N1 = p.N1;
@@ -359,7 +442,7 @@ __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, const double2* __re
     }
     bluestein_core(A, p);
     for (int k = threadIdx.x; k < N1; k += blockDim.x) {
-        double2 out = cconj(cmul(A[P(k)], p.chirp[k]));
+        double2 out = cscale(cconj(cmul(A[P(k)], p.chirp[k])), sc);
         if (REAL) ((double*)map)[(size_t)t * N1 + k] = out.x;
         else ((double2*)map)[(size_t)t * N1 + k] = out;
     }
@@ -384,16 +467,16 @@ int xcd_grid(int ncol) { return 8 * ((ncol + 7) >> 3); }
 
 }  // namespace
 
-hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2* G, hipStream_t st)
+hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2* G, double sc, hipStream_t st)
 {
     const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     hipError_t e;
     if (real) {
         if ((e = set_lds(k_phi_forward<1>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_phi_forward<1>, dim3(p.L), dim3(fft_threads(p)), lds, st, p, map, G);
+        hipLaunchKernelGGL(k_phi_forward<1>, dim3(p.L), dim3(fft_threads(p)), lds, st, p, map, G, sc);
     } else {
         if ((e = set_lds(k_phi_forward<0>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_phi_forward<0>, dim3(p.L), dim3(fft_threads(p)), lds, st, p, map, G);
+        hipLaunchKernelGGL(k_phi_forward<0>, dim3(p.L), dim3(fft_threads(p)), lds, st, p, map, G, sc);
     }
     return hipGetLastError();
 }
@@ -402,8 +485,26 @@ hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, double* 
 {
     const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     hipError_t e;
-    if ((e = set_lds(k_theta_forward, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_theta_forward, dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s, G, Hp);
+    if ((e = set_lds(k_theta_forward<0>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_theta_forward<0>, dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s, G, Hp);
+    return hipGetLastError();
+}
+
+hipError_t launch_theta_inverse_adjoint(const Plan& p, int s, const double2* G, double* Hp, hipStream_t st)
+{
+    const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
+    hipError_t e;
+    if ((e = set_lds(k_theta_forward<1>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_theta_forward<1>, dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s, G, Hp);
+    return hipGetLastError();
+}
+
+hipError_t launch_theta_forward_adjoint(const Plan& p, int s, const double2* Y, double2* Gt, hipStream_t st)
+{
+    const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
+    hipError_t e;
+    if ((e = set_lds(k_theta_forward_adjoint, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_theta_forward_adjoint, dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s, Y, Gt);
     return hipGetLastError();
 }
 
@@ -416,16 +517,16 @@ hipError_t launch_theta_inverse(const Plan& p, int s, const double2* F, double2*
     return hipGetLastError();
 }
 
-hipError_t launch_phi_inverse(const Plan& p, const double2* Ft, void* map, int real, hipStream_t st)
+hipError_t launch_phi_inverse(const Plan& p, const double2* Ft, void* map, int real, double sc, hipStream_t st)
 {
     const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     hipError_t e;
     if (real) {
         if ((e = set_lds(k_phi_inverse<1>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_phi_inverse<1>, dim3(p.L), dim3(fft_threads(p)), lds, st, p, Ft, map);
+        hipLaunchKernelGGL(k_phi_inverse<1>, dim3(p.L), dim3(fft_threads(p)), lds, st, p, Ft, map, sc);
     } else {
         if ((e = set_lds(k_phi_inverse<0>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_phi_inverse<0>, dim3(p.L), dim3(fft_threads(p)), lds, st, p, Ft, map);
+        hipLaunchKernelGGL(k_phi_inverse<0>, dim3(p.L), dim3(fft_threads(p)), lds, st, p, Ft, map, sc);
     }
     return hipGetLastError();
 }

@@ -36,6 +36,7 @@ struct Plan {
     double2* chirp = nullptr;   // exp(-i pi j^2/N1), j < N1
     double2* bhat = nullptr;    // FFT_N2 of the Bluestein kernel, divided by N2
     double2* what = nullptr;    // (2 pi/N2) * DFT_N2 of the theta weights w(k)
+    double2* whatc = nullptr;   // conj(what), for the adjoint of the weight step
     double2* thtw = nullptr;    // exp(-i m' pi/N1)/(2 pi N1) at slot k = m' mod N1
     // contraction work lists (int2: (block start, first order)), dealt over the 8
     // XCDs by order and longest first; (-1, -1) entries are padding
@@ -74,10 +75,15 @@ int build_spin_table(int L, int as, SpinTable& t, std::string& err);
 void free_spin_table(SpinTable& t);
 
 // Kernel launchers (enqueue only).  Buffers: map, G (L x N1), F (N1 x L), coeffs.
-hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2* G, hipStream_t st);
+// sc: 2 pi/N1 for the forward transform, 1 for the adjoint of the inverse.
+hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2* G, double sc, hipStream_t st);
 // Hp: forward Fourier coefficients H_{+-m,n} as records (Re H_{m,n}, Im H_{m,n},
 // Re H_{-m,n}, Im H_{-m,n}) at [(m * Lp + n) * 4], m < L, n < Lp (pad rows zero).
 hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, double* Hp, hipStream_t st);
+// Theta step of the adjoint of the inverse (same output layout as launch_theta_forward).
+hipError_t launch_theta_inverse_adjoint(const Plan& p, int s, const double2* G, double* Hp, hipStream_t st);
+// Theta step of the adjoint of the forward: folded Y (N1 x L) -> Gt (L x N1).
+hipError_t launch_theta_forward_adjoint(const Plan& p, int s, const double2* Y, double2* Gt, hipStream_t st);
 hipError_t launch_contract_forward(const Plan& p, int s, int real, const double* Hp, double2* flm,
                                    hipStream_t st);
 // fs: per-map scratch of L x Lp x 4 doubles (the inverse's scaled coefficient stream),
@@ -86,6 +92,10 @@ hipError_t launch_inverse_stream(const Plan& p, int s, int real, const double2* 
 hipError_t launch_contract_inverse(const Plan& p, const SpinTable& st_, int s, const double* fs, double2* F,
                                    hipStream_t st);
 hipError_t launch_theta_inverse(const Plan& p, int s, const double2* F, double2* Ft, hipStream_t st);
-hipError_t launch_phi_inverse(const Plan& p, const double2* Ft, void* map, int real, hipStream_t st);
+// sc: 1 for the inverse transform, 2 pi/N1 for the adjoint of the forward.
+hipError_t launch_phi_inverse(const Plan& p, const double2* Ft, void* map, int real, double sc, hipStream_t st);
+// Adjoint of the real-map coefficient expansion: y_{l,m} += (-1)^m conj(y_{l,-m}),
+// y_{l,-m} = 0 for m > 0 (in place on the L^2 layout).
+hipError_t launch_real_fold(int L, double2* y, hipStream_t st);
 
 }  // namespace mw

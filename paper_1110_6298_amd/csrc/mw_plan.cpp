@@ -245,6 +245,8 @@ int build_plan(int L, Plan& p, std::string& err)
         wh[j] = make_double2((double)v.real(), (double)v.imag());
     }
     if ((rc = upload(wh, &p.what, p.bytes, err))) return rc;
+    for (auto& v : wh) v.y = -v.y;   // conjugate spectrum, for the adjoint's correlation
+    if ((rc = upload(wh, &p.whatc, p.bytes, err))) return rc;
 
     std::vector<double2> th(N1);
     for (int k = 0; k < N1; ++k) {
@@ -359,7 +361,7 @@ int build_plan(int L, Plan& p, std::string& err)
 
 void free_plan(Plan& p)
 {
-    void* ptrs[] = {p.sqtab, p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.thtw,
+    void* ptrs[] = {p.sqtab, p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.whatc, p.thtw,
                     p.workf, p.worki, p.ckf, p.ckfk, p.cki, p.ckik};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);

@@ -72,10 +72,6 @@ def test_null_device_pointer_rejected():
     assert rc == -1
 
 
-def test_adjoints_reject_real_maps():
-    assert _raw("mw_forward_adjoint", [8], [0], [1]) == -1
-
-
 def test_workspace_size_is_host_only():
     assert mw.workspace_size([64], [0]) >= 2 * 127 * 64 * 16
     assert mw.workspace_size([64, 512], [0, 2]) == mw.workspace_size([512], [2])
