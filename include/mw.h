@@ -33,8 +33,13 @@
  *
  * Precision (applies to the O(L^3) contraction only; every other stage, and the
  * Wigner recursion, always runs in FP64):
- *   MW_FP64  : FP64 throughout.
- *   MW_FP32C : FP32 products with compensated (error-free) FP32 accumulation.
+ *   MW_FP64  : FP64 throughout.  Matches a plain FP64 evaluation of the paper's
+ *              algorithms to <= 1e-12 (infinity-norm relative error).
+ *   MW_FP32C : the FP64 Wigner products Delta*Delta and the Fourier data are
+ *              rounded to FP32 and accumulated in FP32 on the matrix cores over
+ *              segments of the chains, the segments being added in FP64.  Maps
+ *              of one spin in a call share the FP64 recursions.  Stated accuracy:
+ *              <= 1e-6 infinity-norm relative error against FP64.
  *
  * Errors: arguments are validated before anything is enqueued.  Return values
  * are mw_status codes; mw_status_string() gives a description, and

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <utility>
 #include <vector>
@@ -111,9 +112,8 @@ bool capturing(hipStream_t st)
     return cs != hipStreamCaptureStatusNone;
 }
 
-// Fetch (building if needed) the plan, spin table and workspace for one map.
-int get_resources(DeviceState& d, int L, int as, bool need_spin, size_t ws_bytes, bool may_alloc,
-                  const Plan** plan, const SpinTable** spt, void** ws)
+// Plan of band-limit L on this device (built on first use, outside capture).
+int get_plan(DeviceState& d, int L, bool may_alloc, const Plan** plan)
 {
     std::string err;
     auto it = d.plans.find(L);
@@ -125,18 +125,29 @@ int get_resources(DeviceState& d, int L, int as, bool need_spin, size_t ws_bytes
         it = d.plans.emplace(L, p).first;
     }
     *plan = &it->second;
-    if (need_spin) {
-        auto key = std::make_pair(L, as);
-        auto jt = d.spins.find(key);
-        if (jt == d.spins.end()) {
-            if (!may_alloc) return fail(MW_ENOMEM, "spin table L=%d |s|=%d not prepared", L, as);
-            SpinTable t;
-            int rc = mw::build_spin_table(L, as, t, err);
-            if (rc) { mw::free_spin_table(t); return fail(rc == -2 ? MW_ENOMEM : MW_EHIP, "spin table: %s", err.c_str()); }
-            jt = d.spins.emplace(key, t).first;
-        }
-        *spt = &jt->second;
+    return MW_OK;
+}
+
+// Spin-row table Delta^l_{n,|s|} for l < L.
+int get_spin(DeviceState& d, int L, int as, bool may_alloc, const SpinTable** spt)
+{
+    std::string err;
+    auto key = std::make_pair(L, as);
+    auto jt = d.spins.find(key);
+    if (jt == d.spins.end()) {
+        if (!may_alloc) return fail(MW_ENOMEM, "spin table L=%d |s|=%d not prepared", L, as);
+        SpinTable t;
+        int rc = mw::build_spin_table(L, as, t, err);
+        if (rc) { mw::free_spin_table(t); return fail(rc == -2 ? MW_ENOMEM : MW_EHIP, "spin table: %s", err.c_str()); }
+        jt = d.spins.emplace(key, t).first;
     }
+    *spt = &jt->second;
+    return MW_OK;
+}
+
+// The device's workspace, grown to ws_bytes when allowed.
+int get_ws(DeviceState& d, size_t ws_bytes, bool may_alloc, void** ws)
+{
     if (d.ws_bytes < ws_bytes) {
         if (!may_alloc) return fail(MW_ENOMEM, "workspace of %zu bytes not prepared", ws_bytes);
         if (d.ws) (void)hipFree(d.ws);
@@ -153,22 +164,39 @@ enum class Op { Forward, Inverse, ForwardAdjoint, InverseAdjoint };
 
 constexpr double TWO_PI = 6.283185307179586476925286766559;
 
-// Launch sequence of one map.  Workspace: W0 (N1 x L complex), W1 (max of
-// N1 x L complex and the Hp records), W2 (the inverse's coefficient stream).
+struct Regions { double2* W0; double2* W1; double* W2; };
+
+// Workspace slot k of a call whose largest band-limit is Lmax: three regions,
+// W0 (N1 x L complex), W1 (max of N1 x L complex and the H records), W2 (the
+// inverse's coefficient stream), each 256-byte aligned.
+Regions slot(void* ws, int Lmax, int L, int k)
+{
+    char* base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255) + (size_t)k * ws_need(Lmax);
+    Regions r;
+    r.W0 = (double2*)base;
+    r.W1 = (double2*)(base + ws_region(L, 0));
+    r.W2 = (double*)(base + ws_region(L, 0) + ws_region(L, 1));
+    return r;
+}
+
+// FP64 launch sequence of one map.
 hipError_t run_map(Op op, const Plan& p, const SpinTable* sp, int s, int real, const void* in, void* out,
-                   double2* W0, double2* W1, double* W2, hipStream_t st)
+                   const Regions& w, hipStream_t st)
 {
     hipError_t e = hipSuccess;
     const double phi_sc = TWO_PI / (double)p.N1;
+    double2* W0 = w.W0;
+    double2* W1 = w.W1;
+    double* W2 = w.W2;
     switch (op) {
     case Op::Forward:
         e = staged(0, st, [&] { return mw::launch_phi_forward(p, in, real, W0, phi_sc, st); });
-        if (e == hipSuccess) e = staged(1, st, [&] { return mw::launch_theta_forward(p, s, W0, (double*)W1, st); });
+        if (e == hipSuccess) e = staged(1, st, [&] { return mw::launch_theta_forward(p, s, W0, W1, 0, st); });
         if (e == hipSuccess)
             e = staged(2, st, [&] { return mw::launch_contract_forward(p, s, real, (const double*)W1, (double2*)out, st); });
         break;
     case Op::Inverse:
-        e = staged(8, st, [&] { return mw::launch_inverse_stream(p, s, real, (const double2*)in, W2, st); });
+        e = staged(8, st, [&] { return mw::launch_inverse_stream(p, s, real, (const double2*)in, W2, 0, st); });
         if (e == hipSuccess) e = staged(3, st, [&] { return mw::launch_contract_inverse(p, *sp, s, W2, W0, st); });
         if (e == hipSuccess) e = staged(4, st, [&] { return mw::launch_theta_inverse(p, s, W0, W1, st); });
         if (e == hipSuccess) e = staged(5, st, [&] { return mw::launch_phi_inverse(p, W1, out, real, 1.0, st); });
@@ -178,7 +206,7 @@ hipError_t run_map(Op op, const Plan& p, const SpinTable* sp, int s, int real, c
         // of the forward's contraction and fold; then the theta and phi adjoints.
         // The coefficients are used as given (no real-map expansion): with real = 1
         // the result is Re(A^H y), the adjoint of the forward restricted to real maps.
-        e = staged(8, st, [&] { return mw::launch_inverse_stream(p, s, 0, (const double2*)in, W2, st); });
+        e = staged(8, st, [&] { return mw::launch_inverse_stream(p, s, 0, (const double2*)in, W2, 0, st); });
         if (e == hipSuccess) e = staged(6, st, [&] { return mw::launch_contract_inverse(p, *sp, s, W2, W0, st); });
         if (e == hipSuccess) e = staged(8, st, [&] { return mw::launch_theta_forward_adjoint(p, s, W0, W1, st); });
         if (e == hipSuccess) e = staged(8, st, [&] { return mw::launch_phi_inverse(p, W1, out, real, phi_sc, st); });
@@ -188,7 +216,7 @@ hipError_t run_map(Op op, const Plan& p, const SpinTable* sp, int s, int real, c
         // contraction (the conjugate transpose of the inverse's).  With real = 1
         // the real-map coefficient expansion is adjoined last.
         e = staged(8, st, [&] { return mw::launch_phi_forward(p, in, real, W0, 1.0, st); });
-        if (e == hipSuccess) e = staged(8, st, [&] { return mw::launch_theta_inverse_adjoint(p, s, W0, (double*)W1, st); });
+        if (e == hipSuccess) e = staged(8, st, [&] { return mw::launch_theta_inverse_adjoint(p, s, W0, W1, 0, st); });
         if (e == hipSuccess)
             e = staged(7, st, [&] { return mw::launch_contract_forward(p, s, 0, (const double*)W1, (double2*)out, st); });
         if (e == hipSuccess && real) e = staged(8, st, [&] { return mw::launch_real_fold(p.L, (double2*)out, st); });
@@ -197,12 +225,162 @@ hipError_t run_map(Op op, const Plan& p, const SpinTable* sp, int s, int real, c
     return e;
 }
 
+// ---- mixed precision: groups of maps of one spin share the Wigner chains ---
+struct Group {
+    int s = 0, Lmax = 0, G = 1;
+    std::vector<int> maps;   // batch indices, band-limits descending
+};
+
+// Autotuned group size per (largest band-limit, spin, maps of that spin in the
+// call); filled by mw_prepare.
+std::map<std::tuple<int, int, int>, int> g_tuned;
+
+int pow2_ceil(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : 4; }
+
+int default_group(const Plan& p, int nmaps) { return std::min(pow2_ceil(nmaps), mw::mix_group_max(p)); }
+
+// Maps of each spin, sorted by band-limit (largest first) and cut into groups
+// of the tuned (else default) size.
+std::vector<Group> make_groups(DeviceState& d, const int32_t* L, const int32_t* spin, int batch, bool may_alloc,
+                               int& rc)
+{
+    std::map<int, std::vector<int>> by_spin;
+    for (int b = 0; b < batch; ++b) by_spin[spin[b]].push_back(b);
+    std::vector<Group> out;
+    rc = MW_OK;
+    for (auto& kv : by_spin) {
+        auto& v = kv.second;
+        std::stable_sort(v.begin(), v.end(), [L](int a, int b) { return L[a] > L[b]; });
+        const int Lmax = L[v.front()];
+        const Plan* p = nullptr;
+        if ((rc = get_plan(d, Lmax, may_alloc, &p))) return out;
+        auto it = g_tuned.find(std::make_tuple(Lmax, kv.first, (int)v.size()));
+        const int gsz = (it != g_tuned.end()) ? it->second : default_group(*p, (int)v.size());
+        for (size_t i = 0; i < v.size(); i += gsz) {
+            Group g;
+            g.s = kv.first;
+            g.maps.assign(v.begin() + i, v.begin() + std::min(v.size(), i + (size_t)gsz));
+            g.Lmax = L[g.maps.front()];
+            g.G = pow2_ceil((int)g.maps.size());
+            out.push_back(g);
+        }
+    }
+    return out;
+}
+
+// One group in mixed precision: per-map Fourier stages in FP64 around one
+// shared contraction launch.  Map k of the group uses workspace slot k.
+hipError_t run_group(Op op, DeviceState& d, const Group& g, const int32_t* L, const int32_t* reality,
+                     void* const* ptrs, void* ws, int Lws, hipStream_t st, int& rc)
+{
+    hipError_t e = hipSuccess;
+    const Plan* pg = nullptr;
+    const SpinTable* spg = nullptr;
+    const int as = g.s < 0 ? -g.s : g.s;
+    if ((rc = get_plan(d, g.Lmax, false, &pg))) return hipSuccess;
+    const bool inv = (op == Op::Inverse || op == Op::ForwardAdjoint);
+    if (inv && (rc = get_spin(d, g.Lmax, as, false, &spg))) return hipSuccess;
+    mw::MixMaps mm{};
+    mm.n = (int)g.maps.size();
+    std::vector<const Plan*> pl(mm.n);
+    for (int k = 0; k < mm.n; ++k) {
+        const int b = g.maps[k];
+        if ((rc = get_plan(d, L[b], false, &pl[k]))) return hipSuccess;
+        const Regions w = slot(ws, Lws, L[b], k);
+        mm.L[k] = L[b];
+        if (op == Op::Forward || op == Op::InverseAdjoint) {
+            mm.src[k] = (const float*)w.W1;
+            mm.dst[k] = (double2*)ptrs[2 * b + 1];
+        } else {
+            mm.src[k] = (const float*)w.W2;
+            mm.dst[k] = w.W0;
+        }
+    }
+    // Fourier stages before the contraction
+    for (int k = 0; k < mm.n && e == hipSuccess; ++k) {
+        const int b = g.maps[k];
+        const Plan& p = *pl[k];
+        const Regions w = slot(ws, Lws, L[b], k);
+        const int real = reality[b];
+        const void* in = ptrs[2 * b];
+        switch (op) {
+        case Op::Forward:
+            e = staged(0, st, [&] { return mw::launch_phi_forward(p, in, real, w.W0, TWO_PI / (double)p.N1, st); });
+            if (e == hipSuccess) e = staged(1, st, [&] { return mw::launch_theta_forward(p, g.s, w.W0, w.W1, 1, st); });
+            break;
+        case Op::InverseAdjoint:
+            e = staged(8, st, [&] { return mw::launch_phi_forward(p, in, real, w.W0, 1.0, st); });
+            if (e == hipSuccess)
+                e = staged(8, st, [&] { return mw::launch_theta_inverse_adjoint(p, g.s, w.W0, w.W1, 1, st); });
+            break;
+        case Op::Inverse:
+            e = staged(8, st, [&] { return mw::launch_inverse_stream(p, g.s, real, (const double2*)in, w.W2, 1, st); });
+            break;
+        case Op::ForwardAdjoint:
+            e = staged(8, st, [&] { return mw::launch_inverse_stream(p, g.s, 0, (const double2*)in, w.W2, 1, st); });
+            break;
+        }
+    }
+    if (e != hipSuccess) return e;
+    // the shared contraction
+    if (op == Op::Forward || op == Op::InverseAdjoint)
+        e = staged(op == Op::Forward ? 2 : 7, st, [&] { return mw::launch_contract_forward_mix(*pg, g.s, mm, g.G, st); });
+    else
+        e = staged(op == Op::Inverse ? 3 : 6, st,
+                   [&] { return mw::launch_contract_inverse_mix(*pg, *spg, g.s, mm, g.G, st); });
+    // Fourier stages after the contraction
+    for (int k = 0; k < mm.n && e == hipSuccess; ++k) {
+        const int b = g.maps[k];
+        const Plan& p = *pl[k];
+        const Regions w = slot(ws, Lws, L[b], k);
+        const int real = reality[b];
+        void* out = ptrs[2 * b + 1];
+        switch (op) {
+        case Op::Forward:
+            break;
+        case Op::InverseAdjoint:
+            if (real) e = staged(8, st, [&] { return mw::launch_real_fold(p.L, (double2*)out, st); });
+            break;
+        case Op::Inverse:
+            e = staged(4, st, [&] { return mw::launch_theta_inverse(p, g.s, w.W0, w.W1, st); });
+            if (e == hipSuccess) e = staged(5, st, [&] { return mw::launch_phi_inverse(p, w.W1, out, real, 1.0, st); });
+            break;
+        case Op::ForwardAdjoint:
+            e = staged(8, st, [&] { return mw::launch_theta_forward_adjoint(p, g.s, w.W0, w.W1, st); });
+            if (e == hipSuccess)
+                e = staged(8, st, [&] {
+                    return mw::launch_phi_inverse(p, w.W1, out, real, TWO_PI / (double)p.N1, st);
+                });
+            break;
+        }
+    }
+    return e;
+}
+
+int batch_lmax(const int32_t* L, int batch)
+{
+    int m = 0;
+    for (int b = 0; b < batch; ++b) m = std::max(m, (int)L[b]);
+    return m;
+}
+
+// Workspace slots a call needs: one for FP64 (maps run in turn), one per map of
+// the largest group in mixed precision.
+int ws_slots(DeviceState& d, const int32_t* L, const int32_t* spin, int batch, int precision, bool may_alloc,
+             int& rc)
+{
+    rc = MW_OK;
+    if (precision == MW_FP64) return 1;
+    int slots = 1;
+    for (const Group& g : make_groups(d, L, spin, batch, may_alloc, rc)) slots = std::max(slots, (int)g.maps.size());
+    return slots;
+}
+
 int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
         void* const* ptrs, int32_t precision, void* stream)
 {
     int rc = validate(L, spin, reality, batch, ptrs, precision, true);
     if (rc) return rc;
-    if (precision != MW_FP64) return fail(MW_ENOTSUP, "precision %d is not available for this call", precision);
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");
@@ -210,23 +388,97 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     const bool need_spin = (op == Op::Inverse || op == Op::ForwardAdjoint);
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceState& d = g_dev[dev];
-    size_t need = 0;
-    for (int b = 0; b < batch; ++b) need = std::max(need, ws_need(L[b]));
-    for (int b = 0; b < batch; ++b) {
+    const int Lws = batch_lmax(L, batch);
+    const int slots = ws_slots(d, L, spin, batch, precision, may_alloc, rc);
+    if (rc) return rc;
+    void* ws = nullptr;
+    if ((rc = get_ws(d, (size_t)slots * ws_need(Lws) + 256, may_alloc, &ws))) return rc;
+    for (int b = 0; b < batch; ++b) {   // every plan and spin table the call touches
         const Plan* p = nullptr;
         const SpinTable* sp = nullptr;
-        void* ws = nullptr;
-        const int s = spin[b], as = s < 0 ? -s : s;
-        rc = get_resources(d, L[b], as, need_spin, need, may_alloc, &p, &sp, &ws);
+        if ((rc = get_plan(d, L[b], may_alloc, &p))) return rc;
+        if (need_spin && (rc = get_spin(d, L[b], spin[b] < 0 ? -spin[b] : spin[b], may_alloc, &sp))) return rc;
+    }
+    if (precision == MW_FP64) {
+        for (int b = 0; b < batch; ++b) {
+            const Plan* p = nullptr;
+            const SpinTable* sp = nullptr;
+            const int s = spin[b], as = s < 0 ? -s : s;
+            get_plan(d, L[b], false, &p);
+            if (need_spin) get_spin(d, L[b], as, false, &sp);
+            hipError_t e = run_map(op, *p, sp, s, reality[b], ptrs[2 * b], ptrs[2 * b + 1], slot(ws, Lws, L[b], 0), st);
+            if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+        }
+    } else {
+        const std::vector<Group> groups = make_groups(d, L, spin, batch, may_alloc, rc);
         if (rc) return rc;
-        char* base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-        double2* W0 = (double2*)base;
-        double2* W1 = (double2*)(base + ws_region(p->L, 0));
-        double* W2 = (double*)(base + ws_region(p->L, 0) + ws_region(p->L, 1));
-        hipError_t e = run_map(op, *p, sp, s, reality[b], ptrs[2 * b], ptrs[2 * b + 1], W0, W1, W2, st);
-        if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+        for (const Group& g : groups) {
+            if (need_spin) {
+                const SpinTable* sp = nullptr;
+                if ((rc = get_spin(d, g.Lmax, g.s < 0 ? -g.s : g.s, may_alloc, &sp))) return rc;
+            }
+            hipError_t e = run_group(op, d, g, L, reality, ptrs, ws, Lws, st, rc);
+            if (rc) return rc;
+            if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+        }
     }
     g_last_error.clear();
+    return MW_OK;
+}
+
+// Times the mixed forward contraction of one group per candidate size on the
+// workspace (whatever it holds) and keeps the fastest per map.
+int autotune(DeviceState& d, const int32_t* L, const int32_t* spin, int batch, hipStream_t st)
+{
+    std::map<int, std::vector<int>> by_spin;
+    for (int b = 0; b < batch; ++b) by_spin[spin[b]].push_back(b);
+    const int Lws = batch_lmax(L, batch);
+    for (auto& kv : by_spin) {
+        auto& v = kv.second;
+        int Lmax = 0;
+        for (int b : v) Lmax = std::max(Lmax, (int)L[b]);
+        const auto key = std::make_tuple(Lmax, kv.first, (int)v.size());
+        if (g_tuned.count(key)) continue;
+        const Plan* p = nullptr;
+        int rc = get_plan(d, Lmax, true, &p);
+        if (rc) return rc;
+        void* ws = nullptr;
+        const int gmax = std::min(pow2_ceil((int)v.size()), mw::mix_group_max(*p));
+        if ((rc = get_ws(d, (size_t)std::max(gmax, 1) * ws_need(Lws) + 256, true, &ws))) return rc;
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            return fail(MW_EHIP, "hipEventCreate failed");
+        int best = 1;
+        double best_t = 1e30;
+        for (int G = 1; G <= gmax; G <<= 1) {
+            mw::MixMaps mm{};
+            mm.n = G;
+            for (int k = 0; k < G; ++k) {
+                const Regions w = slot(ws, Lws, Lmax, k);
+                // zero staging input: the timing does not depend on the values
+                (void)hipMemsetAsync(w.W1, 0, ws_region(Lmax, 1), st);
+                mm.src[k] = (const float*)w.W1;
+                mm.dst[k] = w.W0;   // f_lm (L^2 entries) fits in W0
+                mm.L[k] = Lmax;
+            }
+            double t = 0;
+            for (int rep = 0; rep < 3; ++rep) {
+                (void)hipEventRecord(e0, st);
+                hipError_t e = mw::launch_contract_forward_mix(*p, kv.first, mm, G, st);
+                (void)hipEventRecord(e1, st);
+                if (e != hipSuccess) { hipEventDestroy(e0); hipEventDestroy(e1); return fail(MW_EHIP, "autotune launch failed"); }
+                (void)hipEventSynchronize(e1);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0) t += ms;
+            }
+            const double per_map = t / G;
+            if (per_map < best_t * 0.97) { best_t = per_map; best = G; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        g_tuned[key] = best;
+    }
     return MW_OK;
 }
 
@@ -264,9 +516,12 @@ int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* real
     int rc = validate(L, spin, reality, batch, nullptr, precision, false);
     if (rc) return rc;
     if (!bytes) return fail(MW_EINVAL, "bytes must be non-NULL");
-    size_t need = 0;
-    for (int b = 0; b < batch; ++b) need = std::max(need, ws_need(L[b]));
-    *bytes = need;
+    int slots = 1;
+    if (precision != MW_FP64) {   // one slot per map of the largest group, at most GMAX
+        std::map<int, int> cnt;
+        for (int b = 0; b < batch; ++b) slots = std::max(slots, std::min(++cnt[spin[b]], mw::GMAX));
+    }
+    *bytes = (size_t)slots * ws_need(batch_lmax(L, batch)) + 256;
     return MW_OK;
 }
 
@@ -278,14 +533,24 @@ int mw_prepare(const int32_t* L, const int32_t* spin, const int32_t* reality, in
     if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceState& d = g_dev[dev];
-    size_t need = 0;
-    for (int b = 0; b < batch; ++b) need = std::max(need, ws_need(L[b]));
+    if (precision != MW_FP64 && (rc = autotune(d, L, spin, batch, nullptr))) return rc;
+    const int Lws = batch_lmax(L, batch);
+    const int slots = ws_slots(d, L, spin, batch, precision, true, rc);
+    if (rc) return rc;
+    void* ws = nullptr;
+    if ((rc = get_ws(d, (size_t)slots * ws_need(Lws) + 256, true, &ws))) return rc;
     for (int b = 0; b < batch; ++b) {
         const Plan* p;
         const SpinTable* sp;
-        void* ws;
         const int as = spin[b] < 0 ? -spin[b] : spin[b];
-        rc = get_resources(d, L[b], as, true, need, true, &p, &sp, &ws);
+        if ((rc = get_plan(d, L[b], true, &p))) return rc;
+        if ((rc = get_spin(d, L[b], as, true, &sp))) return rc;
+    }
+    if (precision != MW_FP64) {   // the groups' spin tables at their largest band-limit
+        for (const Group& g : make_groups(d, L, spin, batch, true, rc)) {
+            const SpinTable* sp;
+            if ((rc = get_spin(d, g.Lmax, g.s < 0 ? -g.s : g.s, true, &sp))) return rc;
+        }
         if (rc) return rc;
     }
     if (hipDeviceSynchronize() != hipSuccess) return fail(MW_EHIP, "hipDeviceSynchronize failed");

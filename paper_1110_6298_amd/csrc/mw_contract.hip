@@ -29,6 +29,8 @@
 // Chains whose start value is below 2^-900 (only for L > ~900) carry an extra
 // exponent: the stored value is x = D * 2^(600k); while k > 0 the chain's
 // contributions are masked (|D| < 2^-300) and it is rescaled when |x| > 2^300.
+#include <algorithm>
+
 #include "mw_internal.h"
 
 namespace mw {
@@ -80,11 +82,9 @@ struct FwdLane {
     int startk[MT], startks;
 };
 
-// One step n: contributions of D_{.,n} (h = the four doubles of H at n for
-// each chain), then the recursion to n-1 with ra = 1/sqrt(Q_n).
-template <int MT, bool EXT, int PAR, bool INJ>
-__device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int mb, int as,
-                                         const Rec8 (&h)[MT], double ra, bool& anyscaled)
+// Chain starts of step n (lanes whose degree l equals n start from the edge).
+template <int MT, bool EXT, bool INJ>
+__device__ __forceinline__ void fwd_inject(FwdLane<MT, EXT>& st, int n, int l, bool& anyscaled)
 {
     if (INJ) {
         if (n == l) {
@@ -100,20 +100,13 @@ __device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int
             anyscaled = __any(sc);
         }
     }
-    double seff = st.sc;
-    if (EXT) seff = (st.ks == 0) ? seff : 0.0;
-#pragma unroll
-    for (int c = 0; c < MT; ++c) {
-        const double* hc = h[c].v + 4 * PAR;
-        double d = st.dc[c];
-        if (EXT) d = (st.k[c] == 0) ? d : 0.0;
-        const double pr = d * seff;
-        st.ap[c][PAR].x = fma(pr, hc[0], st.ap[c][PAR].x);
-        st.ap[c][PAR].y = fma(pr, hc[1], st.ap[c][PAR].y);
-        st.am[c][PAR].x = fma(pr, hc[2], st.am[c][PAR].x);
-        st.am[c][PAR].y = fma(pr, hc[3], st.am[c][PAR].y);
-    }
-    // D_{n-1} = -(2m D_n + a_{n+1} D_{n+1}) / a_n,  a_n = sqrt(Q_n); harmless at n = 0
+}
+
+// Recursion from step n to n-1 with ra = 1/sqrt(Q_n):
+//   D_{n-1} = -(2m D_n + a_{n+1} D_{n+1}) / a_n,  a_n = sqrt(Q_n); harmless at n = 0.
+template <int MT, bool EXT>
+__device__ __forceinline__ void fwd_advance(FwdLane<MT, EXT>& st, int mb, int as, double ra, bool& anyscaled)
+{
     const double an = st.q * ra;
     const double nra = -ra;
 #pragma unroll
@@ -144,6 +137,36 @@ __device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int
         still |= st.ks > 0;
         anyscaled = __any(still);
     }
+}
+
+// Delta_{m_c,n} * Delta_{|s|,n} of the current step (0 while a chain is scaled).
+template <int MT, bool EXT>
+__device__ __forceinline__ double fwd_product(const FwdLane<MT, EXT>& st, int c)
+{
+    double seff = st.sc;
+    if (EXT) seff = (st.ks == 0) ? seff : 0.0;
+    double d = st.dc[c];
+    if (EXT) d = (st.k[c] == 0) ? d : 0.0;
+    return d * seff;
+}
+
+// One step n: contributions of D_{.,n} (h = the four doubles of H at n for
+// each chain), then the recursion to n-1.
+template <int MT, bool EXT, int PAR, bool INJ>
+__device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int mb, int as,
+                                         const Rec8 (&h)[MT], double ra, bool& anyscaled)
+{
+    fwd_inject<MT, EXT, INJ>(st, n, l, anyscaled);
+#pragma unroll
+    for (int c = 0; c < MT; ++c) {
+        const double* hc = h[c].v + 4 * PAR;
+        const double pr = fwd_product<MT, EXT>(st, c);
+        st.ap[c][PAR].x = fma(pr, hc[0], st.ap[c][PAR].x);
+        st.ap[c][PAR].y = fma(pr, hc[1], st.ap[c][PAR].y);
+        st.am[c][PAR].x = fma(pr, hc[2], st.am[c][PAR].x);
+        st.am[c][PAR].y = fma(pr, hc[3], st.am[c][PAR].y);
+    }
+    fwd_advance<MT, EXT>(st, mb, as, ra, anyscaled);
 }
 
 template <int MT>
@@ -244,45 +267,36 @@ __device__ __forceinline__ void ck_level(double& v0, double& v1, int k0, int k1,
     v1 = ldexp(v1, EXT_STEP * (k - k1));
 }
 
-// One workgroup per chain group (64 degrees l0.., MT orders mb..); wave w runs
-// segment w of the row recursions (n in [w*segf, (w+1)*segf) below the top
-// segment, which holds the edge starts).  Partial sums are added in LDS in
-// segment order.
+// Segment of one wave in the forward kernels: pairs ktop..klo of the row
+// recursions, with lane starts in pairs >= kA; idle waves are inactive.
+struct FwdSeg { int ktop, kA, klo; bool active; };
+
+// Chain state of wave w for the group (64 degrees l0.., MT orders mb..): the
+// top segment (w == jtop, jtop = nmax/segf) starts every lane at its own n = l
+// from the edge value; a lower segment w < jtop runs n from (w+1)*segf - 1 down
+// to w*segf, started from the checkpoint pair at n_c = (w+1)*segf (every lane
+// has l >= n_c there).
 template <int MT, bool EXT>
-__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
-    const double* __restrict__ Hp, double2* __restrict__ flm, const double* __restrict__ Rtg,
-    const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,
-    const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int2* __restrict__ work, int L, int Lp,
-    int s, int segf)
+__device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscaled, int w, int l0, int mb, int l,
+                                            int L, int as, int segf, const double* __restrict__ edge,
+                                            const int* __restrict__ edgek, const double2* __restrict__ ckf,
+                                            const int2* __restrict__ ckfk)
 {
-    __shared__ double2 red[SEG_MAX - 1][MT][4][64];
-    extern __shared__ double Rt[];   // copy of the 1/sqrt table (2L+8 entries)
-    const int grp = blockIdx.x;
-    const int w = uniform(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int l0 = uniform(work[grp].x), mb = uniform(work[grp].y);
-    if (l0 < 0) return;   // padding entry of the work list
-    for (int i = threadIdx.x; i < 2 * L + 8; i += blockDim.x) Rt[i] = Rtg[i];
-    __syncthreads();
-    const int l = l0 + lane;
     const bool valid = l < L;
     const int le = valid ? l : L - 1;
-    const int as = s < 0 ? -s : s;
     const int nmax = min(l0 + 63, L - 1);
     const int jtop = nmax / segf;
     const size_t T = (size_t)L * (L + 1) / 2;
-
-    FwdLane<MT, EXT> st;
 #pragma unroll
     for (int c = 0; c < MT; ++c) {
         st.dc[c] = 0.0; st.dn[c] = 0.0; st.k[c] = 0; st.start[c] = 0.0; st.startk[c] = 0;
         st.ap[c][0] = st.ap[c][1] = st.am[c][0] = st.am[c][1] = make_double2(0.0, 0.0);
     }
     st.sc = 0.0; st.sn = 0.0; st.ks = 0; st.anext = 0.0; st.starts = 0.0; st.startks = 0;
-    bool anyscaled = EXT;
-
+    st.q = 0.0; st.dq = 0.0;
+    anyscaled = EXT;
+    FwdSeg g{0, 0, 0, false};
     if (w == jtop) {
-        // top segment: lanes start at their own n = l from the edge
 #pragma unroll
         for (int c = 0; c < MT; ++c) {
             const int m = mb + c;
@@ -296,10 +310,8 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
         const int ktop = nmax >> 1, ntop = 2 * ktop + 1;   // n = L (odd L) is a zero pad step
         st.q = (double)(le + ntop) * (double)(le - ntop + 1);
         st.dq = 2.0 * (double)(ntop - 1);
-        fwd_segment<MT, EXT>(st, ktop, l0 >> 1, (jtop * segf) >> 1, l, le, mb, as, Hp, Rt, Lp, L, anyscaled);
+        g = FwdSeg{ktop, l0 >> 1, (jtop * segf) >> 1, true};
     } else if (w < jtop) {
-        // lower segment: n from (w+1)*segf - 1 down to w*segf, started from the
-        // checkpoint pair at n_c = (w+1)*segf (every lane has l >= n_c)
         const int nc = (w + 1) * segf;
         const size_t base = (size_t)w * T + (size_t)le * (le + 1) / 2;
 #pragma unroll
@@ -328,10 +340,40 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
             for (int c = 0; c < MT; ++c) sc |= st.k[c] > 0;
             anyscaled = __any(sc);
         }
-        fwd_segment<MT, EXT>(st, ntop >> 1, (ntop >> 1) + 1, (w * segf) >> 1, l, le, mb, as, Hp, Rt, Lp, L,
-                             anyscaled);
+        g = FwdSeg{ntop >> 1, (ntop >> 1) + 1, (w * segf) >> 1, true};
     }
+    return g;
+}
 
+// FP64 forward contraction.  One workgroup per chain group (64 degrees l0..,
+// MT orders mb..); wave w runs segment w of the row recursions.  Partial sums
+// are added in LDS in segment order.
+template <int MT, bool EXT>
+__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
+    const double* __restrict__ Hp, double2* __restrict__ flm, const double* __restrict__ Rtg,
+    const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,
+    const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int2* __restrict__ work, int L, int Lp,
+    int s, int segf)
+{
+    __shared__ double2 red[SEG_MAX - 1][MT][4][64];
+    extern __shared__ double Rt[];   // copy of the 1/sqrt table (2L+8 entries)
+    const int grp = blockIdx.x;
+    const int w = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int l0 = uniform(work[grp].x), mb = uniform(work[grp].y);
+    if (l0 < 0) return;   // padding entry of the work list
+    for (int i = threadIdx.x; i < 2 * L + 8; i += blockDim.x) Rt[i] = Rtg[i];
+    __syncthreads();
+    const int l = l0 + lane;
+    const bool valid = l < L;
+    const int le = valid ? l : L - 1;
+    const int as = s < 0 ? -s : s;
+    const int jtop = min(l0 + 63, L - 1) / segf;
+
+    FwdLane<MT, EXT> st;
+    bool anyscaled;
+    const FwdSeg g = fwd_setup<MT, EXT>(st, anyscaled, w, l0, mb, l, L, as, segf, edge, edgek, ckf, ckfk);
+    if (g.active) fwd_segment<MT, EXT>(st, g.ktop, g.kA, g.klo, l, le, mb, as, Hp, Rt, Lp, L, anyscaled);
     if (jtop > 0) {
         if (w > 0 && w <= jtop) {
 #pragma unroll
@@ -391,10 +433,6 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
 // Inverse contraction
 // ===========================================================================
 
-// Per-map stream of the inverse: record (m, l) = (c_l sp(l) f_{l,m}, c_l sm(l) f_{l,-m})
-// for l < Lp (zero where l < m or l >= L), where sp/sm fold the (-1)^l factors of
-// Delta^l_{n,-m} and Delta^l_{n,-s}: sp = (-1)^l for s >= 0 (else 1), sm = (-1)^l
-// for s < 0 (else 1).  Real maps read only m >= 0: f_{l,-m} = (-1)^m conj(f_{l,m}).
 // Inverse coefficient stream: record (c_l sp(l) f_{l,m}, c_l sm(l) f_{l,-m}) at
 // [(m*Lp + l)*4] for 0 <= m <= l < L (zero elsewhere, l < Lp), where sp and sm
 // are the degree-parity factors of the +m and -m terms (Eq. for F_{m m'} with
@@ -402,7 +440,10 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
 // f_lm are contiguous in m) and written along l through LDS.
 constexpr int STR_L = 32, STR_M = 8;
 
-__global__ __launch_bounds__(256) void k_inverse_stream(const double2* __restrict__ flm, double* __restrict__ fs,
+// OUT32 = 1 writes the record as FP32 at [(m*4 + comp)*Lp + l] instead (the
+// layout the mixed-precision inverse stages per order).
+template <int OUT32>
+__global__ __launch_bounds__(256) void k_inverse_stream(const double2* __restrict__ flm, void* __restrict__ fs,
                                                         const double* __restrict__ cl, int L, int Lp, int s,
                                                         int real)
 {
@@ -431,8 +472,16 @@ __global__ __launch_bounds__(256) void k_inverse_stream(const double2* __restric
         const double sp = (s >= 0) ? par : c;
         const double sm = (s >= 0) ? c : par;
         const double2 a = ta[i][k], b = tb[i][k];
-        double4* rec = (double4*)(fs + ((size_t)m * Lp + l) * 4);
-        *rec = make_double4(sp * a.x, sp * a.y, sm * b.x, sm * b.y);
+        if (OUT32) {
+            float* r32 = (float*)fs + (size_t)m * 4 * Lp + l;
+            r32[0] = (float)(sp * a.x);
+            r32[(size_t)Lp] = (float)(sp * a.y);
+            r32[2 * (size_t)Lp] = (float)(sm * b.x);
+            r32[3 * (size_t)Lp] = (float)(sm * b.y);
+        } else {
+            double4* rec = (double4*)((double*)fs + ((size_t)m * Lp + l) * 4);
+            *rec = make_double4(sp * a.x, sp * a.y, sm * b.x, sm * b.y);
+        }
     }
 }
 
@@ -463,24 +512,31 @@ struct InvLane {
     int startk, startks, lz, l0s;
 };
 
-// uniform data of one step: stream record (4 doubles), (Pu_m, Qu_m), (Pu_s, Qu_s)
 template <bool EXT, bool INJ>
-__device__ __forceinline__ void inv_step(InvLane<EXT>& st, int l, int lstart, double nd, const double* f,
-                                         double pum, double qum, double pus, double qus, double rs,
-                                         bool& anyscaled)
+__device__ __forceinline__ void inv_inject(InvLane<EXT>& st, int l, int lstart, bool& anyscaled)
 {
     if (INJ) {
         if (l == st.lz) { st.dc = st.start; if (EXT) st.k = st.startk; }
         if (l == st.l0s && st.l0s > lstart) { st.sc = st.starts; if (EXT) st.ks = st.startks; }
         if (EXT) anyscaled = __any(st.k > 0 || st.ks > 0);
     }
+}
+
+// Delta^l_{n,m} * Delta^l_{n,|s|} of the current step (0 while a chain is scaled).
+template <bool EXT>
+__device__ __forceinline__ double inv_product(const InvLane<EXT>& st)
+{
     double d = st.dc, sv = st.sc;
     if (EXT) { d = (st.k == 0) ? d : 0.0; sv = (st.ks == 0) ? sv : 0.0; }
-    const double pr = d * sv;
-    st.ap.x = fma(pr, f[0], st.ap.x);
-    st.ap.y = fma(pr, f[1], st.ap.y);
-    st.am.x = fma(pr, f[2], st.am.x);
-    st.am.y = fma(pr, f[3], st.am.y);
+    return d * sv;
+}
+
+// Recursion from degree l to l+1 with rs = 1/sqrt((l+1)^2 - n^2) and the
+// uniform factors (Pu_m, Qu_m), (Pu_s, Qu_s) of this degree.
+template <bool EXT>
+__device__ __forceinline__ void inv_advance(InvLane<EXT>& st, double nd, double pum, double qum, double pus,
+                                            double qus, double rs, bool& anyscaled)
+{
     // X_n(l) = n/sqrt((l+1)^2-n^2), Y_n(l) = sqrt(l^2-n^2)/sqrt((l+1)^2-n^2); harmless at l = L-1
     const double xn = nd * rs;
     const double yn = st.sprev * rs;
@@ -502,6 +558,21 @@ __device__ __forceinline__ void inv_step(InvLane<EXT>& st, int l, int lstart, do
         if (st.ks > 0 && fabs(st.sc) > EXT_UP) { st.sc *= EXT_DOWN; st.sp *= EXT_DOWN; st.ks -= 1; }
         anyscaled = __any(st.k > 0 || st.ks > 0);
     }
+}
+
+// uniform data of one step: stream record (4 doubles), (Pu_m, Qu_m), (Pu_s, Qu_s)
+template <bool EXT, bool INJ>
+__device__ __forceinline__ void inv_step(InvLane<EXT>& st, int l, int lstart, double nd, const double* f,
+                                         double pum, double qum, double pus, double qus, double rs,
+                                         bool& anyscaled)
+{
+    inv_inject<EXT, INJ>(st, l, lstart, anyscaled);
+    const double pr = inv_product<EXT>(st);
+    st.ap.x = fma(pr, f[0], st.ap.x);
+    st.ap.y = fma(pr, f[1], st.ap.y);
+    st.am.x = fma(pr, f[2], st.am.x);
+    st.am.y = fma(pr, f[3], st.am.y);
+    inv_advance<EXT>(st, nd, pum, qum, pus, qus, rs, anyscaled);
 }
 
 struct InvU { Rec8 f; double4 cm, cs; };   // pair (l, l+1): stream, (Pu,Qu)_m, (Pu,Qu)_s
@@ -597,49 +668,47 @@ __device__ __forceinline__ void inv_segment(InvLane<EXT>& st, int jfrom, int jA,
 
 struct CkOff { size_t off[SEG_MAX]; };
 
-// One workgroup per chain group (64 orders n0.., one order m); wave 0 runs the
-// degrees from lstart (with every chain start) up to the first boundary
-// j*segi >= max(lA, lstart+2), wave w >= 1 runs the w-th following segment from
-// the checkpoint planes.  Partial sums are added in LDS in segment order.
-template <bool EXT>
-__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
-    const double* __restrict__ fs, double2* __restrict__ F, const double* __restrict__ Rtg,
-    const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
-    const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,
-    const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work, int L, int Lp, int s, int segi,
-    int nsegi)
+// Segment of one wave in the inverse kernels: pairs jfrom..jlast (pair j =
+// degrees 2j, 2j+1), with chain starts in pairs <= jA; idle waves are inactive.
+struct InvSeg { int jfrom, jA, jlast; bool active; };
+
+// Geometry of the inverse group (64 orders n0.., order m): pairs start at the
+// even degree lstart = max(n0, m) rounded down; wave 0 runs up to the first
+// boundary j*segi >= max(lA, lstart+2) (every chain start lies below lA), wave
+// w >= 1 runs the w-th following segment from the checkpoint planes.
+struct InvGeo { int lstart, lA, jb, nseg; };
+
+__device__ __forceinline__ InvGeo inv_geometry(int n0, int m, int as, int segi, int nsegi)
 {
-    __shared__ double2 red[SEG_MAX - 1][2][64];
-    extern __shared__ double Rt[];   // copy of the 1/sqrt table (2L+8 entries)
-    const int grp = blockIdx.x;
-    const int w = uniform(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int n0 = uniform(work[grp].x), m = uniform(work[grp].y);
-    if (n0 < 0) return;   // padding entry of the work list
-    for (int i = threadIdx.x; i < 2 * L + 8; i += blockDim.x) Rt[i] = Rtg[i];
-    __syncthreads();
-    const int n = n0 + lane;
+    InvGeo g;
+    g.lstart = max(n0, m) & ~1;
+    g.lA = max(max(n0 + 64, m + 1), as + 1);
+    g.jb = (max(g.lA, g.lstart + 2) + segi - 1) / segi;
+    g.nseg = (g.jb < nsegi) ? 1 + nsegi - g.jb : 1;
+    return g;
+}
+
+template <bool EXT>
+__device__ __forceinline__ InvSeg inv_setup(InvLane<EXT>& st, bool& anyscaled, const InvGeo& geo, int w, int n,
+                                            int m, int L, int Lp, int as, int segi,
+                                            const double* __restrict__ edge, const int* __restrict__ edgek,
+                                            const double* __restrict__ stab, const int* __restrict__ stabk,
+                                            const double2* __restrict__ cki, const int2* __restrict__ ckik,
+                                            const CkOff& ckoff)
+{
     const bool valid = n < L;
     const int ne = valid ? n : L - 1;
-    const int as = s < 0 ? -s : s;
-    const double nd = (double)ne;
-    // pairs (l, l+1) start at an even l; the step before max(n0, m) is skipped
-    const int lstart = max(n0, m) & ~1;
+    const int lstart = geo.lstart;
     const int jend = (Lp >> 1) - 1;
-    // every chain start lies below lA
-    const int lA = max(max(n0 + 64, m + 1), as + 1);
-    int jb = (max(lA, lstart + 2) + segi - 1) / segi;
-    const int nseg = (jb < nsegi) ? 1 + nsegi - jb : 1;
-
-    InvLane<EXT> st;
     st.dc = 0.0; st.dp = 0.0; st.k = 0;
     st.sc = 0.0; st.sp = 0.0; st.ks = 0; st.starts = 0.0; st.startks = 0;
     st.start = 0.0; st.startk = 0;
     st.ap = st.am = make_double2(0.0, 0.0);
     st.lz = max(n, m);
     st.l0s = max(n, as);
-    bool anyscaled = EXT;
-
+    st.sprev = 0.0; st.q = 0.0; st.dq = 0.0;
+    anyscaled = EXT;
+    InvSeg g{0, 0, -1, false};
     if (w == 0) {
         if (valid) {
             if (n >= m) {
@@ -671,12 +740,12 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
         st.sprev = (lstart >= ne) ? sqrt((double)(lstart - ne) * (double)(lstart + ne)) : 0.0;
         st.q = (double)(lstart + 1 - ne) * (double)(lstart + 1 + ne);
         st.dq = 2.0 * (double)lstart + 3.0;
-        const int jlast = (nseg > 1) ? ((jb * segi) >> 1) - 1 : jend;
-        const int jA = min(jlast, (lA - 1) >> 1);
-        inv_segment<EXT>(st, lstart >> 1, jA, jlast, jend, lstart, ne, nd, m, as, Lp, L, fs, lco, Rt, anyscaled);
-    } else if (w < nseg) {
+        const int jlast = (geo.nseg > 1) ? ((geo.jb * segi) >> 1) - 1 : jend;
+        const int jA = min(jlast, (geo.lA - 1) >> 1);
+        g = InvSeg{lstart >> 1, jA, jlast, true};
+    } else if (w < geo.nseg) {
         // segment from degree c = (jb+w-1)*segi, started from the checkpoint plane
-        const int jj = jb + w - 1;
+        const int jj = geo.jb + w - 1;
         const int c = jj * segi;
         if (valid) {
             const size_t i = ckoff.off[jj] + (size_t)n * (c + 1) + m;
@@ -693,11 +762,47 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
         st.q = (double)(c + 1 - ne) * (double)(c + 1 + ne);
         st.dq = 2.0 * (double)c + 3.0;
         if (EXT) anyscaled = __any(st.k > 0 || st.ks > 0);
-        const int jlast = (w < nseg - 1) ? (((jj + 1) * segi) >> 1) - 1 : jend;
-        inv_segment<EXT>(st, c >> 1, (c >> 1) - 1, jlast, jend, lstart, ne, nd, m, as, Lp, L, fs, lco, Rt,
-                         anyscaled);
+        const int jlast = (w < geo.nseg - 1) ? (((jj + 1) * segi) >> 1) - 1 : jend;
+        g = InvSeg{c >> 1, (c >> 1) - 1, jlast, true};
     }
+    return g;
+}
 
+// FP64 inverse contraction: one workgroup per chain group (64 orders n0.., one
+// order m).  Partial sums are added in LDS in segment order.
+template <bool EXT>
+__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
+    const double* __restrict__ fs, double2* __restrict__ F, const double* __restrict__ Rtg,
+    const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
+    const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,
+    const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work, int L, int Lp, int s, int segi,
+    int nsegi)
+{
+    __shared__ double2 red[SEG_MAX - 1][2][64];
+    extern __shared__ double Rt[];   // copy of the 1/sqrt table (2L+8 entries)
+    const int grp = blockIdx.x;
+    const int w = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int n0 = uniform(work[grp].x), m = uniform(work[grp].y);
+    if (n0 < 0) return;   // padding entry of the work list
+    for (int i = threadIdx.x; i < 2 * L + 8; i += blockDim.x) Rt[i] = Rtg[i];
+    __syncthreads();
+    const int n = n0 + lane;
+    const bool valid = n < L;
+    const int ne = valid ? n : L - 1;
+    const int as = s < 0 ? -s : s;
+    const double nd = (double)ne;
+    const int jend = (Lp >> 1) - 1;
+    const InvGeo geo = inv_geometry(n0, m, as, segi, nsegi);
+    const int nseg = geo.nseg;
+
+    InvLane<EXT> st;
+    bool anyscaled;
+    const InvSeg g = inv_setup<EXT>(st, anyscaled, geo, w, n, m, L, Lp, as, segi, edge, edgek, stab, stabk, cki,
+                                    ckik, ckoff);
+    if (g.active)
+        inv_segment<EXT>(st, g.jfrom, g.jA, g.jlast, jend, geo.lstart, ne, nd, m, as, Lp, L, fs, lco, Rt,
+                         anyscaled);
     if (nseg > 1) {
         if (w > 0 && w < nseg) {
             red[w - 1][0][lane] = st.ap;
@@ -725,6 +830,328 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
     }
 }
 
+// ===========================================================================
+// Mixed precision (MW_FP32C): the same FP64 chains; each step's products
+// Delta * Delta are rounded to FP32 and accumulated by the matrix cores with
+// v_mfma_f32_4x4x1_16b_f32 (16 blocks of a 4x4 outer product per wave).  Block
+// b of the instruction owns lanes 4b..4b+3; with lane i holding its own chain
+// product as the B operand and component (i mod 4) of the uniform data as the A
+// operand, accumulator register v of lane i receives sum_k comp_v(k) * K_i(k):
+// every lane keeps its own four sums and nothing moves between lanes.  Several
+// maps of one spin share the chains: each adds one instruction per step.  The
+// uniform data (FP32, signs of the parity split folded in) is staged in LDS per
+// workgroup; partial sums of the segments are added in FP64.
+// ===========================================================================
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+template <bool EXT, bool INJ, int G>
+__device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT>& st, v4f (&acc)[2][G], int k, int l, int mb, int as,
+                                             const float* __restrict__ Hs, int nA, int comp, const FwdR& r,
+                                             bool& anyscaled)
+{
+    float k1[2], k0[2];
+    fwd_inject<2, EXT, INJ>(st, 2 * k + 1, l, anyscaled);
+    k1[0] = (float)fwd_product<2, EXT>(st, 0);
+    k1[1] = (float)fwd_product<2, EXT>(st, 1);
+    fwd_advance<2, EXT>(st, mb, as, r.hi.y * r.lo.x, anyscaled);
+    fwd_inject<2, EXT, INJ>(st, 2 * k, l, anyscaled);
+    k0[0] = (float)fwd_product<2, EXT>(st, 0);
+    k0[1] = (float)fwd_product<2, EXT>(st, 1);
+    fwd_advance<2, EXT>(st, mb, as, r.hi.x * r.lo.y, anyscaled);
+#pragma unroll
+    for (int b = 0; b < G; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const float2 a = *(const float2*)(Hs + ((b * 2 + c) * 4 + comp) * nA + 2 * k);   // n = 2k, 2k+1
+            acc[c][b] = mfma4(a.y, k1[c], acc[c][b]);
+            acc[c][b] = mfma4(a.x, k0[c], acc[c][b]);
+        }
+}
+
+template <bool EXT, int G>
+__device__ __forceinline__ void fwd_mix_segment(FwdLane<2, EXT>& st, v4f (&acc)[2][G], const FwdSeg& g, int l,
+                                                int le, int mb, int as, const double* __restrict__ Rt,
+                                                const float* __restrict__ Hs, int nA, int comp, bool& anyscaled)
+{
+    FwdR rn = fwd_load_r(Rt, le, g.ktop);
+    int k = g.ktop;
+    for (; k >= max(g.kA, g.klo); --k) {
+        const FwdR r = rn;
+        rn = fwd_load_r(Rt, le, max(k - 1, 0));
+        fwd_mix_pair<EXT, true, G>(st, acc, k, l, mb, as, Hs, nA, comp, r, anyscaled);
+    }
+    for (; k >= g.klo; --k) {
+        const FwdR r = rn;
+        rn = fwd_load_r(Rt, le, max(k - 1, 0));
+        fwd_mix_pair<EXT, false, G>(st, acc, k, l, mb, as, Hs, nA, comp, r, anyscaled);
+    }
+}
+
+// Forward contraction of a group of up to G maps of one spin (band-limits
+// maps.L[b] <= L, the plan's).  maps.src[b]: H of map b in FP32 at
+// [(m*4 + comp)*Lp_b + n], comp = (Re, Im) of sigma_+(n) H_{m,n} and of
+// sigma_-(n) H_{-m,n}, where sigma_+ = (-1)^n for s >= 0 (else 1) and sigma_- =
+// (-1)^n for s < 0 (else 1); maps.dst[b]: f_lm of map b.
+template <bool EXT, int G>
+__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
+    MixMaps maps, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
+    const double* __restrict__ cl, const double2* __restrict__ ckf, const int2* __restrict__ ckfk,
+    const int2* __restrict__ work, int L, int s, int segf)
+{
+    extern __shared__ double smem[];
+    const int grp = blockIdx.x;
+    const int w = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int l0 = uniform(work[grp].x), mb = uniform(work[grp].y);
+    if (l0 < 0) return;   // padding entry of the work list
+    bool any = false;
+    for (int b = 0; b < maps.n; ++b) any |= (l0 < maps.L[b] && mb < maps.L[b]);
+    if (!any) return;
+    const int rtn = 2 * L + 8;
+    double* Rt = smem;
+    float* Hs = (float*)(smem + rtn);
+    const int nmax = min(l0 + 63, L - 1);
+    const int nA = 2 * ((nmax >> 1) + 1);
+    for (int i = threadIdx.x; i < rtn; i += blockDim.x) Rt[i] = Rtg[i];
+    for (int i = threadIdx.x; i < G * 8 * nA; i += blockDim.x) {
+        const int n = i % nA, r = i / nA;
+        const int comp = r & 3, c = (r >> 2) & 1, b = r >> 3;
+        float v = 0.0f;
+        if (b < maps.n) {
+            const int Lb = maps.L[b], m = mb + c;
+            if (m < Lb && n < Lb) v = maps.src[b][((size_t)m * 4 + comp) * (size_t)(Lb + (Lb & 1)) + n];
+        }
+        Hs[i] = v;
+    }
+    __syncthreads();
+    const int l = l0 + lane;
+    const bool valid = l < L;
+    const int le = valid ? l : L - 1;
+    const int as = s < 0 ? -s : s;
+    const int jtop = nmax / segf;
+
+    FwdLane<2, EXT> st;
+    bool anyscaled;
+    const FwdSeg g = fwd_setup<2, EXT>(st, anyscaled, w, l0, mb, l, L, as, segf, edge, edgek, ckf, ckfk);
+    v4f acc[2][G];
+#pragma unroll
+    for (int b = 0; b < G; ++b) acc[0][b] = acc[1][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    if (g.active) fwd_mix_segment<EXT, G>(st, acc, g, l, le, mb, as, Rt, Hs, nA, lane & 3, anyscaled);
+
+    double sum[2][G][4];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < G; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sum[c][b][v] = (double)acc[c][b][v];
+    if (jtop > 0) {
+        __syncthreads();                 // every wave is done with Hs
+        v4f* red = (v4f*)Hs;             // [(w-1)][c][b][lane]
+        if (w > 0 && w <= jtop) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int b = 0; b < G; ++b) red[(((w - 1) * 2 + c) * G + b) * 64 + lane] = acc[c][b];
+        }
+        __syncthreads();
+        if (w != 0) return;
+        for (int j = 1; j <= jtop; ++j)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int b = 0; b < G; ++b) {
+                    const v4f v = red[(((j - 1) * 2 + c) * G + b) * 64 + lane];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) sum[c][b][q] += (double)v[q];
+                }
+    } else if (w != 0) {
+        return;
+    }
+    if (!valid) return;
+    const double base = sgn(s) * cl[l];
+#pragma unroll
+    for (int b = 0; b < G; ++b) {
+        if (b >= maps.n || l >= maps.L[b]) continue;
+        double2* flm = maps.dst[b];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int m = mb + c;
+            if (m > l || m >= maps.L[b]) continue;
+            const double fp = (s >= 0) ? sgn(m + l + s) : sgn(m + s);
+            const double fm = (s >= 0) ? sgn(m + s) : sgn(l + m + s);
+            const double2 op = mul_ipow(make_double2(sum[c][b][0], sum[c][b][1]), ((m + s) % 4 + 4) % 4);
+            flm[(size_t)l * l + l + m] = make_double2(op.x * base * fp, op.y * base * fp);
+            if (m > 0) {
+                const double2 om = mul_ipow(make_double2(sum[c][b][2], sum[c][b][3]), ((-m + s) % 4 + 4) % 4);
+                flm[(size_t)l * l + l - m] = make_double2(om.x * base * fm, om.y * base * fm);
+            }
+        }
+    }
+}
+
+struct InvC { double4 cm, cs; };   // pair (l, l+1): (Pu,Qu)_m, (Pu,Qu)_s
+
+__device__ __forceinline__ void inv_load_c(InvC& u, const double2* __restrict__ lco, int m, int as, int Lp, int j)
+{
+    u.cm = *(const double4*)(lco + (size_t)m * Lp + 2 * j);
+    u.cs = *(const double4*)(lco + (size_t)as * Lp + 2 * j);
+}
+
+template <bool EXT, bool INJ, int G>
+__device__ __forceinline__ void inv_mix_pair(InvLane<EXT>& st, v4f (&acc)[G], int j, int lstart, double nd,
+                                             const InvC& u, const InvR& r, const float* __restrict__ Fs, int nS,
+                                             int lbase, int comp, bool& anyscaled)
+{
+    const int l = 2 * j;
+    inv_inject<EXT, INJ>(st, l, lstart, anyscaled);
+    const float k0 = (float)inv_product<EXT>(st);
+    inv_advance<EXT>(st, nd, u.cm.x, u.cm.y, u.cs.x, u.cs.y, r.a.x * r.b.x, anyscaled);
+    inv_inject<EXT, INJ>(st, l + 1, lstart, anyscaled);
+    const float k1 = (float)inv_product<EXT>(st);
+    inv_advance<EXT>(st, nd, u.cm.z, u.cm.w, u.cs.z, u.cs.w, r.a.y * r.b.y, anyscaled);
+#pragma unroll
+    for (int b = 0; b < G; ++b) {
+        const float2 a = *(const float2*)(Fs + (b * 4 + comp) * nS + (l - lbase));   // degrees l, l+1
+        acc[b] = mfma4(a.x, k0, acc[b]);
+        acc[b] = mfma4(a.y, k1, acc[b]);
+    }
+}
+
+template <bool EXT, int G>
+__device__ __forceinline__ void inv_mix_segment(InvLane<EXT>& st, v4f (&acc)[G], const InvSeg& g, int jend,
+                                                int lstart, int ne, double nd, int m, int as, int Lp,
+                                                const double2* __restrict__ lco, const double* __restrict__ Rt,
+                                                const float* __restrict__ Fs, int nS, int lbase, int comp,
+                                                bool& anyscaled)
+{
+    InvC un;
+    inv_load_c(un, lco, m, as, Lp, g.jfrom);
+    InvR rn = inv_load_r(Rt, ne, g.jfrom);
+    int j = g.jfrom;
+    for (; j <= min(g.jA, g.jlast); ++j) {
+        wait_scalar(un.cm.x);
+        const InvC u = un;
+        const InvR r = rn;
+        const int jn = min(j + 1, jend);
+        inv_load_c(un, lco, m, as, Lp, jn);
+        rn = inv_load_r(Rt, ne, jn);
+        inv_mix_pair<EXT, true, G>(st, acc, j, lstart, nd, u, r, Fs, nS, lbase, comp, anyscaled);
+    }
+    for (; j <= g.jlast; ++j) {
+        wait_scalar(un.cm.x);
+        const InvC u = un;
+        const InvR r = rn;
+        const int jn = min(j + 1, jend);
+        inv_load_c(un, lco, m, as, Lp, jn);
+        rn = inv_load_r(Rt, ne, jn);
+        inv_mix_pair<EXT, false, G>(st, acc, j, lstart, nd, u, r, Fs, nS, lbase, comp, anyscaled);
+    }
+}
+
+// Inverse contraction of a group of up to G maps of one spin (band-limits
+// maps.L[b] <= L).  maps.src[b]: the FP32 coefficient stream of map b at
+// [(m*4 + comp)*Lp_b + l] (the four values of the FP64 stream record);
+// maps.dst[b]: F of map b at [(L_b - 1 + m)*L_b + n].
+template <bool EXT, int G>
+__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse_mix(
+    MixMaps maps, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
+    const double2* __restrict__ lco, const double* __restrict__ stab, const int* __restrict__ stabk,
+    const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work,
+    int L, int Lp, int s, int segi, int nsegi)
+{
+    extern __shared__ double smem[];
+    const int grp = blockIdx.x;
+    const int w = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int n0 = uniform(work[grp].x), m = uniform(work[grp].y);
+    if (n0 < 0) return;   // padding entry of the work list
+    bool any = false;
+    for (int b = 0; b < maps.n; ++b) any |= (n0 < maps.L[b] && m < maps.L[b]);
+    if (!any) return;
+    const int as = s < 0 ? -s : s;
+    const InvGeo geo = inv_geometry(n0, m, as, segi, nsegi);
+    const int rtn = 2 * L + 8;
+    double* Rt = smem;
+    float* Fs = (float*)(smem + rtn);
+    const int lbase = geo.lstart;
+    const int nS = Lp - lbase;
+    for (int i = threadIdx.x; i < rtn; i += blockDim.x) Rt[i] = Rtg[i];
+    for (int i = threadIdx.x; i < G * 4 * nS; i += blockDim.x) {
+        const int l = lbase + i % nS, r = i / nS;
+        const int comp = r & 3, b = r >> 2;
+        float v = 0.0f;
+        if (b < maps.n) {
+            const int Lb = maps.L[b];
+            if (m < Lb && l < Lb) v = maps.src[b][((size_t)m * 4 + comp) * (size_t)(Lb + (Lb & 1)) + l];
+        }
+        Fs[i] = v;
+    }
+    __syncthreads();
+    const int n = n0 + lane;
+    const bool valid = n < L;
+    const int ne = valid ? n : L - 1;
+    const double nd = (double)ne;
+    const int jend = (Lp >> 1) - 1;
+    const int nseg = geo.nseg;
+
+    InvLane<EXT> st;
+    bool anyscaled;
+    const InvSeg g = inv_setup<EXT>(st, anyscaled, geo, w, n, m, L, Lp, as, segi, edge, edgek, stab, stabk, cki,
+                                    ckik, ckoff);
+    v4f acc[G];
+#pragma unroll
+    for (int b = 0; b < G; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
+    if (g.active)
+        inv_mix_segment<EXT, G>(st, acc, g, jend, geo.lstart, ne, nd, m, as, Lp, lco, Rt, Fs, nS, lbase, lane & 3,
+                                anyscaled);
+
+    double sum[G][4];
+#pragma unroll
+    for (int b = 0; b < G; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sum[b][v] = (double)acc[b][v];
+    if (nseg > 1) {
+        __syncthreads();                 // every wave is done with Fs
+        v4f* red = (v4f*)Fs;             // [(w-1)][b][lane]
+        if (w > 0 && w < nseg) {
+#pragma unroll
+            for (int b = 0; b < G; ++b) red[((w - 1) * G + b) * 64 + lane] = acc[b];
+        }
+        __syncthreads();
+        if (w != 0) return;
+        for (int j = 1; j < nseg; ++j)
+#pragma unroll
+            for (int b = 0; b < G; ++b) {
+                const v4f v = red[((j - 1) * G + b) * 64 + lane];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sum[b][q] += (double)v[q];
+            }
+    } else if (w != 0) {
+        return;
+    }
+    const double fsp = sgn(s) * ((s >= 0) ? sgn(n) : 1.0);
+    const double fsm = sgn(s) * ((s < 0) ? sgn(n) : 1.0);
+#pragma unroll
+    for (int b = 0; b < G; ++b) {
+        if (b >= maps.n) continue;
+        const int Lb = maps.L[b];
+        if (n >= Lb || m >= Lb) continue;
+        double2* F = maps.dst[b];
+        const double2 op = mul_ipow(make_double2(sum[b][0], sum[b][1]), ((-(m + s)) % 4 + 4) % 4);
+        F[(size_t)(Lb - 1 + m) * Lb + n] = make_double2(op.x * fsp, op.y * fsp);
+        if (m > 0) {
+            const double2 om = mul_ipow(make_double2(sum[b][2], sum[b][3]), ((m - s) % 4 + 4) % 4);
+            F[(size_t)(Lb - 1 - m) * Lb + n] = make_double2(om.x * fsm, om.y * fsm);
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_contract_forward(const Plan& p, int s, int real, const double* Hp, double2* flm,
@@ -749,10 +1176,12 @@ hipError_t launch_real_fold(int L, double2* y, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_inverse_stream(const Plan& p, int s, int real, const double2* flm, double* fs, hipStream_t st)
+hipError_t launch_inverse_stream(const Plan& p, int s, int real, const double2* flm, void* fs, int out32,
+                                 hipStream_t st)
 {
     const dim3 grid((p.Lp + STR_L - 1) / STR_L, (p.L + STR_M - 1) / STR_M);
-    hipLaunchKernelGGL(k_inverse_stream, grid, dim3(256), 0, st, flm, fs, p.cl, p.L, p.Lp, s, real);
+    if (out32) hipLaunchKernelGGL(k_inverse_stream<1>, grid, dim3(256), 0, st, flm, fs, p.cl, p.L, p.Lp, s, real);
+    else hipLaunchKernelGGL(k_inverse_stream<0>, grid, dim3(256), 0, st, flm, fs, p.cl, p.L, p.Lp, s, real);
     return hipGetLastError();
 }
 
@@ -770,6 +1199,91 @@ hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, co
         hipLaunchKernelGGL((k_contract_inverse<false>), grid, block, lds, st, fs, F, p.rtab, p.edge, p.edgek, p.lco,
                            sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
     return hipGetLastError();
+}
+
+// ---- mixed precision launchers ------------------------------------------
+namespace {
+
+size_t mix_lds_forward(const Plan& p, int G)
+{
+    const size_t stage = (size_t)G * 8 * p.Lp * sizeof(float);
+    const size_t red = (size_t)(SEG_MAX - 1) * 2 * G * 64 * 16;
+    return (size_t)(2 * p.L + 8) * sizeof(double) + std::max(stage, red);
+}
+
+size_t mix_lds_inverse(const Plan& p, int G)
+{
+    const size_t stage = (size_t)G * 4 * p.Lp * sizeof(float);
+    const size_t red = (size_t)(SEG_MAX - 1) * G * 64 * 16;
+    return (size_t)(2 * p.L + 8) * sizeof(double) + std::max(stage, red);
+}
+
+template <class K>
+hipError_t mix_attr(K kernel, size_t bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <bool EXT, int G>
+hipError_t fwd_mix_go(const Plan& p, int s, const MixMaps& maps, hipStream_t st)
+{
+    const size_t lds = mix_lds_forward(p, G);
+    hipError_t e = mix_attr(k_contract_forward_mix<EXT, G>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_contract_forward_mix<EXT, G>), dim3(p.nworkf), dim3(64 * SEG_MAX), lds, st, maps, p.rtab,
+                       p.edge, p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, s, p.segf);
+    return hipGetLastError();
+}
+
+template <bool EXT, int G>
+hipError_t inv_mix_go(const Plan& p, const SpinTable& sp, int s, const MixMaps& maps, hipStream_t st)
+{
+    CkOff off;
+    for (int j = 0; j < SEG_MAX; ++j) off.off[j] = p.cki_off[j];
+    const size_t lds = mix_lds_inverse(p, G);
+    hipError_t e = mix_attr(k_contract_inverse_mix<EXT, G>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_contract_inverse_mix<EXT, G>), dim3(p.nworki), dim3(64 * SEG_MAX), lds, st, maps, p.rtab,
+                       p.edge, p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi,
+                       p.nsegi);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int mix_group_max(const Plan& p)
+{
+    for (int G = GMAX; G > 1; G >>= 1)
+        if (mix_lds_forward(p, G) <= 160 * 1024 && mix_lds_inverse(p, G) <= 160 * 1024) return G;
+    return 1;
+}
+
+hipError_t launch_contract_forward_mix(const Plan& p, int s, const MixMaps& maps, int G, hipStream_t st)
+{
+    if (maps.n < 1 || maps.n > G || G > GMAX) return hipErrorInvalidValue;
+    if (p.ext) {
+        if (G == 1) return fwd_mix_go<true, 1>(p, s, maps, st);
+        if (G == 2) return fwd_mix_go<true, 2>(p, s, maps, st);
+        return fwd_mix_go<true, 4>(p, s, maps, st);
+    }
+    if (G == 1) return fwd_mix_go<false, 1>(p, s, maps, st);
+    if (G == 2) return fwd_mix_go<false, 2>(p, s, maps, st);
+    return fwd_mix_go<false, 4>(p, s, maps, st);
+}
+
+hipError_t launch_contract_inverse_mix(const Plan& p, const SpinTable& sp, int s, const MixMaps& maps, int G,
+                                       hipStream_t st)
+{
+    if (maps.n < 1 || maps.n > G || G > GMAX) return hipErrorInvalidValue;
+    if (p.ext) {
+        if (G == 1) return inv_mix_go<true, 1>(p, sp, s, maps, st);
+        if (G == 2) return inv_mix_go<true, 2>(p, sp, s, maps, st);
+        return inv_mix_go<true, 4>(p, sp, s, maps, st);
+    }
+    if (G == 1) return inv_mix_go<false, 1>(p, sp, s, maps, st);
+    if (G == 2) return inv_mix_go<false, 2>(p, sp, s, maps, st);
+    return inv_mix_go<false, 4>(p, sp, s, maps, st);
 }
 
 }  // namespace mw

@@ -268,9 +268,13 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, const void* __restr
 // instead: Z_{m m'} = sum_{t<L} G_m(theta_t) e^{-i m' theta_t} (the conjugate
 // transpose of Eq.(Fmt): no extension, no 1/(2 pi N1), no weights), folded the
 // same way, because the adjoint's contraction is the forward's.
-template <int ADJ_INV>
+// OUT32 = 1 writes H in FP32 at [(|m|*4 + comp)*Lp + n] instead, comp = (Re, Im)
+// of sigma_+(n) H_{m,n} (m >= 0) and of sigma_-(n) H_{-m,n} (m <= 0), with the
+// parity split of the contraction folded in: sigma_+ = (-1)^n for s >= 0 and
+// sigma_- = (-1)^n for s < 0 (1 otherwise).
+template <int ADJ_INV, int OUT32>
 __global__ __launch_bounds__(512) void k_theta_forward(Plan p, int s, const double2* __restrict__ G,
-                                                       double* __restrict__ Hp)
+                                                       void* __restrict__ Hout)
 {
     extern __shared__ double2 A[];
     const int L = p.L, N1 = p.N1, N2 = p.N2;
@@ -329,9 +333,24 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, int s, const doub
             v = A[P(n)];
             if (n > 0) v = cadd(v, cscale(A[P(wrap - n)], sig));
         }
-        double* rec = Hp + ((size_t)am * p.Lp + n) * 4;
-        if (m >= 0) { rec[0] = v.x; rec[1] = v.y; }
-        if (m <= 0) { rec[2] = v.x; rec[3] = v.y; }
+        if (OUT32) {
+            float* h = (float*)Hout + (size_t)am * 4 * p.Lp + n;
+            const double par = (n & 1) ? -1.0 : 1.0;
+            if (m >= 0) {
+                const double sg = (s >= 0) ? par : 1.0;
+                h[0] = (float)(sg * v.x);
+                h[(size_t)p.Lp] = (float)(sg * v.y);
+            }
+            if (m <= 0) {
+                const double sg = (s < 0) ? par : 1.0;
+                h[2 * (size_t)p.Lp] = (float)(sg * v.x);
+                h[3 * (size_t)p.Lp] = (float)(sg * v.y);
+            }
+        } else {
+            double* rec = (double*)Hout + ((size_t)am * p.Lp + n) * 4;
+            if (m >= 0) { rec[0] = v.x; rec[1] = v.y; }
+            if (m <= 0) { rec[2] = v.x; rec[3] = v.y; }
+        }
     }
 }
 
@@ -481,22 +500,27 @@ hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2*
     return hipGetLastError();
 }
 
-hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, double* Hp, hipStream_t st)
+namespace {
+template <int ADJ_INV, int OUT32>
+hipError_t theta_forward_go(const Plan& p, int s, const double2* G, void* H, hipStream_t st)
 {
     const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     hipError_t e;
-    if ((e = set_lds(k_theta_forward<0>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_theta_forward<0>, dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s, G, Hp);
+    if ((e = set_lds(k_theta_forward<ADJ_INV, OUT32>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_theta_forward<ADJ_INV, OUT32>), dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s,
+                       G, H);
     return hipGetLastError();
 }
+}  // namespace
 
-hipError_t launch_theta_inverse_adjoint(const Plan& p, int s, const double2* G, double* Hp, hipStream_t st)
+hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, void* H, int out32, hipStream_t st)
 {
-    const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
-    hipError_t e;
-    if ((e = set_lds(k_theta_forward<1>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_theta_forward<1>, dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s, G, Hp);
-    return hipGetLastError();
+    return out32 ? theta_forward_go<0, 1>(p, s, G, H, st) : theta_forward_go<0, 0>(p, s, G, H, st);
+}
+
+hipError_t launch_theta_inverse_adjoint(const Plan& p, int s, const double2* G, void* H, int out32, hipStream_t st)
+{
+    return out32 ? theta_forward_go<1, 1>(p, s, G, H, st) : theta_forward_go<1, 0>(p, s, G, H, st);
 }
 
 hipError_t launch_theta_forward_adjoint(const Plan& p, int s, const double2* Y, double2* Gt, hipStream_t st)

@@ -69,6 +69,17 @@ struct SpinTable {
 constexpr int MT_FWD = 2;
 constexpr int MT_INV = 1;
 
+// Mixed-precision contraction: a group of up to GMAX maps of one spin shares the
+// FP64 chains.  src/dst are per-map device pointers (FP32 staged H or stream;
+// f_lm or F), L the per-map band-limits (<= the plan's).
+constexpr int GMAX = 4;
+struct MixMaps {
+    const float* src[GMAX];
+    double2* dst[GMAX];
+    int L[GMAX];
+    int n;
+};
+
 int build_plan(int L, Plan& p, std::string& err);
 void free_plan(Plan& p);
 int build_spin_table(int L, int as, SpinTable& t, std::string& err);
@@ -79,16 +90,25 @@ void free_spin_table(SpinTable& t);
 hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2* G, double sc, hipStream_t st);
 // Hp: forward Fourier coefficients H_{+-m,n} as records (Re H_{m,n}, Im H_{m,n},
 // Re H_{-m,n}, Im H_{-m,n}) at [(m * Lp + n) * 4], m < L, n < Lp (pad rows zero).
-hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, double* Hp, hipStream_t st);
-// Theta step of the adjoint of the inverse (same output layout as launch_theta_forward).
-hipError_t launch_theta_inverse_adjoint(const Plan& p, int s, const double2* G, double* Hp, hipStream_t st);
+// out32 = 1: FP32 H at [(m*4 + comp)*Lp + n] with the parity signs folded (the
+// mixed-precision contraction's staging layout).
+hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, void* H, int out32, hipStream_t st);
+// Theta step of the adjoint of the inverse (same output layouts as launch_theta_forward).
+hipError_t launch_theta_inverse_adjoint(const Plan& p, int s, const double2* G, void* H, int out32, hipStream_t st);
 // Theta step of the adjoint of the forward: folded Y (N1 x L) -> Gt (L x N1).
 hipError_t launch_theta_forward_adjoint(const Plan& p, int s, const double2* Y, double2* Gt, hipStream_t st);
 hipError_t launch_contract_forward(const Plan& p, int s, int real, const double* Hp, double2* flm,
                                    hipStream_t st);
 // fs: per-map scratch of L x Lp x 4 doubles (the inverse's scaled coefficient stream),
 // written by launch_inverse_stream and read by launch_contract_inverse.
-hipError_t launch_inverse_stream(const Plan& p, int s, int real, const double2* flm, double* fs, hipStream_t st);
+hipError_t launch_inverse_stream(const Plan& p, int s, int real, const double2* flm, void* fs, int out32,
+                                 hipStream_t st);
+// Largest group size (1, 2 or 4) whose staging fits the LDS for this plan.
+int mix_group_max(const Plan& p);
+// Mixed-precision contractions of one group (maps.n <= G <= GMAX, G in {1,2,4}).
+hipError_t launch_contract_forward_mix(const Plan& p, int s, const MixMaps& maps, int G, hipStream_t st);
+hipError_t launch_contract_inverse_mix(const Plan& p, const SpinTable& sp, int s, const MixMaps& maps, int G,
+                                       hipStream_t st);
 hipError_t launch_contract_inverse(const Plan& p, const SpinTable& st_, int s, const double* fs, double2* F,
                                    hipStream_t st);
 hipError_t launch_theta_inverse(const Plan& p, int s, const double2* F, double2* Ft, hipStream_t st);

@@ -1,0 +1,160 @@
+"""GPU mixed-precision path (MW_FP32C) against the FP64 CPU oracle.
+
+The O(L^3) contraction rounds Delta*Delta and the Fourier data to FP32 and
+accumulates on the matrix cores; everything else stays FP64.  Stated bound:
+infinity-norm relative error <= 1e-6 against the oracle (FP32 rounding of the
+two factors is 2^-24 each; the sums over up to L terms with random signs and
+segment-wise FP32 accumulation stay two orders of magnitude below the bound
+at L <= 512, measured ~1e-7).
+"""
+import numpy as np
+import pytest
+
+import mwsynth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+FP32C = 1
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mw(tc):
+    import paper_1110_6298_amd as m
+    m.library()
+    return m
+
+
+def dev(tc, x):
+    return tc.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(tc, t):
+    tc.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+CASES = [(1, 0), (2, 1), (3, -2), (8, 0), (17, 3), (31, -3), (64, 2), (65, 0), (100, -1), (129, 7), (257, -2)]
+
+
+@pytest.mark.parametrize("L,s", CASES)
+def test_mixed_inverse_and_forward(orc, tc, mw, L, s):
+    print("mixed L=%d s=%d" % (L, s), flush=True)
+    flm = mwsynth.flm_gaussian(L, s, seed=11000 + L + s)
+    xref = orc.inverse(flm, L, s)
+    x = host(tc, mw.inverse(dev(tc, flm), L, s, precision=FP32C))
+    assert rel(x, xref) < TOL
+    g = xref + 0.5 * mwsynth.grid_gaussian(L, seed=11100 + L)
+    fref = orc.forward(g, L, s)
+    f = host(tc, mw.forward(dev(tc, g), L, s, precision=FP32C))
+    assert rel(f, fref) < TOL
+
+
+@pytest.mark.parametrize("L,s", [(8, 2), (65, -1), (128, 2)])
+def test_mixed_adjoints(orc, tc, mw, L, s):
+    print("mixed adjoints L=%d s=%d" % (L, s), flush=True)
+    y = mwsynth.flm_gaussian(L, 0, seed=12000 + L)
+    ref = orc.forward_adjoint(y, L, s)
+    assert rel(host(tc, mw.forward_adjoint(dev(tc, y), L, s, precision=FP32C)), ref) < TOL
+    g = mwsynth.grid_gaussian(L, seed=12100 + L)
+    ref = orc.inverse_adjoint(g, L, s)
+    assert rel(host(tc, mw.inverse_adjoint(dev(tc, g), L, s, precision=FP32C)), ref) < TOL
+
+
+def test_mixed_config_spin2_l512(orc, tc, mw):
+    """L = 512, s = 2, f_lm ~ (N + iN)/(l+1): the mixed path against the oracle,
+    and the FP64 path's error stated beside it."""
+    w = mwsynth.workload_spin2_l512()
+    L, s, flm = w["L"], w["s"], w["flm"]
+    xref = orc.inverse(flm, L, s)
+    fref = orc.forward(xref, L, s)
+    x32 = host(tc, mw.inverse(dev(tc, flm), L, s, precision=FP32C))
+    f32 = host(tc, mw.forward(dev(tc, xref), L, s, precision=FP32C))
+    e_inv, e_fwd = rel(x32, xref), rel(f32, fref)
+    print("FP32C L=512 s=2: inverse %.3e forward %.3e" % (e_inv, e_fwd), flush=True)
+    assert e_inv < TOL and e_fwd < TOL
+    # a mixed round trip returns the coefficients to the same bound
+    back = host(tc, mw.forward(mw.inverse(dev(tc, flm), L, s, precision=FP32C), L, s, precision=FP32C))
+    assert rel(back, flm) < 2 * TOL
+
+
+def test_mixed_real_maps(orc, tc, mw):
+    L = 96
+    flm = mwsynth.make_real_symmetric(mwsynth.flm_gaussian(L, 0, seed=13000), L)
+    xref = np.real(orc.inverse(flm, L, 0))
+    x = host(tc, mw.inverse(dev(tc, flm), L, 0, reality=1, precision=FP32C))
+    assert x.dtype == np.float64 and rel(x, xref) < TOL
+    f = host(tc, mw.forward(dev(tc, xref), L, 0, reality=1, precision=FP32C))
+    assert rel(f, orc.forward(xref.astype(np.complex128), L, 0)) < TOL
+
+
+def test_mixed_batch_of_uneven_maps(orc, tc, mw):
+    """Maps of several band-limits and spins in one call: maps of one spin share
+    the chains in groups; each map matches the oracle and its own single call."""
+    specs = [(64, 2, 0), (48, 2, 0), (33, 2, 0), (64, 0, 1), (40, 0, 0), (64, 0, 1), (17, -1, 0), (64, 2, 0),
+             (50, 0, 1)]
+    Ls = [a for a, _, _ in specs]
+    ss = [b for _, b, _ in specs]
+    rs = [c for _, _, c in specs]
+    flms = []
+    for i, (L, s, r) in enumerate(specs):
+        f = mwsynth.flm_gaussian(L, s, seed=14000 + i)
+        if r:
+            f = mwsynth.make_real_symmetric(f, L)
+        flms.append(f)
+    mw.prepare(Ls, ss, rs, precision=FP32C)
+    maps = mw.inverse_batch([dev(tc, f) for f in flms], Ls, ss, rs, precision=FP32C)
+    maps_h = [host(tc, m) for m in maps]
+    for i, (L, s, r) in enumerate(specs):
+        ref = orc.inverse(flms[i], L, s)
+        if r:
+            ref = np.real(ref)
+        assert rel(maps_h[i], ref) < TOL, i
+        single = host(tc, mw.inverse(dev(tc, flms[i]), L, s, r, precision=FP32C))
+        assert rel(maps_h[i], single) < TOL, i
+    back = mw.forward_batch([dev(tc, m) for m in maps_h], Ls, ss, rs, precision=FP32C)
+    for i, (L, s, r) in enumerate(specs):
+        grid = maps_h[i].astype(np.complex128)
+        assert rel(host(tc, back[i]), orc.forward(grid, L, s)) < TOL, i
+
+
+def test_mixed_batch_equal_band_limits_is_exact(tc, mw):
+    """Maps of one band-limit and spin are bitwise the same in any group size:
+    each keeps its own accumulators over the same shared chains."""
+    L, s, n = 80, 2, 5
+    flms = [mwsynth.flm_gaussian(L, s, seed=15000 + i) for i in range(n)]
+    outs = mw.inverse_batch([dev(tc, f) for f in flms], [L] * n, [s] * n, precision=FP32C)
+    for i in range(n):
+        single = mw.inverse(dev(tc, flms[i]), L, s, precision=FP32C)
+        assert np.array_equal(host(tc, outs[i]), host(tc, single))
+
+
+def test_mixed_large_l_sampled(orc, tc, mw):
+    """L = 2048 real scalar map with C_l = (l+1)^-2 in mixed precision: sampled
+    coefficients of the forward against the oracle's per-order forward."""
+    w = mwsynth.workload_real_l2048()
+    L, flm = w["L"], w["flm"]
+    x = mw.inverse(dev(tc, flm), L, 0, reality=1)             # FP64 synthesis on the GPU
+    f = host(tc, mw.forward(x, L, 0, reality=1, precision=FP32C))
+    orders = [0, 1, 700, 1500, 2047]
+    ref = orc.forward_orders(host(tc, x).astype(np.complex128), L, 0, orders)
+    got, want = [], []
+    for k, m in enumerate(orders):
+        ls = np.arange(m, L)
+        got.append(f[ls * ls + ls + m])
+        want.append(ref[k, ls])
+    got, want = np.concatenate(got), np.concatenate(want)
+    print("FP32C L=2048 real, sampled orders: %.3e" % rel(got, want), flush=True)
+    assert rel(got, want) < TOL
