@@ -51,6 +51,61 @@ def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+def time_steps(torch, step, steps, warmup):
+    """ms per step of `step` (enqueued on the current stream), timed with events
+    around `steps` calls after `warmup` untimed ones."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def kernel_profile(mw, step, steps):
+    """Average duration (ms) of each stage from libmw's own HIP events, recorded
+    on the launch stream around every launch."""
+    mw.profile_enable(True)
+    for _ in range(steps):
+        step()
+    prof = mw.profile_read()
+    mw.profile_enable(False)
+    return {k: v[0] / v[1] for k, v in prof.items()}
+
+
+def batched_workload(torch, mw, dev, steps, warmup, precision):
+    """The 256-map batch: L uniform on {128, 256, 512}, spin on {0, 2}, half of the
+    maps drawn with real-map coefficient symmetry (only the s = 0 ones run the
+    real path).  One step = one batched inverse + one batched forward call."""
+    import mwsynth
+    maps = mwsynth.workload_batch_mixed()
+    Ls = [m["L"] for m in maps]
+    ss = [m["s"] for m in maps]
+    rs = [1 if (m["real"] and m["s"] == 0) else 0 for m in maps]
+    flm = [torch.from_numpy(m["flm"]).to(dev) for m in maps]
+    grids = [torch.empty((L, 2 * L - 1), dtype=torch.float64 if r else torch.complex128, device=dev)
+             for L, r in zip(Ls, rs)]
+    back = [torch.empty(L * L, dtype=torch.complex128, device=dev) for L in Ls]
+    mw.prepare(Ls, ss, rs, precision=precision)
+
+    def step():
+        mw.inverse_batch(flm, Ls, ss, rs, precision=precision, outs=grids)
+        mw.forward_batch(grids, Ls, ss, rs, precision=precision, outs=back)
+
+    ms = time_steps(torch, step, steps, warmup)
+    err = 0.0
+    for b in range(len(maps)):
+        ref = maps[b]["flm"]
+        got = back[b].cpu().numpy()
+        err = max(err, rel(got, ref))
+    return ms, len(maps), err
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +114,8 @@ def main():
     ap.add_argument("--L", type=int, default=512)
     ap.add_argument("--spin", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-map batched workload")
+    ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle baseline sample (whole round trips)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -81,36 +138,24 @@ def main():
     flm_h = w["flm"]
     dev = torch.device("cuda", 0)
     flm = torch.from_numpy(flm_h).to(dev)
-    xmap = torch.empty((L, 2 * L - 1), dtype=torch.complex128, device=dev)
-    back = torch.empty(L * L, dtype=torch.complex128, device=dev)
+    xmap = {p: torch.empty((L, 2 * L - 1), dtype=torch.complex128, device=dev) for p in (mw.FP64, mw.FP32C)}
+    back = {p: torch.empty(L * L, dtype=torch.complex128, device=dev) for p in (mw.FP64, mw.FP32C)}
     mw.prepare([L], [s])
+    mw.prepare([L], [s], precision=mw.FP32C)
 
-    def step():
-        mw.inverse(flm, L, s, out=xmap)
-        mw.forward(xmap, L, s, out=back)
+    def stepper(prec):
+        def step():
+            mw.inverse(flm, L, s, precision=prec, out=xmap[prec])
+            mw.forward(xmap[prec], L, s, precision=prec, out=back[prec])
+        return step
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
     wall0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
+    ms_step = time_steps(torch, stepper(mw.FP64), args.steps, args.warmup)
     wall = time.perf_counter() - wall0
-    ms_total = t0.elapsed_time(t1)
-    ms_step = ms_total / args.steps
+    per_kernel = kernel_profile(mw, stepper(mw.FP64), args.steps)
+    ms_mixed = time_steps(torch, stepper(mw.FP32C), args.steps, args.warmup)
+    per_kernel_mixed = kernel_profile(mw, stepper(mw.FP32C), args.steps)
 
-    # per-kernel durations: the same steps again with per-launch events
-    mw.profile_enable(True)
-    for _ in range(args.steps):
-        step()
-    prof = mw.profile_read()
-    mw.profile_enable(False)
-    per_kernel = {k: v[0] / v[1] for k, v in prof.items()}
     dom = max(per_kernel, key=lambda k: per_kernel[k])
     flops = contraction_flops(L, s)
     kernels = {k: {"avg_us": 1e3 * v} for k, v in per_kernel.items()}
@@ -130,8 +175,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    x_h = xmap.cpu().numpy()
-    back_h = back.cpu().numpy()
+    x_h = xmap[mw.FP64].cpu().numpy()
+    back_h = back[mw.FP64].cpu().numpy()
+    x32_h = xmap[mw.FP32C].cpu().numpy()
+    back32_h = back[mw.FP32C].cpu().numpy()
     result = {
         "metric": "MW fwd+inv transforms/sec at L=512 s=2 (FP64 vs mixed) at stated max rel error",
         "value": 1e3 / ms_step,
@@ -153,10 +200,27 @@ def main():
         "roofline": {"kernel": dom_c, "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
                      "flops_per_launch": flops},
+        "mixed": {"precision": "fp32c", "dtype": "f32 contraction (MFMA), f64 recursion and Fourier stages",
+                  "value": 1e3 / ms_mixed, "unit": "round trips/s", "ms_per_step": ms_mixed,
+                  "stated_max_rel_err": 1e-6,
+                  "rel_err_vs_fp64": {"inverse_map": rel(x32_h, x_h), "forward_coeffs": rel(back32_h, back_h)},
+                  "round_trip_rel_err": rel(back32_h, flm_h),
+                  "kernels": {k: {"avg_us": 1e3 * v} for k, v in per_kernel_mixed.items()}},
     }
     tr = TRAFFIC.get((dom_c, L, s))
     if tr is not None and tr["source_sha256"] == kernel_source_hash():
         result["roofline"]["traffic"] = tr["bytes"]
+
+    if not args.no_batch:
+        batched = {}
+        for name, prec in (("fp64", mw.FP64), ("fp32c", mw.FP32C)):
+            ms_b, nmaps, err_b = batched_workload(torch, mw, dev, args.batch_steps, 2, prec)
+            batched[name] = {"maps_round_trips_per_s": nmaps * 1e3 / ms_b, "ms_per_step": ms_b,
+                             "round_trip_rel_err": err_b}
+        batched["workload"] = ("256 maps, L uniform on {128,256,512}, spin uniform on {0,2}, 128 with real-map "
+                               "coefficient symmetry (s=0 ones on the real path), f_lm ~ N(0,1)/(l+1), seed 1003; "
+                               "one step = batched inverse + batched forward")
+        result["batched"] = batched
 
     if not args.no_cpu_baseline:
         import oracle
@@ -175,6 +239,8 @@ def main():
                                   "sample": "%d full round trips (inverse + forward) of the same L=%d s=%d map, "
                                             "%.1f s" % (count, L, s, dt)}
         result["max_rel_err_vs_oracle"] = {"inverse_map": rel(x_h, xo), "forward_coeffs": rel(back_h, fo)}
+        result["mixed"]["max_rel_err_vs_oracle"] = {"inverse_map": rel(x32_h, xo),
+                                                    "forward_coeffs": rel(back32_h, fo)}
     print(json.dumps(result))
 
 

@@ -166,12 +166,12 @@ constexpr double TWO_PI = 6.283185307179586476925286766559;
 
 struct Regions { double2* W0; double2* W1; double* W2; };
 
-// Workspace slot k of a call whose largest band-limit is Lmax: three regions,
-// W0 (N1 x L complex), W1 (max of N1 x L complex and the H records), W2 (the
-// inverse's coefficient stream), each 256-byte aligned.
-Regions slot(void* ws, int Lmax, int L, int k)
+// Workspace slot k when the call's largest band-limit is Lws: three regions for
+// a map of band-limit L, W0 (N1 x L complex), W1 (max of N1 x L complex and the
+// H records), W2 (the inverse's coefficient stream), each 256-byte aligned.
+Regions slot(void* ws, int Lws, int L, int k)
 {
-    char* base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255) + (size_t)k * ws_need(Lmax);
+    char* base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255) + (size_t)k * ws_need(Lws);
     Regions r;
     r.W0 = (double2*)base;
     r.W1 = (double2*)(base + ws_region(L, 0));
@@ -179,180 +179,169 @@ Regions slot(void* ws, int Lmax, int L, int k)
     return r;
 }
 
-// FP64 launch sequence of one map.
-hipError_t run_map(Op op, const Plan& p, const SpinTable* sp, int s, int real, const void* in, void* out,
-                   const Regions& w, hipStream_t st)
-{
-    hipError_t e = hipSuccess;
-    const double phi_sc = TWO_PI / (double)p.N1;
-    double2* W0 = w.W0;
-    double2* W1 = w.W1;
-    double* W2 = w.W2;
-    switch (op) {
-    case Op::Forward:
-        e = staged(0, st, [&] { return mw::launch_phi_forward(p, in, real, W0, phi_sc, st); });
-        if (e == hipSuccess) e = staged(1, st, [&] { return mw::launch_theta_forward(p, s, W0, W1, 0, st); });
-        if (e == hipSuccess)
-            e = staged(2, st, [&] { return mw::launch_contract_forward(p, s, real, (const double*)W1, (double2*)out, st); });
-        break;
-    case Op::Inverse:
-        e = staged(8, st, [&] { return mw::launch_inverse_stream(p, s, real, (const double2*)in, W2, 0, st); });
-        if (e == hipSuccess) e = staged(3, st, [&] { return mw::launch_contract_inverse(p, *sp, s, W2, W0, st); });
-        if (e == hipSuccess) e = staged(4, st, [&] { return mw::launch_theta_inverse(p, s, W0, W1, st); });
-        if (e == hipSuccess) e = staged(5, st, [&] { return mw::launch_phi_inverse(p, W1, out, real, 1.0, st); });
-        break;
-    case Op::ForwardAdjoint:
-        // coefficients -> grid: the inverse's contraction is the conjugate transpose
-        // of the forward's contraction and fold; then the theta and phi adjoints.
-        // The coefficients are used as given (no real-map expansion): with real = 1
-        // the result is Re(A^H y), the adjoint of the forward restricted to real maps.
-        e = staged(8, st, [&] { return mw::launch_inverse_stream(p, s, 0, (const double2*)in, W2, 0, st); });
-        if (e == hipSuccess) e = staged(6, st, [&] { return mw::launch_contract_inverse(p, *sp, s, W2, W0, st); });
-        if (e == hipSuccess) e = staged(8, st, [&] { return mw::launch_theta_forward_adjoint(p, s, W0, W1, st); });
-        if (e == hipSuccess) e = staged(8, st, [&] { return mw::launch_phi_inverse(p, W1, out, real, phi_sc, st); });
-        break;
-    case Op::InverseAdjoint:
-        // grid -> coefficients: phi and theta adjoints, then the forward's
-        // contraction (the conjugate transpose of the inverse's).  With real = 1
-        // the real-map coefficient expansion is adjoined last.
-        e = staged(8, st, [&] { return mw::launch_phi_forward(p, in, real, W0, 1.0, st); });
-        if (e == hipSuccess) e = staged(8, st, [&] { return mw::launch_theta_inverse_adjoint(p, s, W0, W1, 0, st); });
-        if (e == hipSuccess)
-            e = staged(7, st, [&] { return mw::launch_contract_forward(p, s, 0, (const double*)W1, (double2*)out, st); });
-        if (e == hipSuccess && real) e = staged(8, st, [&] { return mw::launch_real_fold(p.L, (double2*)out, st); });
-        break;
-    }
-    return e;
-}
-
-// ---- mixed precision: groups of maps of one spin share the Wigner chains ---
-struct Group {
-    int s = 0, Lmax = 0, G = 1;
-    std::vector<int> maps;   // batch indices, band-limits descending
+// Maps of one call with equal band-limit, spin and reality run together: every
+// stage is one launch over the chunk (blockIdx.y = map), and in mixed precision
+// the chunk's maps share the Wigner chains in groups of G.
+struct Chunk {
+    int L = 0, s = 0, real = 0, G = 1;
+    std::vector<int> maps;   // batch indices
 };
 
-// Autotuned group size per (largest band-limit, spin, maps of that spin in the
-// call); filled by mw_prepare.
+// Autotuned group size per (band-limit, spin, maps in the chunk), from mw_prepare.
 std::map<std::tuple<int, int, int>, int> g_tuned;
 
 int pow2_ceil(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : 4; }
 
-int default_group(const Plan& p, int nmaps) { return std::min(pow2_ceil(nmaps), mw::mix_group_max(p)); }
-
-// Maps of each spin, sorted by band-limit (largest first) and cut into groups
-// of the tuned (else default) size.
-std::vector<Group> make_groups(DeviceState& d, const int32_t* L, const int32_t* spin, int batch, bool may_alloc,
-                               int& rc)
+// Chunk capacity: at most MAXB maps, MIXG groups in mixed precision, and 8 GiB
+// of workspace.
+int chunk_cap(int L, int precision, int G)
 {
-    std::map<int, std::vector<int>> by_spin;
-    for (int b = 0; b < batch; ++b) by_spin[spin[b]].push_back(b);
-    std::vector<Group> out;
+    int cap = mw::MAXB;
+    if (precision != MW_FP64) cap = std::min(cap, G * mw::MIXG);
+    const size_t lim = (size_t)8 << 30;
+    cap = std::min<size_t>(cap, std::max<size_t>(1, lim / ws_need(L)));
+    return std::max(cap, 1);
+}
+
+int group_size(DeviceState& d, int L, int s, int n, bool may_alloc, int& rc)
+{
+    const Plan* p = nullptr;
+    rc = get_plan(d, L, may_alloc, &p);
+    if (rc) return 1;
+    auto it = g_tuned.find(std::make_tuple(L, s, n));
+    if (it != g_tuned.end()) return it->second;
+    return std::min(pow2_ceil(n), mw::mix_group_max(*p));
+}
+
+std::vector<Chunk> make_chunks(DeviceState& d, const int32_t* L, const int32_t* spin, const int32_t* reality,
+                               int batch, int precision, bool may_alloc, int& rc)
+{
+    std::map<std::tuple<int, int, int>, std::vector<int>> cls;
+    for (int b = 0; b < batch; ++b) cls[std::make_tuple(-L[b], spin[b], reality[b])].push_back(b);
+    std::vector<Chunk> out;
     rc = MW_OK;
-    for (auto& kv : by_spin) {
-        auto& v = kv.second;
-        std::stable_sort(v.begin(), v.end(), [L](int a, int b) { return L[a] > L[b]; });
-        const int Lmax = L[v.front()];
-        const Plan* p = nullptr;
-        if ((rc = get_plan(d, Lmax, may_alloc, &p))) return out;
-        auto it = g_tuned.find(std::make_tuple(Lmax, kv.first, (int)v.size()));
-        const int gsz = (it != g_tuned.end()) ? it->second : default_group(*p, (int)v.size());
-        for (size_t i = 0; i < v.size(); i += gsz) {
-            Group g;
-            g.s = kv.first;
-            g.maps.assign(v.begin() + i, v.begin() + std::min(v.size(), i + (size_t)gsz));
-            g.Lmax = L[g.maps.front()];
-            g.G = pow2_ceil((int)g.maps.size());
-            out.push_back(g);
+    for (auto& kv : cls) {
+        const int Lc = -std::get<0>(kv.first), sc = std::get<1>(kv.first), rc_ = std::get<2>(kv.first);
+        const auto& v = kv.second;
+        const int G = (precision == MW_FP64) ? 1 : group_size(d, Lc, sc, (int)v.size(), may_alloc, rc);
+        if (rc) return out;
+        const int cap = chunk_cap(Lc, precision, G);
+        for (size_t i = 0; i < v.size(); i += cap) {
+            Chunk c;
+            c.L = Lc; c.s = sc; c.real = rc_; c.G = G;
+            c.maps.assign(v.begin() + i, v.begin() + std::min(v.size(), i + (size_t)cap));
+            out.push_back(c);
         }
     }
     return out;
 }
 
-// One group in mixed precision: per-map Fourier stages in FP64 around one
-// shared contraction launch.  Map k of the group uses workspace slot k.
-hipError_t run_group(Op op, DeviceState& d, const Group& g, const int32_t* L, const int32_t* reality,
-                     void* const* ptrs, void* ws, int Lws, hipStream_t st, int& rc)
+// Per-map descriptor of one stage: map k of the chunk reads in(k), writes out(k).
+template <class In, class Out>
+mw::Batch batch_of(const Chunk& c, In in, Out out)
 {
+    mw::Batch B{};
+    B.n = (int)c.maps.size();
+    for (int k = 0; k < B.n; ++k) {
+        B.in[k] = in(k);
+        B.out[k] = out(k);
+        B.s[k] = c.s;
+    }
+    return B;
+}
+
+// Mixed contraction descriptor: groups of c.G consecutive maps of the chunk.
+template <class Src, class Dst>
+mw::MixBatch mix_of(const Chunk& c, Src src, Dst dst)
+{
+    mw::MixBatch M{};
+    const int n = (int)c.maps.size();
+    M.ng = (n + c.G - 1) / c.G;
+    for (int g = 0; g < M.ng; ++g) {
+        mw::MixMaps& mm = M.g[g];
+        mm.n = std::min(c.G, n - g * c.G);
+        for (int k = 0; k < mm.n; ++k) {
+            const int i = g * c.G + k;
+            mm.src[k] = (const float*)src(i);
+            mm.dst[k] = (double2*)dst(i);
+            mm.L[k] = c.L;
+        }
+    }
+    return M;
+}
+
+// Launch sequence of one chunk.  Map k of the chunk uses workspace slot k.
+hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, int precision, void* const* ptrs,
+                     void* ws, int Lws, hipStream_t st)
+{
+    const bool mix = precision != MW_FP64;
+    const int s = c.s, real = c.real;
+    const double phi_sc = TWO_PI / (double)p.N1;
+    auto user_in = [&](int k) { return (void*)ptrs[2 * c.maps[k]]; };
+    auto user_out = [&](int k) { return (void*)ptrs[2 * c.maps[k] + 1]; };
+    auto w0 = [&](int k) { return (void*)slot(ws, Lws, c.L, k).W0; };
+    auto w1 = [&](int k) { return (void*)slot(ws, Lws, c.L, k).W1; };
+    auto w2 = [&](int k) { return (void*)slot(ws, Lws, c.L, k).W2; };
     hipError_t e = hipSuccess;
-    const Plan* pg = nullptr;
-    const SpinTable* spg = nullptr;
-    const int as = g.s < 0 ? -g.s : g.s;
-    if ((rc = get_plan(d, g.Lmax, false, &pg))) return hipSuccess;
-    const bool inv = (op == Op::Inverse || op == Op::ForwardAdjoint);
-    if (inv && (rc = get_spin(d, g.Lmax, as, false, &spg))) return hipSuccess;
-    mw::MixMaps mm{};
-    mm.n = (int)g.maps.size();
-    std::vector<const Plan*> pl(mm.n);
-    for (int k = 0; k < mm.n; ++k) {
-        const int b = g.maps[k];
-        if ((rc = get_plan(d, L[b], false, &pl[k]))) return hipSuccess;
-        const Regions w = slot(ws, Lws, L[b], k);
-        mm.L[k] = L[b];
-        if (op == Op::Forward || op == Op::InverseAdjoint) {
-            mm.src[k] = (const float*)w.W1;
-            mm.dst[k] = (double2*)ptrs[2 * b + 1];
+    auto go = [&](int stage, auto launch) {
+        if (e == hipSuccess) e = staged(stage, st, launch);
+    };
+    switch (op) {
+    case Op::Forward: {
+        const mw::Batch B1 = batch_of(c, user_in, w0), B2 = batch_of(c, w0, w1), B3 = batch_of(c, w1, user_out);
+        go(0, [&] { return mw::launch_phi_forward(p, B1, real, phi_sc, st); });
+        go(1, [&] { return mw::launch_theta_forward(p, B2, mix, st); });
+        if (mix) {
+            const mw::MixBatch M = mix_of(c, w1, user_out);
+            go(2, [&] { return mw::launch_contract_forward_mix(p, s, M, c.G, st); });
         } else {
-            mm.src[k] = (const float*)w.W2;
-            mm.dst[k] = w.W0;
+            go(2, [&] { return mw::launch_contract_forward(p, s, (const double*)w1(0), ws_need(Lws) / 8, B3, st); });
         }
+        break;
     }
-    // Fourier stages before the contraction
-    for (int k = 0; k < mm.n && e == hipSuccess; ++k) {
-        const int b = g.maps[k];
-        const Plan& p = *pl[k];
-        const Regions w = slot(ws, Lws, L[b], k);
-        const int real = reality[b];
-        const void* in = ptrs[2 * b];
-        switch (op) {
-        case Op::Forward:
-            e = staged(0, st, [&] { return mw::launch_phi_forward(p, in, real, w.W0, TWO_PI / (double)p.N1, st); });
-            if (e == hipSuccess) e = staged(1, st, [&] { return mw::launch_theta_forward(p, g.s, w.W0, w.W1, 1, st); });
-            break;
-        case Op::InverseAdjoint:
-            e = staged(8, st, [&] { return mw::launch_phi_forward(p, in, real, w.W0, 1.0, st); });
-            if (e == hipSuccess)
-                e = staged(8, st, [&] { return mw::launch_theta_inverse_adjoint(p, g.s, w.W0, w.W1, 1, st); });
-            break;
-        case Op::Inverse:
-            e = staged(8, st, [&] { return mw::launch_inverse_stream(p, g.s, real, (const double2*)in, w.W2, 1, st); });
-            break;
-        case Op::ForwardAdjoint:
-            e = staged(8, st, [&] { return mw::launch_inverse_stream(p, g.s, 0, (const double2*)in, w.W2, 1, st); });
-            break;
+    case Op::Inverse:
+    case Op::ForwardAdjoint: {
+        // The adjoint of the forward starts with the inverse's contraction (the
+        // conjugate transpose of the forward's contraction and fold) on the
+        // coefficients as given (no real-map expansion), then the theta and phi
+        // adjoints; with real = 1 it stores Re(A^H y).
+        const bool inv = op == Op::Inverse;
+        const mw::Batch B1 = batch_of(c, user_in, w2), B2 = batch_of(c, w2, w0), B3 = batch_of(c, w0, w1),
+                        B4 = batch_of(c, w1, user_out);
+        go(8, [&] { return mw::launch_inverse_stream(p, s, inv ? real : 0, B1, mix, st); });
+        if (mix) {
+            const mw::MixBatch M = mix_of(c, w2, w0);
+            go(inv ? 3 : 6, [&] { return mw::launch_contract_inverse_mix(p, *sp, s, M, c.G, st); });
+        } else {
+            go(inv ? 3 : 6, [&] {
+                return mw::launch_contract_inverse(p, *sp, s, (const double*)w2(0), ws_need(Lws) / 8, B2, st);
+            });
         }
+        if (inv) {
+            go(4, [&] { return mw::launch_theta_inverse(p, B3, st); });
+            go(5, [&] { return mw::launch_phi_inverse(p, B4, real, 1.0, st); });
+        } else {
+            go(8, [&] { return mw::launch_theta_forward_adjoint(p, B3, st); });
+            go(8, [&] { return mw::launch_phi_inverse(p, B4, real, phi_sc, st); });
+        }
+        break;
     }
-    if (e != hipSuccess) return e;
-    // the shared contraction
-    if (op == Op::Forward || op == Op::InverseAdjoint)
-        e = staged(op == Op::Forward ? 2 : 7, st, [&] { return mw::launch_contract_forward_mix(*pg, g.s, mm, g.G, st); });
-    else
-        e = staged(op == Op::Inverse ? 3 : 6, st,
-                   [&] { return mw::launch_contract_inverse_mix(*pg, *spg, g.s, mm, g.G, st); });
-    // Fourier stages after the contraction
-    for (int k = 0; k < mm.n && e == hipSuccess; ++k) {
-        const int b = g.maps[k];
-        const Plan& p = *pl[k];
-        const Regions w = slot(ws, Lws, L[b], k);
-        const int real = reality[b];
-        void* out = ptrs[2 * b + 1];
-        switch (op) {
-        case Op::Forward:
-            break;
-        case Op::InverseAdjoint:
-            if (real) e = staged(8, st, [&] { return mw::launch_real_fold(p.L, (double2*)out, st); });
-            break;
-        case Op::Inverse:
-            e = staged(4, st, [&] { return mw::launch_theta_inverse(p, g.s, w.W0, w.W1, st); });
-            if (e == hipSuccess) e = staged(5, st, [&] { return mw::launch_phi_inverse(p, w.W1, out, real, 1.0, st); });
-            break;
-        case Op::ForwardAdjoint:
-            e = staged(8, st, [&] { return mw::launch_theta_forward_adjoint(p, g.s, w.W0, w.W1, st); });
-            if (e == hipSuccess)
-                e = staged(8, st, [&] {
-                    return mw::launch_phi_inverse(p, w.W1, out, real, TWO_PI / (double)p.N1, st);
-                });
-            break;
+    case Op::InverseAdjoint: {
+        // grid -> coefficients: phi and theta adjoints, then the forward's
+        // contraction (the conjugate transpose of the inverse's); with real = 1
+        // the real-map coefficient expansion is adjoined last.
+        const mw::Batch B1 = batch_of(c, user_in, w0), B2 = batch_of(c, w0, w1), B3 = batch_of(c, w1, user_out);
+        go(8, [&] { return mw::launch_phi_forward(p, B1, real, 1.0, st); });
+        go(8, [&] { return mw::launch_theta_inverse_adjoint(p, B2, mix, st); });
+        if (mix) {
+            const mw::MixBatch M = mix_of(c, w1, user_out);
+            go(7, [&] { return mw::launch_contract_forward_mix(p, s, M, c.G, st); });
+        } else {
+            go(7, [&] { return mw::launch_contract_forward(p, s, (const double*)w1(0), ws_need(Lws) / 8, B3, st); });
         }
+        if (real) go(8, [&] { return mw::launch_real_fold(p.L, B3, st); });
+        break;
+    }
     }
     return e;
 }
@@ -364,16 +353,11 @@ int batch_lmax(const int32_t* L, int batch)
     return m;
 }
 
-// Workspace slots a call needs: one for FP64 (maps run in turn), one per map of
-// the largest group in mixed precision.
-int ws_slots(DeviceState& d, const int32_t* L, const int32_t* spin, int batch, int precision, bool may_alloc,
-             int& rc)
+size_t chunks_ws(const std::vector<Chunk>& ch, int Lws)
 {
-    rc = MW_OK;
-    if (precision == MW_FP64) return 1;
-    int slots = 1;
-    for (const Group& g : make_groups(d, L, spin, batch, may_alloc, rc)) slots = std::max(slots, (int)g.maps.size());
-    return slots;
+    size_t slots = 1;
+    for (const Chunk& c : ch) slots = std::max(slots, c.maps.size());
+    return slots * ws_need(Lws) + 256;
 }
 
 int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
@@ -388,98 +372,76 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     const bool need_spin = (op == Op::Inverse || op == Op::ForwardAdjoint);
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceState& d = g_dev[dev];
-    const int Lws = batch_lmax(L, batch);
-    const int slots = ws_slots(d, L, spin, batch, precision, may_alloc, rc);
+    const std::vector<Chunk> chunks = make_chunks(d, L, spin, reality, batch, precision, may_alloc, rc);
     if (rc) return rc;
+    const int Lws = batch_lmax(L, batch);
     void* ws = nullptr;
-    if ((rc = get_ws(d, (size_t)slots * ws_need(Lws) + 256, may_alloc, &ws))) return rc;
-    for (int b = 0; b < batch; ++b) {   // every plan and spin table the call touches
+    if ((rc = get_ws(d, chunks_ws(chunks, Lws), may_alloc, &ws))) return rc;
+    for (const Chunk& c : chunks) {
         const Plan* p = nullptr;
         const SpinTable* sp = nullptr;
-        if ((rc = get_plan(d, L[b], may_alloc, &p))) return rc;
-        if (need_spin && (rc = get_spin(d, L[b], spin[b] < 0 ? -spin[b] : spin[b], may_alloc, &sp))) return rc;
-    }
-    if (precision == MW_FP64) {
-        for (int b = 0; b < batch; ++b) {
-            const Plan* p = nullptr;
-            const SpinTable* sp = nullptr;
-            const int s = spin[b], as = s < 0 ? -s : s;
-            get_plan(d, L[b], false, &p);
-            if (need_spin) get_spin(d, L[b], as, false, &sp);
-            hipError_t e = run_map(op, *p, sp, s, reality[b], ptrs[2 * b], ptrs[2 * b + 1], slot(ws, Lws, L[b], 0), st);
-            if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
-        }
-    } else {
-        const std::vector<Group> groups = make_groups(d, L, spin, batch, may_alloc, rc);
-        if (rc) return rc;
-        for (const Group& g : groups) {
-            if (need_spin) {
-                const SpinTable* sp = nullptr;
-                if ((rc = get_spin(d, g.Lmax, g.s < 0 ? -g.s : g.s, may_alloc, &sp))) return rc;
-            }
-            hipError_t e = run_group(op, d, g, L, reality, ptrs, ws, Lws, st, rc);
-            if (rc) return rc;
-            if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
-        }
+        if ((rc = get_plan(d, c.L, may_alloc, &p))) return rc;
+        if (need_spin && (rc = get_spin(d, c.L, c.s < 0 ? -c.s : c.s, may_alloc, &sp))) return rc;
+        hipError_t e = run_chunk(op, c, *p, sp, precision, ptrs, ws, Lws, st);
+        if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     }
     g_last_error.clear();
     return MW_OK;
 }
 
-// Times the mixed forward contraction of one group per candidate size on the
-// workspace (whatever it holds) and keeps the fastest per map.
-int autotune(DeviceState& d, const int32_t* L, const int32_t* spin, int batch, hipStream_t st)
+// Times the mixed forward contraction of one chunk per candidate group size on
+// zeroed workspace and keeps the fastest; results do not depend on the choice
+// (each map keeps its own accumulators over the shared chains).
+int autotune(DeviceState& d, const int32_t* L, const int32_t* spin, const int32_t* reality, int batch)
 {
-    std::map<int, std::vector<int>> by_spin;
-    for (int b = 0; b < batch; ++b) by_spin[spin[b]].push_back(b);
+    std::map<std::tuple<int, int, int>, int> cnt;   // maps per (L, s, reality)
+    for (int b = 0; b < batch; ++b) ++cnt[std::make_tuple(L[b], spin[b], reality[b])];
     const int Lws = batch_lmax(L, batch);
-    for (auto& kv : by_spin) {
-        auto& v = kv.second;
-        int Lmax = 0;
-        for (int b : v) Lmax = std::max(Lmax, (int)L[b]);
-        const auto key = std::make_tuple(Lmax, kv.first, (int)v.size());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(MW_EHIP, "hipEventCreate failed");
+    int rc = MW_OK;
+    for (auto& kv : cnt) {
+        const int Lc = std::get<0>(kv.first), sc = std::get<1>(kv.first), n = kv.second;
+        const auto key = std::make_tuple(Lc, sc, n);
         if (g_tuned.count(key)) continue;
         const Plan* p = nullptr;
-        int rc = get_plan(d, Lmax, true, &p);
-        if (rc) return rc;
+        if ((rc = get_plan(d, Lc, true, &p))) break;
+        const int gmax = std::min(pow2_ceil(n), mw::mix_group_max(*p));
+        const int nt = std::min(n, chunk_cap(Lc, MW_FP32C, gmax));
         void* ws = nullptr;
-        const int gmax = std::min(pow2_ceil((int)v.size()), mw::mix_group_max(*p));
-        if ((rc = get_ws(d, (size_t)std::max(gmax, 1) * ws_need(Lws) + 256, true, &ws))) return rc;
-        hipEvent_t e0, e1;
-        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-            return fail(MW_EHIP, "hipEventCreate failed");
+        if ((rc = get_ws(d, (size_t)nt * ws_need(Lws) + 256, true, &ws))) break;
+        for (int k = 0; k < nt; ++k) (void)hipMemset(slot(ws, Lws, Lc, k).W1, 0, ws_region(Lc, 1));
         int best = 1;
         double best_t = 1e30;
         for (int G = 1; G <= gmax; G <<= 1) {
-            mw::MixMaps mm{};
-            mm.n = G;
-            for (int k = 0; k < G; ++k) {
-                const Regions w = slot(ws, Lws, Lmax, k);
-                // zero staging input: the timing does not depend on the values
-                (void)hipMemsetAsync(w.W1, 0, ws_region(Lmax, 1), st);
-                mm.src[k] = (const float*)w.W1;
-                mm.dst[k] = w.W0;   // f_lm (L^2 entries) fits in W0
-                mm.L[k] = Lmax;
-            }
+            Chunk c;
+            c.L = Lc; c.s = sc; c.G = G;
+            const int nc = std::min(nt, G * mw::MIXG);
+            for (int k = 0; k < nc; ++k) c.maps.push_back(k);
+            const mw::MixBatch M = mix_of(c, [&](int k) { return (void*)slot(ws, Lws, Lc, k).W1; },
+                                          [&](int k) { return (void*)slot(ws, Lws, Lc, k).W0; });
             double t = 0;
             for (int rep = 0; rep < 3; ++rep) {
-                (void)hipEventRecord(e0, st);
-                hipError_t e = mw::launch_contract_forward_mix(*p, kv.first, mm, G, st);
-                (void)hipEventRecord(e1, st);
-                if (e != hipSuccess) { hipEventDestroy(e0); hipEventDestroy(e1); return fail(MW_EHIP, "autotune launch failed"); }
+                (void)hipEventRecord(e0, nullptr);
+                hipError_t e = mw::launch_contract_forward_mix(*p, sc, M, G, nullptr);
+                (void)hipEventRecord(e1, nullptr);
+                if (e != hipSuccess) { rc = fail(MW_EHIP, "autotune launch failed"); break; }
                 (void)hipEventSynchronize(e1);
                 float ms = 0;
                 (void)hipEventElapsedTime(&ms, e0, e1);
                 if (rep > 0) t += ms;
             }
-            const double per_map = t / G;
+            if (rc) break;
+            const double per_map = t / nc;
             if (per_map < best_t * 0.97) { best_t = per_map; best = G; }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        if (rc) break;
         g_tuned[key] = best;
     }
-    return MW_OK;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 }  // namespace
@@ -516,12 +478,16 @@ int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* real
     int rc = validate(L, spin, reality, batch, nullptr, precision, false);
     if (rc) return rc;
     if (!bytes) return fail(MW_EINVAL, "bytes must be non-NULL");
-    int slots = 1;
-    if (precision != MW_FP64) {   // one slot per map of the largest group, at most GMAX
-        std::map<int, int> cnt;
-        for (int b = 0; b < batch; ++b) slots = std::max(slots, std::min(++cnt[spin[b]], mw::GMAX));
+    // the largest chunk of maps with equal (L, spin, reality), capped like the calls cap it
+    std::map<std::tuple<int, int, int>, int> cnt;
+    for (int b = 0; b < batch; ++b) ++cnt[std::make_tuple(L[b], spin[b], reality[b])];
+    size_t slots = 1;
+    for (auto& kv : cnt) {
+        const int Lc = std::get<0>(kv.first);
+        const int G = (precision == MW_FP64) ? 1 : std::min(pow2_ceil(kv.second), mw::GMAX);
+        slots = std::max(slots, (size_t)std::min(kv.second, chunk_cap(Lc, precision, G)));
     }
-    *bytes = (size_t)slots * ws_need(batch_lmax(L, batch)) + 256;
+    *bytes = slots * ws_need(batch_lmax(L, batch)) + 256;
     return MW_OK;
 }
 
@@ -533,12 +499,6 @@ int mw_prepare(const int32_t* L, const int32_t* spin, const int32_t* reality, in
     if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceState& d = g_dev[dev];
-    if (precision != MW_FP64 && (rc = autotune(d, L, spin, batch, nullptr))) return rc;
-    const int Lws = batch_lmax(L, batch);
-    const int slots = ws_slots(d, L, spin, batch, precision, true, rc);
-    if (rc) return rc;
-    void* ws = nullptr;
-    if ((rc = get_ws(d, (size_t)slots * ws_need(Lws) + 256, true, &ws))) return rc;
     for (int b = 0; b < batch; ++b) {
         const Plan* p;
         const SpinTable* sp;
@@ -546,13 +506,11 @@ int mw_prepare(const int32_t* L, const int32_t* spin, const int32_t* reality, in
         if ((rc = get_plan(d, L[b], true, &p))) return rc;
         if ((rc = get_spin(d, L[b], as, true, &sp))) return rc;
     }
-    if (precision != MW_FP64) {   // the groups' spin tables at their largest band-limit
-        for (const Group& g : make_groups(d, L, spin, batch, true, rc)) {
-            const SpinTable* sp;
-            if ((rc = get_spin(d, g.Lmax, g.s < 0 ? -g.s : g.s, true, &sp))) return rc;
-        }
-        if (rc) return rc;
-    }
+    if (precision != MW_FP64 && (rc = autotune(d, L, spin, reality, batch))) return rc;
+    const std::vector<Chunk> chunks = make_chunks(d, L, spin, reality, batch, precision, true, rc);
+    if (rc) return rc;
+    void* ws = nullptr;
+    if ((rc = get_ws(d, chunks_ws(chunks, batch_lmax(L, batch)), true, &ws))) return rc;
     if (hipDeviceSynchronize() != hipSuccess) return fail(MW_EHIP, "hipDeviceSynchronize failed");
     return MW_OK;
 }

@@ -350,13 +350,15 @@ __device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscale
 // are added in LDS in segment order.
 template <int MT, bool EXT>
 __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
-    const double* __restrict__ Hp, double2* __restrict__ flm, const double* __restrict__ Rtg,
+    const double* __restrict__ Hp0, size_t hstride, Batch B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,
     const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int2* __restrict__ work, int L, int Lp,
     int s, int segf)
 {
     __shared__ double2 red[SEG_MAX - 1][MT][4][64];
     extern __shared__ double Rt[];   // copy of the 1/sqrt table (2L+8 entries)
+    const double* __restrict__ Hp = Hp0 + blockIdx.y * hstride;   // map blockIdx.y of the launch
+    double2* __restrict__ flm = (double2*)B.out[blockIdx.y];
     const int grp = blockIdx.x;
     const int w = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -443,10 +445,11 @@ constexpr int STR_L = 32, STR_M = 8;
 // OUT32 = 1 writes the record as FP32 at [(m*4 + comp)*Lp + l] instead (the
 // layout the mixed-precision inverse stages per order).
 template <int OUT32>
-__global__ __launch_bounds__(256) void k_inverse_stream(const double2* __restrict__ flm, void* __restrict__ fs,
-                                                        const double* __restrict__ cl, int L, int Lp, int s,
+__global__ __launch_bounds__(256) void k_inverse_stream(Batch B, const double* __restrict__ cl, int L, int Lp, int s,
                                                         int real)
 {
+    const double2* __restrict__ flm = (const double2*)B.in[blockIdx.z];
+    void* __restrict__ fs = B.out[blockIdx.z];
     __shared__ double2 ta[STR_L][STR_M + 1], tb[STR_L][STR_M + 1];
     const int l0 = blockIdx.x * STR_L, m0 = blockIdx.y * STR_M;
     {
@@ -488,8 +491,9 @@ __global__ __launch_bounds__(256) void k_inverse_stream(const double2* __restric
 // Adjoint of the real-map coefficient expansion f_{l,-m} = (-1)^m conj(f_{l,m})
 // (Sec. IV-G): y_{l,m} += (-1)^m conj(y_{l,-m}) and y_{l,-m} = 0 for m > 0.
 // One thread per (l, m > 0).
-__global__ __launch_bounds__(256) void k_real_fold(double2* __restrict__ y, int L)
+__global__ __launch_bounds__(256) void k_real_fold(Batch B, int L)
 {
+    double2* __restrict__ y = (double2*)B.out[blockIdx.z];
     const int l = blockIdx.y;
     const int m = blockIdx.x * blockDim.x + threadIdx.x + 1;
     if (l >= L || m > l) return;
@@ -772,7 +776,7 @@ __device__ __forceinline__ InvSeg inv_setup(InvLane<EXT>& st, bool& anyscaled, c
 // order m).  Partial sums are added in LDS in segment order.
 template <bool EXT>
 __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
-    const double* __restrict__ fs, double2* __restrict__ F, const double* __restrict__ Rtg,
+    const double* __restrict__ fs0, size_t fstride, Batch B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
     const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,
     const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work, int L, int Lp, int s, int segi,
@@ -780,6 +784,8 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
 {
     __shared__ double2 red[SEG_MAX - 1][2][64];
     extern __shared__ double Rt[];   // copy of the 1/sqrt table (2L+8 entries)
+    const double* __restrict__ fs = fs0 + blockIdx.y * fstride;   // map blockIdx.y of the launch
+    double2* __restrict__ F = (double2*)B.out[blockIdx.y];
     const int grp = blockIdx.x;
     const int w = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -899,11 +905,12 @@ __device__ __forceinline__ void fwd_mix_segment(FwdLane<2, EXT>& st, v4f (&acc)[
 // (-1)^n for s < 0 (else 1); maps.dst[b]: f_lm of map b.
 template <bool EXT, int G>
 __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
-    MixMaps maps, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
+    MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
     const double* __restrict__ cl, const double2* __restrict__ ckf, const int2* __restrict__ ckfk,
     const int2* __restrict__ work, int L, int s, int segf)
 {
     extern __shared__ double smem[];
+    const MixMaps& maps = MB.g[blockIdx.y];
     const int grp = blockIdx.x;
     const int w = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -1060,12 +1067,13 @@ __device__ __forceinline__ void inv_mix_segment(InvLane<EXT>& st, v4f (&acc)[G],
 // maps.dst[b]: F of map b at [(L_b - 1 + m)*L_b + n].
 template <bool EXT, int G>
 __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse_mix(
-    MixMaps maps, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
+    MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
     const double2* __restrict__ lco, const double* __restrict__ stab, const int* __restrict__ stabk,
     const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work,
     int L, int Lp, int s, int segi, int nsegi)
 {
     extern __shared__ double smem[];
+    const MixMaps& maps = MB.g[blockIdx.y];
     const int grp = blockIdx.x;
     const int w = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -1154,49 +1162,47 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse_mix(
 
 }  // namespace
 
-hipError_t launch_contract_forward(const Plan& p, int s, int real, const double* Hp, double2* flm,
+hipError_t launch_contract_forward(const Plan& p, int s, const double* in0, size_t stride, const Batch& B,
                                    hipStream_t st)
 {
-    (void)real;
-    const dim3 grid(p.nworkf), block(64 * SEG_MAX);
+    const dim3 grid(p.nworkf, B.n), block(64 * SEG_MAX);
     const size_t lds = (size_t)(2 * p.L + 8) * sizeof(double);
     if (p.ext)
-        hipLaunchKernelGGL((k_contract_forward<MT_FWD, true>), grid, block, lds, st, Hp, flm, p.rtab, p.edge, p.edgek,
-                           p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
+        hipLaunchKernelGGL((k_contract_forward<MT_FWD, true>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek, p.cl,
+                           p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
     else
-        hipLaunchKernelGGL((k_contract_forward<MT_FWD, false>), grid, block, lds, st, Hp, flm, p.rtab, p.edge,
-                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
+        hipLaunchKernelGGL((k_contract_forward<MT_FWD, false>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek,
+                           p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
     return hipGetLastError();
 }
 
-hipError_t launch_real_fold(int L, double2* y, hipStream_t st)
+hipError_t launch_real_fold(int L, const Batch& B, hipStream_t st)
 {
-    const dim3 grid((L + 255) / 256, L);
-    hipLaunchKernelGGL(k_real_fold, grid, dim3(256), 0, st, y, L);
+    const dim3 grid((L + 255) / 256, L, B.n);
+    hipLaunchKernelGGL(k_real_fold, grid, dim3(256), 0, st, B, L);
     return hipGetLastError();
 }
 
-hipError_t launch_inverse_stream(const Plan& p, int s, int real, const double2* flm, void* fs, int out32,
-                                 hipStream_t st)
+hipError_t launch_inverse_stream(const Plan& p, int s, int real, const Batch& B, int out32, hipStream_t st)
 {
-    const dim3 grid((p.Lp + STR_L - 1) / STR_L, (p.L + STR_M - 1) / STR_M);
-    if (out32) hipLaunchKernelGGL(k_inverse_stream<1>, grid, dim3(256), 0, st, flm, fs, p.cl, p.L, p.Lp, s, real);
-    else hipLaunchKernelGGL(k_inverse_stream<0>, grid, dim3(256), 0, st, flm, fs, p.cl, p.L, p.Lp, s, real);
+    const dim3 grid((p.Lp + STR_L - 1) / STR_L, (p.L + STR_M - 1) / STR_M, B.n);
+    if (out32) hipLaunchKernelGGL(k_inverse_stream<1>, grid, dim3(256), 0, st, B, p.cl, p.L, p.Lp, s, real);
+    else hipLaunchKernelGGL(k_inverse_stream<0>, grid, dim3(256), 0, st, B, p.cl, p.L, p.Lp, s, real);
     return hipGetLastError();
 }
 
-hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, const double* fs, double2* F,
-                                   hipStream_t st)
+hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, const double* in0, size_t stride,
+                                   const Batch& B, hipStream_t st)
 {
     CkOff off;
     for (int j = 0; j < SEG_MAX; ++j) off.off[j] = p.cki_off[j];
-    const dim3 grid(p.nworki), block(64 * SEG_MAX);
+    const dim3 grid(p.nworki, B.n), block(64 * SEG_MAX);
     const size_t lds = (size_t)(2 * p.L + 8) * sizeof(double);
     if (p.ext)
-        hipLaunchKernelGGL((k_contract_inverse<true>), grid, block, lds, st, fs, F, p.rtab, p.edge, p.edgek, p.lco,
+        hipLaunchKernelGGL((k_contract_inverse<true>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek, p.lco,
                            sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
     else
-        hipLaunchKernelGGL((k_contract_inverse<false>), grid, block, lds, st, fs, F, p.rtab, p.edge, p.edgek, p.lco,
+        hipLaunchKernelGGL((k_contract_inverse<false>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek, p.lco,
                            sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
     return hipGetLastError();
 }
@@ -1226,25 +1232,27 @@ hipError_t mix_attr(K kernel, size_t bytes)
 }
 
 template <bool EXT, int G>
-hipError_t fwd_mix_go(const Plan& p, int s, const MixMaps& maps, hipStream_t st)
+hipError_t fwd_mix_go(const Plan& p, int s, const MixBatch& maps, hipStream_t st)
 {
     const size_t lds = mix_lds_forward(p, G);
     hipError_t e = mix_attr(k_contract_forward_mix<EXT, G>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_contract_forward_mix<EXT, G>), dim3(p.nworkf), dim3(64 * SEG_MAX), lds, st, maps, p.rtab,
+    hipLaunchKernelGGL((k_contract_forward_mix<EXT, G>), dim3(p.nworkf, maps.ng), dim3(64 * SEG_MAX), lds, st, maps,
+                       p.rtab,
                        p.edge, p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, s, p.segf);
     return hipGetLastError();
 }
 
 template <bool EXT, int G>
-hipError_t inv_mix_go(const Plan& p, const SpinTable& sp, int s, const MixMaps& maps, hipStream_t st)
+hipError_t inv_mix_go(const Plan& p, const SpinTable& sp, int s, const MixBatch& maps, hipStream_t st)
 {
     CkOff off;
     for (int j = 0; j < SEG_MAX; ++j) off.off[j] = p.cki_off[j];
     const size_t lds = mix_lds_inverse(p, G);
     hipError_t e = mix_attr(k_contract_inverse_mix<EXT, G>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_contract_inverse_mix<EXT, G>), dim3(p.nworki), dim3(64 * SEG_MAX), lds, st, maps, p.rtab,
+    hipLaunchKernelGGL((k_contract_inverse_mix<EXT, G>), dim3(p.nworki, maps.ng), dim3(64 * SEG_MAX), lds, st, maps,
+                       p.rtab,
                        p.edge, p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi,
                        p.nsegi);
     return hipGetLastError();
@@ -1259,9 +1267,17 @@ int mix_group_max(const Plan& p)
     return 1;
 }
 
-hipError_t launch_contract_forward_mix(const Plan& p, int s, const MixMaps& maps, int G, hipStream_t st)
+bool mix_ok(const MixBatch& maps, int G)
 {
-    if (maps.n < 1 || maps.n > G || G > GMAX) return hipErrorInvalidValue;
+    if (maps.ng < 1 || maps.ng > MIXG || G > GMAX) return false;
+    for (int g = 0; g < maps.ng; ++g)
+        if (maps.g[g].n < 1 || maps.g[g].n > G) return false;
+    return true;
+}
+
+hipError_t launch_contract_forward_mix(const Plan& p, int s, const MixBatch& maps, int G, hipStream_t st)
+{
+    if (!mix_ok(maps, G)) return hipErrorInvalidValue;
     if (p.ext) {
         if (G == 1) return fwd_mix_go<true, 1>(p, s, maps, st);
         if (G == 2) return fwd_mix_go<true, 2>(p, s, maps, st);
@@ -1272,10 +1288,10 @@ hipError_t launch_contract_forward_mix(const Plan& p, int s, const MixMaps& maps
     return fwd_mix_go<false, 4>(p, s, maps, st);
 }
 
-hipError_t launch_contract_inverse_mix(const Plan& p, const SpinTable& sp, int s, const MixMaps& maps, int G,
+hipError_t launch_contract_inverse_mix(const Plan& p, const SpinTable& sp, int s, const MixBatch& maps, int G,
                                        hipStream_t st)
 {
-    if (maps.n < 1 || maps.n > G || G > GMAX) return hipErrorInvalidValue;
+    if (!mix_ok(maps, G)) return hipErrorInvalidValue;
     if (p.ext) {
         if (G == 1) return inv_mix_go<true, 1>(p, sp, s, maps, st);
         if (G == 2) return inv_mix_go<true, 2>(p, sp, s, maps, st);

@@ -236,10 +236,11 @@ __device__ __forceinline__ int xcd_column(int ncol)
 // sc = 2pi/N1 for the forward transform and sc = 1 for the adjoint of the inverse.
 // Output G[t][m + L-1].
 template <int REAL>
-__global__ __launch_bounds__(512) void k_phi_forward(Plan p, const void* __restrict__ map, double2* __restrict__ G,
-                                                     double sc)
+__global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
 {
     extern __shared__ double2 A[];
+    const void* __restrict__ map = B.in[blockIdx.y];
+    double2* __restrict__ G = (double2*)B.out[blockIdx.y];
     const int t = blockIdx.x, L = p.L, N1 = p.N1;
     for (int j = threadIdx.x; j < p.N2; j += blockDim.x) {
         double2 v = make_double2(0.0, 0.0);
@@ -273,10 +274,12 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, const void* __restr
 // parity split of the contraction folded in: sigma_+ = (-1)^n for s >= 0 and
 // sigma_- = (-1)^n for s < 0 (1 otherwise).
 template <int ADJ_INV, int OUT32>
-__global__ __launch_bounds__(512) void k_theta_forward(Plan p, int s, const double2* __restrict__ G,
-                                                       void* __restrict__ Hout)
+__global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
 {
     extern __shared__ double2 A[];
+    const int s = B.s[blockIdx.y];
+    const double2* __restrict__ G = (const double2*)B.in[blockIdx.y];
+    void* __restrict__ Hout = B.out[blockIdx.y];
     const int L = p.L, N1 = p.N1, N2 = p.N2;
     const int mi = xcd_column(N1);
     if (mi >= N1) return;
@@ -363,10 +366,12 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, int s, const doub
 //   fold     G_m(theta_t) = Gext(theta_t) + (-1)^{m+s} Gext(theta_{2L-2-t}), t < L-1;
 //            G_m(theta_{L-1}) = Gext(theta_{L-1})
 // Output G[t][m + L-1] (the layout the inverse phi stage reads).
-__global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, int s, const double2* __restrict__ Y,
-                                                               double2* __restrict__ Gt)
+__global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
 {
     extern __shared__ double2 A[];
+    const int s = B.s[blockIdx.y];
+    const double2* __restrict__ Y = (const double2*)B.in[blockIdx.y];
+    double2* __restrict__ Gt = (double2*)B.out[blockIdx.y];
     const int L = p.L, N1 = p.N1, N2 = p.N2;
     const int mi = xcd_column(N1);
     if (mi >= N1) return;
@@ -416,9 +421,12 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, int s, co
 //   F_m(theta_t) = sum_{m'} F_{m m'} e^{i m' theta_t}, t < L only,
 // from the folded F[m + L-1][n] (n >= 0) with F_{m,-n} = (-1)^{m+s} F_{m,n}.
 // Output Ft[t][m + L-1].
-__global__ __launch_bounds__(512) void k_theta_inverse(Plan p, int s, const double2* __restrict__ F, double2* __restrict__ Ft)
+__global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
 {
     extern __shared__ double2 A[];
+    const int s = B.s[blockIdx.y];
+    const double2* __restrict__ F = (const double2*)B.in[blockIdx.y];
+    double2* __restrict__ Ft = (double2*)B.out[blockIdx.y];
     const int L = p.L, N1 = p.N1, N2 = p.N2;
     const int mi = xcd_column(N1);
     if (mi >= N1) return;
@@ -446,10 +454,11 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, int s, const doub
 // sc = 1 for the inverse transform and sc = 2pi/N1 for the adjoint of the forward
 // (whose phi step is the conjugate transpose of the forward's).  REAL stores Re f.
 template <int REAL>
-__global__ __launch_bounds__(512) void k_phi_inverse(Plan p, const double2* __restrict__ Ft, void* __restrict__ map,
-                                                     double sc)
+__global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
 {
     extern __shared__ double2 A[];
+    const double2* __restrict__ Ft = (const double2*)B.in[blockIdx.y];
+    void* __restrict__ map = B.out[blockIdx.y];
     const int t = blockIdx.x, L = p.L, N1 = p.N1;
     for (int j = threadIdx.x; j < p.N2; j += blockDim.x) {
         double2 v = make_double2(0.0, 0.0);
@@ -486,71 +495,73 @@ int xcd_grid(int ncol) { return 8 * ((ncol + 7) >> 3); }
 
 }  // namespace
 
-hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2* G, double sc, hipStream_t st)
+hipError_t launch_phi_forward(const Plan& p, const Batch& B, int real, double sc, hipStream_t st)
 {
     const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
+    const dim3 grid(p.L, B.n);
     hipError_t e;
     if (real) {
         if ((e = set_lds(k_phi_forward<1>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_phi_forward<1>, dim3(p.L), dim3(fft_threads(p)), lds, st, p, map, G, sc);
+        hipLaunchKernelGGL(k_phi_forward<1>, grid, dim3(fft_threads(p)), lds, st, p, B, sc);
     } else {
         if ((e = set_lds(k_phi_forward<0>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_phi_forward<0>, dim3(p.L), dim3(fft_threads(p)), lds, st, p, map, G, sc);
+        hipLaunchKernelGGL(k_phi_forward<0>, grid, dim3(fft_threads(p)), lds, st, p, B, sc);
     }
     return hipGetLastError();
 }
 
 namespace {
 template <int ADJ_INV, int OUT32>
-hipError_t theta_forward_go(const Plan& p, int s, const double2* G, void* H, hipStream_t st)
+hipError_t theta_forward_go(const Plan& p, const Batch& B, hipStream_t st)
 {
     const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     hipError_t e;
     if ((e = set_lds(k_theta_forward<ADJ_INV, OUT32>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_theta_forward<ADJ_INV, OUT32>), dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s,
-                       G, H);
+    hipLaunchKernelGGL((k_theta_forward<ADJ_INV, OUT32>), dim3(xcd_grid(p.N1), B.n), dim3(fft_threads(p)), lds, st,
+                       p, B);
     return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, void* H, int out32, hipStream_t st)
+hipError_t launch_theta_forward(const Plan& p, const Batch& B, int out32, hipStream_t st)
 {
-    return out32 ? theta_forward_go<0, 1>(p, s, G, H, st) : theta_forward_go<0, 0>(p, s, G, H, st);
+    return out32 ? theta_forward_go<0, 1>(p, B, st) : theta_forward_go<0, 0>(p, B, st);
 }
 
-hipError_t launch_theta_inverse_adjoint(const Plan& p, int s, const double2* G, void* H, int out32, hipStream_t st)
+hipError_t launch_theta_inverse_adjoint(const Plan& p, const Batch& B, int out32, hipStream_t st)
 {
-    return out32 ? theta_forward_go<1, 1>(p, s, G, H, st) : theta_forward_go<1, 0>(p, s, G, H, st);
+    return out32 ? theta_forward_go<1, 1>(p, B, st) : theta_forward_go<1, 0>(p, B, st);
 }
 
-hipError_t launch_theta_forward_adjoint(const Plan& p, int s, const double2* Y, double2* Gt, hipStream_t st)
+hipError_t launch_theta_forward_adjoint(const Plan& p, const Batch& B, hipStream_t st)
 {
     const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     hipError_t e;
     if ((e = set_lds(k_theta_forward_adjoint, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_theta_forward_adjoint, dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s, Y, Gt);
+    hipLaunchKernelGGL(k_theta_forward_adjoint, dim3(xcd_grid(p.N1), B.n), dim3(fft_threads(p)), lds, st, p, B);
     return hipGetLastError();
 }
 
-hipError_t launch_theta_inverse(const Plan& p, int s, const double2* F, double2* Ft, hipStream_t st)
+hipError_t launch_theta_inverse(const Plan& p, const Batch& B, hipStream_t st)
 {
     const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     hipError_t e;
     if ((e = set_lds(k_theta_inverse, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_theta_inverse, dim3(xcd_grid(p.N1)), dim3(fft_threads(p)), lds, st, p, s, F, Ft);
+    hipLaunchKernelGGL(k_theta_inverse, dim3(xcd_grid(p.N1), B.n), dim3(fft_threads(p)), lds, st, p, B);
     return hipGetLastError();
 }
 
-hipError_t launch_phi_inverse(const Plan& p, const double2* Ft, void* map, int real, double sc, hipStream_t st)
+hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc, hipStream_t st)
 {
     const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
+    const dim3 grid(p.L, B.n);
     hipError_t e;
     if (real) {
         if ((e = set_lds(k_phi_inverse<1>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_phi_inverse<1>, dim3(p.L), dim3(fft_threads(p)), lds, st, p, Ft, map, sc);
+        hipLaunchKernelGGL(k_phi_inverse<1>, grid, dim3(fft_threads(p)), lds, st, p, B, sc);
     } else {
         if ((e = set_lds(k_phi_inverse<0>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_phi_inverse<0>, dim3(p.L), dim3(fft_threads(p)), lds, st, p, Ft, map, sc);
+        hipLaunchKernelGGL(k_phi_inverse<0>, grid, dim3(fft_threads(p)), lds, st, p, B, sc);
     }
     return hipGetLastError();
 }

@@ -79,43 +79,59 @@ struct MixMaps {
     int L[GMAX];
     int n;
 };
+// Groups of one mixed launch (blockIdx.y = group).
+constexpr int MIXG = 8;
+struct MixBatch {
+    MixMaps g[MIXG];
+    int ng;
+};
+
+// Maps of one batched launch (blockIdx.y, or z for 3-D grids, = map): per-map
+// input and output device pointers and spins; all maps of a launch share the
+// plan (band-limit).  Passed by value as a kernel argument.
+constexpr int MAXB = 32;
+struct Batch {
+    const void* in[MAXB];
+    void* out[MAXB];
+    int s[MAXB];
+    int n;
+};
 
 int build_plan(int L, Plan& p, std::string& err);
 void free_plan(Plan& p);
 int build_spin_table(int L, int as, SpinTable& t, std::string& err);
 void free_spin_table(SpinTable& t);
 
-// Kernel launchers (enqueue only).  Buffers: map, G (L x N1), F (N1 x L), coeffs.
+// Kernel launchers (enqueue only); each runs the maps of B (one plan) in one launch.
 // sc: 2 pi/N1 for the forward transform, 1 for the adjoint of the inverse.
-hipError_t launch_phi_forward(const Plan& p, const void* map, int real, double2* G, double sc, hipStream_t st);
-// Hp: forward Fourier coefficients H_{+-m,n} as records (Re H_{m,n}, Im H_{m,n},
-// Re H_{-m,n}, Im H_{-m,n}) at [(m * Lp + n) * 4], m < L, n < Lp (pad rows zero).
-// out32 = 1: FP32 H at [(m*4 + comp)*Lp + n] with the parity signs folded (the
-// mixed-precision contraction's staging layout).
-hipError_t launch_theta_forward(const Plan& p, int s, const double2* G, void* H, int out32, hipStream_t st);
+hipError_t launch_phi_forward(const Plan& p, const Batch& B, int real, double sc, hipStream_t st);
+// Forward theta stage.  Output: Hp records (Re H_{m,n}, Im H_{m,n}, Re H_{-m,n}, Im H_{-m,n})
+// at [(m * Lp + n) * 4], m < L, n < Lp (pad rows zero); with out32 = 1 FP32 H at
+// [(m*4 + comp)*Lp + n] with the parity signs folded (the mixed contraction's layout).
+hipError_t launch_theta_forward(const Plan& p, const Batch& B, int out32, hipStream_t st);
 // Theta step of the adjoint of the inverse (same output layouts as launch_theta_forward).
-hipError_t launch_theta_inverse_adjoint(const Plan& p, int s, const double2* G, void* H, int out32, hipStream_t st);
+hipError_t launch_theta_inverse_adjoint(const Plan& p, const Batch& B, int out32, hipStream_t st);
 // Theta step of the adjoint of the forward: folded Y (N1 x L) -> Gt (L x N1).
-hipError_t launch_theta_forward_adjoint(const Plan& p, int s, const double2* Y, double2* Gt, hipStream_t st);
-hipError_t launch_contract_forward(const Plan& p, int s, int real, const double* Hp, double2* flm,
+hipError_t launch_theta_forward_adjoint(const Plan& p, const Batch& B, hipStream_t st);
+// FP64 contractions: map k of the launch reads in0 + k*stride (doubles; the
+// chunk's workspace slots are equally spaced) and writes B.out[k].
+hipError_t launch_contract_forward(const Plan& p, int s, const double* in0, size_t stride, const Batch& B,
                                    hipStream_t st);
-// fs: per-map scratch of L x Lp x 4 doubles (the inverse's scaled coefficient stream),
-// written by launch_inverse_stream and read by launch_contract_inverse.
-hipError_t launch_inverse_stream(const Plan& p, int s, int real, const double2* flm, void* fs, int out32,
-                                 hipStream_t st);
+// Inverse coefficient stream (L x Lp x 4 doubles, or FP32 at [(m*4+comp)*Lp + l]).
+hipError_t launch_inverse_stream(const Plan& p, int s, int real, const Batch& B, int out32, hipStream_t st);
+hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, const double* in0, size_t stride,
+                                   const Batch& B, hipStream_t st);
+hipError_t launch_theta_inverse(const Plan& p, const Batch& B, hipStream_t st);
+// sc: 1 for the inverse transform, 2 pi/N1 for the adjoint of the forward.
+hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc, hipStream_t st);
+// Adjoint of the real-map coefficient expansion: y_{l,m} += (-1)^m conj(y_{l,-m}),
+// y_{l,-m} = 0 for m > 0 (in place on the L^2 layout of B.out).
+hipError_t launch_real_fold(int L, const Batch& B, hipStream_t st);
 // Largest group size (1, 2 or 4) whose staging fits the LDS for this plan.
 int mix_group_max(const Plan& p);
-// Mixed-precision contractions of one group (maps.n <= G <= GMAX, G in {1,2,4}).
-hipError_t launch_contract_forward_mix(const Plan& p, int s, const MixMaps& maps, int G, hipStream_t st);
-hipError_t launch_contract_inverse_mix(const Plan& p, const SpinTable& sp, int s, const MixMaps& maps, int G,
+// Mixed-precision contractions of up to MIXG groups (each maps.n <= G <= GMAX, G in {1,2,4}).
+hipError_t launch_contract_forward_mix(const Plan& p, int s, const MixBatch& maps, int G, hipStream_t st);
+hipError_t launch_contract_inverse_mix(const Plan& p, const SpinTable& sp, int s, const MixBatch& maps, int G,
                                        hipStream_t st);
-hipError_t launch_contract_inverse(const Plan& p, const SpinTable& st_, int s, const double* fs, double2* F,
-                                   hipStream_t st);
-hipError_t launch_theta_inverse(const Plan& p, int s, const double2* F, double2* Ft, hipStream_t st);
-// sc: 1 for the inverse transform, 2 pi/N1 for the adjoint of the forward.
-hipError_t launch_phi_inverse(const Plan& p, const double2* Ft, void* map, int real, double sc, hipStream_t st);
-// Adjoint of the real-map coefficient expansion: y_{l,m} += (-1)^m conj(y_{l,-m}),
-// y_{l,-m} = 0 for m > 0 (in place on the L^2 layout).
-hipError_t launch_real_fold(int L, double2* y, hipStream_t st);
 
 }  // namespace mw
