@@ -120,11 +120,24 @@ int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* real
 
 /* Create the plan tables and workspace a call with these arguments needs, on the
  * current device, so that a later call (e.g. one under stream capture) performs
- * no allocation.  Synchronises the device. */
+ * no allocation.  With precision MW_FP32C it also times the candidate group
+ * sizes of the shared-recursion contraction for each (L, spin, reality) class of
+ * the batch and keeps the fastest for later calls of the same shape (the
+ * results do not depend on the choice).  Synchronises the device.
+ *
+ * Batching: a call runs its maps in chunks of equal (L, spin, reality), each
+ * stage of a chunk being one kernel launch over all its maps; calls under
+ * stream capture (hipGraph) record those launches with their arguments and
+ * replay them unchanged.  Call mw_prepare with the same arguments first: a call
+ * under capture that would need an allocation fails with MW_ENOMEM.  Workspaces
+ * outgrown by later calls stay allocated until mw_release, so a captured graph
+ * stays valid until then; concurrent calls (or replays) on one device share the
+ * workspace and must be ordered by the caller. */
 int mw_prepare(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                int32_t precision);
 
-/* Free every plan and workspace of the library (all devices).  Synchronises. */
+/* Free every plan and workspace of the library (all devices), which also
+ * invalidates graphs captured from library calls.  Synchronises. */
 int mw_release(void);
 
 /* Static description of a status code. */

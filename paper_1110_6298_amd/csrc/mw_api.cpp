@@ -29,6 +29,9 @@ struct DeviceState {
     std::map<std::pair<int, int>, SpinTable> spins;  // by (L, |s|)
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    // Outgrown workspaces stay allocated until mw_release: a graph captured
+    // earlier may still reference one.
+    std::vector<void*> retired;
 };
 
 std::mutex g_mu;
@@ -150,7 +153,7 @@ int get_ws(DeviceState& d, size_t ws_bytes, bool may_alloc, void** ws)
 {
     if (d.ws_bytes < ws_bytes) {
         if (!may_alloc) return fail(MW_ENOMEM, "workspace of %zu bytes not prepared", ws_bytes);
-        if (d.ws) (void)hipFree(d.ws);
+        if (d.ws) d.retired.push_back(d.ws);
         d.ws = nullptr;
         d.ws_bytes = 0;
         if (hipMalloc(&d.ws, ws_bytes) != hipSuccess) return fail(MW_ENOMEM, "workspace hipMalloc(%zu) failed", ws_bytes);
@@ -526,6 +529,7 @@ int mw_release(void)
         for (auto& pp : kv.second.plans) mw::free_plan(pp.second);
         for (auto& ss : kv.second.spins) mw::free_spin_table(ss.second);
         if (kv.second.ws) (void)hipFree(kv.second.ws);
+        for (void* q : kv.second.retired) (void)hipFree(q);
     }
     g_dev.clear();
     (void)hipSetDevice(cur);
