@@ -78,7 +78,7 @@ def kernel_profile(mw, step, steps):
     return {k: v[0] / v[1] for k, v in prof.items()}
 
 
-def batched_workload(torch, mw, dev, steps, warmup, precision):
+def batched_workload(torch, mw, dev, steps, warmup, precision, graph=False):
     """The 256-map batch: L uniform on {128, 256, 512}, spin on {0, 2}, half of the
     maps drawn with real-map coefficient symmetry (only the s = 0 ones run the
     real path).  One step = one batched inverse + one batched forward call."""
@@ -97,7 +97,19 @@ def batched_workload(torch, mw, dev, steps, warmup, precision):
         mw.inverse_batch(flm, Ls, ss, rs, precision=precision, outs=grids)
         mw.forward_batch(grids, Ls, ss, rs, precision=precision, outs=back)
 
-    ms = time_steps(torch, step, steps, warmup)
+    if graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        ms = time_steps(torch, g.replay, steps, warmup)
+    else:
+        ms = time_steps(torch, step, steps, warmup)
     err = 0.0
     for b in range(len(maps)):
         ref = maps[b]["flm"]
@@ -213,8 +225,9 @@ def main():
 
     if not args.no_batch:
         batched = {}
-        for name, prec in (("fp64", mw.FP64), ("fp32c", mw.FP32C)):
-            ms_b, nmaps, err_b = batched_workload(torch, mw, dev, args.batch_steps, 2, prec)
+        for name, prec, graph in (("fp64", mw.FP64, False), ("fp32c", mw.FP32C, False),
+                                  ("fp64_graph", mw.FP64, True), ("fp32c_graph", mw.FP32C, True)):
+            ms_b, nmaps, err_b = batched_workload(torch, mw, dev, args.batch_steps, 2, prec, graph)
             batched[name] = {"maps_round_trips_per_s": nmaps * 1e3 / ms_b, "ms_per_step": ms_b,
                              "round_trip_rel_err": err_b}
         batched["workload"] = ("256 maps, L uniform on {128,256,512}, spin uniform on {0,2}, 128 with real-map "

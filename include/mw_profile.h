@@ -34,6 +34,12 @@ int mw_profile_read(double* ms, int* count);
 /* Name of a stage id ("" if out of range). */
 const char* mw_profile_stage_name(int stage);
 
+/* Group size (maps sharing one set of Wigner recursions) that mw_prepare's
+ * autotuner chose for mixed-precision calls with `nmaps` maps of band-limit L
+ * and spin s on the current device; *G = 0 when that shape was not tuned
+ * (calls then use the largest size the LDS allows, up to the map count). */
+int mw_profile_tuned_group(int L, int spin, int nmaps, int* G);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmw.so")
 EXPORTS = ("mw_forward", "mw_inverse", "mw_forward_adjoint", "mw_inverse_adjoint",
            "mw_workspace_size", "mw_prepare", "mw_release", "mw_status_string",
            "mw_last_error", "mw_version")
-PROFILE_EXPORTS = ("mw_profile_enable", "mw_profile_read", "mw_profile_stage_name")
+PROFILE_EXPORTS = ("mw_profile_enable", "mw_profile_read", "mw_profile_stage_name", "mw_profile_tuned_group")
 NSTAGE = 9
 
 _lib = None
@@ -74,6 +74,9 @@ def library():
         lib.mw_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         lib.mw_profile_stage_name.restype = ctypes.c_char_p
         lib.mw_profile_stage_name.argtypes = [ctypes.c_int]
+        lib.mw_profile_tuned_group.restype = ctypes.c_int
+        lib.mw_profile_tuned_group.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(ctypes.c_int)]
         _lib = lib
     return _lib
 
@@ -232,6 +235,13 @@ def profile_read() -> dict:
     cnt = (ctypes.c_int * NSTAGE)()
     _check(lib.mw_profile_read(ms, cnt), "mw_profile_read")
     return {lib.mw_profile_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(NSTAGE) if cnt[i]}
+
+
+def tuned_group(L: int, spin: int, nmaps: int) -> int:
+    """Group size the autotuner chose for this mixed-precision shape (0 = not tuned)."""
+    g = ctypes.c_int(0)
+    _check(library().mw_profile_tuned_group(L, spin, nmaps, ctypes.byref(g)), "mw_profile_tuned_group")
+    return int(g.value)
 
 
 def release() -> None:

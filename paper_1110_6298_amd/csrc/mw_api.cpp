@@ -582,6 +582,15 @@ int mw_profile_read(double* ms, int* count)
     return rc;
 }
 
+int mw_profile_tuned_group(int L, int spin, int nmaps, int* G)
+{
+    if (!G) return fail(MW_EINVAL, "G must be non-NULL");
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_tuned.find(std::make_tuple(L, spin, nmaps));
+    *G = (it == g_tuned.end()) ? 0 : it->second;
+    return MW_OK;
+}
+
 const char* mw_profile_stage_name(int stage)
 {
     static const char* names[MW_PROFILE_NSTAGE] = {

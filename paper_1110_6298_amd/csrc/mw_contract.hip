@@ -57,6 +57,29 @@ constexpr double EXT_DOWN = 0x1p-600;
 
 struct alignas(64) Rec8 { double v[8]; };    // 64-byte scalar-load unit
 
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef float fv2 __attribute__((ext_vector_type(2)));
+
+// Block-wide copy of n elements from global memory to LDS with the loads of
+// eight elements per thread in flight together (one memory wait per eight).
+template <class T>
+__device__ __forceinline__ void block_copy(T* __restrict__ dst, const T* __restrict__ src, int n)
+{
+    for (int base = 0; base < n; base += 8 * (int)blockDim.x) {
+        T v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int i = base + j * (int)blockDim.x + (int)threadIdx.x;
+            if (i < n) v[j] = src[i];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int i = base + j * (int)blockDim.x + (int)threadIdx.x;
+            if (i < n) dst[i] = v[j];
+        }
+    }
+}
+
 // 1/sqrt(i) for i = j-1 .. j, read from the shifted table Rt (Rt[j] = 1/sqrt(j-1),
 // Rt[0] = Rt[1] = 0), so that indices below 0 read zeros.
 __device__ __forceinline__ double2 rpair(const double* __restrict__ Rt, int j)
@@ -364,7 +387,7 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
     const int lane = threadIdx.x & 63;
     const int l0 = uniform(work[grp].x), mb = uniform(work[grp].y);
     if (l0 < 0) return;   // padding entry of the work list
-    for (int i = threadIdx.x; i < 2 * L + 8; i += blockDim.x) Rt[i] = Rtg[i];
+    block_copy((dv2*)Rt, (const dv2*)Rtg, L + 4);
     __syncthreads();
     const int l = l0 + lane;
     const bool valid = l < L;
@@ -791,7 +814,7 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
     const int lane = threadIdx.x & 63;
     const int n0 = uniform(work[grp].x), m = uniform(work[grp].y);
     if (n0 < 0) return;   // padding entry of the work list
-    for (int i = threadIdx.x; i < 2 * L + 8; i += blockDim.x) Rt[i] = Rtg[i];
+    block_copy((dv2*)Rt, (const dv2*)Rtg, L + 4);
     __syncthreads();
     const int n = n0 + lane;
     const bool valid = n < L;
@@ -924,16 +947,33 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
     float* Hs = (float*)(smem + rtn);
     const int nmax = min(l0 + 63, L - 1);
     const int nA = 2 * ((nmax >> 1) + 1);
-    for (int i = threadIdx.x; i < rtn; i += blockDim.x) Rt[i] = Rtg[i];
-    for (int i = threadIdx.x; i < G * 8 * nA; i += blockDim.x) {
-        const int n = i % nA, r = i / nA;
-        const int comp = r & 3, c = (r >> 2) & 1, b = r >> 3;
-        float v = 0.0f;
-        if (b < maps.n) {
-            const int Lb = maps.L[b], m = mb + c;
-            if (m < Lb && n < Lb) v = maps.src[b][((size_t)m * 4 + comp) * (size_t)(Lb + (Lb & 1)) + n];
+    block_copy((dv2*)Rt, (const dv2*)Rtg, rtn / 2);
+    {
+        // rows (b, c, comp) of nA floats, copied as float2 pairs (n, n+1); a map's
+        // rows hold Lp_b entries with the pad n = L_b (odd L_b) zero
+        const int h2 = nA / 2, total = G * 8 * h2;
+        for (int base = 0; base < total; base += 8 * (int)blockDim.x) {
+            fv2 v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = base + j * (int)blockDim.x + (int)threadIdx.x;
+                v[j] = fv2{0.0f, 0.0f};
+                if (i < total) {
+                    const int r = i / h2, n = 2 * (i - r * h2);
+                    const int comp = r & 3, c = (r >> 2) & 1, b = r >> 3;
+                    if (b < maps.n) {
+                        const int Lb = maps.L[b], m = mb + c;
+                        if (m < Lb && n < Lb)
+                            v[j] = *(const fv2*)(maps.src[b] + ((size_t)m * 4 + comp) * (size_t)(Lb + (Lb & 1)) + n);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = base + j * (int)blockDim.x + (int)threadIdx.x;
+                if (i < total) ((fv2*)Hs)[i] = v[j];
+            }
         }
-        Hs[i] = v;
     }
     __syncthreads();
     const int l = l0 + lane;
@@ -1089,16 +1129,32 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse_mix(
     float* Fs = (float*)(smem + rtn);
     const int lbase = geo.lstart;
     const int nS = Lp - lbase;
-    for (int i = threadIdx.x; i < rtn; i += blockDim.x) Rt[i] = Rtg[i];
-    for (int i = threadIdx.x; i < G * 4 * nS; i += blockDim.x) {
-        const int l = lbase + i % nS, r = i / nS;
-        const int comp = r & 3, b = r >> 2;
-        float v = 0.0f;
-        if (b < maps.n) {
-            const int Lb = maps.L[b];
-            if (m < Lb && l < Lb) v = maps.src[b][((size_t)m * 4 + comp) * (size_t)(Lb + (Lb & 1)) + l];
+    block_copy((dv2*)Rt, (const dv2*)Rtg, rtn / 2);
+    {
+        // rows (b, comp) of nS floats from degree lbase (even), copied as float2 pairs
+        const int h2 = nS / 2, total = G * 4 * h2;
+        for (int base = 0; base < total; base += 8 * (int)blockDim.x) {
+            fv2 v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = base + j * (int)blockDim.x + (int)threadIdx.x;
+                v[j] = fv2{0.0f, 0.0f};
+                if (i < total) {
+                    const int r = i / h2, l = lbase + 2 * (i - r * h2);
+                    const int comp = r & 3, b = r >> 2;
+                    if (b < maps.n) {
+                        const int Lb = maps.L[b];
+                        if (m < Lb && l < Lb)
+                            v[j] = *(const fv2*)(maps.src[b] + ((size_t)m * 4 + comp) * (size_t)(Lb + (Lb & 1)) + l);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = base + j * (int)blockDim.x + (int)threadIdx.x;
+                if (i < total) ((fv2*)Fs)[i] = v[j];
+            }
         }
-        Fs[i] = v;
     }
     __syncthreads();
     const int n = n0 + lane;

@@ -30,6 +30,31 @@ __device__ __forceinline__ double2 mul_dir_i(double2 a)
 // radix-16 pass then fall on distinct banks.
 __device__ __forceinline__ int P(int i) { return i + (i >> 4); }
 
+// Block-wide loop over j = threadIdx.x + q*blockDim.x < n (n <= 16*blockDim.x):
+// the global loads ld(j) of eight consecutive q are all issued before any result
+// is used by use(j, value), so a thread waits for memory twice, not 16 times.
+struct Pair2 { double2 a, b; };
+
+template <class Ld, class Use>
+__device__ __forceinline__ void staged_loop(int n, Ld ld, Use use)
+{
+    using V = decltype(ld(0));
+#pragma unroll
+    for (int h = 0; h < 16; h += 8) {
+        V v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = threadIdx.x + (h + q) * blockDim.x;
+            if (j < n) v[q] = ld(j);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = threadIdx.x + (h + q) * blockDim.x;
+            if (j < n) use(j, v[q]);
+        }
+    }
+}
+
 // In-place DFT of 4 values: a_k <- sum_j a_j w^{jk}, w = exp(DIR 2 pi i/4).
 template <int DIR>
 __device__ __forceinline__ void bf4(double2& a0, double2& a1, double2& a2, double2& a3)
@@ -110,8 +135,8 @@ __device__ __forceinline__ void twiddle_powers(double2* u, double2 w)
 // passes): each thread holds up to 16/R butterflies in one 16-value register set.
 // With post != nullptr every output X_j is stored as X_j * post[j].
 template <int DIR, int R>
-__device__ __forceinline__ void last_pass(double2* x, int N, int logN, int p, int logp,
-                                          const double2* __restrict__ tw, const double2* __restrict__ post)
+__device__ __forceinline__ void last_pass(double2* x, int N, int p, const double2 (&wl)[8],
+                                          const double2* __restrict__ post)
 {
     constexpr int r = (R == 2) ? 1 : (R == 4) ? 2 : 3;
     constexpr int QM = 16 / R;
@@ -124,8 +149,9 @@ __device__ __forceinline__ void last_pass(double2* x, int N, int logN, int p, in
             const int k = i & (p - 1);
 #pragma unroll
             for (int t = 0; t < R; ++t) u[q * R + t] = x[P(i + t * NB)];
-            double2 w = tw[k << (logN - logp - r)];
+            double2 w = wl[q];
             if (DIR > 0) w = cconj(w);
+            (void)k;
             twiddle_powers<R>(u + q * R, w);
             double2* v = u + q * R;
             if (R == 2) {
@@ -180,16 +206,41 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const dou
                                           const double2* __restrict__ post = nullptr)
 {
     const int i = threadIdx.x;
-    int p = 1, logp = 0;
+    const int n16 = logN >> 2;       // radix-16 passes (at most 3 for N <= 8192)
+    const int r = logN - 4 * n16;    // final radix 2^r, none when r = 0
+    // every twiddle base this thread needs, loaded together before the first pass
+    double2 w16p[3], wl[8];
+    {
+        int p = 1, logp = 0;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            w16p[s] = make_double2(1.0, 0.0);
+            if (s < n16) {
+                if (i < (N >> 4)) w16p[s] = tw[(i & (p - 1)) << (logN - logp - 4)];
+                p <<= 4;
+                logp += 4;
+            }
+        }
+        const int NB = r ? (N >> r) : 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int iq = i + q * blockDim.x;
+            wl[q] = make_double2(1.0, 0.0);
+            if (r && q < (16 >> r) && iq < NB) wl[q] = tw[(iq & (p - 1)) << (logN - logp - r)];
+        }
+    }
+    int p = 1;
     __syncthreads();
-    while (logN - logp >= 4) {
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        if (s >= n16) break;
         const int NB = N >> 4;
         double2 u[16];
         const int k = i & (p - 1);
         if (i < NB) {
 #pragma unroll
             for (int t = 0; t < 16; ++t) u[t] = x[P(i + t * NB)];
-            double2 w = tw[k << (logN - logp - 4)];
+            double2 w = w16p[s];
             if (DIR > 0) w = cconj(w);
             twiddle_powers<16>(u, w);
             dft16<DIR>(u);
@@ -200,13 +251,12 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const dou
 #pragma unroll
             for (int t = 0; t < 16; ++t) x[P(j + t * p)] = u[t];
         }
-        p <<= 4; logp += 4;
+        p <<= 4;
         __syncthreads();
     }
-    const int r = logN - logp;
-    if (r == 1) last_pass<DIR, 2>(x, N, logN, p, logp, tw, post);
-    else if (r == 2) last_pass<DIR, 4>(x, N, logN, p, logp, tw, post);
-    else if (r == 3) last_pass<DIR, 8>(x, N, logN, p, logp, tw, post);
+    if (r == 1) last_pass<DIR, 2>(x, N, p, wl, post);
+    else if (r == 2) last_pass<DIR, 4>(x, N, p, wl, post);
+    else if (r == 3) last_pass<DIR, 8>(x, N, p, wl, post);
     else if (post) {
         for (int j = threadIdx.x; j < N; j += blockDim.x) x[P(j)] = cmul(x[P(j)], post[j]);
         __syncthreads();
@@ -242,20 +292,25 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
     const void* __restrict__ map = B.in[blockIdx.y];
     double2* __restrict__ G = (double2*)B.out[blockIdx.y];
     const int t = blockIdx.x, L = p.L, N1 = p.N1;
-    for (int j = threadIdx.x; j < p.N2; j += blockDim.x) {
-        double2 v = make_double2(0.0, 0.0);
-        if (j < N1) {
-            double2 f = REAL ? make_double2(((const double*)map)[(size_t)t * N1 + j], 0.0)
-                             : ((const double2*)map)[(size_t)t * N1 + j];
-            v = cmul(f, p.chirp[j]);
-        }
-        A[P(j)] = v;
-    }
+    staged_loop(
+        p.N2,
+        [&](int j) {
+            Pair2 v{make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+            if (j < N1) {
+                v.a = REAL ? make_double2(((const double*)map)[(size_t)t * N1 + j], 0.0)
+                           : ((const double2*)map)[(size_t)t * N1 + j];
+                v.b = p.chirp[j];
+            }
+            return v;
+        },
+        [&](int j, const Pair2& v) { A[P(j)] = cmul(v.a, v.b); });
     bluestein_core(A, p);
-    for (int k = threadIdx.x; k < N1; k += blockDim.x) {
-        const int m = (k <= L - 1) ? k : k - N1;
-        G[(size_t)t * N1 + (m + L - 1)] = cscale(cmul(A[P(k)], p.chirp[k]), sc);
-    }
+    staged_loop(
+        N1, [&](int k) { return p.chirp[k]; },
+        [&](int k, double2 c) {
+            const int m = (k <= L - 1) ? k : k - N1;
+            G[(size_t)t * N1 + (m + L - 1)] = cscale(cmul(A[P(k)], c), sc);
+        });
 }
 
 // Forward theta stage for order m (Sec. IV-B..IV-D):
@@ -285,16 +340,18 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
     if (mi >= N1) return;
     const int m = mi - (L - 1);
     const double sig = ((m + s) & 1) ? -1.0 : 1.0;
-    for (int j = threadIdx.x; j < N2; j += blockDim.x) {
-        double2 v = make_double2(0.0, 0.0);
-        if (j < N1) {
-            double2 g;
-            if (j < L) g = G[(size_t)j * N1 + mi];
-            else g = ADJ_INV ? make_double2(0.0, 0.0) : cscale(G[(size_t)(2 * L - 2 - j) * N1 + mi], sig);
-            v = cmul(g, p.chirp[j]);
-        }
-        A[P(j)] = v;
-    }
+    staged_loop(
+        N2,
+        [&](int j) {
+            Pair2 v{make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+            if (j < N1) {
+                if (j < L) v.a = G[(size_t)j * N1 + mi];
+                else if (!ADJ_INV) v.a = G[(size_t)(2 * L - 2 - j) * N1 + mi];
+                v.b = p.chirp[j];
+            }
+            return v;
+        },
+        [&](int j, const Pair2& v) { A[P(j)] = cmul((j < L) ? v.a : cscale(v.a, sig), v.b); });
     bluestein_core(A, p);
     // F_{m'} into registers (N1 <= N2/2 <= 8 * blockDim.x), then scatter to slot m' mod N2.
     double2 r[8];
@@ -379,12 +436,16 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
     const double sig = ((m + s) & 1) ? -1.0 : 1.0;
     for (int j = threadIdx.x; j < N2; j += blockDim.x) A[P(j)] = make_double2(0.0, 0.0);
     __syncthreads();
-    for (int k = threadIdx.x; k < N1; k += blockDim.x) {
-        const int mp = (k <= L - 1) ? k : k - N1;
-        double2 y = Y[(size_t)mi * L + (mp < 0 ? -mp : mp)];
-        if (mp < 0) y = cscale(y, sig);
-        A[P((mp + N2) & (N2 - 1))] = y;
-    }
+    staged_loop(
+        N1,
+        [&](int k) {
+            const int mp = (k <= L - 1) ? k : k - N1;
+            return Y[(size_t)mi * L + (mp < 0 ? -mp : mp)];
+        },
+        [&](int k, double2 y) {
+            const int mp = (k <= L - 1) ? k : k - N1;
+            A[P((mp + N2) & (N2 - 1))] = (mp < 0) ? cscale(y, sig) : y;
+        });
     block_fft<+1>(A, N2, p.logN2, p.tw, p.whatc);
     block_fft<-1>(A, N2, p.logN2, p.tw);
     // Z_{m''} e^{+i m'' pi/N1}/(2 pi N1) = Z conj(thtw), conjugated and chirped for the
@@ -407,14 +468,13 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
     }
     for (int j = threadIdx.x + 8 * blockDim.x; j < N2; j += blockDim.x) A[P(j)] = make_double2(0.0, 0.0);
     bluestein_core(A, p);
-    for (int t = threadIdx.x; t < L; t += blockDim.x) {
-        double2 v = cconj(cmul(A[P(t)], p.chirp[t]));
-        if (t <= L - 2) {
-            const int u = 2 * L - 2 - t;
-            v = cadd(v, cscale(cconj(cmul(A[P(u)], p.chirp[u])), sig));
-        }
-        Gt[(size_t)t * N1 + mi] = v;
-    }
+    staged_loop(
+        L, [&](int t) { return Pair2{p.chirp[t], p.chirp[2 * L - 2 - t]}; },
+        [&](int t, const Pair2& c) {
+            double2 v = cconj(cmul(A[P(t)], c.a));
+            if (t <= L - 2) v = cadd(v, cscale(cconj(cmul(A[P(2 * L - 2 - t)], c.b)), sig));
+            Gt[(size_t)t * N1 + mi] = v;
+        });
 }
 
 // Inverse theta stage for order m (Sec. IV-E, Eq.(Fmt)):
@@ -433,21 +493,30 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
     const int m = mi - (L - 1);
     const double sig = ((m + s) & 1) ? -1.0 : 1.0;
     const double unscale = 2.0 * 3.14159265358979323846 * (double)N1;
-    for (int j = threadIdx.x; j < N2; j += blockDim.x) {
-        double2 v = make_double2(0.0, 0.0);
-        if (j < N1) {
+    struct Tri { double2 f, w, c; };
+    staged_loop(
+        N2,
+        [&](int j) {
+            Tri v{make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+            if (j < N1) {
+                const int mp = (j <= L - 1) ? j : j - N1;
+                v.f = F[(size_t)mi * L + (mp < 0 ? -mp : mp)];
+                v.w = p.thtw[j];
+                v.c = p.chirp[j];
+            }
+            return v;
+        },
+        [&](int j, const Tri& v) {
             const int mp = (j <= L - 1) ? j : j - N1;
-            double2 f = F[(size_t)mi * L + (mp < 0 ? -mp : mp)];
-            if (mp < 0) f = cscale(f, sig);
+            const double2 f = (mp < 0) ? cscale(v.f, sig) : v.f;
             // y = f e^{+i m' pi/N1};  conj(thtw) * 2 pi N1 = e^{+i m' pi/N1}
-            double2 y = cmul(f, cscale(cconj(p.thtw[j]), unscale));
-            v = cmul(cconj(y), p.chirp[j]);
-        }
-        A[P(j)] = v;
-    }
+            const double2 y = cmul(f, cscale(cconj(v.w), unscale));
+            A[P(j)] = cmul(cconj(y), v.c);
+        });
     bluestein_core(A, p);
-    for (int t = threadIdx.x; t < L; t += blockDim.x)
-        Ft[(size_t)t * N1 + mi] = cconj(cmul(A[P(t)], p.chirp[t]));
+    staged_loop(
+        L, [&](int t) { return p.chirp[t]; },
+        [&](int t, double2 c) { Ft[(size_t)t * N1 + mi] = cconj(cmul(A[P(t)], c)); });
 }
 
 // Inverse phi stage (Eq.(f_pfft)): f(t, p) = sc sum_m F_m(theta_t) e^{i m phi_p}, with
@@ -460,20 +529,26 @@ __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
     const double2* __restrict__ Ft = (const double2*)B.in[blockIdx.y];
     void* __restrict__ map = B.out[blockIdx.y];
     const int t = blockIdx.x, L = p.L, N1 = p.N1;
-    for (int j = threadIdx.x; j < p.N2; j += blockDim.x) {
-        double2 v = make_double2(0.0, 0.0);
-        if (j < N1) {
-            const int m = (j <= L - 1) ? j : j - N1;
-            v = cmul(cconj(Ft[(size_t)t * N1 + (m + L - 1)]), p.chirp[j]);
-        }
-        A[P(j)] = v;
-    }
+    staged_loop(
+        p.N2,
+        [&](int j) {
+            Pair2 v{make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+            if (j < N1) {
+                const int m = (j <= L - 1) ? j : j - N1;
+                v.a = Ft[(size_t)t * N1 + (m + L - 1)];
+                v.b = p.chirp[j];
+            }
+            return v;
+        },
+        [&](int j, const Pair2& v) { A[P(j)] = cmul(cconj(v.a), v.b); });
     bluestein_core(A, p);
-    for (int k = threadIdx.x; k < N1; k += blockDim.x) {
-        double2 out = cscale(cconj(cmul(A[P(k)], p.chirp[k])), sc);
-        if (REAL) ((double*)map)[(size_t)t * N1 + k] = out.x;
-        else ((double2*)map)[(size_t)t * N1 + k] = out;
-    }
+    staged_loop(
+        N1, [&](int k) { return p.chirp[k]; },
+        [&](int k, double2 c) {
+            const double2 out = cscale(cconj(cmul(A[P(k)], c)), sc);
+            if (REAL) ((double*)map)[(size_t)t * N1 + k] = out.x;
+            else ((double2*)map)[(size_t)t * N1 + k] = out;
+        });
 }
 
 int fft_threads(const Plan& p)
