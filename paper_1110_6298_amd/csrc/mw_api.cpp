@@ -293,12 +293,14 @@ hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, 
     case Op::Forward: {
         const mw::Batch B1 = batch_of(c, user_in, w0), B2 = batch_of(c, w0, w1), B3 = batch_of(c, w1, user_out);
         go(0, [&] { return mw::launch_phi_forward(p, B1, real, phi_sc, st); });
-        go(1, [&] { return mw::launch_theta_forward(p, B2, mix, st); });
+        go(1, [&] { return mw::launch_theta_forward(p, B2, mix, real, st); });
         if (mix) {
             const mw::MixBatch M = mix_of(c, w1, user_out);
             go(2, [&] { return mw::launch_contract_forward_mix(p, s, M, c.G, st); });
         } else {
-            go(2, [&] { return mw::launch_contract_forward(p, s, (const double*)w1(0), ws_need(Lws) / 8, B3, st); });
+            go(2, [&] {
+                return mw::launch_contract_forward(p, s, real, (const double*)w1(0), ws_need(Lws) / 8, B3, st);
+            });
         }
         break;
     }
@@ -317,12 +319,14 @@ hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, 
             go(inv ? 3 : 6, [&] { return mw::launch_contract_inverse_mix(p, *sp, s, M, c.G, st); });
         } else {
             go(inv ? 3 : 6, [&] {
-                return mw::launch_contract_inverse(p, *sp, s, (const double*)w2(0), ws_need(Lws) / 8, B2, st);
+                return mw::launch_contract_inverse(p, *sp, s, inv ? real : 0, (const double*)w2(0), ws_need(Lws) / 8,
+                                                   B2, st);
             });
         }
         if (inv) {
-            go(4, [&] { return mw::launch_theta_inverse(p, B3, st); });
-            go(5, [&] { return mw::launch_phi_inverse(p, B4, real, 1.0, st); });
+            // real maps: orders m >= 0 only, negative orders by conjugate symmetry
+            go(4, [&] { return mw::launch_theta_inverse(p, B3, real, st); });
+            go(5, [&] { return mw::launch_phi_inverse(p, B4, real ? 2 : 0, 1.0, st); });
         } else {
             go(8, [&] { return mw::launch_theta_forward_adjoint(p, B3, st); });
             go(8, [&] { return mw::launch_phi_inverse(p, B4, real, phi_sc, st); });
@@ -340,7 +344,9 @@ hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, 
             const mw::MixBatch M = mix_of(c, w1, user_out);
             go(7, [&] { return mw::launch_contract_forward_mix(p, s, M, c.G, st); });
         } else {
-            go(7, [&] { return mw::launch_contract_forward(p, s, (const double*)w1(0), ws_need(Lws) / 8, B3, st); });
+            go(7, [&] {
+                return mw::launch_contract_forward(p, s, 0, (const double*)w1(0), ws_need(Lws) / 8, B3, st);
+            });
         }
         if (real) go(8, [&] { return mw::launch_real_fold(p.L, B3, st); });
         break;

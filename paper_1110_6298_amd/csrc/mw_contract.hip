@@ -175,7 +175,7 @@ __device__ __forceinline__ double fwd_product(const FwdLane<MT, EXT>& st, int c)
 
 // One step n: contributions of D_{.,n} (h = the four doubles of H at n for
 // each chain), then the recursion to n-1.
-template <int MT, bool EXT, int PAR, bool INJ>
+template <int MT, bool EXT, int PAR, bool INJ, bool RL>
 __device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int mb, int as,
                                          const Rec8 (&h)[MT], double ra, bool& anyscaled)
 {
@@ -186,8 +186,10 @@ __device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int
         const double pr = fwd_product<MT, EXT>(st, c);
         st.ap[c][PAR].x = fma(pr, hc[0], st.ap[c][PAR].x);
         st.ap[c][PAR].y = fma(pr, hc[1], st.ap[c][PAR].y);
-        st.am[c][PAR].x = fma(pr, hc[2], st.am[c][PAR].x);
-        st.am[c][PAR].y = fma(pr, hc[3], st.am[c][PAR].y);
+        if (!RL) {   // real maps: f_{l,-m} follows from f_{l,m}
+            st.am[c][PAR].x = fma(pr, hc[2], st.am[c][PAR].x);
+            st.am[c][PAR].y = fma(pr, hc[3], st.am[c][PAR].y);
+        }
     }
     fwd_advance<MT, EXT>(st, mb, as, ra, anyscaled);
 }
@@ -213,18 +215,18 @@ __device__ __forceinline__ FwdR fwd_load_r(const double* __restrict__ Rt, int le
     return r;
 }
 
-template <int MT, bool EXT, bool INJ>
+template <int MT, bool EXT, bool INJ, bool RL>
 __device__ __forceinline__ void fwd_pair(FwdLane<MT, EXT>& st, int k, int l, int mb, int as,
                                          const Rec8 (&h)[MT], const FwdR& r, bool& anyscaled)
 {
     // n = 2k+1: 1/sqrt(l+n) = hi.y, 1/sqrt(l-n+1) = lo.x;  n = 2k: hi.x, lo.y
-    fwd_step<MT, EXT, 1, INJ>(st, 2 * k + 1, l, mb, as, h, r.hi.y * r.lo.x, anyscaled);
-    fwd_step<MT, EXT, 0, INJ>(st, 2 * k, l, mb, as, h, r.hi.x * r.lo.y, anyscaled);
+    fwd_step<MT, EXT, 1, INJ, RL>(st, 2 * k + 1, l, mb, as, h, r.hi.y * r.lo.x, anyscaled);
+    fwd_step<MT, EXT, 0, INJ, RL>(st, 2 * k, l, mb, as, h, r.hi.x * r.lo.y, anyscaled);
 }
 
 // Pairs kfrom, kfrom-1, ..., kto+1 (an even count); on entry A holds pair kfrom,
 // on exit A holds pair kto (pair 0 when kto < 0).
-template <int MT, bool EXT, bool INJ>
+template <int MT, bool EXT, bool INJ, bool RL>
 __device__ __forceinline__ void fwd_phase(FwdLane<MT, EXT>& st, int kfrom, int kto, int l, int le, int mb,
                                           int as, const double* __restrict__ Hp, const double* __restrict__ Rt,
                                           int Lp, int L, Rec8 (&hA)[MT], Rec8 (&hB)[MT], FwdR& rA, FwdR& rB,
@@ -236,20 +238,20 @@ __device__ __forceinline__ void fwd_phase(FwdLane<MT, EXT>& st, int kfrom, int k
         fwd_load_h<MT>(hB, Hp, mb, Lp, L, k - 1);
         rB = fwd_load_r(Rt, le, k - 1);
         __builtin_amdgcn_sched_barrier(0);
-        fwd_pair<MT, EXT, INJ>(st, k, l, mb, as, hA, rA, anyscaled);
+        fwd_pair<MT, EXT, INJ, RL>(st, k, l, mb, as, hA, rA, anyscaled);
         wait_scalar(hB[0].v[0]);
         __builtin_amdgcn_sched_barrier(0);
         const int k2 = max(k - 2, 0);
         fwd_load_h<MT>(hA, Hp, mb, Lp, L, k2);
         rA = fwd_load_r(Rt, le, k2);
         __builtin_amdgcn_sched_barrier(0);
-        fwd_pair<MT, EXT, INJ>(st, k - 1, l, mb, as, hB, rB, anyscaled);
+        fwd_pair<MT, EXT, INJ, RL>(st, k - 1, l, mb, as, hB, rB, anyscaled);
     }
 }
 
 // Pairs ktop .. klo of one segment; pairs >= kA (kA in [klo, ktop+1]) contain
 // lane starts.  Phase loops cover even pair counts; a leftover pair is peeled.
-template <int MT, bool EXT>
+template <int MT, bool EXT, bool RL>
 __device__ __forceinline__ void fwd_segment(FwdLane<MT, EXT>& st, int ktop, int kA, int klo, int l, int le, int mb,
                                             int as, const double* __restrict__ Hp, const double* __restrict__ Rt,
                                             int Lp, int L, bool& anyscaled)
@@ -262,20 +264,21 @@ __device__ __forceinline__ void fwd_segment(FwdLane<MT, EXT>& st, int ktop, int 
     if ((cntA & 1) && kA > klo) { --kA; ++cntA; }
     if (cntA > 0) {
         const int klastA = (cntA & 1) ? kA + 1 : kA;
-        fwd_phase<MT, EXT, true>(st, ktop, klastA - 1, l, le, mb, as, Hp, Rt, Lp, L, hA, hB, rA, rB, anyscaled);
+        fwd_phase<MT, EXT, true, RL>(st, ktop, klastA - 1, l, le, mb, as, Hp, Rt, Lp, L, hA, hB, rA, rB, anyscaled);
         if (cntA & 1) {            // kA = klo, in A
             wait_scalar(hA[0].v[0]);
-            fwd_pair<MT, EXT, true>(st, kA, l, mb, as, hA, rA, anyscaled);
+            fwd_pair<MT, EXT, true, RL>(st, kA, l, mb, as, hA, rA, anyscaled);
             return;
         }
     }
     const int cntB = kA - klo;     // pairs kA-1 .. klo, A holds kA-1
     if (cntB > 0) {
         const int klastB = (cntB & 1) ? klo + 1 : klo;
-        fwd_phase<MT, EXT, false>(st, kA - 1, klastB - 1, l, le, mb, as, Hp, Rt, Lp, L, hA, hB, rA, rB, anyscaled);
+        fwd_phase<MT, EXT, false, RL>(st, kA - 1, klastB - 1, l, le, mb, as, Hp, Rt, Lp, L, hA, hB, rA, rB,
+                                     anyscaled);
         if (cntB & 1) {
             wait_scalar(hA[0].v[0]);
-            fwd_pair<MT, EXT, false>(st, klo, l, mb, as, hA, rA, anyscaled);
+            fwd_pair<MT, EXT, false, RL>(st, klo, l, mb, as, hA, rA, anyscaled);
         }
     }
 }
@@ -371,7 +374,7 @@ __device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscale
 // FP64 forward contraction.  One workgroup per chain group (64 degrees l0..,
 // MT orders mb..); wave w runs segment w of the row recursions.  Partial sums
 // are added in LDS in segment order.
-template <int MT, bool EXT>
+template <int MT, bool EXT, bool RL>
 __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
     const double* __restrict__ Hp0, size_t hstride, Batch B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,
@@ -398,7 +401,7 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
     FwdLane<MT, EXT> st;
     bool anyscaled;
     const FwdSeg g = fwd_setup<MT, EXT>(st, anyscaled, w, l0, mb, l, L, as, segf, edge, edgek, ckf, ckfk);
-    if (g.active) fwd_segment<MT, EXT>(st, g.ktop, g.kA, g.klo, l, le, mb, as, Hp, Rt, Lp, L, anyscaled);
+    if (g.active) fwd_segment<MT, EXT, RL>(st, g.ktop, g.kA, g.klo, l, le, mb, as, Hp, Rt, Lp, L, anyscaled);
     if (jtop > 0) {
         if (w > 0 && w <= jtop) {
 #pragma unroll
@@ -446,10 +449,16 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
         }
         const double base = sgn(s) * c_l;
         double2 op = mul_ipow(sp, ((m + s) % 4 + 4) % 4);
-        flm[(size_t)l * l + l + m] = make_double2(op.x * base * fp, op.y * base * fp);
+        const double2 fpm = make_double2(op.x * base * fp, op.y * base * fp);
+        flm[(size_t)l * l + l + m] = fpm;
         if (m > 0) {
-            double2 om = mul_ipow(sm, ((-m + s) % 4 + 4) % 4);
-            flm[(size_t)l * l + l - m] = make_double2(om.x * base * fm, om.y * base * fm);
+            if (RL) {   // real scalar map: f_{l,-m} = (-1)^m conj(f_{l,m}) (Sec. IV-G)
+                const double sg = sgn(m);
+                flm[(size_t)l * l + l - m] = make_double2(sg * fpm.x, -sg * fpm.y);
+            } else {
+                double2 om = mul_ipow(sm, ((-m + s) % 4 + 4) % 4);
+                flm[(size_t)l * l + l - m] = make_double2(om.x * base * fm, om.y * base * fm);
+            }
         }
     }
 }
@@ -588,7 +597,7 @@ __device__ __forceinline__ void inv_advance(InvLane<EXT>& st, double nd, double 
 }
 
 // uniform data of one step: stream record (4 doubles), (Pu_m, Qu_m), (Pu_s, Qu_s)
-template <bool EXT, bool INJ>
+template <bool EXT, bool INJ, bool RL>
 __device__ __forceinline__ void inv_step(InvLane<EXT>& st, int l, int lstart, double nd, const double* f,
                                          double pum, double qum, double pus, double qus, double rs,
                                          bool& anyscaled)
@@ -597,8 +606,10 @@ __device__ __forceinline__ void inv_step(InvLane<EXT>& st, int l, int lstart, do
     const double pr = inv_product<EXT>(st);
     st.ap.x = fma(pr, f[0], st.ap.x);
     st.ap.y = fma(pr, f[1], st.ap.y);
-    st.am.x = fma(pr, f[2], st.am.x);
-    st.am.y = fma(pr, f[3], st.am.y);
+    if (!RL) {   // real maps: the orders -m are not needed (F_{-m}(theta) = conj(F_m(theta)))
+        st.am.x = fma(pr, f[2], st.am.x);
+        st.am.y = fma(pr, f[3], st.am.y);
+    }
     inv_advance<EXT>(st, nd, pum, qum, pus, qus, rs, anyscaled);
 }
 
@@ -622,18 +633,19 @@ __device__ __forceinline__ InvR inv_load_r(const double* __restrict__ Rt, int ne
     return r;
 }
 
-template <bool EXT, bool INJ>
+template <bool EXT, bool INJ, bool RL>
 __device__ __forceinline__ void inv_pair(InvLane<EXT>& st, int j, int lstart, double nd, const InvU& u,
                                          const InvR& r, bool& anyscaled)
 {
     const int l = 2 * j;
-    inv_step<EXT, INJ>(st, l, lstart, nd, u.f.v, u.cm.x, u.cm.y, u.cs.x, u.cs.y, r.a.x * r.b.x, anyscaled);
-    inv_step<EXT, INJ>(st, l + 1, lstart, nd, u.f.v + 4, u.cm.z, u.cm.w, u.cs.z, u.cs.w, r.a.y * r.b.y, anyscaled);
+    inv_step<EXT, INJ, RL>(st, l, lstart, nd, u.f.v, u.cm.x, u.cm.y, u.cs.x, u.cs.y, r.a.x * r.b.x, anyscaled);
+    inv_step<EXT, INJ, RL>(st, l + 1, lstart, nd, u.f.v + 4, u.cm.z, u.cm.w, u.cs.z, u.cs.w, r.a.y * r.b.y,
+                           anyscaled);
 }
 
 // Pairs jfrom .. jlast (ascending, an even count); on entry A holds pair jfrom,
 // on exit A holds pair min(jlast + 1, jend).
-template <bool EXT, bool INJ>
+template <bool EXT, bool INJ, bool RL>
 __device__ __forceinline__ void inv_phase(InvLane<EXT>& st, int jfrom, int jlast, int jend, int lstart, int ne,
                                           double nd, int m, int as, int Lp, int L, const double* __restrict__ fs,
                                           const double2* __restrict__ lco, const double* __restrict__ Rt, InvU& uA,
@@ -645,21 +657,21 @@ __device__ __forceinline__ void inv_phase(InvLane<EXT>& st, int jfrom, int jlast
         inv_load_u(uB, fs, lco, m, as, Lp, L, j + 1);
         rB = inv_load_r(Rt, ne, j + 1);
         __builtin_amdgcn_sched_barrier(0);
-        inv_pair<EXT, INJ>(st, j, lstart, nd, uA, rA, anyscaled);
+        inv_pair<EXT, INJ, RL>(st, j, lstart, nd, uA, rA, anyscaled);
         wait_scalar(uB.f.v[0]);
         __builtin_amdgcn_sched_barrier(0);
         const int j2 = min(j + 2, jend);
         inv_load_u(uA, fs, lco, m, as, Lp, L, j2);
         rA = inv_load_r(Rt, ne, j2);
         __builtin_amdgcn_sched_barrier(0);
-        inv_pair<EXT, INJ>(st, j + 1, lstart, nd, uB, rB, anyscaled);
+        inv_pair<EXT, INJ, RL>(st, j + 1, lstart, nd, uB, rB, anyscaled);
     }
 }
 
 // Pairs jfrom .. jlast of one segment (ascending); pairs <= jA (jA in
 // [jfrom-1, jlast]) contain chain starts.  Phase loops cover even pair counts; a
 // leftover pair is peeled.
-template <bool EXT>
+template <bool EXT, bool RL>
 __device__ __forceinline__ void inv_segment(InvLane<EXT>& st, int jfrom, int jA, int jlast, int jend, int lstart,
                                             int ne, double nd, int m, int as, int Lp, int L,
                                             const double* __restrict__ fs, const double2* __restrict__ lco,
@@ -673,22 +685,22 @@ __device__ __forceinline__ void inv_segment(InvLane<EXT>& st, int jfrom, int jA,
     if ((cntA & 1) && jA < jlast) { ++jA; ++cntA; }
     if (cntA > 0) {
         const int jlastA = (cntA & 1) ? jA - 1 : jA;
-        inv_phase<EXT, true>(st, jfrom, jlastA, jend, lstart, ne, nd, m, as, Lp, L, fs, lco, Rt, uA, uB, rA, rB,
+        inv_phase<EXT, true, RL>(st, jfrom, jlastA, jend, lstart, ne, nd, m, as, Lp, L, fs, lco, Rt, uA, uB, rA, rB,
                              anyscaled);
         if (cntA & 1) {             // jA = jlast, in A
             wait_scalar(uA.f.v[0]);
-            inv_pair<EXT, true>(st, jA, lstart, nd, uA, rA, anyscaled);
+            inv_pair<EXT, true, RL>(st, jA, lstart, nd, uA, rA, anyscaled);
             return;
         }
     }
     const int cntB = jlast - jA;    // pairs jA+1 .. jlast, A holds jA+1
     if (cntB > 0) {
         const int jlastB = (cntB & 1) ? jlast - 1 : jlast;
-        inv_phase<EXT, false>(st, jA + 1, jlastB, jend, lstart, ne, nd, m, as, Lp, L, fs, lco, Rt, uA, uB, rA, rB,
+        inv_phase<EXT, false, RL>(st, jA + 1, jlastB, jend, lstart, ne, nd, m, as, Lp, L, fs, lco, Rt, uA, uB, rA, rB,
                               anyscaled);
         if (cntB & 1) {
             wait_scalar(uA.f.v[0]);
-            inv_pair<EXT, false>(st, jlast, lstart, nd, uA, rA, anyscaled);
+            inv_pair<EXT, false, RL>(st, jlast, lstart, nd, uA, rA, anyscaled);
         }
     }
 }
@@ -797,7 +809,7 @@ __device__ __forceinline__ InvSeg inv_setup(InvLane<EXT>& st, bool& anyscaled, c
 
 // FP64 inverse contraction: one workgroup per chain group (64 orders n0.., one
 // order m).  Partial sums are added in LDS in segment order.
-template <bool EXT>
+template <bool EXT, bool RL>
 __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
     const double* __restrict__ fs0, size_t fstride, Batch B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
@@ -830,7 +842,7 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
     const InvSeg g = inv_setup<EXT>(st, anyscaled, geo, w, n, m, L, Lp, as, segi, edge, edgek, stab, stabk, cki,
                                     ckik, ckoff);
     if (g.active)
-        inv_segment<EXT>(st, g.jfrom, g.jA, g.jlast, jend, geo.lstart, ne, nd, m, as, Lp, L, fs, lco, Rt,
+        inv_segment<EXT, RL>(st, g.jfrom, g.jA, g.jlast, jend, geo.lstart, ne, nd, m, as, Lp, L, fs, lco, Rt,
                          anyscaled);
     if (nseg > 1) {
         if (w > 0 && w < nseg) {
@@ -853,7 +865,7 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
     const double fsm = sgn(s) * ((s < 0) ? sgn(n) : 1.0);
     double2 op = mul_ipow(st.ap, ((-(m + s)) % 4 + 4) % 4);
     F[(size_t)(L - 1 + m) * L + n] = make_double2(op.x * fsp, op.y * fsp);
-    if (m > 0) {
+    if (!RL && m > 0) {
         double2 om = mul_ipow(st.am, ((m - s) % 4 + 4) % 4);
         F[(size_t)(L - 1 - m) * L + n] = make_double2(om.x * fsm, om.y * fsm);
     }
@@ -1218,18 +1230,23 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse_mix(
 
 }  // namespace
 
-hipError_t launch_contract_forward(const Plan& p, int s, const double* in0, size_t stride, const Batch& B,
-                                   hipStream_t st)
+namespace {
+template <bool EXT, bool RL>
+hipError_t fwd_go(const Plan& p, int s, const double* in0, size_t stride, const Batch& B, hipStream_t st)
 {
     const dim3 grid(p.nworkf, B.n), block(64 * SEG_MAX);
     const size_t lds = (size_t)(2 * p.L + 8) * sizeof(double);
-    if (p.ext)
-        hipLaunchKernelGGL((k_contract_forward<MT_FWD, true>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek, p.cl,
-                           p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
-    else
-        hipLaunchKernelGGL((k_contract_forward<MT_FWD, false>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek,
-                           p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
+    hipLaunchKernelGGL((k_contract_forward<MT_FWD, EXT, RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge,
+                       p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_contract_forward(const Plan& p, int s, int real, const double* in0, size_t stride, const Batch& B,
+                                   hipStream_t st)
+{
+    if (p.ext) return real ? fwd_go<true, true>(p, s, in0, stride, B, st) : fwd_go<true, false>(p, s, in0, stride, B, st);
+    return real ? fwd_go<false, true>(p, s, in0, stride, B, st) : fwd_go<false, false>(p, s, in0, stride, B, st);
 }
 
 hipError_t launch_real_fold(int L, const Batch& B, hipStream_t st)
@@ -1247,20 +1264,27 @@ hipError_t launch_inverse_stream(const Plan& p, int s, int real, const Batch& B,
     return hipGetLastError();
 }
 
-hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, const double* in0, size_t stride,
-                                   const Batch& B, hipStream_t st)
+namespace {
+template <bool EXT, bool RL>
+hipError_t inv_go(const Plan& p, const SpinTable& sp, int s, const double* in0, size_t stride, const Batch& B,
+                  hipStream_t st)
 {
     CkOff off;
     for (int j = 0; j < SEG_MAX; ++j) off.off[j] = p.cki_off[j];
     const dim3 grid(p.nworki, B.n), block(64 * SEG_MAX);
     const size_t lds = (size_t)(2 * p.L + 8) * sizeof(double);
-    if (p.ext)
-        hipLaunchKernelGGL((k_contract_inverse<true>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek, p.lco,
-                           sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
-    else
-        hipLaunchKernelGGL((k_contract_inverse<false>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek, p.lco,
-                           sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
+    hipLaunchKernelGGL((k_contract_inverse<EXT, RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek,
+                       p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, int real, const double* in0,
+                                   size_t stride, const Batch& B, hipStream_t st)
+{
+    if (p.ext)
+        return real ? inv_go<true, true>(p, sp, s, in0, stride, B, st) : inv_go<true, false>(p, sp, s, in0, stride, B, st);
+    return real ? inv_go<false, true>(p, sp, s, in0, stride, B, st) : inv_go<false, false>(p, sp, s, in0, stride, B, st);
 }
 
 // ---- mixed precision launchers ------------------------------------------

@@ -328,7 +328,10 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
 // of sigma_+(n) H_{m,n} (m >= 0) and of sigma_-(n) H_{-m,n} (m <= 0), with the
 // parity split of the contraction folded in: sigma_+ = (-1)^n for s >= 0 and
 // sigma_- = (-1)^n for s < 0 (1 otherwise).
-template <int ADJ_INV, int OUT32>
+// HALF = 1 (real scalar maps, Sec. IV-G): only the orders m >= 0 run; the map
+// being real, G_{-m}(theta) = conj(G_m(theta)) and hence H_{-m,n} =
+// (-1)^{m+s} conj(H_{m,n}), which order m writes into the -m half of its row.
+template <int ADJ_INV, int OUT32, int HALF>
 __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
 {
     extern __shared__ double2 A[];
@@ -336,7 +339,7 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
     const double2* __restrict__ G = (const double2*)B.in[blockIdx.y];
     void* __restrict__ Hout = B.out[blockIdx.y];
     const int L = p.L, N1 = p.N1, N2 = p.N2;
-    const int mi = xcd_column(N1);
+    const int mi = HALF ? xcd_column(L) + (L - 1) : xcd_column(N1);
     if (mi >= N1) return;
     const int m = mi - (L - 1);
     const double sig = ((m + s) & 1) ? -1.0 : 1.0;
@@ -393,23 +396,26 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
             v = A[P(n)];
             if (n > 0) v = cadd(v, cscale(A[P(wrap - n)], sig));
         }
+        // the -m half: H_{-m,n} itself, or (-1)^{m+s} conj(H_{m,n}) for a real map
+        const double2 vm = HALF ? cscale(cconj(v), sig) : v;
+        const bool pos = m >= 0, neg = HALF || m <= 0;
         if (OUT32) {
             float* h = (float*)Hout + (size_t)am * 4 * p.Lp + n;
             const double par = (n & 1) ? -1.0 : 1.0;
-            if (m >= 0) {
+            if (pos) {
                 const double sg = (s >= 0) ? par : 1.0;
                 h[0] = (float)(sg * v.x);
                 h[(size_t)p.Lp] = (float)(sg * v.y);
             }
-            if (m <= 0) {
+            if (neg) {
                 const double sg = (s < 0) ? par : 1.0;
-                h[2 * (size_t)p.Lp] = (float)(sg * v.x);
-                h[3 * (size_t)p.Lp] = (float)(sg * v.y);
+                h[2 * (size_t)p.Lp] = (float)(sg * vm.x);
+                h[3 * (size_t)p.Lp] = (float)(sg * vm.y);
             }
         } else {
             double* rec = (double*)Hout + ((size_t)am * p.Lp + n) * 4;
-            if (m >= 0) { rec[0] = v.x; rec[1] = v.y; }
-            if (m <= 0) { rec[2] = v.x; rec[3] = v.y; }
+            if (pos) { rec[0] = v.x; rec[1] = v.y; }
+            if (neg) { rec[2] = vm.x; rec[3] = vm.y; }
         }
     }
 }
@@ -481,6 +487,9 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
 //   F_m(theta_t) = sum_{m'} F_{m m'} e^{i m' theta_t}, t < L only,
 // from the folded F[m + L-1][n] (n >= 0) with F_{m,-n} = (-1)^{m+s} F_{m,n}.
 // Output Ft[t][m + L-1].
+// HALF = 1 (real scalar maps): only the orders m >= 0 run; the inverse phi stage
+// takes F_{-m}(theta) = conj(F_m(theta)).
+template <int HALF>
 __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
 {
     extern __shared__ double2 A[];
@@ -488,7 +497,7 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
     const double2* __restrict__ F = (const double2*)B.in[blockIdx.y];
     double2* __restrict__ Ft = (double2*)B.out[blockIdx.y];
     const int L = p.L, N1 = p.N1, N2 = p.N2;
-    const int mi = xcd_column(N1);
+    const int mi = HALF ? xcd_column(L) + (L - 1) : xcd_column(N1);
     if (mi >= N1) return;
     const int m = mi - (L - 1);
     const double sig = ((m + s) & 1) ? -1.0 : 1.0;
@@ -521,7 +530,9 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
 
 // Inverse phi stage (Eq.(f_pfft)): f(t, p) = sc sum_m F_m(theta_t) e^{i m phi_p}, with
 // sc = 1 for the inverse transform and sc = 2pi/N1 for the adjoint of the forward
-// (whose phi step is the conjugate transpose of the forward's).  REAL stores Re f.
+// (whose phi step is the conjugate transpose of the forward's).  REAL = 1 stores
+// Re f; REAL = 2 (real scalar maps) reads the orders m >= 0 only, takes
+// F_{-m} = conj(F_m) and stores f, which is then real.
 template <int REAL>
 __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
 {
@@ -535,12 +546,15 @@ __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
             Pair2 v{make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
             if (j < N1) {
                 const int m = (j <= L - 1) ? j : j - N1;
-                v.a = Ft[(size_t)t * N1 + (m + L - 1)];
+                v.a = Ft[(size_t)t * N1 + ((REAL == 2 && m < 0 ? -m : m) + L - 1)];
                 v.b = p.chirp[j];
             }
             return v;
         },
-        [&](int j, const Pair2& v) { A[P(j)] = cmul(cconj(v.a), v.b); });
+        [&](int j, const Pair2& v) {
+            const bool neg = REAL == 2 && j > L - 1 && j < N1;     // order m = j - N1 < 0
+            A[P(j)] = cmul(neg ? v.a : cconj(v.a), v.b);            // conj(F_m), F_m = conj(F_{-m})
+        });
     bluestein_core(A, p);
     staged_loop(
         N1, [&](int k) { return p.chirp[k]; },
@@ -586,26 +600,28 @@ hipError_t launch_phi_forward(const Plan& p, const Batch& B, int real, double sc
 }
 
 namespace {
-template <int ADJ_INV, int OUT32>
+template <int ADJ_INV, int OUT32, int HALF>
 hipError_t theta_forward_go(const Plan& p, const Batch& B, hipStream_t st)
 {
     const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     hipError_t e;
-    if ((e = set_lds(k_theta_forward<ADJ_INV, OUT32>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_theta_forward<ADJ_INV, OUT32>), dim3(xcd_grid(p.N1), B.n), dim3(fft_threads(p)), lds, st,
-                       p, B);
+    if ((e = set_lds(k_theta_forward<ADJ_INV, OUT32, HALF>, lds)) != hipSuccess) return e;
+    const int cols = HALF ? p.L : p.N1;
+    hipLaunchKernelGGL((k_theta_forward<ADJ_INV, OUT32, HALF>), dim3(xcd_grid(cols), B.n), dim3(fft_threads(p)),
+                       lds, st, p, B);
     return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_theta_forward(const Plan& p, const Batch& B, int out32, hipStream_t st)
+hipError_t launch_theta_forward(const Plan& p, const Batch& B, int out32, int half, hipStream_t st)
 {
-    return out32 ? theta_forward_go<0, 1>(p, B, st) : theta_forward_go<0, 0>(p, B, st);
+    if (half) return out32 ? theta_forward_go<0, 1, 1>(p, B, st) : theta_forward_go<0, 0, 1>(p, B, st);
+    return out32 ? theta_forward_go<0, 1, 0>(p, B, st) : theta_forward_go<0, 0, 0>(p, B, st);
 }
 
 hipError_t launch_theta_inverse_adjoint(const Plan& p, const Batch& B, int out32, hipStream_t st)
 {
-    return out32 ? theta_forward_go<1, 1>(p, B, st) : theta_forward_go<1, 0>(p, B, st);
+    return out32 ? theta_forward_go<1, 1, 0>(p, B, st) : theta_forward_go<1, 0, 0>(p, B, st);
 }
 
 hipError_t launch_theta_forward_adjoint(const Plan& p, const Batch& B, hipStream_t st)
@@ -617,12 +633,17 @@ hipError_t launch_theta_forward_adjoint(const Plan& p, const Batch& B, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_theta_inverse(const Plan& p, const Batch& B, hipStream_t st)
+hipError_t launch_theta_inverse(const Plan& p, const Batch& B, int half, hipStream_t st)
 {
     const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     hipError_t e;
-    if ((e = set_lds(k_theta_inverse, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_theta_inverse, dim3(xcd_grid(p.N1), B.n), dim3(fft_threads(p)), lds, st, p, B);
+    if (half) {
+        if ((e = set_lds(k_theta_inverse<1>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_theta_inverse<1>, dim3(xcd_grid(p.L), B.n), dim3(fft_threads(p)), lds, st, p, B);
+    } else {
+        if ((e = set_lds(k_theta_inverse<0>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_theta_inverse<0>, dim3(xcd_grid(p.N1), B.n), dim3(fft_threads(p)), lds, st, p, B);
+    }
     return hipGetLastError();
 }
 
@@ -631,7 +652,10 @@ hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc
     const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     const dim3 grid(p.L, B.n);
     hipError_t e;
-    if (real) {
+    if (real == 2) {
+        if ((e = set_lds(k_phi_inverse<2>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_phi_inverse<2>, grid, dim3(fft_threads(p)), lds, st, p, B, sc);
+    } else if (real) {
         if ((e = set_lds(k_phi_inverse<1>, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_phi_inverse<1>, grid, dim3(fft_threads(p)), lds, st, p, B, sc);
     } else {

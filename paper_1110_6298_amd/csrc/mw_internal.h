@@ -108,21 +108,27 @@ hipError_t launch_phi_forward(const Plan& p, const Batch& B, int real, double sc
 // Forward theta stage.  Output: Hp records (Re H_{m,n}, Im H_{m,n}, Re H_{-m,n}, Im H_{-m,n})
 // at [(m * Lp + n) * 4], m < L, n < Lp (pad rows zero); with out32 = 1 FP32 H at
 // [(m*4 + comp)*Lp + n] with the parity signs folded (the mixed contraction's layout).
-hipError_t launch_theta_forward(const Plan& p, const Batch& B, int out32, hipStream_t st);
+// half = 1: real scalar maps, only the orders m >= 0 run (the -m halves by symmetry).
+hipError_t launch_theta_forward(const Plan& p, const Batch& B, int out32, int half, hipStream_t st);
 // Theta step of the adjoint of the inverse (same output layouts as launch_theta_forward).
 hipError_t launch_theta_inverse_adjoint(const Plan& p, const Batch& B, int out32, hipStream_t st);
 // Theta step of the adjoint of the forward: folded Y (N1 x L) -> Gt (L x N1).
 hipError_t launch_theta_forward_adjoint(const Plan& p, const Batch& B, hipStream_t st);
 // FP64 contractions: map k of the launch reads in0 + k*stride (doubles; the
-// chunk's workspace slots are equally spaced) and writes B.out[k].
-hipError_t launch_contract_forward(const Plan& p, int s, const double* in0, size_t stride, const Batch& B,
+// chunk's workspace slots are equally spaced) and writes B.out[k].  real = 1
+// (real scalar maps): the forward writes f_{l,-m} = (-1)^m conj(f_{l,m}) and the
+// inverse writes only the orders m >= 0 of F.
+hipError_t launch_contract_forward(const Plan& p, int s, int real, const double* in0, size_t stride, const Batch& B,
                                    hipStream_t st);
 // Inverse coefficient stream (L x Lp x 4 doubles, or FP32 at [(m*4+comp)*Lp + l]).
 hipError_t launch_inverse_stream(const Plan& p, int s, int real, const Batch& B, int out32, hipStream_t st);
-hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, const double* in0, size_t stride,
-                                   const Batch& B, hipStream_t st);
-hipError_t launch_theta_inverse(const Plan& p, const Batch& B, hipStream_t st);
+hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, int real, const double* in0,
+                                   size_t stride, const Batch& B, hipStream_t st);
+// half = 1: real scalar maps, only the orders m >= 0 (for launch_phi_inverse with real = 2).
+hipError_t launch_theta_inverse(const Plan& p, const Batch& B, int half, hipStream_t st);
 // sc: 1 for the inverse transform, 2 pi/N1 for the adjoint of the forward.
+// real: 0 complex output; 1 the real part of the full synthesis; 2 a real map
+// synthesised from the orders m >= 0 with F_{-m} = conj(F_m).
 hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc, hipStream_t st);
 // Adjoint of the real-map coefficient expansion: y_{l,m} += (-1)^m conj(y_{l,-m}),
 // y_{l,-m} = 0 for m > 0 (in place on the L^2 layout of B.out).
