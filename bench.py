@@ -37,11 +37,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def contraction_flops(L, s):
+def contraction_flops(L, s, real=False):
     """Algorithmic flops of one contraction launch: 4 per folded term (l, m, m'>=0)
     (complex H times the real product Delta*Delta), plus 5 per Wigner
-    eighth-wedge element 0 <= m <= m' <= l generated (one three-term step)."""
-    terms = sum((2 * l + 1) * (l + 1) for l in range(abs(s), L))
+    eighth-wedge element 0 <= m <= m' <= l generated (one three-term step).  A
+    real scalar map needs the orders m >= 0 only."""
+    terms = sum(((l + 1) if real else (2 * l + 1)) * (l + 1) for l in range(abs(s), L))
     wedge = sum((l + 1) * (l + 2) // 2 for l in range(L))
     return 4.0 * terms + 5.0 * wedge
 
@@ -118,6 +119,40 @@ def batched_workload(torch, mw, dev, steps, warmup, precision, graph=False):
     return ms, len(maps), err
 
 
+def large_workload(torch, mw, dev, steps, warmup):
+    """L = 2048, s = 0, one real map with C_l = (l+1)^-2 (seed 1004): round trips
+    in FP64 and FP32C, per-kernel durations and the contraction roofline."""
+    import mwsynth
+    w = mwsynth.workload_real_l2048()
+    L, flm_h = w["L"], w["flm"]
+    flm = torch.from_numpy(flm_h).to(dev)
+    out = {}
+    for name, prec in (("fp64", mw.FP64), ("fp32c", mw.FP32C)):
+        x = torch.empty((L, 2 * L - 1), dtype=torch.float64, device=dev)
+        back = torch.empty(L * L, dtype=torch.complex128, device=dev)
+        mw.prepare([L], [0], [1], precision=prec)
+
+        def step():
+            mw.inverse(flm, L, 0, reality=1, precision=prec, out=x)
+            mw.forward(x, L, 0, reality=1, precision=prec, out=back)
+
+        ms = time_steps(torch, step, steps, warmup)
+        pk = kernel_profile(mw, step, steps)
+        err = rel(back.cpu().numpy(), flm_h)
+        flops = contraction_flops(L, 0, real=True)
+        dom = "contract_forward" if pk.get("contract_forward", 0) >= pk.get("contract_inverse", 0) \
+            else "contract_inverse"
+        ach = flops / (pk[dom] * 1e-3)
+        out[name] = {"round_trips_per_s": 1e3 / ms, "ms_per_step": ms, "round_trip_rel_err": err,
+                     "kernels": {k: {"avg_us": 1e3 * v} for k, v in pk.items()}}
+        if prec == mw.FP64:
+            out[name]["roofline"] = {"kernel": dom, "bound": "alu", "achieved": ach / 1e12,
+                                     "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                                     "frac": ach / PEAK_FP64_VALU, "flops_per_launch": flops}
+    out["workload"] = "L=2048, s=0, one real map, C_l=(l+1)^-2, seed 1004; one step = inverse + forward"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +162,7 @@ def main():
     ap.add_argument("--spin", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-map batched workload")
+    ap.add_argument("--no-large", action="store_true", help="skip the L=2048 real-map workload")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle baseline sample (whole round trips)")
@@ -234,6 +270,9 @@ def main():
                                "coefficient symmetry (s=0 ones on the real path), f_lm ~ N(0,1)/(l+1), seed 1003; "
                                "one step = batched inverse + batched forward")
         result["batched"] = batched
+
+    if not args.no_large:
+        result["large_l2048"] = large_workload(torch, mw, dev, 5, 1)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -257,9 +257,11 @@ int build_plan(int L, Plan& p, std::string& err)
     }
     if ((rc = upload(th, &p.thtw, p.bytes, err))) return rc;
 
-    // chain segmentation (only where a chain is long relative to the parallelism)
+    // chain segmentation: SEG_MAX waves of a workgroup share each chain, the
+    // checkpoints at the boundaries (O(L^2) each, by the degree recursion or the
+    // row recursion in long double) restarting the later segments
     {
-        const int seg = (L <= 1024) ? 64 * std::max(1, (L + 64 * SEG_MAX - 1) / (64 * SEG_MAX)) : 0;
+        const int seg = 64 * std::max(1, (L + 64 * SEG_MAX - 1) / (64 * SEG_MAX));
         p.segf = p.segi = (seg > 0 && seg < L) ? seg : (L + 63) / 64 * 64 + 64;
         p.nsegf = p.nsegi = (p.segf < L) ? (L + p.segf - 1) / p.segf : 1;
         if (p.nsegf > SEG_MAX) { err = "segmentation exceeds SEG_MAX"; return -3; }
