@@ -375,14 +375,16 @@ __device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscale
 // MT orders mb..); wave w runs segment w of the row recursions.  Partial sums
 // are added in LDS in segment order.
 template <int MT, bool EXT, bool RL>
-__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
+__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(5))) void k_contract_forward(
     const double* __restrict__ Hp0, size_t hstride, Batch B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,
     const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int2* __restrict__ work, int L, int Lp,
     int s, int segf)
 {
-    __shared__ double2 red[SEG_MAX - 1][MT][4][64];
-    extern __shared__ double Rt[];   // copy of the 1/sqrt table (2L+8 entries)
+    // LDS: the 1/sqrt table (2L+8 entries) during the chains, then the partial
+    // sums of the lower segments, red[(w-1)][c][k][lane] (sized by the launcher)
+    extern __shared__ double Rt[];
+    double2* red = (double2*)Rt;
     const double* __restrict__ Hp = Hp0 + blockIdx.y * hstride;   // map blockIdx.y of the launch
     double2* __restrict__ flm = (double2*)B.out[blockIdx.y];
     const int grp = blockIdx.x;
@@ -403,13 +405,15 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
     const FwdSeg g = fwd_setup<MT, EXT>(st, anyscaled, w, l0, mb, l, L, as, segf, edge, edgek, ckf, ckfk);
     if (g.active) fwd_segment<MT, EXT, RL>(st, g.ktop, g.kA, g.klo, l, le, mb, as, Hp, Rt, Lp, L, anyscaled);
     if (jtop > 0) {
+        auto R = [&](int j, int c, int k) -> double2& { return red[(((j - 1) * MT + c) * 4 + k) * 64 + lane]; };
+        __syncthreads();                 // every wave is done with the 1/sqrt table
         if (w > 0 && w <= jtop) {
 #pragma unroll
             for (int c = 0; c < MT; ++c) {
-                red[w - 1][c][0][lane] = st.ap[c][0];
-                red[w - 1][c][1][lane] = st.ap[c][1];
-                red[w - 1][c][2][lane] = st.am[c][0];
-                red[w - 1][c][3][lane] = st.am[c][1];
+                R(w, c, 0) = st.ap[c][0];
+                R(w, c, 1) = st.ap[c][1];
+                R(w, c, 2) = st.am[c][0];
+                R(w, c, 3) = st.am[c][1];
             }
         }
         __syncthreads();
@@ -418,10 +422,10 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward(
 #pragma unroll
             for (int c = 0; c < MT; ++c) {
                 double2 v;
-                v = red[j - 1][c][0][lane]; st.ap[c][0].x += v.x; st.ap[c][0].y += v.y;
-                v = red[j - 1][c][1][lane]; st.ap[c][1].x += v.x; st.ap[c][1].y += v.y;
-                v = red[j - 1][c][2][lane]; st.am[c][0].x += v.x; st.am[c][0].y += v.y;
-                v = red[j - 1][c][3][lane]; st.am[c][1].x += v.x; st.am[c][1].y += v.y;
+                v = R(j, c, 0); st.ap[c][0].x += v.x; st.ap[c][0].y += v.y;
+                v = R(j, c, 1); st.ap[c][1].x += v.x; st.ap[c][1].y += v.y;
+                v = R(j, c, 2); st.am[c][0].x += v.x; st.am[c][0].y += v.y;
+                v = R(j, c, 3); st.am[c][1].x += v.x; st.am[c][1].y += v.y;
             }
         }
     } else if (w != 0) {
@@ -810,7 +814,7 @@ __device__ __forceinline__ InvSeg inv_setup(InvLane<EXT>& st, bool& anyscaled, c
 // FP64 inverse contraction: one workgroup per chain group (64 orders n0.., one
 // order m).  Partial sums are added in LDS in segment order.
 template <bool EXT, bool RL>
-__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse(
+__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(5))) void k_contract_inverse(
     const double* __restrict__ fs0, size_t fstride, Batch B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
     const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,
@@ -1235,7 +1239,8 @@ template <bool EXT, bool RL>
 hipError_t fwd_go(const Plan& p, int s, const double* in0, size_t stride, const Batch& B, hipStream_t st)
 {
     const dim3 grid(p.nworkf, B.n), block(64 * SEG_MAX);
-    const size_t lds = (size_t)(2 * p.L + 8) * sizeof(double);
+    const size_t red = (size_t)(SEG_MAX - 1) * MT_FWD * 4 * 64 * sizeof(double2);
+    const size_t lds = std::max((size_t)(2 * p.L + 8) * sizeof(double), red);
     hipLaunchKernelGGL((k_contract_forward<MT_FWD, EXT, RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge,
                        p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
     return hipGetLastError();
