@@ -26,9 +26,10 @@ __device__ __forceinline__ double2 mul_dir_i(double2 a)
     return DIR < 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
 }
 
-// LDS index with one pad slot per 16 entries: the stride-16 stores of a
-// radix-16 pass then fall on distinct banks.
-__device__ __forceinline__ int P(int i) { return i + (i >> 4); }
+// LDS index with one pad slot per RB entries (RB = the FFT's main radix): the
+// stride-RB stores of a main pass then fall on distinct banks.
+template <int RB>
+__device__ __forceinline__ int Pr(int i) { return i + i / RB; }
 
 // Block-wide loop over j = threadIdx.x + q*blockDim.x < n (n <= 16*blockDim.x):
 // the global loads ld(j) of eight consecutive q are all issued before any result
@@ -111,6 +112,23 @@ __device__ __forceinline__ void dft16(double2 (&v)[16])
     t = v[11]; v[11] = v[14]; v[14] = t;
 }
 
+// DFT of 8 values in registers as 2 x 4 (natural order in and out).
+template <int DIR>
+__device__ __forceinline__ void dft8(double2* v)
+{
+    double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    bf4<DIR>(e0, e1, e2, e3);
+    bf4<DIR>(o0, o1, o2, o3);
+    o1 = cmul(o1, w16<DIR, 2>());
+    o2 = cmul(o2, w16<DIR, 4>());
+    o3 = cmul(o3, w16<DIR, 6>());
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
 // u_t *= w^t for t = 1..15, each power formed from w, w^2, w^4, w^8 (bits of t),
 // i.e. a product of at most four factors.
 template <int R>
@@ -131,24 +149,24 @@ __device__ __forceinline__ void twiddle_powers(double2* u, double2 w)
     }
 }
 
-// Final Stockham pass of radix R = 2, 4 or 8 (the factor left after the radix-16
-// passes): each thread holds up to 16/R butterflies in one 16-value register set.
-// With post != nullptr every output X_j is stored as X_j * post[j].
-template <int DIR, int R>
+// Final Stockham pass of radix R = 2, 4 or 8 (the factor left after the main
+// radix-RB passes): each thread holds RB/R butterflies in one RB-value register
+// set.  With post != nullptr every output X_j is stored as X_j * post[j].
+template <int DIR, int R, int RB>
 __device__ __forceinline__ void last_pass(double2* x, int N, int p, const double2 (&wl)[8],
                                           const double2* __restrict__ post)
 {
     constexpr int r = (R == 2) ? 1 : (R == 4) ? 2 : 3;
-    constexpr int QM = 16 / R;
+    constexpr int QM = RB / R;
     const int NB = N >> r;
-    double2 u[16];
+    double2 u[RB];
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
         const int i = threadIdx.x + q * blockDim.x;
         if (i < NB) {
             const int k = i & (p - 1);
 #pragma unroll
-            for (int t = 0; t < R; ++t) u[q * R + t] = x[P(i + t * NB)];
+            for (int t = 0; t < R; ++t) u[q * R + t] = x[Pr<RB>(i + t * NB)];
             double2 w = wl[q];
             if (DIR > 0) w = cconj(w);
             (void)k;
@@ -160,18 +178,7 @@ __device__ __forceinline__ void last_pass(double2* x, int N, int p, const double
             } else if (R == 4) {
                 bf4<DIR>(v[0], v[1], v[2], v[3]);
             } else {
-                // radix 8 = 2 x 4: DFT4 of even and odd inputs, twiddle w8^c, combine
-                double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
-                double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
-                bf4<DIR>(e0, e1, e2, e3);
-                bf4<DIR>(o0, o1, o2, o3);
-                o1 = cmul(o1, w16<DIR, 2>());
-                o2 = cmul(o2, w16<DIR, 4>());
-                o3 = cmul(o3, w16<DIR, 6>());
-                v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
-                v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
-                v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
-                v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+                dft8<DIR>(v);
             }
         }
     }
@@ -184,10 +191,10 @@ __device__ __forceinline__ void last_pass(double2* x, int N, int p, const double
             const int j = ((i - k) << r) + k;
             if (post) {
 #pragma unroll
-                for (int t = 0; t < R; ++t) x[P(j + t * p)] = cmul(u[q * R + t], post[j + t * p]);
+                for (int t = 0; t < R; ++t) x[Pr<RB>(j + t * p)] = cmul(u[q * R + t], post[j + t * p]);
             } else {
 #pragma unroll
-                for (int t = 0; t < R; ++t) x[P(j + t * p)] = u[q * R + t];
+                for (int t = 0; t < R; ++t) x[Pr<RB>(j + t * p)] = u[q * R + t];
             }
         }
     }
@@ -195,80 +202,81 @@ __device__ __forceinline__ void last_pass(double2* x, int N, int p, const double
 }
 
 // Block-wide in-place FFT of length N = 2^logN (16 <= N <= 8192) held in LDS
-// at padded positions P(j): Stockham radix-16 passes, one butterfly per thread
-// in registers, then one radix-2/4/8 pass for the remaining factor.  Needs
-// blockDim.x >= N/16.
+// at padded positions Pr<RB>(j): Stockham passes of radix RB (16 or 8), one
+// butterfly per thread in registers, then one radix-2/4/8 pass for the
+// remaining factor.  Needs blockDim.x >= N/RB.
 //   DIR = -1:  X_j = sum_k x_k exp(-2 pi i j k / N)
 //   DIR = +1:  X_j = sum_k x_k exp(+2 pi i j k / N)   (no 1/N)
 // tw[e] = exp(-2 pi i e / N).  With post != nullptr the result is X_j * post[j].
-template <int DIR>
+template <int DIR, int RB>
 __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const double2* __restrict__ tw,
                                           const double2* __restrict__ post = nullptr)
 {
+    constexpr int lr = (RB == 16) ? 4 : 3;
     const int i = threadIdx.x;
-    const int n16 = logN >> 2;       // radix-16 passes (at most 3 for N <= 8192)
-    const int r = logN - 4 * n16;    // final radix 2^r, none when r = 0
-    // every twiddle base this thread needs, loaded together before the first pass
-    double2 w16p[3], wl[8];
-    {
-        int p = 1, logp = 0;
+    const int np = logN / lr;        // main passes (at most 4 for N <= 8192)
+    const int r = logN - lr * np;    // final radix 2^r, none when r = 0
+    int p = 1, logp = 0;
+    __syncthreads();
 #pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            w16p[s] = make_double2(1.0, 0.0);
-            if (s < n16) {
-                if (i < (N >> 4)) w16p[s] = tw[(i & (p - 1)) << (logN - logp - 4)];
-                p <<= 4;
-                logp += 4;
+    for (int s = 0; s < 4; ++s) {
+        if (s >= np) break;
+        const int NB = N >> lr;
+        double2 u[RB];
+        const int k = i & (p - 1);
+        if (i < NB) {
+#pragma unroll
+            for (int t = 0; t < RB; ++t) u[t] = x[Pr<RB>(i + t * NB)];
+            if (s > 0) {   // the first pass has k = 0: no twiddles
+                double2 w = tw[k << (logN - logp - lr)];
+                if (DIR > 0) w = cconj(w);
+                twiddle_powers<RB>(u, w);
             }
+            if constexpr (RB == 16) dft16<DIR>(u);
+            else dft8<DIR>(u);
         }
+        __syncthreads();
+        if (i < NB) {
+            const int j = ((i - k) << lr) + k;
+#pragma unroll
+            for (int t = 0; t < RB; ++t) x[Pr<RB>(j + t * p)] = u[t];
+        }
+        p <<= lr;
+        logp += lr;
+        __syncthreads();
+    }
+    double2 wl[8];   // twiddle bases of the final pass
+    {
         const int NB = r ? (N >> r) : 0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int iq = i + q * blockDim.x;
             wl[q] = make_double2(1.0, 0.0);
-            if (r && q < (16 >> r) && iq < NB) wl[q] = tw[(iq & (p - 1)) << (logN - logp - r)];
+            if (r && q < (RB >> r) && iq < NB) wl[q] = tw[(iq & (p - 1)) << (logN - logp - r)];
         }
     }
-    int p = 1;
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-        if (s >= n16) break;
-        const int NB = N >> 4;
-        double2 u[16];
-        const int k = i & (p - 1);
-        if (i < NB) {
-#pragma unroll
-            for (int t = 0; t < 16; ++t) u[t] = x[P(i + t * NB)];
-            double2 w = w16p[s];
-            if (DIR > 0) w = cconj(w);
-            twiddle_powers<16>(u, w);
-            dft16<DIR>(u);
+    if (r == 1) last_pass<DIR, 2, RB>(x, N, p, wl, post);
+    else if (r == 2) last_pass<DIR, 4, RB>(x, N, p, wl, post);
+    else if constexpr (RB == 16) {
+        if (r == 3) last_pass<DIR, 8, RB>(x, N, p, wl, post);
+        else if (post) {
+            for (int j = threadIdx.x; j < N; j += blockDim.x) x[Pr<RB>(j)] = cmul(x[Pr<RB>(j)], post[j]);
+            __syncthreads();
         }
-        __syncthreads();
-        if (i < NB) {
-            const int j = ((i - k) << 4) + k;
-#pragma unroll
-            for (int t = 0; t < 16; ++t) x[P(j + t * p)] = u[t];
-        }
-        p <<= 4;
-        __syncthreads();
     }
-    if (r == 1) last_pass<DIR, 2>(x, N, p, wl, post);
-    else if (r == 2) last_pass<DIR, 4>(x, N, p, wl, post);
-    else if (r == 3) last_pass<DIR, 8>(x, N, p, wl, post);
     else if (post) {
-        for (int j = threadIdx.x; j < N; j += blockDim.x) x[P(j)] = cmul(x[P(j)], post[j]);
+        for (int j = threadIdx.x; j < N; j += blockDim.x) x[Pr<RB>(j)] = cmul(x[Pr<RB>(j)], post[j]);
         __syncthreads();
     }
 }
 
 // Bluestein DFT of length N1 of the chirped, zero-padded sequence a_j already in
 // x[P(j)], j < N2: on return x[P(k)] * chirp[k] = sum_j a_j exp(-2 pi i j k / N1), k < N1.
+template <int RB>
 __device__ __forceinline__ void bluestein_core(double2* x, const Plan& p)
 {
-    block_fft<-1>(x, p.N2, p.logN2, p.tw, p.bhat);
-    block_fft<+1>(x, p.N2, p.logN2, p.tw);
+    block_fft<-1, RB>(x, p.N2, p.logN2, p.tw, p.bhat);
+    block_fft<+1, RB>(x, p.N2, p.logN2, p.tw);
 }
 
 // XCD-aware column index: consecutive workgroups are dealt round-robin over the
@@ -285,7 +293,7 @@ __device__ __forceinline__ int xcd_column(int ncol)
 // Forward phi stage (Sec. IV-D): G_m(theta_t) = sc sum_p f(t, p) e^{-i m phi_p}, with
 // sc = 2pi/N1 for the forward transform and sc = 1 for the adjoint of the inverse.
 // Output G[t][m + L-1].
-template <int REAL>
+template <int REAL, int RB>
 __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
 {
     extern __shared__ double2 A[];
@@ -303,13 +311,13 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
             }
             return v;
         },
-        [&](int j, const Pair2& v) { A[P(j)] = cmul(v.a, v.b); });
-    bluestein_core(A, p);
+        [&](int j, const Pair2& v) { A[Pr<RB>(j)] = cmul(v.a, v.b); });
+    bluestein_core<RB>(A, p);
     staged_loop(
         N1, [&](int k) { return p.chirp[k]; },
         [&](int k, double2 c) {
             const int m = (k <= L - 1) ? k : k - N1;
-            G[(size_t)t * N1 + (m + L - 1)] = cscale(cmul(A[P(k)], c), sc);
+            G[(size_t)t * N1 + (m + L - 1)] = cscale(cmul(A[Pr<RB>(k)], c), sc);
         });
 }
 
@@ -331,7 +339,7 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
 // HALF = 1 (real scalar maps, Sec. IV-G): only the orders m >= 0 run; the map
 // being real, G_{-m}(theta) = conj(G_m(theta)) and hence H_{-m,n} =
 // (-1)^{m+s} conj(H_{m,n}), which order m writes into the -m half of its row.
-template <int ADJ_INV, int OUT32, int HALF>
+template <int ADJ_INV, int OUT32, int HALF, int RB>
 __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
 {
     extern __shared__ double2 A[];
@@ -354,15 +362,15 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
             }
             return v;
         },
-        [&](int j, const Pair2& v) { A[P(j)] = cmul((j < L) ? v.a : cscale(v.a, sig), v.b); });
-    bluestein_core(A, p);
+        [&](int j, const Pair2& v) { A[Pr<RB>(j)] = cmul((j < L) ? v.a : cscale(v.a, sig), v.b); });
+    bluestein_core<RB>(A, p);
     // F_{m'} into registers (N1 <= N2/2 <= 8 * blockDim.x), then scatter to slot m' mod N2.
     double2 r[8];
     const double unscale = ADJ_INV ? 2.0 * 3.14159265358979323846 * (double)N1 : 1.0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int k = threadIdx.x + q * blockDim.x;
-        if (k < N1) r[q] = cscale(cmul(cmul(A[P(k)], p.chirp[k]), p.thtw[k]), unscale);
+        if (k < N1) r[q] = cscale(cmul(cmul(A[Pr<RB>(k)], p.chirp[k]), p.thtw[k]), unscale);
     }
     __syncthreads();
     int wrap;   // index of -n is wrap - n
@@ -370,31 +378,31 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int k = threadIdx.x + q * blockDim.x;
-            if (k < N1) A[P(k)] = r[q];
+            if (k < N1) A[Pr<RB>(k)] = r[q];
         }
         __syncthreads();
         wrap = N1;
     } else {
-        for (int j = threadIdx.x; j < N2; j += blockDim.x) A[P(j)] = make_double2(0.0, 0.0);
+        for (int j = threadIdx.x; j < N2; j += blockDim.x) A[Pr<RB>(j)] = make_double2(0.0, 0.0);
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int k = threadIdx.x + q * blockDim.x;
             if (k < N1) {
                 const int mp = (k <= L - 1) ? k : k - N1;
-                A[P((mp + N2) & (N2 - 1))] = r[q];
+                A[Pr<RB>((mp + N2) & (N2 - 1))] = r[q];
             }
         }
-        block_fft<+1>(A, N2, p.logN2, p.tw, p.what);
-        block_fft<-1>(A, N2, p.logN2, p.tw);
+        block_fft<+1, RB>(A, N2, p.logN2, p.tw, p.what);
+        block_fft<-1, RB>(A, N2, p.logN2, p.tw);
         wrap = N2;
     }
     const int am = m < 0 ? -m : m;
     for (int n = threadIdx.x; n < p.Lp; n += blockDim.x) {
         double2 v = make_double2(0.0, 0.0);
         if (n < L) {
-            v = A[P(n)];
-            if (n > 0) v = cadd(v, cscale(A[P(wrap - n)], sig));
+            v = A[Pr<RB>(n)];
+            if (n > 0) v = cadd(v, cscale(A[Pr<RB>(wrap - n)], sig));
         }
         // the -m half: H_{-m,n} itself, or (-1)^{m+s} conj(H_{m,n}) for a real map
         const double2 vm = HALF ? cscale(cconj(v), sig) : v;
@@ -429,6 +437,7 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
 //   fold     G_m(theta_t) = Gext(theta_t) + (-1)^{m+s} Gext(theta_{2L-2-t}), t < L-1;
 //            G_m(theta_{L-1}) = Gext(theta_{L-1})
 // Output G[t][m + L-1] (the layout the inverse phi stage reads).
+template <int RB>
 __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
 {
     extern __shared__ double2 A[];
@@ -440,7 +449,7 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
     if (mi >= N1) return;
     const int m = mi - (L - 1);
     const double sig = ((m + s) & 1) ? -1.0 : 1.0;
-    for (int j = threadIdx.x; j < N2; j += blockDim.x) A[P(j)] = make_double2(0.0, 0.0);
+    for (int j = threadIdx.x; j < N2; j += blockDim.x) A[Pr<RB>(j)] = make_double2(0.0, 0.0);
     __syncthreads();
     staged_loop(
         N1,
@@ -450,10 +459,10 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
         },
         [&](int k, double2 y) {
             const int mp = (k <= L - 1) ? k : k - N1;
-            A[P((mp + N2) & (N2 - 1))] = (mp < 0) ? cscale(y, sig) : y;
+            A[Pr<RB>((mp + N2) & (N2 - 1))] = (mp < 0) ? cscale(y, sig) : y;
         });
-    block_fft<+1>(A, N2, p.logN2, p.tw, p.whatc);
-    block_fft<-1>(A, N2, p.logN2, p.tw);
+    block_fft<+1, RB>(A, N2, p.logN2, p.tw, p.whatc);
+    block_fft<-1, RB>(A, N2, p.logN2, p.tw);
     // Z_{m''} e^{+i m'' pi/N1}/(2 pi N1) = Z conj(thtw), conjugated and chirped for the
     // Bluestein evaluation of the positive-exponent DFT
     double2 r[8];
@@ -462,7 +471,7 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
         const int k = threadIdx.x + q * blockDim.x;
         if (k < N1) {
             const int mp = (k <= L - 1) ? k : k - N1;
-            const double2 y = cmul(A[P((mp + N2) & (N2 - 1))], cconj(p.thtw[k]));
+            const double2 y = cmul(A[Pr<RB>((mp + N2) & (N2 - 1))], cconj(p.thtw[k]));
             r[q] = cmul(cconj(y), p.chirp[k]);
         }
     }
@@ -470,15 +479,15 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int k = threadIdx.x + q * blockDim.x;
-        if (k < N2) A[P(k)] = (k < N1) ? r[q] : make_double2(0.0, 0.0);
+        if (k < N2) A[Pr<RB>(k)] = (k < N1) ? r[q] : make_double2(0.0, 0.0);
     }
-    for (int j = threadIdx.x + 8 * blockDim.x; j < N2; j += blockDim.x) A[P(j)] = make_double2(0.0, 0.0);
-    bluestein_core(A, p);
+    for (int j = threadIdx.x + 8 * blockDim.x; j < N2; j += blockDim.x) A[Pr<RB>(j)] = make_double2(0.0, 0.0);
+    bluestein_core<RB>(A, p);
     staged_loop(
         L, [&](int t) { return Pair2{p.chirp[t], p.chirp[2 * L - 2 - t]}; },
         [&](int t, const Pair2& c) {
-            double2 v = cconj(cmul(A[P(t)], c.a));
-            if (t <= L - 2) v = cadd(v, cscale(cconj(cmul(A[P(2 * L - 2 - t)], c.b)), sig));
+            double2 v = cconj(cmul(A[Pr<RB>(t)], c.a));
+            if (t <= L - 2) v = cadd(v, cscale(cconj(cmul(A[Pr<RB>(2 * L - 2 - t)], c.b)), sig));
             Gt[(size_t)t * N1 + mi] = v;
         });
 }
@@ -489,7 +498,7 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
 // Output Ft[t][m + L-1].
 // HALF = 1 (real scalar maps): only the orders m >= 0 run; the inverse phi stage
 // takes F_{-m}(theta) = conj(F_m(theta)).
-template <int HALF>
+template <int HALF, int RB>
 __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
 {
     extern __shared__ double2 A[];
@@ -520,12 +529,12 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
             const double2 f = (mp < 0) ? cscale(v.f, sig) : v.f;
             // y = f e^{+i m' pi/N1};  conj(thtw) * 2 pi N1 = e^{+i m' pi/N1}
             const double2 y = cmul(f, cscale(cconj(v.w), unscale));
-            A[P(j)] = cmul(cconj(y), v.c);
+            A[Pr<RB>(j)] = cmul(cconj(y), v.c);
         });
-    bluestein_core(A, p);
+    bluestein_core<RB>(A, p);
     staged_loop(
         L, [&](int t) { return p.chirp[t]; },
-        [&](int t, double2 c) { Ft[(size_t)t * N1 + mi] = cconj(cmul(A[P(t)], c)); });
+        [&](int t, double2 c) { Ft[(size_t)t * N1 + mi] = cconj(cmul(A[Pr<RB>(t)], c)); });
 }
 
 // Inverse phi stage (Eq.(f_pfft)): f(t, p) = sc sum_m F_m(theta_t) e^{i m phi_p}, with
@@ -533,7 +542,7 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
 // (whose phi step is the conjugate transpose of the forward's).  REAL = 1 stores
 // Re f; REAL = 2 (real scalar maps) reads the orders m >= 0 only, takes
 // F_{-m} = conj(F_m) and stores f, which is then real.
-template <int REAL>
+template <int REAL, int RB>
 __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
 {
     extern __shared__ double2 A[];
@@ -553,25 +562,38 @@ __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
         },
         [&](int j, const Pair2& v) {
             const bool neg = REAL == 2 && j > L - 1 && j < N1;     // order m = j - N1 < 0
-            A[P(j)] = cmul(neg ? v.a : cconj(v.a), v.b);            // conj(F_m), F_m = conj(F_{-m})
+            A[Pr<RB>(j)] = cmul(neg ? v.a : cconj(v.a), v.b);            // conj(F_m), F_m = conj(F_{-m})
         });
-    bluestein_core(A, p);
+    bluestein_core<RB>(A, p);
     staged_loop(
         N1, [&](int k) { return p.chirp[k]; },
         [&](int k, double2 c) {
-            const double2 out = cscale(cconj(cmul(A[P(k)], c)), sc);
+            const double2 out = cscale(cconj(cmul(A[Pr<RB>(k)], c)), sc);
             if (REAL) ((double*)map)[(size_t)t * N1 + k] = out.x;
             else ((double2*)map)[(size_t)t * N1 + k] = out;
         });
 }
 
-int fft_threads(const Plan& p)
+// Main radix of the FFTs for a plan.  It depends on the band-limit only, so a
+// map's result does not depend on the batch it runs in.  Radix 8 runs twice the
+// threads per transform of radix 16 for the same work; both keep a workgroup
+// within the kernels' 512-thread launch bound (radix 8 up to N2 = 4096).
+int fft_radix(const Plan& p, long nblocks)
 {
-    int t = p.N2 / 16;
+    (void)nblocks;
+    return (p.N2 / 8 <= 512) ? 8 : 16;
+}
+
+// Threads per FFT workgroup: one main-pass butterfly each (N2/rb <= 512, the
+// kernels' launch bound), at least one wavefront.
+int fft_threads(const Plan& p, int rb)
+{
+    int t = p.N2 / rb;
     if (t < 64) t = 64;
-    if (t > 1024) t = 1024;
     return t;
 }
+
+size_t fft_lds(const Plan& p, int rb) { return (size_t)(p.N2 + p.N2 / rb) * sizeof(double2); }
 
 template <class K>
 hipError_t set_lds(K kernel, size_t bytes)
@@ -582,87 +604,74 @@ hipError_t set_lds(K kernel, size_t bytes)
 
 int xcd_grid(int ncol) { return 8 * ((ncol + 7) >> 3); }
 
+// Launches kernel K<RB> with the radix chosen for this grid.
+template <template <int> class KS, class... Args>
+hipError_t fft_launch(const Plan& p, dim3 grid, hipStream_t st, Args... args)
+{
+    const int rb = fft_radix(p, (long)grid.x * grid.y);
+    hipError_t e;
+    if (rb == 16) {
+        auto k = KS<16>::fn();
+        if ((e = set_lds(k, fft_lds(p, 16))) != hipSuccess) return e;
+        hipLaunchKernelGGL(k, grid, dim3(fft_threads(p, 16)), fft_lds(p, 16), st, args...);
+    } else {
+        auto k = KS<8>::fn();
+        if ((e = set_lds(k, fft_lds(p, 8))) != hipSuccess) return e;
+        hipLaunchKernelGGL(k, grid, dim3(fft_threads(p, 8)), fft_lds(p, 8), st, args...);
+    }
+    return hipGetLastError();
+}
+
+template <int REAL> struct PhiF { template <int RB> struct K { static auto fn() { return k_phi_forward<REAL, RB>; } }; };
+template <int REAL> struct PhiI { template <int RB> struct K { static auto fn() { return k_phi_inverse<REAL, RB>; } }; };
+template <int A, int O, int H> struct ThF { template <int RB> struct K { static auto fn() { return k_theta_forward<A, O, H, RB>; } }; };
+template <int H> struct ThI { template <int RB> struct K { static auto fn() { return k_theta_inverse<H, RB>; } }; };
+template <int RB> struct ThFA { static auto fn() { return k_theta_forward_adjoint<RB>; } };
+
 }  // namespace
 
 hipError_t launch_phi_forward(const Plan& p, const Batch& B, int real, double sc, hipStream_t st)
 {
-    const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     const dim3 grid(p.L, B.n);
-    hipError_t e;
-    if (real) {
-        if ((e = set_lds(k_phi_forward<1>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_phi_forward<1>, grid, dim3(fft_threads(p)), lds, st, p, B, sc);
-    } else {
-        if ((e = set_lds(k_phi_forward<0>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_phi_forward<0>, grid, dim3(fft_threads(p)), lds, st, p, B, sc);
-    }
-    return hipGetLastError();
+    if (real) return fft_launch<PhiF<1>::K>(p, grid, st, p, B, sc);
+    return fft_launch<PhiF<0>::K>(p, grid, st, p, B, sc);
 }
-
-namespace {
-template <int ADJ_INV, int OUT32, int HALF>
-hipError_t theta_forward_go(const Plan& p, const Batch& B, hipStream_t st)
-{
-    const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
-    hipError_t e;
-    if ((e = set_lds(k_theta_forward<ADJ_INV, OUT32, HALF>, lds)) != hipSuccess) return e;
-    const int cols = HALF ? p.L : p.N1;
-    hipLaunchKernelGGL((k_theta_forward<ADJ_INV, OUT32, HALF>), dim3(xcd_grid(cols), B.n), dim3(fft_threads(p)),
-                       lds, st, p, B);
-    return hipGetLastError();
-}
-}  // namespace
 
 hipError_t launch_theta_forward(const Plan& p, const Batch& B, int out32, int half, hipStream_t st)
 {
-    if (half) return out32 ? theta_forward_go<0, 1, 1>(p, B, st) : theta_forward_go<0, 0, 1>(p, B, st);
-    return out32 ? theta_forward_go<0, 1, 0>(p, B, st) : theta_forward_go<0, 0, 0>(p, B, st);
+    const dim3 grid(xcd_grid(half ? p.L : p.N1), B.n);
+    if (half) {
+        if (out32) return fft_launch<ThF<0, 1, 1>::K>(p, grid, st, p, B);
+        return fft_launch<ThF<0, 0, 1>::K>(p, grid, st, p, B);
+    }
+    if (out32) return fft_launch<ThF<0, 1, 0>::K>(p, grid, st, p, B);
+    return fft_launch<ThF<0, 0, 0>::K>(p, grid, st, p, B);
 }
 
 hipError_t launch_theta_inverse_adjoint(const Plan& p, const Batch& B, int out32, hipStream_t st)
 {
-    return out32 ? theta_forward_go<1, 1, 0>(p, B, st) : theta_forward_go<1, 0, 0>(p, B, st);
+    const dim3 grid(xcd_grid(p.N1), B.n);
+    if (out32) return fft_launch<ThF<1, 1, 0>::K>(p, grid, st, p, B);
+    return fft_launch<ThF<1, 0, 0>::K>(p, grid, st, p, B);
 }
 
 hipError_t launch_theta_forward_adjoint(const Plan& p, const Batch& B, hipStream_t st)
 {
-    const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
-    hipError_t e;
-    if ((e = set_lds(k_theta_forward_adjoint, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_theta_forward_adjoint, dim3(xcd_grid(p.N1), B.n), dim3(fft_threads(p)), lds, st, p, B);
-    return hipGetLastError();
+    return fft_launch<ThFA>(p, dim3(xcd_grid(p.N1), B.n), st, p, B);
 }
 
 hipError_t launch_theta_inverse(const Plan& p, const Batch& B, int half, hipStream_t st)
 {
-    const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
-    hipError_t e;
-    if (half) {
-        if ((e = set_lds(k_theta_inverse<1>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_theta_inverse<1>, dim3(xcd_grid(p.L), B.n), dim3(fft_threads(p)), lds, st, p, B);
-    } else {
-        if ((e = set_lds(k_theta_inverse<0>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_theta_inverse<0>, dim3(xcd_grid(p.N1), B.n), dim3(fft_threads(p)), lds, st, p, B);
-    }
-    return hipGetLastError();
+    if (half) return fft_launch<ThI<1>::K>(p, dim3(xcd_grid(p.L), B.n), st, p, B);
+    return fft_launch<ThI<0>::K>(p, dim3(xcd_grid(p.N1), B.n), st, p, B);
 }
 
 hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc, hipStream_t st)
 {
-    const size_t lds = (size_t)(p.N2 + p.N2 / 16) * sizeof(double2);
     const dim3 grid(p.L, B.n);
-    hipError_t e;
-    if (real == 2) {
-        if ((e = set_lds(k_phi_inverse<2>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_phi_inverse<2>, grid, dim3(fft_threads(p)), lds, st, p, B, sc);
-    } else if (real) {
-        if ((e = set_lds(k_phi_inverse<1>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_phi_inverse<1>, grid, dim3(fft_threads(p)), lds, st, p, B, sc);
-    } else {
-        if ((e = set_lds(k_phi_inverse<0>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_phi_inverse<0>, grid, dim3(fft_threads(p)), lds, st, p, B, sc);
-    }
-    return hipGetLastError();
+    if (real == 2) return fft_launch<PhiI<2>::K>(p, grid, st, p, B, sc);
+    if (real) return fft_launch<PhiI<1>::K>(p, grid, st, p, B, sc);
+    return fft_launch<PhiI<0>::K>(p, grid, st, p, B, sc);
 }
 
 }  // namespace mw
