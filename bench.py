@@ -20,11 +20,11 @@ PEAK_FP64_VALU = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 
 # HBM traffic of the contraction kernels per launch at L=512 s=2, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters
-# read for a plain copy of known size (profiles/traffic_roundtrip_L512_s2_fp64.md).
+# read for a plain copy of known size (profiles/traffic_roundtrip_L512_s2.md).
 # Valid only while the kernel and plan sources are unchanged: keyed by their SHA-256.
 TRAFFIC = {
-    ("contract_inverse", 512, 2): {"bytes": 58307655, "source_sha256": "009620d6f95546ad19215ddd224347936349e869eac96de622133808e0bbde83"},
-    ("contract_forward", 512, 2): {"bytes": 52361573, "source_sha256": "009620d6f95546ad19215ddd224347936349e869eac96de622133808e0bbde83"},
+    ("contract_inverse", 512, 2): {"bytes": 85378199, "source_sha256": "7d87655d2323e857de90d5dfcdfdc59fcd25d389657dfd09c9a66e6335358169"},
+    ("contract_forward", 512, 2): {"bytes": 60644449, "source_sha256": "7d87655d2323e857de90d5dfcdfdc59fcd25d389657dfd09c9a66e6335358169"},
 }
 KERNEL_SOURCES = ("paper_1110_6298_amd/csrc/mw_contract.hip", "paper_1110_6298_amd/csrc/mw_plan.cpp")
 
