@@ -814,8 +814,8 @@ __device__ __forceinline__ InvSeg inv_setup(InvLane<EXT>& st, bool& anyscaled, c
 // FP64 inverse contraction: one workgroup per chain group (64 orders n0.., one
 // order m).  Partial sums are added in LDS in segment order.
 template <bool EXT, bool RL>
-__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(5))) void k_contract_inverse(
-    const double* __restrict__ fs0, size_t fstride, Batch B, const double* __restrict__ Rtg,
+__device__ __forceinline__ void contract_inverse_body(
+    const double* __restrict__ fs0, size_t fstride, const Batch& B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
     const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,
     const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work, int L, int Lp, int s, int segi,
@@ -874,6 +874,32 @@ __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(5)
         F[(size_t)(L - 1 - m) * L + n] = make_double2(om.x * fsm, om.y * fsm);
     }
 }
+
+// The plain variant fits six waves per SIMD without spills in its loops; the
+// exponent-extended one (large band-limits) keeps five.
+#define MW_INVERSE_ARGS                                                                                          \
+    const double* __restrict__ fs0, size_t fstride, Batch B, const double* __restrict__ Rtg,                    \
+        const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,         \
+        const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,        \
+        const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work, int L, int Lp, int s,         \
+        int segi, int nsegi
+#define MW_INVERSE_PASS fs0, fstride, B, Rtg, edge, edgek, lco, stab, stabk, cki, ckik, ckoff, work, L, Lp, s, segi, nsegi
+
+template <bool RL>
+__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(6))) void k_contract_inverse(
+    MW_INVERSE_ARGS)
+{
+    contract_inverse_body<false, RL>(MW_INVERSE_PASS);
+}
+
+template <bool RL>
+__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(5))) void k_contract_inverse_ext(
+    MW_INVERSE_ARGS)
+{
+    contract_inverse_body<true, RL>(MW_INVERSE_PASS);
+}
+#undef MW_INVERSE_ARGS
+#undef MW_INVERSE_PASS
 
 // ===========================================================================
 // Mixed precision (MW_FP32C): the same FP64 chains; each step's products
@@ -1278,8 +1304,12 @@ hipError_t inv_go(const Plan& p, const SpinTable& sp, int s, const double* in0, 
     for (int j = 0; j < SEG_MAX; ++j) off.off[j] = p.cki_off[j];
     const dim3 grid(p.nworki, B.n), block(64 * SEG_MAX);
     const size_t lds = (size_t)(2 * p.L + 8) * sizeof(double);
-    hipLaunchKernelGGL((k_contract_inverse<EXT, RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek,
-                       p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
+    if (EXT)
+        hipLaunchKernelGGL((k_contract_inverse_ext<RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge,
+                           p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
+    else
+        hipLaunchKernelGGL((k_contract_inverse<RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek,
+                           p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
     return hipGetLastError();
 }
 }  // namespace
