@@ -920,9 +920,45 @@ __device__ __forceinline__ v4f mfma4(float a, float b, v4f c)
     return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
 }
 
+// The staged FP32 data reaches the matrix cores through a per-wave window in
+// LDS of WIN steps, refilled at each window boundary from registers that were
+// loaded from global memory one window earlier (a wave reads only the window
+// it wrote, so no barrier is needed).
+constexpr int WIN = 32;                  // steps (n or l values) per window; 16 pairs
+
+// Forward window q (n in [WIN*q, WIN*q + WIN)): rows (b, c, comp) of WIN floats,
+// 8G rows, held as 4G float2 values per lane of the wave.
+template <int G>
+struct FwdWin { fv2 v[2 * G]; };
+
+template <int G>
+__device__ __forceinline__ void fwd_win_load(FwdWin<G>& r, const MixMaps& maps, int mb, int q, int lane)
+{
+#pragma unroll
+    for (int t = 0; t < 2 * G; ++t) {
+        const int e = lane + 64 * t;                  // float2 index in the window, 16 per row
+        const int row = e >> 4, n = WIN * q + 2 * (e & 15);
+        const int comp = row & 3, c = (row >> 2) & 1, b = row >> 3;
+        r.v[t] = fv2{0.0f, 0.0f};
+        if (b < maps.n) {
+            const int Lb = maps.L[b], m = mb + c;
+            // rows hold Lp_b entries, the pad n = L_b (odd L_b) zero
+            if (m < Lb && n < Lb)
+                r.v[t] = *(const fv2*)(maps.src[b] + ((size_t)m * 4 + comp) * (size_t)(Lb + (Lb & 1)) + n);
+        }
+    }
+}
+
+template <int G>
+__device__ __forceinline__ void win_store(float* __restrict__ win, const fv2* v, int lane)
+{
+#pragma unroll
+    for (int t = 0; t < G; ++t) ((fv2*)win)[lane + 64 * t] = v[t];
+}
+
 template <bool EXT, bool INJ, int G>
 __device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT>& st, v4f (&acc)[2][G], int k, int l, int mb, int as,
-                                             const float* __restrict__ Hs, int nA, int comp, const FwdR& r,
+                                             const float* __restrict__ win, int comp, const FwdR& r,
                                              bool& anyscaled)
 {
     float k1[2], k0[2];
@@ -934,11 +970,12 @@ __device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT>& st, v4f (&acc)[2][
     k0[0] = (float)fwd_product<2, EXT>(st, 0);
     k0[1] = (float)fwd_product<2, EXT>(st, 1);
     fwd_advance<2, EXT>(st, mb, as, r.hi.x * r.lo.y, anyscaled);
+    const int off = 2 * k - WIN * (k / (WIN / 2));   // n = 2k within its window
 #pragma unroll
     for (int b = 0; b < G; ++b)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const float2 a = *(const float2*)(Hs + ((b * 2 + c) * 4 + comp) * nA + 2 * k);   // n = 2k, 2k+1
+            const fv2 a = *(const fv2*)(win + ((b * 2 + c) * 4 + comp) * WIN + off);   // n = 2k, 2k+1
             acc[c][b] = mfma4(a.y, k1[c], acc[c][b]);
             acc[c][b] = mfma4(a.x, k0[c], acc[c][b]);
         }
@@ -947,19 +984,32 @@ __device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT>& st, v4f (&acc)[2][
 template <bool EXT, int G>
 __device__ __forceinline__ void fwd_mix_segment(FwdLane<2, EXT>& st, v4f (&acc)[2][G], const FwdSeg& g, int l,
                                                 int le, int mb, int as, const double* __restrict__ Rt,
-                                                const float* __restrict__ Hs, int nA, int comp, bool& anyscaled)
+                                                float* __restrict__ win, const MixMaps& maps, int lane,
+                                                bool& anyscaled)
 {
+    constexpr int PW = WIN / 2;   // pairs per window
+    const int comp = lane & 3;
+    FwdWin<G> nxt;
+    fwd_win_load<G>(nxt, maps, mb, g.ktop / PW, lane);
     FwdR rn = fwd_load_r(Rt, le, g.ktop);
+    auto enter = [&](int k) {
+        if (k == g.ktop || (k % PW) == PW - 1) {       // entering window k / PW
+            win_store<2 * G>(win, nxt.v, lane);
+            if (k / PW > g.klo / PW) fwd_win_load<G>(nxt, maps, mb, k / PW - 1, lane);
+        }
+    };
     int k = g.ktop;
-    for (; k >= max(g.kA, g.klo); --k) {
+    for (; k >= max(g.kA, g.klo); --k) {               // pairs with lane starts
+        enter(k);
         const FwdR r = rn;
         rn = fwd_load_r(Rt, le, max(k - 1, 0));
-        fwd_mix_pair<EXT, true, G>(st, acc, k, l, mb, as, Hs, nA, comp, r, anyscaled);
+        fwd_mix_pair<EXT, true, G>(st, acc, k, l, mb, as, win, comp, r, anyscaled);
     }
     for (; k >= g.klo; --k) {
+        enter(k);
         const FwdR r = rn;
         rn = fwd_load_r(Rt, le, max(k - 1, 0));
-        fwd_mix_pair<EXT, false, G>(st, acc, k, l, mb, as, Hs, nA, comp, r, anyscaled);
+        fwd_mix_pair<EXT, false, G>(st, acc, k, l, mb, as, win, comp, r, anyscaled);
     }
 }
 
@@ -986,37 +1036,10 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
     if (!any) return;
     const int rtn = 2 * L + 8;
     double* Rt = smem;
-    float* Hs = (float*)(smem + rtn);
+    float* Hs = (float*)(smem + rtn);                  // per-wave windows, later the reduction
+    float* win = Hs + w * (G * 8 * WIN);
     const int nmax = min(l0 + 63, L - 1);
-    const int nA = 2 * ((nmax >> 1) + 1);
     block_copy((dv2*)Rt, (const dv2*)Rtg, rtn / 2);
-    {
-        // rows (b, c, comp) of nA floats, copied as float2 pairs (n, n+1); a map's
-        // rows hold Lp_b entries with the pad n = L_b (odd L_b) zero
-        const int h2 = nA / 2, total = G * 8 * h2;
-        for (int base = 0; base < total; base += 8 * (int)blockDim.x) {
-            fv2 v[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int i = base + j * (int)blockDim.x + (int)threadIdx.x;
-                v[j] = fv2{0.0f, 0.0f};
-                if (i < total) {
-                    const int r = i / h2, n = 2 * (i - r * h2);
-                    const int comp = r & 3, c = (r >> 2) & 1, b = r >> 3;
-                    if (b < maps.n) {
-                        const int Lb = maps.L[b], m = mb + c;
-                        if (m < Lb && n < Lb)
-                            v[j] = *(const fv2*)(maps.src[b] + ((size_t)m * 4 + comp) * (size_t)(Lb + (Lb & 1)) + n);
-                    }
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int i = base + j * (int)blockDim.x + (int)threadIdx.x;
-                if (i < total) ((fv2*)Hs)[i] = v[j];
-            }
-        }
-    }
     __syncthreads();
     const int l = l0 + lane;
     const bool valid = l < L;
@@ -1030,7 +1053,7 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
     v4f acc[2][G];
 #pragma unroll
     for (int b = 0; b < G; ++b) acc[0][b] = acc[1][b] = v4f{0.f, 0.f, 0.f, 0.f};
-    if (g.active) fwd_mix_segment<EXT, G>(st, acc, g, l, le, mb, as, Rt, Hs, nA, lane & 3, anyscaled);
+    if (g.active) fwd_mix_segment<EXT, G>(st, acc, g, l, le, mb, as, Rt, win, maps, lane, anyscaled);
 
     double sum[2][G][4];
 #pragma unroll
@@ -1040,7 +1063,7 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
 #pragma unroll
             for (int v = 0; v < 4; ++v) sum[c][b][v] = (double)acc[c][b][v];
     if (jtop > 0) {
-        __syncthreads();                 // every wave is done with Hs
+        __syncthreads();                 // every wave is done with its window
         v4f* red = (v4f*)Hs;             // [(w-1)][c][b][lane]
         if (w > 0 && w <= jtop) {
 #pragma unroll
@@ -1092,10 +1115,32 @@ __device__ __forceinline__ void inv_load_c(InvC& u, const double2* __restrict__ 
     u.cs = *(const double4*)(lco + (size_t)as * Lp + 2 * j);
 }
 
+// Inverse window q (l in [WIN*q, WIN*q + WIN)): rows (b, comp) of WIN floats,
+// 4G rows, held as 2G float2 values... i.e. G per lane of the wave.
+template <int G>
+struct InvWin { fv2 v[G]; };
+
+template <int G>
+__device__ __forceinline__ void inv_win_load(InvWin<G>& r, const MixMaps& maps, int m, int q, int lane)
+{
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+        const int e = lane + 64 * t;                  // float2 index in the window, 16 per row
+        const int row = e >> 4, l = WIN * q + 2 * (e & 15);
+        const int comp = row & 3, b = row >> 2;
+        r.v[t] = fv2{0.0f, 0.0f};
+        if (b < maps.n) {
+            const int Lb = maps.L[b];
+            if (m < Lb && l < Lb)
+                r.v[t] = *(const fv2*)(maps.src[b] + ((size_t)m * 4 + comp) * (size_t)(Lb + (Lb & 1)) + l);
+        }
+    }
+}
+
 template <bool EXT, bool INJ, int G>
 __device__ __forceinline__ void inv_mix_pair(InvLane<EXT>& st, v4f (&acc)[G], int j, int lstart, double nd,
-                                             const InvC& u, const InvR& r, const float* __restrict__ Fs, int nS,
-                                             int lbase, int comp, bool& anyscaled)
+                                             const InvC& u, const InvR& r, const float* __restrict__ win, int comp,
+                                             bool& anyscaled)
 {
     const int l = 2 * j;
     inv_inject<EXT, INJ>(st, l, lstart, anyscaled);
@@ -1104,9 +1149,10 @@ __device__ __forceinline__ void inv_mix_pair(InvLane<EXT>& st, v4f (&acc)[G], in
     inv_inject<EXT, INJ>(st, l + 1, lstart, anyscaled);
     const float k1 = (float)inv_product<EXT>(st);
     inv_advance<EXT>(st, nd, u.cm.z, u.cm.w, u.cs.z, u.cs.w, r.a.y * r.b.y, anyscaled);
+    const int off = l - WIN * (j / (WIN / 2));   // degree l within its window
 #pragma unroll
     for (int b = 0; b < G; ++b) {
-        const float2 a = *(const float2*)(Fs + (b * 4 + comp) * nS + (l - lbase));   // degrees l, l+1
+        const fv2 a = *(const fv2*)(win + (b * 4 + comp) * WIN + off);   // degrees l, l+1
         acc[b] = mfma4(a.x, k0, acc[b]);
         acc[b] = mfma4(a.y, k1, acc[b]);
     }
@@ -1116,30 +1162,42 @@ template <bool EXT, int G>
 __device__ __forceinline__ void inv_mix_segment(InvLane<EXT>& st, v4f (&acc)[G], const InvSeg& g, int jend,
                                                 int lstart, int ne, double nd, int m, int as, int Lp,
                                                 const double2* __restrict__ lco, const double* __restrict__ Rt,
-                                                const float* __restrict__ Fs, int nS, int lbase, int comp,
+                                                float* __restrict__ win, const MixMaps& maps, int lane,
                                                 bool& anyscaled)
 {
+    constexpr int PW = WIN / 2;   // pairs per window
+    const int comp = lane & 3;
+    InvWin<G> nxt;
+    inv_win_load<G>(nxt, maps, m, g.jfrom / PW, lane);
     InvC un;
     inv_load_c(un, lco, m, as, Lp, g.jfrom);
     InvR rn = inv_load_r(Rt, ne, g.jfrom);
+    auto enter = [&](int j) {
+        if (j == g.jfrom || (j % PW) == 0) {          // entering window j / PW
+            win_store<G>(win, nxt.v, lane);
+            if (j / PW < g.jlast / PW) inv_win_load<G>(nxt, maps, m, j / PW + 1, lane);
+        }
+    };
     int j = g.jfrom;
-    for (; j <= min(g.jA, g.jlast); ++j) {
+    for (; j <= min(g.jA, g.jlast); ++j) {            // pairs with chain starts
+        enter(j);
         wait_scalar(un.cm.x);
         const InvC u = un;
         const InvR r = rn;
         const int jn = min(j + 1, jend);
         inv_load_c(un, lco, m, as, Lp, jn);
         rn = inv_load_r(Rt, ne, jn);
-        inv_mix_pair<EXT, true, G>(st, acc, j, lstart, nd, u, r, Fs, nS, lbase, comp, anyscaled);
+        inv_mix_pair<EXT, true, G>(st, acc, j, lstart, nd, u, r, win, comp, anyscaled);
     }
     for (; j <= g.jlast; ++j) {
+        enter(j);
         wait_scalar(un.cm.x);
         const InvC u = un;
         const InvR r = rn;
         const int jn = min(j + 1, jend);
         inv_load_c(un, lco, m, as, Lp, jn);
         rn = inv_load_r(Rt, ne, jn);
-        inv_mix_pair<EXT, false, G>(st, acc, j, lstart, nd, u, r, Fs, nS, lbase, comp, anyscaled);
+        inv_mix_pair<EXT, false, G>(st, acc, j, lstart, nd, u, r, win, comp, anyscaled);
     }
 }
 
@@ -1168,36 +1226,9 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse_mix(
     const InvGeo geo = inv_geometry(n0, m, as, segi, nsegi);
     const int rtn = 2 * L + 8;
     double* Rt = smem;
-    float* Fs = (float*)(smem + rtn);
-    const int lbase = geo.lstart;
-    const int nS = Lp - lbase;
+    float* Fs = (float*)(smem + rtn);                  // per-wave windows, later the reduction
+    float* win = Fs + w * (G * 4 * WIN);
     block_copy((dv2*)Rt, (const dv2*)Rtg, rtn / 2);
-    {
-        // rows (b, comp) of nS floats from degree lbase (even), copied as float2 pairs
-        const int h2 = nS / 2, total = G * 4 * h2;
-        for (int base = 0; base < total; base += 8 * (int)blockDim.x) {
-            fv2 v[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int i = base + j * (int)blockDim.x + (int)threadIdx.x;
-                v[j] = fv2{0.0f, 0.0f};
-                if (i < total) {
-                    const int r = i / h2, l = lbase + 2 * (i - r * h2);
-                    const int comp = r & 3, b = r >> 2;
-                    if (b < maps.n) {
-                        const int Lb = maps.L[b];
-                        if (m < Lb && l < Lb)
-                            v[j] = *(const fv2*)(maps.src[b] + ((size_t)m * 4 + comp) * (size_t)(Lb + (Lb & 1)) + l);
-                    }
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int i = base + j * (int)blockDim.x + (int)threadIdx.x;
-                if (i < total) ((fv2*)Fs)[i] = v[j];
-            }
-        }
-    }
     __syncthreads();
     const int n = n0 + lane;
     const bool valid = n < L;
@@ -1214,7 +1245,7 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse_mix(
 #pragma unroll
     for (int b = 0; b < G; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
     if (g.active)
-        inv_mix_segment<EXT, G>(st, acc, g, jend, geo.lstart, ne, nd, m, as, Lp, lco, Rt, Fs, nS, lbase, lane & 3,
+        inv_mix_segment<EXT, G>(st, acc, g, jend, geo.lstart, ne, nd, m, as, Lp, lco, Rt, win, maps, lane,
                                 anyscaled);
 
     double sum[G][4];
@@ -1223,7 +1254,7 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse_mix(
 #pragma unroll
         for (int v = 0; v < 4; ++v) sum[b][v] = (double)acc[b][v];
     if (nseg > 1) {
-        __syncthreads();                 // every wave is done with Fs
+        __syncthreads();                 // every wave is done with its window
         v4f* red = (v4f*)Fs;             // [(w-1)][b][lane]
         if (w > 0 && w < nseg) {
 #pragma unroll
@@ -1327,14 +1358,14 @@ namespace {
 
 size_t mix_lds_forward(const Plan& p, int G)
 {
-    const size_t stage = (size_t)G * 8 * p.Lp * sizeof(float);
+    const size_t stage = (size_t)SEG_MAX * G * 8 * WIN * sizeof(float);
     const size_t red = (size_t)(SEG_MAX - 1) * 2 * G * 64 * 16;
     return (size_t)(2 * p.L + 8) * sizeof(double) + std::max(stage, red);
 }
 
 size_t mix_lds_inverse(const Plan& p, int G)
 {
-    const size_t stage = (size_t)G * 4 * p.Lp * sizeof(float);
+    const size_t stage = (size_t)SEG_MAX * G * 4 * WIN * sizeof(float);
     const size_t red = (size_t)(SEG_MAX - 1) * G * 64 * 16;
     return (size_t)(2 * p.L + 8) * sizeof(double) + std::max(stage, red);
 }
