@@ -600,33 +600,7 @@ __device__ __forceinline__ void inv_advance(InvLane<EXT>& st, double nd, double 
     }
 }
 
-// uniform data of one step: stream record (4 doubles), (Pu_m, Qu_m), (Pu_s, Qu_s)
-template <bool EXT, bool INJ, bool RL>
-__device__ __forceinline__ void inv_step(InvLane<EXT>& st, int l, int lstart, double nd, const double* f,
-                                         double pum, double qum, double pus, double qus, double rs,
-                                         bool& anyscaled)
-{
-    inv_inject<EXT, INJ>(st, l, lstart, anyscaled);
-    const double pr = inv_product<EXT>(st);
-    st.ap.x = fma(pr, f[0], st.ap.x);
-    st.ap.y = fma(pr, f[1], st.ap.y);
-    if (!RL) {   // real maps: the orders -m are not needed (F_{-m}(theta) = conj(F_m(theta)))
-        st.am.x = fma(pr, f[2], st.am.x);
-        st.am.y = fma(pr, f[3], st.am.y);
-    }
-    inv_advance<EXT>(st, nd, pum, qum, pus, qus, rs, anyscaled);
-}
-
-struct InvU { Rec8 f; double4 cm, cs; };   // pair (l, l+1): stream, (Pu,Qu)_m, (Pu,Qu)_s
 struct InvR { double2 a, b; };             // 1/sqrt of l+1-n .. l+2-n and l+1+n .. l+2+n
-
-__device__ __forceinline__ void inv_load_u(InvU& u, const double* __restrict__ fs, const double2* __restrict__ lco,
-                                           int m, int as, int Lp, int L, int j)
-{
-    u.f = *(const Rec8*)(fs + ((size_t)m * Lp + 2 * j) * 4);
-    u.cm = *(const double4*)(lco + (size_t)m * Lp + 2 * j);
-    u.cs = *(const double4*)(lco + (size_t)as * Lp + 2 * j);
-}
 
 __device__ __forceinline__ InvR inv_load_r(const double* __restrict__ Rt, int ne, int j)
 {
@@ -635,78 +609,6 @@ __device__ __forceinline__ InvR inv_load_r(const double* __restrict__ Rt, int ne
     r.a = rpair(Rt, max(l + 1 - ne, -1) + 1);   // 1/sqrt(l+1-n), 1/sqrt(l+2-n)  (0 below 0)
     r.b = rpair(Rt, l + 2 + ne);                // 1/sqrt(l+1+n), 1/sqrt(l+2+n)
     return r;
-}
-
-template <bool EXT, bool INJ, bool RL>
-__device__ __forceinline__ void inv_pair(InvLane<EXT>& st, int j, int lstart, double nd, const InvU& u,
-                                         const InvR& r, bool& anyscaled)
-{
-    const int l = 2 * j;
-    inv_step<EXT, INJ, RL>(st, l, lstart, nd, u.f.v, u.cm.x, u.cm.y, u.cs.x, u.cs.y, r.a.x * r.b.x, anyscaled);
-    inv_step<EXT, INJ, RL>(st, l + 1, lstart, nd, u.f.v + 4, u.cm.z, u.cm.w, u.cs.z, u.cs.w, r.a.y * r.b.y,
-                           anyscaled);
-}
-
-// Pairs jfrom .. jlast (ascending, an even count); on entry A holds pair jfrom,
-// on exit A holds pair min(jlast + 1, jend).
-template <bool EXT, bool INJ, bool RL>
-__device__ __forceinline__ void inv_phase(InvLane<EXT>& st, int jfrom, int jlast, int jend, int lstart, int ne,
-                                          double nd, int m, int as, int Lp, int L, const double* __restrict__ fs,
-                                          const double2* __restrict__ lco, const double* __restrict__ Rt, InvU& uA,
-                                          InvU& uB, InvR& rA, InvR& rB, bool& anyscaled)
-{
-    for (int j = jfrom; j < jlast; j += 2) {
-        wait_scalar(uA.f.v[0]);
-        __builtin_amdgcn_sched_barrier(0);
-        inv_load_u(uB, fs, lco, m, as, Lp, L, j + 1);
-        rB = inv_load_r(Rt, ne, j + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        inv_pair<EXT, INJ, RL>(st, j, lstart, nd, uA, rA, anyscaled);
-        wait_scalar(uB.f.v[0]);
-        __builtin_amdgcn_sched_barrier(0);
-        const int j2 = min(j + 2, jend);
-        inv_load_u(uA, fs, lco, m, as, Lp, L, j2);
-        rA = inv_load_r(Rt, ne, j2);
-        __builtin_amdgcn_sched_barrier(0);
-        inv_pair<EXT, INJ, RL>(st, j + 1, lstart, nd, uB, rB, anyscaled);
-    }
-}
-
-// Pairs jfrom .. jlast of one segment (ascending); pairs <= jA (jA in
-// [jfrom-1, jlast]) contain chain starts.  Phase loops cover even pair counts; a
-// leftover pair is peeled.
-template <bool EXT, bool RL>
-__device__ __forceinline__ void inv_segment(InvLane<EXT>& st, int jfrom, int jA, int jlast, int jend, int lstart,
-                                            int ne, double nd, int m, int as, int Lp, int L,
-                                            const double* __restrict__ fs, const double2* __restrict__ lco,
-                                            const double* __restrict__ Rt, bool& anyscaled)
-{
-    InvU uA, uB;
-    InvR rA, rB;
-    inv_load_u(uA, fs, lco, m, as, Lp, L, jfrom);
-    rA = inv_load_r(Rt, ne, jfrom);
-    int cntA = jA - jfrom + 1;
-    if ((cntA & 1) && jA < jlast) { ++jA; ++cntA; }
-    if (cntA > 0) {
-        const int jlastA = (cntA & 1) ? jA - 1 : jA;
-        inv_phase<EXT, true, RL>(st, jfrom, jlastA, jend, lstart, ne, nd, m, as, Lp, L, fs, lco, Rt, uA, uB, rA, rB,
-                             anyscaled);
-        if (cntA & 1) {             // jA = jlast, in A
-            wait_scalar(uA.f.v[0]);
-            inv_pair<EXT, true, RL>(st, jA, lstart, nd, uA, rA, anyscaled);
-            return;
-        }
-    }
-    const int cntB = jlast - jA;    // pairs jA+1 .. jlast, A holds jA+1
-    if (cntB > 0) {
-        const int jlastB = (cntB & 1) ? jlast - 1 : jlast;
-        inv_phase<EXT, false, RL>(st, jA + 1, jlastB, jend, lstart, ne, nd, m, as, Lp, L, fs, lco, Rt, uA, uB, rA, rB,
-                              anyscaled);
-        if (cntB & 1) {
-            wait_scalar(uA.f.v[0]);
-            inv_pair<EXT, false, RL>(st, jlast, lstart, nd, uA, rA, anyscaled);
-        }
-    }
 }
 
 struct CkOff { size_t off[SEG_MAX]; };
@@ -811,24 +713,234 @@ __device__ __forceinline__ InvSeg inv_setup(InvLane<EXT>& st, bool& anyscaled, c
     return g;
 }
 
-// FP64 inverse contraction: one workgroup per chain group (64 orders n0.., one
-// order m).  Partial sums are added in LDS in segment order.
+// ===========================================================================
+// FP64 inverse contraction, two orders per wavefront.  The orders m0, m0+1 of a
+// group share everything that depends on n and l only: X_n(l), Y_n(l), the
+// exact q bookkeeping and the spin chain Delta^l_{n,|s|}; each order keeps its
+// own chain Delta^l_{n,m} and sums.  The uniform data of a step (both orders'
+// stream records and (Pu, Qu), and (Pu, Qu) of |s|) is 28 scalar registers, so
+// it is double-buffered step by step.
+// ===========================================================================
+template <bool EXT>
+struct InvLane2 {
+    double dc[2], dp[2];       // Delta^l_{n,m_c}, Delta^{l-1}_{n,m_c}
+    double sc, sp;             // Delta^l_{n,|s|}, Delta^{l-1}_{n,|s|}
+    double2 ap[2], am[2];
+    int k[2], ks;
+    double q, dq, sprev;
+    double start[2], starts;
+    int startk[2], startks, lz[2], l0s;
+};
+
+struct InvS2 { double4 f0, f1; double2 c0, c1, cs; };   // one step l
+
+__device__ __forceinline__ void inv2_load(InvS2& u, const double* __restrict__ fs, const double2* __restrict__ lco,
+                                          int m0, int as, int Lp, int L, int l)
+{
+    const int m1 = min(m0 + 1, L - 1);   // order L (odd L) never starts; any row will do
+    u.f0 = *(const double4*)(fs + ((size_t)m0 * Lp + l) * 4);
+    u.f1 = *(const double4*)(fs + ((size_t)m1 * Lp + l) * 4);
+    u.c0 = lco[(size_t)m0 * Lp + l];
+    u.c1 = lco[(size_t)m1 * Lp + l];
+    u.cs = lco[(size_t)as * Lp + l];
+}
+
+template <bool EXT, bool INJ, bool RL>
+__device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, double nd, const InvS2& u, double rs,
+                                          bool& anyscaled)
+{
+    if (INJ) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            if (l == st.lz[c]) { st.dc[c] = st.start[c]; if (EXT) st.k[c] = st.startk[c]; }
+        if (l == st.l0s && st.l0s > lstart) { st.sc = st.starts; if (EXT) st.ks = st.startks; }
+        if (EXT) anyscaled = __any(st.k[0] > 0 || st.k[1] > 0 || st.ks > 0);
+    }
+    double sv = st.sc;
+    if (EXT) sv = (st.ks == 0) ? sv : 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const double4 f = c ? u.f1 : u.f0;
+        double d = st.dc[c];
+        if (EXT) d = (st.k[c] == 0) ? d : 0.0;
+        const double pr = d * sv;
+        st.ap[c].x = fma(pr, f.x, st.ap[c].x);
+        st.ap[c].y = fma(pr, f.y, st.ap[c].y);
+        if (!RL) {
+            st.am[c].x = fma(pr, f.z, st.am[c].x);
+            st.am[c].y = fma(pr, f.w, st.am[c].y);
+        }
+    }
+    // X_n(l) = n/sqrt((l+1)^2-n^2), Y_n(l) = sqrt(l^2-n^2)/sqrt((l+1)^2-n^2); harmless at l = L-1
+    const double xn = nd * rs;
+    const double yn = st.sprev * rs;
+    st.sprev = st.q * rs;
+    st.q += st.dq;
+    st.dq += 2.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const double2 pq = c ? u.c1 : u.c0;
+        const double dn = fma(pq.x * xn, st.dc[c], (pq.y * yn) * st.dp[c]);
+        st.dp[c] = st.dc[c];
+        st.dc[c] = dn;
+    }
+    {
+        const double sn = fma(u.cs.x * xn, st.sc, (u.cs.y * yn) * st.sp);
+        st.sp = st.sc;
+        st.sc = sn;
+    }
+    if (EXT && anyscaled) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            if (st.k[c] > 0 && fabs(st.dc[c]) > EXT_UP) { st.dc[c] *= EXT_DOWN; st.dp[c] *= EXT_DOWN; st.k[c] -= 1; }
+        if (st.ks > 0 && fabs(st.sc) > EXT_UP) { st.sc *= EXT_DOWN; st.sp *= EXT_DOWN; st.ks -= 1; }
+        anyscaled = __any(st.k[0] > 0 || st.k[1] > 0 || st.ks > 0);
+    }
+}
+
+// Pairs jfrom .. jlast (pair j = steps 2j, 2j+1); A holds even steps, B odd ones.
+template <bool EXT, bool INJ, bool RL>
+__device__ __forceinline__ void inv2_phase(InvLane2<EXT>& st, int jfrom, int jlast, int lend, int lstart, int ne,
+                                           double nd, int m0, int as, int Lp, int L, const double* __restrict__ fs,
+                                           const double2* __restrict__ lco, const double* __restrict__ Rt, InvS2& uA,
+                                           InvS2& uB, InvR& r, bool& anyscaled)
+{
+    for (int j = jfrom; j <= jlast; ++j) {
+        wait_scalar(uA.f0.x);
+        __builtin_amdgcn_sched_barrier(0);
+        inv2_load(uB, fs, lco, m0, as, Lp, L, 2 * j + 1);
+        const InvR rn = inv_load_r(Rt, ne, min(j + 1, lend >> 1));
+        __builtin_amdgcn_sched_barrier(0);
+        inv2_step<EXT, INJ, RL>(st, 2 * j, lstart, nd, uA, r.a.x * r.b.x, anyscaled);
+        wait_scalar(uB.f0.x);
+        __builtin_amdgcn_sched_barrier(0);
+        inv2_load(uA, fs, lco, m0, as, Lp, L, min(2 * j + 2, lend));
+        __builtin_amdgcn_sched_barrier(0);
+        inv2_step<EXT, INJ, RL>(st, 2 * j + 1, lstart, nd, uB, r.a.y * r.b.y, anyscaled);
+        r = rn;
+    }
+}
+
+__device__ __forceinline__ InvGeo inv2_geometry(int n0, int m0, int as, int segi, int nsegi)
+{
+    InvGeo g;
+    g.lstart = max(n0, m0) & ~1;
+    g.lA = max(max(n0 + 64, m0 + 2), as + 1);   // every chain start of both orders lies below lA
+    g.jb = (max(g.lA, g.lstart + 2) + segi - 1) / segi;
+    g.nseg = (g.jb < nsegi) ? 1 + nsegi - g.jb : 1;
+    return g;
+}
+
+template <bool EXT>
+__device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled, const InvGeo& geo, int w, int n,
+                                             int m0, int L, int Lp, int as, int segi,
+                                             const double* __restrict__ edge, const int* __restrict__ edgek,
+                                             const double* __restrict__ stab, const int* __restrict__ stabk,
+                                             const double2* __restrict__ cki, const int2* __restrict__ ckik,
+                                             const CkOff& ckoff)
+{
+    const bool valid = n < L;
+    const int ne = valid ? n : L - 1;
+    const int lstart = geo.lstart;
+    const int jend = (Lp >> 1) - 1;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        st.dc[c] = 0.0; st.dp[c] = 0.0; st.k[c] = 0; st.start[c] = 0.0; st.startk[c] = 0;
+        st.ap[c] = st.am[c] = make_double2(0.0, 0.0);
+        st.lz[c] = max(n, m0 + c);
+    }
+    st.sc = 0.0; st.sp = 0.0; st.ks = 0; st.starts = 0.0; st.startks = 0;
+    st.l0s = max(n, as);
+    st.sprev = 0.0; st.q = 0.0; st.dq = 0.0;
+    anyscaled = EXT;
+    InvSeg g{0, 0, -1, false};
+    if (w == 0) {
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int m = m0 + c;
+                if (m >= L) continue;
+                if (n >= m) {
+                    const size_t i = (size_t)n * (n + 1) / 2 + m;
+                    st.start[c] = ((n - m) & 1) ? -edge[i] : edge[i];
+                    if (EXT) st.startk[c] = edgek[i];
+                } else {
+                    const size_t i = (size_t)m * (m + 1) / 2 + n;
+                    st.start[c] = edge[i];
+                    if (EXT) st.startk[c] = edgek[i];
+                }
+            }
+            // spin chain: from the table at lstart when already running, else injected
+            if (st.l0s <= lstart) {
+                double v1 = stab[(size_t)lstart * L + n], v0 = 0.0;
+                int k1 = EXT ? stabk[(size_t)lstart * L + n] : 0, k0 = k1;
+                if (lstart >= 1) {
+                    v0 = stab[(size_t)(lstart - 1) * L + n];
+                    k0 = EXT ? stabk[(size_t)(lstart - 1) * L + n] : 0;
+                }
+                int kk;
+                ck_level<EXT>(v0, v1, k0, k1, kk);
+                st.sc = v1; st.sp = v0; st.ks = kk;
+            } else if (st.l0s < L) {
+                st.starts = stab[(size_t)st.l0s * L + n];
+                st.startks = EXT ? stabk[(size_t)st.l0s * L + n] : 0;
+            }
+        }
+        st.sprev = (lstart >= ne) ? sqrt((double)(lstart - ne) * (double)(lstart + ne)) : 0.0;
+        st.q = (double)(lstart + 1 - ne) * (double)(lstart + 1 + ne);
+        st.dq = 2.0 * (double)lstart + 3.0;
+        const int jlast = (geo.nseg > 1) ? ((geo.jb * segi) >> 1) - 1 : jend;
+        const int jA = min(jlast, (geo.lA - 1) >> 1);
+        g = InvSeg{lstart >> 1, jA, jlast, true};
+    } else if (w < geo.nseg) {
+        // segment from degree c = (jb+w-1)*segi (> m0+1), started from the checkpoint plane
+        const int jj = geo.jb + w - 1;
+        const int cdeg = jj * segi;
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int m = m0 + c;
+                if (m >= L) continue;
+                const size_t i = ckoff.off[jj] + (size_t)n * (cdeg + 1) + m;
+                double2 v = cki[i];
+                int kk = 0;
+                if (EXT) { const int2 kv = ckik[i]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
+                st.dp[c] = v.x; st.dc[c] = v.y; st.k[c] = kk;
+            }
+            double v1 = stab[(size_t)cdeg * L + n], v0 = stab[(size_t)(cdeg - 1) * L + n];
+            int k1 = EXT ? stabk[(size_t)cdeg * L + n] : 0, k0 = EXT ? stabk[(size_t)(cdeg - 1) * L + n] : 0;
+            int kk;
+            ck_level<EXT>(v0, v1, k0, k1, kk);
+            st.sc = v1; st.sp = v0; st.ks = kk;
+        }
+        st.sprev = sqrt(fmax(0.0, (double)(cdeg - ne) * (double)(cdeg + ne)));
+        st.q = (double)(cdeg + 1 - ne) * (double)(cdeg + 1 + ne);
+        st.dq = 2.0 * (double)cdeg + 3.0;
+        if (EXT) anyscaled = __any(st.k[0] > 0 || st.k[1] > 0 || st.ks > 0);
+        const int jlast = (w < geo.nseg - 1) ? (((jj + 1) * segi) >> 1) - 1 : jend;
+        g = InvSeg{cdeg >> 1, (cdeg >> 1) - 1, jlast, true};
+    }
+    return g;
+}
+
 template <bool EXT, bool RL>
-__device__ __forceinline__ void contract_inverse_body(
+__device__ __forceinline__ void contract_inverse2_body(
     const double* __restrict__ fs0, size_t fstride, const Batch& B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
     const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,
     const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work, int L, int Lp, int s, int segi,
     int nsegi)
 {
-    __shared__ double2 red[SEG_MAX - 1][2][64];
-    extern __shared__ double Rt[];   // copy of the 1/sqrt table (2L+8 entries)
+    // LDS: the 1/sqrt table during the chains, then the partial sums of the
+    // later segments, red[(w-1)][c][2][lane] (sized by the launcher)
+    extern __shared__ double Rt[];
+    double2* red = (double2*)Rt;
     const double* __restrict__ fs = fs0 + blockIdx.y * fstride;   // map blockIdx.y of the launch
     double2* __restrict__ F = (double2*)B.out[blockIdx.y];
     const int grp = blockIdx.x;
     const int w = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int n0 = uniform(work[grp].x), m = uniform(work[grp].y);
+    const int n0 = uniform(work[grp].x), m0 = uniform(work[grp].y);
     if (n0 < 0) return;   // padding entry of the work list
     block_copy((dv2*)Rt, (const dv2*)Rtg, L + 4);
     __syncthreads();
@@ -837,29 +949,43 @@ __device__ __forceinline__ void contract_inverse_body(
     const int ne = valid ? n : L - 1;
     const int as = s < 0 ? -s : s;
     const double nd = (double)ne;
-    const int jend = (Lp >> 1) - 1;
-    const InvGeo geo = inv_geometry(n0, m, as, segi, nsegi);
+    const int lend = Lp - 1;
+    const InvGeo geo = inv2_geometry(n0, m0, as, segi, nsegi);
     const int nseg = geo.nseg;
 
-    InvLane<EXT> st;
+    InvLane2<EXT> st;
     bool anyscaled;
-    const InvSeg g = inv_setup<EXT>(st, anyscaled, geo, w, n, m, L, Lp, as, segi, edge, edgek, stab, stabk, cki,
-                                    ckik, ckoff);
-    if (g.active)
-        inv_segment<EXT, RL>(st, g.jfrom, g.jA, g.jlast, jend, geo.lstart, ne, nd, m, as, Lp, L, fs, lco, Rt,
-                         anyscaled);
+    const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, segi, edge, edgek, stab, stabk, cki,
+                                     ckik, ckoff);
+    if (g.active) {
+        InvS2 uA, uB;
+        inv2_load(uA, fs, lco, m0, as, Lp, L, 2 * g.jfrom);
+        InvR r = inv_load_r(Rt, ne, g.jfrom);
+        const int jA = min(g.jA, g.jlast);
+        if (g.jfrom <= jA)
+            inv2_phase<EXT, true, RL>(st, g.jfrom, jA, lend, geo.lstart, ne, nd, m0, as, Lp, L, fs, lco, Rt, uA, uB, r,
+                                      anyscaled);
+        if (max(g.jfrom, jA + 1) <= g.jlast)
+            inv2_phase<EXT, false, RL>(st, max(g.jfrom, jA + 1), g.jlast, lend, geo.lstart, ne, nd, m0, as, Lp, L, fs,
+                                       lco, Rt, uA, uB, r, anyscaled);
+    }
+
     if (nseg > 1) {
+        auto R = [&](int j, int c, int k) -> double2& { return red[(((j - 1) * 2 + c) * 2 + k) * 64 + lane]; };
+        __syncthreads();                 // every wave is done with the 1/sqrt table
         if (w > 0 && w < nseg) {
-            red[w - 1][0][lane] = st.ap;
-            red[w - 1][1][lane] = st.am;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) { R(w, c, 0) = st.ap[c]; R(w, c, 1) = st.am[c]; }
         }
         __syncthreads();
         if (w != 0) return;
-        for (int j = 1; j < nseg; ++j) {
-            const double2 a = red[j - 1][0][lane], b = red[j - 1][1][lane];
-            st.ap.x += a.x; st.ap.y += a.y;
-            st.am.x += b.x; st.am.y += b.y;
-        }
+        for (int j = 1; j < nseg; ++j)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const double2 a = R(j, c, 0), b = R(j, c, 1);
+                st.ap[c].x += a.x; st.ap[c].y += a.y;
+                st.am[c].x += b.x; st.am[c].y += b.y;
+            }
     } else if (w != 0) {
         return;
     }
@@ -867,39 +993,40 @@ __device__ __forceinline__ void contract_inverse_body(
     if (!valid) return;
     const double fsp = sgn(s) * ((s >= 0) ? sgn(n) : 1.0);
     const double fsm = sgn(s) * ((s < 0) ? sgn(n) : 1.0);
-    double2 op = mul_ipow(st.ap, ((-(m + s)) % 4 + 4) % 4);
-    F[(size_t)(L - 1 + m) * L + n] = make_double2(op.x * fsp, op.y * fsp);
-    if (!RL && m > 0) {
-        double2 om = mul_ipow(st.am, ((m - s) % 4 + 4) % 4);
-        F[(size_t)(L - 1 - m) * L + n] = make_double2(om.x * fsm, om.y * fsm);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int m = m0 + c;
+        if (m >= L) continue;
+        const double2 op = mul_ipow(st.ap[c], ((-(m + s)) % 4 + 4) % 4);
+        F[(size_t)(L - 1 + m) * L + n] = make_double2(op.x * fsp, op.y * fsp);
+        if (!RL && m > 0) {
+            const double2 om = mul_ipow(st.am[c], ((m - s) % 4 + 4) % 4);
+            F[(size_t)(L - 1 - m) * L + n] = make_double2(om.x * fsm, om.y * fsm);
+        }
     }
 }
 
-// The plain variant fits six waves per SIMD without spills in its loops; the
-// exponent-extended one (large band-limits) keeps five.
-#define MW_INVERSE_ARGS                                                                                          \
+#define MW_INVERSE2_ARGS                                                                                         \
     const double* __restrict__ fs0, size_t fstride, Batch B, const double* __restrict__ Rtg,                    \
         const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,         \
         const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,        \
         const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work, int L, int Lp, int s,         \
         int segi, int nsegi
-#define MW_INVERSE_PASS fs0, fstride, B, Rtg, edge, edgek, lco, stab, stabk, cki, ckik, ckoff, work, L, Lp, s, segi, nsegi
+#define MW_INVERSE2_PASS fs0, fstride, B, Rtg, edge, edgek, lco, stab, stabk, cki, ckik, ckoff, work, L, Lp, s, segi, nsegi
 
 template <bool RL>
-__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(6))) void k_contract_inverse(
-    MW_INVERSE_ARGS)
+__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse2(MW_INVERSE2_ARGS)
 {
-    contract_inverse_body<false, RL>(MW_INVERSE_PASS);
+    contract_inverse2_body<false, RL>(MW_INVERSE2_PASS);
 }
 
 template <bool RL>
-__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(5))) void k_contract_inverse_ext(
-    MW_INVERSE_ARGS)
+__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse2_ext(MW_INVERSE2_ARGS)
 {
-    contract_inverse_body<true, RL>(MW_INVERSE_PASS);
+    contract_inverse2_body<true, RL>(MW_INVERSE2_PASS);
 }
-#undef MW_INVERSE_ARGS
-#undef MW_INVERSE_PASS
+#undef MW_INVERSE2_ARGS
+#undef MW_INVERSE2_PASS
 
 // ===========================================================================
 // Mixed precision (MW_FP32C): the same FP64 chains; each step's products
@@ -1333,14 +1460,16 @@ hipError_t inv_go(const Plan& p, const SpinTable& sp, int s, const double* in0, 
 {
     CkOff off;
     for (int j = 0; j < SEG_MAX; ++j) off.off[j] = p.cki_off[j];
-    const dim3 grid(p.nworki, B.n), block(64 * SEG_MAX);
-    const size_t lds = (size_t)(2 * p.L + 8) * sizeof(double);
+    const dim3 grid(p.nworki2, B.n), block(64 * SEG_MAX);
+    const size_t red = (size_t)(SEG_MAX - 1) * 2 * 2 * 64 * sizeof(double2);
+    const size_t lds = std::max((size_t)(2 * p.L + 8) * sizeof(double), red);
     if (EXT)
-        hipLaunchKernelGGL((k_contract_inverse_ext<RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge,
-                           p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
+        hipLaunchKernelGGL((k_contract_inverse2_ext<RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge,
+                           p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki2, p.L, p.Lp, s, p.segi,
+                           p.nsegi);
     else
-        hipLaunchKernelGGL((k_contract_inverse<RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek,
-                           p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi, p.nsegi);
+        hipLaunchKernelGGL((k_contract_inverse2<RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek,
+                           p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki2, p.L, p.Lp, s, p.segi, p.nsegi);
     return hipGetLastError();
 }
 }  // namespace

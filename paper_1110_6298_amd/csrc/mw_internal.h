@@ -41,7 +41,8 @@ struct Plan {
     // contraction work lists (int2: (block start, first order)), dealt over the 8
     // XCDs by order and longest first; (-1, -1) entries are padding
     int2* workf = nullptr; int nworkf = 0;   // forward: (l0, m0)
-    int2* worki = nullptr; int nworki = 0;   // inverse: (n0, m0)
+    int2* worki = nullptr; int nworki = 0;   // inverse, one order per group: (n0, m)
+    int2* worki2 = nullptr; int nworki2 = 0; // inverse, orders in pairs: (n0, m0)
     // Chain segmentation.  The forward splits every row recursion at the global
     // boundaries n = j*segf (j = 1..nsegf-1); ckf holds, for boundary j at
     // [(j-1)*L(L+1)/2 + l(l+1)/2 + m], the pair (Delta^l_{m,n-1}, Delta^l_{m,n})
@@ -67,7 +68,8 @@ struct SpinTable {
 
 // Chains per lane in the contraction kernels (work-list granularity in m).
 constexpr int MT_FWD = 2;
-constexpr int MT_INV = 1;
+constexpr int MT_INV = 1;    // mixed-precision inverse
+constexpr int MT_INV2 = 2;   // FP64 inverse
 
 // Mixed-precision contraction: a group of up to GMAX maps of one spin shares the
 // FP64 chains.  src/dst are per-map device pointers (FP32 staged H or stream;

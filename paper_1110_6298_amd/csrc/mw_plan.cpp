@@ -346,17 +346,25 @@ int build_plan(int L, Plan& p, std::string& err)
         deal(per, wf);
         p.nworkf = (int)wf.size();
         if ((rc = upload(wf, &p.workf, p.bytes, err))) return rc;
-        for (auto& v : per) v.clear();
-        for (int n0 = 0; n0 < L; n0 += 64)
-            for (int m0 = 0; m0 < L; m0 += MT_INV) per[(m0 / MT_INV) & 7].push_back(make_int2(n0, m0));
-        for (auto& v : per)
-            std::stable_sort(v.begin(), v.end(), [L](int2 a, int2 b) {
-                return (L - std::max(a.x, a.y)) > (L - std::max(b.x, b.y));
-            });
-        std::vector<int2> wi;
-        deal(per, wi);
-        p.nworki = (int)wi.size();
-        if ((rc = upload(wi, &p.worki, p.bytes, err))) return rc;
+        // inverse: orders one at a time (mixed precision) and in pairs (FP64)
+        for (int mt : {MT_INV, MT_INV2}) {
+            for (auto& v : per) v.clear();
+            for (int n0 = 0; n0 < L; n0 += 64)
+                for (int m0 = 0; m0 < L; m0 += mt) per[(m0 / mt) & 7].push_back(make_int2(n0, m0));
+            for (auto& v : per)
+                std::stable_sort(v.begin(), v.end(), [L](int2 a, int2 b) {
+                    return (L - std::max(a.x, a.y)) > (L - std::max(b.x, b.y));
+                });
+            std::vector<int2> wi;
+            deal(per, wi);
+            if (mt == MT_INV) {
+                p.nworki = (int)wi.size();
+                if ((rc = upload(wi, &p.worki, p.bytes, err))) return rc;
+            } else {
+                p.nworki2 = (int)wi.size();
+                if ((rc = upload(wi, &p.worki2, p.bytes, err))) return rc;
+            }
+        }
     }
     return 0;
 }
@@ -364,7 +372,7 @@ int build_plan(int L, Plan& p, std::string& err)
 void free_plan(Plan& p)
 {
     void* ptrs[] = {p.sqtab, p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.whatc, p.thtw,
-                    p.workf, p.worki, p.ckf, p.ckfk, p.cki, p.ckik};
+                    p.workf, p.worki, p.worki2, p.ckf, p.ckfk, p.cki, p.ckik};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p = Plan();
