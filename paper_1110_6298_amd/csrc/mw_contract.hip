@@ -611,7 +611,7 @@ __device__ __forceinline__ InvR inv_load_r(const double* __restrict__ Rt, int ne
     return r;
 }
 
-struct CkOff { size_t off[SEG_MAX]; };
+struct CkOff { size_t off[SEGI_MAX]; };
 
 // Segment of one wave in the inverse kernels: pairs jfrom..jlast (pair j =
 // degrees 2j, 2j+1), with chain starts in pairs <= jA; idle waves are inactive.
@@ -734,15 +734,25 @@ struct InvLane2 {
 
 struct InvS2 { double4 f0, f1; double2 c0, c1, cs; };   // one step l
 
-__device__ __forceinline__ void inv2_load(InvS2& u, const double* __restrict__ fs, const double2* __restrict__ lco,
-                                          int m0, int as, int Lp, int L, int l)
+// Rows of the uniform data of a group: stream records of both orders, their
+// (Pu, Qu) factors and those of |s|, each indexed by the degree l.
+struct Inv2Rows { const double4* f0; const double4* f1; const double2* c0; const double2* c1; const double2* cs; };
+
+__device__ __forceinline__ Inv2Rows inv2_rows(const double* __restrict__ fs, const double2* __restrict__ lco, int m0,
+                                              int as, int Lp, int L)
 {
     const int m1 = min(m0 + 1, L - 1);   // order L (odd L) never starts; any row will do
-    u.f0 = *(const double4*)(fs + ((size_t)m0 * Lp + l) * 4);
-    u.f1 = *(const double4*)(fs + ((size_t)m1 * Lp + l) * 4);
-    u.c0 = lco[(size_t)m0 * Lp + l];
-    u.c1 = lco[(size_t)m1 * Lp + l];
-    u.cs = lco[(size_t)as * Lp + l];
+    return Inv2Rows{(const double4*)(fs + (size_t)m0 * Lp * 4), (const double4*)(fs + (size_t)m1 * Lp * 4),
+                    lco + (size_t)m0 * Lp, lco + (size_t)m1 * Lp, lco + (size_t)as * Lp};
+}
+
+__device__ __forceinline__ void inv2_load(InvS2& u, const Inv2Rows& w, int l)
+{
+    u.f0 = w.f0[l];
+    u.f1 = w.f1[l];
+    u.c0 = w.c0[l];
+    u.c1 = w.c1[l];
+    u.cs = w.cs[l];
 }
 
 template <bool EXT, bool INJ, bool RL>
@@ -801,20 +811,19 @@ __device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, 
 // Pairs jfrom .. jlast (pair j = steps 2j, 2j+1); A holds even steps, B odd ones.
 template <bool EXT, bool INJ, bool RL>
 __device__ __forceinline__ void inv2_phase(InvLane2<EXT>& st, int jfrom, int jlast, int lend, int lstart, int ne,
-                                           double nd, int m0, int as, int Lp, int L, const double* __restrict__ fs,
-                                           const double2* __restrict__ lco, const double* __restrict__ Rt, InvS2& uA,
+                                           double nd, const Inv2Rows& rows, const double* __restrict__ Rt, InvS2& uA,
                                            InvS2& uB, InvR& r, bool& anyscaled)
 {
     for (int j = jfrom; j <= jlast; ++j) {
         wait_scalar(uA.f0.x);
         __builtin_amdgcn_sched_barrier(0);
-        inv2_load(uB, fs, lco, m0, as, Lp, L, 2 * j + 1);
+        inv2_load(uB, rows, 2 * j + 1);
         const InvR rn = inv_load_r(Rt, ne, min(j + 1, lend >> 1));
         __builtin_amdgcn_sched_barrier(0);
         inv2_step<EXT, INJ, RL>(st, 2 * j, lstart, nd, uA, r.a.x * r.b.x, anyscaled);
         wait_scalar(uB.f0.x);
         __builtin_amdgcn_sched_barrier(0);
-        inv2_load(uA, fs, lco, m0, as, Lp, L, min(2 * j + 2, lend));
+        inv2_load(uA, rows, min(2 * j + 2, lend));
         __builtin_amdgcn_sched_barrier(0);
         inv2_step<EXT, INJ, RL>(st, 2 * j + 1, lstart, nd, uB, r.a.y * r.b.y, anyscaled);
         r = rn;
@@ -931,10 +940,11 @@ __device__ __forceinline__ void contract_inverse2_body(
     const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work, int L, int Lp, int s, int segi,
     int nsegi)
 {
-    // LDS: the 1/sqrt table during the chains, then the partial sums of the
-    // later segments, red[(w-1)][c][2][lane] (sized by the launcher)
-    extern __shared__ double Rt[];
-    double2* red = (double2*)Rt;
+    // LDS: the partial sums of the later segments, red[(w-1)][c][2][lane].  The
+    // 1/sqrt table is read from global memory (L1-resident): an LDS copy would
+    // hold the workgroup's LDS while its idle segment waves have exited.
+    __shared__ double2 red[(SEGI_MAX - 1) * 2 * 2 * 64];
+    const double* __restrict__ Rt = Rtg;
     const double* __restrict__ fs = fs0 + blockIdx.y * fstride;   // map blockIdx.y of the launch
     double2* __restrict__ F = (double2*)B.out[blockIdx.y];
     const int grp = blockIdx.x;
@@ -942,8 +952,6 @@ __device__ __forceinline__ void contract_inverse2_body(
     const int lane = threadIdx.x & 63;
     const int n0 = uniform(work[grp].x), m0 = uniform(work[grp].y);
     if (n0 < 0) return;   // padding entry of the work list
-    block_copy((dv2*)Rt, (const dv2*)Rtg, L + 4);
-    __syncthreads();
     const int n = n0 + lane;
     const bool valid = n < L;
     const int ne = valid ? n : L - 1;
@@ -958,21 +966,20 @@ __device__ __forceinline__ void contract_inverse2_body(
     const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, segi, edge, edgek, stab, stabk, cki,
                                      ckik, ckoff);
     if (g.active) {
+        const Inv2Rows rows = inv2_rows(fs, lco, m0, as, Lp, L);
         InvS2 uA, uB;
-        inv2_load(uA, fs, lco, m0, as, Lp, L, 2 * g.jfrom);
+        inv2_load(uA, rows, 2 * g.jfrom);
         InvR r = inv_load_r(Rt, ne, g.jfrom);
         const int jA = min(g.jA, g.jlast);
         if (g.jfrom <= jA)
-            inv2_phase<EXT, true, RL>(st, g.jfrom, jA, lend, geo.lstart, ne, nd, m0, as, Lp, L, fs, lco, Rt, uA, uB, r,
-                                      anyscaled);
+            inv2_phase<EXT, true, RL>(st, g.jfrom, jA, lend, geo.lstart, ne, nd, rows, Rt, uA, uB, r, anyscaled);
         if (max(g.jfrom, jA + 1) <= g.jlast)
-            inv2_phase<EXT, false, RL>(st, max(g.jfrom, jA + 1), g.jlast, lend, geo.lstart, ne, nd, m0, as, Lp, L, fs,
-                                       lco, Rt, uA, uB, r, anyscaled);
+            inv2_phase<EXT, false, RL>(st, max(g.jfrom, jA + 1), g.jlast, lend, geo.lstart, ne, nd, rows, Rt, uA, uB, r,
+                                       anyscaled);
     }
 
     if (nseg > 1) {
         auto R = [&](int j, int c, int k) -> double2& { return red[(((j - 1) * 2 + c) * 2 + k) * 64 + lane]; };
-        __syncthreads();                 // every wave is done with the 1/sqrt table
         if (w > 0 && w < nseg) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) { R(w, c, 0) = st.ap[c]; R(w, c, 1) = st.am[c]; }
@@ -1015,13 +1022,13 @@ __device__ __forceinline__ void contract_inverse2_body(
 #define MW_INVERSE2_PASS fs0, fstride, B, Rtg, edge, edgek, lco, stab, stabk, cki, ckik, ckoff, work, L, Lp, s, segi, nsegi
 
 template <bool RL>
-__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse2(MW_INVERSE2_ARGS)
+__global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse2(MW_INVERSE2_ARGS)
 {
     contract_inverse2_body<false, RL>(MW_INVERSE2_PASS);
 }
 
 template <bool RL>
-__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse2_ext(MW_INVERSE2_ARGS)
+__global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse2_ext(MW_INVERSE2_ARGS)
 {
     contract_inverse2_body<true, RL>(MW_INVERSE2_PASS);
 }
@@ -1333,7 +1340,7 @@ __device__ __forceinline__ void inv_mix_segment(InvLane<EXT>& st, v4f (&acc)[G],
 // [(m*4 + comp)*Lp_b + l] (the four values of the FP64 stream record);
 // maps.dst[b]: F of map b at [(L_b - 1 + m)*L_b + n].
 template <bool EXT, int G>
-__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_inverse_mix(
+__global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse_mix(
     MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
     const double2* __restrict__ lco, const double* __restrict__ stab, const int* __restrict__ stabk,
     const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work,
@@ -1459,10 +1466,9 @@ hipError_t inv_go(const Plan& p, const SpinTable& sp, int s, const double* in0, 
                   hipStream_t st)
 {
     CkOff off;
-    for (int j = 0; j < SEG_MAX; ++j) off.off[j] = p.cki_off[j];
-    const dim3 grid(p.nworki2, B.n), block(64 * SEG_MAX);
-    const size_t red = (size_t)(SEG_MAX - 1) * 2 * 2 * 64 * sizeof(double2);
-    const size_t lds = std::max((size_t)(2 * p.L + 8) * sizeof(double), red);
+    for (int j = 0; j < SEGI_MAX; ++j) off.off[j] = p.cki_off[j];
+    const dim3 grid(p.nworki2, B.n), block(64 * SEGI_MAX);
+    const size_t lds = 0;
     if (EXT)
         hipLaunchKernelGGL((k_contract_inverse2_ext<RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge,
                            p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki2, p.L, p.Lp, s, p.segi,
@@ -1494,8 +1500,8 @@ size_t mix_lds_forward(const Plan& p, int G)
 
 size_t mix_lds_inverse(const Plan& p, int G)
 {
-    const size_t stage = (size_t)SEG_MAX * G * 4 * WIN * sizeof(float);
-    const size_t red = (size_t)(SEG_MAX - 1) * G * 64 * 16;
+    const size_t stage = (size_t)SEGI_MAX * G * 4 * WIN * sizeof(float);
+    const size_t red = (size_t)(SEGI_MAX - 1) * G * 64 * 16;
     return (size_t)(2 * p.L + 8) * sizeof(double) + std::max(stage, red);
 }
 
@@ -1522,11 +1528,11 @@ template <bool EXT, int G>
 hipError_t inv_mix_go(const Plan& p, const SpinTable& sp, int s, const MixBatch& maps, hipStream_t st)
 {
     CkOff off;
-    for (int j = 0; j < SEG_MAX; ++j) off.off[j] = p.cki_off[j];
+    for (int j = 0; j < SEGI_MAX; ++j) off.off[j] = p.cki_off[j];
     const size_t lds = mix_lds_inverse(p, G);
     hipError_t e = mix_attr(k_contract_inverse_mix<EXT, G>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_contract_inverse_mix<EXT, G>), dim3(p.nworki, maps.ng), dim3(64 * SEG_MAX), lds, st, maps,
+    hipLaunchKernelGGL((k_contract_inverse_mix<EXT, G>), dim3(p.nworki, maps.ng), dim3(64 * SEGI_MAX), lds, st, maps,
                        p.rtab,
                        p.edge, p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi,
                        p.nsegi);

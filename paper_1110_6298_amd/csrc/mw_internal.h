@@ -15,8 +15,12 @@ namespace mw {
 constexpr int EXT_STEP = 600;
 constexpr int EXT_LIMIT = 900;
 
-// Waves per contraction workgroup = maximum number of segments of one chain.
+// Waves per contraction workgroup = maximum number of segments of one chain:
+// SEG_MAX for the forward row recursions, SEGI_MAX for the inverse degree
+// recursions.  Eight inverse segments were measured slower than four: the
+// extra restarts cost more than the added waves hide.
 constexpr int SEG_MAX = 4;
+constexpr int SEGI_MAX = 4;
 
 // Band-limit-dependent constants, built once per (device, L) on the host in
 // long double and uploaded.  All device pointers are owned by the plan.
@@ -53,7 +57,7 @@ struct Plan {
     int segf = 0, nsegf = 1, segi = 0, nsegi = 1;
     double2* ckf = nullptr; int2* ckfk = nullptr;
     double2* cki = nullptr; int2* ckik = nullptr;
-    size_t cki_off[SEG_MAX] = {0};
+    size_t cki_off[SEGI_MAX] = {0};
     size_t bytes = 0;
 };
 

@@ -257,14 +257,21 @@ int build_plan(int L, Plan& p, std::string& err)
     }
     if ((rc = upload(th, &p.thtw, p.bytes, err))) return rc;
 
-    // chain segmentation: SEG_MAX waves of a workgroup share each chain, the
-    // checkpoints at the boundaries (O(L^2) each, by the degree recursion or the
-    // row recursion in long double) restarting the later segments
+    // chain segmentation: up to SEG_MAX (forward) or SEGI_MAX (inverse) waves of
+    // a workgroup share each chain, the checkpoints at the boundaries (O(L^2)
+    // each, by the degree recursion or the row recursion in long double)
+    // restarting the later segments; segments are multiples of 64 degrees
     {
-        const int seg = 64 * std::max(1, (L + 64 * SEG_MAX - 1) / (64 * SEG_MAX));
-        p.segf = p.segi = (seg > 0 && seg < L) ? seg : (L + 63) / 64 * 64 + 64;
-        p.nsegf = p.nsegi = (p.segf < L) ? (L + p.segf - 1) / p.segf : 1;
-        if (p.nsegf > SEG_MAX) { err = "segmentation exceeds SEG_MAX"; return -3; }
+        auto segment = [L](int smax, int& seg, int& nseg) {
+            const int sz = 64 * std::max(1, (L + 64 * smax - 1) / (64 * smax));
+            seg = (sz < L) ? sz : (L + 63) / 64 * 64 + 64;
+            nseg = (seg < L) ? (L + seg - 1) / seg : 1;
+            return nseg <= smax;
+        };
+        if (!segment(SEG_MAX, p.segf, p.nsegf) || !segment(SEGI_MAX, p.segi, p.nsegi)) {
+            err = "segmentation exceeds the waves of a workgroup";
+            return -3;
+        }
         const size_t T = (size_t)L * (L + 1) / 2;
         if (p.nsegf > 1) {
             std::vector<double2> ck((size_t)(p.nsegf - 1) * T, make_double2(0.0, 0.0));
