@@ -132,15 +132,16 @@ int get_plan(DeviceState& d, int L, bool may_alloc, const Plan** plan)
 }
 
 // Spin-row table Delta^l_{n,|s|} for l < L.
-int get_spin(DeviceState& d, int L, int as, bool may_alloc, const SpinTable** spt)
+int get_spin(DeviceState& d, const Plan& p, int as, bool may_alloc, const SpinTable** spt)
 {
     std::string err;
+    const int L = p.L;
     auto key = std::make_pair(L, as);
     auto jt = d.spins.find(key);
     if (jt == d.spins.end()) {
         if (!may_alloc) return fail(MW_ENOMEM, "spin table L=%d |s|=%d not prepared", L, as);
         SpinTable t;
-        int rc = mw::build_spin_table(L, as, t, err);
+        int rc = mw::build_spin_table(p, as, t, err);
         if (rc) { mw::free_spin_table(t); return fail(rc == -2 ? MW_ENOMEM : MW_EHIP, "spin table: %s", err.c_str()); }
         jt = d.spins.emplace(key, t).first;
     }
@@ -390,7 +391,7 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
         const Plan* p = nullptr;
         const SpinTable* sp = nullptr;
         if ((rc = get_plan(d, c.L, may_alloc, &p))) return rc;
-        if (need_spin && (rc = get_spin(d, c.L, c.s < 0 ? -c.s : c.s, may_alloc, &sp))) return rc;
+        if (need_spin && (rc = get_spin(d, *p, c.s < 0 ? -c.s : c.s, may_alloc, &sp))) return rc;
         hipError_t e = run_chunk(op, c, *p, sp, precision, ptrs, ws, Lws, st);
         if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     }
@@ -513,7 +514,7 @@ int mw_prepare(const int32_t* L, const int32_t* spin, const int32_t* reality, in
         const SpinTable* sp;
         const int as = spin[b] < 0 ? -spin[b] : spin[b];
         if ((rc = get_plan(d, L[b], true, &p))) return rc;
-        if ((rc = get_spin(d, L[b], as, true, &sp))) return rc;
+        if ((rc = get_spin(d, *p, as, true, &sp))) return rc;
     }
     if (precision != MW_FP64 && (rc = autotune(d, L, spin, reality, batch))) return rc;
     const std::vector<Chunk> chunks = make_chunks(d, L, spin, reality, batch, precision, true, rc);

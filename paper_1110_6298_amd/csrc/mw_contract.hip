@@ -60,26 +60,6 @@ struct alignas(64) Rec8 { double v[8]; };    // 64-byte scalar-load unit
 typedef double dv2 __attribute__((ext_vector_type(2)));
 typedef float fv2 __attribute__((ext_vector_type(2)));
 
-// Block-wide copy of n elements from global memory to LDS with the loads of
-// eight elements per thread in flight together (one memory wait per eight).
-template <class T>
-__device__ __forceinline__ void block_copy(T* __restrict__ dst, const T* __restrict__ src, int n)
-{
-    for (int base = 0; base < n; base += 8 * (int)blockDim.x) {
-        T v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int i = base + j * (int)blockDim.x + (int)threadIdx.x;
-            if (i < n) v[j] = src[i];
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int i = base + j * (int)blockDim.x + (int)threadIdx.x;
-            if (i < n) dst[i] = v[j];
-        }
-    }
-}
-
 // 1/sqrt(i) for i = j-1 .. j, read from the shifted table Rt (Rt[j] = 1/sqrt(j-1),
 // Rt[0] = Rt[1] = 0), so that indices below 0 read zeros.
 __device__ __forceinline__ double2 rpair(const double* __restrict__ Rt, int j)
@@ -375,16 +355,17 @@ __device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscale
 // MT orders mb..); wave w runs segment w of the row recursions.  Partial sums
 // are added in LDS in segment order.
 template <int MT, bool EXT, bool RL>
-__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(5))) void k_contract_forward(
-    const double* __restrict__ Hp0, size_t hstride, Batch B, const double* __restrict__ Rtg,
+__device__ __forceinline__ void contract_forward_body(
+    const double* __restrict__ Hp0, size_t hstride, const Batch& B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,
     const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int2* __restrict__ work, int L, int Lp,
     int s, int segf)
 {
-    // LDS: the 1/sqrt table (2L+8 entries) during the chains, then the partial
-    // sums of the lower segments, red[(w-1)][c][k][lane] (sized by the launcher)
-    extern __shared__ double Rt[];
-    double2* red = (double2*)Rt;
+    // LDS: the partial sums of the lower segments, red[(w-1)][c][k][lane].  The
+    // 1/sqrt table is read from global memory (L1-resident), so the LDS of a
+    // workgroup does not grow with L.
+    __shared__ double2 red[(SEG_MAX - 1) * MT * 4 * 64];
+    const double* __restrict__ Rt = Rtg;
     const double* __restrict__ Hp = Hp0 + blockIdx.y * hstride;   // map blockIdx.y of the launch
     double2* __restrict__ flm = (double2*)B.out[blockIdx.y];
     const int grp = blockIdx.x;
@@ -392,8 +373,6 @@ __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(5)
     const int lane = threadIdx.x & 63;
     const int l0 = uniform(work[grp].x), mb = uniform(work[grp].y);
     if (l0 < 0) return;   // padding entry of the work list
-    block_copy((dv2*)Rt, (const dv2*)Rtg, L + 4);
-    __syncthreads();
     const int l = l0 + lane;
     const bool valid = l < L;
     const int le = valid ? l : L - 1;
@@ -406,7 +385,6 @@ __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(5)
     if (g.active) fwd_segment<MT, EXT, RL>(st, g.ktop, g.kA, g.klo, l, le, mb, as, Hp, Rt, Lp, L, anyscaled);
     if (jtop > 0) {
         auto R = [&](int j, int c, int k) -> double2& { return red[(((j - 1) * MT + c) * 4 + k) * 64 + lane]; };
-        __syncthreads();                 // every wave is done with the 1/sqrt table
         if (w > 0 && w <= jtop) {
 #pragma unroll
             for (int c = 0; c < MT; ++c) {
@@ -466,6 +444,32 @@ __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(5)
         }
     }
 }
+
+
+// The plain variant runs five waves per SIMD without spills in its loops; the
+// exponent-extended one (large band-limits) needs the registers of four.
+#define MW_FORWARD_ARGS                                                                                          \
+    const double* __restrict__ Hp0, size_t hstride, Batch B, const double* __restrict__ Rtg,                    \
+        const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,           \
+        const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int2* __restrict__ work, int L,    \
+        int Lp, int s, int segf
+#define MW_FORWARD_PASS Hp0, hstride, B, Rtg, edge, edgek, cl, ckf, ckfk, work, L, Lp, s, segf
+
+template <int MT, bool RL>
+__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(5))) void k_contract_forward(
+    MW_FORWARD_ARGS)
+{
+    contract_forward_body<MT, false, RL>(MW_FORWARD_PASS);
+}
+
+template <int MT, bool RL>
+__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(4))) void k_contract_forward_ext(
+    MW_FORWARD_ARGS)
+{
+    contract_forward_body<MT, true, RL>(MW_FORWARD_PASS);
+}
+#undef MW_FORWARD_ARGS
+#undef MW_FORWARD_PASS
 
 // ===========================================================================
 // Inverse contraction
@@ -830,16 +834,6 @@ __device__ __forceinline__ void inv2_phase(InvLane2<EXT>& st, int jfrom, int jla
     }
 }
 
-__device__ __forceinline__ InvGeo inv2_geometry(int n0, int m0, int as, int segi, int nsegi)
-{
-    InvGeo g;
-    g.lstart = max(n0, m0) & ~1;
-    g.lA = max(max(n0 + 64, m0 + 2), as + 1);   // every chain start of both orders lies below lA
-    g.jb = (max(g.lA, g.lstart + 2) + segi - 1) / segi;
-    g.nseg = (g.jb < nsegi) ? 1 + nsegi - g.jb : 1;
-    return g;
-}
-
 template <bool EXT>
 __device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled, const InvGeo& geo, int w, int n,
                                              int m0, int L, int Lp, int as, int segi,
@@ -937,63 +931,71 @@ __device__ __forceinline__ void contract_inverse2_body(
     const double* __restrict__ fs0, size_t fstride, const Batch& B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
     const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,
-    const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work, int L, int Lp, int s, int segi,
-    int nsegi)
+    const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work, int L, int Lp, int s, int segi)
 {
-    // LDS: the partial sums of the later segments, red[(w-1)][c][2][lane].  The
-    // 1/sqrt table is read from global memory (L1-resident): an LDS copy would
-    // hold the workgroup's LDS while its idle segment waves have exited.
-    __shared__ double2 red[(SEGI_MAX - 1) * 2 * 2 * 64];
+    // LDS: the partial sums of later segments, red[slot][c][2][lane].  The 1/sqrt
+    // table is read from global memory (L1-resident), so the LDS of a workgroup
+    // stays small and does not grow with L.
+    __shared__ double2 red[SEGI_MAX * 2 * 2 * 64];
     const double* __restrict__ Rt = Rtg;
     const double* __restrict__ fs = fs0 + blockIdx.y * fstride;   // map blockIdx.y of the launch
     double2* __restrict__ F = (double2*)B.out[blockIdx.y];
-    const int grp = blockIdx.x;
-    const int w = uniform(threadIdx.x >> 6);
+    const int slot = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int n0 = uniform(work[grp].x), m0 = uniform(work[grp].y);
-    if (n0 < 0) return;   // padding entry of the work list
+    // this wave's segment: see the work-list layout of the spin table
+    const int4 d = work[(size_t)blockIdx.x * SEGI_MAX + slot];
+    const int n0 = uniform(d.x), m0 = uniform(d.y), code = uniform(d.z), jb = uniform(d.w);
+    const bool item = n0 >= 0;
+    const int w = code & 0xff, nseg = (code >> 8) & 0xff, lead = (code >> 16) & 0xff;
+    const bool bar = (code >> 24) & 1;   // the same for every slot of the workgroup
     const int n = n0 + lane;
-    const bool valid = n < L;
+    const bool valid = item && n < L;
     const int ne = valid ? n : L - 1;
     const int as = s < 0 ? -s : s;
     const double nd = (double)ne;
     const int lend = Lp - 1;
-    const InvGeo geo = inv2_geometry(n0, m0, as, segi, nsegi);
-    const int nseg = geo.nseg;
 
     InvLane2<EXT> st;
-    bool anyscaled;
-    const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, segi, edge, edgek, stab, stabk, cki,
-                                     ckik, ckoff);
-    if (g.active) {
-        const Inv2Rows rows = inv2_rows(fs, lco, m0, as, Lp, L);
-        InvS2 uA, uB;
-        inv2_load(uA, rows, 2 * g.jfrom);
-        InvR r = inv_load_r(Rt, ne, g.jfrom);
-        const int jA = min(g.jA, g.jlast);
-        if (g.jfrom <= jA)
-            inv2_phase<EXT, true, RL>(st, g.jfrom, jA, lend, geo.lstart, ne, nd, rows, Rt, uA, uB, r, anyscaled);
-        if (max(g.jfrom, jA + 1) <= g.jlast)
-            inv2_phase<EXT, false, RL>(st, max(g.jfrom, jA + 1), g.jlast, lend, geo.lstart, ne, nd, rows, Rt, uA, uB, r,
-                                       anyscaled);
+    if (item) {
+        InvGeo geo;
+        geo.lstart = max(n0, m0) & ~1;
+        geo.lA = max(max(n0 + 64, m0 + 2), as + 1);   // every chain start of both orders lies below lA
+        geo.jb = jb;
+        geo.nseg = nseg;
+        bool anyscaled;
+        const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, segi, edge, edgek, stab, stabk,
+                                         cki, ckik, ckoff);
+        if (g.active) {
+            const Inv2Rows rows = inv2_rows(fs, lco, m0, as, Lp, L);
+            InvS2 uA, uB;
+            inv2_load(uA, rows, 2 * g.jfrom);
+            InvR r = inv_load_r(Rt, ne, g.jfrom);
+            const int jA = min(g.jA, g.jlast);
+            if (g.jfrom <= jA)
+                inv2_phase<EXT, true, RL>(st, g.jfrom, jA, lend, geo.lstart, ne, nd, rows, Rt, uA, uB, r, anyscaled);
+            if (max(g.jfrom, jA + 1) <= g.jlast)
+                inv2_phase<EXT, false, RL>(st, max(g.jfrom, jA + 1), g.jlast, lend, geo.lstart, ne, nd, rows, Rt, uA,
+                                           uB, r, anyscaled);
+        }
     }
 
-    if (nseg > 1) {
-        auto R = [&](int j, int c, int k) -> double2& { return red[(((j - 1) * 2 + c) * 2 + k) * 64 + lane]; };
-        if (w > 0 && w < nseg) {
+    if (bar) {
+        // every wave of the workgroup (empty slots too) meets at this one barrier
+        auto R = [&](int k, int c, int h) -> double2& { return red[((k * 2 + c) * 2 + h) * 64 + lane]; };
+        if (item && w > 0) {
 #pragma unroll
-            for (int c = 0; c < 2; ++c) { R(w, c, 0) = st.ap[c]; R(w, c, 1) = st.am[c]; }
+            for (int c = 0; c < 2; ++c) { R(slot, c, 0) = st.ap[c]; R(slot, c, 1) = st.am[c]; }
         }
         __syncthreads();
-        if (w != 0) return;
-        for (int j = 1; j < nseg; ++j)
+        if (!item || w != 0) return;
+        for (int k = 1; k < nseg; ++k)
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const double2 a = R(j, c, 0), b = R(j, c, 1);
+                const double2 a = R(lead + k, c, 0), b = R(lead + k, c, 1);
                 st.ap[c].x += a.x; st.ap[c].y += a.y;
                 st.am[c].x += b.x; st.am[c].y += b.y;
             }
-    } else if (w != 0) {
+    } else if (!item) {
         return;
     }
 
@@ -1017,9 +1019,9 @@ __device__ __forceinline__ void contract_inverse2_body(
     const double* __restrict__ fs0, size_t fstride, Batch B, const double* __restrict__ Rtg,                    \
         const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,         \
         const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,        \
-        const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work, int L, int Lp, int s,         \
-        int segi, int nsegi
-#define MW_INVERSE2_PASS fs0, fstride, B, Rtg, edge, edgek, lco, stab, stabk, cki, ckik, ckoff, work, L, Lp, s, segi, nsegi
+        const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work, int L, int Lp, int s,         \
+        int segi
+#define MW_INVERSE2_PASS fs0, fstride, B, Rtg, edge, edgek, lco, stab, stabk, cki, ckik, ckoff, work, L, Lp, s, segi
 
 template <bool RL>
 __global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse2(MW_INVERSE2_ARGS)
@@ -1168,13 +1170,10 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
     bool any = false;
     for (int b = 0; b < maps.n; ++b) any |= (l0 < maps.L[b] && mb < maps.L[b]);
     if (!any) return;
-    const int rtn = 2 * L + 8;
-    double* Rt = smem;
-    float* Hs = (float*)(smem + rtn);                  // per-wave windows, later the reduction
+    const double* __restrict__ Rt = Rtg;               // 1/sqrt table, L1-resident
+    float* Hs = (float*)smem;                          // per-wave windows, later the reduction
     float* win = Hs + w * (G * 8 * WIN);
     const int nmax = min(l0 + 63, L - 1);
-    block_copy((dv2*)Rt, (const dv2*)Rtg, rtn / 2);
-    __syncthreads();
     const int l = l0 + lane;
     const bool valid = l < L;
     const int le = valid ? l : L - 1;
@@ -1358,12 +1357,9 @@ __global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse_mix(
     if (!any) return;
     const int as = s < 0 ? -s : s;
     const InvGeo geo = inv_geometry(n0, m, as, segi, nsegi);
-    const int rtn = 2 * L + 8;
-    double* Rt = smem;
-    float* Fs = (float*)(smem + rtn);                  // per-wave windows, later the reduction
+    const double* __restrict__ Rt = Rtg;               // 1/sqrt table, L1-resident
+    float* Fs = (float*)smem;                          // per-wave windows, later the reduction
     float* win = Fs + w * (G * 4 * WIN);
-    block_copy((dv2*)Rt, (const dv2*)Rtg, rtn / 2);
-    __syncthreads();
     const int n = n0 + lane;
     const bool valid = n < L;
     const int ne = valid ? n : L - 1;
@@ -1430,10 +1426,12 @@ template <bool EXT, bool RL>
 hipError_t fwd_go(const Plan& p, int s, const double* in0, size_t stride, const Batch& B, hipStream_t st)
 {
     const dim3 grid(p.nworkf, B.n), block(64 * SEG_MAX);
-    const size_t red = (size_t)(SEG_MAX - 1) * MT_FWD * 4 * 64 * sizeof(double2);
-    const size_t lds = std::max((size_t)(2 * p.L + 8) * sizeof(double), red);
-    hipLaunchKernelGGL((k_contract_forward<MT_FWD, EXT, RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge,
-                       p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
+    if (EXT)
+        hipLaunchKernelGGL((k_contract_forward_ext<MT_FWD, RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
+                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
+    else
+        hipLaunchKernelGGL((k_contract_forward<MT_FWD, RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
+                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
     return hipGetLastError();
 }
 }  // namespace
@@ -1467,15 +1465,13 @@ hipError_t inv_go(const Plan& p, const SpinTable& sp, int s, const double* in0, 
 {
     CkOff off;
     for (int j = 0; j < SEGI_MAX; ++j) off.off[j] = p.cki_off[j];
-    const dim3 grid(p.nworki2, B.n), block(64 * SEGI_MAX);
-    const size_t lds = 0;
+    const dim3 grid(sp.nwinv, B.n), block(64 * SEGI_MAX);
     if (EXT)
-        hipLaunchKernelGGL((k_contract_inverse2_ext<RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge,
-                           p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki2, p.L, p.Lp, s, p.segi,
-                           p.nsegi);
+        hipLaunchKernelGGL((k_contract_inverse2_ext<RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
+                           p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s, p.segi);
     else
-        hipLaunchKernelGGL((k_contract_inverse2<RL>), grid, block, lds, st, in0, stride, B, p.rtab, p.edge, p.edgek,
-                           p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki2, p.L, p.Lp, s, p.segi, p.nsegi);
+        hipLaunchKernelGGL((k_contract_inverse2<RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge, p.edgek,
+                           p.lco, sp.val, sp.k, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s, p.segi);
     return hipGetLastError();
 }
 }  // namespace
@@ -1491,18 +1487,18 @@ hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, in
 // ---- mixed precision launchers ------------------------------------------
 namespace {
 
-size_t mix_lds_forward(const Plan& p, int G)
+size_t mix_lds_forward(int G)
 {
     const size_t stage = (size_t)SEG_MAX * G * 8 * WIN * sizeof(float);
     const size_t red = (size_t)(SEG_MAX - 1) * 2 * G * 64 * 16;
-    return (size_t)(2 * p.L + 8) * sizeof(double) + std::max(stage, red);
+    return std::max(stage, red);
 }
 
-size_t mix_lds_inverse(const Plan& p, int G)
+size_t mix_lds_inverse(int G)
 {
     const size_t stage = (size_t)SEGI_MAX * G * 4 * WIN * sizeof(float);
     const size_t red = (size_t)(SEGI_MAX - 1) * G * 64 * 16;
-    return (size_t)(2 * p.L + 8) * sizeof(double) + std::max(stage, red);
+    return std::max(stage, red);
 }
 
 template <class K>
@@ -1515,7 +1511,7 @@ hipError_t mix_attr(K kernel, size_t bytes)
 template <bool EXT, int G>
 hipError_t fwd_mix_go(const Plan& p, int s, const MixBatch& maps, hipStream_t st)
 {
-    const size_t lds = mix_lds_forward(p, G);
+    const size_t lds = mix_lds_forward(G);
     hipError_t e = mix_attr(k_contract_forward_mix<EXT, G>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_contract_forward_mix<EXT, G>), dim3(p.nworkf, maps.ng), dim3(64 * SEG_MAX), lds, st, maps,
@@ -1529,7 +1525,7 @@ hipError_t inv_mix_go(const Plan& p, const SpinTable& sp, int s, const MixBatch&
 {
     CkOff off;
     for (int j = 0; j < SEGI_MAX; ++j) off.off[j] = p.cki_off[j];
-    const size_t lds = mix_lds_inverse(p, G);
+    const size_t lds = mix_lds_inverse(G);
     hipError_t e = mix_attr(k_contract_inverse_mix<EXT, G>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_contract_inverse_mix<EXT, G>), dim3(p.nworki, maps.ng), dim3(64 * SEGI_MAX), lds, st, maps,
@@ -1541,10 +1537,10 @@ hipError_t inv_mix_go(const Plan& p, const SpinTable& sp, int s, const MixBatch&
 
 }  // namespace
 
-int mix_group_max(const Plan& p)
+int mix_group_max(const Plan&)
 {
     for (int G = GMAX; G > 1; G >>= 1)
-        if (mix_lds_forward(p, G) <= 160 * 1024 && mix_lds_inverse(p, G) <= 160 * 1024) return G;
+        if (mix_lds_forward(G) <= 160 * 1024 && mix_lds_inverse(G) <= 160 * 1024) return G;
     return 1;
 }
 

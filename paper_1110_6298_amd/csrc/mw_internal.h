@@ -46,7 +46,6 @@ struct Plan {
     // XCDs by order and longest first; (-1, -1) entries are padding
     int2* workf = nullptr; int nworkf = 0;   // forward: (l0, m0)
     int2* worki = nullptr; int nworki = 0;   // inverse, one order per group: (n0, m)
-    int2* worki2 = nullptr; int nworki2 = 0; // inverse, orders in pairs: (n0, m0)
     // Chain segmentation.  The forward splits every row recursion at the global
     // boundaries n = j*segf (j = 1..nsegf-1); ckf holds, for boundary j at
     // [(j-1)*L(L+1)/2 + l(l+1)/2 + m], the pair (Delta^l_{m,n-1}, Delta^l_{m,n})
@@ -62,18 +61,25 @@ struct Plan {
 };
 
 // Spin-row start table for the inverse l-recursion: Delta^l_{n,|s|} at [l*L + n]
-// (mantissa * 2^(EXT_STEP*k)), with its exponent level.
+// (mantissa * 2^(EXT_STEP*k)), with its exponent level.  It also holds the
+// work list of the FP64 inverse contraction, whose segmentation depends on |s|:
+// SEGI_MAX wave slots per workgroup, slot i of workgroup g at [g*SEGI_MAX + i] =
+// (n0, m0, seg | nseg << 8 | lead << 16, jb) for segment seg of the chain group
+// (n0 .. n0+63, orders m0, m0+1) whose nseg segments sit in slots lead ..
+// lead+nseg-1 of the same workgroup, the first boundary of its later segments
+// being jb*segi; (-1, 0, 0, 0) marks an empty slot.
 struct SpinTable {
     int L = 0, as = 0;
     double* val = nullptr;
     int* k = nullptr;
+    int4* winv = nullptr;
+    int nwinv = 0;   // workgroups
     size_t bytes = 0;
 };
 
 // Chains per lane in the contraction kernels (work-list granularity in m).
 constexpr int MT_FWD = 2;
 constexpr int MT_INV = 1;    // mixed-precision inverse
-constexpr int MT_INV2 = 2;   // FP64 inverse
 
 // Mixed-precision contraction: a group of up to GMAX maps of one spin shares the
 // FP64 chains.  src/dst are per-map device pointers (FP32 staged H or stream;
@@ -105,7 +111,7 @@ struct Batch {
 
 int build_plan(int L, Plan& p, std::string& err);
 void free_plan(Plan& p);
-int build_spin_table(int L, int as, SpinTable& t, std::string& err);
+int build_spin_table(const Plan& p, int as, SpinTable& t, std::string& err);
 void free_spin_table(SpinTable& t);
 
 // Kernel launchers (enqueue only); each runs the maps of B (one plan) in one launch.

@@ -353,25 +353,19 @@ int build_plan(int L, Plan& p, std::string& err)
         deal(per, wf);
         p.nworkf = (int)wf.size();
         if ((rc = upload(wf, &p.workf, p.bytes, err))) return rc;
-        // inverse: orders one at a time (mixed precision) and in pairs (FP64)
-        for (int mt : {MT_INV, MT_INV2}) {
-            for (auto& v : per) v.clear();
-            for (int n0 = 0; n0 < L; n0 += 64)
-                for (int m0 = 0; m0 < L; m0 += mt) per[(m0 / mt) & 7].push_back(make_int2(n0, m0));
-            for (auto& v : per)
-                std::stable_sort(v.begin(), v.end(), [L](int2 a, int2 b) {
-                    return (L - std::max(a.x, a.y)) > (L - std::max(b.x, b.y));
-                });
-            std::vector<int2> wi;
-            deal(per, wi);
-            if (mt == MT_INV) {
-                p.nworki = (int)wi.size();
-                if ((rc = upload(wi, &p.worki, p.bytes, err))) return rc;
-            } else {
-                p.nworki2 = (int)wi.size();
-                if ((rc = upload(wi, &p.worki2, p.bytes, err))) return rc;
-            }
-        }
+        // mixed-precision inverse: one order per group (the FP64 inverse packs
+        // its segments per spin, see inverse_work)
+        for (auto& v : per) v.clear();
+        for (int n0 = 0; n0 < L; n0 += 64)
+            for (int m0 = 0; m0 < L; m0 += MT_INV) per[(m0 / MT_INV) & 7].push_back(make_int2(n0, m0));
+        for (auto& v : per)
+            std::stable_sort(v.begin(), v.end(), [L](int2 a, int2 b) {
+                return (L - std::max(a.x, a.y)) > (L - std::max(b.x, b.y));
+            });
+        std::vector<int2> wi;
+        deal(per, wi);
+        p.nworki = (int)wi.size();
+        if ((rc = upload(wi, &p.worki, p.bytes, err))) return rc;
     }
     return 0;
 }
@@ -379,16 +373,85 @@ int build_plan(int L, Plan& p, std::string& err)
 void free_plan(Plan& p)
 {
     void* ptrs[] = {p.sqtab, p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.whatc, p.thtw,
-                    p.workf, p.worki, p.worki2, p.ckf, p.ckfk, p.cki, p.ckik};
+                    p.workf, p.worki, p.ckf, p.ckfk, p.cki, p.ckik};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p = Plan();
 }
 
+// Work list of the FP64 inverse contraction (layout in mw_internal.h).  Chain
+// group (n0, m0) starts its pairs at lstart = max(n0, m0) rounded down to even;
+// every chain start (n, m or |s|) lies below lA, so its first segment runs to
+// the first boundary j*segi >= max(lA, lstart+2) and the others follow the
+// boundaries.  Groups are dealt to the 8 XCDs by order pair, longest first.
+// Their segments are packed into workgroups of SEGI_MAX wave slots: groups of
+// one segment four to a workgroup (no barrier, every wave exits when done),
+// groups of several segments first-fit into the last few open workgroups (so
+// that waves meeting at the reduction barrier have similar lengths).
+static std::vector<int4> inverse_work(const Plan& p, int as)
+{
+    const int L = p.L, Lp = p.Lp, segi = p.segi, nsegi = p.nsegi;
+    struct Item { int n0, m0, nseg, jb, len; };
+    struct Group { int used, len; bool bar; int4 slot[SEGI_MAX]; };
+    std::vector<std::vector<Group>> per(8);
+    for (int x = 0; x < 8; ++x) {
+        std::vector<Item> items;
+        for (int n0 = 0; n0 < L; n0 += 64)
+            for (int m0 = 2 * x; m0 < L; m0 += 16) {
+                const int lstart = std::max(n0, m0) & ~1;
+                const int lA = std::max(std::max(n0 + 64, m0 + 2), as + 1);
+                const int jb = (std::max(lA, lstart + 2) + segi - 1) / segi;
+                const int nseg = (jb < nsegi) ? 1 + nsegi - jb : 1;
+                items.push_back(Item{n0, m0, nseg, jb, Lp - lstart});
+            }
+        std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.len > b.len; });
+        std::vector<Group>& gs = per[x];
+        std::vector<int> open;   // groups with free slots, oldest first
+        constexpr int WINDOW = 4;
+        for (const Item& it : items) {
+            const bool bar = it.nseg > 1;
+            int g = -1;
+            for (int k = (int)open.size() - 1; k >= 0 && g < 0; --k) {
+                Group& c = gs[open[k]];
+                if (c.bar == bar && SEGI_MAX - c.used >= it.nseg) g = open[k];
+            }
+            if (g < 0) {
+                Group c;
+                c.used = 0;
+                c.len = it.len;
+                c.bar = bar;
+                for (int i = 0; i < SEGI_MAX; ++i) c.slot[i] = make_int4(-1, 0, bar ? 1 << 24 : 0, 0);
+                gs.push_back(c);
+                g = (int)gs.size() - 1;
+                open.push_back(g);
+                if ((int)open.size() > WINDOW) open.erase(open.begin());
+            }
+            Group& c = gs[g];
+            for (int w = 0; w < it.nseg; ++w)
+                c.slot[c.used + w] = make_int4(it.n0, it.m0, w | (it.nseg << 8) | (c.used << 16) | (bar ? 1 << 24 : 0),
+                                               it.jb);
+            c.used += it.nseg;
+            if (c.used == SEGI_MAX)
+                for (size_t k = 0; k < open.size(); ++k)
+                    if (open[k] == g) { open.erase(open.begin() + k); break; }
+        }
+        std::stable_sort(gs.begin(), gs.end(), [](const Group& a, const Group& b) { return a.len > b.len; });
+    }
+    size_t n = 0;
+    for (auto& v : per) n = std::max(n, v.size());
+    std::vector<int4> out;
+    out.reserve(n * 8 * SEGI_MAX);
+    for (size_t g = 0; g < n; ++g)
+        for (auto& v : per)
+            for (int i = 0; i < SEGI_MAX; ++i) out.push_back(g < v.size() ? v[g].slot[i] : make_int4(-1, 0, 0, 0));
+    return out;
+}
+
 // Delta^l_{n,|s|} for n <= l < L by the upward l-recursion in long double,
 // started at l0 = max(n, |s|) from the edge value.
-int build_spin_table(int L, int as, SpinTable& t, std::string& err)
+int build_spin_table(const Plan& p, int as, SpinTable& t, std::string& err)
 {
+    const int L = p.L;
     t = SpinTable();
     t.L = L;
     t.as = as;
@@ -425,6 +488,9 @@ int build_spin_table(int L, int as, SpinTable& t, std::string& err)
     int rc;
     if ((rc = upload(val, &t.val, t.bytes, err))) return rc;
     if ((rc = upload(kk, &t.k, t.bytes, err))) return rc;
+    const std::vector<int4> w = inverse_work(p, as);
+    t.nwinv = (int)(w.size() / SEGI_MAX);
+    if ((rc = upload(w, &t.winv, t.bytes, err))) return rc;
     return 0;
 }
 
@@ -432,6 +498,7 @@ void free_spin_table(SpinTable& t)
 {
     if (t.val) (void)hipFree(t.val);
     if (t.k) (void)hipFree(t.k);
+    if (t.winv) (void)hipFree(t.winv);
     t = SpinTable();
 }
 
