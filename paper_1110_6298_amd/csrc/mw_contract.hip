@@ -739,25 +739,33 @@ struct InvLane2 {
 struct InvS2 { double4 f0, f1; double2 c0, c1, cs; };   // one step l
 
 // Rows of the uniform data of a group: stream records of both orders, their
-// (Pu, Qu) factors and those of |s|, each indexed by the degree l.
-struct Inv2Rows { const double4* f0; const double4* f1; const double2* c0; const double2* c1; const double2* cs; };
+// (Pu, Qu) factors and those of |s|, each indexed by the degree l.  Addresses
+// are a base pointer plus a 32-bit byte offset (scalar loads take the offset
+// in a register, so a row costs one register instead of a 64-bit pointer).
+struct Inv2Rows {
+    const char* f;   // stream records, 32 bytes per (m, l)
+    const char* c;   // (Pu, Qu), 16 bytes per (m, l)
+    unsigned f0, f1, c0, c1, cs;   // byte offsets of the rows at l = 0
+};
 
 __device__ __forceinline__ Inv2Rows inv2_rows(const double* __restrict__ fs, const double2* __restrict__ lco, int m0,
                                               int as, int Lp, int L)
 {
     const int m1 = min(m0 + 1, L - 1);   // order L (odd L) never starts; any row will do
-    return Inv2Rows{(const double4*)(fs + (size_t)m0 * Lp * 4), (const double4*)(fs + (size_t)m1 * Lp * 4),
-                    lco + (size_t)m0 * Lp, lco + (size_t)m1 * Lp, lco + (size_t)as * Lp};
+    return Inv2Rows{(const char*)fs, (const char*)lco, (unsigned)(m0 * Lp) * 32u, (unsigned)(m1 * Lp) * 32u,
+                    (unsigned)(m0 * Lp) * 16u, (unsigned)(m1 * Lp) * 16u, (unsigned)(as * Lp) * 16u};
 }
 
 __device__ __forceinline__ void inv2_load(InvS2& u, const Inv2Rows& w, int l)
 {
-    u.f0 = w.f0[l];
-    u.f1 = w.f1[l];
-    u.c0 = w.c0[l];
-    u.c1 = w.c1[l];
-    u.cs = w.cs[l];
+    const unsigned lf = (unsigned)l * 32u, lc = (unsigned)l * 16u;
+    u.f0 = *(const double4*)(w.f + (w.f0 + lf));
+    u.f1 = *(const double4*)(w.f + (w.f1 + lf));
+    u.c0 = *(const double2*)(w.c + (w.c0 + lc));
+    u.c1 = *(const double2*)(w.c + (w.c1 + lc));
+    u.cs = *(const double2*)(w.c + (w.cs + lc));
 }
+
 
 template <bool EXT, bool INJ, bool RL>
 __device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, double nd, const InvS2& u, double rs,
