@@ -95,7 +95,7 @@ __device__ __forceinline__ void dft16(double2 (&v)[16])
     v[1 + 8] = cmul(v[1 + 8], w16<DIR, 2>());
     v[1 + 12] = cmul(v[1 + 12], w16<DIR, 3>());
     v[2 + 4] = cmul(v[2 + 4], w16<DIR, 2>());
-    v[2 + 8] = cmul(v[2 + 8], w16<DIR, 4>());
+    v[2 + 8] = mul_dir_i<DIR>(v[2 + 8]);   // w16^4 = DIR i
     v[2 + 12] = cmul(v[2 + 12], w16<DIR, 6>());
     v[3 + 4] = cmul(v[3 + 4], w16<DIR, 3>());
     v[3 + 8] = cmul(v[3 + 8], w16<DIR, 6>());
@@ -121,7 +121,7 @@ __device__ __forceinline__ void dft8(double2* v)
     bf4<DIR>(e0, e1, e2, e3);
     bf4<DIR>(o0, o1, o2, o3);
     o1 = cmul(o1, w16<DIR, 2>());
-    o2 = cmul(o2, w16<DIR, 4>());
+    o2 = mul_dir_i<DIR>(o2);   // w16^4 = DIR i
     o3 = cmul(o3, w16<DIR, 6>());
     v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
     v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
@@ -153,7 +153,7 @@ __device__ __forceinline__ void twiddle_powers(double2* u, double2 w)
 // radix-RB passes): each thread holds RB/R butterflies in one RB-value register
 // set.  With post != nullptr every output X_j is stored as X_j * post[j].
 template <int DIR, int R, int RB>
-__device__ __forceinline__ void last_pass(double2* x, int N, int p, const double2 (&wl)[8],
+__device__ __forceinline__ void last_pass(double2* x, int N, int p, const double2 (&wl)[RB / 2],
                                           const double2* __restrict__ post)
 {
     constexpr int r = (R == 2) ? 1 : (R == 4) ? 2 : 3;
@@ -201,22 +201,61 @@ __device__ __forceinline__ void last_pass(double2* x, int N, int p, const double
     __syncthreads();
 }
 
+// Twiddle bases of one thread for every FFT of length N = 2^logN in a kernel
+// (all FFTs of a kernel share N and the thread layout, so they are read from
+// the table once, at the kernel's start, instead of once per pass):
+//   w[s-1]  = exp(-2 pi i k / (p RB)) of main pass s >= 1 (p = RB^s, k = i mod p)
+//   wl[q]   = the bases of the final radix-2^r pass for butterfly i + q*blockDim.
+template <int RB>
+struct FftTw {
+    double2 w[3];
+    double2 wl[RB / 2];   // the final pass has radix >= 2: at most RB/2 butterflies per thread
+};
+
+template <int RB>
+__device__ __forceinline__ FftTw<RB> fft_twiddles(int N, int logN, const double2* __restrict__ tw)
+{
+    constexpr int lr = (RB == 16) ? 4 : 3;
+    const int i = threadIdx.x;
+    const int np = logN / lr;
+    const int r = logN - lr * np;
+    FftTw<RB> T;
+#pragma unroll
+    for (int s = 1; s < 4; ++s) {
+        T.w[s - 1] = make_double2(1.0, 0.0);
+        if (s < np) {
+            const int logp = lr * s;
+            T.w[s - 1] = tw[(i & ((1 << logp) - 1)) << (logN - logp - lr)];
+        }
+    }
+    const int logp = lr * np;
+    const int NB = r ? (N >> r) : 0;
+#pragma unroll
+    for (int q = 0; q < RB / 2; ++q) {
+        const int iq = i + q * blockDim.x;
+        T.wl[q] = make_double2(1.0, 0.0);
+        if (r && q < (RB >> r) && iq < NB) T.wl[q] = tw[(iq & ((1 << logp) - 1)) << (logN - logp - r)];
+    }
+    return T;
+}
+
 // Block-wide in-place FFT of length N = 2^logN (16 <= N <= 8192) held in LDS
 // at padded positions Pr<RB>(j): Stockham passes of radix RB (16 or 8), one
 // butterfly per thread in registers, then one radix-2/4/8 pass for the
 // remaining factor.  Needs blockDim.x >= N/RB.
 //   DIR = -1:  X_j = sum_k x_k exp(-2 pi i j k / N)
 //   DIR = +1:  X_j = sum_k x_k exp(+2 pi i j k / N)   (no 1/N)
-// tw[e] = exp(-2 pi i e / N).  With post != nullptr the result is X_j * post[j].
+// T: the thread's twiddle bases for this N.  With post != nullptr the result is
+// X_j * post[j].
 template <int DIR, int RB>
-__device__ __forceinline__ void block_fft(double2* x, int N, int logN, const double2* __restrict__ tw,
+__device__ __forceinline__ void block_fft(double2* x, int N, int logN, const FftTw<RB>& T,
                                           const double2* __restrict__ post = nullptr)
 {
     constexpr int lr = (RB == 16) ? 4 : 3;
     const int i = threadIdx.x;
     const int np = logN / lr;        // main passes (at most 4 for N <= 8192)
     const int r = logN - lr * np;    // final radix 2^r, none when r = 0
-    int p = 1, logp = 0;
+    int p = 1;
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -228,7 +267,7 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const dou
 #pragma unroll
             for (int t = 0; t < RB; ++t) u[t] = x[Pr<RB>(i + t * NB)];
             if (s > 0) {   // the first pass has k = 0: no twiddles
-                double2 w = tw[k << (logN - logp - lr)];
+                double2 w = T.w[s > 0 ? s - 1 : 0];
                 if (DIR > 0) w = cconj(w);
                 twiddle_powers<RB>(u, w);
             }
@@ -242,23 +281,12 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const dou
             for (int t = 0; t < RB; ++t) x[Pr<RB>(j + t * p)] = u[t];
         }
         p <<= lr;
-        logp += lr;
         __syncthreads();
     }
-    double2 wl[8];   // twiddle bases of the final pass
-    {
-        const int NB = r ? (N >> r) : 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int iq = i + q * blockDim.x;
-            wl[q] = make_double2(1.0, 0.0);
-            if (r && q < (RB >> r) && iq < NB) wl[q] = tw[(iq & (p - 1)) << (logN - logp - r)];
-        }
-    }
-    if (r == 1) last_pass<DIR, 2, RB>(x, N, p, wl, post);
-    else if (r == 2) last_pass<DIR, 4, RB>(x, N, p, wl, post);
+    if (r == 1) last_pass<DIR, 2, RB>(x, N, p, T.wl, post);
+    else if (r == 2) last_pass<DIR, 4, RB>(x, N, p, T.wl, post);
     else if constexpr (RB == 16) {
-        if (r == 3) last_pass<DIR, 8, RB>(x, N, p, wl, post);
+        if (r == 3) last_pass<DIR, 8, RB>(x, N, p, T.wl, post);
         else if (post) {
             for (int j = threadIdx.x; j < N; j += blockDim.x) x[Pr<RB>(j)] = cmul(x[Pr<RB>(j)], post[j]);
             __syncthreads();
@@ -273,10 +301,10 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const dou
 // Bluestein DFT of length N1 of the chirped, zero-padded sequence a_j already in
 // x[P(j)], j < N2: on return x[P(k)] * chirp[k] = sum_j a_j exp(-2 pi i j k / N1), k < N1.
 template <int RB>
-__device__ __forceinline__ void bluestein_core(double2* x, const Plan& p)
+__device__ __forceinline__ void bluestein_core(double2* x, const Plan& p, const FftTw<RB>& T)
 {
-    block_fft<-1, RB>(x, p.N2, p.logN2, p.tw, p.bhat);
-    block_fft<+1, RB>(x, p.N2, p.logN2, p.tw);
+    block_fft<-1, RB>(x, p.N2, p.logN2, T, p.bhat);
+    block_fft<+1, RB>(x, p.N2, p.logN2, T);
 }
 
 // XCD-aware column index: consecutive workgroups are dealt round-robin over the
@@ -312,7 +340,9 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
             return v;
         },
         [&](int j, const Pair2& v) { A[Pr<RB>(j)] = cmul(v.a, v.b); });
-    bluestein_core<RB>(A, p);
+    // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
+    const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
+    bluestein_core<RB>(A, p, T);
     staged_loop(
         N1, [&](int k) { return p.chirp[k]; },
         [&](int k, double2 c) {
@@ -363,7 +393,9 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
             return v;
         },
         [&](int j, const Pair2& v) { A[Pr<RB>(j)] = cmul((j < L) ? v.a : cscale(v.a, sig), v.b); });
-    bluestein_core<RB>(A, p);
+    // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
+    const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
+    bluestein_core<RB>(A, p, T);
     // F_{m'} into registers (N1 <= N2/2 <= 8 * blockDim.x), then scatter to slot m' mod N2.
     double2 r[8];
     const double unscale = ADJ_INV ? 2.0 * 3.14159265358979323846 * (double)N1 : 1.0;
@@ -393,8 +425,8 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
                 A[Pr<RB>((mp + N2) & (N2 - 1))] = r[q];
             }
         }
-        block_fft<+1, RB>(A, N2, p.logN2, p.tw, p.what);
-        block_fft<-1, RB>(A, N2, p.logN2, p.tw);
+        block_fft<+1, RB>(A, N2, p.logN2, T, p.what);
+        block_fft<-1, RB>(A, N2, p.logN2, T);
         wrap = N2;
     }
     const int am = m < 0 ? -m : m;
@@ -461,8 +493,10 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
             const int mp = (k <= L - 1) ? k : k - N1;
             A[Pr<RB>((mp + N2) & (N2 - 1))] = (mp < 0) ? cscale(y, sig) : y;
         });
-    block_fft<+1, RB>(A, N2, p.logN2, p.tw, p.whatc);
-    block_fft<-1, RB>(A, N2, p.logN2, p.tw);
+    // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
+    const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
+    block_fft<+1, RB>(A, N2, p.logN2, T, p.whatc);
+    block_fft<-1, RB>(A, N2, p.logN2, T);
     // Z_{m''} e^{+i m'' pi/N1}/(2 pi N1) = Z conj(thtw), conjugated and chirped for the
     // Bluestein evaluation of the positive-exponent DFT
     double2 r[8];
@@ -482,7 +516,7 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
         if (k < N2) A[Pr<RB>(k)] = (k < N1) ? r[q] : make_double2(0.0, 0.0);
     }
     for (int j = threadIdx.x + 8 * blockDim.x; j < N2; j += blockDim.x) A[Pr<RB>(j)] = make_double2(0.0, 0.0);
-    bluestein_core<RB>(A, p);
+    bluestein_core<RB>(A, p, T);
     staged_loop(
         L, [&](int t) { return Pair2{p.chirp[t], p.chirp[2 * L - 2 - t]}; },
         [&](int t, const Pair2& c) {
@@ -531,7 +565,9 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
             const double2 y = cmul(f, cscale(cconj(v.w), unscale));
             A[Pr<RB>(j)] = cmul(cconj(y), v.c);
         });
-    bluestein_core<RB>(A, p);
+    // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
+    const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
+    bluestein_core<RB>(A, p, T);
     staged_loop(
         L, [&](int t) { return p.chirp[t]; },
         [&](int t, double2 c) { Ft[(size_t)t * N1 + mi] = cconj(cmul(A[Pr<RB>(t)], c)); });
@@ -564,7 +600,9 @@ __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
             const bool neg = REAL == 2 && j > L - 1 && j < N1;     // order m = j - N1 < 0
             A[Pr<RB>(j)] = cmul(neg ? v.a : cconj(v.a), v.b);            // conj(F_m), F_m = conj(F_{-m})
         });
-    bluestein_core<RB>(A, p);
+    // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
+    const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
+    bluestein_core<RB>(A, p, T);
     staged_loop(
         N1, [&](int k) { return p.chirp[k]; },
         [&](int k, double2 c) {
