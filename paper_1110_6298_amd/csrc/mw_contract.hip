@@ -180,8 +180,10 @@ __device__ __forceinline__ void fwd_load_h(Rec8 (&h)[MT], const double* __restri
 {
 #pragma unroll
     for (int c = 0; c < MT; ++c) {
+        // base plus a 32-bit byte offset: one scalar offset register per load
         const int m = min(mb + c, L - 1);
-        h[c] = *(const Rec8*)(Hp + ((size_t)m * Lp + 2 * k) * 4);
+        const unsigned off = ((unsigned)(m * Lp) + 2u * (unsigned)k) * 32u;
+        h[c] = *(const Rec8*)((const char*)Hp + off);
     }
 }
 
@@ -358,55 +360,60 @@ template <int MT, bool EXT, bool RL>
 __device__ __forceinline__ void contract_forward_body(
     const double* __restrict__ Hp0, size_t hstride, const Batch& B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,
-    const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int2* __restrict__ work, int L, int Lp,
+    const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int4* __restrict__ work, int L, int Lp,
     int s, int segf)
 {
-    // LDS: the partial sums of the lower segments, red[(w-1)][c][k][lane].  The
+    // LDS: the partial sums of upper segments, red[slot][c][k][lane].  The
     // 1/sqrt table is read from global memory (L1-resident), so the LDS of a
     // workgroup does not grow with L.
-    __shared__ double2 red[(SEG_MAX - 1) * MT * 4 * 64];
+    __shared__ double2 red[SEG_MAX * MT * 4 * 64];
     const double* __restrict__ Rt = Rtg;
     const double* __restrict__ Hp = Hp0 + blockIdx.y * hstride;   // map blockIdx.y of the launch
     double2* __restrict__ flm = (double2*)B.out[blockIdx.y];
-    const int grp = blockIdx.x;
-    const int w = uniform(threadIdx.x >> 6);
+    const int slot = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int l0 = uniform(work[grp].x), mb = uniform(work[grp].y);
-    if (l0 < 0) return;   // padding entry of the work list
+    // this wave's segment: see the work-list layout of the plan
+    const int4 d = work[(size_t)blockIdx.x * SEG_MAX + slot];
+    const int l0 = uniform(d.x), mb = uniform(d.y), code = uniform(d.z);
+    const bool item = l0 >= 0;
+    const int w = code & 0xff, nseg = (code >> 8) & 0xff, lead = (code >> 16) & 0xff;
+    const bool bar = (code >> 24) & 1;   // the same for every slot of the workgroup
     const int l = l0 + lane;
-    const bool valid = l < L;
+    const bool valid = item && l < L;
     const int le = valid ? l : L - 1;
     const int as = s < 0 ? -s : s;
-    const int jtop = min(l0 + 63, L - 1) / segf;
 
     FwdLane<MT, EXT> st;
-    bool anyscaled;
-    const FwdSeg g = fwd_setup<MT, EXT>(st, anyscaled, w, l0, mb, l, L, as, segf, edge, edgek, ckf, ckfk);
-    if (g.active) fwd_segment<MT, EXT, RL>(st, g.ktop, g.kA, g.klo, l, le, mb, as, Hp, Rt, Lp, L, anyscaled);
-    if (jtop > 0) {
-        auto R = [&](int j, int c, int k) -> double2& { return red[(((j - 1) * MT + c) * 4 + k) * 64 + lane]; };
-        if (w > 0 && w <= jtop) {
+    if (item) {
+        bool anyscaled;
+        const FwdSeg g = fwd_setup<MT, EXT>(st, anyscaled, w, l0, mb, l, L, as, segf, edge, edgek, ckf, ckfk);
+        if (g.active) fwd_segment<MT, EXT, RL>(st, g.ktop, g.kA, g.klo, l, le, mb, as, Hp, Rt, Lp, L, anyscaled);
+    }
+    if (bar) {
+        // every wave of the workgroup (empty slots too) meets at this one barrier
+        auto R = [&](int j, int c, int k) -> double2& { return red[((j * MT + c) * 4 + k) * 64 + lane]; };
+        if (item && w > 0) {
 #pragma unroll
             for (int c = 0; c < MT; ++c) {
-                R(w, c, 0) = st.ap[c][0];
-                R(w, c, 1) = st.ap[c][1];
-                R(w, c, 2) = st.am[c][0];
-                R(w, c, 3) = st.am[c][1];
+                R(slot, c, 0) = st.ap[c][0];
+                R(slot, c, 1) = st.ap[c][1];
+                R(slot, c, 2) = st.am[c][0];
+                R(slot, c, 3) = st.am[c][1];
             }
         }
         __syncthreads();
-        if (w != 0) return;
-        for (int j = 1; j <= jtop; ++j) {
+        if (!item || w != 0) return;
+        for (int j = 1; j < nseg; ++j) {
 #pragma unroll
             for (int c = 0; c < MT; ++c) {
                 double2 v;
-                v = R(j, c, 0); st.ap[c][0].x += v.x; st.ap[c][0].y += v.y;
-                v = R(j, c, 1); st.ap[c][1].x += v.x; st.ap[c][1].y += v.y;
-                v = R(j, c, 2); st.am[c][0].x += v.x; st.am[c][0].y += v.y;
-                v = R(j, c, 3); st.am[c][1].x += v.x; st.am[c][1].y += v.y;
+                v = R(lead + j, c, 0); st.ap[c][0].x += v.x; st.ap[c][0].y += v.y;
+                v = R(lead + j, c, 1); st.ap[c][1].x += v.x; st.ap[c][1].y += v.y;
+                v = R(lead + j, c, 2); st.am[c][0].x += v.x; st.am[c][0].y += v.y;
+                v = R(lead + j, c, 3); st.am[c][1].x += v.x; st.am[c][1].y += v.y;
             }
         }
-    } else if (w != 0) {
+    } else if (!item) {
         return;
     }
 
@@ -451,7 +458,7 @@ __device__ __forceinline__ void contract_forward_body(
 #define MW_FORWARD_ARGS                                                                                          \
     const double* __restrict__ Hp0, size_t hstride, Batch B, const double* __restrict__ Rtg,                    \
         const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,           \
-        const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int2* __restrict__ work, int L,    \
+        const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int4* __restrict__ work, int L,    \
         int Lp, int s, int segf
 #define MW_FORWARD_PASS Hp0, hstride, B, Rtg, edge, edgek, cl, ckf, ckfk, work, L, Lp, s, segf
 
@@ -1433,13 +1440,13 @@ namespace {
 template <bool EXT, bool RL>
 hipError_t fwd_go(const Plan& p, int s, const double* in0, size_t stride, const Batch& B, hipStream_t st)
 {
-    const dim3 grid(p.nworkf, B.n), block(64 * SEG_MAX);
+    const dim3 grid(p.nworkf4, B.n), block(64 * SEG_MAX);
     if (EXT)
         hipLaunchKernelGGL((k_contract_forward_ext<MT_FWD, RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
-                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
+                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, p.Lp, s, p.segf);
     else
         hipLaunchKernelGGL((k_contract_forward<MT_FWD, RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
-                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, p.Lp, s, p.segf);
+                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, p.Lp, s, p.segf);
     return hipGetLastError();
 }
 }  // namespace

@@ -44,7 +44,13 @@ struct Plan {
     double2* thtw = nullptr;    // exp(-i m' pi/N1)/(2 pi N1) at slot k = m' mod N1
     // contraction work lists (int2: (block start, first order)), dealt over the 8
     // XCDs by order and longest first; (-1, -1) entries are padding
-    int2* workf = nullptr; int nworkf = 0;   // forward: (l0, m0)
+    int2* workf = nullptr; int nworkf = 0;   // mixed-precision forward: (l0, m0)
+    // FP64 forward: SEG_MAX wave slots per workgroup, slot i of workgroup g at
+    // [g*SEG_MAX + i] = (l0, mb, seg | nseg << 8 | lead << 16 | barrier << 24, 0)
+    // for segment seg of the chain group (degrees l0 .., orders mb, mb+1) whose
+    // nseg segments sit in slots lead .. lead+nseg-1 of the same workgroup;
+    // (-1, 0, barrier << 24, 0) marks an empty slot
+    int4* workf4 = nullptr; int nworkf4 = 0;   // workgroups
     int2* worki = nullptr; int nworki = 0;   // inverse, one order per group: (n0, m)
     // Chain segmentation.  The forward splits every row recursion at the global
     // boundaries n = j*segf (j = 1..nsegf-1); ckf holds, for boundary j at

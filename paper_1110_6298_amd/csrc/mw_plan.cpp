@@ -143,6 +143,8 @@ int upload(const std::vector<T>& h, T** d, size_t& bytes, std::string& err)
 
 }  // namespace
 
+static std::vector<int4> forward_work(const Plan& p);   // below
+
 int build_plan(int L, Plan& p, std::string& err)
 {
     p = Plan();
@@ -353,6 +355,9 @@ int build_plan(int L, Plan& p, std::string& err)
         deal(per, wf);
         p.nworkf = (int)wf.size();
         if ((rc = upload(wf, &p.workf, p.bytes, err))) return rc;
+        const std::vector<int4> wf4 = forward_work(p);
+        p.nworkf4 = (int)(wf4.size() / SEG_MAX);
+        if ((rc = upload(wf4, &p.workf4, p.bytes, err))) return rc;
         // mixed-precision inverse: one order per group (the FP64 inverse packs
         // its segments per spin, see inverse_work)
         for (auto& v : per) v.clear();
@@ -373,78 +378,107 @@ int build_plan(int L, Plan& p, std::string& err)
 void free_plan(Plan& p)
 {
     void* ptrs[] = {p.sqtab, p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.whatc, p.thtw,
-                    p.workf, p.worki, p.ckf, p.ckfk, p.cki, p.ckik};
+                    p.workf, p.workf4, p.worki, p.ckf, p.ckfk, p.cki, p.ckik};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p = Plan();
 }
 
-// Work list of the FP64 inverse contraction (layout in mw_internal.h).  Chain
-// group (n0, m0) starts its pairs at lstart = max(n0, m0) rounded down to even;
-// every chain start (n, m or |s|) lies below lA, so its first segment runs to
-// the first boundary j*segi >= max(lA, lstart+2) and the others follow the
-// boundaries.  Groups are dealt to the 8 XCDs by order pair, longest first.
-// Their segments are packed into workgroups of SEGI_MAX wave slots: groups of
-// one segment four to a workgroup (no barrier, every wave exits when done),
-// groups of several segments first-fit into the last few open workgroups (so
-// that waves meeting at the reduction barrier have similar lengths).
-static std::vector<int4> inverse_work(const Plan& p, int as)
+// Packing of the segments of chain groups into workgroups of `slots` wave slots
+// (layout of the resulting work list in mw_internal.h).  items[x] are the
+// groups dealt to XCD x, (a, b) = (first lane index, first order), with their
+// segment count, first-boundary index jb and the length that orders them.
+// Groups of one segment go four to a workgroup with no barrier (every wave
+// exits when done); groups of several segments are placed first-fit into the
+// last few open workgroups, so that waves meeting at the reduction barrier
+// have similar lengths.  Workgroups are ordered longest first per XCD and
+// dealt round-robin over the 8 XCDs.
+struct SegItem { int a, b, nseg, jb, len; };
+
+static std::vector<int4> pack_segments(std::vector<std::vector<SegItem>>& items, int slots)
 {
-    const int L = p.L, Lp = p.Lp, segi = p.segi, nsegi = p.nsegi;
-    struct Item { int n0, m0, nseg, jb, len; };
-    struct Group { int used, len; bool bar; int4 slot[SEGI_MAX]; };
-    std::vector<std::vector<Group>> per(8);
-    for (int x = 0; x < 8; ++x) {
-        std::vector<Item> items;
-        for (int n0 = 0; n0 < L; n0 += 64)
-            for (int m0 = 2 * x; m0 < L; m0 += 16) {
-                const int lstart = std::max(n0, m0) & ~1;
-                const int lA = std::max(std::max(n0 + 64, m0 + 2), as + 1);
-                const int jb = (std::max(lA, lstart + 2) + segi - 1) / segi;
-                const int nseg = (jb < nsegi) ? 1 + nsegi - jb : 1;
-                items.push_back(Item{n0, m0, nseg, jb, Lp - lstart});
-            }
-        std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.len > b.len; });
+    struct Group { int used, len; bool bar; int4 slot[SEGI_MAX > SEG_MAX ? SEGI_MAX : SEG_MAX]; };
+    std::vector<std::vector<Group>> per(items.size());
+    for (size_t x = 0; x < items.size(); ++x) {
+        std::vector<SegItem>& it = items[x];
+        std::stable_sort(it.begin(), it.end(), [](const SegItem& u, const SegItem& v) { return u.len > v.len; });
         std::vector<Group>& gs = per[x];
         std::vector<int> open;   // groups with free slots, oldest first
         constexpr int WINDOW = 4;
-        for (const Item& it : items) {
-            const bool bar = it.nseg > 1;
+        for (const SegItem& t : it) {
+            const bool bar = t.nseg > 1;
             int g = -1;
             for (int k = (int)open.size() - 1; k >= 0 && g < 0; --k) {
-                Group& c = gs[open[k]];
-                if (c.bar == bar && SEGI_MAX - c.used >= it.nseg) g = open[k];
+                const Group& c = gs[open[k]];
+                if (c.bar == bar && slots - c.used >= t.nseg) g = open[k];
             }
             if (g < 0) {
                 Group c;
                 c.used = 0;
-                c.len = it.len;
+                c.len = t.len;
                 c.bar = bar;
-                for (int i = 0; i < SEGI_MAX; ++i) c.slot[i] = make_int4(-1, 0, bar ? 1 << 24 : 0, 0);
+                for (int i = 0; i < slots; ++i) c.slot[i] = make_int4(-1, 0, bar ? 1 << 24 : 0, 0);
                 gs.push_back(c);
                 g = (int)gs.size() - 1;
                 open.push_back(g);
                 if ((int)open.size() > WINDOW) open.erase(open.begin());
             }
             Group& c = gs[g];
-            for (int w = 0; w < it.nseg; ++w)
-                c.slot[c.used + w] = make_int4(it.n0, it.m0, w | (it.nseg << 8) | (c.used << 16) | (bar ? 1 << 24 : 0),
-                                               it.jb);
-            c.used += it.nseg;
-            if (c.used == SEGI_MAX)
+            for (int w = 0; w < t.nseg; ++w)
+                c.slot[c.used + w] =
+                    make_int4(t.a, t.b, w | (t.nseg << 8) | (c.used << 16) | (bar ? 1 << 24 : 0), t.jb);
+            c.used += t.nseg;
+            if (c.used == slots)
                 for (size_t k = 0; k < open.size(); ++k)
                     if (open[k] == g) { open.erase(open.begin() + k); break; }
         }
-        std::stable_sort(gs.begin(), gs.end(), [](const Group& a, const Group& b) { return a.len > b.len; });
+        std::stable_sort(gs.begin(), gs.end(), [](const Group& u, const Group& v) { return u.len > v.len; });
     }
     size_t n = 0;
     for (auto& v : per) n = std::max(n, v.size());
     std::vector<int4> out;
-    out.reserve(n * 8 * SEGI_MAX);
+    out.reserve(n * per.size() * slots);
     for (size_t g = 0; g < n; ++g)
         for (auto& v : per)
-            for (int i = 0; i < SEGI_MAX; ++i) out.push_back(g < v.size() ? v[g].slot[i] : make_int4(-1, 0, 0, 0));
+            for (int i = 0; i < slots; ++i) out.push_back(g < v.size() ? v[g].slot[i] : make_int4(-1, 0, 0, 0));
     return out;
+}
+
+// FP64 inverse contraction: group (n0, m0) starts its pairs at lstart =
+// max(n0, m0) rounded down to even; every chain start (n, m or |s|) lies below
+// lA, so its first segment runs to the first boundary j*segi >= max(lA,
+// lstart+2) and the others follow the boundaries.  Dealt to XCDs by order pair.
+static std::vector<int4> inverse_work(const Plan& p, int as)
+{
+    const int L = p.L, Lp = p.Lp, segi = p.segi, nsegi = p.nsegi;
+    std::vector<std::vector<SegItem>> items(8);
+    for (int n0 = 0; n0 < L; n0 += 64)
+        for (int m0 = 0; m0 < L; m0 += 2) {
+            const int lstart = std::max(n0, m0) & ~1;
+            const int lA = std::max(std::max(n0 + 64, m0 + 2), as + 1);
+            const int jb = (std::max(lA, lstart + 2) + segi - 1) / segi;
+            const int nseg = (jb < nsegi) ? 1 + nsegi - jb : 1;
+            items[(m0 / 2) & 7].push_back(SegItem{n0, m0, nseg, jb, Lp - lstart});
+        }
+    return pack_segments(items, SEGI_MAX);
+}
+
+// FP64 forward contraction: group (l0, mb) runs the row recursions from nmax =
+// min(l0+63, L-1) down to 0, in segments w = 0 .. jtop (jtop = nmax/segf) of
+// n in [w*segf, (w+1)*segf); the top one also starts the lanes.  Dealt to XCDs
+// by order pair; ordered by the longest segment.
+static std::vector<int4> forward_work(const Plan& p)
+{
+    const int L = p.L, segf = p.segf;
+    std::vector<std::vector<SegItem>> items(8);
+    for (int l0 = 0; l0 < L; l0 += 64) {
+        const int nmax = std::min(l0 + 63, L - 1);
+        const int jtop = nmax / segf;
+        const int len = std::max(nmax - jtop * segf + 1, jtop > 0 ? segf : 0);
+        for (int mb = 0; mb <= nmax; mb += MT_FWD)
+            items[(mb / MT_FWD) & 7].push_back(SegItem{l0, mb, jtop + 1, 0, len});
+    }
+    return pack_segments(items, SEG_MAX);
 }
 
 // Delta^l_{n,|s|} for n <= l < L by the upward l-recursion in long double,
