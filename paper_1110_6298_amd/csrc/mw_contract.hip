@@ -463,7 +463,7 @@ __device__ __forceinline__ void contract_forward_body(
 #define MW_FORWARD_PASS Hp0, hstride, B, Rtg, edge, edgek, cl, ckf, ckfk, work, L, Lp, s, segf
 
 template <int MT, bool RL>
-__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(5))) void k_contract_forward(
+__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(4))) void k_contract_forward(
     MW_FORWARD_ARGS)
 {
     contract_forward_body<MT, false, RL>(MW_FORWARD_PASS);
