@@ -23,8 +23,8 @@ PEAK_FP64_VALU = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 # read for a plain copy of known size (profiles/traffic_roundtrip_L512_s2.md).
 # Valid only while the kernel and plan sources are unchanged: keyed by their SHA-256.
 TRAFFIC = {
-    ("contract_inverse", 512, 2): {"bytes": 85378199, "source_sha256": "7d87655d2323e857de90d5dfcdfdc59fcd25d389657dfd09c9a66e6335358169"},
-    ("contract_forward", 512, 2): {"bytes": 60644449, "source_sha256": "7d87655d2323e857de90d5dfcdfdc59fcd25d389657dfd09c9a66e6335358169"},
+    ("contract_inverse", 512, 2): {"bytes": 47938274, "source_sha256": "06feabc51d2f8679cfd3dfea3dd85b0ad033ab98885ea31e0fd3e79b19f75c5c"},
+    ("contract_forward", 512, 2): {"bytes": 52271500, "source_sha256": "06feabc51d2f8679cfd3dfea3dd85b0ad033ab98885ea31e0fd3e79b19f75c5c"},
 }
 KERNEL_SOURCES = ("paper_1110_6298_amd/csrc/mw_contract.hip", "paper_1110_6298_amd/csrc/mw_plan.cpp")
 
