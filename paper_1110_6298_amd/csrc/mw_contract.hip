@@ -309,33 +309,36 @@ __device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscale
         for (int c = 0; c < MT; ++c) {
             const int m = mb + c;
             const bool ok = valid && m <= l;
-            st.start[c] = ok ? edge[(size_t)l * (l + 1) / 2 + m] : 0.0;
-            st.startk[c] = (EXT && ok) ? edgek[(size_t)l * (l + 1) / 2 + m] : 0;
+            // the table holds (-1)^(l-m) Delta^l_{m,l}
+            st.start[c] = ok ? sgn(l - m) * edge[(size_t)m * L + l] : 0.0;
+            st.startk[c] = (EXT && ok) ? edgek[(size_t)m * L + l] : 0;
         }
         const bool oks = valid && as <= l;
-        st.starts = oks ? edge[(size_t)le * (le + 1) / 2 + as] : 0.0;
-        st.startks = (EXT && oks) ? edgek[(size_t)le * (le + 1) / 2 + as] : 0;
+        st.starts = oks ? sgn(le - as) * edge[(size_t)as * L + le] : 0.0;
+        st.startks = (EXT && oks) ? edgek[(size_t)as * L + le] : 0;
         const int ktop = nmax >> 1, ntop = 2 * ktop + 1;   // n = L (odd L) is a zero pad step
         st.q = (double)(le + ntop) * (double)(le - ntop + 1);
         st.dq = 2.0 * (double)(ntop - 1);
         g = FwdSeg{ktop, l0 >> 1, (jtop * segf) >> 1, true};
     } else if (w < jtop) {
         const int nc = (w + 1) * segf;
-        const size_t base = (size_t)w * T + (size_t)le * (le + 1) / 2;
+        const size_t base = (size_t)w * T;
 #pragma unroll
         for (int c = 0; c < MT; ++c) {
             const int m = mb + c;
             if (valid && m <= l) {
-                double2 v = ckf[base + m];
+                const size_t i = base + tri_m(m, l, L);
+                double2 v = ckf[i];
                 int kk = 0;
-                if (EXT) { const int2 kv = ckfk[base + m]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
+                if (EXT) { const int2 kv = ckfk[i]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
                 st.dc[c] = v.x; st.dn[c] = v.y; st.k[c] = kk;
             }
         }
         if (valid && as <= l) {
-            double2 v = ckf[base + as];
+            const size_t i = base + tri_m(as, l, L);
+            double2 v = ckf[i];
             int kk = 0;
-            if (EXT) { const int2 kv = ckfk[base + as]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
+            if (EXT) { const int2 kv = ckfk[i]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
             st.sc = v.x; st.sn = v.y; st.ks = kk;
         }
         st.anext = sqrt(fmax(0.0, (double)(le + nc) * (double)(le - nc + 1)));
@@ -667,15 +670,8 @@ __device__ __forceinline__ InvSeg inv_setup(InvLane<EXT>& st, bool& anyscaled, c
     InvSeg g{0, 0, -1, false};
     if (w == 0) {
         if (valid) {
-            if (n >= m) {
-                const size_t i = (size_t)n * (n + 1) / 2 + m;
-                st.start = ((n - m) & 1) ? -edge[i] : edge[i];
-                if (EXT) st.startk = edgek[i];
-            } else {
-                const size_t i = (size_t)m * (m + 1) / 2 + n;
-                st.start = edge[i];
-                if (EXT) st.startk = edgek[i];
-            }
+            st.start = edge[(size_t)m * L + n];
+            if (EXT) st.startk = edgek[(size_t)m * L + n];
             // spin chain: from the table at lstart when already running, else injected
             if (st.l0s <= lstart) {
                 double v1 = stab[(size_t)lstart * L + n], v0 = 0.0;
@@ -704,7 +700,7 @@ __device__ __forceinline__ InvSeg inv_setup(InvLane<EXT>& st, bool& anyscaled, c
         const int jj = geo.jb + w - 1;
         const int c = jj * segi;
         if (valid) {
-            const size_t i = ckoff.off[jj] + (size_t)n * (c + 1) + m;
+            const size_t i = ckoff.off[jj] + (size_t)m * (c + 1) + n;
             double2 v = cki[i];
             int kk = 0;
             if (EXT) { const int2 kv = ckik[i]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
@@ -878,15 +874,8 @@ __device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled,
             for (int c = 0; c < 2; ++c) {
                 const int m = m0 + c;
                 if (m >= L) continue;
-                if (n >= m) {
-                    const size_t i = (size_t)n * (n + 1) / 2 + m;
-                    st.start[c] = ((n - m) & 1) ? -edge[i] : edge[i];
-                    if (EXT) st.startk[c] = edgek[i];
-                } else {
-                    const size_t i = (size_t)m * (m + 1) / 2 + n;
-                    st.start[c] = edge[i];
-                    if (EXT) st.startk[c] = edgek[i];
-                }
+                st.start[c] = edge[(size_t)m * L + n];
+                if (EXT) st.startk[c] = edgek[(size_t)m * L + n];
             }
             // spin chain: from the table at lstart when already running, else injected
             if (st.l0s <= lstart) {
@@ -919,7 +908,7 @@ __device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled,
             for (int c = 0; c < 2; ++c) {
                 const int m = m0 + c;
                 if (m >= L) continue;
-                const size_t i = ckoff.off[jj] + (size_t)n * (cdeg + 1) + m;
+                const size_t i = ckoff.off[jj] + (size_t)m * (cdeg + 1) + n;
                 double2 v = cki[i];
                 int kk = 0;
                 if (EXT) { const int2 kv = ckik[i]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }

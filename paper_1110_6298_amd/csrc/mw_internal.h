@@ -22,6 +22,12 @@ constexpr int EXT_LIMIT = 900;
 constexpr int SEG_MAX = 4;
 constexpr int SEGI_MAX = 4;
 
+// Order-major index of the triangle l >= m of an L x L table (see Plan::edgem).
+__host__ __device__ inline size_t tri_m(int m, int l, int L)
+{
+    return (size_t)m * L - (size_t)m * (m - 1) / 2 + (size_t)(l - m);
+}
+
 // Band-limit-dependent constants, built once per (device, L) on the host in
 // long double and uploaded.  All device pointers are owned by the plan.
 struct Plan {
@@ -31,8 +37,13 @@ struct Plan {
     // Wigner tables
     double2* sqtab = nullptr;   // (sqrt k, 1/sqrt k), k = 0..2L+2; entry 0 = (0, 0)
     double* rtab = nullptr;     // rtab[j] = 1/sqrt(j-1) for j >= 2, rtab[0] = rtab[1] = 0; 2L+8 entries
-    double* edge = nullptr;     // Delta^l_{m,l}, packed l(l+1)/2 + m, as mantissa * 2^(EXT_STEP*k)
-    int* edgek = nullptr;       // k of each edge entry
+    // Chain start values, order-major and square: at [m*L + n] the value of
+    // Delta^{l0}_{n,m} at l0 = max(n, m), i.e. (-1)^(n-m) Delta^n_{m,n} for n >= m
+    // and Delta^m_{n,m} for n < m (edge values, Delta^l_{m,l} = 2^-l sqrt(C(2l, l+m))),
+    // as mantissa * 2^(EXT_STEP*k).  64 consecutive n (or l) of one order are one
+    // contiguous read.
+    double* edge = nullptr;
+    int* edgek = nullptr;       // k of each entry
     double2* lco = nullptr;     // l-recursion factors (Pu_m(l), Qu_m(l)) at [m*Lp + l] (0 for l >= L)
     double* cl = nullptr;       // sqrt((2l+1)/(4 pi))
     // Fourier tables
@@ -54,10 +65,10 @@ struct Plan {
     int2* worki = nullptr; int nworki = 0;   // inverse, one order per group: (n0, m)
     // Chain segmentation.  The forward splits every row recursion at the global
     // boundaries n = j*segf (j = 1..nsegf-1); ckf holds, for boundary j at
-    // [(j-1)*L(L+1)/2 + l(l+1)/2 + m], the pair (Delta^l_{m,n-1}, Delta^l_{m,n})
+    // [(j-1)*L(L+1)/2 + tri_m(m, l)], the pair (Delta^l_{m,n-1}, Delta^l_{m,n})
     // as mantissas with exponent levels ckfk.  The inverse splits every degree
     // recursion at l = j*segi; cki holds, for boundary j, the pair
-    // (Delta^{c-1}_{n,m}, Delta^{c}_{n,m}), c = j*segi, at cki_off[j] + n*(c+1) + m
+    // (Delta^{c-1}_{n,m}, Delta^{c}_{n,m}), c = j*segi, at cki_off[j] + m*(c+1) + n
     // (n, m <= c), with levels ckik.
     int segf = 0, nsegf = 1, segi = 0, nsegi = 1;
     double2* ckf = nullptr; int2* ckfk = nullptr;

@@ -176,8 +176,19 @@ int build_plan(int L, Plan& p, std::string& err)
         split_ext(E[i], ex[i], ek[i]);
         if (ek[i]) p.ext = true;
     }
-    if ((rc = upload(ex, &p.edge, p.bytes, err))) return rc;
-    if ((rc = upload(ek, &p.edgek, p.bytes, err))) return rc;
+    {
+        std::vector<double> sq2((size_t)L * L);
+        std::vector<int> sk2((size_t)L * L);
+        for (int m = 0; m < L; ++m)
+            for (int n = 0; n < L; ++n) {
+                const size_t i = (n >= m) ? (size_t)n * (n + 1) / 2 + m : (size_t)m * (m + 1) / 2 + n;
+                const bool neg = n >= m && ((n - m) & 1);
+                sq2[(size_t)m * L + n] = neg ? -ex[i] : ex[i];
+                sk2[(size_t)m * L + n] = ek[i];
+            }
+        if ((rc = upload(sq2, &p.edge, p.bytes, err))) return rc;
+        if ((rc = upload(sk2, &p.edgek, p.bytes, err))) return rc;
+    }
 
     // l-recursion factors at beta = pi/2, split into an m part (this table) and an
     // n part formed in the kernel:
@@ -289,7 +300,7 @@ int build_plan(int L, Plan& p, std::string& err)
                         int k0, k1;
                         split_signed(c0[l], x0, k0);
                         split_signed(c1[l], x1, k1);
-                        const size_t i = (size_t)(j - 1) * T + (size_t)l * (l + 1) / 2 + m;
+                        const size_t i = (size_t)(j - 1) * T + tri_m(m, l, L);
                         ck[i] = make_double2(x0, x1);
                         ckk[i] = make_int2(k0, k1);
                     }
@@ -322,8 +333,8 @@ int build_plan(int L, Plan& p, std::string& err)
                         int k0, k1;
                         split_signed(v0, x0, k0);
                         split_signed(v1, x1, k1);
-                        ck[p.cki_off[j] + (size_t)n * (c + 1) + m] = make_double2(x0, x1);
-                        ckk[p.cki_off[j] + (size_t)n * (c + 1) + m] = make_int2(k0, k1);
+                        ck[p.cki_off[j] + (size_t)m * (c + 1) + n] = make_double2(x0, x1);
+                        ckk[p.cki_off[j] + (size_t)m * (c + 1) + n] = make_int2(k0, k1);
                     }
                 }
             }
