@@ -554,66 +554,6 @@ __global__ __launch_bounds__(256) void k_real_fold(Batch B, int L)
     y[c - m] = make_double2(0.0, 0.0);
 }
 
-template <bool EXT>
-struct InvLane {
-    double dc, dp;             // Delta^l_{n,m}, Delta^{l-1}_{n,m}
-    double sc, sp;             // Delta^l_{n,|s|}, Delta^{l-1}_{n,|s|}
-    double2 ap, am;
-    int k, ks;
-    double q, dq;              // (l+1)^2 - n^2 and 2l+3 of the current step (exact)
-    double sprev;              // sqrt(l^2 - n^2)
-    double start, starts;
-    int startk, startks, lz, l0s;
-};
-
-template <bool EXT, bool INJ>
-__device__ __forceinline__ void inv_inject(InvLane<EXT>& st, int l, int lstart, bool& anyscaled)
-{
-    if (INJ) {
-        if (l == st.lz) { st.dc = st.start; if (EXT) st.k = st.startk; }
-        if (l == st.l0s && st.l0s > lstart) { st.sc = st.starts; if (EXT) st.ks = st.startks; }
-        if (EXT) anyscaled = __any(st.k > 0 || st.ks > 0);
-    }
-}
-
-// Delta^l_{n,m} * Delta^l_{n,|s|} of the current step (0 while a chain is scaled).
-template <bool EXT>
-__device__ __forceinline__ double inv_product(const InvLane<EXT>& st)
-{
-    double d = st.dc, sv = st.sc;
-    if (EXT) { d = (st.k == 0) ? d : 0.0; sv = (st.ks == 0) ? sv : 0.0; }
-    return d * sv;
-}
-
-// Recursion from degree l to l+1 with rs = 1/sqrt((l+1)^2 - n^2) and the
-// uniform factors (Pu_m, Qu_m), (Pu_s, Qu_s) of this degree.
-template <bool EXT>
-__device__ __forceinline__ void inv_advance(InvLane<EXT>& st, double nd, double pum, double qum, double pus,
-                                            double qus, double rs, bool& anyscaled)
-{
-    // X_n(l) = n/sqrt((l+1)^2-n^2), Y_n(l) = sqrt(l^2-n^2)/sqrt((l+1)^2-n^2); harmless at l = L-1
-    const double xn = nd * rs;
-    const double yn = st.sprev * rs;
-    st.sprev = st.q * rs;
-    st.q += st.dq;
-    st.dq += 2.0;
-    {
-        const double dn = fma(pum * xn, st.dc, (qum * yn) * st.dp);
-        st.dp = st.dc;
-        st.dc = dn;
-    }
-    {
-        const double sn = fma(pus * xn, st.sc, (qus * yn) * st.sp);
-        st.sp = st.sc;
-        st.sc = sn;
-    }
-    if (EXT && anyscaled) {
-        if (st.k > 0 && fabs(st.dc) > EXT_UP) { st.dc *= EXT_DOWN; st.dp *= EXT_DOWN; st.k -= 1; }
-        if (st.ks > 0 && fabs(st.sc) > EXT_UP) { st.sc *= EXT_DOWN; st.sp *= EXT_DOWN; st.ks -= 1; }
-        anyscaled = __any(st.k > 0 || st.ks > 0);
-    }
-}
-
 struct InvR { double2 a, b; };             // 1/sqrt of l+1-n .. l+2-n and l+1+n .. l+2+n
 
 __device__ __forceinline__ InvR inv_load_r(const double* __restrict__ Rt, int ne, int j)
@@ -636,89 +576,6 @@ struct InvSeg { int jfrom, jA, jlast; bool active; };
 // boundary j*segi >= max(lA, lstart+2) (every chain start lies below lA), wave
 // w >= 1 runs the w-th following segment from the checkpoint planes.
 struct InvGeo { int lstart, lA, jb, nseg; };
-
-__device__ __forceinline__ InvGeo inv_geometry(int n0, int m, int as, int segi, int nsegi)
-{
-    InvGeo g;
-    g.lstart = max(n0, m) & ~1;
-    g.lA = max(max(n0 + 64, m + 1), as + 1);
-    g.jb = (max(g.lA, g.lstart + 2) + segi - 1) / segi;
-    g.nseg = (g.jb < nsegi) ? 1 + nsegi - g.jb : 1;
-    return g;
-}
-
-template <bool EXT>
-__device__ __forceinline__ InvSeg inv_setup(InvLane<EXT>& st, bool& anyscaled, const InvGeo& geo, int w, int n,
-                                            int m, int L, int Lp, int as, int segi,
-                                            const double* __restrict__ edge, const int* __restrict__ edgek,
-                                            const double* __restrict__ stab, const int* __restrict__ stabk,
-                                            const double2* __restrict__ cki, const int2* __restrict__ ckik,
-                                            const CkOff& ckoff)
-{
-    const bool valid = n < L;
-    const int ne = valid ? n : L - 1;
-    const int lstart = geo.lstart;
-    const int jend = (Lp >> 1) - 1;
-    st.dc = 0.0; st.dp = 0.0; st.k = 0;
-    st.sc = 0.0; st.sp = 0.0; st.ks = 0; st.starts = 0.0; st.startks = 0;
-    st.start = 0.0; st.startk = 0;
-    st.ap = st.am = make_double2(0.0, 0.0);
-    st.lz = max(n, m);
-    st.l0s = max(n, as);
-    st.sprev = 0.0; st.q = 0.0; st.dq = 0.0;
-    anyscaled = EXT;
-    InvSeg g{0, 0, -1, false};
-    if (w == 0) {
-        if (valid) {
-            st.start = edge[(size_t)m * L + n];
-            if (EXT) st.startk = edgek[(size_t)m * L + n];
-            // spin chain: from the table at lstart when already running, else injected
-            if (st.l0s <= lstart) {
-                double v1 = stab[(size_t)lstart * L + n], v0 = 0.0;
-                int k1 = EXT ? stabk[(size_t)lstart * L + n] : 0, k0 = k1;
-                if (lstart >= 1) {
-                    v0 = stab[(size_t)(lstart - 1) * L + n];
-                    k0 = EXT ? stabk[(size_t)(lstart - 1) * L + n] : 0;
-                }
-                int kk;
-                ck_level<EXT>(v0, v1, k0, k1, kk);
-                st.sc = v1; st.sp = v0; st.ks = kk;
-            } else if (st.l0s < L) {
-                st.starts = stab[(size_t)st.l0s * L + n];
-                st.startks = EXT ? stabk[(size_t)st.l0s * L + n] : 0;
-            }
-        }
-        // sqrt(l^2 - n^2) at l = lstart, and q = (l+1)^2 - n^2 of the first step
-        st.sprev = (lstart >= ne) ? sqrt((double)(lstart - ne) * (double)(lstart + ne)) : 0.0;
-        st.q = (double)(lstart + 1 - ne) * (double)(lstart + 1 + ne);
-        st.dq = 2.0 * (double)lstart + 3.0;
-        const int jlast = (geo.nseg > 1) ? ((geo.jb * segi) >> 1) - 1 : jend;
-        const int jA = min(jlast, (geo.lA - 1) >> 1);
-        g = InvSeg{lstart >> 1, jA, jlast, true};
-    } else if (w < geo.nseg) {
-        // segment from degree c = (jb+w-1)*segi, started from the checkpoint plane
-        const int jj = geo.jb + w - 1;
-        const int c = jj * segi;
-        if (valid) {
-            const size_t i = ckoff.off[jj] + (size_t)m * (c + 1) + n;
-            double2 v = cki[i];
-            int kk = 0;
-            if (EXT) { const int2 kv = ckik[i]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
-            st.dp = v.x; st.dc = v.y; st.k = kk;
-            double v1 = stab[(size_t)c * L + n], v0 = stab[(size_t)(c - 1) * L + n];
-            int k1 = EXT ? stabk[(size_t)c * L + n] : 0, k0 = EXT ? stabk[(size_t)(c - 1) * L + n] : 0;
-            ck_level<EXT>(v0, v1, k0, k1, kk);
-            st.sc = v1; st.sp = v0; st.ks = kk;
-        }
-        st.sprev = sqrt(fmax(0.0, (double)(c - ne) * (double)(c + ne)));
-        st.q = (double)(c + 1 - ne) * (double)(c + 1 + ne);
-        st.dq = 2.0 * (double)c + 3.0;
-        if (EXT) anyscaled = __any(st.k > 0 || st.ks > 0);
-        const int jlast = (w < geo.nseg - 1) ? (((jj + 1) * segi) >> 1) - 1 : jend;
-        g = InvSeg{c >> 1, (c >> 1) - 1, jlast, true};
-    }
-    return g;
-}
 
 // ===========================================================================
 // FP64 inverse contraction, two orders per wavefront.  The orders m0, m0+1 of a
@@ -770,8 +627,12 @@ __device__ __forceinline__ void inv2_load(InvS2& u, const Inv2Rows& w, int l)
 }
 
 
-template <bool EXT, bool INJ, bool RL>
-__device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, double nd, const InvS2& u, double rs,
+// One step l of both orders' chains and the spin chain: injections, the
+// products pr[c] = Delta^l_{n,m_c} Delta^l_{n,|s|} of this step, then the
+// recursion to l+1.  (c0, c1, cs): (Pu, Qu) of the two orders and of |s| at l.
+template <bool EXT, bool INJ>
+__device__ __forceinline__ void inv2_core(InvLane2<EXT>& st, int l, int lstart, double nd, const double2& c0,
+                                          const double2& c1, const double2& cs, double rs, double (&pr)[2],
                                           bool& anyscaled)
 {
     if (INJ) {
@@ -785,16 +646,9 @@ __device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, 
     if (EXT) sv = (st.ks == 0) ? sv : 0.0;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        const double4 f = c ? u.f1 : u.f0;
         double d = st.dc[c];
         if (EXT) d = (st.k[c] == 0) ? d : 0.0;
-        const double pr = d * sv;
-        st.ap[c].x = fma(pr, f.x, st.ap[c].x);
-        st.ap[c].y = fma(pr, f.y, st.ap[c].y);
-        if (!RL) {
-            st.am[c].x = fma(pr, f.z, st.am[c].x);
-            st.am[c].y = fma(pr, f.w, st.am[c].y);
-        }
+        pr[c] = d * sv;
     }
     // X_n(l) = n/sqrt((l+1)^2-n^2), Y_n(l) = sqrt(l^2-n^2)/sqrt((l+1)^2-n^2); harmless at l = L-1
     const double xn = nd * rs;
@@ -804,13 +658,13 @@ __device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, 
     st.dq += 2.0;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        const double2 pq = c ? u.c1 : u.c0;
+        const double2 pq = c ? c1 : c0;
         const double dn = fma(pq.x * xn, st.dc[c], (pq.y * yn) * st.dp[c]);
         st.dp[c] = st.dc[c];
         st.dc[c] = dn;
     }
     {
-        const double sn = fma(u.cs.x * xn, st.sc, (u.cs.y * yn) * st.sp);
+        const double sn = fma(cs.x * xn, st.sc, (cs.y * yn) * st.sp);
         st.sp = st.sc;
         st.sc = sn;
     }
@@ -820,6 +674,24 @@ __device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, 
             if (st.k[c] > 0 && fabs(st.dc[c]) > EXT_UP) { st.dc[c] *= EXT_DOWN; st.dp[c] *= EXT_DOWN; st.k[c] -= 1; }
         if (st.ks > 0 && fabs(st.sc) > EXT_UP) { st.sc *= EXT_DOWN; st.sp *= EXT_DOWN; st.ks -= 1; }
         anyscaled = __any(st.k[0] > 0 || st.k[1] > 0 || st.ks > 0);
+    }
+}
+
+template <bool EXT, bool INJ, bool RL>
+__device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, double nd, const InvS2& u, double rs,
+                                          bool& anyscaled)
+{
+    double pr[2];
+    inv2_core<EXT, INJ>(st, l, lstart, nd, u.c0, u.c1, u.cs, rs, pr, anyscaled);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const double4 f = c ? u.f1 : u.f0;
+        st.ap[c].x = fma(pr[c], f.x, st.ap[c].x);
+        st.ap[c].y = fma(pr[c], f.y, st.ap[c].y);
+        if (!RL) {
+            st.am[c].x = fma(pr[c], f.z, st.am[c].x);
+            st.am[c].y = fma(pr[c], f.w, st.am[c].y);
+        }
     }
 }
 
@@ -1244,27 +1116,36 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
     }
 }
 
-struct InvC { double4 cm, cs; };   // pair (l, l+1): (Pu,Qu)_m, (Pu,Qu)_s
+// ---------------------------------------------------------------------------
+// Mixed-precision inverse contraction, two orders per wavefront: the chains of
+// the FP64 two-order kernel (inv2_core), with each step's products rounded to
+// FP32 and accumulated by v_mfma_f32_4x4x1_16b_f32 against the FP32 stream of
+// every map of the group (windows of WIN degrees in LDS, as in the one-order
+// kernel).  Work list: the packed segment list of the spin table.
+struct InvC2 { double4 c0, c1, cs; };   // pair (l, l+1): (Pu,Qu) of m0, of m0+1 and of |s|
 
-__device__ __forceinline__ void inv_load_c(InvC& u, const double2* __restrict__ lco, int m, int as, int Lp, int j)
+__device__ __forceinline__ void inv2m_load_c(InvC2& u, const Inv2Rows& w, int j)
 {
-    u.cm = *(const double4*)(lco + (size_t)m * Lp + 2 * j);
-    u.cs = *(const double4*)(lco + (size_t)as * Lp + 2 * j);
+    const unsigned lc = (unsigned)(2 * j) * 16u;
+    u.c0 = *(const double4*)(w.c + (w.c0 + lc));
+    u.c1 = *(const double4*)(w.c + (w.c1 + lc));
+    u.cs = *(const double4*)(w.c + (w.cs + lc));
 }
 
-// Inverse window q (l in [WIN*q, WIN*q + WIN)): rows (b, comp) of WIN floats,
-// 4G rows, held as 2G float2 values... i.e. G per lane of the wave.
+// Window q of the group: rows r = (b*2 + c)*4 + comp (map b, order m0+c, stream
+// component comp) of WIN floats; each lane holds 2G float2 of them.
 template <int G>
-struct InvWin { fv2 v[G]; };
+struct InvWin2 { fv2 v[2 * G]; };
 
 template <int G>
-__device__ __forceinline__ void inv_win_load(InvWin<G>& r, const MixMaps& maps, int m, int q, int lane)
+__device__ __forceinline__ void inv2m_win_load(InvWin2<G>& r, const MixMaps& maps, int m0, int q, int lane)
 {
 #pragma unroll
-    for (int t = 0; t < G; ++t) {
+    for (int t = 0; t < 2 * G; ++t) {
         const int e = lane + 64 * t;                  // float2 index in the window, 16 per row
         const int row = e >> 4, l = WIN * q + 2 * (e & 15);
-        const int comp = row & 3, b = row >> 2;
+        const int comp = row & 3, c = (row >> 2) & 1, b = row >> 3;
+        const int m = m0 + c;
         r.v[t] = fv2{0.0f, 0.0f};
         if (b < maps.n) {
             const int Lb = maps.L[b];
@@ -1275,150 +1156,177 @@ __device__ __forceinline__ void inv_win_load(InvWin<G>& r, const MixMaps& maps, 
 }
 
 template <bool EXT, bool INJ, int G>
-__device__ __forceinline__ void inv_mix_pair(InvLane<EXT>& st, v4f (&acc)[G], int j, int lstart, double nd,
-                                             const InvC& u, const InvR& r, const float* __restrict__ win, int comp,
-                                             bool& anyscaled)
+__device__ __forceinline__ void inv2m_pair(InvLane2<EXT>& st, v4f (&acc)[2][G], int j, int lstart, double nd,
+                                           const InvC2& u, const InvR& r, const float* __restrict__ win, int comp,
+                                           bool& anyscaled)
 {
     const int l = 2 * j;
-    inv_inject<EXT, INJ>(st, l, lstart, anyscaled);
-    const float k0 = (float)inv_product<EXT>(st);
-    inv_advance<EXT>(st, nd, u.cm.x, u.cm.y, u.cs.x, u.cs.y, r.a.x * r.b.x, anyscaled);
-    inv_inject<EXT, INJ>(st, l + 1, lstart, anyscaled);
-    const float k1 = (float)inv_product<EXT>(st);
-    inv_advance<EXT>(st, nd, u.cm.z, u.cm.w, u.cs.z, u.cs.w, r.a.y * r.b.y, anyscaled);
+    double p0[2], p1[2];
+    inv2_core<EXT, INJ>(st, l, lstart, nd, make_double2(u.c0.x, u.c0.y), make_double2(u.c1.x, u.c1.y),
+                        make_double2(u.cs.x, u.cs.y), r.a.x * r.b.x, p0, anyscaled);
+    inv2_core<EXT, INJ>(st, l + 1, lstart, nd, make_double2(u.c0.z, u.c0.w), make_double2(u.c1.z, u.c1.w),
+                        make_double2(u.cs.z, u.cs.w), r.a.y * r.b.y, p1, anyscaled);
     const int off = l - WIN * (j / (WIN / 2));   // degree l within its window
 #pragma unroll
-    for (int b = 0; b < G; ++b) {
-        const fv2 a = *(const fv2*)(win + (b * 4 + comp) * WIN + off);   // degrees l, l+1
-        acc[b] = mfma4(a.x, k0, acc[b]);
-        acc[b] = mfma4(a.y, k1, acc[b]);
+    for (int c = 0; c < 2; ++c) {
+        const float k0 = (float)p0[c], k1 = (float)p1[c];
+#pragma unroll
+        for (int b = 0; b < G; ++b) {
+            const fv2 a = *(const fv2*)(win + ((b * 2 + c) * 4 + comp) * WIN + off);   // degrees l, l+1
+            acc[c][b] = mfma4(a.x, k0, acc[c][b]);
+            acc[c][b] = mfma4(a.y, k1, acc[c][b]);
+        }
     }
 }
 
 template <bool EXT, int G>
-__device__ __forceinline__ void inv_mix_segment(InvLane<EXT>& st, v4f (&acc)[G], const InvSeg& g, int jend,
-                                                int lstart, int ne, double nd, int m, int as, int Lp,
-                                                const double2* __restrict__ lco, const double* __restrict__ Rt,
-                                                float* __restrict__ win, const MixMaps& maps, int lane,
-                                                bool& anyscaled)
+__device__ __forceinline__ void inv2m_segment(InvLane2<EXT>& st, v4f (&acc)[2][G], const InvSeg& g, int jend,
+                                              int lstart, int ne, double nd, int m0, const Inv2Rows& rows,
+                                              const double* __restrict__ Rt, float* __restrict__ win,
+                                              const MixMaps& maps, int lane, bool& anyscaled)
 {
     constexpr int PW = WIN / 2;   // pairs per window
     const int comp = lane & 3;
-    InvWin<G> nxt;
-    inv_win_load<G>(nxt, maps, m, g.jfrom / PW, lane);
-    InvC un;
-    inv_load_c(un, lco, m, as, Lp, g.jfrom);
+    InvWin2<G> nxt;
+    inv2m_win_load<G>(nxt, maps, m0, g.jfrom / PW, lane);
+    InvC2 un;
+    inv2m_load_c(un, rows, g.jfrom);
     InvR rn = inv_load_r(Rt, ne, g.jfrom);
     auto enter = [&](int j) {
         if (j == g.jfrom || (j % PW) == 0) {          // entering window j / PW
-            win_store<G>(win, nxt.v, lane);
-            if (j / PW < g.jlast / PW) inv_win_load<G>(nxt, maps, m, j / PW + 1, lane);
+            win_store<2 * G>(win, nxt.v, lane);
+            if (j / PW < g.jlast / PW) inv2m_win_load<G>(nxt, maps, m0, j / PW + 1, lane);
         }
     };
     int j = g.jfrom;
     for (; j <= min(g.jA, g.jlast); ++j) {            // pairs with chain starts
         enter(j);
-        wait_scalar(un.cm.x);
-        const InvC u = un;
+        wait_scalar(un.c0.x);
+        const InvC2 u = un;
         const InvR r = rn;
         const int jn = min(j + 1, jend);
-        inv_load_c(un, lco, m, as, Lp, jn);
+        inv2m_load_c(un, rows, jn);
         rn = inv_load_r(Rt, ne, jn);
-        inv_mix_pair<EXT, true, G>(st, acc, j, lstart, nd, u, r, win, comp, anyscaled);
+        inv2m_pair<EXT, true, G>(st, acc, j, lstart, nd, u, r, win, comp, anyscaled);
     }
     for (; j <= g.jlast; ++j) {
         enter(j);
-        wait_scalar(un.cm.x);
-        const InvC u = un;
+        wait_scalar(un.c0.x);
+        const InvC2 u = un;
         const InvR r = rn;
         const int jn = min(j + 1, jend);
-        inv_load_c(un, lco, m, as, Lp, jn);
+        inv2m_load_c(un, rows, jn);
         rn = inv_load_r(Rt, ne, jn);
-        inv_mix_pair<EXT, false, G>(st, acc, j, lstart, nd, u, r, win, comp, anyscaled);
+        inv2m_pair<EXT, false, G>(st, acc, j, lstart, nd, u, r, win, comp, anyscaled);
     }
 }
 
-// Inverse contraction of a group of up to G maps of one spin (band-limits
-// maps.L[b] <= L).  maps.src[b]: the FP32 coefficient stream of map b at
-// [(m*4 + comp)*Lp_b + l] (the four values of the FP64 stream record);
-// maps.dst[b]: F of map b at [(L_b - 1 + m)*L_b + n].
+// LDS floats per wave slot: its window, later its partial sums (a v4f per
+// order, map and lane).
+__host__ __device__ constexpr int inv2m_slot_floats(int G)
+{
+    return (2 * G * 4 * WIN > 2 * G * 64 * 4) ? 2 * G * 4 * WIN : 2 * G * 64 * 4;
+}
+
 template <bool EXT, int G>
-__global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse_mix(
+__global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse2_mix(
     MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
     const double2* __restrict__ lco, const double* __restrict__ stab, const int* __restrict__ stabk,
-    const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff, const int2* __restrict__ work,
-    int L, int Lp, int s, int segi, int nsegi)
+    const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work,
+    int L, int Lp, int s, int segi)
 {
     extern __shared__ double smem[];
     const MixMaps& maps = MB.g[blockIdx.y];
-    const int grp = blockIdx.x;
-    const int w = uniform(threadIdx.x >> 6);
+    const int slot = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int n0 = uniform(work[grp].x), m = uniform(work[grp].y);
-    if (n0 < 0) return;   // padding entry of the work list
-    bool any = false;
-    for (int b = 0; b < maps.n; ++b) any |= (n0 < maps.L[b] && m < maps.L[b]);
-    if (!any) return;
-    const int as = s < 0 ? -s : s;
-    const InvGeo geo = inv_geometry(n0, m, as, segi, nsegi);
+    // this wave's segment: see the work-list layout of the spin table
+    const int4 d = work[(size_t)blockIdx.x * SEGI_MAX + slot];
+    const int n0 = uniform(d.x), m0 = uniform(d.y), code = uniform(d.z), jb = uniform(d.w);
+    const bool item = n0 >= 0;
+    const int w = code & 0xff, nseg = (code >> 8) & 0xff, lead = (code >> 16) & 0xff;
+    const bool bar = (code >> 24) & 1;   // the same for every slot of the workgroup
+    bool any = false;                    // does any map of the group have this (n0, m0) block?
+    for (int b = 0; b < maps.n; ++b) any |= (n0 < maps.L[b] && m0 < maps.L[b]);
     const double* __restrict__ Rt = Rtg;               // 1/sqrt table, L1-resident
-    float* Fs = (float*)smem;                          // per-wave windows, later the reduction
-    float* win = Fs + w * (G * 4 * WIN);
+    float* region = (float*)smem + slot * inv2m_slot_floats(G);
+    const int as = s < 0 ? -s : s;
     const int n = n0 + lane;
-    const bool valid = n < L;
+    const bool valid = item && n < L;
     const int ne = valid ? n : L - 1;
     const double nd = (double)ne;
     const int jend = (Lp >> 1) - 1;
-    const int nseg = geo.nseg;
 
-    InvLane<EXT> st;
-    bool anyscaled;
-    const InvSeg g = inv_setup<EXT>(st, anyscaled, geo, w, n, m, L, Lp, as, segi, edge, edgek, stab, stabk, cki,
-                                    ckik, ckoff);
-    v4f acc[G];
+    v4f acc[2][G];
 #pragma unroll
-    for (int b = 0; b < G; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
-    if (g.active)
-        inv_mix_segment<EXT, G>(st, acc, g, jend, geo.lstart, ne, nd, m, as, Lp, lco, Rt, win, maps, lane,
-                                anyscaled);
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < G; ++b) acc[c][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    if (item && any) {
+        InvGeo geo;
+        geo.lstart = max(n0, m0) & ~1;
+        geo.lA = max(max(n0 + 64, m0 + 2), as + 1);   // every chain start of both orders lies below lA
+        geo.jb = jb;
+        geo.nseg = nseg;
+        InvLane2<EXT> st;
+        bool anyscaled;
+        const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, segi, edge, edgek, stab, stabk,
+                                         cki, ckik, ckoff);
+        if (g.active)
+            inv2m_segment<EXT, G>(st, acc, g, jend, geo.lstart, ne, nd, m0, inv2_rows(nullptr, lco, m0, as, Lp, L),
+                                  Rt, region, maps, lane, anyscaled);
+    }
 
-    double sum[G][4];
+    double sum[2][G][4];
 #pragma unroll
-    for (int b = 0; b < G; ++b)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sum[b][v] = (double)acc[b][v];
-    if (nseg > 1) {
-        __syncthreads();                 // every wave is done with its window
-        v4f* red = (v4f*)Fs;             // [(w-1)][b][lane]
-        if (w > 0 && w < nseg) {
+        for (int b = 0; b < G; ++b)
 #pragma unroll
-            for (int b = 0; b < G; ++b) red[((w - 1) * G + b) * 64 + lane] = acc[b];
+            for (int v = 0; v < 4; ++v) sum[c][b][v] = (double)acc[c][b][v];
+    if (bar) {
+        // every wave of the workgroup (empty slots too) meets at this one barrier;
+        // a wave's partial sums overwrite its own window, which it no longer reads
+        if (item && w > 0) {
+            v4f* red = (v4f*)region;
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int b = 0; b < G; ++b) red[(c * G + b) * 64 + lane] = acc[c][b];
         }
         __syncthreads();
-        if (w != 0) return;
-        for (int j = 1; j < nseg; ++j)
+        if (!item || w != 0) return;
+        for (int k = 1; k < nseg; ++k) {
+            const v4f* red = (const v4f*)((const float*)smem + (lead + k) * inv2m_slot_floats(G));
 #pragma unroll
-            for (int b = 0; b < G; ++b) {
-                const v4f v = red[((j - 1) * G + b) * 64 + lane];
+            for (int c = 0; c < 2; ++c)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) sum[b][q] += (double)v[q];
-            }
-    } else if (w != 0) {
+                for (int b = 0; b < G; ++b) {
+                    const v4f v = red[(c * G + b) * 64 + lane];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) sum[c][b][q] += (double)v[q];
+                }
+        }
+    } else if (!item) {
         return;
     }
+    if (!valid) return;
     const double fsp = sgn(s) * ((s >= 0) ? sgn(n) : 1.0);
     const double fsm = sgn(s) * ((s < 0) ? sgn(n) : 1.0);
 #pragma unroll
-    for (int b = 0; b < G; ++b) {
-        if (b >= maps.n) continue;
-        const int Lb = maps.L[b];
-        if (n >= Lb || m >= Lb) continue;
-        double2* F = maps.dst[b];
-        const double2 op = mul_ipow(make_double2(sum[b][0], sum[b][1]), ((-(m + s)) % 4 + 4) % 4);
-        F[(size_t)(Lb - 1 + m) * Lb + n] = make_double2(op.x * fsp, op.y * fsp);
-        if (m > 0) {
-            const double2 om = mul_ipow(make_double2(sum[b][2], sum[b][3]), ((m - s) % 4 + 4) % 4);
-            F[(size_t)(Lb - 1 - m) * Lb + n] = make_double2(om.x * fsm, om.y * fsm);
+    for (int c = 0; c < 2; ++c) {
+        const int m = m0 + c;
+#pragma unroll
+        for (int b = 0; b < G; ++b) {
+            if (b >= maps.n) continue;
+            const int Lb = maps.L[b];
+            if (n >= Lb || m >= Lb) continue;
+            double2* F = maps.dst[b];
+            const double2 op = mul_ipow(make_double2(sum[c][b][0], sum[c][b][1]), ((-(m + s)) % 4 + 4) % 4);
+            F[(size_t)(Lb - 1 + m) * Lb + n] = make_double2(op.x * fsp, op.y * fsp);
+            if (m > 0) {
+                const double2 om = mul_ipow(make_double2(sum[c][b][2], sum[c][b][3]), ((m - s) % 4 + 4) % 4);
+                F[(size_t)(Lb - 1 - m) * Lb + n] = make_double2(om.x * fsm, om.y * fsm);
+            }
         }
     }
 }
@@ -1498,13 +1406,6 @@ size_t mix_lds_forward(int G)
     return std::max(stage, red);
 }
 
-size_t mix_lds_inverse(int G)
-{
-    const size_t stage = (size_t)SEGI_MAX * G * 4 * WIN * sizeof(float);
-    const size_t red = (size_t)(SEGI_MAX - 1) * G * 64 * 16;
-    return std::max(stage, red);
-}
-
 template <class K>
 hipError_t mix_attr(K kernel, size_t bytes)
 {
@@ -1529,13 +1430,12 @@ hipError_t inv_mix_go(const Plan& p, const SpinTable& sp, int s, const MixBatch&
 {
     CkOff off;
     for (int j = 0; j < SEGI_MAX; ++j) off.off[j] = p.cki_off[j];
-    const size_t lds = mix_lds_inverse(G);
-    hipError_t e = mix_attr(k_contract_inverse_mix<EXT, G>, lds);
+    const size_t lds = (size_t)SEGI_MAX * inv2m_slot_floats(G) * sizeof(float);
+    hipError_t e = mix_attr(k_contract_inverse2_mix<EXT, G>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_contract_inverse_mix<EXT, G>), dim3(p.nworki, maps.ng), dim3(64 * SEGI_MAX), lds, st, maps,
-                       p.rtab,
-                       p.edge, p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, p.worki, p.L, p.Lp, s, p.segi,
-                       p.nsegi);
+    hipLaunchKernelGGL((k_contract_inverse2_mix<EXT, G>), dim3(sp.nwinv, maps.ng), dim3(64 * SEGI_MAX), lds, st,
+                       maps, p.rtab, p.edge, p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s,
+                       p.segi);
     return hipGetLastError();
 }
 
@@ -1544,7 +1444,8 @@ hipError_t inv_mix_go(const Plan& p, const SpinTable& sp, int s, const MixBatch&
 int mix_group_max(const Plan&)
 {
     for (int G = GMAX; G > 1; G >>= 1)
-        if (mix_lds_forward(G) <= 160 * 1024 && mix_lds_inverse(G) <= 160 * 1024) return G;
+        if (mix_lds_forward(G) <= 160 * 1024 && (size_t)SEGI_MAX * inv2m_slot_floats(G) * 4 <= 160 * 1024)
+            return G;
     return 1;
 }
 

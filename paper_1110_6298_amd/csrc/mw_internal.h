@@ -62,7 +62,6 @@ struct Plan {
     // nseg segments sit in slots lead .. lead+nseg-1 of the same workgroup;
     // (-1, 0, barrier << 24, 0) marks an empty slot
     int4* workf4 = nullptr; int nworkf4 = 0;   // workgroups
-    int2* worki = nullptr; int nworki = 0;   // inverse, one order per group: (n0, m)
     // Chain segmentation.  The forward splits every row recursion at the global
     // boundaries n = j*segf (j = 1..nsegf-1); ckf holds, for boundary j at
     // [(j-1)*L(L+1)/2 + tri_m(m, l)], the pair (Delta^l_{m,n-1}, Delta^l_{m,n})
@@ -96,7 +95,6 @@ struct SpinTable {
 
 // Chains per lane in the contraction kernels (work-list granularity in m).
 constexpr int MT_FWD = 2;
-constexpr int MT_INV = 1;    // mixed-precision inverse
 
 // Mixed-precision contraction: a group of up to GMAX maps of one spin shares the
 // FP64 chains.  src/dst are per-map device pointers (FP32 staged H or stream;

@@ -369,19 +369,6 @@ int build_plan(int L, Plan& p, std::string& err)
         const std::vector<int4> wf4 = forward_work(p);
         p.nworkf4 = (int)(wf4.size() / SEG_MAX);
         if ((rc = upload(wf4, &p.workf4, p.bytes, err))) return rc;
-        // mixed-precision inverse: one order per group (the FP64 inverse packs
-        // its segments per spin, see inverse_work)
-        for (auto& v : per) v.clear();
-        for (int n0 = 0; n0 < L; n0 += 64)
-            for (int m0 = 0; m0 < L; m0 += MT_INV) per[(m0 / MT_INV) & 7].push_back(make_int2(n0, m0));
-        for (auto& v : per)
-            std::stable_sort(v.begin(), v.end(), [L](int2 a, int2 b) {
-                return (L - std::max(a.x, a.y)) > (L - std::max(b.x, b.y));
-            });
-        std::vector<int2> wi;
-        deal(per, wi);
-        p.nworki = (int)wi.size();
-        if ((rc = upload(wi, &p.worki, p.bytes, err))) return rc;
     }
     return 0;
 }
@@ -389,7 +376,7 @@ int build_plan(int L, Plan& p, std::string& err)
 void free_plan(Plan& p)
 {
     void* ptrs[] = {p.sqtab, p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.whatc, p.thtw,
-                    p.workf, p.workf4, p.worki, p.ckf, p.ckfk, p.cki, p.ckik};
+                    p.workf, p.workf4, p.ckf, p.ckfk, p.cki, p.ckik};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p = Plan();
