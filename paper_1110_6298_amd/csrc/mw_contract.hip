@@ -1030,39 +1030,47 @@ __device__ __forceinline__ void fwd_mix_segment(FwdLane<2, EXT>& st, v4f (&acc)[
 // [(m*4 + comp)*Lp_b + n], comp = (Re, Im) of sigma_+(n) H_{m,n} and of
 // sigma_-(n) H_{-m,n}, where sigma_+ = (-1)^n for s >= 0 (else 1) and sigma_- =
 // (-1)^n for s < 0 (else 1); maps.dst[b]: f_lm of map b.
+// LDS floats per wave slot of the mixed forward: its window, later its partial
+// sums (a v4f per order, map and lane).
+__host__ __device__ constexpr int fwdm_slot_floats(int G)
+{
+    return (G * 8 * WIN > 2 * G * 64 * 4) ? G * 8 * WIN : 2 * G * 64 * 4;
+}
+
 template <bool EXT, int G>
 __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
     MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
     const double* __restrict__ cl, const double2* __restrict__ ckf, const int2* __restrict__ ckfk,
-    const int2* __restrict__ work, int L, int s, int segf)
+    const int4* __restrict__ work, int L, int s, int segf)
 {
     extern __shared__ double smem[];
     const MixMaps& maps = MB.g[blockIdx.y];
-    const int grp = blockIdx.x;
-    const int w = uniform(threadIdx.x >> 6);
+    const int slot = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int l0 = uniform(work[grp].x), mb = uniform(work[grp].y);
-    if (l0 < 0) return;   // padding entry of the work list
-    bool any = false;
+    // this wave's segment: see the work-list layout of the plan
+    const int4 d = work[(size_t)blockIdx.x * SEG_MAX + slot];
+    const int l0 = uniform(d.x), mb = uniform(d.y), code = uniform(d.z);
+    const bool item = l0 >= 0;
+    const int w = code & 0xff, nseg = (code >> 8) & 0xff, lead = (code >> 16) & 0xff;
+    const bool bar = (code >> 24) & 1;   // the same for every slot of the workgroup
+    bool any = false;                    // does any map of the group have this (l0, mb) block?
     for (int b = 0; b < maps.n; ++b) any |= (l0 < maps.L[b] && mb < maps.L[b]);
-    if (!any) return;
     const double* __restrict__ Rt = Rtg;               // 1/sqrt table, L1-resident
-    float* Hs = (float*)smem;                          // per-wave windows, later the reduction
-    float* win = Hs + w * (G * 8 * WIN);
-    const int nmax = min(l0 + 63, L - 1);
+    float* region = (float*)smem + slot * fwdm_slot_floats(G);
     const int l = l0 + lane;
-    const bool valid = l < L;
+    const bool valid = item && l < L;
     const int le = valid ? l : L - 1;
     const int as = s < 0 ? -s : s;
-    const int jtop = nmax / segf;
 
-    FwdLane<2, EXT> st;
-    bool anyscaled;
-    const FwdSeg g = fwd_setup<2, EXT>(st, anyscaled, w, l0, mb, l, L, as, segf, edge, edgek, ckf, ckfk);
     v4f acc[2][G];
 #pragma unroll
     for (int b = 0; b < G; ++b) acc[0][b] = acc[1][b] = v4f{0.f, 0.f, 0.f, 0.f};
-    if (g.active) fwd_mix_segment<EXT, G>(st, acc, g, l, le, mb, as, Rt, win, maps, lane, anyscaled);
+    if (item && any) {
+        FwdLane<2, EXT> st;
+        bool anyscaled;
+        const FwdSeg g = fwd_setup<2, EXT>(st, anyscaled, w, l0, mb, l, L, as, segf, edge, edgek, ckf, ckfk);
+        if (g.active) fwd_mix_segment<EXT, G>(st, acc, g, l, le, mb, as, Rt, region, maps, lane, anyscaled);
+    }
 
     double sum[2][G][4];
 #pragma unroll
@@ -1071,27 +1079,30 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
         for (int b = 0; b < G; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) sum[c][b][v] = (double)acc[c][b][v];
-    if (jtop > 0) {
-        __syncthreads();                 // every wave is done with its window
-        v4f* red = (v4f*)Hs;             // [(w-1)][c][b][lane]
-        if (w > 0 && w <= jtop) {
+    if (bar) {
+        // every wave of the workgroup (empty slots too) meets at this one barrier;
+        // a wave's partial sums overwrite its own window, which it no longer reads
+        if (item && w > 0) {
+            v4f* red = (v4f*)region;
 #pragma unroll
             for (int c = 0; c < 2; ++c)
 #pragma unroll
-                for (int b = 0; b < G; ++b) red[(((w - 1) * 2 + c) * G + b) * 64 + lane] = acc[c][b];
+                for (int b = 0; b < G; ++b) red[(c * G + b) * 64 + lane] = acc[c][b];
         }
         __syncthreads();
-        if (w != 0) return;
-        for (int j = 1; j <= jtop; ++j)
+        if (!item || w != 0) return;
+        for (int k = 1; k < nseg; ++k) {
+            const v4f* red = (const v4f*)((const float*)smem + (lead + k) * fwdm_slot_floats(G));
 #pragma unroll
             for (int c = 0; c < 2; ++c)
 #pragma unroll
                 for (int b = 0; b < G; ++b) {
-                    const v4f v = red[(((j - 1) * 2 + c) * G + b) * 64 + lane];
+                    const v4f v = red[(c * G + b) * 64 + lane];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) sum[c][b][q] += (double)v[q];
                 }
-    } else if (w != 0) {
+        }
+    } else if (!item) {
         return;
     }
     if (!valid) return;
@@ -1399,12 +1410,7 @@ hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, in
 // ---- mixed precision launchers ------------------------------------------
 namespace {
 
-size_t mix_lds_forward(int G)
-{
-    const size_t stage = (size_t)SEG_MAX * G * 8 * WIN * sizeof(float);
-    const size_t red = (size_t)(SEG_MAX - 1) * 2 * G * 64 * 16;
-    return std::max(stage, red);
-}
+size_t mix_lds_forward(int G) { return (size_t)SEG_MAX * fwdm_slot_floats(G) * sizeof(float); }
 
 template <class K>
 hipError_t mix_attr(K kernel, size_t bytes)
@@ -1419,9 +1425,8 @@ hipError_t fwd_mix_go(const Plan& p, int s, const MixBatch& maps, hipStream_t st
     const size_t lds = mix_lds_forward(G);
     hipError_t e = mix_attr(k_contract_forward_mix<EXT, G>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_contract_forward_mix<EXT, G>), dim3(p.nworkf, maps.ng), dim3(64 * SEG_MAX), lds, st, maps,
-                       p.rtab,
-                       p.edge, p.edgek, p.cl, p.ckf, p.ckfk, p.workf, p.L, s, p.segf);
+    hipLaunchKernelGGL((k_contract_forward_mix<EXT, G>), dim3(p.nworkf4, maps.ng), dim3(64 * SEG_MAX), lds, st,
+                       maps, p.rtab, p.edge, p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, s, p.segf);
     return hipGetLastError();
 }
 

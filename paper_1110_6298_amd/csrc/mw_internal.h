@@ -53,10 +53,8 @@ struct Plan {
     double2* what = nullptr;    // (2 pi/N2) * DFT_N2 of the theta weights w(k)
     double2* whatc = nullptr;   // conj(what), for the adjoint of the weight step
     double2* thtw = nullptr;    // exp(-i m' pi/N1)/(2 pi N1) at slot k = m' mod N1
-    // contraction work lists (int2: (block start, first order)), dealt over the 8
-    // XCDs by order and longest first; (-1, -1) entries are padding
-    int2* workf = nullptr; int nworkf = 0;   // mixed-precision forward: (l0, m0)
-    // FP64 forward: SEG_MAX wave slots per workgroup, slot i of workgroup g at
+    // Work list of the forward contractions (FP64 and mixed), dealt over the 8
+    // XCDs by order pair and longest first: SEG_MAX wave slots per workgroup, slot i of workgroup g at
     // [g*SEG_MAX + i] = (l0, mb, seg | nseg << 8 | lead << 16 | barrier << 24, 0)
     // for segment seg of the chain group (degrees l0 .., orders mb, mb+1) whose
     // nseg segments sit in slots lead .. lead+nseg-1 of the same workgroup;

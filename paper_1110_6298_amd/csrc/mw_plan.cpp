@@ -343,29 +343,9 @@ int build_plan(int L, Plan& p, std::string& err)
         }
     }
 
-    // Work lists (one entry per chain group; a workgroup runs its segments).
-    // Workgroups are dealt round-robin over the 8 XCDs, so entry i runs on XCD
-    // i mod 8.  All groups of one order (block) go to the same XCD, where its L2
-    // serves the rows they share; within an XCD the longest groups go first.
-    // Shorter XCD lists are padded with (-1, -1) entries, which exit at once.
+    // Work list of the forward contractions (FP64 and mixed): packed segments,
+    // see forward_work.
     {
-        auto deal = [](std::vector<std::vector<int2>>& per, std::vector<int2>& out) {
-            size_t n = 0;
-            for (auto& v : per) n = std::max(n, v.size());
-            out.clear();
-            for (size_t i = 0; i < n; ++i)
-                for (auto& v : per) out.push_back(i < v.size() ? v[i] : make_int2(-1, -1));
-        };
-        std::vector<std::vector<int2>> per(8);
-        for (int l0 = 0; l0 < L; l0 += 64)
-            for (int m0 = 0; m0 <= std::min(l0 + 63, L - 1); m0 += MT_FWD)
-                per[(m0 / MT_FWD) & 7].push_back(make_int2(l0, m0));
-        for (auto& v : per)
-            std::stable_sort(v.begin(), v.end(), [](int2 a, int2 b) { return a.x > b.x; });
-        std::vector<int2> wf;
-        deal(per, wf);
-        p.nworkf = (int)wf.size();
-        if ((rc = upload(wf, &p.workf, p.bytes, err))) return rc;
         const std::vector<int4> wf4 = forward_work(p);
         p.nworkf4 = (int)(wf4.size() / SEG_MAX);
         if ((rc = upload(wf4, &p.workf4, p.bytes, err))) return rc;
@@ -376,7 +356,7 @@ int build_plan(int L, Plan& p, std::string& err)
 void free_plan(Plan& p)
 {
     void* ptrs[] = {p.sqtab, p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.whatc, p.thtw,
-                    p.workf, p.workf4, p.ckf, p.ckfk, p.cki, p.ckik};
+                    p.workf4, p.ckf, p.ckfk, p.cki, p.ckik};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p = Plan();
