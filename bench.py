@@ -23,8 +23,8 @@ PEAK_FP64_VALU = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 # read for a plain copy of known size (profiles/traffic_roundtrip_L512_s2.md).
 # Valid only while the kernel and plan sources are unchanged: keyed by their SHA-256.
 TRAFFIC = {
-    ("contract_inverse", 512, 2): {"bytes": 47938274, "source_sha256": "06feabc51d2f8679cfd3dfea3dd85b0ad033ab98885ea31e0fd3e79b19f75c5c"},
-    ("contract_forward", 512, 2): {"bytes": 52271500, "source_sha256": "06feabc51d2f8679cfd3dfea3dd85b0ad033ab98885ea31e0fd3e79b19f75c5c"},
+    ("contract_inverse", 512, 2): {"bytes": 28888741, "source_sha256": "0af6a5e847ae647bf9968be10dc57ab0ed6f6789faecc92e1cfb7d962bc685bf"},
+    ("contract_forward", 512, 2): {"bytes": 29212999, "source_sha256": "0af6a5e847ae647bf9968be10dc57ab0ed6f6789faecc92e1cfb7d962bc685bf"},
 }
 KERNEL_SOURCES = ("paper_1110_6298_amd/csrc/mw_contract.hip", "paper_1110_6298_amd/csrc/mw_plan.cpp")
 
