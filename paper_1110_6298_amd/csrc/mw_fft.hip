@@ -320,14 +320,18 @@ __device__ __forceinline__ int xcd_column(int ncol)
 // ---------------------------------------------------------------------------
 // Forward phi stage (Sec. IV-D): G_m(theta_t) = sc sum_p f(t, p) e^{-i m phi_p}, with
 // sc = 2pi/N1 for the forward transform and sc = 1 for the adjoint of the inverse.
-// Output G[t][m + L-1].
+// Output order-major, G[m + L-1][t], so that the theta stage reads each order's
+// column as one contiguous row; rings are dealt to XCDs in contiguous ranges,
+// so the L2 of one XCD merges the partial lines that neighbouring rings write.
 template <int REAL, int RB>
 __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
 {
     extern __shared__ double2 A[];
     const void* __restrict__ map = B.in[blockIdx.y];
     double2* __restrict__ G = (double2*)B.out[blockIdx.y];
-    const int t = blockIdx.x, L = p.L, N1 = p.N1;
+    const int L = p.L, N1 = p.N1;
+    const int t = xcd_column(L);
+    if (t >= L) return;
     staged_loop(
         p.N2,
         [&](int j) {
@@ -347,7 +351,7 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
         N1, [&](int k) { return p.chirp[k]; },
         [&](int k, double2 c) {
             const int m = (k <= L - 1) ? k : k - N1;
-            G[(size_t)t * N1 + (m + L - 1)] = cscale(cmul(A[Pr<RB>(k)], c), sc);
+            G[(size_t)(m + L - 1) * L + t] = cscale(cmul(A[Pr<RB>(k)], c), sc);
         });
 }
 
@@ -386,8 +390,8 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
         [&](int j) {
             Pair2 v{make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
             if (j < N1) {
-                if (j < L) v.a = G[(size_t)j * N1 + mi];
-                else if (!ADJ_INV) v.a = G[(size_t)(2 * L - 2 - j) * N1 + mi];
+                if (j < L) v.a = G[(size_t)mi * L + j];
+                else if (!ADJ_INV) v.a = G[(size_t)mi * L + (2 * L - 2 - j)];
                 v.b = p.chirp[j];
             }
             return v;
@@ -584,7 +588,9 @@ __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
     extern __shared__ double2 A[];
     const double2* __restrict__ Ft = (const double2*)B.in[blockIdx.y];
     void* __restrict__ map = B.out[blockIdx.y];
-    const int t = blockIdx.x, L = p.L, N1 = p.N1;
+    const int L = p.L, N1 = p.N1;
+    const int t = xcd_column(L);
+    if (t >= L) return;
     staged_loop(
         p.N2,
         [&](int j) {
@@ -670,7 +676,7 @@ template <int RB> struct ThFA { static auto fn() { return k_theta_forward_adjoin
 
 hipError_t launch_phi_forward(const Plan& p, const Batch& B, int real, double sc, hipStream_t st)
 {
-    const dim3 grid(p.L, B.n);
+    const dim3 grid(xcd_grid(p.L), B.n);
     if (real) return fft_launch<PhiF<1>::K>(p, grid, st, p, B, sc);
     return fft_launch<PhiF<0>::K>(p, grid, st, p, B, sc);
 }
@@ -706,7 +712,7 @@ hipError_t launch_theta_inverse(const Plan& p, const Batch& B, int half, hipStre
 
 hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc, hipStream_t st)
 {
-    const dim3 grid(p.L, B.n);
+    const dim3 grid(xcd_grid(p.L), B.n);   // rings dealt to XCDs in contiguous ranges
     if (real == 2) return fft_launch<PhiI<2>::K>(p, grid, st, p, B, sc);
     if (real) return fft_launch<PhiI<1>::K>(p, grid, st, p, B, sc);
     return fft_launch<PhiI<0>::K>(p, grid, st, p, B, sc);
