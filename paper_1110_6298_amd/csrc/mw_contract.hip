@@ -64,9 +64,13 @@ typedef float fv2 __attribute__((ext_vector_type(2)));
 // Rt[0] = Rt[1] = 0), so that indices below 0 read zeros.
 __device__ __forceinline__ double2 rpair(const double* __restrict__ Rt, int j)
 {
+    // table base in scalar registers plus a 32-bit byte offset per lane (no
+    // 64-bit address arithmetic in the vector unit)
+    const char* base = (const char*)Rt;
+    const unsigned off = (unsigned)j * 8u;
     double2 r;
-    r.x = Rt[j];
-    r.y = Rt[j + 1];
+    r.x = *(const double*)(base + off);
+    r.y = *(const double*)(base + off + 8u);
     return r;
 }
 
@@ -696,24 +700,49 @@ __device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, 
 }
 
 // Pairs jfrom .. jlast (pair j = steps 2j, 2j+1); A holds even steps, B odd ones.
+// The 1/sqrt factors alternate between two register sets over pairs (two pairs
+// per iteration, an odd last pair peeled); r holds those of pair jfrom on entry
+// and of pair jlast+1 on return.
 template <bool EXT, bool INJ, bool RL>
 __device__ __forceinline__ void inv2_phase(InvLane2<EXT>& st, int jfrom, int jlast, int lend, int lstart, int ne,
                                            double nd, const Inv2Rows& rows, const double* __restrict__ Rt, InvS2& uA,
                                            InvS2& uB, InvR& r, bool& anyscaled)
 {
-    for (int j = jfrom; j <= jlast; ++j) {
+    const int jr = lend >> 1;   // last pair whose factors exist
+    InvR rB;
+    auto half = [&](int l, const InvR& rc) {   // steps l (in A) and l+1 (in B)
         wait_scalar(uA.f0.x);
         __builtin_amdgcn_sched_barrier(0);
-        inv2_load(uB, rows, 2 * j + 1);
-        const InvR rn = inv_load_r(Rt, ne, min(j + 1, lend >> 1));
+        inv2_load(uB, rows, l + 1);
         __builtin_amdgcn_sched_barrier(0);
-        inv2_step<EXT, INJ, RL>(st, 2 * j, lstart, nd, uA, r.a.x * r.b.x, anyscaled);
+        inv2_step<EXT, INJ, RL>(st, l, lstart, nd, uA, rc.a.x * rc.b.x, anyscaled);
         wait_scalar(uB.f0.x);
         __builtin_amdgcn_sched_barrier(0);
-        inv2_load(uA, rows, min(2 * j + 2, lend));
+        inv2_load(uA, rows, min(l + 2, lend));
         __builtin_amdgcn_sched_barrier(0);
-        inv2_step<EXT, INJ, RL>(st, 2 * j + 1, lstart, nd, uB, r.a.y * r.b.y, anyscaled);
-        r = rn;
+        inv2_step<EXT, INJ, RL>(st, l + 1, lstart, nd, uB, rc.a.y * rc.b.y, anyscaled);
+    };
+    if constexpr (EXT) {
+        // the exponent-extended variant keeps one pair per iteration: unrolled,
+        // it needs more registers than five waves per SIMD leave
+        for (int j = jfrom; j <= jlast; ++j) {
+            rB = inv_load_r(Rt, ne, min(j + 1, jr));
+            half(2 * j, r);
+            r = rB;
+        }
+    } else {
+        int j = jfrom;
+        for (; j < jlast; j += 2) {
+            rB = inv_load_r(Rt, ne, min(j + 1, jr));
+            half(2 * j, r);
+            r = inv_load_r(Rt, ne, min(j + 2, jr));
+            half(2 * j + 2, rB);
+        }
+        if (j == jlast) {
+            rB = inv_load_r(Rt, ne, min(j + 1, jr));
+            half(2 * j, r);
+            r = rB;
+        }
     }
 }
 
@@ -900,7 +929,8 @@ __device__ __forceinline__ void contract_inverse2_body(
 #define MW_INVERSE2_PASS fs0, fstride, B, Rtg, edge, edgek, lco, stab, stabk, cki, ckik, ckoff, work, L, Lp, s, segi
 
 template <bool RL>
-__global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse2(MW_INVERSE2_ARGS)
+__global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(6))) void k_contract_inverse2(
+    MW_INVERSE2_ARGS)
 {
     contract_inverse2_body<false, RL>(MW_INVERSE2_PASS);
 }
