@@ -26,10 +26,17 @@ __device__ __forceinline__ double2 mul_dir_i(double2 a)
     return DIR < 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
 }
 
-// LDS index with one pad slot per RB entries (RB = the FFT's main radix): the
-// stride-RB stores of a main pass then fall on distinct banks.
+// LDS index of FFT entry i.  A 128-byte LDS row holds 8 complex entries.  For
+// RB = 8 the column (i mod 8) is XOR-ed with the row's low three bits, so the
+// stride-8 stores of a main pass and the unit-stride loads both fall on distinct
+// banks with no padding (the buffer is exactly N entries); for RB = 16 one pad
+// entry per 16 does the same for the stride-16 stores.
 template <int RB>
-__device__ __forceinline__ int Pr(int i) { return i + i / RB; }
+__device__ __forceinline__ int Pr(int i)
+{
+    if constexpr (RB == 8) return i ^ ((i >> 3) & 7);
+    else return i + i / RB;
+}
 
 // Block-wide loop over j = threadIdx.x + q*blockDim.x < n (n <= 16*blockDim.x):
 // the global loads ld(j) of eight consecutive q are all issued before any result
@@ -637,7 +644,7 @@ int fft_threads(const Plan& p, int rb)
     return t;
 }
 
-size_t fft_lds(const Plan& p, int rb) { return (size_t)(p.N2 + p.N2 / rb) * sizeof(double2); }
+size_t fft_lds(const Plan& p, int rb) { return (size_t)(p.N2 + (rb == 8 ? 0 : p.N2 / rb)) * sizeof(double2); }
 
 template <class K>
 hipError_t set_lds(K kernel, size_t bytes)
