@@ -409,11 +409,12 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
     bluestein_core<RB>(A, p, T);
     // F_{m'} into registers (N1 <= N2/2 <= 8 * blockDim.x), then scatter to slot m' mod N2.
     double2 r[8];
-    const double unscale = ADJ_INV ? 2.0 * 3.14159265358979323846 * (double)N1 : 1.0;
+    // chirp_k e^{-i m' pi/N1} (and 1/(2 pi N1) for the forward proper)
+    const double scale = ADJ_INV ? 1.0 : p.thsc;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int k = threadIdx.x + q * blockDim.x;
-        if (k < N1) r[q] = cscale(cmul(cmul(A[Pr<RB>(k)], p.chirp[k]), p.thtw[k]), unscale);
+        if (k < N1) r[q] = cscale(cmul(A[Pr<RB>(k)], p.thwc[k]), scale);
     }
     __syncthreads();
     int wrap;   // index of -n is wrap - n
@@ -555,26 +556,22 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
     if (mi >= N1) return;
     const int m = mi - (L - 1);
     const double sig = ((m + s) & 1) ? -1.0 : 1.0;
-    const double unscale = 2.0 * 3.14159265358979323846 * (double)N1;
-    struct Tri { double2 f, w, c; };
     staged_loop(
         N2,
         [&](int j) {
-            Tri v{make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+            Pair2 v{make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
             if (j < N1) {
                 const int mp = (j <= L - 1) ? j : j - N1;
-                v.f = F[(size_t)mi * L + (mp < 0 ? -mp : mp)];
-                v.w = p.thtw[j];
-                v.c = p.chirp[j];
+                v.a = F[(size_t)mi * L + (mp < 0 ? -mp : mp)];
+                v.b = p.thwc[j];
             }
             return v;
         },
-        [&](int j, const Tri& v) {
+        [&](int j, const Pair2& v) {
             const int mp = (j <= L - 1) ? j : j - N1;
-            const double2 f = (mp < 0) ? cscale(v.f, sig) : v.f;
-            // y = f e^{+i m' pi/N1};  conj(thtw) * 2 pi N1 = e^{+i m' pi/N1}
-            const double2 y = cmul(f, cscale(cconj(v.w), unscale));
-            A[Pr<RB>(j)] = cmul(cconj(y), v.c);
+            const double2 f = (mp < 0) ? cscale(v.a, sig) : v.a;
+            // conj(f e^{+i m' pi/N1}) chirp_j = conj(f) (e^{-i m' pi/N1} chirp_j)
+            A[Pr<RB>(j)] = cmul(cconj(f), v.b);
         });
     // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
     const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);

@@ -53,6 +53,8 @@ struct Plan {
     double2* what = nullptr;    // (2 pi/N2) * DFT_N2 of the theta weights w(k)
     double2* whatc = nullptr;   // conj(what), for the adjoint of the weight step
     double2* thtw = nullptr;    // exp(-i m' pi/N1)/(2 pi N1) at slot k = m' mod N1
+    double2* thwc = nullptr;    // exp(-i m' pi/N1) chirp_k at slot k = m' mod N1
+    double thsc = 0.0;          // 1/(2 pi N1)
     // Work list of the forward contractions (FP64 and mixed), dealt over the 8
     // XCDs by order pair and longest first: SEG_MAX wave slots per workgroup, slot i of workgroup g at
     // [g*SEG_MAX + i] = (l0, mb, seg | nseg << 8 | lead << 16 | barrier << 24, 0)

@@ -269,6 +269,18 @@ int build_plan(int L, Plan& p, std::string& err)
         th[k] = make_double2((double)(cosl(a) * sc), (double)(sinl(a) * sc));
     }
     if ((rc = upload(th, &p.thtw, p.bytes, err))) return rc;
+    {
+        // e^{-i m' pi/N1} chirp_k, rounded once (the theta stages' chirp and twiddle product)
+        std::vector<double2> wc(N1);
+        for (int k = 0; k < N1; ++k) {
+            const int mp = (k <= L - 1) ? k : k - N1;
+            const ld a = -PI_L * (ld)mp / (ld)N1;
+            const cld v = cld(cosl(a), sinl(a)) * c[k];
+            wc[k] = make_double2((double)v.real(), (double)v.imag());
+        }
+        if ((rc = upload(wc, &p.thwc, p.bytes, err))) return rc;
+        p.thsc = (double)(1.0L / (2.0L * PI_L * (ld)N1));
+    }
 
     // chain segmentation: up to SEG_MAX (forward) or SEGI_MAX (inverse) waves of
     // a workgroup share each chain, the checkpoints at the boundaries (O(L^2)
@@ -355,7 +367,7 @@ int build_plan(int L, Plan& p, std::string& err)
 
 void free_plan(Plan& p)
 {
-    void* ptrs[] = {p.sqtab, p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.whatc, p.thtw,
+    void* ptrs[] = {p.sqtab, p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.whatc, p.thtw, p.thwc,
                     p.workf4, p.ckf, p.ckfk, p.cki, p.ckik};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
