@@ -35,7 +35,6 @@ struct Plan {
     int Lp = 0;              // L rounded up to even (row length of the forward H layout)
     bool ext = false;        // some start value needs the exponent extension
     // Wigner tables
-    double2* sqtab = nullptr;   // (sqrt k, 1/sqrt k), k = 0..2L+2; entry 0 = (0, 0)
     double* rtab = nullptr;     // rtab[j] = 1/sqrt(j-1) for j >= 2, rtab[0] = rtab[1] = 0; 2L+8 entries
     // Chain start values, order-major and square: at [m*L + n] the value of
     // Delta^{l0}_{n,m} at l0 = max(n, m), i.e. (-1)^(n-m) Delta^n_{m,n} for n >= m

@@ -157,13 +157,7 @@ int build_plan(int L, Plan& p, std::string& err)
     const int N1 = p.N1, N2 = p.N2;
     int rc;
 
-    // sqrt table
-    std::vector<double2> sq(2 * L + 3);
-    for (int k = 0; k < (int)sq.size(); ++k) {
-        ld r = sqrtl((ld)k);
-        sq[k] = make_double2((double)r, k ? (double)(1.0L / r) : 0.0);
-    }
-    if ((rc = upload(sq, &p.sqtab, p.bytes, err))) return rc;
+    // 1/sqrt table, shifted: rt[j] = 1/sqrt(j-1), rt[0] = rt[1] = 0
     std::vector<double> rt(2 * L + 8, 0.0);
     for (int j = 2; j < (int)rt.size(); ++j) rt[j] = (double)(1.0L / sqrtl((ld)(j - 1)));
     if ((rc = upload(rt, &p.rtab, p.bytes, err))) return rc;
@@ -367,7 +361,7 @@ int build_plan(int L, Plan& p, std::string& err)
 
 void free_plan(Plan& p)
 {
-    void* ptrs[] = {p.sqtab, p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.whatc, p.thtw, p.thwc,
+    void* ptrs[] = {p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.whatc, p.thtw, p.thwc,
                     p.workf4, p.ckf, p.ckfk, p.cki, p.ckik};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
