@@ -114,7 +114,9 @@ int mw_forward_adjoint(const int32_t* L, const int32_t* spin, const int32_t* rea
 int mw_inverse_adjoint(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                        void* const* ptrs, int32_t precision, void* stream);
 
-/* Bytes of workspace one call with these arguments needs (plan tables excluded). */
+/* Bytes of workspace one call with these arguments needs (plan tables excluded).
+ * A call whose maps form several chunks (see mw_prepare) runs them alternately
+ * on two internal streams, each with its own half of the workspace. */
 int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                       int32_t precision, size_t* bytes);
 
@@ -126,7 +128,9 @@ int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* real
  * results do not depend on the choice).  Synchronises the device.
  *
  * Batching: a call runs its maps in chunks of equal (L, spin, reality), each
- * stage of a chunk being one kernel launch over all its maps; calls under
+ * stage of a chunk being one kernel launch over all its maps.  Several chunks
+ * alternate over two internal streams (created here or on the first such call)
+ * that fork from and join back into the caller's stream; calls under
  * stream capture (hipGraph) record those launches with their arguments and
  * replay them unchanged.  Call mw_prepare with the same arguments first: a call
  * under capture that would need an allocation fails with MW_ENOMEM.  Workspaces

@@ -32,7 +32,24 @@ struct DeviceState {
     // Outgrown workspaces stay allocated until mw_release: a graph captured
     // earlier may still reference one.
     std::vector<void*> retired;
+    // Two internal streams (default priority) on which the chunks of a call
+    // alternate, each with its half of the workspace, so that one chunk's
+    // Fourier stages (LDS-bound) overlap another's contractions (VALU-bound);
+    // fork and join events tie them to the caller's stream.
+    hipStream_t lane[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
 };
+
+// Create the two chunk streams and their events on the current device.
+bool make_lanes(DeviceState& d)
+{
+    if (d.lane[0]) return true;
+    for (int k = 0; k < 2; ++k) {
+        if (hipStreamCreateWithFlags(&d.lane[k], hipStreamNonBlocking) != hipSuccess) return false;
+        if (hipEventCreateWithFlags(&d.join[k], hipEventDisableTiming) != hipSuccess) return false;
+    }
+    return hipEventCreateWithFlags(&d.fork, hipEventDisableTiming) == hipSuccess;
+}
 
 std::mutex g_mu;
 std::map<int, DeviceState> g_dev;
@@ -370,6 +387,9 @@ size_t chunks_ws(const std::vector<Chunk>& ch, int Lws)
     return slots * ws_need(Lws) + 256;
 }
 
+// Workspace of a call: one half per chunk stream when it has several chunks.
+size_t call_ws(const std::vector<Chunk>& ch, int Lws) { return (ch.size() > 1 ? 2 : 1) * chunks_ws(ch, Lws); }
+
 int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
         void* const* ptrs, int32_t precision, void* stream)
 {
@@ -386,15 +406,34 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     if (rc) return rc;
     const int Lws = batch_lmax(L, batch);
     void* ws = nullptr;
-    if ((rc = get_ws(d, chunks_ws(chunks, Lws), may_alloc, &ws))) return rc;
-    for (const Chunk& c : chunks) {
+    if ((rc = get_ws(d, call_ws(chunks, Lws), may_alloc, &ws))) return rc;
+    // several chunks alternate over the two chunk streams (per-stage profiling
+    // keeps the caller's stream, so that its events time one launch each)
+    const bool lanes = chunks.size() > 1 && !g_prof_on && (d.lane[0] || (may_alloc && make_lanes(d)));
+    const size_t half = chunks_ws(chunks, Lws);
+    if (lanes) {
+        if (hipEventRecord(d.fork, st) != hipSuccess || hipStreamWaitEvent(d.lane[0], d.fork, 0) != hipSuccess ||
+            hipStreamWaitEvent(d.lane[1], d.fork, 0) != hipSuccess)
+            return fail(MW_EHIP, "stream fork failed");
+    }
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < chunks.size() && e == hipSuccess; ++i) {
+        const Chunk& c = chunks[i];
         const Plan* p = nullptr;
         const SpinTable* sp = nullptr;
         if ((rc = get_plan(d, c.L, may_alloc, &p))) return rc;
         if (need_spin && (rc = get_spin(d, *p, c.s < 0 ? -c.s : c.s, may_alloc, &sp))) return rc;
-        hipError_t e = run_chunk(op, c, *p, sp, precision, ptrs, ws, Lws, st);
-        if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+        hipStream_t cs = lanes ? d.lane[i & 1] : st;
+        void* cws = lanes ? (void*)((char*)ws + (i & 1) * half) : ws;
+        e = run_chunk(op, c, *p, sp, precision, ptrs, cws, Lws, cs);
     }
+    if (lanes) {
+        // join both chunk streams back into the caller's stream, also after a failed launch
+        for (int k = 0; k < 2; ++k)
+            if (hipEventRecord(d.join[k], d.lane[k]) != hipSuccess || hipStreamWaitEvent(st, d.join[k], 0) != hipSuccess)
+                return fail(MW_EHIP, "stream join failed");
+    }
+    if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     g_last_error.clear();
     return MW_OK;
 }
@@ -491,13 +530,16 @@ int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* real
     // the largest chunk of maps with equal (L, spin, reality), capped like the calls cap it
     std::map<std::tuple<int, int, int>, int> cnt;
     for (int b = 0; b < batch; ++b) ++cnt[std::make_tuple(L[b], spin[b], reality[b])];
-    size_t slots = 1;
+    size_t slots = 1, nchunks = 0;
     for (auto& kv : cnt) {
         const int Lc = std::get<0>(kv.first);
         const int G = (precision == MW_FP64) ? 1 : std::min(pow2_ceil(kv.second), mw::GMAX);
-        slots = std::max(slots, (size_t)std::min(kv.second, chunk_cap(Lc, precision, G)));
+        const int cap = chunk_cap(Lc, precision, G);
+        slots = std::max(slots, (size_t)std::min(kv.second, cap));
+        nchunks += (kv.second + cap - 1) / cap;
     }
-    *bytes = slots * ws_need(batch_lmax(L, batch)) + 256;
+    // one half per chunk stream when the call has several chunks
+    *bytes = (nchunks > 1 ? 2 : 1) * (slots * ws_need(batch_lmax(L, batch)) + 256);
     return MW_OK;
 }
 
@@ -520,7 +562,8 @@ int mw_prepare(const int32_t* L, const int32_t* spin, const int32_t* reality, in
     const std::vector<Chunk> chunks = make_chunks(d, L, spin, reality, batch, precision, true, rc);
     if (rc) return rc;
     void* ws = nullptr;
-    if ((rc = get_ws(d, chunks_ws(chunks, batch_lmax(L, batch)), true, &ws))) return rc;
+    if ((rc = get_ws(d, call_ws(chunks, batch_lmax(L, batch)), true, &ws))) return rc;
+    if (chunks.size() > 1 && !make_lanes(d)) return fail(MW_EHIP, "chunk stream creation failed");
     if (hipDeviceSynchronize() != hipSuccess) return fail(MW_EHIP, "hipDeviceSynchronize failed");
     return MW_OK;
 }
@@ -537,6 +580,11 @@ int mw_release(void)
         for (auto& ss : kv.second.spins) mw::free_spin_table(ss.second);
         if (kv.second.ws) (void)hipFree(kv.second.ws);
         for (void* q : kv.second.retired) (void)hipFree(q);
+        for (int k = 0; k < 2; ++k) {
+            if (kv.second.lane[k]) (void)hipStreamDestroy(kv.second.lane[k]);
+            if (kv.second.join[k]) (void)hipEventDestroy(kv.second.join[k]);
+        }
+        if (kv.second.fork) (void)hipEventDestroy(kv.second.fork);
     }
     g_dev.clear();
     (void)hipSetDevice(cur);
