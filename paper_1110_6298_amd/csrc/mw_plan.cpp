@@ -375,13 +375,53 @@ void free_plan(Plan& p)
 // Groups of one segment go four to a workgroup with no barrier (every wave
 // exits when done); groups of several segments are placed first-fit into the
 // last few open workgroups, so that waves meeting at the reduction barrier
-// have similar lengths.  Workgroups are ordered longest first per XCD and
-// dealt round-robin over the 8 XCDs.
-struct SegItem { int a, b, nseg, jb, len; };
+// have similar lengths.  Workgroups are dealt round-robin over the 8 XCDs
+// (workgroup k*8 + x is the k-th of XCD x); per XCD they are ordered as in
+// balance_cus when at most `resident` per compute unit are needed (the launch
+// fits at once), else longest first, which is what dynamic dispatch wants.
+// work: the group's steps summed over its segments, plus a start-up cost per
+// segment.
+struct SegItem { int a, b, nseg, jb, len, work; };
 
-static std::vector<int4> pack_segments(std::vector<std::vector<SegItem>>& items, int slots)
+// Workgroups per compute unit that the contraction kernels keep resident (the
+// lowest occupancy among the variants that read each list: the FP64 inverse
+// holds five to seven waves per SIMD, the forward four).
+constexpr int RESIDENT_INV = 5;
+constexpr int RESIDENT_FWD = 4;
+
+// Order of the workgroups of one XCD when all of them are resident at once:
+// the dispatcher then fills the 32 compute units of an XCD round-robin, so its
+// k-th and (k+32)-th workgroups share a compute unit.  The workgroups are
+// assigned, heaviest first, to the least-loaded of the 32 position classes
+// k mod 32 (each taking as many as it has positions) and laid out class by
+// class.  Plain longest-first order would give the unit at position 0 the
+// heaviest workgroup of every block of 32.
+template <class G>
+static void balance_cus(std::vector<G>& gs)
 {
-    struct Group { int used, len; bool bar; int4 slot[SEGI_MAX > SEG_MAX ? SEGI_MAX : SEG_MAX]; };
+    constexpr int C = 32;
+    const int n = (int)gs.size();
+    std::stable_sort(gs.begin(), gs.end(), [](const G& u, const G& v) { return u.work > v.work; });
+    std::vector<std::vector<int>> bin(C);
+    std::vector<long> load(C, 0);
+    for (int i = 0; i < n; ++i) {
+        int best = -1;
+        for (int c = 0; c < C; ++c) {
+            const int cap = n / C + (c < n % C ? 1 : 0);
+            if ((int)bin[c].size() < cap && (best < 0 || load[c] < load[best])) best = c;
+        }
+        bin[best].push_back(i);
+        load[best] += gs[i].work;
+    }
+    std::vector<G> out;
+    out.reserve(n);
+    for (int k = 0; k < n; ++k) out.push_back(gs[bin[k % C][k / C]]);
+    gs.swap(out);
+}
+
+static std::vector<int4> pack_segments(std::vector<std::vector<SegItem>>& items, int slots, int resident)
+{
+    struct Group { int used, len; long work; bool bar; int4 slot[SEGI_MAX > SEG_MAX ? SEGI_MAX : SEG_MAX]; };
     std::vector<std::vector<Group>> per(items.size());
     for (size_t x = 0; x < items.size(); ++x) {
         std::vector<SegItem>& it = items[x];
@@ -400,6 +440,7 @@ static std::vector<int4> pack_segments(std::vector<std::vector<SegItem>>& items,
                 Group c;
                 c.used = 0;
                 c.len = t.len;
+                c.work = 0;
                 c.bar = bar;
                 for (int i = 0; i < slots; ++i) c.slot[i] = make_int4(-1, 0, bar ? 1 << 24 : 0, 0);
                 gs.push_back(c);
@@ -412,14 +453,18 @@ static std::vector<int4> pack_segments(std::vector<std::vector<SegItem>>& items,
                 c.slot[c.used + w] =
                     make_int4(t.a, t.b, w | (t.nseg << 8) | (c.used << 16) | (bar ? 1 << 24 : 0), t.jb);
             c.used += t.nseg;
+            c.work += t.work;
             if (c.used == slots)
                 for (size_t k = 0; k < open.size(); ++k)
                     if (open[k] == g) { open.erase(open.begin() + k); break; }
         }
-        std::stable_sort(gs.begin(), gs.end(), [](const Group& u, const Group& v) { return u.len > v.len; });
     }
-    size_t n = 0;
+    size_t n = 0;   // workgroups of the busiest XCD
     for (auto& v : per) n = std::max(n, v.size());
+    for (auto& gs : per) {
+        if (n <= (size_t)32 * resident) balance_cus(gs);
+        else std::stable_sort(gs.begin(), gs.end(), [](const Group& u, const Group& v) { return u.len > v.len; });
+    }
     std::vector<int4> out;
     out.reserve(n * per.size() * slots);
     for (size_t g = 0; g < n; ++g)
@@ -442,9 +487,9 @@ static std::vector<int4> inverse_work(const Plan& p, int as)
             const int lA = std::max(std::max(n0 + 64, m0 + 2), as + 1);
             const int jb = (std::max(lA, lstart + 2) + segi - 1) / segi;
             const int nseg = (jb < nsegi) ? 1 + nsegi - jb : 1;
-            items[(m0 / 2) & 7].push_back(SegItem{n0, m0, nseg, jb, Lp - lstart});
+            items[(m0 / 2) & 7].push_back(SegItem{n0, m0, nseg, jb, Lp - lstart, Lp - lstart + 16 * nseg});
         }
-    return pack_segments(items, SEGI_MAX);
+    return pack_segments(items, SEGI_MAX, RESIDENT_INV);
 }
 
 // FP64 forward contraction: group (l0, mb) runs the row recursions from nmax =
@@ -460,9 +505,9 @@ static std::vector<int4> forward_work(const Plan& p)
         const int jtop = nmax / segf;
         const int len = std::max(nmax - jtop * segf + 1, jtop > 0 ? segf : 0);
         for (int mb = 0; mb <= nmax; mb += MT_FWD)
-            items[(mb / MT_FWD) & 7].push_back(SegItem{l0, mb, jtop + 1, 0, len});
+            items[(mb / MT_FWD) & 7].push_back(SegItem{l0, mb, jtop + 1, 0, len, nmax + 1 + 16 * (jtop + 1)});
     }
-    return pack_segments(items, SEG_MAX);
+    return pack_segments(items, SEG_MAX, RESIDENT_FWD);
 }
 
 // Delta^l_{n,|s|} for n <= l < L by the upward l-recursion in long double,
