@@ -631,6 +631,23 @@ __device__ __forceinline__ void inv2_load(InvS2& u, const Inv2Rows& w, int l)
 }
 
 
+// Brings the first lines of a segment's uniform rows into the L2 before its
+// loop: lane i reads one dword of line i of each row (stream records, 32 bytes
+// per degree; (Pu, Qu) rows, 16 bytes), starting at degree l0 and clamped to
+// degree lend.  Waves of one order pair start their segments at the same
+// degrees, so without this every new line of the loop would be a miss beyond
+// the L2 for all of them at once; the values feed only a register use.
+__device__ __forceinline__ unsigned inv2_touch(const Inv2Rows& w, int l0, int lend, int lane)
+{
+    const unsigned df = (unsigned)min(l0 + 2 * lane, lend), dc = (unsigned)min(l0 + 4 * lane, lend);
+    unsigned t = *(const unsigned*)(w.f + (w.f0 + df * 32u));
+    t += *(const unsigned*)(w.f + (w.f1 + df * 32u));
+    t += *(const unsigned*)(w.c + (w.c0 + dc * 16u));
+    t += *(const unsigned*)(w.c + (w.c1 + dc * 16u));
+    t += *(const unsigned*)(w.c + (w.cs + dc * 16u));
+    return t;
+}
+
 // One step l of both orders' chains and the spin chain: injections, the
 // products pr[c] = Delta^l_{n,m_c} Delta^l_{n,|s|} of this step, then the
 // recursion to l+1.  (c0, c1, cs): (Pu, Qu) of the two orders and of |s| at l.
@@ -867,11 +884,13 @@ __device__ __forceinline__ void contract_inverse2_body(
         geo.lA = max(max(n0 + 64, m0 + 2), as + 1);   // every chain start of both orders lies below lA
         geo.jb = jb;
         geo.nseg = nseg;
+        const Inv2Rows rows = inv2_rows(fs, lco, m0, as, Lp, L);
+        const unsigned touched = inv2_touch(rows, (w == 0) ? geo.lstart : (jb + w - 1) * segi, lend, lane);
         bool anyscaled;
         const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, segi, edge, edgek, stab, stabk,
                                          cki, ckik, ckoff);
+        asm volatile("" ::"v"(touched));
         if (g.active) {
-            const Inv2Rows rows = inv2_rows(fs, lco, m0, as, Lp, L);
             InvS2 uA, uB;
             inv2_load(uA, rows, 2 * g.jfrom);
             InvR r = inv_load_r(Rt, ne, g.jfrom);
