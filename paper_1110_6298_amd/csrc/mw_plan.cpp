@@ -145,6 +145,17 @@ int upload(const std::vector<T>& h, T** d, size_t& bytes, std::string& err)
 
 static std::vector<int4> forward_work(const Plan& p);   // below
 
+// Chain segmentation for band-limit L: up to smax waves of a workgroup share
+// each chain, in segments of seg (a multiple of 64) degrees or rows, nseg of
+// them over the whole range; false if more than smax would be needed.
+static bool segment_chains(int L, int smax, int& seg, int& nseg)
+{
+    const int sz = 64 * std::max(1, (L + 64 * smax - 1) / (64 * smax));
+    seg = (sz < L) ? sz : (L + 63) / 64 * 64 + 64;
+    nseg = (seg < L) ? (L + seg - 1) / seg : 1;
+    return nseg <= smax;
+}
+
 int build_plan(int L, Plan& p, std::string& err)
 {
     p = Plan();
@@ -276,18 +287,11 @@ int build_plan(int L, Plan& p, std::string& err)
         p.thsc = (double)(1.0L / (2.0L * PI_L * (ld)N1));
     }
 
-    // chain segmentation: up to SEG_MAX (forward) or SEGI_MAX (inverse) waves of
-    // a workgroup share each chain, the checkpoints at the boundaries (O(L^2)
-    // each, by the degree recursion or the row recursion in long double)
-    // restarting the later segments; segments are multiples of 64 degrees
+    // chain segmentation (segment_chains), the checkpoints at the boundaries
+    // (O(L^2) each, by the degree recursion or the row recursion in long double)
+    // restarting the later segments
     {
-        auto segment = [L](int smax, int& seg, int& nseg) {
-            const int sz = 64 * std::max(1, (L + 64 * smax - 1) / (64 * smax));
-            seg = (sz < L) ? sz : (L + 63) / 64 * 64 + 64;
-            nseg = (seg < L) ? (L + seg - 1) / seg : 1;
-            return nseg <= smax;
-        };
-        if (!segment(SEG_MAX, p.segf, p.nsegf) || !segment(SEGI_MAX, p.segi, p.nsegi)) {
+        if (!segment_chains(L, SEG_MAX, p.segf, p.nsegf) || !segment_chains(L, SEGI_MAX, p.segi, p.nsegi)) {
             err = "segmentation exceeds the waves of a workgroup";
             return -3;
         }

@@ -1,0 +1,168 @@
+// Host-only checks of the contraction work lists that the plan builder packs
+// (inverse_work, forward_work in mw_plan.cpp): every segment of every chain
+// group appears exactly once, the segments of a group sit in consecutive slots
+// of one workgroup with a consistent lead slot, barrier flags match the groups
+// a workgroup holds, restart boundaries lie where checkpoints exist, and a list
+// that fits the GPU at once spreads its steps evenly over the compute units.
+// Built and run by tests/test_host_plan.py; prints one line per failure.
+#include "../../paper_1110_6298_amd/csrc/mw_plan.cpp"
+
+#include <cstdio>
+#include <map>
+#include <tuple>
+
+using namespace mw;
+
+static long bad = 0;
+#define CHECK(c, ...)                        \
+    do {                                     \
+        if (!(c)) {                          \
+            ++bad;                           \
+            if (bad < 20) printf(__VA_ARGS__); \
+        }                                    \
+    } while (0)
+
+// Steps of each slot and the per-CU totals when workgroup k*8 + x runs on CU
+// (x, k mod 32) of XCD x: the spread must stay within one workgroup's steps of
+// the mean whenever the list fits at once.
+static void check_balance(const char* tag, int L, const std::vector<int4>& w, int slots, int resident,
+                          const std::vector<long>& steps)
+{
+    const size_t nwg = w.size() / slots;
+    if ((nwg + 7) / 8 > (size_t)32 * resident) return;
+    std::vector<long> cu(256, 0);
+    long heaviest = 0, total = 0;
+    for (size_t g = 0; g < nwg; ++g) {
+        long wg = 0;
+        for (int i = 0; i < slots; ++i) wg += steps[g * slots + i];
+        cu[(g % 8) * 32 + (g / 8) % 32] += wg;
+        heaviest = std::max(heaviest, wg);
+        total += wg;
+    }
+    long mx = 0;
+    for (long c : cu) mx = std::max(mx, c);
+    CHECK(mx <= total / 256 + heaviest, "%s L=%d: busiest CU %ld steps, mean %ld, heaviest workgroup %ld\n", tag, L,
+          mx, total / 256, heaviest);
+}
+
+static void check_inverse(int L, int as)
+{
+    Plan p;
+    p.L = L;
+    p.Lp = L + (L & 1);
+    CHECK(segment_chains(L, SEGI_MAX, p.segi, p.nsegi), "inverse L=%d: segmentation\n", L);
+    const std::vector<int4> w = inverse_work(p, as);
+    CHECK(w.size() % SEGI_MAX == 0, "inverse L=%d: size\n", L);
+    std::map<std::tuple<int, int, int>, int> seen;
+    std::vector<long> steps(w.size(), 0);
+    for (size_t g = 0; g < w.size() / SEGI_MAX; ++g) {
+        const int4* s = &w[g * SEGI_MAX];
+        const int bar = (s[0].z >> 24) & 1;
+        int anymulti = 0, items = 0;
+        for (int i = 0; i < SEGI_MAX; ++i) {
+            CHECK(((s[i].z >> 24) & 1) == bar, "inverse L=%d s=%d: barrier flag differs within workgroup %zu\n", L,
+                  as, g);
+            if (s[i].x < 0) continue;
+            ++items;
+            const int n0 = s[i].x, m0 = s[i].y, seg = s[i].z & 0xff, nseg = (s[i].z >> 8) & 0xff;
+            const int lead = (s[i].z >> 16) & 0xff, jb = s[i].w;
+            anymulti |= nseg > 1;
+            CHECK(n0 % 64 == 0 && n0 < L && m0 % 2 == 0 && m0 < L, "inverse L=%d: group (%d, %d)\n", L, n0, m0);
+            CHECK(lead + seg == i && lead + nseg <= SEGI_MAX, "inverse L=%d: slot layout\n", L);
+            for (int k = 0; k < nseg && lead + k < SEGI_MAX; ++k) {
+                const int4 o = s[lead + k];
+                CHECK(o.x == n0 && o.y == m0 && (o.z & 0xff) == k && ((o.z >> 8) & 0xff) == nseg && o.w == jb,
+                      "inverse L=%d: sibling segment\n", L);
+            }
+            // every chain start (n, m or |s|) lies below lA; later segments restart at
+            // checkpoint planes c = j*segi with 0 < j < nsegi above all of them
+            const int lstart = std::max(n0, m0) & ~1;
+            const int lA = std::max(std::max(n0 + 64, m0 + 2), as + 1);
+            if (nseg > 1) CHECK(jb * p.segi >= std::max(lA, lstart + 2), "inverse L=%d: first boundary\n", L);
+            if (seg >= 1) {
+                const int c = (jb + seg - 1) * p.segi;
+                CHECK(c < L && c >= lA && jb + seg - 1 < p.nsegi, "inverse L=%d s=%d: restart degree %d\n", L, as, c);
+            }
+            const int from = (seg == 0) ? lstart : (jb + seg - 1) * p.segi;
+            const int to = (seg == nseg - 1) ? p.Lp : (jb + seg) * p.segi;
+            CHECK(to > from, "inverse L=%d: empty segment\n", L);
+            steps[g * SEGI_MAX + i] = to - from;
+            CHECK(seen[std::make_tuple(n0, m0, seg)]++ == 0, "inverse L=%d: duplicate segment\n", L);
+        }
+        CHECK(!items || bar == anymulti, "inverse L=%d: barrier flag of workgroup %zu\n", L, g);
+    }
+    // the chains of every group are covered from lstart to the last degree
+    for (int n0 = 0; n0 < L; n0 += 64)
+        for (int m0 = 0; m0 < L; m0 += 2) {
+            int nseg = -1;
+            for (int k = 0; k < SEGI_MAX; ++k)
+                if (seen.count(std::make_tuple(n0, m0, k))) nseg = k + 1;
+            CHECK(nseg >= 1, "inverse L=%d s=%d: group (%d, %d) missing\n", L, as, n0, m0);
+            for (int k = 0; k < nseg; ++k)
+                CHECK(seen.count(std::make_tuple(n0, m0, k)) == 1, "inverse L=%d: segment gap\n", L);
+        }
+    check_balance("inverse", L, w, SEGI_MAX, RESIDENT_INV, steps);
+}
+
+static void check_forward(int L)
+{
+    Plan p;
+    p.L = L;
+    p.Lp = L + (L & 1);
+    CHECK(segment_chains(L, SEG_MAX, p.segf, p.nsegf), "forward L=%d: segmentation\n", L);
+    const std::vector<int4> w = forward_work(p);
+    CHECK(w.size() % SEG_MAX == 0, "forward L=%d: size\n", L);
+    std::map<std::tuple<int, int, int>, int> seen;
+    std::vector<long> steps(w.size(), 0);
+    for (size_t g = 0; g < w.size() / SEG_MAX; ++g) {
+        const int4* s = &w[g * SEG_MAX];
+        const int bar = (s[0].z >> 24) & 1;
+        int anymulti = 0, items = 0;
+        for (int i = 0; i < SEG_MAX; ++i) {
+            CHECK(((s[i].z >> 24) & 1) == bar, "forward L=%d: barrier flag differs\n", L);
+            if (s[i].x < 0) continue;
+            ++items;
+            const int l0 = s[i].x, mb = s[i].y, seg = s[i].z & 0xff, nseg = (s[i].z >> 8) & 0xff;
+            const int lead = (s[i].z >> 16) & 0xff;
+            const int nmax = std::min(l0 + 63, L - 1);
+            anymulti |= nseg > 1;
+            CHECK(l0 % 64 == 0 && mb % MT_FWD == 0 && mb <= nmax, "forward L=%d: group (%d, %d)\n", L, l0, mb);
+            CHECK(nseg == nmax / p.segf + 1 && seg < nseg, "forward L=%d: segment count\n", L);
+            CHECK(lead + seg == i && lead + nseg <= SEG_MAX, "forward L=%d: slot layout\n", L);
+            for (int k = 0; k < nseg && lead + k < SEG_MAX; ++k) {
+                const int4 o = s[lead + k];
+                CHECK(o.x == l0 && o.y == mb && (o.z & 0xff) == k, "forward L=%d: sibling segment\n", L);
+            }
+            steps[g * SEG_MAX + i] = std::min((seg + 1) * p.segf, nmax + 1) - seg * p.segf;
+            CHECK(seen[std::make_tuple(l0, mb, seg)]++ == 0, "forward L=%d: duplicate segment\n", L);
+        }
+        CHECK(!items || bar == anymulti, "forward L=%d: barrier flag of workgroup %zu\n", L, g);
+    }
+    for (int l0 = 0; l0 < L; l0 += 64) {
+        const int nmax = std::min(l0 + 63, L - 1);
+        for (int mb = 0; mb <= nmax; mb += MT_FWD)
+            for (int k = 0; k <= nmax / p.segf; ++k)
+                CHECK(seen.count(std::make_tuple(l0, mb, k)) == 1, "forward L=%d: segment (%d, %d, %d) missing\n", L,
+                      l0, mb, k);
+    }
+    check_balance("forward", L, w, SEG_MAX, RESIDENT_FWD, steps);
+}
+
+int main()
+{
+    std::vector<int> Ls;
+    for (int L = 1; L <= 260; ++L) Ls.push_back(L);
+    for (int L : {300, 383, 384, 511, 512, 513, 640, 901, 1000, 1024, 1500, 2047, 2048}) Ls.push_back(L);
+    long cases = 0;
+    for (int L : Ls) {
+        check_forward(L);
+        ++cases;
+        for (int as : {0, 1, 2, 3, 7, 63, 64, 65, 100, 200, L - 1}) {
+            if (as < 0 || as >= L) continue;
+            check_inverse(L, as);
+            ++cases;
+        }
+    }
+    printf("%ld work lists checked, %ld problems\n", cases, bad);
+    return bad != 0;
+}
