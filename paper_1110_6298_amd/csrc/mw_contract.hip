@@ -1239,46 +1239,67 @@ __device__ __forceinline__ void inv2m_pair(InvLane2<EXT>& st, v4f (&acc)[2][G], 
     }
 }
 
+// Pairs j .. jto of a segment (INJ: pairs with chain starts), window by window:
+// on entering window q the window loaded one window earlier is stored to LDS and
+// window q+1 requested; the pairs of a window then run two at a time with the
+// uniform data and 1/sqrt factors alternating between the A and B register sets
+// (A holds pair j on entry and on return).
+template <bool EXT, bool INJ, int G>
+__device__ __forceinline__ void inv2m_run(InvLane2<EXT>& st, v4f (&acc)[2][G], const InvSeg& g, int& j, int jto,
+                                          int jend, int lstart, int ne, double nd, int m0, const Inv2Rows& rows,
+                                          const double* __restrict__ Rt, float* __restrict__ win,
+                                          const MixMaps& maps, int lane, InvWin2<G>& nxt, InvC2& uA, InvR& rA,
+                                          bool& anyscaled)
+{
+    constexpr int PW = WIN / 2;   // pairs per window
+    const int comp = lane & 3;
+    InvC2 uB;
+    InvR rB;
+    while (j <= jto) {
+        if (j == g.jfrom || (j % PW) == 0) {          // entering window j / PW
+            win_store<2 * G>(win, nxt.v, lane);
+            if (j / PW < g.jlast / PW) inv2m_win_load<G>(nxt, maps, m0, j / PW + 1, lane);
+        }
+        const int jw = min(jto, (j / PW) * PW + PW - 1);   // last pair of this window in range
+        for (; j < jw; j += 2) {
+            wait_scalar(uA.c0.x);
+            inv2m_load_c(uB, rows, min(j + 1, jend));
+            rB = inv_load_r(Rt, ne, min(j + 1, jend));
+            inv2m_pair<EXT, INJ, G>(st, acc, j, lstart, nd, uA, rA, win, comp, anyscaled);
+            wait_scalar(uB.c0.x);
+            inv2m_load_c(uA, rows, min(j + 2, jend));
+            rA = inv_load_r(Rt, ne, min(j + 2, jend));
+            inv2m_pair<EXT, INJ, G>(st, acc, j + 1, lstart, nd, uB, rB, win, comp, anyscaled);
+        }
+        if (j == jw) {                                 // odd pair left in the window
+            wait_scalar(uA.c0.x);
+            inv2m_load_c(uB, rows, min(j + 1, jend));
+            rB = inv_load_r(Rt, ne, min(j + 1, jend));
+            inv2m_pair<EXT, INJ, G>(st, acc, j, lstart, nd, uA, rA, win, comp, anyscaled);
+            uA = uB;
+            rA = rB;
+            ++j;
+        }
+    }
+}
+
 template <bool EXT, int G>
 __device__ __forceinline__ void inv2m_segment(InvLane2<EXT>& st, v4f (&acc)[2][G], const InvSeg& g, int jend,
                                               int lstart, int ne, double nd, int m0, const Inv2Rows& rows,
                                               const double* __restrict__ Rt, float* __restrict__ win,
                                               const MixMaps& maps, int lane, bool& anyscaled)
 {
-    constexpr int PW = WIN / 2;   // pairs per window
-    const int comp = lane & 3;
+    constexpr int PW = WIN / 2;
     InvWin2<G> nxt;
     inv2m_win_load<G>(nxt, maps, m0, g.jfrom / PW, lane);
-    InvC2 un;
-    inv2m_load_c(un, rows, g.jfrom);
-    InvR rn = inv_load_r(Rt, ne, g.jfrom);
-    auto enter = [&](int j) {
-        if (j == g.jfrom || (j % PW) == 0) {          // entering window j / PW
-            win_store<2 * G>(win, nxt.v, lane);
-            if (j / PW < g.jlast / PW) inv2m_win_load<G>(nxt, maps, m0, j / PW + 1, lane);
-        }
-    };
+    InvC2 uA;
+    inv2m_load_c(uA, rows, g.jfrom);
+    InvR rA = inv_load_r(Rt, ne, g.jfrom);
     int j = g.jfrom;
-    for (; j <= min(g.jA, g.jlast); ++j) {            // pairs with chain starts
-        enter(j);
-        wait_scalar(un.c0.x);
-        const InvC2 u = un;
-        const InvR r = rn;
-        const int jn = min(j + 1, jend);
-        inv2m_load_c(un, rows, jn);
-        rn = inv_load_r(Rt, ne, jn);
-        inv2m_pair<EXT, true, G>(st, acc, j, lstart, nd, u, r, win, comp, anyscaled);
-    }
-    for (; j <= g.jlast; ++j) {
-        enter(j);
-        wait_scalar(un.c0.x);
-        const InvC2 u = un;
-        const InvR r = rn;
-        const int jn = min(j + 1, jend);
-        inv2m_load_c(un, rows, jn);
-        rn = inv_load_r(Rt, ne, jn);
-        inv2m_pair<EXT, false, G>(st, acc, j, lstart, nd, u, r, win, comp, anyscaled);
-    }
+    inv2m_run<EXT, true, G>(st, acc, g, j, min(g.jA, g.jlast), jend, lstart, ne, nd, m0, rows, Rt, win, maps, lane,
+                            nxt, uA, rA, anyscaled);   // pairs with chain starts
+    inv2m_run<EXT, false, G>(st, acc, g, j, g.jlast, jend, lstart, ne, nd, m0, rows, Rt, win, maps, lane, nxt, uA,
+                             rA, anyscaled);
 }
 
 // LDS floats per wave slot: its window, later its partial sums (a v4f per
