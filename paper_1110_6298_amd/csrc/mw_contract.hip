@@ -1042,36 +1042,55 @@ __device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT>& st, v4f (&acc)[2][
         }
 }
 
+// Pairs k .. kto (descending; INJ: pairs with lane starts), window by window:
+// on entering window q the window loaded one window earlier is stored to LDS and
+// window q-1 requested; the pairs of a window then run two at a time with the
+// 1/sqrt factors alternating between the A and B register sets (A holds pair k
+// on entry and on return).
+template <bool EXT, bool INJ, int G>
+__device__ __forceinline__ void fwd_mix_run(FwdLane<2, EXT>& st, v4f (&acc)[2][G], const FwdSeg& g, int& k, int kto,
+                                            int l, int le, int mb, int as, const double* __restrict__ Rt,
+                                            float* __restrict__ win, const MixMaps& maps, int lane, FwdWin<G>& nxt,
+                                            FwdR& rA, bool& anyscaled)
+{
+    constexpr int PW = WIN / 2;   // pairs per window
+    const int comp = lane & 3;
+    FwdR rB;
+    while (k >= kto) {
+        if (k == g.ktop || (k % PW) == PW - 1) {       // entering window k / PW
+            win_store<2 * G>(win, nxt.v, lane);
+            if (k / PW > g.klo / PW) fwd_win_load<G>(nxt, maps, mb, k / PW - 1, lane);
+        }
+        const int kw = max(kto, (k / PW) * PW);        // lowest pair of this window in range
+        for (; k > kw; k -= 2) {
+            rB = fwd_load_r(Rt, le, max(k - 1, 0));
+            fwd_mix_pair<EXT, INJ, G>(st, acc, k, l, mb, as, win, comp, rA, anyscaled);
+            rA = fwd_load_r(Rt, le, max(k - 2, 0));
+            fwd_mix_pair<EXT, INJ, G>(st, acc, k - 1, l, mb, as, win, comp, rB, anyscaled);
+        }
+        if (k == kw) {                                 // odd pair left in the window
+            rB = fwd_load_r(Rt, le, max(k - 1, 0));
+            fwd_mix_pair<EXT, INJ, G>(st, acc, k, l, mb, as, win, comp, rA, anyscaled);
+            rA = rB;
+            --k;
+        }
+    }
+}
+
 template <bool EXT, int G>
 __device__ __forceinline__ void fwd_mix_segment(FwdLane<2, EXT>& st, v4f (&acc)[2][G], const FwdSeg& g, int l,
                                                 int le, int mb, int as, const double* __restrict__ Rt,
                                                 float* __restrict__ win, const MixMaps& maps, int lane,
                                                 bool& anyscaled)
 {
-    constexpr int PW = WIN / 2;   // pairs per window
-    const int comp = lane & 3;
+    constexpr int PW = WIN / 2;
     FwdWin<G> nxt;
     fwd_win_load<G>(nxt, maps, mb, g.ktop / PW, lane);
-    FwdR rn = fwd_load_r(Rt, le, g.ktop);
-    auto enter = [&](int k) {
-        if (k == g.ktop || (k % PW) == PW - 1) {       // entering window k / PW
-            win_store<2 * G>(win, nxt.v, lane);
-            if (k / PW > g.klo / PW) fwd_win_load<G>(nxt, maps, mb, k / PW - 1, lane);
-        }
-    };
+    FwdR rA = fwd_load_r(Rt, le, g.ktop);
     int k = g.ktop;
-    for (; k >= max(g.kA, g.klo); --k) {               // pairs with lane starts
-        enter(k);
-        const FwdR r = rn;
-        rn = fwd_load_r(Rt, le, max(k - 1, 0));
-        fwd_mix_pair<EXT, true, G>(st, acc, k, l, mb, as, win, comp, r, anyscaled);
-    }
-    for (; k >= g.klo; --k) {
-        enter(k);
-        const FwdR r = rn;
-        rn = fwd_load_r(Rt, le, max(k - 1, 0));
-        fwd_mix_pair<EXT, false, G>(st, acc, k, l, mb, as, win, comp, r, anyscaled);
-    }
+    fwd_mix_run<EXT, true, G>(st, acc, g, k, max(g.kA, g.klo), l, le, mb, as, Rt, win, maps, lane, nxt, rA,
+                              anyscaled);   // pairs with lane starts
+    fwd_mix_run<EXT, false, G>(st, acc, g, k, g.klo, l, le, mb, as, Rt, win, maps, lane, nxt, rA, anyscaled);
 }
 
 // Forward contraction of a group of up to G maps of one spin (band-limits
