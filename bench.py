@@ -23,8 +23,8 @@ PEAK_FP64_VALU = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 # read for a plain copy of known size (profiles/traffic_roundtrip_L512_s2.md).
 # Valid only while the kernel and plan sources are unchanged: keyed by their SHA-256.
 TRAFFIC = {
-    ("contract_inverse", 512, 2): {"bytes": 22938709, "source_sha256": "4e67ac0bb49d90ae464432ec39413ceb5676202e8c7c8bb6f679e8c1f0a86e56"},
-    ("contract_forward", 512, 2): {"bytes": 29202758, "source_sha256": "4e67ac0bb49d90ae464432ec39413ceb5676202e8c7c8bb6f679e8c1f0a86e56"},
+    ("contract_inverse", 512, 2): {"bytes": 22938709, "source_sha256": "9cea837af10a6b3ded3e2930a6bc8117b66312676aa5de838c480751f6ca7c7f"},
+    ("contract_forward", 512, 2): {"bytes": 29202758, "source_sha256": "9cea837af10a6b3ded3e2930a6bc8117b66312676aa5de838c480751f6ca7c7f"},
 }
 KERNEL_SOURCES = ("paper_1110_6298_amd/csrc/mw_contract.hip", "paper_1110_6298_amd/csrc/mw_plan.cpp")
 

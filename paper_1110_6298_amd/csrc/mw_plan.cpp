@@ -387,9 +387,11 @@ void free_plan(Plan& p)
 // segment.
 struct SegItem { int a, b, nseg, jb, len, work; };
 
-// Workgroups per compute unit that the contraction kernels keep resident (the
-// lowest occupancy among the variants that read each list: the FP64 inverse
-// holds five to seven waves per SIMD, the forward four).
+// Workgroups per compute unit that the FP64 contraction kernels keep resident:
+// the inverse holds five (exponent-extended) or six waves per SIMD, the forward
+// four.  The mixed kernels read the same lists with as few as three or four;
+// where that is fewer than a list needs, their last workgroups start as others
+// finish.
 constexpr int RESIDENT_INV = 5;
 constexpr int RESIDENT_FWD = 4;
 
