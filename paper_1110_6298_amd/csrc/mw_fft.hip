@@ -6,6 +6,8 @@
 // Every DFT of the odd length N1 is evaluated with Bluestein's chirp identity
 // on a power-of-two FFT of length N2 >= 4L-3 (the same N2 that the weight
 // convolution needs), held entirely in LDS.
+#include <type_traits>
+
 #include "mw_internal.h"
 
 namespace mw {
@@ -159,9 +161,17 @@ __device__ __forceinline__ void twiddle_powers(double2* u, double2 w)
 // Final Stockham pass of radix R = 2, 4 or 8 (the factor left after the main
 // radix-RB passes): each thread holds RB/R butterflies in one RB-value register
 // set.  With post != nullptr every output X_j is stored as X_j * post[j].
-template <int DIR, int R, int RB>
+// Final store of a transform: PlainStore keeps output X_o at slot o; any other
+// Store is called as st(o, X_o) once per output in the last pass's write phase
+// (after every read of that pass), so it may write X_o, changed, to a slot of
+// its choosing as long as the slots of all outputs are distinct.
+struct PlainStore {
+    __device__ void operator()(int, double2) const {}   // never called
+};
+
+template <int DIR, int R, int RB, class Store = PlainStore>
 __device__ __forceinline__ void last_pass(double2* x, int N, int p, const double2 (&wl)[RB / 2],
-                                          const double2* __restrict__ post)
+                                          const double2* __restrict__ post, const Store& st = Store())
 {
     constexpr int r = (R == 2) ? 1 : (R == 4) ? 2 : 3;
     constexpr int QM = RB / R;
@@ -196,7 +206,10 @@ __device__ __forceinline__ void last_pass(double2* x, int N, int p, const double
         if (i < NB) {
             const int k = i & (p - 1);
             const int j = ((i - k) << r) + k;
-            if (post) {
+            if constexpr (!std::is_same_v<Store, PlainStore>) {
+#pragma unroll
+                for (int t = 0; t < R; ++t) st(j + t * p, u[q * R + t]);
+            } else if (post) {
 #pragma unroll
                 for (int t = 0; t < R; ++t) x[Pr<RB>(j + t * p)] = cmul(u[q * R + t], post[j + t * p]);
             } else {
@@ -253,11 +266,13 @@ __device__ __forceinline__ FftTw<RB> fft_twiddles(int N, int logN, const double2
 //   DIR = -1:  X_j = sum_k x_k exp(-2 pi i j k / N)
 //   DIR = +1:  X_j = sum_k x_k exp(+2 pi i j k / N)   (no 1/N)
 // T: the thread's twiddle bases for this N.  With post != nullptr the result is
-// X_j * post[j].
-template <int DIR, int RB>
+// X_j * post[j].  st: the final store (see PlainStore); with a Store other than
+// PlainStore, post is not applied.
+template <int DIR, int RB, class Store = PlainStore>
 __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const FftTw<RB>& T,
-                                          const double2* __restrict__ post = nullptr)
+                                          const double2* __restrict__ post = nullptr, const Store& st = Store())
 {
+    constexpr bool plain = std::is_same_v<Store, PlainStore>;
     constexpr int lr = (RB == 16) ? 4 : 3;
     const int i = threadIdx.x;
     const int np = logN / lr;        // main passes (at most 4 for N <= 8192)
@@ -284,22 +299,27 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const Fft
         __syncthreads();
         if (i < NB) {
             const int j = ((i - k) << lr) + k;
+            if (!plain && r == 0 && s == np - 1) {   // the last pass: outputs through st
 #pragma unroll
-            for (int t = 0; t < RB; ++t) x[Pr<RB>(j + t * p)] = u[t];
+                for (int t = 0; t < RB; ++t) st(j + t * p, u[t]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < RB; ++t) x[Pr<RB>(j + t * p)] = u[t];
+            }
         }
         p <<= lr;
         __syncthreads();
     }
-    if (r == 1) last_pass<DIR, 2, RB>(x, N, p, T.wl, post);
-    else if (r == 2) last_pass<DIR, 4, RB>(x, N, p, T.wl, post);
+    if (r == 1) last_pass<DIR, 2, RB>(x, N, p, T.wl, post, st);
+    else if (r == 2) last_pass<DIR, 4, RB>(x, N, p, T.wl, post, st);
     else if constexpr (RB == 16) {
-        if (r == 3) last_pass<DIR, 8, RB>(x, N, p, T.wl, post);
-        else if (post) {
+        if (r == 3) last_pass<DIR, 8, RB>(x, N, p, T.wl, post, st);
+        else if (plain && post) {
             for (int j = threadIdx.x; j < N; j += blockDim.x) x[Pr<RB>(j)] = cmul(x[Pr<RB>(j)], post[j]);
             __syncthreads();
         }
     }
-    else if (post) {
+    else if (plain && post) {
         for (int j = threadIdx.x; j < N; j += blockDim.x) x[Pr<RB>(j)] = cmul(x[Pr<RB>(j)], post[j]);
         __syncthreads();
     }
@@ -406,19 +426,17 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
         [&](int j, const Pair2& v) { A[Pr<RB>(j)] = cmul((j < L) ? v.a : cscale(v.a, sig), v.b); });
     // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
     const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
-    bluestein_core<RB>(A, p, T);
-    // F_{m'} into registers (N1 <= N2/2 <= 8 * blockDim.x), then scatter to slot m' mod N2.
-    double2 r[8];
-    // chirp_k e^{-i m' pi/N1} (and 1/(2 pi N1) for the forward proper)
-    const double scale = ADJ_INV ? 1.0 : p.thsc;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int k = threadIdx.x + q * blockDim.x;
-        if (k < N1) r[q] = cscale(cmul(A[Pr<RB>(k)], p.thwc[k]), scale);
-    }
-    __syncthreads();
     int wrap;   // index of -n is wrap - n
-    if (ADJ_INV) {
+    if constexpr (ADJ_INV) {
+        bluestein_core<RB>(A, p, T);
+        // F_{m'} = chirp_k e^{-i m' pi/N1} times the Bluestein output, k < N1
+        double2 r[8];   // N1 <= N2/2 <= 8 * blockDim.x
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int k = threadIdx.x + q * blockDim.x;
+            if (k < N1) r[q] = cmul(A[Pr<RB>(k)], p.thwc[k]);
+        }
+        __syncthreads();
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int k = threadIdx.x + q * blockDim.x;
@@ -427,16 +445,16 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
         __syncthreads();
         wrap = N1;
     } else {
-        for (int j = threadIdx.x; j < N2; j += blockDim.x) A[Pr<RB>(j)] = make_double2(0.0, 0.0);
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int k = threadIdx.x + q * blockDim.x;
-            if (k < N1) {
-                const int mp = (k <= L - 1) ? k : k - N1;
-                A[Pr<RB>((mp + N2) & (N2 - 1))] = r[q];
-            }
-        }
+        // Bluestein with its last store fused with the move onto the N2 grid:
+        // output k < N1 is F_{m'} / (chirp_k e^{-i m' pi/N1} / (2 pi N1)) and goes to
+        // slot m' mod N2 (m' = k, or k - N1 for k >= L); outputs k >= N1 are not
+        // needed and their slots k - N1 + L fill the zeros in between (a bijection).
+        const double scale = p.thsc;
+        block_fft<-1, RB>(A, N2, p.logN2, T, p.bhat);
+        block_fft<+1, RB>(A, N2, p.logN2, T, nullptr, [&](int k, double2 v) {
+            if (k < N1) A[Pr<RB>(k < L ? k : k + (N2 - N1))] = cscale(cmul(v, p.thwc[k]), scale);
+            else A[Pr<RB>(k - N1 + L)] = make_double2(0.0, 0.0);
+        });
         block_fft<+1, RB>(A, N2, p.logN2, T, p.what);
         block_fft<-1, RB>(A, N2, p.logN2, T);
         wrap = N2;
