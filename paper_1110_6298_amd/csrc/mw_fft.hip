@@ -334,6 +334,15 @@ __device__ __forceinline__ void bluestein_core(double2* x, const Plan& p, const 
     block_fft<+1, RB>(x, p.N2, p.logN2, T);
 }
 
+// The same with the final store st (see PlainStore): st(k, X_k) receives the
+// output before the chirp, k < N2.
+template <int RB, class Store>
+__device__ __forceinline__ void bluestein_core(double2* x, const Plan& p, const FftTw<RB>& T, const Store& st)
+{
+    block_fft<-1, RB>(x, p.N2, p.logN2, T, p.bhat);
+    block_fft<+1, RB>(x, p.N2, p.logN2, T, nullptr, st);
+}
+
 // XCD-aware column index: consecutive workgroups are dealt round-robin over the
 // 8 XCDs; give each XCD a contiguous range of columns so neighbouring columns
 // (which share cache lines of the row-major intermediates) meet in one L2.
@@ -373,6 +382,8 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
         [&](int j, const Pair2& v) { A[Pr<RB>(j)] = cmul(v.a, v.b); });
     // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
     const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
+    // (outputs stored from LDS in batches: written straight from the last pass,
+    // the stride-L stores of G were measured slower)
     bluestein_core<RB>(A, p, T);
     staged_loop(
         N1, [&](int k) { return p.chirp[k]; },
@@ -593,10 +604,9 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
         });
     // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
     const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
-    bluestein_core<RB>(A, p, T);
-    staged_loop(
-        L, [&](int t) { return p.chirp[t]; },
-        [&](int t, double2 c) { Ft[(size_t)t * N1 + mi] = cconj(cmul(A[Pr<RB>(t)], c)); });
+    bluestein_core<RB>(A, p, T, [&](int t, double2 v) {   // outputs t < L, straight to Ft
+        if (t < L) Ft[(size_t)t * N1 + mi] = cconj(cmul(v, p.chirp[t]));
+    });
 }
 
 // Inverse phi stage (Eq.(f_pfft)): f(t, p) = sc sum_m F_m(theta_t) e^{i m phi_p}, with
@@ -630,14 +640,13 @@ __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
         });
     // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
     const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
-    bluestein_core<RB>(A, p, T);
-    staged_loop(
-        N1, [&](int k) { return p.chirp[k]; },
-        [&](int k, double2 c) {
-            const double2 out = cscale(cconj(cmul(A[Pr<RB>(k)], c)), sc);
+    bluestein_core<RB>(A, p, T, [&](int k, double2 v) {   // outputs k < N1, straight to the map
+        if (k < N1) {
+            const double2 out = cscale(cconj(cmul(v, p.chirp[k])), sc);
             if (REAL) ((double*)map)[(size_t)t * N1 + k] = out.x;
             else ((double2*)map)[(size_t)t * N1 + k] = out;
-        });
+        }
+    });
 }
 
 // Main radix of the FFTs for a plan.  It depends on the band-limit only, so a
