@@ -169,6 +169,13 @@ struct PlainStore {
     __device__ void operator()(int, double2) const {}   // never called
 };
 
+// First load of a transform: PlainLoad reads the input from LDS; any other Load
+// is called as ld(j) for every input j < N by the first pass (which needs no
+// twiddles), so the input can come straight from global memory.
+struct PlainLoad {
+    __device__ double2 operator()(int) const { return make_double2(0.0, 0.0); }   // never called
+};
+
 template <int DIR, int R, int RB, class Store = PlainStore>
 __device__ __forceinline__ void last_pass(double2* x, int N, int p, const double2 (&wl)[RB / 2],
                                           const double2* __restrict__ post, const Store& st = Store())
@@ -267,12 +274,14 @@ __device__ __forceinline__ FftTw<RB> fft_twiddles(int N, int logN, const double2
 //   DIR = +1:  X_j = sum_k x_k exp(+2 pi i j k / N)   (no 1/N)
 // T: the thread's twiddle bases for this N.  With post != nullptr the result is
 // X_j * post[j].  st: the final store (see PlainStore); with a Store other than
-// PlainStore, post is not applied.
-template <int DIR, int RB, class Store = PlainStore>
+// PlainStore, post is not applied.  ld: the first load (see PlainLoad).
+template <int DIR, int RB, class Store = PlainStore, class Load = PlainLoad>
 __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const FftTw<RB>& T,
-                                          const double2* __restrict__ post = nullptr, const Store& st = Store())
+                                          const double2* __restrict__ post = nullptr, const Store& st = Store(),
+                                          const Load& ld = Load())
 {
     constexpr bool plain = std::is_same_v<Store, PlainStore>;
+    constexpr bool plain_ld = std::is_same_v<Load, PlainLoad>;
     constexpr int lr = (RB == 16) ? 4 : 3;
     const int i = threadIdx.x;
     const int np = logN / lr;        // main passes (at most 4 for N <= 8192)
@@ -286,8 +295,13 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const Fft
         double2 u[RB];
         const int k = i & (p - 1);
         if (i < NB) {
+            if (!plain_ld && s == 0) {
 #pragma unroll
-            for (int t = 0; t < RB; ++t) u[t] = x[Pr<RB>(i + t * NB)];
+                for (int t = 0; t < RB; ++t) u[t] = ld(i + t * NB);
+            } else {
+#pragma unroll
+                for (int t = 0; t < RB; ++t) u[t] = x[Pr<RB>(i + t * NB)];
+            }
             if (s > 0) {   // the first pass has k = 0: no twiddles
                 double2 w = T.w[s > 0 ? s - 1 : 0];
                 if (DIR > 0) w = cconj(w);
@@ -334,12 +348,14 @@ __device__ __forceinline__ void bluestein_core(double2* x, const Plan& p, const 
     block_fft<+1, RB>(x, p.N2, p.logN2, T);
 }
 
-// The same with the final store st (see PlainStore): st(k, X_k) receives the
-// output before the chirp, k < N2.
-template <int RB, class Store>
-__device__ __forceinline__ void bluestein_core(double2* x, const Plan& p, const FftTw<RB>& T, const Store& st)
+// The same with the first load ld (see PlainLoad: ld(j) returns the chirped,
+// zero-padded input a_j, j < N2) and the final store st (see PlainStore:
+// st(k, X_k) receives the output before the chirp, k < N2).
+template <int RB, class Load, class Store = PlainStore>
+__device__ __forceinline__ void bluestein_core(double2* x, const Plan& p, const FftTw<RB>& T, const Load& ld,
+                                               const Store& st = Store())
 {
-    block_fft<-1, RB>(x, p.N2, p.logN2, T, p.bhat);
+    block_fft<-1, RB>(x, p.N2, p.logN2, T, p.bhat, PlainStore(), ld);
     block_fft<+1, RB>(x, p.N2, p.logN2, T, nullptr, st);
 }
 
@@ -368,23 +384,17 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
     const int L = p.L, N1 = p.N1;
     const int t = xcd_column(L);
     if (t >= L) return;
-    staged_loop(
-        p.N2,
-        [&](int j) {
-            Pair2 v{make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
-            if (j < N1) {
-                v.a = REAL ? make_double2(((const double*)map)[(size_t)t * N1 + j], 0.0)
-                           : ((const double2*)map)[(size_t)t * N1 + j];
-                v.b = p.chirp[j];
-            }
-            return v;
-        },
-        [&](int j, const Pair2& v) { A[Pr<RB>(j)] = cmul(v.a, v.b); });
-    // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
+    // twiddle bases of all FFTs below, read before the first pass (it needs none)
     const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
-    // (outputs stored from LDS in batches: written straight from the last pass,
+    // the ring's samples, chirped and zero-padded, read by the first pass; the
+    // outputs are stored from LDS in batches (written straight from the last pass,
     // the stride-L stores of G were measured slower)
-    bluestein_core<RB>(A, p, T);
+    bluestein_core<RB>(A, p, T, [&](int j) {
+        if (j >= N1) return make_double2(0.0, 0.0);
+        const double2 a = REAL ? make_double2(((const double*)map)[(size_t)t * N1 + j], 0.0)
+                               : ((const double2*)map)[(size_t)t * N1 + j];
+        return cmul(a, p.chirp[j]);
+    });
     staged_loop(
         N1, [&](int k) { return p.chirp[k]; },
         [&](int k, double2 c) {
@@ -423,23 +433,20 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
     if (mi >= N1) return;
     const int m = mi - (L - 1);
     const double sig = ((m + s) & 1) ? -1.0 : 1.0;
-    staged_loop(
-        N2,
-        [&](int j) {
-            Pair2 v{make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
-            if (j < N1) {
-                if (j < L) v.a = G[(size_t)mi * L + j];
-                else if (!ADJ_INV) v.a = G[(size_t)mi * L + (2 * L - 2 - j)];
-                v.b = p.chirp[j];
-            }
-            return v;
-        },
-        [&](int j, const Pair2& v) { A[Pr<RB>(j)] = cmul((j < L) ? v.a : cscale(v.a, sig), v.b); });
-    // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
+    // twiddle bases of all FFTs below, read before the first pass (it needs none)
     const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
+    // the extended column (t < L as given, then (-1)^{m+s} times the mirror image;
+    // the adjoint of the inverse has no extension), chirped and zero-padded
+    auto ld = [&](int j) {
+        if (j >= N1) return make_double2(0.0, 0.0);
+        double2 a = make_double2(0.0, 0.0);
+        if (j < L) a = G[(size_t)mi * L + j];
+        else if (!ADJ_INV) a = cscale(G[(size_t)mi * L + (2 * L - 2 - j)], sig);
+        return cmul(a, p.chirp[j]);
+    };
     int wrap;   // index of -n is wrap - n
     if constexpr (ADJ_INV) {
-        bluestein_core<RB>(A, p, T);
+        bluestein_core<RB>(A, p, T, ld);
         // F_{m'} = chirp_k e^{-i m' pi/N1} times the Bluestein output, k < N1
         double2 r[8];   // N1 <= N2/2 <= 8 * blockDim.x
 #pragma unroll
@@ -461,7 +468,7 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
         // slot m' mod N2 (m' = k, or k - N1 for k >= L); outputs k >= N1 are not
         // needed and their slots k - N1 + L fill the zeros in between (a bijection).
         const double scale = p.thsc;
-        block_fft<-1, RB>(A, N2, p.logN2, T, p.bhat);
+        block_fft<-1, RB>(A, N2, p.logN2, T, p.bhat, PlainStore(), ld);
         block_fft<+1, RB>(A, N2, p.logN2, T, nullptr, [&](int k, double2 v) {
             if (k < N1) A[Pr<RB>(k < L ? k : k + (N2 - N1))] = cscale(cmul(v, p.thwc[k]), scale);
             else A[Pr<RB>(k - N1 + L)] = make_double2(0.0, 0.0);
@@ -585,28 +592,20 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
     if (mi >= N1) return;
     const int m = mi - (L - 1);
     const double sig = ((m + s) & 1) ? -1.0 : 1.0;
-    staged_loop(
-        N2,
-        [&](int j) {
-            Pair2 v{make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
-            if (j < N1) {
-                const int mp = (j <= L - 1) ? j : j - N1;
-                v.a = F[(size_t)mi * L + (mp < 0 ? -mp : mp)];
-                v.b = p.thwc[j];
-            }
-            return v;
-        },
-        [&](int j, const Pair2& v) {
-            const int mp = (j <= L - 1) ? j : j - N1;
-            const double2 f = (mp < 0) ? cscale(v.a, sig) : v.a;
-            // conj(f e^{+i m' pi/N1}) chirp_j = conj(f) (e^{-i m' pi/N1} chirp_j)
-            A[Pr<RB>(j)] = cmul(cconj(f), v.b);
-        });
-    // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
+    // twiddle bases of all FFTs below, read before the first pass (it needs none)
     const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
-    bluestein_core<RB>(A, p, T, [&](int t, double2 v) {   // outputs t < L, straight to Ft
-        if (t < L) Ft[(size_t)t * N1 + mi] = cconj(cmul(v, p.chirp[t]));
-    });
+    bluestein_core<RB>(
+        A, p, T,
+        [&](int j) {   // the unfolded F_{mm'}, m' = j or j - N1, as conj(f e^{+i m' pi/N1}) chirp_j
+            if (j >= N1) return make_double2(0.0, 0.0);
+            const int mp = (j <= L - 1) ? j : j - N1;
+            double2 f = F[(size_t)mi * L + (mp < 0 ? -mp : mp)];
+            if (mp < 0) f = cscale(f, sig);
+            return cmul(cconj(f), p.thwc[j]);   // thwc_j = e^{-i m' pi/N1} chirp_j
+        },
+        [&](int t, double2 v) {   // outputs t < L, straight to Ft
+            if (t < L) Ft[(size_t)t * N1 + mi] = cconj(cmul(v, p.chirp[t]));
+        });
 }
 
 // Inverse phi stage (Eq.(f_pfft)): f(t, p) = sc sum_m F_m(theta_t) e^{i m phi_p}, with
@@ -623,30 +622,24 @@ __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
     const int L = p.L, N1 = p.N1;
     const int t = xcd_column(L);
     if (t >= L) return;
-    staged_loop(
-        p.N2,
-        [&](int j) {
-            Pair2 v{make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
-            if (j < N1) {
-                const int m = (j <= L - 1) ? j : j - N1;
-                v.a = Ft[(size_t)t * N1 + ((REAL == 2 && m < 0 ? -m : m) + L - 1)];
-                v.b = p.chirp[j];
-            }
-            return v;
-        },
-        [&](int j, const Pair2& v) {
-            const bool neg = REAL == 2 && j > L - 1 && j < N1;     // order m = j - N1 < 0
-            A[Pr<RB>(j)] = cmul(neg ? v.a : cconj(v.a), v.b);            // conj(F_m), F_m = conj(F_{-m})
-        });
-    // twiddle bases of all FFTs below, read while the first pass runs (it needs none)
+    // twiddle bases of all FFTs below, read before the first pass (it needs none)
     const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
-    bluestein_core<RB>(A, p, T, [&](int k, double2 v) {   // outputs k < N1, straight to the map
-        if (k < N1) {
-            const double2 out = cscale(cconj(cmul(v, p.chirp[k])), sc);
-            if (REAL) ((double*)map)[(size_t)t * N1 + k] = out.x;
-            else ((double2*)map)[(size_t)t * N1 + k] = out;
-        }
-    });
+    bluestein_core<RB>(
+        A, p, T,
+        [&](int j) {   // conj(F_m) chirp_j, m = j or j - N1 (F_m = conj(F_{-m}) for REAL = 2)
+            if (j >= N1) return make_double2(0.0, 0.0);
+            const int m = (j <= L - 1) ? j : j - N1;
+            const double2 a = Ft[(size_t)t * N1 + ((REAL == 2 && m < 0 ? -m : m) + L - 1)];
+            const bool neg = REAL == 2 && m < 0;
+            return cmul(neg ? a : cconj(a), p.chirp[j]);
+        },
+        [&](int k, double2 v) {   // outputs k < N1, straight to the map
+            if (k < N1) {
+                const double2 out = cscale(cconj(cmul(v, p.chirp[k])), sc);
+                if (REAL) ((double*)map)[(size_t)t * N1 + k] = out.x;
+                else ((double2*)map)[(size_t)t * N1 + k] = out;
+            }
+        });
 }
 
 // Main radix of the FFTs for a plan.  It depends on the band-limit only, so a
