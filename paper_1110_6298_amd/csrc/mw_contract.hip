@@ -986,9 +986,13 @@ __device__ __forceinline__ v4f mfma4(float a, float b, v4f c)
 // loaded from global memory one window earlier (a wave reads only the window
 // it wrote, so no barrier is needed).
 constexpr int WIN = 32;                  // steps (n or l values) per window; 16 pairs
+// LDS floats per window row: two more than WIN, so that the four component rows
+// one step reads (one address each, broadcast to their lanes) start on banks 2
+// apart instead of all on one bank.
+constexpr int WROW = WIN + 2;
 
 // Forward window q (n in [WIN*q, WIN*q + WIN)): rows (b, c, comp) of WIN floats,
-// 8G rows, held as 4G float2 values per lane of the wave.
+// 8G rows, held as 2G float2 values per lane of the wave (in LDS, rows of WROW).
 template <int G>
 struct FwdWin { fv2 v[2 * G]; };
 
@@ -1014,7 +1018,10 @@ template <int G>
 __device__ __forceinline__ void win_store(float* __restrict__ win, const fv2* v, int lane)
 {
 #pragma unroll
-    for (int t = 0; t < G; ++t) ((fv2*)win)[lane + 64 * t] = v[t];
+    for (int t = 0; t < G; ++t) {
+        const int e = lane + 64 * t;   // float2 index in the window, 16 per row
+        ((fv2*)win)[(e >> 4) * (WROW / 2) + (e & 15)] = v[t];
+    }
 }
 
 template <bool EXT, bool INJ, int G>
@@ -1036,7 +1043,7 @@ __device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT>& st, v4f (&acc)[2][
     for (int b = 0; b < G; ++b)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const fv2 a = *(const fv2*)(win + ((b * 2 + c) * 4 + comp) * WIN + off);   // n = 2k, 2k+1
+            const fv2 a = *(const fv2*)(win + ((b * 2 + c) * 4 + comp) * WROW + off);   // n = 2k, 2k+1
             acc[c][b] = mfma4(a.y, k1[c], acc[c][b]);
             acc[c][b] = mfma4(a.x, k0[c], acc[c][b]);
         }
@@ -1102,7 +1109,7 @@ __device__ __forceinline__ void fwd_mix_segment(FwdLane<2, EXT>& st, v4f (&acc)[
 // sums (a v4f per order, map and lane).
 __host__ __device__ constexpr int fwdm_slot_floats(int G)
 {
-    return (G * 8 * WIN > 2 * G * 64 * 4) ? G * 8 * WIN : 2 * G * 64 * 4;
+    return (G * 8 * WROW > 2 * G * 64 * 4) ? G * 8 * WROW : 2 * G * 64 * 4;
 }
 
 template <bool EXT, int G>
@@ -1251,7 +1258,7 @@ __device__ __forceinline__ void inv2m_pair(InvLane2<EXT>& st, v4f (&acc)[2][G], 
         const float k0 = (float)p0[c], k1 = (float)p1[c];
 #pragma unroll
         for (int b = 0; b < G; ++b) {
-            const fv2 a = *(const fv2*)(win + ((b * 2 + c) * 4 + comp) * WIN + off);   // degrees l, l+1
+            const fv2 a = *(const fv2*)(win + ((b * 2 + c) * 4 + comp) * WROW + off);   // degrees l, l+1
             acc[c][b] = mfma4(a.x, k0, acc[c][b]);
             acc[c][b] = mfma4(a.y, k1, acc[c][b]);
         }
@@ -1325,7 +1332,7 @@ __device__ __forceinline__ void inv2m_segment(InvLane2<EXT>& st, v4f (&acc)[2][G
 // order, map and lane).
 __host__ __device__ constexpr int inv2m_slot_floats(int G)
 {
-    return (2 * G * 4 * WIN > 2 * G * 64 * 4) ? 2 * G * 4 * WIN : 2 * G * 64 * 4;
+    return (2 * G * 4 * WROW > 2 * G * 64 * 4) ? 2 * G * 4 * WROW : 2 * G * 64 * 4;
 }
 
 template <bool EXT, int G>
