@@ -429,8 +429,11 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
     const double2* __restrict__ G = (const double2*)B.in[blockIdx.y];
     void* __restrict__ Hout = B.out[blockIdx.y];
     const int L = p.L, N1 = p.N1, N2 = p.N2;
-    const int mi = HALF ? xcd_column(L) + (L - 1) : xcd_column(N1);
-    if (mi >= N1) return;
+    // columns interleave +m and -m (c = 0, 1, 2, ... -> m = 0, 1, -1, 2, -2, ...), so
+    // the two workgroups that write the halves of one row of H records share an XCD
+    const int c = HALF ? xcd_column(L) : xcd_column(N1);
+    if (c >= (HALF ? L : N1)) return;
+    const int mi = HALF ? c + (L - 1) : ((c & 1) ? (L - 1) + ((c + 1) >> 1) : (L - 1) - (c >> 1));
     const int m = mi - (L - 1);
     const double sig = ((m + s) & 1) ? -1.0 : 1.0;
     // twiddle bases of all FFTs below, read before the first pass (it needs none)
