@@ -501,7 +501,8 @@ static std::vector<int4> inverse_work(const Plan& p, int as)
 // FP64 forward contraction: group (l0, mb) runs the row recursions from nmax =
 // min(l0+63, L-1) down to 0, in segments w = 0 .. jtop (jtop = nmax/segf) of
 // n in [w*segf, (w+1)*segf); the top one also starts the lanes.  Dealt to XCDs
-// by order pair; ordered by the longest segment.
+// by chunks of eight orders (for L >= 256), so that the waves writing the f_lm
+// of one line (orders m..m+7 at one degree) meet in one L2.
 static std::vector<int4> forward_work(const Plan& p)
 {
     const int L = p.L, segf = p.segf;
@@ -510,8 +511,15 @@ static std::vector<int4> forward_work(const Plan& p)
         const int nmax = std::min(l0 + 63, L - 1);
         const int jtop = nmax / segf;
         const int len = std::max(nmax - jtop * segf + 1, jtop > 0 ? segf : 0);
-        for (int mb = 0; mb <= nmax; mb += MT_FWD)
-            items[(mb / MT_FWD) & 7].push_back(SegItem{l0, mb, jtop + 1, 0, len, nmax + 1 + 16 * (jtop + 1)});
+        for (int mb = 0; mb <= nmax; mb += MT_FWD) {
+            // orders in chunks of 8 (one 128-byte line of f_lm per degree), dealt
+            // to the XCDs back and forth so every XCD gets low and high orders;
+            // below L = 256 (fewer than four rounds of chunks) the XCDs would get
+            // unequal shares, and order pairs are dealt round-robin instead
+            const int chunk = mb >> 3, pos = chunk & 7;
+            const int x = (L < 256) ? (mb / MT_FWD) & 7 : (((chunk >> 3) & 1) ? 7 - pos : pos);
+            items[x].push_back(SegItem{l0, mb, jtop + 1, 0, len, nmax + 1 + 16 * (jtop + 1)});
+        }
     }
     return pack_segments(items, SEG_MAX, RESIDENT_FWD);
 }
