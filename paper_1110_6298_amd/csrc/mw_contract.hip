@@ -569,17 +569,18 @@ __device__ __forceinline__ InvR inv_load_r(const double* __restrict__ Rt, int ne
     return r;
 }
 
-struct CkOff { size_t off[SEGI_MAX]; };
+struct CkOff { size_t off[CKI_MAX]; };   // start of checkpoint plane k (k >= 1)
 
 // Segment of one wave in the inverse kernels: pairs jfrom..jlast (pair j =
 // degrees 2j, 2j+1), with chain starts in pairs <= jA; idle waves are inactive.
 struct InvSeg { int jfrom, jA, jlast; bool active; };
 
 // Geometry of the inverse group (64 orders n0.., order m): pairs start at the
-// even degree lstart = max(n0, m) rounded down; wave 0 runs up to the first
-// boundary j*segi >= max(lA, lstart+2) (every chain start lies below lA), wave
-// w >= 1 runs the w-th following segment from the checkpoint planes.
-struct InvGeo { int lstart, lA, jb, nseg; };
+// even degree lstart = max(n0, m) rounded down; the wave's segment covers the
+// degrees [cs, ce): wave 0 from lstart (cs = lstart) up to a boundary beyond
+// every chain start (all lie below lA), wave w >= 1 from the checkpoint plane at
+// degree cs (a multiple of the plane spacing).
+struct InvGeo { int lstart, lA, cs, ce, nseg; };
 
 // ===========================================================================
 // FP64 inverse contraction, two orders per wavefront.  The orders m0, m0+1 of a
@@ -765,7 +766,7 @@ __device__ __forceinline__ void inv2_phase(InvLane2<EXT>& st, int jfrom, int jla
 
 template <bool EXT>
 __device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled, const InvGeo& geo, int w, int n,
-                                             int m0, int L, int Lp, int as, int segi,
+                                             int m0, int L, int Lp, int as, int ckg,
                                              const double* __restrict__ edge, const int* __restrict__ edgek,
                                              const double* __restrict__ stab, const int* __restrict__ stabk,
                                              const double2* __restrict__ cki, const int2* __restrict__ ckik,
@@ -814,13 +815,13 @@ __device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled,
         st.sprev = (lstart >= ne) ? sqrt((double)(lstart - ne) * (double)(lstart + ne)) : 0.0;
         st.q = (double)(lstart + 1 - ne) * (double)(lstart + 1 + ne);
         st.dq = 2.0 * (double)lstart + 3.0;
-        const int jlast = (geo.nseg > 1) ? ((geo.jb * segi) >> 1) - 1 : jend;
+        const int jlast = min(geo.ce >> 1, jend + 1) - 1;
         const int jA = min(jlast, (geo.lA - 1) >> 1);
         g = InvSeg{lstart >> 1, jA, jlast, true};
     } else if (w < geo.nseg) {
-        // segment from degree c = (jb+w-1)*segi (> m0+1), started from the checkpoint plane
-        const int jj = geo.jb + w - 1;
-        const int cdeg = jj * segi;
+        // segment from degree cdeg (> m0+1), started from its checkpoint plane
+        const int cdeg = geo.cs;
+        const int jj = cdeg / ckg;
         if (valid) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -842,7 +843,7 @@ __device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled,
         st.q = (double)(cdeg + 1 - ne) * (double)(cdeg + 1 + ne);
         st.dq = 2.0 * (double)cdeg + 3.0;
         if (EXT) anyscaled = __any(st.k[0] > 0 || st.k[1] > 0 || st.ks > 0);
-        const int jlast = (w < geo.nseg - 1) ? (((jj + 1) * segi) >> 1) - 1 : jend;
+        const int jlast = min(geo.ce >> 1, jend + 1) - 1;
         g = InvSeg{cdeg >> 1, (cdeg >> 1) - 1, jlast, true};
     }
     return g;
@@ -853,7 +854,7 @@ __device__ __forceinline__ void contract_inverse2_body(
     const double* __restrict__ fs0, size_t fstride, const Batch& B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
     const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,
-    const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work, int L, int Lp, int s, int segi)
+    const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work, int L, int Lp, int s, int ckg)
 {
     // LDS: the partial sums of later segments, red[slot][c][2][lane].  The 1/sqrt
     // table is read from global memory (L1-resident), so the LDS of a workgroup
@@ -866,7 +867,7 @@ __device__ __forceinline__ void contract_inverse2_body(
     const int lane = threadIdx.x & 63;
     // this wave's segment: see the work-list layout of the spin table
     const int4 d = work[(size_t)blockIdx.x * SEGI_MAX + slot];
-    const int n0 = uniform(d.x), m0 = uniform(d.y), code = uniform(d.z), jb = uniform(d.w);
+    const int n0 = uniform(d.x), m0 = uniform(d.y), code = uniform(d.z), bounds = uniform(d.w);
     const bool item = n0 >= 0;
     const int w = code & 0xff, nseg = (code >> 8) & 0xff, lead = (code >> 16) & 0xff;
     const bool bar = (code >> 24) & 1;   // the same for every slot of the workgroup
@@ -882,12 +883,13 @@ __device__ __forceinline__ void contract_inverse2_body(
         InvGeo geo;
         geo.lstart = max(n0, m0) & ~1;
         geo.lA = max(max(n0 + 64, m0 + 2), as + 1);   // every chain start of both orders lies below lA
-        geo.jb = jb;
+        geo.cs = bounds & 0xffff;
+        geo.ce = (int)((unsigned)bounds >> 16);
         geo.nseg = nseg;
         const Inv2Rows rows = inv2_rows(fs, lco, m0, as, Lp, L);
-        const unsigned touched = inv2_touch(rows, (w == 0) ? geo.lstart : (jb + w - 1) * segi, lend, lane);
+        const unsigned touched = inv2_touch(rows, geo.cs, lend, lane);
         bool anyscaled;
-        const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, segi, edge, edgek, stab, stabk,
+        const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, ckg, edge, edgek, stab, stabk,
                                          cki, ckik, ckoff);
         asm volatile("" ::"v"(touched));
         if (g.active) {
@@ -944,8 +946,8 @@ __device__ __forceinline__ void contract_inverse2_body(
         const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,         \
         const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,        \
         const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work, int L, int Lp, int s,         \
-        int segi
-#define MW_INVERSE2_PASS fs0, fstride, B, Rtg, edge, edgek, lco, stab, stabk, cki, ckik, ckoff, work, L, Lp, s, segi
+        int ckg
+#define MW_INVERSE2_PASS fs0, fstride, B, Rtg, edge, edgek, lco, stab, stabk, cki, ckik, ckoff, work, L, Lp, s, ckg
 
 template <bool RL>
 __global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(6))) void k_contract_inverse2(
@@ -1340,7 +1342,7 @@ __global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse2_mix(
     MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
     const double2* __restrict__ lco, const double* __restrict__ stab, const int* __restrict__ stabk,
     const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work,
-    int L, int Lp, int s, int segi)
+    int L, int Lp, int s, int ckg)
 {
     extern __shared__ double smem[];
     const MixMaps& maps = MB.g[blockIdx.y];
@@ -1348,7 +1350,7 @@ __global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse2_mix(
     const int lane = threadIdx.x & 63;
     // this wave's segment: see the work-list layout of the spin table
     const int4 d = work[(size_t)blockIdx.x * SEGI_MAX + slot];
-    const int n0 = uniform(d.x), m0 = uniform(d.y), code = uniform(d.z), jb = uniform(d.w);
+    const int n0 = uniform(d.x), m0 = uniform(d.y), code = uniform(d.z), bounds = uniform(d.w);
     const bool item = n0 >= 0;
     const int w = code & 0xff, nseg = (code >> 8) & 0xff, lead = (code >> 16) & 0xff;
     const bool bar = (code >> 24) & 1;   // the same for every slot of the workgroup
@@ -1372,11 +1374,12 @@ __global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse2_mix(
         InvGeo geo;
         geo.lstart = max(n0, m0) & ~1;
         geo.lA = max(max(n0 + 64, m0 + 2), as + 1);   // every chain start of both orders lies below lA
-        geo.jb = jb;
+        geo.cs = bounds & 0xffff;
+        geo.ce = (int)((unsigned)bounds >> 16);
         geo.nseg = nseg;
         InvLane2<EXT> st;
         bool anyscaled;
-        const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, segi, edge, edgek, stab, stabk,
+        const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, ckg, edge, edgek, stab, stabk,
                                          cki, ckik, ckoff);
         if (g.active)
             inv2m_segment<EXT, G>(st, acc, g, jend, geo.lstart, ne, nd, m0, inv2_rows(nullptr, lco, m0, as, Lp, L),
@@ -1483,14 +1486,14 @@ hipError_t inv_go(const Plan& p, const SpinTable& sp, int s, const double* in0, 
                   hipStream_t st)
 {
     CkOff off;
-    for (int j = 0; j < SEGI_MAX; ++j) off.off[j] = p.cki_off[j];
+    for (int j = 0; j < CKI_MAX; ++j) off.off[j] = p.cki_off[j];
     const dim3 grid(sp.nwinv, B.n), block(64 * SEGI_MAX);
     if (EXT)
         hipLaunchKernelGGL((k_contract_inverse2_ext<RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
-                           p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s, p.segi);
+                           p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s, p.ckg);
     else
         hipLaunchKernelGGL((k_contract_inverse2<RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge, p.edgek,
-                           p.lco, sp.val, sp.k, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s, p.segi);
+                           p.lco, sp.val, sp.k, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s, p.ckg);
     return hipGetLastError();
 }
 }  // namespace
@@ -1530,13 +1533,13 @@ template <bool EXT, int G>
 hipError_t inv_mix_go(const Plan& p, const SpinTable& sp, int s, const MixBatch& maps, hipStream_t st)
 {
     CkOff off;
-    for (int j = 0; j < SEGI_MAX; ++j) off.off[j] = p.cki_off[j];
+    for (int j = 0; j < CKI_MAX; ++j) off.off[j] = p.cki_off[j];
     const size_t lds = (size_t)SEGI_MAX * inv2m_slot_floats(G) * sizeof(float);
     hipError_t e = mix_attr(k_contract_inverse2_mix<EXT, G>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_contract_inverse2_mix<EXT, G>), dim3(sp.nwinv, maps.ng), dim3(64 * SEGI_MAX), lds, st,
                        maps, p.rtab, p.edge, p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s,
-                       p.segi);
+                       p.ckg);
     return hipGetLastError();
 }
 

@@ -21,6 +21,8 @@ constexpr int EXT_LIMIT = 900;
 // extra restarts cost more than the added waves hide.
 constexpr int SEG_MAX = 4;
 constexpr int SEGI_MAX = 4;
+// Checkpoint planes of the inverse: at most CKI_MAX - 1 of them.
+constexpr int CKI_MAX = 16;
 
 // Order-major index of the triangle l >= m of an L x L table (see Plan::edgem).
 __host__ __device__ inline size_t tri_m(int m, int l, int L)
@@ -65,13 +67,16 @@ struct Plan {
     // boundaries n = j*segf (j = 1..nsegf-1); ckf holds, for boundary j at
     // [(j-1)*L(L+1)/2 + tri_m(m, l)], the pair (Delta^l_{m,n-1}, Delta^l_{m,n})
     // as mantissas with exponent levels ckfk.  The inverse splits every degree
-    // recursion at l = j*segi; cki holds, for boundary j, the pair
-    // (Delta^{c-1}_{n,m}, Delta^{c}_{n,m}), c = j*segi, at cki_off[j] + m*(c+1) + n
+    // recursion at degrees c = k*ckg of a grid finer than its segments (so that
+    // each chain group picks boundaries that even out its segments, see
+    // inverse_work); cki holds, for plane k = 1 .. nck-1, the pair
+    // (Delta^{c-1}_{n,m}, Delta^{c}_{n,m}), c = k*ckg, at cki_off[k] + m*(c+1) + n
     // (n, m <= c), with levels ckik.
     int segf = 0, nsegf = 1, segi = 0, nsegi = 1;
+    int ckg = 0, nck = 1;
     double2* ckf = nullptr; int2* ckfk = nullptr;
     double2* cki = nullptr; int2* ckik = nullptr;
-    size_t cki_off[SEGI_MAX] = {0};
+    size_t cki_off[CKI_MAX] = {0};
     size_t bytes = 0;
 };
 
@@ -79,10 +84,11 @@ struct Plan {
 // (mantissa * 2^(EXT_STEP*k)), with its exponent level.  It also holds the
 // work list of the FP64 inverse contraction, whose segmentation depends on |s|:
 // SEGI_MAX wave slots per workgroup, slot i of workgroup g at [g*SEGI_MAX + i] =
-// (n0, m0, seg | nseg << 8 | lead << 16, jb) for segment seg of the chain group
-// (n0 .. n0+63, orders m0, m0+1) whose nseg segments sit in slots lead ..
-// lead+nseg-1 of the same workgroup, the first boundary of its later segments
-// being jb*segi; (-1, 0, 0, 0) marks an empty slot.
+// (n0, m0, seg | nseg << 8 | lead << 16 | barrier << 24, cs | ce << 16) for
+// segment seg, degrees [cs, ce), of the chain group (n0 .. n0+63, orders m0,
+// m0+1) whose nseg segments sit in slots lead .. lead+nseg-1 of the same
+// workgroup (cs of a later segment is a checkpoint plane); (-1, 0, barrier << 24,
+// 0) marks an empty slot.
 struct SpinTable {
     int L = 0, as = 0;
     double* val = nullptr;

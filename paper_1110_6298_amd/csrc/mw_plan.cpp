@@ -156,6 +156,17 @@ static bool segment_chains(int L, int smax, int& seg, int& nseg)
     return nseg <= smax;
 }
 
+// Grid of the inverse checkpoint planes: degrees c = k*g, 0 < c < L, k < n.
+// Up to L = 1024 the planes are four times denser than the segments (at least
+// 16 degrees apart, at most 15 planes), so that a chain group can choose
+// boundaries that split its own range evenly; above, one plane per segment
+// length (the planes hold O(L^2) values each).
+static void cki_grid(int L, int segi, int& g, int& n)
+{
+    g = (L <= 1024) ? std::max(16, segi / 4) : segi;
+    n = (L - 1) / g + 1;
+}
+
 int build_plan(int L, Plan& p, std::string& err)
 {
     p = Plan();
@@ -319,18 +330,19 @@ int build_plan(int L, Plan& p, std::string& err)
             if ((rc = upload(ck, &p.ckf, p.bytes, err))) return rc;
             if ((rc = upload(ckk, &p.ckfk, p.bytes, err))) return rc;
         }
-        if (p.nsegi > 1) {
+        cki_grid(L, p.segi, p.ckg, p.nck);
+        if (p.nck > 1) {
             size_t tot = 0;
-            for (int j = 1; j < p.nsegi; ++j) {
-                const int c = j * p.segi;
+            for (int j = 1; j < p.nck; ++j) {
+                const int c = j * p.ckg;
                 p.cki_off[j] = tot;
                 tot += (size_t)(c + 1) * (c + 1);
             }
             std::vector<double2> ck(tot, make_double2(0.0, 0.0));
             std::vector<int2> ckk(tot, make_int2(0, 0));
             std::vector<ld> r0, r1;
-            for (int j = 1; j < p.nsegi; ++j) {
-                const int c = j * p.segi;
+            for (int j = 1; j < p.nck; ++j) {
+                const int c = j * p.ckg;
                 for (int m = 0; m <= c; ++m) {
                     row_chain(E, c, m, r1);                    // Delta^c_{m,n}
                     if (m <= c - 1) row_chain(E, c - 1, m, r0);  // Delta^{c-1}_{m,n}
@@ -385,7 +397,8 @@ void free_plan(Plan& p)
 // fits at once), else longest first, which is what dynamic dispatch wants.
 // work: the group's steps summed over its segments, plus a start-up cost per
 // segment.
-struct SegItem { int a, b, nseg, jb, len, work; };
+// dw: the descriptor's last word for each segment (see the work-list layouts).
+struct SegItem { int a, b, nseg, jb, len, work; int dw[SEGI_MAX > SEG_MAX ? SEGI_MAX : SEG_MAX]; };
 
 // Workgroups per compute unit that the FP64 contraction kernels keep resident:
 // the inverse holds five (exponent-extended) or six waves per SIMD, the forward
@@ -457,7 +470,7 @@ static std::vector<int4> pack_segments(std::vector<std::vector<SegItem>>& items,
             Group& c = gs[g];
             for (int w = 0; w < t.nseg; ++w)
                 c.slot[c.used + w] =
-                    make_int4(t.a, t.b, w | (t.nseg << 8) | (c.used << 16) | (bar ? 1 << 24 : 0), t.jb);
+                    make_int4(t.a, t.b, w | (t.nseg << 8) | (c.used << 16) | (bar ? 1 << 24 : 0), t.dw[w]);
             c.used += t.nseg;
             c.work += t.work;
             if (c.used == slots)
@@ -479,21 +492,57 @@ static std::vector<int4> pack_segments(std::vector<std::vector<SegItem>>& items,
     return out;
 }
 
+// Segments of a chain over the degrees [l0, end) whose first segment must reach
+// lmin (every chain start lies below it): at most smax segments with boundaries
+// on the checkpoint planes c = k*g (0 < k < n), the longest as short as
+// possible.  bnd[0] = l0, bnd[nseg] = end; returns nseg.
+static int split_chain(int l0, int end, int lmin, int g, int n, int smax, int* bnd)
+{
+    // fewest segments no longer than T, boundaries as far out as allowed
+    auto greedy = [&](int T, int* b) {
+        int k = 0;
+        b[0] = l0;
+        while (end - b[k] > T) {
+            int c = -1;
+            for (int j = 1; j < n; ++j) {
+                const int cj = j * g;
+                if (cj > b[k] && cj <= b[k] + T && (k > 0 || cj >= lmin)) c = cj;
+            }
+            if (c < 0 || k + 1 >= smax) return -1;
+            b[++k] = c;
+        }
+        b[k + 1] = end;
+        return k + 1;
+    };
+    int lo = 1, hi = end - l0;   // hi is always feasible (one segment)
+    while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        int b[SEGI_MAX + 1];
+        if (greedy(mid, b) > 0) hi = mid;
+        else lo = mid + 1;
+    }
+    return greedy(hi, bnd);
+}
+
 // FP64 inverse contraction: group (n0, m0) starts its pairs at lstart =
 // max(n0, m0) rounded down to even; every chain start (n, m or |s|) lies below
-// lA, so its first segment runs to the first boundary j*segi >= max(lA,
-// lstart+2) and the others follow the boundaries.  Dealt to XCDs by order pair.
+// lA, so its first segment runs to a boundary >= max(lA, lstart+2); the
+// boundaries (split_chain) make the group's longest segment as short as the
+// planes allow.  Descriptor word: segment start | end << 16 (degrees).  Dealt
+// to XCDs by order pair.
 static std::vector<int4> inverse_work(const Plan& p, int as)
 {
-    const int L = p.L, Lp = p.Lp, segi = p.segi, nsegi = p.nsegi;
+    const int L = p.L, Lp = p.Lp;
     std::vector<std::vector<SegItem>> items(8);
     for (int n0 = 0; n0 < L; n0 += 64)
         for (int m0 = 0; m0 < L; m0 += 2) {
             const int lstart = std::max(n0, m0) & ~1;
             const int lA = std::max(std::max(n0 + 64, m0 + 2), as + 1);
-            const int jb = (std::max(lA, lstart + 2) + segi - 1) / segi;
-            const int nseg = (jb < nsegi) ? 1 + nsegi - jb : 1;
-            items[(m0 / 2) & 7].push_back(SegItem{n0, m0, nseg, jb, Lp - lstart, Lp - lstart + 16 * nseg});
+            int bnd[SEGI_MAX + 1];
+            const int nseg = split_chain(lstart, Lp, std::max(lA, lstart + 2), p.ckg, p.nck, SEGI_MAX, bnd);
+            SegItem t{n0, m0, nseg, 0, Lp - lstart, Lp - lstart + 16 * nseg, {}};
+            for (int w = 0; w < nseg; ++w) t.dw[w] = bnd[w] | (bnd[w + 1] << 16);
+            items[(m0 / 2) & 7].push_back(t);
         }
     return pack_segments(items, SEGI_MAX, RESIDENT_INV);
 }

@@ -51,6 +51,9 @@ static void check_inverse(int L, int as)
     p.L = L;
     p.Lp = L + (L & 1);
     CHECK(segment_chains(L, SEGI_MAX, p.segi, p.nsegi), "inverse L=%d: segmentation\n", L);
+    cki_grid(L, p.segi, p.ckg, p.nck);
+    CHECK(p.nck <= CKI_MAX && p.ckg % 2 == 0, "inverse L=%d: plane grid\n", L);
+    auto plane = [&](int c) { return c > 0 && c < L && c % p.ckg == 0 && c / p.ckg < p.nck; };
     const std::vector<int4> w = inverse_work(p, as);
     CHECK(w.size() % SEGI_MAX == 0, "inverse L=%d: size\n", L);
     std::map<std::tuple<int, int, int>, int> seen;
@@ -65,28 +68,33 @@ static void check_inverse(int L, int as)
             if (s[i].x < 0) continue;
             ++items;
             const int n0 = s[i].x, m0 = s[i].y, seg = s[i].z & 0xff, nseg = (s[i].z >> 8) & 0xff;
-            const int lead = (s[i].z >> 16) & 0xff, jb = s[i].w;
+            const int lead = (s[i].z >> 16) & 0xff;
+            const int cs = s[i].w & 0xffff, ce = (int)((unsigned)s[i].w >> 16);
             anymulti |= nseg > 1;
             CHECK(n0 % 64 == 0 && n0 < L && m0 % 2 == 0 && m0 < L, "inverse L=%d: group (%d, %d)\n", L, n0, m0);
             CHECK(lead + seg == i && lead + nseg <= SEGI_MAX, "inverse L=%d: slot layout\n", L);
             for (int k = 0; k < nseg && lead + k < SEGI_MAX; ++k) {
                 const int4 o = s[lead + k];
-                CHECK(o.x == n0 && o.y == m0 && (o.z & 0xff) == k && ((o.z >> 8) & 0xff) == nseg && o.w == jb,
+                CHECK(o.x == n0 && o.y == m0 && (o.z & 0xff) == k && ((o.z >> 8) & 0xff) == nseg,
                       "inverse L=%d: sibling segment\n", L);
+                // consecutive segments of the group meet at their common boundary
+                if (k + 1 < nseg && lead + k + 1 < SEGI_MAX)
+                    CHECK(((unsigned)o.w >> 16) == (unsigned)(s[lead + k + 1].w & 0xffff),
+                          "inverse L=%d: segments not contiguous\n", L);
             }
-            // every chain start (n, m or |s|) lies below lA; later segments restart at
-            // checkpoint planes c = j*segi with 0 < j < nsegi above all of them
+            // every chain start (n, m or |s|) lies below lA: the first segment starts at
+            // lstart and reaches past lA; later ones restart at checkpoint planes; the
+            // last one ends with the degrees
             const int lstart = std::max(n0, m0) & ~1;
             const int lA = std::max(std::max(n0 + 64, m0 + 2), as + 1);
-            if (nseg > 1) CHECK(jb * p.segi >= std::max(lA, lstart + 2), "inverse L=%d: first boundary\n", L);
-            if (seg >= 1) {
-                const int c = (jb + seg - 1) * p.segi;
-                CHECK(c < L && c >= lA && jb + seg - 1 < p.nsegi, "inverse L=%d s=%d: restart degree %d\n", L, as, c);
-            }
-            const int from = (seg == 0) ? lstart : (jb + seg - 1) * p.segi;
-            const int to = (seg == nseg - 1) ? p.Lp : (jb + seg) * p.segi;
-            CHECK(to > from, "inverse L=%d: empty segment\n", L);
-            steps[g * SEGI_MAX + i] = to - from;
+            if (seg == 0) CHECK(cs == lstart, "inverse L=%d: first segment start\n", L);
+            if (seg == 0 && nseg > 1)
+                CHECK(ce >= std::max(lA, lstart + 2) && plane(ce), "inverse L=%d s=%d: first boundary %d\n", L, as, ce);
+            if (seg >= 1) CHECK(plane(cs) && cs >= lA, "inverse L=%d s=%d: restart degree %d\n", L, as, cs);
+            if (seg == nseg - 1) CHECK(ce == p.Lp, "inverse L=%d: last segment end\n", L);
+            CHECK(ce > cs && cs % 2 == 0 && ce % 2 == 0, "inverse L=%d: segment [%d, %d)\n", L, cs, ce);
+            CHECK(nseg >= 1 && nseg <= SEGI_MAX, "inverse L=%d: segment count\n", L);
+            steps[g * SEGI_MAX + i] = ce - cs;
             CHECK(seen[std::make_tuple(n0, m0, seg)]++ == 0, "inverse L=%d: duplicate segment\n", L);
         }
         CHECK(!items || bar == anymulti, "inverse L=%d: barrier flag of workgroup %zu\n", L, g);
