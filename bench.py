@@ -23,8 +23,8 @@ PEAK_FP64_VALU = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 # read for a plain copy of known size (profiles/traffic_roundtrip_L512_s2.md).
 # Valid only while the kernel and plan sources are unchanged: keyed by their SHA-256.
 TRAFFIC = {
-    ("contract_inverse", 512, 2): {"bytes": 22940079, "source_sha256": "04924af9ce88faa93c0a2c75aef53bd3c35474c20de6f4a53b25e8999b5ff12b"},
-    ("contract_forward", 512, 2): {"bytes": 27531236, "source_sha256": "04924af9ce88faa93c0a2c75aef53bd3c35474c20de6f4a53b25e8999b5ff12b"},
+    ("contract_inverse", 512, 2): {"bytes": 28221422, "source_sha256": "0a815464f9c6e08b614d1303e6fb78bddaffd98726b796c0d258a41eb27eb0a4"},
+    ("contract_forward", 512, 2): {"bytes": 27530922, "source_sha256": "0a815464f9c6e08b614d1303e6fb78bddaffd98726b796c0d258a41eb27eb0a4"},
 }
 KERNEL_SOURCES = ("paper_1110_6298_amd/csrc/mw_contract.hip", "paper_1110_6298_amd/csrc/mw_plan.cpp")
 
