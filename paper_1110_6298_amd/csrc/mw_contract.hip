@@ -283,21 +283,20 @@ __device__ __forceinline__ void ck_level(double& v0, double& v1, int k0, int k1,
 // recursions, with lane starts in pairs >= kA; idle waves are inactive.
 struct FwdSeg { int ktop, kA, klo; bool active; };
 
-// Chain state of wave w for the group (64 degrees l0.., MT orders mb..): the
-// top segment (w == jtop, jtop = nmax/segf) starts every lane at its own n = l
-// from the edge value; a lower segment w < jtop runs n from (w+1)*segf - 1 down
-// to w*segf, started from the checkpoint pair at n_c = (w+1)*segf (every lane
-// has l >= n_c there).
+// Chain state of wave w (rows [lo, hi)) for the group (64 degrees l0.., MT
+// orders mb..): the top segment (w == nseg-1, hi = nmax+1, lo <= l0) starts
+// every lane at its own n = l from the edge value; a lower segment runs n from
+// hi-1 down to lo, started from the checkpoint pair of the plane at n_c = hi, a
+// multiple of ckfg (every lane has l >= n_c there).
 template <int MT, bool EXT>
-__device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscaled, int w, int l0, int mb, int l,
-                                            int L, int as, int segf, const double* __restrict__ edge,
-                                            const int* __restrict__ edgek, const double2* __restrict__ ckf,
-                                            const int2* __restrict__ ckfk)
+__device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscaled, int w, int nseg, int lo, int hi,
+                                            int l0, int mb, int l, int L, int as, int ckfg,
+                                            const double* __restrict__ edge, const int* __restrict__ edgek,
+                                            const double2* __restrict__ ckf, const int2* __restrict__ ckfk)
 {
     const bool valid = l < L;
     const int le = valid ? l : L - 1;
     const int nmax = min(l0 + 63, L - 1);
-    const int jtop = nmax / segf;
     const size_t T = (size_t)L * (L + 1) / 2;
 #pragma unroll
     for (int c = 0; c < MT; ++c) {
@@ -308,7 +307,7 @@ __device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscale
     st.q = 0.0; st.dq = 0.0;
     anyscaled = EXT;
     FwdSeg g{0, 0, 0, false};
-    if (w == jtop) {
+    if (w == nseg - 1) {
 #pragma unroll
         for (int c = 0; c < MT; ++c) {
             const int m = mb + c;
@@ -323,10 +322,10 @@ __device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscale
         const int ktop = nmax >> 1, ntop = 2 * ktop + 1;   // n = L (odd L) is a zero pad step
         st.q = (double)(le + ntop) * (double)(le - ntop + 1);
         st.dq = 2.0 * (double)(ntop - 1);
-        g = FwdSeg{ktop, l0 >> 1, (jtop * segf) >> 1, true};
-    } else if (w < jtop) {
-        const int nc = (w + 1) * segf;
-        const size_t base = (size_t)w * T;
+        g = FwdSeg{ktop, l0 >> 1, lo >> 1, true};
+    } else if (w < nseg - 1) {
+        const int nc = hi;
+        const size_t base = (size_t)(nc / ckfg - 1) * T;
 #pragma unroll
         for (int c = 0; c < MT; ++c) {
             const int m = mb + c;
@@ -355,7 +354,7 @@ __device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscale
             for (int c = 0; c < MT; ++c) sc |= st.k[c] > 0;
             anyscaled = __any(sc);
         }
-        g = FwdSeg{ntop >> 1, (ntop >> 1) + 1, (w * segf) >> 1, true};
+        g = FwdSeg{ntop >> 1, (ntop >> 1) + 1, lo >> 1, true};
     }
     return g;
 }
@@ -368,7 +367,7 @@ __device__ __forceinline__ void contract_forward_body(
     const double* __restrict__ Hp0, size_t hstride, const Batch& B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,
     const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int4* __restrict__ work, int L, int Lp,
-    int s, int segf)
+    int s, int ckfg)
 {
     // LDS: the partial sums of upper segments, red[slot][c][k][lane].  The
     // 1/sqrt table is read from global memory (L1-resident), so the LDS of a
@@ -381,9 +380,10 @@ __device__ __forceinline__ void contract_forward_body(
     const int lane = threadIdx.x & 63;
     // this wave's segment: see the work-list layout of the plan
     const int4 d = work[(size_t)blockIdx.x * SEG_MAX + slot];
-    const int l0 = uniform(d.x), mb = uniform(d.y), code = uniform(d.z);
+    const int l0 = uniform(d.x), mb = uniform(d.y), code = uniform(d.z), rows = uniform(d.w);
     const bool item = l0 >= 0;
     const int w = code & 0xff, nseg = (code >> 8) & 0xff, lead = (code >> 16) & 0xff;
+    const int lo = rows & 0xffff, hi = (int)((unsigned)rows >> 16);   // this segment's rows [lo, hi)
     const bool bar = (code >> 24) & 1;   // the same for every slot of the workgroup
     const int l = l0 + lane;
     const bool valid = item && l < L;
@@ -393,7 +393,8 @@ __device__ __forceinline__ void contract_forward_body(
     FwdLane<MT, EXT> st;
     if (item) {
         bool anyscaled;
-        const FwdSeg g = fwd_setup<MT, EXT>(st, anyscaled, w, l0, mb, l, L, as, segf, edge, edgek, ckf, ckfk);
+        const FwdSeg g =
+            fwd_setup<MT, EXT>(st, anyscaled, w, nseg, lo, hi, l0, mb, l, L, as, ckfg, edge, edgek, ckf, ckfk);
         if (g.active) fwd_segment<MT, EXT, RL>(st, g.ktop, g.kA, g.klo, l, le, mb, as, Hp, Rt, Lp, L, anyscaled);
     }
     if (bar) {
@@ -466,8 +467,8 @@ __device__ __forceinline__ void contract_forward_body(
     const double* __restrict__ Hp0, size_t hstride, Batch B, const double* __restrict__ Rtg,                    \
         const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,           \
         const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int4* __restrict__ work, int L,    \
-        int Lp, int s, int segf
-#define MW_FORWARD_PASS Hp0, hstride, B, Rtg, edge, edgek, cl, ckf, ckfk, work, L, Lp, s, segf
+        int Lp, int s, int ckfg
+#define MW_FORWARD_PASS Hp0, hstride, B, Rtg, edge, edgek, cl, ckf, ckfk, work, L, Lp, s, ckfg
 
 template <int MT, bool RL>
 __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(4))) void k_contract_forward(
@@ -1118,7 +1119,7 @@ template <bool EXT, int G>
 __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
     MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
     const double* __restrict__ cl, const double2* __restrict__ ckf, const int2* __restrict__ ckfk,
-    const int4* __restrict__ work, int L, int s, int segf)
+    const int4* __restrict__ work, int L, int s, int ckfg)
 {
     extern __shared__ double smem[];
     const MixMaps& maps = MB.g[blockIdx.y];
@@ -1126,9 +1127,10 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
     const int lane = threadIdx.x & 63;
     // this wave's segment: see the work-list layout of the plan
     const int4 d = work[(size_t)blockIdx.x * SEG_MAX + slot];
-    const int l0 = uniform(d.x), mb = uniform(d.y), code = uniform(d.z);
+    const int l0 = uniform(d.x), mb = uniform(d.y), code = uniform(d.z), rows = uniform(d.w);
     const bool item = l0 >= 0;
     const int w = code & 0xff, nseg = (code >> 8) & 0xff, lead = (code >> 16) & 0xff;
+    const int lo = rows & 0xffff, hi = (int)((unsigned)rows >> 16);   // this segment's rows [lo, hi)
     const bool bar = (code >> 24) & 1;   // the same for every slot of the workgroup
     bool any = false;                    // does any map of the group have this (l0, mb) block?
     for (int b = 0; b < maps.n; ++b) any |= (l0 < maps.L[b] && mb < maps.L[b]);
@@ -1145,7 +1147,8 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
     if (item && any) {
         FwdLane<2, EXT> st;
         bool anyscaled;
-        const FwdSeg g = fwd_setup<2, EXT>(st, anyscaled, w, l0, mb, l, L, as, segf, edge, edgek, ckf, ckfk);
+        const FwdSeg g =
+            fwd_setup<2, EXT>(st, anyscaled, w, nseg, lo, hi, l0, mb, l, L, as, ckfg, edge, edgek, ckf, ckfk);
         if (g.active) fwd_mix_segment<EXT, G>(st, acc, g, l, le, mb, as, Rt, region, maps, lane, anyscaled);
     }
 
@@ -1450,10 +1453,10 @@ hipError_t fwd_go(const Plan& p, int s, const double* in0, size_t stride, const 
     const dim3 grid(p.nworkf4, B.n), block(64 * SEG_MAX);
     if (EXT)
         hipLaunchKernelGGL((k_contract_forward_ext<MT_FWD, RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
-                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, p.Lp, s, p.segf);
+                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, p.Lp, s, p.ckfg);
     else
         hipLaunchKernelGGL((k_contract_forward<MT_FWD, RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
-                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, p.Lp, s, p.segf);
+                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, p.Lp, s, p.ckfg);
     return hipGetLastError();
 }
 }  // namespace
@@ -1525,7 +1528,7 @@ hipError_t fwd_mix_go(const Plan& p, int s, const MixBatch& maps, hipStream_t st
     hipError_t e = mix_attr(k_contract_forward_mix<EXT, G>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_contract_forward_mix<EXT, G>), dim3(p.nworkf4, maps.ng), dim3(64 * SEG_MAX), lds, st,
-                       maps, p.rtab, p.edge, p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, s, p.segf);
+                       maps, p.rtab, p.edge, p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, s, p.ckfg);
     return hipGetLastError();
 }
 

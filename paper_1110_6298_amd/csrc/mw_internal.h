@@ -57,23 +57,25 @@ struct Plan {
     double2* thwc = nullptr;    // exp(-i m' pi/N1) chirp_k at slot k = m' mod N1
     double thsc = 0.0;          // 1/(2 pi N1)
     // Work list of the forward contractions (FP64 and mixed), dealt over the 8
-    // XCDs by order pair and longest first: SEG_MAX wave slots per workgroup, slot i of workgroup g at
-    // [g*SEG_MAX + i] = (l0, mb, seg | nseg << 8 | lead << 16 | barrier << 24, 0)
-    // for segment seg of the chain group (degrees l0 .., orders mb, mb+1) whose
-    // nseg segments sit in slots lead .. lead+nseg-1 of the same workgroup;
-    // (-1, 0, barrier << 24, 0) marks an empty slot
+    // XCDs: SEG_MAX wave slots per workgroup, slot i of workgroup g at
+    // [g*SEG_MAX + i] = (l0, mb, seg | nseg << 8 | lead << 16 | barrier << 24,
+    // lo | hi << 16) for segment seg, rows [lo, hi), of the chain group (degrees
+    // l0 .., orders mb, mb+1) whose nseg segments sit in slots lead ..
+    // lead+nseg-1 of the same workgroup; (-1, 0, barrier << 24, 0) marks an empty
+    // slot
     int4* workf4 = nullptr; int nworkf4 = 0;   // workgroups
-    // Chain segmentation.  The forward splits every row recursion at the global
-    // boundaries n = j*segf (j = 1..nsegf-1); ckf holds, for boundary j at
-    // [(j-1)*L(L+1)/2 + tri_m(m, l)], the pair (Delta^l_{m,n-1}, Delta^l_{m,n})
-    // as mantissas with exponent levels ckfk.  The inverse splits every degree
-    // recursion at degrees c = k*ckg of a grid finer than its segments (so that
-    // each chain group picks boundaries that even out its segments, see
-    // inverse_work); cki holds, for plane k = 1 .. nck-1, the pair
-    // (Delta^{c-1}_{n,m}, Delta^{c}_{n,m}), c = k*ckg, at cki_off[k] + m*(c+1) + n
-    // (n, m <= c), with levels ckik.
+    // Chain segmentation: each chain group splits its chain into at most
+    // SEG_MAX / SEGI_MAX segments, choosing the boundaries among checkpoint
+    // planes on a grid finer than the segments (forward_work, inverse_work).
+    // The forward's planes lie at rows n = j*ckfg (j = 1..nckf-1); ckf holds,
+    // for plane j at [(j-1)*L(L+1)/2 + tri_m(m, l)], the pair
+    // (Delta^l_{m,n-1}, Delta^l_{m,n}) as mantissas with exponent levels ckfk.
+    // The inverse's planes lie at degrees c = k*ckg (k = 1..nck-1); cki holds,
+    // for plane k, the pair (Delta^{c-1}_{n,m}, Delta^{c}_{n,m}) at
+    // cki_off[k] + m*(c+1) + n (n, m <= c), with levels ckik.  segf, segi: the
+    // segment lengths the grids derive from.
     int segf = 0, nsegf = 1, segi = 0, nsegi = 1;
-    int ckg = 0, nck = 1;
+    int ckg = 0, nck = 1, ckfg = 0, nckf = 1;
     double2* ckf = nullptr; int2* ckfk = nullptr;
     double2* cki = nullptr; int2* ckik = nullptr;
     size_t cki_off[CKI_MAX] = {0};

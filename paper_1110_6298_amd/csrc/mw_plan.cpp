@@ -156,14 +156,14 @@ static bool segment_chains(int L, int smax, int& seg, int& nseg)
     return nseg <= smax;
 }
 
-// Grid of the inverse checkpoint planes: degrees c = k*g, 0 < c < L, k < n.
-// Up to L = 1024 the planes are four times denser than the segments (at least
-// 16 degrees apart, at most 15 planes), so that a chain group can choose
+// Grid of the checkpoint planes for segments of length seg: c = k*g, 0 < c < L,
+// k < n.  Up to L = 1024 the planes are four times denser than the segments
+// (at least 16 apart, at most 15 planes), so that a chain group can choose
 // boundaries that split its own range evenly; above, one plane per segment
 // length (the planes hold O(L^2) values each).
-static void cki_grid(int L, int segi, int& g, int& n)
+static void ck_grid(int L, int seg, int& g, int& n)
 {
-    g = (L <= 1024) ? std::max(16, segi / 4) : segi;
+    g = (L <= 1024) ? std::max(16, seg / 4) : seg;
     n = (L - 1) / g + 1;
 }
 
@@ -307,12 +307,13 @@ int build_plan(int L, Plan& p, std::string& err)
             return -3;
         }
         const size_t T = (size_t)L * (L + 1) / 2;
-        if (p.nsegf > 1) {
-            std::vector<double2> ck((size_t)(p.nsegf - 1) * T, make_double2(0.0, 0.0));
-            std::vector<int2> ckk((size_t)(p.nsegf - 1) * T, make_int2(0, 0));
+        ck_grid(L, p.segf, p.ckfg, p.nckf);
+        if (p.nckf > 1) {
+            std::vector<double2> ck((size_t)(p.nckf - 1) * T, make_double2(0.0, 0.0));
+            std::vector<int2> ckk((size_t)(p.nckf - 1) * T, make_int2(0, 0));
             std::vector<ld> c0, c1;
-            for (int j = 1; j < p.nsegf; ++j) {
-                const int nc = j * p.segf;
+            for (int j = 1; j < p.nckf; ++j) {
+                const int nc = j * p.ckfg;
                 for (int m = 0; m < L; ++m) {
                     degree_chain(E, L, m, nc - 1, c0);
                     degree_chain(E, L, m, nc, c1);
@@ -330,7 +331,7 @@ int build_plan(int L, Plan& p, std::string& err)
             if ((rc = upload(ck, &p.ckf, p.bytes, err))) return rc;
             if ((rc = upload(ckk, &p.ckfk, p.bytes, err))) return rc;
         }
-        cki_grid(L, p.segi, p.ckg, p.nck);
+        ck_grid(L, p.segi, p.ckg, p.nck);
         if (p.nck > 1) {
             size_t tot = 0;
             for (int j = 1; j < p.nck; ++j) {
@@ -492,11 +493,11 @@ static std::vector<int4> pack_segments(std::vector<std::vector<SegItem>>& items,
     return out;
 }
 
-// Segments of a chain over the degrees [l0, end) whose first segment must reach
-// lmin (every chain start lies below it): at most smax segments with boundaries
-// on the checkpoint planes c = k*g (0 < k < n), the longest as short as
+// Segments of a chain over the steps [l0, end) whose first segment must reach
+// lmin (every chain start lies before it): at most smax segments with
+// boundaries among the ascending candidates cand, the longest as short as
 // possible.  bnd[0] = l0, bnd[nseg] = end; returns nseg.
-static int split_chain(int l0, int end, int lmin, int g, int n, int smax, int* bnd)
+static int split_chain(int l0, int end, int lmin, const std::vector<int>& cand, int smax, int* bnd)
 {
     // fewest segments no longer than T, boundaries as far out as allowed
     auto greedy = [&](int T, int* b) {
@@ -504,10 +505,8 @@ static int split_chain(int l0, int end, int lmin, int g, int n, int smax, int* b
         b[0] = l0;
         while (end - b[k] > T) {
             int c = -1;
-            for (int j = 1; j < n; ++j) {
-                const int cj = j * g;
+            for (const int cj : cand)
                 if (cj > b[k] && cj <= b[k] + T && (k > 0 || cj >= lmin)) c = cj;
-            }
             if (c < 0 || k + 1 >= smax) return -1;
             b[++k] = c;
         }
@@ -517,7 +516,7 @@ static int split_chain(int l0, int end, int lmin, int g, int n, int smax, int* b
     int lo = 1, hi = end - l0;   // hi is always feasible (one segment)
     while (lo < hi) {
         const int mid = (lo + hi) / 2;
-        int b[SEGI_MAX + 1];
+        int b[(SEGI_MAX > SEG_MAX ? SEGI_MAX : SEG_MAX) + 1];
         if (greedy(mid, b) > 0) hi = mid;
         else lo = mid + 1;
     }
@@ -533,13 +532,15 @@ static int split_chain(int l0, int end, int lmin, int g, int n, int smax, int* b
 static std::vector<int4> inverse_work(const Plan& p, int as)
 {
     const int L = p.L, Lp = p.Lp;
+    std::vector<int> cand;   // the checkpoint planes
+    for (int k = 1; k < p.nck; ++k) cand.push_back(k * p.ckg);
     std::vector<std::vector<SegItem>> items(8);
     for (int n0 = 0; n0 < L; n0 += 64)
         for (int m0 = 0; m0 < L; m0 += 2) {
             const int lstart = std::max(n0, m0) & ~1;
             const int lA = std::max(std::max(n0 + 64, m0 + 2), as + 1);
             int bnd[SEGI_MAX + 1];
-            const int nseg = split_chain(lstart, Lp, std::max(lA, lstart + 2), p.ckg, p.nck, SEGI_MAX, bnd);
+            const int nseg = split_chain(lstart, Lp, std::max(lA, lstart + 2), cand, SEGI_MAX, bnd);
             SegItem t{n0, m0, nseg, 0, Lp - lstart, Lp - lstart + 16 * nseg, {}};
             for (int w = 0; w < nseg; ++w) t.dw[w] = bnd[w] | (bnd[w + 1] << 16);
             items[(m0 / 2) & 7].push_back(t);
@@ -548,18 +549,28 @@ static std::vector<int4> inverse_work(const Plan& p, int as)
 }
 
 // FP64 forward contraction: group (l0, mb) runs the row recursions from nmax =
-// min(l0+63, L-1) down to 0, in segments w = 0 .. jtop (jtop = nmax/segf) of
-// n in [w*segf, (w+1)*segf); the top one also starts the lanes.  Dealt to XCDs
-// by chunks of eight orders (for L >= 256), so that the waves writing the f_lm
-// of one line (orders m..m+7 at one degree) meet in one L2.
+// min(l0+63, L-1) down to 0 in at most SEG_MAX segments: segment w covers the
+// rows [lo, hi) (w = 0 the lowest); the top one (w = nseg-1) runs from nmax and
+// starts the lanes, so it reaches down to l0 at least, and each lower one
+// starts from the checkpoint plane at row hi.  The boundaries make the group's
+// longest segment as short as the planes allow (split_chain on the rows counted
+// from the top).  Descriptor word: lo | hi << 16.  Dealt to XCDs by chunks of
+// eight orders (for L >= 256), so that the waves writing the f_lm of one line
+// (orders m..m+7 at one degree) meet in one L2.
 static std::vector<int4> forward_work(const Plan& p)
 {
-    const int L = p.L, segf = p.segf;
+    const int L = p.L;
     std::vector<std::vector<SegItem>> items(8);
     for (int l0 = 0; l0 < L; l0 += 64) {
-        const int nmax = std::min(l0 + 63, L - 1);
-        const int jtop = nmax / segf;
-        const int len = std::max(nmax - jtop * segf + 1, jtop > 0 ? segf : 0);
+        const int nmax = std::min(l0 + 63, L - 1), R = nmax + 1;
+        // rows counted from the top: r = R - n; planes at rows k*ckfg <= nmax
+        std::vector<int> cand;
+        for (int k = p.nckf - 1; k >= 1; --k)
+            if (k * p.ckfg <= nmax) cand.push_back(R - k * p.ckfg);
+        int bnd[SEG_MAX + 1];
+        const int nseg = split_chain(0, R, R - l0, cand, SEG_MAX, bnd);
+        int len = 0;
+        for (int k = 0; k < nseg; ++k) len = std::max(len, bnd[k + 1] - bnd[k]);
         for (int mb = 0; mb <= nmax; mb += MT_FWD) {
             // orders in chunks of 8 (one 128-byte line of f_lm per degree), dealt
             // to the XCDs back and forth so every XCD gets low and high orders;
@@ -567,7 +578,12 @@ static std::vector<int4> forward_work(const Plan& p)
             // unequal shares, and order pairs are dealt round-robin instead
             const int chunk = mb >> 3, pos = chunk & 7;
             const int x = (L < 256) ? (mb / MT_FWD) & 7 : (((chunk >> 3) & 1) ? 7 - pos : pos);
-            items[x].push_back(SegItem{l0, mb, jtop + 1, 0, len, nmax + 1 + 16 * (jtop + 1)});
+            SegItem t{l0, mb, nseg, 0, len, nmax + 1 + 16 * nseg, {}};
+            for (int w = 0; w < nseg; ++w) {   // w = 0 lowest: top-down segment k = nseg-1-w
+                const int k = nseg - 1 - w;
+                t.dw[w] = (R - bnd[k + 1]) | ((R - bnd[k]) << 16);
+            }
+            items[x].push_back(t);
         }
     }
     return pack_segments(items, SEG_MAX, RESIDENT_FWD);

@@ -51,7 +51,7 @@ static void check_inverse(int L, int as)
     p.L = L;
     p.Lp = L + (L & 1);
     CHECK(segment_chains(L, SEGI_MAX, p.segi, p.nsegi), "inverse L=%d: segmentation\n", L);
-    cki_grid(L, p.segi, p.ckg, p.nck);
+    ck_grid(L, p.segi, p.ckg, p.nck);
     CHECK(p.nck <= CKI_MAX && p.ckg % 2 == 0, "inverse L=%d: plane grid\n", L);
     auto plane = [&](int c) { return c > 0 && c < L && c % p.ckg == 0 && c / p.ckg < p.nck; };
     const std::vector<int4> w = inverse_work(p, as);
@@ -118,6 +118,9 @@ static void check_forward(int L)
     p.L = L;
     p.Lp = L + (L & 1);
     CHECK(segment_chains(L, SEG_MAX, p.segf, p.nsegf), "forward L=%d: segmentation\n", L);
+    ck_grid(L, p.segf, p.ckfg, p.nckf);
+    CHECK(p.nckf <= CKI_MAX && p.ckfg % 2 == 0, "forward L=%d: plane grid\n", L);
+    auto plane = [&](int c) { return c > 0 && c < L && c % p.ckfg == 0 && c / p.ckfg < p.nckf; };
     const std::vector<int4> w = forward_work(p);
     CHECK(w.size() % SEG_MAX == 0, "forward L=%d: size\n", L);
     std::map<std::tuple<int, int, int>, int> seen;
@@ -132,26 +135,40 @@ static void check_forward(int L)
             ++items;
             const int l0 = s[i].x, mb = s[i].y, seg = s[i].z & 0xff, nseg = (s[i].z >> 8) & 0xff;
             const int lead = (s[i].z >> 16) & 0xff;
+            const int lo = s[i].w & 0xffff, hi = (int)((unsigned)s[i].w >> 16);
             const int nmax = std::min(l0 + 63, L - 1);
             anymulti |= nseg > 1;
             CHECK(l0 % 64 == 0 && mb % MT_FWD == 0 && mb <= nmax, "forward L=%d: group (%d, %d)\n", L, l0, mb);
-            CHECK(nseg == nmax / p.segf + 1 && seg < nseg, "forward L=%d: segment count\n", L);
+            CHECK(nseg >= 1 && nseg <= SEG_MAX && seg < nseg, "forward L=%d: segment count\n", L);
             CHECK(lead + seg == i && lead + nseg <= SEG_MAX, "forward L=%d: slot layout\n", L);
             for (int k = 0; k < nseg && lead + k < SEG_MAX; ++k) {
                 const int4 o = s[lead + k];
                 CHECK(o.x == l0 && o.y == mb && (o.z & 0xff) == k, "forward L=%d: sibling segment\n", L);
+                // segment k ends where segment k+1 starts
+                if (k + 1 < nseg && lead + k + 1 < SEG_MAX)
+                    CHECK(((unsigned)o.w >> 16) == (unsigned)(s[lead + k + 1].w & 0xffff),
+                          "forward L=%d: segments not contiguous\n", L);
             }
-            steps[g * SEG_MAX + i] = std::min((seg + 1) * p.segf, nmax + 1) - seg * p.segf;
+            // the lowest segment ends at row 0, the top one starts at nmax and reaches
+            // down past every lane start (l0); lower ones restart at checkpoint planes
+            if (seg == 0) CHECK(lo == 0, "forward L=%d: lowest segment\n", L);
+            if (seg == nseg - 1) CHECK(hi == nmax + 1 && lo <= l0, "forward L=%d: top segment [%d, %d)\n", L, lo, hi);
+            else CHECK(plane(hi) && hi <= l0, "forward L=%d: restart row %d\n", L, hi);
+            CHECK(hi > lo && lo % 2 == 0, "forward L=%d: segment [%d, %d)\n", L, lo, hi);
+            steps[g * SEG_MAX + i] = hi - lo;
             CHECK(seen[std::make_tuple(l0, mb, seg)]++ == 0, "forward L=%d: duplicate segment\n", L);
         }
         CHECK(!items || bar == anymulti, "forward L=%d: barrier flag of workgroup %zu\n", L, g);
     }
     for (int l0 = 0; l0 < L; l0 += 64) {
         const int nmax = std::min(l0 + 63, L - 1);
-        for (int mb = 0; mb <= nmax; mb += MT_FWD)
-            for (int k = 0; k <= nmax / p.segf; ++k)
-                CHECK(seen.count(std::make_tuple(l0, mb, k)) == 1, "forward L=%d: segment (%d, %d, %d) missing\n", L,
-                      l0, mb, k);
+        for (int mb = 0; mb <= nmax; mb += MT_FWD) {
+            int nseg = 0;
+            while (nseg < SEG_MAX && seen.count(std::make_tuple(l0, mb, nseg))) ++nseg;
+            CHECK(nseg >= 1, "forward L=%d: group (%d, %d) missing\n", L, l0, mb);
+            for (int k = nseg; k < SEG_MAX; ++k)
+                CHECK(seen.count(std::make_tuple(l0, mb, k)) == 0, "forward L=%d: segment gap\n", L);
+        }
     }
     check_balance("forward", L, w, SEG_MAX, RESIDENT_FWD, steps);
 }
