@@ -388,26 +388,30 @@ void free_plan(Plan& p)
 // Packing of the segments of chain groups into workgroups of `slots` wave slots
 // (layout of the resulting work list in mw_internal.h).  items[x] are the
 // groups dealt to XCD x, (a, b) = (first lane index, first order), with their
-// segment count, first-boundary index jb and the length that orders them.
+// segment count, the length that orders them (the longest segment for the
+// forward, the whole chain for the inverse) and each segment's descriptor word.
 // Groups of one segment go four to a workgroup with no barrier (every wave
 // exits when done); groups of several segments are placed first-fit into the
 // last few open workgroups, so that waves meeting at the reduction barrier
 // have similar lengths.  Workgroups are dealt round-robin over the 8 XCDs
 // (workgroup k*8 + x is the k-th of XCD x); per XCD they are ordered as in
 // balance_cus when at most `resident` per compute unit are needed (the launch
-// fits at once), else longest first, which is what dynamic dispatch wants.
+// fits at once, or nearly), else longest first, which is what dynamic dispatch
+// wants.
 // work: the group's steps summed over its segments, plus a start-up cost per
 // segment.
 // dw: the descriptor's last word for each segment (see the work-list layouts).
-struct SegItem { int a, b, nseg, jb, len, work; int dw[SEGI_MAX > SEG_MAX ? SEGI_MAX : SEG_MAX]; };
+struct SegItem { int a, b, nseg, len, work; int dw[SEGI_MAX > SEG_MAX ? SEGI_MAX : SEG_MAX]; };
 
-// Workgroups per compute unit that the FP64 contraction kernels keep resident:
-// the inverse holds five (exponent-extended) or six waves per SIMD, the forward
-// four.  The mixed kernels read the same lists with as few as three or four;
-// where that is fewer than a list needs, their last workgroups start as others
-// finish.
-constexpr int RESIDENT_INV = 5;
-constexpr int RESIDENT_FWD = 4;
+// Workgroups per compute unit up to which a work list is laid out for the
+// round-robin placement (balance_cus) rather than longest first.  The FP64
+// inverse holds five (exponent-extended) or six waves per SIMD, the forward
+// four, the mixed kernels three or four; lists a little longer than what fits at
+// once still gain from the balanced layout (their last workgroups start as
+// others finish), measured at L = 512 with 203 inverse and 137 forward
+// workgroups per XCD.
+constexpr int RESIDENT_INV = 7;
+constexpr int RESIDENT_FWD = 5;
 
 // Order of the workgroups of one XCD when all of them are resident at once:
 // the dispatcher then fills the 32 compute units of an XCD round-robin, so its
@@ -541,7 +545,7 @@ static std::vector<int4> inverse_work(const Plan& p, int as)
             const int lA = std::max(std::max(n0 + 64, m0 + 2), as + 1);
             int bnd[SEGI_MAX + 1];
             const int nseg = split_chain(lstart, Lp, std::max(lA, lstart + 2), cand, SEGI_MAX, bnd);
-            SegItem t{n0, m0, nseg, 0, Lp - lstart, Lp - lstart + 16 * nseg, {}};
+            SegItem t{n0, m0, nseg, Lp - lstart, Lp - lstart + 16 * nseg, {}};
             for (int w = 0; w < nseg; ++w) t.dw[w] = bnd[w] | (bnd[w + 1] << 16);
             items[(m0 / 2) & 7].push_back(t);
         }
@@ -578,7 +582,7 @@ static std::vector<int4> forward_work(const Plan& p)
             // unequal shares, and order pairs are dealt round-robin instead
             const int chunk = mb >> 3, pos = chunk & 7;
             const int x = (L < 256) ? (mb / MT_FWD) & 7 : (((chunk >> 3) & 1) ? 7 - pos : pos);
-            SegItem t{l0, mb, nseg, 0, len, nmax + 1 + 16 * nseg, {}};
+            SegItem t{l0, mb, nseg, len, nmax + 1 + 16 * nseg, {}};
             for (int w = 0; w < nseg; ++w) {   // w = 0 lowest: top-down segment k = nseg-1-w
                 const int k = nseg - 1 - w;
                 t.dw[w] = (R - bnd[k + 1]) | ((R - bnd[k]) << 16);
