@@ -23,8 +23,8 @@ PEAK_FP64_VALU = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 # read for a plain copy of known size (profiles/traffic_roundtrip_L512_s2.md).
 # Valid only while the kernel and plan sources are unchanged: keyed by their SHA-256.
 TRAFFIC = {
-    ("contract_inverse", 512, 2): {"bytes": 28211052, "source_sha256": "b540d8325773d1fc8cd7b7d9ea47b4d333382156c79d7401595edb042bb1c698"},
-    ("contract_forward", 512, 2): {"bytes": 29425268, "source_sha256": "b540d8325773d1fc8cd7b7d9ea47b4d333382156c79d7401595edb042bb1c698"},
+    ("contract_inverse", 512, 2): {"bytes": 28219212, "source_sha256": "b66d213ad79ec9ec557ce76a28e74243a34466ea7053f3411da95faed3062203"},
+    ("contract_forward", 512, 2): {"bytes": 29423502, "source_sha256": "b66d213ad79ec9ec557ce76a28e74243a34466ea7053f3411da95faed3062203"},
 }
 KERNEL_SOURCES = ("paper_1110_6298_amd/csrc/mw_contract.hip", "paper_1110_6298_amd/csrc/mw_plan.cpp")
 

@@ -950,15 +950,18 @@ __device__ __forceinline__ void contract_inverse2_body(
         int ckg
 #define MW_INVERSE2_PASS fs0, fstride, B, Rtg, edge, edgek, lco, stab, stabk, cki, ckik, ckoff, work, L, Lp, s, ckg
 
+// Register budgets: a real map keeps no -m sums, which leaves room for one more
+// wave per SIMD (seven plain, six exponent-extended) without spills in the loops.
 template <bool RL>
-__global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(6))) void k_contract_inverse2(
+__global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(RL ? 7 : 6))) void k_contract_inverse2(
     MW_INVERSE2_ARGS)
 {
     contract_inverse2_body<false, RL>(MW_INVERSE2_PASS);
 }
 
 template <bool RL>
-__global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse2_ext(MW_INVERSE2_ARGS)
+__global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(RL ? 6 : 4))) void k_contract_inverse2_ext(
+    MW_INVERSE2_ARGS)
 {
     contract_inverse2_body<true, RL>(MW_INVERSE2_PASS);
 }

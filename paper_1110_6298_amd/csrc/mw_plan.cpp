@@ -405,11 +405,11 @@ struct SegItem { int a, b, nseg, len, work; int dw[SEGI_MAX > SEG_MAX ? SEGI_MAX
 
 // Workgroups per compute unit up to which a work list is laid out for the
 // round-robin placement (balance_cus) rather than longest first.  The FP64
-// inverse holds five (exponent-extended) or six waves per SIMD, the forward
-// four, the mixed kernels three or four; lists a little longer than what fits at
-// once still gain from the balanced layout (their last workgroups start as
-// others finish), measured at L = 512 with 203 inverse and 137 forward
-// workgroups per XCD.
+// inverse holds four to seven waves per SIMD (complex or real map, plain or
+// exponent-extended), the forward four or five, the mixed kernels two to four;
+// lists a little longer than what fits at once still gain from the balanced
+// layout (their last workgroups start as others finish), measured at L = 512
+// with 203 inverse and 137 forward workgroups per XCD.
 constexpr int RESIDENT_INV = 7;
 constexpr int RESIDENT_FWD = 5;
 
