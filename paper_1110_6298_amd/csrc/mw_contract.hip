@@ -461,8 +461,9 @@ __device__ __forceinline__ void contract_forward_body(
 }
 
 
-// The plain variant runs five waves per SIMD without spills in its loops; the
-// exponent-extended one (large band-limits) needs the registers of four.
+// Four waves per SIMD for a complex map (five spill in the loops and are
+// slower), plain or exponent-extended; a real map's plain variant fits five,
+// the most its 32 KB of LDS per workgroup allows.
 #define MW_FORWARD_ARGS                                                                                          \
     const double* __restrict__ Hp0, size_t hstride, Batch B, const double* __restrict__ Rtg,                    \
         const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,           \
@@ -743,7 +744,7 @@ __device__ __forceinline__ void inv2_phase(InvLane2<EXT>& st, int jfrom, int jla
     };
     if constexpr (EXT) {
         // the exponent-extended variant keeps one pair per iteration: unrolled,
-        // it needs more registers than five waves per SIMD leave
+        // it needs more registers than its wave budget leaves
         for (int j = jfrom; j <= jlast; ++j) {
             rB = inv_load_r(Rt, ne, min(j + 1, jr));
             half(2 * j, r);
