@@ -171,8 +171,8 @@ def main():
                          "(a plain read+write kernel of known size, for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(maps are independent; see DESIGN.md for how the work would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(maps are independent, so a batch would shard by map with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
