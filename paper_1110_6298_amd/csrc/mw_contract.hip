@@ -491,18 +491,19 @@ __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(4)
 // Inverse contraction
 // ===========================================================================
 
-// Inverse coefficient stream: record (c_l sp(l) f_{l,m}, c_l sm(l) f_{l,-m}) at
-// [(m*Lp + l)*4] for 0 <= m <= l < L (zero elsewhere, l < Lp), where sp and sm
+// Inverse coefficient stream: record (c_l sp(l) f_{l,m}, c_l sm(l) f_{l,-m}) / (h_m(l) h_|s|(l))
+// at [(m*Lp + l)*4] for 0 <= m <= l < L (zero elsewhere, l < Lp), where sp and sm
 // are the degree-parity factors of the +m and -m terms (Eq. for F_{m m'} with
-// the order symmetries of Delta).  A 32(l) x 8(m) tile is read along m (rows of
+// the order symmetries of Delta) and h the scales of the contraction's chains
+// (the .y of the l-recursion table), which the division undoes.  A 32(l) x 8(m) tile is read along m (rows of
 // f_lm are contiguous in m) and written along l through LDS.
 constexpr int STR_L = 32, STR_M = 8;
 
 // OUT32 = 1 writes the record as FP32 at [(m*4 + comp)*Lp + l] instead (the
 // layout the mixed-precision inverse stages per order).
 template <int OUT32>
-__global__ __launch_bounds__(256) void k_inverse_stream(Batch B, const double* __restrict__ cl, int L, int Lp, int s,
-                                                        int real)
+__global__ __launch_bounds__(256) void k_inverse_stream(Batch B, const double* __restrict__ cl,
+                                                        const double2* __restrict__ lco, int L, int Lp, int s, int real)
 {
     const double2* __restrict__ flm = (const double2*)B.in[blockIdx.z];
     void* __restrict__ fs = B.out[blockIdx.z];
@@ -526,7 +527,8 @@ __global__ __launch_bounds__(256) void k_inverse_stream(Batch B, const double* _
         const int i = threadIdx.x % STR_L, k = threadIdx.x / STR_L;   // write: l = l0+i, m = m0+k
         const int l = l0 + i, m = m0 + k;
         if (m >= L || l >= Lp) return;
-        const double c = (l < L) ? cl[l] : 0.0;
+        const int as = s < 0 ? -s : s;
+        const double c = (l < L) ? cl[l] / (lco[(size_t)m * Lp + l].y * lco[(size_t)as * Lp + l].y) : 0.0;
         const double par = (l & 1) ? -c : c;
         const double sp = (s >= 0) ? par : c;
         const double sm = (s >= 0) ? c : par;
@@ -589,7 +591,7 @@ struct InvGeo { int lstart, lA, cs, ce, nseg; };
 // group share everything that depends on n and l only: X_n(l), Y_n(l), the
 // exact q bookkeeping and the spin chain Delta^l_{n,|s|}; each order keeps its
 // own chain Delta^l_{n,m} and sums.  The uniform data of a step (both orders'
-// stream records and (Pu, Qu), and (Pu, Qu) of |s|) is 28 scalar registers, so
+// stream records and (Pu', h), and (Pu', h) of |s|) is 28 scalar registers, so
 // it is double-buffered step by step.
 // ===========================================================================
 template <bool EXT>
@@ -606,12 +608,12 @@ struct InvLane2 {
 struct InvS2 { double4 f0, f1; double2 c0, c1, cs; };   // one step l
 
 // Rows of the uniform data of a group: stream records of both orders, their
-// (Pu, Qu) factors and those of |s|, each indexed by the degree l.  Addresses
+// (Pu', h) factors and those of |s|, each indexed by the degree l.  Addresses
 // are a base pointer plus a 32-bit byte offset (scalar loads take the offset
 // in a register, so a row costs one register instead of a 64-bit pointer).
 struct Inv2Rows {
     const char* f;   // stream records, 32 bytes per (m, l)
-    const char* c;   // (Pu, Qu), 16 bytes per (m, l)
+    const char* c;   // (Pu', h), 16 bytes per (m, l)
     unsigned f0, f1, c0, c1, cs;   // byte offsets of the rows at l = 0
 };
 
@@ -636,7 +638,7 @@ __device__ __forceinline__ void inv2_load(InvS2& u, const Inv2Rows& w, int l)
 
 // Brings the first lines of a segment's uniform rows into the L2 before its
 // loop: lane i reads one dword of line i of each row (stream records, 32 bytes
-// per degree; (Pu, Qu) rows, 16 bytes), starting at degree l0 and clamped to
+// per degree; (Pu', h) rows, 16 bytes), starting at degree l0 and clamped to
 // degree lend.  Waves of one order pair start their segments at the same
 // degrees, so without this every new line of the loop would be a miss beyond
 // the L2 for all of them at once; the values feed only a register use.
@@ -652,8 +654,9 @@ __device__ __forceinline__ unsigned inv2_touch(const Inv2Rows& w, int l0, int le
 }
 
 // One step l of both orders' chains and the spin chain: injections, the
-// products pr[c] = Delta^l_{n,m_c} Delta^l_{n,|s|} of this step, then the
-// recursion to l+1.  (c0, c1, cs): (Pu, Qu) of the two orders and of |s| at l.
+// products pr[c] = e^l_{n,m_c} e^l_{n,|s|} of this step (scaled chains, e = h Delta;
+// the coefficient records carry 1/(h_m h_|s|)), then the recursion to l+1.
+// (c0, c1, cs): (Pu', h) of the two orders and of |s| at l.
 template <bool EXT, bool INJ>
 __device__ __forceinline__ void inv2_core(InvLane2<EXT>& st, int l, int lstart, double nd, const double2& c0,
                                           const double2& c1, const double2& cs, double rs, double (&pr)[2],
@@ -680,15 +683,16 @@ __device__ __forceinline__ void inv2_core(InvLane2<EXT>& st, int l, int lstart, 
     st.sprev = st.q * rs;
     st.q += st.dq;
     st.dq += 2.0;
+    // scaled chains: the Delta^{l-1} term has coefficient 1 (.x = Pu'_m(l))
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const double2 pq = c ? c1 : c0;
-        const double dn = fma(pq.x * xn, st.dc[c], (pq.y * yn) * st.dp[c]);
+        const double dn = fma(pq.x * xn, st.dc[c], yn * st.dp[c]);
         st.dp[c] = st.dc[c];
         st.dc[c] = dn;
     }
     {
-        const double sn = fma(cs.x * xn, st.sc, (cs.y * yn) * st.sp);
+        const double sn = fma(cs.x * xn, st.sc, yn * st.sp);
         st.sp = st.sc;
         st.sc = sn;
     }
@@ -766,9 +770,11 @@ __device__ __forceinline__ void inv2_phase(InvLane2<EXT>& st, int jfrom, int jla
     }
 }
 
+// Start values are scaled by h_m(l) (the .y of the l-recursion table) at their
+// degree, so that the chains run as e = h Delta.
 template <bool EXT>
 __device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled, const InvGeo& geo, int w, int n,
-                                             int m0, int L, int Lp, int as, int ckg,
+                                             int m0, int L, int Lp, int as, int ckg, const double2* __restrict__ lco,
                                              const double* __restrict__ edge, const int* __restrict__ edgek,
                                              const double* __restrict__ stab, const int* __restrict__ stabk,
                                              const double2* __restrict__ cki, const int2* __restrict__ ckik,
@@ -795,22 +801,23 @@ __device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled,
             for (int c = 0; c < 2; ++c) {
                 const int m = m0 + c;
                 if (m >= L) continue;
-                st.start[c] = edge[(size_t)m * L + n];
+                st.start[c] = edge[(size_t)m * L + n] * lco[(size_t)m * Lp + st.lz[c]].y;
                 if (EXT) st.startk[c] = edgek[(size_t)m * L + n];
             }
             // spin chain: from the table at lstart when already running, else injected
             if (st.l0s <= lstart) {
                 double v1 = stab[(size_t)lstart * L + n], v0 = 0.0;
                 int k1 = EXT ? stabk[(size_t)lstart * L + n] : 0, k0 = k1;
+                v1 *= lco[(size_t)as * Lp + lstart].y;
                 if (lstart >= 1) {
-                    v0 = stab[(size_t)(lstart - 1) * L + n];
+                    v0 = stab[(size_t)(lstart - 1) * L + n] * lco[(size_t)as * Lp + lstart - 1].y;
                     k0 = EXT ? stabk[(size_t)(lstart - 1) * L + n] : 0;
                 }
                 int kk;
                 ck_level<EXT>(v0, v1, k0, k1, kk);
                 st.sc = v1; st.sp = v0; st.ks = kk;
             } else if (st.l0s < L) {
-                st.starts = stab[(size_t)st.l0s * L + n];
+                st.starts = stab[(size_t)st.l0s * L + n] * lco[(size_t)as * Lp + st.l0s].y;
                 st.startks = EXT ? stabk[(size_t)st.l0s * L + n] : 0;
             }
         }
@@ -831,11 +838,14 @@ __device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled,
                 if (m >= L) continue;
                 const size_t i = ckoff.off[jj] + (size_t)m * (cdeg + 1) + n;
                 double2 v = cki[i];
+                v.x *= lco[(size_t)m * Lp + cdeg - 1].y;
+                v.y *= lco[(size_t)m * Lp + cdeg].y;
                 int kk = 0;
                 if (EXT) { const int2 kv = ckik[i]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
                 st.dp[c] = v.x; st.dc[c] = v.y; st.k[c] = kk;
             }
-            double v1 = stab[(size_t)cdeg * L + n], v0 = stab[(size_t)(cdeg - 1) * L + n];
+            double v1 = stab[(size_t)cdeg * L + n] * lco[(size_t)as * Lp + cdeg].y;
+            double v0 = stab[(size_t)(cdeg - 1) * L + n] * lco[(size_t)as * Lp + cdeg - 1].y;
             int k1 = EXT ? stabk[(size_t)cdeg * L + n] : 0, k0 = EXT ? stabk[(size_t)(cdeg - 1) * L + n] : 0;
             int kk;
             ck_level<EXT>(v0, v1, k0, k1, kk);
@@ -891,7 +901,7 @@ __device__ __forceinline__ void contract_inverse2_body(
         const Inv2Rows rows = inv2_rows(fs, lco, m0, as, Lp, L);
         const unsigned touched = inv2_touch(rows, geo.cs, lend, lane);
         bool anyscaled;
-        const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, ckg, edge, edgek, stab, stabk,
+        const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, ckg, lco, edge, edgek, stab, stabk,
                                          cki, ckik, ckoff);
         asm volatile("" ::"v"(touched));
         if (g.active) {
@@ -1217,7 +1227,7 @@ __global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
 // FP32 and accumulated by v_mfma_f32_4x4x1_16b_f32 against the FP32 stream of
 // every map of the group (windows of WIN degrees in LDS, as in the one-order
 // kernel).  Work list: the packed segment list of the spin table.
-struct InvC2 { double4 c0, c1, cs; };   // pair (l, l+1): (Pu,Qu) of m0, of m0+1 and of |s|
+struct InvC2 { double4 c0, c1, cs; };   // pair (l, l+1): (Pu', h) of m0, of m0+1 and of |s|
 
 __device__ __forceinline__ void inv2m_load_c(InvC2& u, const Inv2Rows& w, int j)
 {
@@ -1344,8 +1354,10 @@ __host__ __device__ constexpr int inv2m_slot_floats(int G)
     return (2 * G * 4 * WROW > 2 * G * 64 * 4) ? 2 * G * 4 * WROW : 2 * G * 64 * 4;
 }
 
+// Groups of four maps hold three waves per SIMD (136 VGPRs beside the 32 AGPRs of
+// their accumulators); left alone the allocator can take two more and drop to two.
 template <bool EXT, int G>
-__global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse2_mix(
+__global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(G == 4 ? 3 : 4))) void k_contract_inverse2_mix(
     MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
     const double2* __restrict__ lco, const double* __restrict__ stab, const int* __restrict__ stabk,
     const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work,
@@ -1386,7 +1398,7 @@ __global__ __launch_bounds__(64 * SEGI_MAX) void k_contract_inverse2_mix(
         geo.nseg = nseg;
         InvLane2<EXT> st;
         bool anyscaled;
-        const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, ckg, edge, edgek, stab, stabk,
+        const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, ckg, lco, edge, edgek, stab, stabk,
                                          cki, ckik, ckoff);
         if (g.active)
             inv2m_segment<EXT, G>(st, acc, g, jend, geo.lstart, ne, nd, m0, inv2_rows(nullptr, lco, m0, as, Lp, L),
@@ -1482,8 +1494,8 @@ hipError_t launch_real_fold(int L, const Batch& B, hipStream_t st)
 hipError_t launch_inverse_stream(const Plan& p, int s, int real, const Batch& B, int out32, hipStream_t st)
 {
     const dim3 grid((p.Lp + STR_L - 1) / STR_L, (p.L + STR_M - 1) / STR_M, B.n);
-    if (out32) hipLaunchKernelGGL(k_inverse_stream<1>, grid, dim3(256), 0, st, B, p.cl, p.L, p.Lp, s, real);
-    else hipLaunchKernelGGL(k_inverse_stream<0>, grid, dim3(256), 0, st, B, p.cl, p.L, p.Lp, s, real);
+    if (out32) hipLaunchKernelGGL(k_inverse_stream<1>, grid, dim3(256), 0, st, B, p.cl, p.lco, p.L, p.Lp, s, real);
+    else hipLaunchKernelGGL(k_inverse_stream<0>, grid, dim3(256), 0, st, B, p.cl, p.lco, p.L, p.Lp, s, real);
     return hipGetLastError();
 }
 

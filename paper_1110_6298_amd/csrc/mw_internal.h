@@ -45,7 +45,7 @@ struct Plan {
     // contiguous read.
     double* edge = nullptr;
     int* edgek = nullptr;       // k of each entry
-    double2* lco = nullptr;     // l-recursion factors (Pu_m(l), Qu_m(l)) at [m*Lp + l] (0 for l >= L)
+    double2* lco = nullptr;     // scaled l-recursion factor and scale (Pu'_m(l), h_m(l)) at [m*Lp + l]
     double* cl = nullptr;       // sqrt((2l+1)/(4 pi))
     // Fourier tables
     double2* tw = nullptr;      // exp(-2 pi i e/N2), e < N2

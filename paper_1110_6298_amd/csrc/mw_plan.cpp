@@ -210,15 +210,29 @@ int build_plan(int L, Plan& p, std::string& err)
     // n part formed in the kernel:
     //  Delta^{l+1} = Pu_m(l) X_n(l) Delta^l + Qu_m(l) Y_n(l) Delta^{l-1}
     //  Pu_m(l) = -(2l+1) m / (l sqrt((l+1)^2 - m^2)),  Qu_m(l) = -(l+1)/l sqrt((l^2-m^2)/((l+1)^2-m^2))
-    std::vector<double2> lco((size_t)L * p.Lp, make_double2(0.0, 0.0));
-    for (int m = 0; m < L; ++m)
-        for (int l = std::max(1, m); l < L; ++l) {
-            ld a = (ld)(l + 1) * (l + 1) - (ld)m * m;
-            ld b = (ld)l * l - (ld)m * m;
-            ld pu = -(2.0L * l + 1.0L) * (ld)m / ((ld)l * sqrtl(a));
-            ld qu = -((ld)(l + 1) / (ld)l) * sqrtl(b / a);
-            lco[(size_t)m * p.Lp + l] = make_double2((double)pu, (double)qu);
+    // The inverse runs the chains scaled, e_l = h_m(l) Delta^l, with h_m(m) =
+    // h_m(m+1) = 1 and h_m(l+1) = h_m(l-1) / Qu_m(l), so that the Delta^{l-1} term
+    // has coefficient 1:  e_{l+1} = Pu'_m(l) X_n(l) e_l + Y_n(l) e_{l-1},
+    // Pu'_m(l) = Pu_m(l) h_m(l+1) / h_m(l).  |Qu_m(l)| is close to 1 away from
+    // l = m, so h stays in [1, 5] up to L = 2048.  Entry [m*Lp + l] holds
+    // (Pu'_m(l), h_m(l)); h = 1 where the chain does not exist (l < m, l >= L).
+    std::vector<double2> lco((size_t)L * p.Lp, make_double2(0.0, 1.0));
+    for (int m = 0; m < L; ++m) {
+        ld hprev = 1.0L, hcur = 1.0L;   // h_m(l-1), h_m(l) at l = m
+        for (int l = m; l < L; ++l) {
+            const ld a = (ld)(l + 1) * (l + 1) - (ld)m * m;
+            const ld pu = (l == 0) ? 0.0L : -(2.0L * l + 1.0L) * (ld)m / ((ld)l * sqrtl(a));
+            ld hnext = 1.0L;   // h_m(l+1)
+            if (l > m) {
+                const ld b = (ld)l * l - (ld)m * m;
+                const ld qu = -((ld)(l + 1) / (ld)l) * sqrtl(b / a);
+                hnext = hprev / qu;
+            }
+            lco[(size_t)m * p.Lp + l] = make_double2((double)(pu * hnext / hcur), (double)hcur);
+            hprev = hcur;
+            hcur = hnext;
         }
+    }
     if ((rc = upload(lco, &p.lco, p.bytes, err))) return rc;
 
     std::vector<double> cl(L);
