@@ -23,8 +23,8 @@ PEAK_FP64_VALU = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 # read for a plain copy of known size (profiles/traffic_roundtrip_L512_s2.md).
 # Valid only while the kernel and plan sources are unchanged: keyed by their SHA-256.
 TRAFFIC = {
-    ("contract_inverse", 512, 2): {"bytes": 29674347, "source_sha256": "1d771b445266f67bdd6f6990619e5e22e8a85f03f91d32ae5360471bcd8a9963"},
-    ("contract_forward", 512, 2): {"bytes": 29424627, "source_sha256": "1d771b445266f67bdd6f6990619e5e22e8a85f03f91d32ae5360471bcd8a9963"},
+    ("contract_inverse", 512, 2): {"bytes": 29683724, "source_sha256": "894e192efbfc40adb1478cf0290886d096348bc352f9f9c7d85a6edb24c987f7"},
+    ("contract_forward", 512, 2): {"bytes": 29424079, "source_sha256": "894e192efbfc40adb1478cf0290886d096348bc352f9f9c7d85a6edb24c987f7"},
 }
 KERNEL_SOURCES = ("paper_1110_6298_amd/csrc/mw_contract.hip", "paper_1110_6298_amd/csrc/mw_plan.cpp")
 

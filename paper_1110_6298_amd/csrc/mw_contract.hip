@@ -1129,8 +1129,10 @@ __host__ __device__ constexpr int fwdm_slot_floats(int G)
     return (G * 8 * WROW > 2 * G * 64 * 4) ? G * 8 * WROW : 2 * G * 64 * 4;
 }
 
+// Wave budgets as for the mixed inverse: five waves per SIMD for one map (96
+// VGPRs, the accumulators in ordinary VGPRs), four for two, three for four.
 template <bool EXT, int G>
-__global__ __launch_bounds__(64 * SEG_MAX) void k_contract_forward_mix(
+__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(G == 1 ? 5 : (G == 4 ? 3 : 4)))) void k_contract_forward_mix(
     MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
     const double* __restrict__ cl, const double2* __restrict__ ckf, const int2* __restrict__ ckfk,
     const int4* __restrict__ work, int L, int s, int ckfg)
