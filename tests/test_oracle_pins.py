@@ -240,6 +240,25 @@ def test_forward_orders_matches_full(orc):
             assert abs(part[k, l] - ref) < 1e-15
 
 
+@pytest.mark.parametrize("L", [5, 9, 20])
+@pytest.mark.parametrize("s", [0, 2, -3])
+def test_inverse_orders_are_ring_fourier_coefficients(orc, L, s):
+    # Eq.(f_pfft): F_m(theta_t) is the phi-Fourier coefficient of ring t of the
+    # inverse map, (1/N1) sum_p f(theta_t, phi_p) e^{-i m phi_p}.  The map comes
+    # from the full inverse (itself pinned by brute-force synthesis), the ring
+    # DFT from numpy; negative m sit at residue m mod N1.
+    if abs(s) >= L:
+        pytest.skip("spin needs |s| < L")
+    N1 = 2 * L - 1
+    flm = mwsynth.flm_gaussian(L, s, seed=40 + L)
+    ring_dft = np.fft.fft(orc.inverse(flm, L, s), axis=1) / N1    # [t][m mod N1]
+    ms = sorted({-(L - 1), -2, -1, 0, 1, 3 % L, L - 1})
+    got = orc.inverse_orders(flm, L, s, ms)
+    scale = np.abs(ring_dft).max()
+    for k, m in enumerate(ms):
+        np.testing.assert_allclose(got[k], ring_dft[:, m % N1], atol=1e-14 * scale, rtol=0)
+
+
 # --------------------------------------------------------------------------
 # Adjoints (dot-product identity)
 # --------------------------------------------------------------------------
