@@ -47,8 +47,9 @@
  *
  * Memory: the library owns per-band-limit plan tables and a workspace for
  * intermediates, both allocated on first use on the current device (outside any
- * stream capture) and kept until mw_release() or process exit.  It never frees
- * caller memory.
+ * stream capture) and kept until mw_release() or process exit.  A caller may
+ * instead bind a workspace of its own to a stream (mw_set_workspace).  The
+ * library never frees caller memory.
  * ---------------------------------------------------------------------------
  */
 #ifndef MW_H
@@ -120,6 +121,21 @@ int mw_inverse_adjoint(const int32_t* L, const int32_t* spin, const int32_t* rea
 int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                       int32_t precision, size_t* bytes);
 
+/* Bind a caller-owned DEVICE buffer of `bytes` bytes (dptr, 256-byte alignment
+ * not required) as the workspace of every later call on `stream` (a hipStream_t;
+ * NULL = the default stream) on the current device; dptr = NULL unbinds it, and
+ * calls on that stream use the library's workspace again.  A bound call never
+ * allocates or touches the library's workspace: if the call needs more than
+ * `bytes` (mw_workspace_size with the same arguments) it fails with MW_ENOMEM
+ * before enqueueing anything.  Calls on different streams with buffers of their
+ * own may therefore run concurrently.  Plan tables are still the library's:
+ * under stream capture, prepare them first (mw_prepare).  The buffer's contents
+ * on entry do not matter; the caller keeps ownership and must keep it allocated
+ * until every call (or captured graph replay) that used it has completed.
+ * Enqueues nothing and does not synchronise.  MW_EINVAL for dptr != NULL with
+ * bytes = 0. */
+int mw_set_workspace(void* dptr, size_t bytes, void* stream);
+
 /* Create the plan tables and workspace a call with these arguments needs, on the
  * current device, so that a later call (e.g. one under stream capture) performs
  * no allocation.  With precision MW_FP32C it also times the candidate group
@@ -133,7 +149,8 @@ int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* real
  * that fork from and join back into the caller's stream; calls under
  * stream capture (hipGraph) record those launches with their arguments and
  * replay them unchanged.  Call mw_prepare with the same arguments first: a call
- * under capture that would need an allocation fails with MW_ENOMEM.  Workspaces
+ * under capture that would need an allocation fails with MW_ENOMEM, before it
+ * enqueues anything (the capture stays usable).  Workspaces
  * outgrown by later calls stay allocated until mw_release, so a captured graph
  * stays valid until then; concurrent calls (or replays) on one device share the
  * workspace and must be ordered by the caller. */

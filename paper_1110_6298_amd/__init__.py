@@ -20,14 +20,14 @@ from typing import Sequence
 
 __all__ = ["forward", "inverse", "forward_adjoint", "inverse_adjoint", "forward_batch",
            "inverse_batch", "forward_adjoint_batch", "inverse_adjoint_batch", "prepare", "release",
-           "workspace_size", "library", "MWError", "FP64", "FP32C", "EXPORTS", "LIB_PATH"]
+           "workspace_size", "set_workspace", "library", "MWError", "FP64", "FP32C", "EXPORTS", "LIB_PATH"]
 
 FP64, FP32C = 0, 1
 _PREC = {"fp64": FP64, "fp32c": FP32C, FP64: FP64, FP32C: FP32C}
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmw.so")
 EXPORTS = ("mw_forward", "mw_inverse", "mw_forward_adjoint", "mw_inverse_adjoint",
-           "mw_workspace_size", "mw_prepare", "mw_release", "mw_status_string",
+           "mw_workspace_size", "mw_set_workspace", "mw_prepare", "mw_release", "mw_status_string",
            "mw_last_error", "mw_version")
 PROFILE_EXPORTS = ("mw_profile_enable", "mw_profile_read", "mw_profile_stage_name", "mw_profile_tuned_group")
 NSTAGE = 9
@@ -58,6 +58,8 @@ def library():
         lib.mw_workspace_size.restype = ctypes.c_int
         lib.mw_workspace_size.argtypes = [i32p, i32p, i32p, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_size_t)]
+        lib.mw_set_workspace.restype = ctypes.c_int
+        lib.mw_set_workspace.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         lib.mw_prepare.restype = ctypes.c_int
         lib.mw_prepare.argtypes = [i32p, i32p, i32p, ctypes.c_int32, ctypes.c_int32]
         lib.mw_release.restype = ctypes.c_int
@@ -221,6 +223,20 @@ def workspace_size(Ls, spins, realities=None, precision=FP64) -> int:
     _check(library().mw_workspace_size(_arr(Ls), _arr(spins), _arr(realities), n, _PREC[precision],
                                        ctypes.byref(out)), "mw_workspace_size")
     return int(out.value)
+
+
+def set_workspace(buf, stream=None) -> None:
+    """Bind a caller-owned device buffer (a CUDA tensor, or None to unbind) as the
+    workspace of later calls on ``stream`` (default: the current torch stream).
+    The caller keeps the tensor alive while those calls (or graph replays) run."""
+    if buf is None:
+        ptr, nbytes = None, 0
+    else:
+        import torch
+        if not isinstance(buf, torch.Tensor) or not buf.is_cuda or not buf.is_contiguous():
+            raise TypeError("the workspace must be a contiguous CUDA tensor")
+        ptr, nbytes = ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()
+    _check(library().mw_set_workspace(ptr, nbytes, _stream_handle(stream)), "mw_set_workspace")
 
 
 def profile_enable(on: bool = True) -> None:

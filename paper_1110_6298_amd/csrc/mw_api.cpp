@@ -38,6 +38,9 @@ struct DeviceState {
     // fork and join events tie them to the caller's stream.
     hipStream_t lane[2] = {nullptr, nullptr};
     hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+    // Caller-owned workspaces bound to streams (mw_set_workspace): calls on such
+    // a stream use the caller's buffer and never the library's.
+    std::map<hipStream_t, std::pair<void*, size_t>> user_ws;
 };
 
 // Create the two chunk streams and their events on the current device.
@@ -224,28 +227,27 @@ int chunk_cap(int L, int precision, int G)
     return std::max(cap, 1);
 }
 
-int group_size(DeviceState& d, int L, int s, int n, bool may_alloc, int& rc)
+// Group size of a mixed-precision chunk: the autotuned one for this shape, else
+// the largest the LDS allows, up to the map count.
+int group_size(int L, int s, int n)
 {
-    const Plan* p = nullptr;
-    rc = get_plan(d, L, may_alloc, &p);
-    if (rc) return 1;
     auto it = g_tuned.find(std::make_tuple(L, s, n));
     if (it != g_tuned.end()) return it->second;
-    return std::min(pow2_ceil(n), mw::mix_group_max(*p));
+    return std::min(pow2_ceil(n), mw::mix_group_max());
 }
 
-std::vector<Chunk> make_chunks(DeviceState& d, const int32_t* L, const int32_t* spin, const int32_t* reality,
-                               int batch, int precision, bool may_alloc, int& rc)
+// Chunks of a call (host only: no plan, no allocation), the same for the call
+// itself, mw_prepare and mw_workspace_size.
+std::vector<Chunk> make_chunks(const int32_t* L, const int32_t* spin, const int32_t* reality, int batch,
+                               int precision)
 {
     std::map<std::tuple<int, int, int>, std::vector<int>> cls;
     for (int b = 0; b < batch; ++b) cls[std::make_tuple(-L[b], spin[b], reality[b])].push_back(b);
     std::vector<Chunk> out;
-    rc = MW_OK;
     for (auto& kv : cls) {
         const int Lc = -std::get<0>(kv.first), sc = std::get<1>(kv.first), rc_ = std::get<2>(kv.first);
         const auto& v = kv.second;
-        const int G = (precision == MW_FP64) ? 1 : group_size(d, Lc, sc, (int)v.size(), may_alloc, rc);
-        if (rc) return out;
+        const int G = (precision == MW_FP64) ? 1 : group_size(Lc, sc, (int)v.size());
         const int cap = chunk_cap(Lc, precision, G);
         for (size_t i = 0; i < v.size(); i += cap) {
             Chunk c;
@@ -402,11 +404,28 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     const bool need_spin = (op == Op::Inverse || op == Op::ForwardAdjoint);
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceState& d = g_dev[dev];
-    const std::vector<Chunk> chunks = make_chunks(d, L, spin, reality, batch, precision, may_alloc, rc);
-    if (rc) return rc;
+    const std::vector<Chunk> chunks = make_chunks(L, spin, reality, batch, precision);
+    // every plan, spin table and the workspace are resolved before anything is
+    // enqueued, so that a failure leaves the stream (and a capture) untouched
+    std::vector<const Plan*> plans(chunks.size(), nullptr);
+    std::vector<const SpinTable*> spins(chunks.size(), nullptr);
+    for (size_t i = 0; i < chunks.size(); ++i) {
+        const Chunk& c = chunks[i];
+        if ((rc = get_plan(d, c.L, may_alloc, &plans[i]))) return rc;
+        if (need_spin && (rc = get_spin(d, *plans[i], c.s < 0 ? -c.s : c.s, may_alloc, &spins[i]))) return rc;
+    }
     const int Lws = batch_lmax(L, batch);
+    const size_t need = call_ws(chunks, Lws);
     void* ws = nullptr;
-    if ((rc = get_ws(d, call_ws(chunks, Lws), may_alloc, &ws))) return rc;
+    auto uw = d.user_ws.find(st);
+    if (uw != d.user_ws.end()) {
+        if (uw->second.second < need)
+            return fail(MW_ENOMEM, "the workspace set for this stream has %zu bytes, this call needs %zu",
+                        uw->second.second, need);
+        ws = uw->second.first;
+    } else if ((rc = get_ws(d, need, may_alloc, &ws))) {
+        return rc;
+    }
     // several chunks alternate over the two chunk streams (per-stage profiling
     // keeps the caller's stream, so that its events time one launch each)
     const bool lanes = chunks.size() > 1 && !g_prof_on && (d.lane[0] || (may_alloc && make_lanes(d)));
@@ -418,20 +437,17 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     }
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < chunks.size() && e == hipSuccess; ++i) {
-        const Chunk& c = chunks[i];
-        const Plan* p = nullptr;
-        const SpinTable* sp = nullptr;
-        if ((rc = get_plan(d, c.L, may_alloc, &p))) return rc;
-        if (need_spin && (rc = get_spin(d, *p, c.s < 0 ? -c.s : c.s, may_alloc, &sp))) return rc;
         hipStream_t cs = lanes ? d.lane[i & 1] : st;
         void* cws = lanes ? (void*)((char*)ws + (i & 1) * half) : ws;
-        e = run_chunk(op, c, *p, sp, precision, ptrs, cws, Lws, cs);
+        e = run_chunk(op, chunks[i], *plans[i], spins[i], precision, ptrs, cws, Lws, cs);
     }
     if (lanes) {
         // join both chunk streams back into the caller's stream, also after a failed launch
+        bool joined = true;
         for (int k = 0; k < 2; ++k)
-            if (hipEventRecord(d.join[k], d.lane[k]) != hipSuccess || hipStreamWaitEvent(st, d.join[k], 0) != hipSuccess)
-                return fail(MW_EHIP, "stream join failed");
+            joined = (hipEventRecord(d.join[k], d.lane[k]) == hipSuccess &&
+                      hipStreamWaitEvent(st, d.join[k], 0) == hipSuccess) && joined;
+        if (!joined) return fail(MW_EHIP, "stream join failed");
     }
     if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     g_last_error.clear();
@@ -456,7 +472,7 @@ int autotune(DeviceState& d, const int32_t* L, const int32_t* spin, const int32_
         if (g_tuned.count(key)) continue;
         const Plan* p = nullptr;
         if ((rc = get_plan(d, Lc, true, &p))) break;
-        const int gmax = std::min(pow2_ceil(n), mw::mix_group_max(*p));
+        const int gmax = std::min(pow2_ceil(n), mw::mix_group_max());
         const int nt = std::min(n, chunk_cap(Lc, MW_FP32C, gmax));
         void* ws = nullptr;
         if ((rc = get_ws(d, (size_t)nt * ws_need(Lws) + 256, true, &ws))) break;
@@ -527,19 +543,9 @@ int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* real
     int rc = validate(L, spin, reality, batch, nullptr, precision, false);
     if (rc) return rc;
     if (!bytes) return fail(MW_EINVAL, "bytes must be non-NULL");
-    // the largest chunk of maps with equal (L, spin, reality), capped like the calls cap it
-    std::map<std::tuple<int, int, int>, int> cnt;
-    for (int b = 0; b < batch; ++b) ++cnt[std::make_tuple(L[b], spin[b], reality[b])];
-    size_t slots = 1, nchunks = 0;
-    for (auto& kv : cnt) {
-        const int Lc = std::get<0>(kv.first);
-        const int G = (precision == MW_FP64) ? 1 : std::min(pow2_ceil(kv.second), mw::GMAX);
-        const int cap = chunk_cap(Lc, precision, G);
-        slots = std::max(slots, (size_t)std::min(kv.second, cap));
-        nchunks += (kv.second + cap - 1) / cap;
-    }
-    // one half per chunk stream when the call has several chunks
-    *bytes = (nchunks > 1 ? 2 : 1) * (slots * ws_need(batch_lmax(L, batch)) + 256);
+    // the chunks the call itself would form (group sizes as tuned so far)
+    std::lock_guard<std::mutex> lock(g_mu);
+    *bytes = call_ws(make_chunks(L, spin, reality, batch, precision), batch_lmax(L, batch));
     return MW_OK;
 }
 
@@ -550,6 +556,9 @@ int mw_prepare(const int32_t* L, const int32_t* spin, const int32_t* reality, in
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");
     std::lock_guard<std::mutex> lock(g_mu);
+    // work already in flight (on any stream) may use the workspace that the
+    // autotuner below overwrites
+    if (hipDeviceSynchronize() != hipSuccess) return fail(MW_EHIP, "hipDeviceSynchronize failed");
     DeviceState& d = g_dev[dev];
     for (int b = 0; b < batch; ++b) {
         const Plan* p;
@@ -559,12 +568,25 @@ int mw_prepare(const int32_t* L, const int32_t* spin, const int32_t* reality, in
         if ((rc = get_spin(d, *p, as, true, &sp))) return rc;
     }
     if (precision != MW_FP64 && (rc = autotune(d, L, spin, reality, batch))) return rc;
-    const std::vector<Chunk> chunks = make_chunks(d, L, spin, reality, batch, precision, true, rc);
-    if (rc) return rc;
+    const std::vector<Chunk> chunks = make_chunks(L, spin, reality, batch, precision);
     void* ws = nullptr;
     if ((rc = get_ws(d, call_ws(chunks, batch_lmax(L, batch)), true, &ws))) return rc;
     if (chunks.size() > 1 && !make_lanes(d)) return fail(MW_EHIP, "chunk stream creation failed");
     if (hipDeviceSynchronize() != hipSuccess) return fail(MW_EHIP, "hipDeviceSynchronize failed");
+    return MW_OK;
+}
+
+int mw_set_workspace(void* dptr, size_t bytes, void* stream)
+{
+    if (dptr && bytes == 0) return fail(MW_EINVAL, "a workspace needs bytes > 0");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState& d = g_dev[dev];
+    hipStream_t st = (hipStream_t)stream;
+    if (dptr) d.user_ws[st] = std::make_pair(dptr, bytes);
+    else d.user_ws.erase(st);
+    g_last_error.clear();
     return MW_OK;
 }
 

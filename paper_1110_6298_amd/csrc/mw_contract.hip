@@ -1566,7 +1566,7 @@ hipError_t inv_mix_go(const Plan& p, const SpinTable& sp, int s, const MixBatch&
 
 }  // namespace
 
-int mix_group_max(const Plan&)
+int mix_group_max()
 {
     for (int G = GMAX; G > 1; G >>= 1)
         if (mix_lds_forward(G) <= 160 * 1024 && (size_t)SEGI_MAX * inv2m_slot_floats(G) * 4 <= 160 * 1024)

@@ -167,8 +167,8 @@ hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc
 // Adjoint of the real-map coefficient expansion: y_{l,m} += (-1)^m conj(y_{l,-m}),
 // y_{l,-m} = 0 for m > 0 (in place on the L^2 layout of B.out).
 hipError_t launch_real_fold(int L, const Batch& B, hipStream_t st);
-// Largest group size (1, 2 or 4) whose staging fits the LDS for this plan.
-int mix_group_max(const Plan& p);
+// Largest group size (1, 2 or 4) whose staging fits the LDS (independent of L).
+int mix_group_max();
 // Mixed-precision contractions of up to MIXG groups (each maps.n <= G <= GMAX, G in {1,2,4}).
 hipError_t launch_contract_forward_mix(const Plan& p, int s, const MixBatch& maps, int G, hipStream_t st);
 hipError_t launch_contract_inverse_mix(const Plan& p, const SpinTable& sp, int s, const MixBatch& maps, int G,

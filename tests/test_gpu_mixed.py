@@ -158,3 +158,92 @@ def test_mixed_large_l_sampled(orc, tc, mw):
     got, want = np.concatenate(got), np.concatenate(want)
     print("FP32C L=2048 real, sampled orders: %.3e" % rel(got, want), flush=True)
     assert rel(got, want) < TOL
+
+
+def _rows(f, L, orders):
+    """[orders][L] rows of an L*L coefficient vector (0 where |m| > l)."""
+    out = np.zeros((len(orders), L), dtype=np.complex128)
+    for k, m in enumerate(orders):
+        ls = np.arange(abs(m), L)
+        out[k, ls] = f[ls * ls + ls + m]
+    return out
+
+
+def _ring_orders(x, L, orders):
+    """phi-Fourier coefficients F_m(theta_t) of a map's rings: [orders][t]."""
+    spec = np.fft.fft(np.asarray(x, dtype=np.complex128), axis=1) / (2 * L - 1)
+    return spec[:, np.array(orders) % (2 * L - 1)].T
+
+
+@pytest.mark.parametrize("L,s,real", [(512, 2, 0), (256, 2, 0), (256, 0, 1)])
+def test_mixed_groups_at_batch_sizes(orc, tc, mw, L, s, real):
+    """Four maps of one class in one call (one group of four sharing the chains,
+    several chain segments restarted from checkpoint planes at these L): two of
+    them against the oracle on sampled orders, all four bitwise against single
+    calls (per-map arithmetic does not depend on the group)."""
+    print("mixed groups L=%d s=%d real=%d" % (L, s, real), flush=True)
+    n = 4
+    flm = []
+    for i in range(n):
+        f = mwsynth.flm_gaussian(L, s, seed=16000 + 10 * L + i, decay=1.0)
+        flm.append(mwsynth.make_real_symmetric(f, L) if real else f)
+    maps = mw.inverse_batch([dev(tc, f) for f in flm], [L] * n, [s] * n, [real] * n, precision=FP32C)
+    maps_h = [host(tc, t) for t in maps]
+    orders = [0, 1, 7, L // 2, L - 1] + ([] if real else [-1, -(L // 3), -(L - 1)])
+    for i in range(n):
+        single = host(tc, mw.inverse(dev(tc, flm[i]), L, s, real, precision=FP32C))
+        assert np.array_equal(maps_h[i], single), i
+    for i in range(2):
+        e = rel(_ring_orders(maps_h[i], L, orders), orc.inverse_orders(flm[i], L, s, orders))
+        print("  FP32C inverse, map %d: %.3e" % (i, e), flush=True)
+        assert e < TOL
+    grids = [m + 0.25 * mwsynth.grid_gaussian(L, seed=16500 + i, real=bool(real)) for i, m in enumerate(maps_h)]
+    fw = mw.forward_batch([dev(tc, g) for g in grids], [L] * n, [s] * n, [real] * n, precision=FP32C)
+    fw_h = [host(tc, t) for t in fw]
+    for i in range(n):
+        single = host(tc, mw.forward(dev(tc, grids[i]), L, s, real, precision=FP32C))
+        assert np.array_equal(fw_h[i], single), i
+    for i in range(2):
+        ref = orc.forward_orders(grids[i].astype(np.complex128), L, s, orders)
+        e = rel(_rows(fw_h[i], L, orders), ref)
+        print("  FP32C forward, map %d: %.3e" % (i, e), flush=True)
+        assert e < TOL
+
+
+def test_mixed_inverse_large_l_sampled(orc, tc, mw):
+    """L = 2048 real scalar map (C_l = (l+1)^-2): the exponent-extended mixed
+    inverse on sampled orders of its rings' phi-spectra against the oracle, and
+    the per-degree error of the mixed round trip against the input."""
+    w = mwsynth.workload_real_l2048()
+    L, flm = w["L"], w["flm"]
+    x = host(tc, mw.inverse(dev(tc, flm), L, 0, reality=1, precision=FP32C))
+    orders = [0, 1, 2, 700, 1024, 1500, 2046, 2047]
+    e = rel(_ring_orders(x, L, orders), orc.inverse_orders(flm, L, 0, orders))
+    print("FP32C L=2048 real inverse, sampled orders: %.3e" % e, flush=True)
+    assert e < TOL
+    back = host(tc, mw.forward(dev(tc, x), L, 0, reality=1, precision=FP32C))
+    e_rt = rel(back, flm)
+    e_deg = rel_per_degree(back, flm, L)
+    print("FP32C L=2048 real round trip: %.3e, per degree %.3e" % (e_rt, e_deg), flush=True)
+    assert e_rt < 2 * TOL
+    assert e_deg < PER_DEGREE_TOL
+
+
+def rel_per_degree(got, ref, L):
+    """max over l of max_m |got - ref| / max_m |ref| (the per-degree relative error)."""
+    worst = 0.0
+    for l in range(L):
+        sl = slice(l * l, (l + 1) * (l + 1))
+        den = np.abs(ref[sl]).max()
+        if den > 0:
+            worst = max(worst, float(np.abs(got[sl] - ref[sl]).max() / den))
+    return worst
+
+
+# The per-degree error of the mixed path: FP32 rounding of both factors of each
+# product (2^-24 relative each) over sums of up to L terms, relative to the
+# largest coefficient of that degree; for spectra that fall by three orders of
+# magnitude across l (C_l = (l+1)^-2 at L = 2048), the terms of a high degree
+# are dominated by the low-degree content of the data, so the bound is wider
+# than the global one.
+PER_DEGREE_TOL = 1e-3

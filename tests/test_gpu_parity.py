@@ -17,6 +17,35 @@ def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+def rel_per_degree_rows(got, ref):
+    """Per-degree relative error on [orders][l] rows: max over l of
+    max_m |got - ref| / max_m |ref| over the orders present."""
+    den = np.abs(ref).max(axis=0)
+    num = np.abs(got - ref).max(axis=0)
+    ok = den > 0
+    return float((num[ok] / den[ok]).max())
+
+
+def rel_per_degree(got, ref, L):
+    """max over l of max_m |got - ref| / max_m |ref| on the L*L layout."""
+    worst = 0.0
+    for l in range(L):
+        sl = slice(l * l, (l + 1) * (l + 1))
+        den = np.abs(ref[sl]).max()
+        if den > 0:
+            worst = max(worst, float(np.abs(got[sl] - ref[sl]).max() / den))
+    return worst
+
+
+# Per-degree bound of the FP64 path.  Each coefficient of degree l is a sum of
+# O(L) products of unit-bounded Wigner values with Fourier data whose size is set
+# by the whole spectrum, so its absolute rounding error is about
+# eps * sqrt(L) * max|f|; relative to the largest coefficient of degree l that
+# is eps * sqrt(L) times the spectrum's dynamic range max|f| / max_m|f_l|
+# (about 2L for f ~ 1/(l+1)), i.e. about 1e-11 at L = 2048.
+PER_DEGREE_TOL = 1e-10
+
+
 @pytest.fixture(scope="module")
 def tc():
     import torch
@@ -92,6 +121,9 @@ def test_config_spin2_l512_fp64(tc, mw, spin2_l512):
     got_f = host(tc, mw.forward(dev(tc, x), L, s))
     assert rel(got_f, fref) < TOL
     assert rel(got_f, flm) < TOL
+    e_deg, e_deg_rt = rel_per_degree(got_f, fref, L), rel_per_degree(got_f, flm, L)
+    print("FP64 L=512 s=2 forward per-degree error: %.3e vs oracle, %.3e vs input" % (e_deg, e_deg_rt), flush=True)
+    assert e_deg < PER_DEGREE_TOL and e_deg_rt < PER_DEGREE_TOL
 
 
 @pytest.mark.parametrize("L", [7, 64, 130])
@@ -181,6 +213,10 @@ def test_large_l_sampled_and_round_trip(orc, tc, mw, L, s, real):
         for ll in range(abs(mm), L):
             got_rows[k, ll] = got_f[ll * ll + ll + mm]
     assert rel(got_rows, ref_f) < TOL
+    e_deg = rel_per_degree_rows(got_rows, ref_f)
     # round trip on the band-limited map
     back = host(tc, mw.forward(dev(tc, x), L, s, reality=real))
     assert rel(back, flm) < TOL
+    e_deg_rt = rel_per_degree(back, flm, L)
+    print("  per-degree error: forward %.3e (sampled orders), round trip %.3e" % (e_deg, e_deg_rt), flush=True)
+    assert e_deg < PER_DEGREE_TOL and e_deg_rt < PER_DEGREE_TOL
