@@ -85,6 +85,28 @@ typedef enum {
 int mw_forward(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                void* const* ptrs, int32_t precision, void* stream);
 
+/* Forward transform that allocates nothing, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, layouts and results as mw_forward (the
+ * same kernels, bit for bit), but the intermediates live in a static device
+ * array of MW_NOALLOC_BYTES that every device the library runs on holds from
+ * the library's load until the process ends; the call makes no hipMalloc,
+ * hipFree or other allocation, creates no stream or event, and runs all of its
+ * maps on `stream` (no internal streams).
+ *   - The plan tables must exist: call mw_prepare with the same arguments once
+ *     beforehand, else MW_ENOMEM before anything is enqueued.
+ *   - Limit: the workspace of the call (one set of slots for the largest chunk
+ *     of equal (L, spin, reality); about 25 MB per map at L = 512, 6.3 MB at
+ *     L = 256) must fit MW_NOALLOC_BYTES, else MW_ENOMEM before anything is
+ *     enqueued (mw_last_error gives both sizes).
+ *   - Every call on one device shares that device's array, which keeps the last
+ *     call's intermediates (nothing in it needs to start at zero).  Calls that
+ *     overlap on one device (different streams, or graph replays in flight)
+ *     race on it: the caller must order them. */
+#define MW_NOALLOC_BYTES ((size_t)64 << 20)
+int mw_forward_noalloc(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                       void* const* ptrs, int32_t precision, void* stream);
+
 /* Inverse transform (Sec. IV-E): ptrs[2b] = coeffs, ptrs[2b+1] = map. */
 int mw_inverse(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                void* const* ptrs, int32_t precision, void* stream);

@@ -18,7 +18,7 @@ import ctypes
 import os
 from typing import Sequence
 
-__all__ = ["forward", "inverse", "forward_adjoint", "inverse_adjoint", "forward_batch",
+__all__ = ["forward", "inverse", "forward_noalloc", "forward_noalloc_batch", "forward_adjoint", "inverse_adjoint", "forward_batch",
            "inverse_batch", "forward_adjoint_batch", "inverse_adjoint_batch", "prepare", "release",
            "workspace_size", "set_workspace", "library", "MWError", "FP64", "FP32C", "EXPORTS", "LIB_PATH"]
 
@@ -26,7 +26,7 @@ FP64, FP32C = 0, 1
 _PREC = {"fp64": FP64, "fp32c": FP32C, FP64: FP64, FP32C: FP32C}
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmw.so")
-EXPORTS = ("mw_forward", "mw_inverse", "mw_forward_adjoint", "mw_inverse_adjoint",
+EXPORTS = ("mw_forward", "mw_forward_noalloc", "mw_inverse", "mw_forward_adjoint", "mw_inverse_adjoint",
            "mw_workspace_size", "mw_set_workspace", "mw_prepare", "mw_release", "mw_status_string",
            "mw_last_error", "mw_version")
 PROFILE_EXPORTS = ("mw_profile_enable", "mw_profile_read", "mw_profile_stage_name", "mw_profile_tuned_group")
@@ -51,7 +51,8 @@ def library():
         lib = ctypes.CDLL(LIB_PATH)
         i32p = ctypes.POINTER(ctypes.c_int32)
         vpp = ctypes.POINTER(ctypes.c_void_p)
-        for name in ("mw_forward", "mw_inverse", "mw_forward_adjoint", "mw_inverse_adjoint"):
+        for name in ("mw_forward", "mw_forward_noalloc", "mw_inverse", "mw_forward_adjoint",
+                     "mw_inverse_adjoint"):
             fn = getattr(lib, name)
             fn.restype = ctypes.c_int
             fn.argtypes = [i32p, i32p, i32p, ctypes.c_int32, vpp, ctypes.c_int32, ctypes.c_void_p]
@@ -132,6 +133,7 @@ def _map_shape(L):
 _MAP, _COEF = "map", "coeffs"
 _OPS = {  # name: (input kind, output kind)
     "mw_forward": (_MAP, _COEF),
+    "mw_forward_noalloc": (_MAP, _COEF),
     "mw_inverse": (_COEF, _MAP),
     "mw_forward_adjoint": (_COEF, _MAP),
     "mw_inverse_adjoint": (_MAP, _COEF),
@@ -173,6 +175,13 @@ def forward_batch(maps, Ls, spins, realities=None, precision=FP64, outs=None, st
     return _batch("mw_forward", maps, Ls, spins, realities, precision, outs, stream)
 
 
+def forward_noalloc_batch(maps, Ls, spins, realities=None, precision=FP64, outs=None, stream=None):
+    """mw_forward_noalloc: the forward transforms of a batch with the library's
+    static device scratch as workspace (no allocation in the call; the plans
+    must have been prepared, and the call's workspace must fit MW_NOALLOC_BYTES)."""
+    return _batch("mw_forward_noalloc", maps, Ls, spins, realities, precision, outs, stream)
+
+
 def inverse_batch(coeffs, Ls, spins, realities=None, precision=FP64, outs=None, stream=None):
     """Inverse transforms of a batch of coefficient vectors in one library call."""
     return _batch("mw_inverse", coeffs, Ls, spins, realities, precision, outs, stream)
@@ -191,6 +200,12 @@ def inverse_adjoint_batch(maps, Ls, spins, realities=None, precision=FP64, outs=
 def forward(x, L: int, spin: int = 0, reality: int = 0, precision=FP64, out=None, stream=None):
     """Forward MW transform of one map (L, 2L-1) -> coefficients (L*L,)."""
     return forward_batch([x], [L], [spin], [reality], precision, [out], stream)[0]
+
+
+def forward_noalloc(x, L: int, spin: int = 0, reality: int = 0, precision=FP64, out=None, stream=None):
+    """Forward transform of one map without any allocation in the call (see
+    forward_noalloc_batch)."""
+    return forward_noalloc_batch([x], [L], [spin], [reality], precision, [out], stream)[0]
 
 
 def inverse(flm, L: int, spin: int = 0, reality: int = 0, precision=FP64, out=None, stream=None):

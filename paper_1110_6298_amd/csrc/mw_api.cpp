@@ -24,6 +24,14 @@ using mw::SpinTable;
 
 thread_local std::string g_last_error;
 
+// Workspace of mw_forward_noalloc: a file-scope device array, so that the entry
+// point needs no allocation.  Each device holds its own copy (at its own
+// address) from the library's load until the process ends.  In host code the
+// name is only a stand-in for the symbol: the device address comes from
+// hipGetSymbolAddress, once per device (DeviceState::scratch).
+constexpr size_t NOALLOC_BYTES = MW_NOALLOC_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
 struct DeviceState {
     std::map<int, Plan> plans;                    // by L
     std::map<std::pair<int, int>, SpinTable> spins;  // by (L, |s|)
@@ -41,6 +49,9 @@ struct DeviceState {
     // Caller-owned workspaces bound to streams (mw_set_workspace): calls on such
     // a stream use the caller's buffer and never the library's.
     std::map<hipStream_t, std::pair<void*, size_t>> user_ws;
+    // Device address of this device's copy of `scratch` (set on the first
+    // mw_forward_noalloc call on the device).
+    void* scratch = nullptr;
 };
 
 // Create the two chunk streams and their events on the current device.
@@ -73,9 +84,9 @@ hipEvent_t take_event()
 
 // Runs one launcher, bracketed by events when profiling is on.
 template <class F>
-hipError_t staged(int stage, hipStream_t st, F&& launch)
+hipError_t staged(int stage, hipStream_t st, bool prof, F&& launch)
 {
-    if (!g_prof_on) return launch();
+    if (!g_prof_on || !prof) return launch();
     ProfRec r{stage, take_event(), take_event()};
     (void)hipEventRecord(r.a, st);
     hipError_t e = launch();
@@ -294,8 +305,10 @@ mw::MixBatch mix_of(const Chunk& c, Src src, Dst dst)
 }
 
 // Launch sequence of one chunk.  Map k of the chunk uses workspace slot k.
+// prof = false: no per-stage events even when profiling is on (the
+// allocation-free entry point creates none).
 hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, int precision, void* const* ptrs,
-                     void* ws, int Lws, hipStream_t st)
+                     void* ws, int Lws, hipStream_t st, bool prof = true)
 {
     const bool mix = precision != MW_FP64;
     const int s = c.s, real = c.real;
@@ -307,7 +320,7 @@ hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, 
     auto w2 = [&](int k) { return (void*)slot(ws, Lws, c.L, k).W2; };
     hipError_t e = hipSuccess;
     auto go = [&](int stage, auto launch) {
-        if (e == hipSuccess) e = staged(stage, st, launch);
+        if (e == hipSuccess) e = staged(stage, st, prof, launch);
     };
     switch (op) {
     case Op::Forward: {
@@ -517,6 +530,44 @@ int mw_forward(const int32_t* L, const int32_t* spin, const int32_t* reality, in
                void* const* ptrs, int32_t precision, void* stream)
 {
     return run(Op::Forward, L, spin, reality, batch, ptrs, precision, stream);
+}
+
+int mw_forward_noalloc(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                       void* const* ptrs, int32_t precision, void* stream)
+{
+    int rc = validate(L, spin, reality, batch, ptrs, precision, true);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState& d = g_dev[dev];
+    const std::vector<Chunk> chunks = make_chunks(L, spin, reality, batch, precision);
+    std::vector<const Plan*> plans(chunks.size(), nullptr);
+    for (size_t i = 0; i < chunks.size(); ++i)
+        if ((rc = get_plan(d, chunks[i].L, false, &plans[i])))
+            return fail(MW_ENOMEM, "mw_forward_noalloc: plan for L=%d not prepared (call mw_prepare first)",
+                        chunks[i].L);
+    // the chunks run one after another on the caller's stream, all in the one
+    // set of workspace slots
+    const int Lws = batch_lmax(L, batch);
+    const size_t need = chunks_ws(chunks, Lws);
+    if (need > NOALLOC_BYTES)
+        return fail(MW_ENOMEM, "mw_forward_noalloc: this call needs %zu bytes of workspace, the static scratch holds %zu",
+                    need, NOALLOC_BYTES);
+    if (!d.scratch) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MW_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        d.scratch = ptr;
+    }
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < chunks.size() && e == hipSuccess; ++i)
+        e = run_chunk(Op::Forward, chunks[i], *plans[i], nullptr, precision, ptrs, d.scratch, Lws, st, false);
+    if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    g_last_error.clear();
+    return MW_OK;
 }
 
 int mw_inverse(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,

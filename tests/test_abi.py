@@ -47,7 +47,8 @@ def _raw(name, Ls, spins, reals, batch=None, ptrs=True, prec=0):
     return getattr(lib, name)(arr(Ls), arr(spins), arr(reals), n, pp, prec, None)
 
 
-@pytest.mark.parametrize("name", ["mw_forward", "mw_inverse", "mw_forward_adjoint", "mw_inverse_adjoint"])
+@pytest.mark.parametrize("name", ["mw_forward", "mw_forward_noalloc", "mw_inverse", "mw_forward_adjoint",
+                                  "mw_inverse_adjoint"])
 @pytest.mark.parametrize("Ls,spins,reals,batch,ptrs,prec", [
     ([0], [0], [0], None, True, 0),          # L < 1
     ([2049], [0], [0], None, True, 0),       # L > 2048
