@@ -75,8 +75,13 @@ typedef enum {
     MW_FP32C = 1
 } mw_precision;
 
+/* Largest band-limit: the Wigner recursions stay accurate to l = 4095 with their
+ * exponent-extended start values, the stability range the paper reports for its
+ * own recursion (Sec. V-C, V-D). */
+#define MW_LMAX 4096
+
 /* Validation rules shared by all transform entry points (MW_EINVAL otherwise):
- *   1 <= batch;  for every map b: 1 <= L[b] <= 2048, |spin[b]| < L[b],
+ *   1 <= batch;  for every map b: 1 <= L[b] <= MW_LMAX, |spin[b]| < L[b],
  *   reality[b] in {0, 1}, reality[b] = 1 only with spin[b] = 0 (the real-signal
  *   saving of Sec. IV-G is for scalar maps), ptrs and ptrs[0..2*batch-1] non-NULL,
  *   precision one of mw_precision. */

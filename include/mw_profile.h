@@ -40,6 +40,15 @@ const char* mw_profile_stage_name(int stage);
  * (calls then use the largest size the LDS allows, up to the map count). */
 int mw_profile_tuned_group(int L, int spin, int nmaps, int* G);
 
+/* Fourier-kernel layout of plans built from now on (a test hook): mode 0 (the
+ * default) runs the N2-point transforms in LDS up to N2 = 8192 and splits them
+ * into half-length pairs above (band-limits L > 2048); mode 1 splits them for
+ * every plan with N2 >= 2048 (L >= 257), so that the split kernels can be
+ * compared with the oracle at band-limits it evaluates quickly.  Plans already
+ * built keep their layout (plans are cached per band-limit until mw_release).
+ * Results agree with the unsplit kernels to rounding. */
+int mw_profile_split_fft(int mode);
+
 #ifdef __cplusplus
 }
 #endif

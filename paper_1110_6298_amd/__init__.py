@@ -29,7 +29,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmw.so")
 EXPORTS = ("mw_forward", "mw_forward_noalloc", "mw_inverse", "mw_forward_adjoint", "mw_inverse_adjoint",
            "mw_workspace_size", "mw_set_workspace", "mw_prepare", "mw_release", "mw_status_string",
            "mw_last_error", "mw_version")
-PROFILE_EXPORTS = ("mw_profile_enable", "mw_profile_read", "mw_profile_stage_name", "mw_profile_tuned_group")
+PROFILE_EXPORTS = ("mw_profile_enable", "mw_profile_read", "mw_profile_stage_name", "mw_profile_tuned_group",
+                   "mw_profile_split_fft")
 NSTAGE = 9
 
 _lib = None
@@ -77,6 +78,8 @@ def library():
         lib.mw_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         lib.mw_profile_stage_name.restype = ctypes.c_char_p
         lib.mw_profile_stage_name.argtypes = [ctypes.c_int]
+        lib.mw_profile_split_fft.restype = ctypes.c_int
+        lib.mw_profile_split_fft.argtypes = [ctypes.c_int]
         lib.mw_profile_tuned_group.restype = ctypes.c_int
         lib.mw_profile_tuned_group.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                ctypes.POINTER(ctypes.c_int)]
@@ -273,6 +276,13 @@ def tuned_group(L: int, spin: int, nmaps: int) -> int:
     g = ctypes.c_int(0)
     _check(library().mw_profile_tuned_group(L, spin, nmaps, ctypes.byref(g)), "mw_profile_tuned_group")
     return int(g.value)
+
+
+def split_fft(mode: int) -> None:
+    """Test hook: mode 1 builds every later plan with N2 >= 2048 (L >= 257) with
+    the split half-length Fourier kernels that L > 2048 needs; mode 0 restores
+    the default."""
+    _check(library().mw_profile_split_fft(int(mode)), "mw_profile_split_fft")
 
 
 def release() -> None:

@@ -114,7 +114,7 @@ int validate(const int32_t* L, const int32_t* spin, const int32_t* reality, int3
     if (precision != MW_FP64 && precision != MW_FP32C) return fail(MW_EINVAL, "unknown precision %d", precision);
     if (need_ptrs && !ptrs) return fail(MW_EINVAL, "ptrs must be non-NULL");
     for (int b = 0; b < batch; ++b) {
-        if (L[b] < 1 || L[b] > 2048) return fail(MW_EINVAL, "map %d: L = %d outside [1, 2048]", b, L[b]);
+        if (L[b] < 1 || L[b] > MW_LMAX) return fail(MW_EINVAL, "map %d: L = %d outside [1, %d]", b, L[b], MW_LMAX);
         if (spin[b] <= -L[b] || spin[b] >= L[b])
             return fail(MW_EINVAL, "map %d: |spin| = %d must be < L = %d", b, spin[b], L[b]);
         if (reality[b] != 0 && reality[b] != 1) return fail(MW_EINVAL, "map %d: reality must be 0 or 1", b);
@@ -708,6 +708,14 @@ int mw_profile_read(double* ms, int* count)
     }
     g_prof.clear();
     return rc;
+}
+
+int mw_profile_split_fft(int mode)
+{
+    if (mode != 0 && mode != 1) return fail(MW_EINVAL, "split mode must be 0 or 1");
+    std::lock_guard<std::mutex> lock(g_mu);
+    mw::g_split_min_n2 = mode ? 2048 : 16384;
+    return MW_OK;
 }
 
 int mw_profile_tuned_group(int L, int spin, int nmaps, int* G)

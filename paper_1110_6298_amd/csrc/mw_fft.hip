@@ -176,6 +176,20 @@ struct PlainLoad {
     __device__ double2 operator()(int) const { return make_double2(0.0, 0.0); }   // never called
 };
 
+// First load from registers: with N == RB * blockDim.x the first pass of thread
+// i reads the inputs j = i + t*blockDim.x (t < RB) into its register t, so an
+// input that thread i already holds as its t-th value can be passed as
+// RegLoad{f}, f(t, j) returning input j from the thread's register t (t is a
+// compile-time index after unrolling).
+template <class F>
+struct RegLoad {
+    F f;
+};
+template <class F>
+__device__ __forceinline__ RegLoad<F> reg_load(F f) { return RegLoad<F>{f}; }
+template <class T> struct is_reg_load : std::false_type {};
+template <class F> struct is_reg_load<RegLoad<F>> : std::true_type {};
+
 template <int DIR, int R, int RB, class Store = PlainStore>
 __device__ __forceinline__ void last_pass(double2* x, int N, int p, const double2 (&wl)[RB / 2],
                                           const double2* __restrict__ post, const Store& st = Store())
@@ -239,8 +253,10 @@ struct FftTw {
     double2 wl[RB / 2];   // the final pass has radix >= 2: at most RB/2 butterflies per thread
 };
 
+// shift: the table holds exp(-2 pi i e/(N 2^shift)) (a plan's N2 table serves
+// the half-length transforms of split plans with shift = 1).
 template <int RB>
-__device__ __forceinline__ FftTw<RB> fft_twiddles(int N, int logN, const double2* __restrict__ tw)
+__device__ __forceinline__ FftTw<RB> fft_twiddles(int N, int logN, const double2* __restrict__ tw, int shift = 0)
 {
     constexpr int lr = (RB == 16) ? 4 : 3;
     const int i = threadIdx.x;
@@ -252,7 +268,7 @@ __device__ __forceinline__ FftTw<RB> fft_twiddles(int N, int logN, const double2
         T.w[s - 1] = make_double2(1.0, 0.0);
         if (s < np) {
             const int logp = lr * s;
-            T.w[s - 1] = tw[(i & ((1 << logp) - 1)) << (logN - logp - lr)];
+            T.w[s - 1] = tw[(i & ((1 << logp) - 1)) << (logN - logp - lr + shift)];
         }
     }
     const int logp = lr * np;
@@ -261,7 +277,7 @@ __device__ __forceinline__ FftTw<RB> fft_twiddles(int N, int logN, const double2
     for (int q = 0; q < RB / 2; ++q) {
         const int iq = i + q * blockDim.x;
         T.wl[q] = make_double2(1.0, 0.0);
-        if (r && q < (RB >> r) && iq < NB) T.wl[q] = tw[(iq & ((1 << logp) - 1)) << (logN - logp - r)];
+        if (r && q < (RB >> r) && iq < NB) T.wl[q] = tw[(iq & ((1 << logp) - 1)) << (logN - logp - r + shift)];
     }
     return T;
 }
@@ -282,6 +298,7 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const Fft
 {
     constexpr bool plain = std::is_same_v<Store, PlainStore>;
     constexpr bool plain_ld = std::is_same_v<Load, PlainLoad>;
+    constexpr bool reg_ld = is_reg_load<Load>::value;
     constexpr int lr = (RB == 16) ? 4 : 3;
     const int i = threadIdx.x;
     const int np = logN / lr;        // main passes (at most 4 for N <= 8192)
@@ -295,7 +312,15 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const Fft
         double2 u[RB];
         const int k = i & (p - 1);
         if (i < NB) {
-            if (!plain_ld && s == 0) {
+            if constexpr (reg_ld) {
+                if (s == 0) {
+#pragma unroll
+                    for (int t = 0; t < RB; ++t) u[t] = ld.f(t, i + t * NB);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < RB; ++t) u[t] = x[Pr<RB>(i + t * NB)];
+                }
+            } else if (!plain_ld && s == 0) {
 #pragma unroll
                 for (int t = 0; t < RB; ++t) u[t] = ld(i + t * NB);
             } else {
@@ -359,6 +384,57 @@ __device__ __forceinline__ void bluestein_core(double2* x, const Plan& p, const 
     block_fft<+1, RB>(x, p.N2, p.logN2, T, nullptr, st);
 }
 
+// Split plans (N2 = 2 NH larger than the LDS holds, L > 2048): the N2-point
+// transforms of a convolution run as two NH-point convolutions, one per parity
+// of the frequency index (decimation in frequency).  With w = exp(-2 pi i/N2)
+// and an input a_j that vanishes for j >= NH,
+//   even:  E = IFFT_NH( FFT_NH(a_j)      * K[2k'] )
+//   odd:   O = IFFT_NH( FFT_NH(a_j w^j)  * K[2k'+1] )
+//   y_n = E_n + w^{-n} O_n   (n < NH),
+// where K is the kernel spectrum, stored de-interleaved by the plan (even
+// frequencies first, then odd).  NH = RB * blockDim.x: each thread holds RB
+// values of a vector, those at j = threadIdx.x + q*blockDim.x.
+//
+// Bluestein DFT of length N1 <= NH on a split plan: lde(j) / ldo(j) (or
+// RegLoad forms) give the first-pass inputs a_j and a_j w^j; on return
+// x[Pr(n)] = y_n for n < NH, the same values bluestein_core leaves for n < N1.
+template <int RB, class LdE, class LdO>
+__device__ __forceinline__ void bluestein_split(double2* x, const Plan& p, const FftTw<RB>& T, const LdE& lde,
+                                                const LdO& ldo)
+{
+    const int NH = p.N2 >> 1, logNH = p.logN2 - 1;
+    block_fft<-1, RB>(x, NH, logNH, T, p.bhat, PlainStore(), lde);
+    block_fft<+1, RB>(x, NH, logNH, T);
+    double2 e[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) e[q] = x[Pr<RB>(threadIdx.x + q * blockDim.x)];
+    block_fft<-1, RB>(x, NH, logNH, T, p.bhat + NH, PlainStore(), ldo);   // begins with a barrier
+    block_fft<+1, RB>(x, NH, logNH, T);
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const int j = threadIdx.x + q * blockDim.x;
+        x[Pr<RB>(j)] = cadd(e[q], cmul(cconj(p.tw[j]), x[Pr<RB>(j)]));
+    }
+    __syncthreads();
+}
+
+// Twiddle bases of a kernel's FFTs: length N2, or NH = N2/2 on a split plan.
+template <int RB, bool SP>
+__device__ __forceinline__ FftTw<RB> plan_twiddles(const Plan& p)
+{
+    if constexpr (SP) return fft_twiddles<RB>(p.N2 >> 1, p.logN2 - 1, p.tw, 1);
+    else return fft_twiddles<RB>(p.N2, p.logN2, p.tw);
+}
+
+// Bluestein DFT of length N1 of the input ld(j) (zero for j >= N1) on either
+// kind of plan; on return x[Pr(k)] * chirp[k] = sum_j a_j exp(-2 pi i j k/N1), k < N1.
+template <int RB, bool SP, class Load>
+__device__ __forceinline__ void bluestein_any(double2* x, const Plan& p, const FftTw<RB>& T, const Load& ld)
+{
+    if constexpr (SP) bluestein_split<RB>(x, p, T, ld, [&](int j) { return cmul(ld(j), p.tw[j]); });
+    else bluestein_core<RB>(x, p, T, ld);
+}
+
 // XCD-aware column index: consecutive workgroups are dealt round-robin over the
 // 8 XCDs; give each XCD a contiguous range of columns so neighbouring columns
 // (which share cache lines of the row-major intermediates) meet in one L2.
@@ -375,7 +451,7 @@ __device__ __forceinline__ int xcd_column(int ncol)
 // Output order-major, G[m + L-1][t], so that the theta stage reads each order's
 // column as one contiguous row; rings are dealt to XCDs in contiguous ranges,
 // so the L2 of one XCD merges the partial lines that neighbouring rings write.
-template <int REAL, int RB>
+template <int REAL, int RB, bool SP>
 __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
 {
     extern __shared__ double2 A[];
@@ -385,11 +461,11 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
     const int t = xcd_column(L);
     if (t >= L) return;
     // twiddle bases of all FFTs below, read before the first pass (it needs none)
-    const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
+    const FftTw<RB> T = plan_twiddles<RB, SP>(p);
     // the ring's samples, chirped and zero-padded, read by the first pass; the
     // outputs are stored from LDS in batches (written straight from the last pass,
     // the stride-L stores of G were measured slower)
-    bluestein_core<RB>(A, p, T, [&](int j) {
+    bluestein_any<RB, SP>(A, p, T, [&](int j) {
         if (j >= N1) return make_double2(0.0, 0.0);
         const double2 a = REAL ? make_double2(((const double*)map)[(size_t)t * N1 + j], 0.0)
                                : ((const double2*)map)[(size_t)t * N1 + j];
@@ -421,7 +497,14 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
 // HALF = 1 (real scalar maps, Sec. IV-G): only the orders m >= 0 run; the map
 // being real, G_{-m}(theta) = conj(G_m(theta)) and hence H_{-m,n} =
 // (-1)^{m+s} conj(H_{m,n}), which order m writes into the -m half of its row.
-template <int ADJ_INV, int OUT32, int HALF, int RB>
+//
+// Split plans (L > 2048): the Bluestein step and the weight step run as pairs of
+// half-length convolutions (bluestein_split); the weight step's N2-grid input
+// lies in [0, L) (m' >= 0) and [N2 - L + 1, N2) (m' < 0), so its two halves do
+// not overlap and fold onto one half grid, and the fold of the output is split
+// in the same way: H_n = P_n + w^n O_n - (-1)^{m+s} w^{NH-n} O_{NH-n} with
+// P_n = E_n + (-1)^{m+s} E_{NH-n} from the even pass (P_0 = E_0, H_0 = P_0 + O_0).
+template <int ADJ_INV, int OUT32, int HALF, int RB, bool SP>
 __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
 {
     extern __shared__ double2 A[];
@@ -437,7 +520,7 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
     const int m = mi - (L - 1);
     const double sig = ((m + s) & 1) ? -1.0 : 1.0;
     // twiddle bases of all FFTs below, read before the first pass (it needs none)
-    const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
+    const FftTw<RB> T = plan_twiddles<RB, SP>(p);
     // the extended column (t < L as given, then (-1)^{m+s} times the mirror image;
     // the adjoint of the inverse has no extension), chirped and zero-padded
     auto ld = [&](int j) {
@@ -447,46 +530,9 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
         else if (!ADJ_INV) a = cscale(G[(size_t)mi * L + (2 * L - 2 - j)], sig);
         return cmul(a, p.chirp[j]);
     };
-    int wrap;   // index of -n is wrap - n
-    if constexpr (ADJ_INV) {
-        bluestein_core<RB>(A, p, T, ld);
-        // F_{m'} = chirp_k e^{-i m' pi/N1} times the Bluestein output, k < N1
-        double2 r[8];   // N1 <= N2/2 <= 8 * blockDim.x
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int k = threadIdx.x + q * blockDim.x;
-            if (k < N1) r[q] = cmul(A[Pr<RB>(k)], p.thwc[k]);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int k = threadIdx.x + q * blockDim.x;
-            if (k < N1) A[Pr<RB>(k)] = r[q];
-        }
-        __syncthreads();
-        wrap = N1;
-    } else {
-        // Bluestein with its last store fused with the move onto the N2 grid:
-        // output k < N1 is F_{m'} / (chirp_k e^{-i m' pi/N1} / (2 pi N1)) and goes to
-        // slot m' mod N2 (m' = k, or k - N1 for k >= L); outputs k >= N1 are not
-        // needed and their slots k - N1 + L fill the zeros in between (a bijection).
-        const double scale = p.thsc;
-        block_fft<-1, RB>(A, N2, p.logN2, T, p.bhat, PlainStore(), ld);
-        block_fft<+1, RB>(A, N2, p.logN2, T, nullptr, [&](int k, double2 v) {
-            if (k < N1) A[Pr<RB>(k < L ? k : k + (N2 - N1))] = cscale(cmul(v, p.thwc[k]), scale);
-            else A[Pr<RB>(k - N1 + L)] = make_double2(0.0, 0.0);
-        });
-        block_fft<+1, RB>(A, N2, p.logN2, T, p.what);
-        block_fft<-1, RB>(A, N2, p.logN2, T);
-        wrap = N2;
-    }
     const int am = m < 0 ? -m : m;
-    for (int n = threadIdx.x; n < p.Lp; n += blockDim.x) {
-        double2 v = make_double2(0.0, 0.0);
-        if (n < L) {
-            v = A[Pr<RB>(n)];
-            if (n > 0) v = cadd(v, cscale(A[Pr<RB>(wrap - n)], sig));
-        }
+    // output of order m for n < Lp (pad entry n = L of odd L: v = 0)
+    auto store = [&](int n, double2 v) {
         // the -m half: H_{-m,n} itself, or (-1)^{m+s} conj(H_{m,n}) for a real map
         const double2 vm = HALF ? cscale(cconj(v), sig) : v;
         const bool pos = m >= 0, neg = HALF || m <= 0;
@@ -508,6 +554,95 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
             if (pos) { rec[0] = v.x; rec[1] = v.y; }
             if (neg) { rec[2] = vm.x; rec[3] = vm.y; }
         }
+    };
+    if constexpr (SP && !ADJ_INV) {
+        const int NH = N2 >> 1, logNH = p.logN2 - 1;
+        const double scale = p.thsc;
+        bluestein_split<RB>(A, p, T, ld, [&](int j) { return cmul(ld(j), p.tw[j]); });
+        // the weight step's input on the half grid: F_{m'} for m' = j (j < L) and
+        // m' = j - NH (j > NH - L), Bluestein output k = j or j - NH + N1
+        double2 v[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int j = threadIdx.x + q * blockDim.x;
+            const int k = (j < L) ? j : (j > NH - L) ? j - NH + N1 : -1;
+            v[q] = (k >= 0) ? cscale(cmul(A[Pr<RB>(k)], p.thwc[k]), scale) : make_double2(0.0, 0.0);
+        }
+        // even frequencies (block_fft begins with a barrier: the reads above are done)
+        block_fft<+1, RB>(A, NH, logNH, T, p.what, PlainStore(), reg_load([&](int t, int) { return v[t]; }));
+        block_fft<-1, RB>(A, NH, logNH, T);
+        double2 P[RB / 2];   // n = threadIdx.x + q*blockDim.x < L <= NH/2
+#pragma unroll
+        for (int q = 0; q < RB / 2; ++q) {
+            const int n = threadIdx.x + q * blockDim.x;
+            P[q] = make_double2(0.0, 0.0);
+            if (n < L) {
+                P[q] = A[Pr<RB>(n)];
+                if (n > 0) P[q] = cadd(P[q], cscale(A[Pr<RB>(NH - n)], sig));
+            }
+        }
+        // odd frequencies: input (c_lo - c_hi)_j w^{-j}
+        block_fft<+1, RB>(A, NH, logNH, T, p.what + NH, PlainStore(), reg_load([&](int t, int j) {
+                              const double2 c = cmul(v[t], cconj(p.tw[j]));
+                              return (j < L) ? c : cscale(c, -1.0);
+                          }));
+        block_fft<-1, RB>(A, NH, logNH, T);
+#pragma unroll
+        for (int q = 0; q < RB / 2; ++q) {
+            const int n = threadIdx.x + q * blockDim.x;
+            if (n < p.Lp) {
+                double2 h = make_double2(0.0, 0.0);
+                if (n == 0) {
+                    h = cadd(P[q], A[Pr<RB>(0)]);
+                } else if (n < L) {
+                    h = cadd(P[q], cmul(p.tw[n], A[Pr<RB>(n)]));
+                    h = csub(h, cscale(cmul(p.tw[NH - n], A[Pr<RB>(NH - n)]), sig));
+                }
+                store(n, h);
+            }
+        }
+        return;
+    }
+    int wrap = N2;   // index of -n is wrap - n
+    if constexpr (ADJ_INV) {
+        bluestein_any<RB, SP>(A, p, T, ld);
+        // F_{m'} = chirp_k e^{-i m' pi/N1} times the Bluestein output, k < N1
+        constexpr int Q = SP ? RB : 8;   // N1 <= Q * blockDim.x
+        double2 r[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int k = threadIdx.x + q * blockDim.x;
+            if (k < N1) r[q] = cmul(A[Pr<RB>(k)], p.thwc[k]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int k = threadIdx.x + q * blockDim.x;
+            if (k < N1) A[Pr<RB>(k)] = r[q];
+        }
+        __syncthreads();
+        wrap = N1;
+    } else if constexpr (!SP) {
+        // Bluestein with its last store fused with the move onto the N2 grid:
+        // output k < N1 is F_{m'} / (chirp_k e^{-i m' pi/N1} / (2 pi N1)) and goes to
+        // slot m' mod N2 (m' = k, or k - N1 for k >= L); outputs k >= N1 are not
+        // needed and their slots k - N1 + L fill the zeros in between (a bijection).
+        const double scale = p.thsc;
+        block_fft<-1, RB>(A, N2, p.logN2, T, p.bhat, PlainStore(), ld);
+        block_fft<+1, RB>(A, N2, p.logN2, T, nullptr, [&](int k, double2 v) {
+            if (k < N1) A[Pr<RB>(k < L ? k : k + (N2 - N1))] = cscale(cmul(v, p.thwc[k]), scale);
+            else A[Pr<RB>(k - N1 + L)] = make_double2(0.0, 0.0);
+        });
+        block_fft<+1, RB>(A, N2, p.logN2, T, p.what);
+        block_fft<-1, RB>(A, N2, p.logN2, T);
+    }
+    for (int n = threadIdx.x; n < p.Lp; n += blockDim.x) {
+        double2 v = make_double2(0.0, 0.0);
+        if (n < L) {
+            v = A[Pr<RB>(n)];
+            if (n > 0) v = cadd(v, cscale(A[Pr<RB>(wrap - n)], sig));
+        }
+        store(n, v);
     }
 }
 
@@ -520,7 +655,11 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
 //   fold     G_m(theta_t) = Gext(theta_t) + (-1)^{m+s} Gext(theta_{2L-2-t}), t < L-1;
 //            G_m(theta_{L-1}) = Gext(theta_{L-1})
 // Output G[t][m + L-1] (the layout the inverse phi stage reads).
-template <int RB>
+// Split plans (L > 2048): the correlation runs as its even- and odd-frequency
+// halves on the half grid (see k_theta_forward), its output at slot j of the half
+// grid being E_j + w^j O_j (m' = j >= 0) or E_j - w^j O_j (m' = j - NH < 0), and
+// the Bluestein step as bluestein_split on inputs held in registers.
+template <int RB, bool SP>
 __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
 {
     extern __shared__ double2 A[];
@@ -532,6 +671,59 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
     if (mi >= N1) return;
     const int m = mi - (L - 1);
     const double sig = ((m + s) & 1) ? -1.0 : 1.0;
+    auto finish = [&]() {   // the Bluestein output in A: fold back onto t < L
+        staged_loop(
+            L, [&](int t) { return Pair2{p.chirp[t], p.chirp[2 * L - 2 - t]}; },
+            [&](int t, const Pair2& c) {
+                double2 v = cconj(cmul(A[Pr<RB>(t)], c.a));
+                if (t <= L - 2) v = cadd(v, cscale(cconj(cmul(A[Pr<RB>(2 * L - 2 - t)], c.b)), sig));
+                Gt[(size_t)t * N1 + mi] = v;
+            });
+    };
+    if constexpr (SP) {
+        const int NH = N2 >> 1, logNH = p.logN2 - 1;
+        const FftTw<RB> T = plan_twiddles<RB, SP>(p);
+        // the unfolded Y on the half grid: m' = j (j < L) or j - NH (j > NH - L)
+        auto ldY = [&](int j) {
+            const int mp = (j < L) ? j : (j > NH - L) ? j - NH : NH;
+            if (mp == NH) return make_double2(0.0, 0.0);
+            const double2 y = Y[(size_t)mi * L + (mp < 0 ? -mp : mp)];
+            return (mp < 0) ? cscale(y, sig) : y;
+        };
+        block_fft<+1, RB>(A, NH, logNH, T, p.whatc, PlainStore(), ldY);
+        block_fft<-1, RB>(A, NH, logNH, T);
+        double2 e[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) e[q] = A[Pr<RB>(threadIdx.x + q * blockDim.x)];
+        block_fft<+1, RB>(A, NH, logNH, T, p.whatc + NH, PlainStore(), [&](int j) {
+            const double2 c = cmul(ldY(j), cconj(p.tw[j]));
+            return (j < L) ? c : cscale(c, -1.0);
+        });
+        block_fft<-1, RB>(A, NH, logNH, T);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int j = threadIdx.x + q * blockDim.x;
+            const double2 o = cmul(p.tw[j], A[Pr<RB>(j)]);
+            A[Pr<RB>(j)] = (j < L) ? cadd(e[q], o) : csub(e[q], o);
+        }
+        __syncthreads();
+        // Z_{m''} conj(thtw), conjugated and chirped (the Bluestein input, k < N1)
+        double2 r[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int k = threadIdx.x + q * blockDim.x;
+            r[q] = make_double2(0.0, 0.0);
+            if (k < N1) {
+                const int mp = (k <= L - 1) ? k : k - N1;
+                const double2 y = cmul(A[Pr<RB>((mp + NH) & (NH - 1))], cconj(p.thtw[k]));
+                r[q] = cmul(cconj(y), p.chirp[k]);
+            }
+        }
+        bluestein_split<RB>(A, p, T, reg_load([&](int t, int) { return r[t]; }),
+                            reg_load([&](int t, int j) { return cmul(r[t], p.tw[j]); }));
+        finish();
+        return;
+    }
     for (int j = threadIdx.x; j < N2; j += blockDim.x) A[Pr<RB>(j)] = make_double2(0.0, 0.0);
     __syncthreads();
     staged_loop(
@@ -568,13 +760,7 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
     }
     for (int j = threadIdx.x + 8 * blockDim.x; j < N2; j += blockDim.x) A[Pr<RB>(j)] = make_double2(0.0, 0.0);
     bluestein_core<RB>(A, p, T);
-    staged_loop(
-        L, [&](int t) { return Pair2{p.chirp[t], p.chirp[2 * L - 2 - t]}; },
-        [&](int t, const Pair2& c) {
-            double2 v = cconj(cmul(A[Pr<RB>(t)], c.a));
-            if (t <= L - 2) v = cadd(v, cscale(cconj(cmul(A[Pr<RB>(2 * L - 2 - t)], c.b)), sig));
-            Gt[(size_t)t * N1 + mi] = v;
-        });
+    finish();
 }
 
 // Inverse theta stage for order m (Sec. IV-E, Eq.(Fmt)):
@@ -583,7 +769,7 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
 // Output Ft[t][m + L-1].
 // HALF = 1 (real scalar maps): only the orders m >= 0 run; the inverse phi stage
 // takes F_{-m}(theta) = conj(F_m(theta)).
-template <int HALF, int RB>
+template <int HALF, int RB, bool SP>
 __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
 {
     extern __shared__ double2 A[];
@@ -596,19 +782,24 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
     const int m = mi - (L - 1);
     const double sig = ((m + s) & 1) ? -1.0 : 1.0;
     // twiddle bases of all FFTs below, read before the first pass (it needs none)
-    const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
-    bluestein_core<RB>(
-        A, p, T,
-        [&](int j) {   // the unfolded F_{mm'}, m' = j or j - N1, as conj(f e^{+i m' pi/N1}) chirp_j
-            if (j >= N1) return make_double2(0.0, 0.0);
-            const int mp = (j <= L - 1) ? j : j - N1;
-            double2 f = F[(size_t)mi * L + (mp < 0 ? -mp : mp)];
-            if (mp < 0) f = cscale(f, sig);
-            return cmul(cconj(f), p.thwc[j]);   // thwc_j = e^{-i m' pi/N1} chirp_j
-        },
-        [&](int t, double2 v) {   // outputs t < L, straight to Ft
+    const FftTw<RB> T = plan_twiddles<RB, SP>(p);
+    auto ld = [&](int j) {   // the unfolded F_{mm'}, m' = j or j - N1, as conj(f e^{+i m' pi/N1}) chirp_j
+        if (j >= N1) return make_double2(0.0, 0.0);
+        const int mp = (j <= L - 1) ? j : j - N1;
+        double2 f = F[(size_t)mi * L + (mp < 0 ? -mp : mp)];
+        if (mp < 0) f = cscale(f, sig);
+        return cmul(cconj(f), p.thwc[j]);   // thwc_j = e^{-i m' pi/N1} chirp_j
+    };
+    if constexpr (SP) {
+        bluestein_split<RB>(A, p, T, ld, [&](int j) { return cmul(ld(j), p.tw[j]); });
+        staged_loop(
+            L, [&](int t) { return p.chirp[t]; },
+            [&](int t, double2 c) { Ft[(size_t)t * N1 + mi] = cconj(cmul(A[Pr<RB>(t)], c)); });
+    } else {
+        bluestein_core<RB>(A, p, T, ld, [&](int t, double2 v) {   // outputs t < L, straight to Ft
             if (t < L) Ft[(size_t)t * N1 + mi] = cconj(cmul(v, p.chirp[t]));
         });
+    }
 }
 
 // Inverse phi stage (Eq.(f_pfft)): f(t, p) = sc sum_m F_m(theta_t) e^{i m phi_p}, with
@@ -616,7 +807,7 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
 // (whose phi step is the conjugate transpose of the forward's).  REAL = 1 stores
 // Re f; REAL = 2 (real scalar maps) reads the orders m >= 0 only, takes
 // F_{-m} = conj(F_m) and stores f, which is then real.
-template <int REAL, int RB>
+template <int REAL, int RB, bool SP>
 __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
 {
     extern __shared__ double2 A[];
@@ -626,45 +817,61 @@ __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
     const int t = xcd_column(L);
     if (t >= L) return;
     // twiddle bases of all FFTs below, read before the first pass (it needs none)
-    const FftTw<RB> T = fft_twiddles<RB>(p.N2, p.logN2, p.tw);
-    bluestein_core<RB>(
-        A, p, T,
-        [&](int j) {   // conj(F_m) chirp_j, m = j or j - N1 (F_m = conj(F_{-m}) for REAL = 2)
-            if (j >= N1) return make_double2(0.0, 0.0);
-            const int m = (j <= L - 1) ? j : j - N1;
-            const double2 a = Ft[(size_t)t * N1 + ((REAL == 2 && m < 0 ? -m : m) + L - 1)];
-            const bool neg = REAL == 2 && m < 0;
-            return cmul(neg ? a : cconj(a), p.chirp[j]);
-        },
-        [&](int k, double2 v) {   // outputs k < N1, straight to the map
-            if (k < N1) {
-                const double2 out = cscale(cconj(cmul(v, p.chirp[k])), sc);
-                if (REAL) ((double*)map)[(size_t)t * N1 + k] = out.x;
-                else ((double2*)map)[(size_t)t * N1 + k] = out;
-            }
+    const FftTw<RB> T = plan_twiddles<RB, SP>(p);
+    auto ld = [&](int j) {   // conj(F_m) chirp_j, m = j or j - N1 (F_m = conj(F_{-m}) for REAL = 2)
+        if (j >= N1) return make_double2(0.0, 0.0);
+        const int m = (j <= L - 1) ? j : j - N1;
+        const double2 a = Ft[(size_t)t * N1 + ((REAL == 2 && m < 0 ? -m : m) + L - 1)];
+        const bool neg = REAL == 2 && m < 0;
+        return cmul(neg ? a : cconj(a), p.chirp[j]);
+    };
+    auto put = [&](int k, double2 v) {   // output k < N1 (v before the chirp)
+        const double2 out = cscale(cconj(cmul(v, p.chirp[k])), sc);
+        if (REAL) ((double*)map)[(size_t)t * N1 + k] = out.x;
+        else ((double2*)map)[(size_t)t * N1 + k] = out;
+    };
+    if constexpr (SP) {
+        bluestein_split<RB>(A, p, T, ld, [&](int j) { return cmul(ld(j), p.tw[j]); });
+        for (int k = threadIdx.x; k < N1; k += blockDim.x) put(k, A[Pr<RB>(k)]);
+    } else {
+        bluestein_core<RB>(A, p, T, ld, [&](int k, double2 v) {   // outputs k < N1, straight to the map
+            if (k < N1) put(k, v);
         });
+    }
 }
 
 // Main radix of the FFTs for a plan.  It depends on the band-limit only, so a
 // map's result does not depend on the batch it runs in.  Radix 8 runs twice the
 // threads per transform of radix 16 for the same work; both keep a workgroup
-// within the kernels' 512-thread launch bound (radix 8 up to N2 = 4096).
-int fft_radix(const Plan& p, long nblocks)
+// within the kernels' 512-thread launch bound (radix 8 up to N2 = 4096).  Split
+// plans (N2 above the 8192-point transforms the LDS holds) run their
+// half-length transforms in radix 16 with one butterfly per thread, NH / 16
+// threads (512 at L = 4096; every thread holds RB values of a half-length vector).
+bool fft_split(const Plan& p) { return p.split; }
+
+int fft_radix(const Plan& p)
 {
-    (void)nblocks;
+    if (fft_split(p)) return 16;
     return (p.N2 / 8 <= 512) ? 8 : 16;
 }
 
-// Threads per FFT workgroup: one main-pass butterfly each (N2/rb <= 512, the
-// kernels' launch bound), at least one wavefront.
+// Length of the transforms a kernel runs in LDS: N2, or N2/2 on a split plan.
+int fft_len(const Plan& p) { return fft_split(p) ? p.N2 / 2 : p.N2; }
+
+// Threads per FFT workgroup: one main-pass butterfly each (length/rb <= 512,
+// the kernels' launch bound), at least one wavefront.
 int fft_threads(const Plan& p, int rb)
 {
-    int t = p.N2 / rb;
+    int t = fft_len(p) / rb;
     if (t < 64) t = 64;
     return t;
 }
 
-size_t fft_lds(const Plan& p, int rb) { return (size_t)(p.N2 + (rb == 8 ? 0 : p.N2 / rb)) * sizeof(double2); }
+size_t fft_lds(const Plan& p, int rb)
+{
+    const int n = fft_len(p);
+    return (size_t)(n + (rb == 8 ? 0 : n / rb)) * sizeof(double2);
+}
 
 template <class K>
 hipError_t set_lds(K kernel, size_t bytes)
@@ -675,29 +882,37 @@ hipError_t set_lds(K kernel, size_t bytes)
 
 int xcd_grid(int ncol) { return 8 * ((ncol + 7) >> 3); }
 
-// Launches kernel K<RB> with the radix chosen for this grid.
-template <template <int> class KS, class... Args>
-hipError_t fft_launch(const Plan& p, dim3 grid, hipStream_t st, Args... args)
+template <class K, class... Args>
+hipError_t fft_go(K k, const Plan& p, int rb, dim3 grid, hipStream_t st, Args... args)
 {
-    const int rb = fft_radix(p, (long)grid.x * grid.y);
     hipError_t e;
-    if (rb == 16) {
-        auto k = KS<16>::fn();
-        if ((e = set_lds(k, fft_lds(p, 16))) != hipSuccess) return e;
-        hipLaunchKernelGGL(k, grid, dim3(fft_threads(p, 16)), fft_lds(p, 16), st, args...);
-    } else {
-        auto k = KS<8>::fn();
-        if ((e = set_lds(k, fft_lds(p, 8))) != hipSuccess) return e;
-        hipLaunchKernelGGL(k, grid, dim3(fft_threads(p, 8)), fft_lds(p, 8), st, args...);
-    }
+    if ((e = set_lds(k, fft_lds(p, rb))) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, grid, dim3(fft_threads(p, rb)), fft_lds(p, rb), st, args...);
     return hipGetLastError();
 }
 
-template <int REAL> struct PhiF { template <int RB> struct K { static auto fn() { return k_phi_forward<REAL, RB>; } }; };
-template <int REAL> struct PhiI { template <int RB> struct K { static auto fn() { return k_phi_inverse<REAL, RB>; } }; };
-template <int A, int O, int H> struct ThF { template <int RB> struct K { static auto fn() { return k_theta_forward<A, O, H, RB>; } }; };
-template <int H> struct ThI { template <int RB> struct K { static auto fn() { return k_theta_inverse<H, RB>; } }; };
-template <int RB> struct ThFA { static auto fn() { return k_theta_forward_adjoint<RB>; } };
+// Launches kernel K<RB, SP> with the radix and split mode of the plan.
+template <template <int, bool> class KS, class... Args>
+hipError_t fft_launch(const Plan& p, dim3 grid, hipStream_t st, Args... args)
+{
+    if (fft_split(p)) return fft_go(KS<16, true>::fn(), p, 16, grid, st, args...);
+    if (fft_radix(p) == 16) return fft_go(KS<16, false>::fn(), p, 16, grid, st, args...);
+    return fft_go(KS<8, false>::fn(), p, 8, grid, st, args...);
+}
+
+template <int REAL> struct PhiF {
+    template <int RB, bool SP> struct K { static auto fn() { return k_phi_forward<REAL, RB, SP>; } };
+};
+template <int REAL> struct PhiI {
+    template <int RB, bool SP> struct K { static auto fn() { return k_phi_inverse<REAL, RB, SP>; } };
+};
+template <int A, int O, int H> struct ThF {
+    template <int RB, bool SP> struct K { static auto fn() { return k_theta_forward<A, O, H, RB, SP>; } };
+};
+template <int H> struct ThI {
+    template <int RB, bool SP> struct K { static auto fn() { return k_theta_inverse<H, RB, SP>; } };
+};
+template <int RB, bool SP> struct ThFA { static auto fn() { return k_theta_forward_adjoint<RB, SP>; } };
 
 }  // namespace
 

@@ -35,6 +35,9 @@ __host__ __device__ inline size_t tri_m(int m, int l, int L)
 struct Plan {
     int L = 0, N1 = 0, N2 = 0, logN2 = 0;
     int Lp = 0;              // L rounded up to even (row length of the forward H layout)
+    // The Fourier kernels run their N2-point transforms as pairs of N2/2-point
+    // ones (N2 above what the LDS holds, or forced by mw_profile_split_fft).
+    bool split = false;
     bool ext = false;        // some start value needs the exponent extension
     // Wigner tables
     double* rtab = nullptr;     // rtab[j] = 1/sqrt(j-1) for j >= 2, rtab[0] = rtab[1] = 0; 2L+8 entries
@@ -50,6 +53,8 @@ struct Plan {
     // Fourier tables
     double2* tw = nullptr;      // exp(-2 pi i e/N2), e < N2
     double2* chirp = nullptr;   // exp(-i pi j^2/N1), j < N1
+    // The three spectra below are stored in frequency order, or for split plans
+    // even frequencies first, then odd ones (the half-length convolutions).
     double2* bhat = nullptr;    // FFT_N2 of the Bluestein kernel, divided by N2
     double2* what = nullptr;    // (2 pi/N2) * DFT_N2 of the theta weights w(k)
     double2* whatc = nullptr;   // conj(what), for the adjoint of the weight step
@@ -131,6 +136,9 @@ struct Batch {
     int n;
 };
 
+// Smallest N2 whose plans are split (plan_split_min): 16384 by default; 2048
+// under the test hook mw_profile_split_fft(1).
+extern int g_split_min_n2;
 int build_plan(int L, Plan& p, std::string& err);
 void free_plan(Plan& p);
 int build_spin_table(const Plan& p, int as, SpinTable& t, std::string& err);

@@ -145,6 +145,18 @@ int upload(const std::vector<T>& h, T** d, size_t& bytes, std::string& err)
 
 static std::vector<int4> forward_work(const Plan& p);   // below
 
+int g_split_min_n2 = 16384;
+
+// Slot of frequency j in the stored kernel spectra (bhat, what, whatc): j
+// itself, or on a split plan (N2 larger than the 8192-point transforms the LDS
+// holds, L > 2048) the de-interleaved order [even j | odd j] that the
+// half-length convolutions of the Fourier kernels read.
+static int spectrum_slot(int j, int N2, bool split)
+{
+    if (!split) return j;
+    return (j & 1) ? N2 / 2 + (j >> 1) : (j >> 1);
+}
+
 // Chain segmentation for band-limit L: up to smax waves of a workgroup share
 // each chain, in segments of seg (a multiple of 64) degrees or rows, nseg of
 // them over the whole range; false if more than smax would be needed.
@@ -176,6 +188,7 @@ int build_plan(int L, Plan& p, std::string& err)
     p.N2 = std::max(16, next_pow2(4 * L - 3));
     p.logN2 = 0;
     while ((1 << p.logN2) < p.N2) ++p.logN2;
+    p.split = p.N2 >= g_split_min_n2;
     const int N1 = p.N1, N2 = p.N2;
     int rc;
 
@@ -266,7 +279,7 @@ int build_plan(int L, Plan& p, std::string& err)
     std::vector<double2> bh(N2);
     for (int j = 0; j < N2; ++j) {
         cld v = bv[j] / (ld)N2;
-        bh[j] = make_double2((double)v.real(), (double)v.imag());
+        bh[(size_t)spectrum_slot(j, N2, p.split)] = make_double2((double)v.real(), (double)v.imag());
     }
     if ((rc = upload(bh, &p.bhat, p.bytes, err))) return rc;
 
@@ -285,7 +298,7 @@ int build_plan(int L, Plan& p, std::string& err)
     std::vector<double2> wh(N2);
     for (int j = 0; j < N2; ++j) {
         cld v = wv[j] * (2.0L * PI_L / (ld)N2);
-        wh[j] = make_double2((double)v.real(), (double)v.imag());
+        wh[(size_t)spectrum_slot(j, N2, p.split)] = make_double2((double)v.real(), (double)v.imag());
     }
     if ((rc = upload(wh, &p.what, p.bytes, err))) return rc;
     for (auto& v : wh) v.y = -v.y;   // conjugate spectrum, for the adjoint's correlation

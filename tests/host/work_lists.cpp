@@ -177,7 +177,8 @@ int main()
 {
     std::vector<int> Ls;
     for (int L = 1; L <= 260; ++L) Ls.push_back(L);
-    for (int L : {300, 383, 384, 511, 512, 513, 640, 901, 1000, 1024, 1500, 2047, 2048}) Ls.push_back(L);
+    for (int L : {300, 383, 384, 511, 512, 513, 640, 901, 1000, 1024, 1500, 2047, 2048, 2049, 3001, 4095, 4096})
+        Ls.push_back(L);
     long cases = 0;
     for (int L : Ls) {
         check_forward(L);

@@ -51,7 +51,7 @@ def _raw(name, Ls, spins, reals, batch=None, ptrs=True, prec=0):
                                   "mw_inverse_adjoint"])
 @pytest.mark.parametrize("Ls,spins,reals,batch,ptrs,prec", [
     ([0], [0], [0], None, True, 0),          # L < 1
-    ([2049], [0], [0], None, True, 0),       # L > 2048
+    ([4097], [0], [0], None, True, 0),       # L > MW_LMAX = 4096
     ([8], [8], [0], None, True, 0),          # |s| >= L
     ([8], [-8], [0], None, True, 0),
     ([8], [2], [1], None, True, 0),          # reality needs s = 0
