@@ -56,6 +56,8 @@ def _load():
             "orc_forward_adjoint": (I, [I, I, D, D]),
             "orc_inverse_adjoint": (I, [I, I, D, D]),
             "orc_row_plain": (I, [I, I, D]),
+            "orc_quad_weights": (I, [I, I, D]),
+            "orc_integrate": (I, [I, I, I, D, D]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(lib, name)
@@ -202,3 +204,23 @@ def row_plain(l: int, m: int) -> np.ndarray:
     out = np.zeros(l + 1)
     _check(_load().orc_row_plain(l, m, _dp(out)), "row_plain")
     return out
+
+
+def quad_weights(L: int, s: int) -> np.ndarray:
+    """Weights q(theta_t), t < L, of the explicit quadrature Eq.(quadrature)
+    (complex as evaluated; the imaginary part vanishes up to rounding)."""
+    out = np.zeros(L, dtype=np.complex128)
+    _check(_load().orc_quad_weights(L, s, _dp(out.view(np.float64))), "quad_weights")
+    return out
+
+
+def integrate(f, L: int, s: int) -> complex:
+    """Integral of a map over the sphere by Eq.(quadrature): f of shape (L, L)
+    (the rule's grid, phi'_p = 2 pi p/L) or (L, 2L-1) (the transform grid)."""
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.complex128))
+    if f.ndim != 2 or f.shape[0] != L or f.shape[1] not in (L, 2 * L - 1):
+        raise ValueError("map must have shape (L, L) or (L, 2L-1)")
+    out = np.zeros(1, dtype=np.complex128)
+    _check(_load().orc_integrate(L, s, f.shape[1], _dp(f.view(np.float64)), _dp(out.view(np.float64))),
+           "integrate")
+    return complex(out[0])

@@ -651,3 +651,56 @@ int orc_row_plain(int l, int m, double* out)
     }
     return 0;
 }
+
+/* ======================================================================== */
+/* Explicit quadrature (Sec. IV-F, Eq.(quadrature)).                          */
+/* ======================================================================== */
+/* wtilde(theta_t) = 1/(2L-1) sum_{m'=-(L-1)}^{L-1} w(-m') e^{i m' theta_t}
+ * (the inverse DFT of the reflected weights), and the weights
+ *   q(theta_t) = (2 pi/L) [wtilde(theta_t) + (1 - delta_{t,L-1}) (-1)^s wtilde(theta_{2L-2-t})],
+ * t < L (the contributions of (pi, 2 pi) folded back onto [0, pi]).
+ * q_ri[2t], q_ri[2t+1] = Re, Im of q(theta_t); the imaginary part vanishes up
+ * to rounding (w(-m') and w(m') are conjugate). */
+static cplx wtilde(int L, int t)
+{
+    const int N1 = 2 * L - 1;
+    cplx acc = 0.0;
+    for (int mp = -(L - 1); mp <= L - 1; ++mp)
+        acc += weight(-mp) * conj(unit_root((long long)mp * (2 * t + 1), 2LL * N1));
+    return acc / (double)N1;
+}
+
+int orc_quad_weights(int L, int s, double* q_ri)
+{
+    if (check_args(L, s) || !q_ri) return -1;
+    cplx* q = (cplx*)q_ri;
+    for (int t = 0; t < L; ++t) {
+        cplx v = wtilde(L, t);
+        if (t != L - 1) v += sgn(s) * wtilde(L, 2 * L - 2 - t);
+        q[t] = (2.0 * PI / L) * v;
+    }
+    return 0;
+}
+
+/* I = sum_{t<L} sum_{p<nphi} f(theta_t, 2 pi p/nphi) q(theta_t) (L/nphi).
+ * nphi = L is the paper's rule (phi'_p = 2 pi p/L, L(L-1)+1 distinct samples);
+ * nphi = 2L-1 applies the same theta weights on the transform grid, the phi
+ * sum (2 pi/nphi) sum_p being the exact phi integral of a band-limited ring for
+ * either nphi.  f: [t][p] complex, L x nphi.  out_ri: Re, Im of I. */
+int orc_integrate(int L, int s, int nphi, const double* f_ri, double* out_ri)
+{
+    if (check_args(L, s) || (nphi != L && nphi != 2 * L - 1) || !f_ri || !out_ri) return -1;
+    const cplx* f = (const cplx*)f_ri;
+    cplx* q = (cplx*)malloc(sizeof(cplx) * (size_t)L);
+    if (!q) return -2;
+    orc_quad_weights(L, s, (double*)q);
+    cplx acc = 0.0;
+    for (int t = 0; t < L; ++t) {
+        cplx ring = 0.0;
+        for (int p = 0; p < nphi; ++p) ring += f[(size_t)t * nphi + p];
+        acc += ring * creal(q[t]);
+    }
+    *(cplx*)out_ri = acc * ((double)L / (double)nphi);
+    free(q);
+    return 0;
+}

@@ -320,3 +320,65 @@ def test_plain_row_recursion_fails_at_large_l(orc):
     row0 = orc.row_plain(l, 3)  # start ~ l^-1/4 is representable: row stays unitary
     norm0 = row0[0] ** 2 + 2 * np.sum(row0[1:] ** 2)
     assert abs(norm0 - 1.0) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Explicit quadrature (Sec. IV-F, Eq.(quadrature))
+# --------------------------------------------------------------------------
+def _synth_on(flm, L, s, theta, phi):
+    """Brute-force synthesis sum_lm f_lm sY_lm on an arbitrary product grid."""
+    TH, PH = np.meshgrid(theta, phi, indexing="ij")
+    f = np.zeros(TH.shape, dtype=np.complex128)
+    for l in range(abs(s), L):
+        for m in range(-l, l + 1):
+            c = flm[l * l + l + m]
+            if c != 0:
+                f += c * brute.spin_harmonic(l, m, s, TH, PH)
+    return f
+
+
+def _exact_integral(flm, L, s):
+    """int dOmega sum_lm f_lm sY_lm: only m = 0 survives the phi integral (2 pi);
+    the theta integral of sin(theta) sY_l0(theta, 0) by 120-point Gauss-Legendre
+    in theta on [0, pi] (smooth integrand, converged to rounding)."""
+    x, w = np.polynomial.legendre.leggauss(120)
+    th = 0.5 * np.pi * (x + 1.0)
+    wt = 0.5 * np.pi * w
+    tot = 0.0
+    for l in range(abs(s), L):
+        y = brute.spin_harmonic(l, 0, s, th, np.zeros_like(th))
+        tot += flm[l * l + l] * 2.0 * np.pi * np.sum(wt * np.sin(th) * y)
+    return tot
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 8, 33])
+def test_quadrature_weights_integrate_one(orc, L):
+    # f = 1: L rings of L samples, sum_t L q_t = 4 pi; the weights are real
+    q = orc.quad_weights(L, 0)
+    assert abs(L * q.real.sum() - 4 * np.pi) < 1e-13
+    assert np.abs(q.imag).max() < 1e-15
+    assert np.allclose(orc.integrate(np.ones((L, L)), L, 0), 4 * np.pi, rtol=1e-14, atol=0)
+    assert np.allclose(orc.integrate(np.ones((L, 2 * L - 1)), L, 0), 4 * np.pi, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("L", [2, 3, 5, 8])
+def test_quadrature_exact_for_band_limited_scalar(orc, L):
+    # int Y_lm dOmega = sqrt(4 pi) delta_l0 delta_m0, so I = sqrt(4 pi) f_00
+    flm = mwsynth.flm_gaussian(L, 0, seed=900 + L)
+    theta = np.pi * (2 * np.arange(L) + 1) / (2 * L - 1)
+    for nphi in (L, 2 * L - 1):
+        f = _synth_on(flm, L, 0, theta, 2 * np.pi * np.arange(nphi) / nphi)
+        got = orc.integrate(f, L, 0)
+        assert abs(got - math.sqrt(4 * np.pi) * flm[0]) < 1e-13 * np.abs(flm).max(), nphi
+
+
+@pytest.mark.parametrize("L,s", [(4, 1), (5, 2), (6, -3), (7, 2)])
+def test_quadrature_exact_for_band_limited_spin(orc, L, s):
+    # spin-s maps: the rule reproduces int dOmega f, computed independently
+    flm = mwsynth.flm_gaussian(L, s, seed=950 + L)
+    theta = np.pi * (2 * np.arange(L) + 1) / (2 * L - 1)
+    ref = _exact_integral(flm, L, s)
+    assert abs(ref) > 1e-3
+    for nphi in (L, 2 * L - 1):
+        f = _synth_on(flm, L, s, theta, 2 * np.pi * np.arange(nphi) / nphi)
+        assert abs(orc.integrate(f, L, s) - ref) < 1e-13 * np.abs(flm).max(), nphi
