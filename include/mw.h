@@ -142,6 +142,33 @@ int mw_forward_adjoint(const int32_t* L, const int32_t* spin, const int32_t* rea
 int mw_inverse_adjoint(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                        void* const* ptrs, int32_t precision, void* stream);
 
+/* Explicit quadrature (Sec. IV-F, Eq.(quadrature)): the weights
+ *   q(theta_t) = (2 pi/L) [wt(theta_t) + (1 - delta_{t,L-1}) (-1)^s wt(theta_{2L-2-t})],
+ *   wt(theta_t) = 1/(2L-1) sum_{m'=-(L-1)}^{L-1} w(-m') e^{i m' theta_t},
+ * t < L, with the weights w of the theta convolution (Sec. IV-D), written to the
+ * DEVICE array q (L doubles).  Validation as for the transforms (1 <= L <=
+ * MW_LMAX, |spin| < L, q non-NULL), else MW_EINVAL.  Enqueued on `stream`. */
+int mw_quadrature_weights(int32_t L, int32_t spin, double* q, void* stream);
+
+/* Sampling grids of mw_integrate. */
+#define MW_GRID_QUADRATURE 0   /* the rule's grid: L rings of L samples, phi'_p = 2 pi p/L */
+#define MW_GRID_TRANSFORM 1    /* the transforms' grid: L rings of 2L-1 samples */
+
+/* Integral over the sphere of each map of a batch by the explicit quadrature
+ * (Sec. IV-F): I = sum_{t<L} sum_{p<nphi} f(theta_t, 2 pi p/nphi) q(theta_t) L/nphi,
+ * exact for maps band-limited at L (for nphi = L this is Eq.(quadrature) itself;
+ * on the transform grid, nphi = 2L-1, the phi sum is the same exact phi
+ * integral of a band-limited ring).  ptrs[2b] = map, row-major [t][p] with
+ * nphi = L (MW_GRID_QUADRATURE) or 2L-1 (MW_GRID_TRANSFORM) samples per ring,
+ * complex128, or float64 when reality = 1; ptrs[2b+1] = one complex128, I.
+ * For spin maps the integral is that of the spin-s function as sampled.
+ * Validation as for the transforms (precision does not apply), grid one of the
+ * two values above, else MW_EINVAL.  Uses batch x L x 16 bytes of the workspace
+ * (the library's, or one bound with mw_set_workspace); enqueued on `stream`;
+ * the sums run in a fixed order (results do not depend on scheduling). */
+int mw_integrate(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch, void* const* ptrs,
+                 int32_t grid, void* stream);
+
 /* Bytes of workspace one call with these arguments needs (plan tables excluded).
  * A call whose maps form several chunks (see mw_prepare) runs them alternately
  * on two internal streams, each with its own half of the workspace. */

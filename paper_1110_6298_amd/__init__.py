@@ -18,7 +18,8 @@ import ctypes
 import os
 from typing import Sequence
 
-__all__ = ["forward", "inverse", "forward_noalloc", "forward_noalloc_batch", "forward_adjoint", "inverse_adjoint", "forward_batch",
+__all__ = ["forward", "inverse", "forward_noalloc", "forward_noalloc_batch", "quadrature_weights", "integrate",
+           "integrate_batch", "forward_adjoint", "inverse_adjoint", "forward_batch",
            "inverse_batch", "forward_adjoint_batch", "inverse_adjoint_batch", "prepare", "release",
            "workspace_size", "set_workspace", "library", "MWError", "FP64", "FP32C", "EXPORTS", "LIB_PATH"]
 
@@ -26,7 +27,7 @@ FP64, FP32C = 0, 1
 _PREC = {"fp64": FP64, "fp32c": FP32C, FP64: FP64, FP32C: FP32C}
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmw.so")
-EXPORTS = ("mw_forward", "mw_forward_noalloc", "mw_inverse", "mw_forward_adjoint", "mw_inverse_adjoint",
+EXPORTS = ("mw_forward", "mw_forward_noalloc", "mw_inverse", "mw_quadrature_weights", "mw_integrate", "mw_forward_adjoint", "mw_inverse_adjoint",
            "mw_workspace_size", "mw_set_workspace", "mw_prepare", "mw_release", "mw_status_string",
            "mw_last_error", "mw_version")
 PROFILE_EXPORTS = ("mw_profile_enable", "mw_profile_read", "mw_profile_stage_name", "mw_profile_tuned_group",
@@ -57,6 +58,10 @@ def library():
             fn = getattr(lib, name)
             fn.restype = ctypes.c_int
             fn.argtypes = [i32p, i32p, i32p, ctypes.c_int32, vpp, ctypes.c_int32, ctypes.c_void_p]
+        lib.mw_quadrature_weights.restype = ctypes.c_int
+        lib.mw_quadrature_weights.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+        lib.mw_integrate.restype = ctypes.c_int
+        lib.mw_integrate.argtypes = [i32p, i32p, i32p, ctypes.c_int32, vpp, ctypes.c_int32, ctypes.c_void_p]
         lib.mw_workspace_size.restype = ctypes.c_int
         lib.mw_workspace_size.argtypes = [i32p, i32p, i32p, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_size_t)]
@@ -225,6 +230,55 @@ def forward_adjoint(y, L: int, spin: int = 0, reality: int = 0, precision=FP64, 
 def inverse_adjoint(g, L: int, spin: int = 0, reality: int = 0, precision=FP64, out=None, stream=None):
     """Conjugate transpose of the inverse map: grid (L, 2L-1) -> coefficients (L*L,)."""
     return inverse_adjoint_batch([g], [L], [spin], [reality], precision, [out], stream)[0]
+
+
+GRID_QUADRATURE, GRID_TRANSFORM = 0, 1
+
+
+def quadrature_weights(L: int, spin: int = 0, out=None, stream=None):
+    """Weights q(theta_t), t < L, of the explicit quadrature (float64, on cuda)."""
+    import torch
+    if out is None:
+        out = torch.empty(L, dtype=torch.float64, device="cuda")
+    _check_tensor(out, (L,), (torch.float64,), "q")
+    _check(library().mw_quadrature_weights(int(L), int(spin), ctypes.c_void_p(out.data_ptr()),
+                                           _stream_handle(stream)), "mw_quadrature_weights")
+    return out
+
+
+def integrate_batch(maps, Ls, spins, realities=None, outs=None, stream=None):
+    """Integrals over the sphere of a batch of maps by the explicit quadrature.
+    Each map has shape (L, L) (the rule's grid) or (L, 2L-1) (the transforms'
+    grid; all maps of one call on the same kind of grid); float64 when its
+    reality is 1, else complex128.  Returns complex128 tensors of shape (1,)."""
+    import torch
+    n = len(maps)
+    realities = [0] * n if realities is None else list(realities)
+    if not (len(Ls) == len(spins) == len(realities) == n) or n == 0:
+        raise ValueError("maps, Ls, spins and realities must have the same, nonzero length")
+    grid = GRID_QUADRATURE if maps[0].dim() == 2 and maps[0].shape[1] == int(Ls[0]) else GRID_TRANSFORM
+    outs = list(outs) if outs is not None else [None] * n
+    ptrs = []
+    for b in range(n):
+        L = int(Ls[b])
+        shp = (L, L) if grid == GRID_QUADRATURE else (L, 2 * L - 1)
+        dt = torch.float64 if realities[b] else torch.complex128
+        _check_tensor(maps[b], shp, (dt,), "map %d" % b)
+        if outs[b] is None:
+            outs[b] = torch.empty(1, dtype=torch.complex128, device=maps[b].device)
+        _check_tensor(outs[b], (1,), (torch.complex128,), "integral %d" % b)
+        ptrs += [maps[b].data_ptr(), outs[b].data_ptr()]
+    lib = library()
+    parr = (ctypes.c_void_p * (2 * n))(*[ctypes.c_void_p(int(p)) for p in ptrs])
+    _check(lib.mw_integrate(_arr(Ls), _arr(spins), _arr(realities), n,
+                            ctypes.cast(parr, ctypes.POINTER(ctypes.c_void_p)), grid, _stream_handle(stream)),
+           "mw_integrate")
+    return outs
+
+
+def integrate(f, L: int, spin: int = 0, reality: int = 0, stream=None):
+    """Integral over the sphere of one map (shape (L, L) or (L, 2L-1))."""
+    return integrate_batch([f], [L], [spin], [reality], None, stream)[0]
 
 
 def prepare(Ls, spins, realities=None, precision=FP64) -> None:

@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmw.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["mw_plan.cpp", "mw_api.cpp", "mw_fft.hip", "mw_contract.hip"]
+SOURCES = ["mw_plan.cpp", "mw_api.cpp", "mw_fft.hip", "mw_contract.hip", "mw_quad.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = [

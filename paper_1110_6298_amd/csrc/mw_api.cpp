@@ -588,6 +588,58 @@ int mw_inverse_adjoint(const int32_t* L, const int32_t* spin, const int32_t* rea
     return run(Op::InverseAdjoint, L, spin, reality, batch, ptrs, precision, stream);
 }
 
+int mw_quadrature_weights(int32_t L, int32_t spin, double* q, void* stream)
+{
+    if (L < 1 || L > MW_LMAX) return fail(MW_EINVAL, "L = %d outside [1, %d]", L, MW_LMAX);
+    if (spin <= -L || spin >= L) return fail(MW_EINVAL, "|spin| = %d must be < L = %d", spin, L);
+    if (!q) return fail(MW_EINVAL, "q must be non-NULL");
+    const hipError_t e = mw::launch_quad_weights(L, spin, q, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    g_last_error.clear();
+    return MW_OK;
+}
+
+int mw_integrate(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch, void* const* ptrs,
+                 int32_t grid, void* stream)
+{
+    int rc = validate(L, spin, reality, batch, ptrs, MW_FP64, true);
+    if (rc) return rc;
+    if (grid != MW_GRID_QUADRATURE && grid != MW_GRID_TRANSFORM)
+        return fail(MW_EINVAL, "grid must be MW_GRID_QUADRATURE or MW_GRID_TRANSFORM (got %d)", grid);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState& d = g_dev[dev];
+    // maps of equal (L, spin, reality) share a launch; the ring partials of a
+    // chunk (maps x L complex) live in the workspace
+    const std::vector<Chunk> chunks = make_chunks(L, spin, reality, batch, MW_FP64);
+    size_t need = 256;
+    for (const Chunk& c : chunks) need = std::max(need, c.maps.size() * (size_t)c.L * sizeof(double2) + 256);
+    void* ws = nullptr;
+    auto uw = d.user_ws.find(st);
+    if (uw != d.user_ws.end()) {
+        if (uw->second.second < need)
+            return fail(MW_ENOMEM, "the workspace set for this stream has %zu bytes, this call needs %zu",
+                        uw->second.second, need);
+        ws = uw->second.first;
+    } else if ((rc = get_ws(d, need, !capturing(st), &ws))) {
+        return rc;
+    }
+    double2* partial = (double2*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < chunks.size() && e == hipSuccess; ++i) {
+        const Chunk& c = chunks[i];
+        const int nphi = grid == MW_GRID_QUADRATURE ? c.L : 2 * c.L - 1;
+        const mw::Batch B = batch_of(c, [&](int k) { return (void*)ptrs[2 * c.maps[k]]; },
+                                     [&](int k) { return (void*)ptrs[2 * c.maps[k] + 1]; });
+        e = mw::launch_integrate(c.L, nphi, c.real, B, partial, st);
+    }
+    if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    g_last_error.clear();
+    return MW_OK;
+}
+
 int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                       int32_t precision, size_t* bytes)
 {

@@ -182,4 +182,11 @@ hipError_t launch_contract_forward_mix(const Plan& p, int s, const MixBatch& map
 hipError_t launch_contract_inverse_mix(const Plan& p, const SpinTable& sp, int s, const MixBatch& maps, int G,
                                        hipStream_t st);
 
+// Explicit quadrature (mw_quad.hip): the weights q(theta_t), t < L, into q
+// (device, L doubles); the integrals of the maps of B (B.in[k]: L x nphi map,
+// float64 when real, else complex128; B.out[k]: one complex128), with partial
+// (device, B.n * L complex) as scratch.
+hipError_t launch_quad_weights(int L, int s, double* q, hipStream_t st);
+hipError_t launch_integrate(int L, int nphi, int real, const Batch& B, double2* partial, hipStream_t st);
+
 }  // namespace mw
