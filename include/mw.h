@@ -142,6 +142,33 @@ int mw_forward_adjoint(const int32_t* L, const int32_t* spin, const int32_t* rea
 int mw_inverse_adjoint(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                        void* const* ptrs, int32_t precision, void* stream);
 
+/* Compact storage (Sec. IV-C): the sampling theorem needs N_MW = (L-1)(2L-1)+1
+ * samples, the south pole theta = pi being one point.  These four entry points
+ * take and return maps in that layout: rings t = 0..L-2 row-major as in the
+ * full layout ([t][p], 2L-1 samples each), then one sample C = f(pi, phi_0 = 0)
+ * at index (L-1)(2L-1) (the full layout truncated after that sample).  The
+ * pole ring of a band-limited spin-s map is C e^{i s phi_p}: at theta = pi only
+ * the order m = s survives (Sec. IV-B, the footnote on the poles), and
+ *   mw_forward_compact          = mw_forward of the full grid whose pole ring is
+ *                                 C e^{i s phi_p} (exact for band-limited maps);
+ *   mw_inverse_compact          = mw_inverse keeping the pole ring's p = 0 sample;
+ *   mw_forward_adjoint_compact  = adjoint of mw_forward_compact: the full
+ *                                 adjoint's rows, and sum_p e^{-i s phi_p} x(pi, phi_p)
+ *                                 as the pole sample;
+ *   mw_inverse_adjoint_compact  = adjoint of mw_inverse_compact: the full
+ *                                 adjoint of the map with the pole sample at p = 0
+ *                                 and zeros on the rest of that ring.
+ * Arguments, validation, coefficient layout, batching, streams and workspace as
+ * for the full-grid entry points (real maps: float64, s = 0, C real). */
+int mw_forward_compact(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                       void* const* ptrs, int32_t precision, void* stream);
+int mw_inverse_compact(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                       void* const* ptrs, int32_t precision, void* stream);
+int mw_forward_adjoint_compact(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                               void* const* ptrs, int32_t precision, void* stream);
+int mw_inverse_adjoint_compact(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                               void* const* ptrs, int32_t precision, void* stream);
+
 /* Explicit quadrature (Sec. IV-F, Eq.(quadrature)): the weights
  *   q(theta_t) = (2 pi/L) [wt(theta_t) + (1 - delta_{t,L-1}) (-1)^s wt(theta_{2L-2-t})],
  *   wt(theta_t) = 1/(2L-1) sum_{m'=-(L-1)}^{L-1} w(-m') e^{i m' theta_t},

@@ -224,3 +224,56 @@ def integrate(f, L: int, s: int) -> complex:
     _check(_load().orc_integrate(L, s, f.shape[1], _dp(f.view(np.float64)), _dp(out.view(np.float64))),
            "integrate")
     return complex(out[0])
+
+
+# --------------------------------------------------------------------------
+# Compact storage (Sec. IV-C): N_MW = (L-1)(2L-1)+1 samples, the south pole once.
+# The pole ring of a band-limited spin-s map is C e^{i s phi_p} with C = f(pi, 0)
+# (at theta = pi only the order m = s survives; footnote on the poles, Sec. IV-B).
+# --------------------------------------------------------------------------
+def _pole_phase(L: int, s: int) -> np.ndarray:
+    n1 = 2 * L - 1
+    k = (s * np.arange(n1)) % n1
+    return np.exp(2j * np.pi * k / n1)
+
+
+def compact(f, L: int) -> np.ndarray:
+    """Compact storage of a full-grid map: rings t < L-1, then f(pi, phi_0)."""
+    f = np.asarray(f)
+    return np.concatenate([f[:L - 1].reshape(-1), f[L - 1, :1]])
+
+
+def expand_pole(fc, L: int, s: int) -> np.ndarray:
+    """Full grid from compact storage, the pole ring C e^{i s phi_p}."""
+    fc = np.asarray(fc, dtype=np.complex128)
+    n1 = 2 * L - 1
+    f = np.zeros((L, n1), dtype=np.complex128)
+    f[:L - 1] = fc[:(L - 1) * n1].reshape(L - 1, n1)
+    f[L - 1] = fc[(L - 1) * n1] * _pole_phase(L, s)
+    return f
+
+
+def forward_compact(fc, L: int, s: int) -> np.ndarray:
+    return forward(expand_pole(fc, L, s), L, s)
+
+
+def inverse_compact(flm, L: int, s: int) -> np.ndarray:
+    return compact(inverse(flm, L, s), L)
+
+
+def forward_adjoint_compact(y, L: int, s: int) -> np.ndarray:
+    """Adjoint of forward_compact: the full adjoint's rings t < L-1 and, as the
+    pole sample, sum_p e^{-i s phi_p} times its pole ring."""
+    g = forward_adjoint(y, L, s)
+    return np.concatenate([g[:L - 1].reshape(-1), [np.sum(np.conj(_pole_phase(L, s)) * g[L - 1])]])
+
+
+def inverse_adjoint_compact(gc, L: int, s: int) -> np.ndarray:
+    """Adjoint of inverse_compact: the full adjoint of the map whose pole ring
+    holds the pole sample at p = 0 and zeros elsewhere."""
+    gc = np.asarray(gc, dtype=np.complex128)
+    n1 = 2 * L - 1
+    g = np.zeros((L, n1), dtype=np.complex128)
+    g[:L - 1] = gc[:(L - 1) * n1].reshape(L - 1, n1)
+    g[L - 1, 0] = gc[(L - 1) * n1]
+    return inverse_adjoint(g, L, s)

@@ -18,7 +18,7 @@ import ctypes
 import os
 from typing import Sequence
 
-__all__ = ["forward", "inverse", "forward_noalloc", "forward_noalloc_batch", "quadrature_weights", "integrate",
+__all__ = ["forward", "inverse", "forward_compact", "inverse_compact", "compact_batch", "forward_noalloc", "forward_noalloc_batch", "quadrature_weights", "integrate",
            "integrate_batch", "forward_adjoint", "inverse_adjoint", "forward_batch",
            "inverse_batch", "forward_adjoint_batch", "inverse_adjoint_batch", "prepare", "release",
            "workspace_size", "set_workspace", "library", "MWError", "FP64", "FP32C", "EXPORTS", "LIB_PATH"]
@@ -27,7 +27,8 @@ FP64, FP32C = 0, 1
 _PREC = {"fp64": FP64, "fp32c": FP32C, FP64: FP64, FP32C: FP32C}
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmw.so")
-EXPORTS = ("mw_forward", "mw_forward_noalloc", "mw_inverse", "mw_quadrature_weights", "mw_integrate", "mw_forward_adjoint", "mw_inverse_adjoint",
+EXPORTS = ("mw_forward", "mw_forward_noalloc", "mw_inverse", "mw_quadrature_weights", "mw_integrate",
+           "mw_forward_compact", "mw_inverse_compact", "mw_forward_adjoint_compact", "mw_inverse_adjoint_compact", "mw_forward_adjoint", "mw_inverse_adjoint",
            "mw_workspace_size", "mw_set_workspace", "mw_prepare", "mw_release", "mw_status_string",
            "mw_last_error", "mw_version")
 PROFILE_EXPORTS = ("mw_profile_enable", "mw_profile_read", "mw_profile_stage_name", "mw_profile_tuned_group",
@@ -54,7 +55,8 @@ def library():
         i32p = ctypes.POINTER(ctypes.c_int32)
         vpp = ctypes.POINTER(ctypes.c_void_p)
         for name in ("mw_forward", "mw_forward_noalloc", "mw_inverse", "mw_forward_adjoint",
-                     "mw_inverse_adjoint"):
+                     "mw_inverse_adjoint", "mw_forward_compact", "mw_inverse_compact",
+                     "mw_forward_adjoint_compact", "mw_inverse_adjoint_compact"):
             fn = getattr(lib, name)
             fn.restype = ctypes.c_int
             fn.argtypes = [i32p, i32p, i32p, ctypes.c_int32, vpp, ctypes.c_int32, ctypes.c_void_p]
@@ -138,8 +140,12 @@ def _map_shape(L):
     return (L, 2 * L - 1)
 
 
-_MAP, _COEF = "map", "coeffs"
+_MAP, _COEF, _CMAP = "map", "coeffs", "compact map"
 _OPS = {  # name: (input kind, output kind)
+    "mw_forward_compact": (_CMAP, _COEF),
+    "mw_inverse_compact": (_COEF, _CMAP),
+    "mw_forward_adjoint_compact": (_COEF, _CMAP),
+    "mw_inverse_adjoint_compact": (_CMAP, _COEF),
     "mw_forward": (_MAP, _COEF),
     "mw_forward_noalloc": (_MAP, _COEF),
     "mw_inverse": (_COEF, _MAP),
@@ -152,6 +158,8 @@ def _kind_spec(kind, L, real):
     import torch
     if kind == _MAP:
         return _map_shape(L), (torch.float64 if real else torch.complex128)
+    if kind == _CMAP:
+        return ((L - 1) * (2 * L - 1) + 1,), (torch.float64 if real else torch.complex128)
     return (L * L,), torch.complex128
 
 
@@ -203,6 +211,23 @@ def forward_adjoint_batch(coeffs, Ls, spins, realities=None, precision=FP64, out
 def inverse_adjoint_batch(maps, Ls, spins, realities=None, precision=FP64, outs=None, stream=None):
     """Adjoints of the inverse map (grid -> coefficients) for a batch."""
     return _batch("mw_inverse_adjoint", maps, Ls, spins, realities, precision, outs, stream)
+
+
+def compact_batch(name, inputs, Ls, spins, realities=None, precision=FP64, outs=None, stream=None):
+    """The compact-storage transforms (Sec. IV-C): ``name`` is one of "forward",
+    "inverse", "forward_adjoint", "inverse_adjoint"; maps are 1-D tensors of
+    (L-1)(2L-1)+1 samples (the rings t < L-1, then the south-pole sample)."""
+    return _batch("mw_%s_compact" % name, inputs, Ls, spins, realities, precision, outs, stream)
+
+
+def forward_compact(x, L: int, spin: int = 0, reality: int = 0, precision=FP64, out=None, stream=None):
+    """Forward transform of one map in compact storage ((L-1)(2L-1)+1 samples)."""
+    return compact_batch("forward", [x], [L], [spin], [reality], precision, [out], stream)[0]
+
+
+def inverse_compact(flm, L: int, spin: int = 0, reality: int = 0, precision=FP64, out=None, stream=None):
+    """Inverse transform of one coefficient vector into compact storage."""
+    return compact_batch("inverse", [flm], [L], [spin], [reality], precision, [out], stream)[0]
 
 
 def forward(x, L: int, spin: int = 0, reality: int = 0, precision=FP64, out=None, stream=None):

@@ -307,9 +307,14 @@ mw::MixBatch mix_of(const Chunk& c, Src src, Dst dst)
 // Launch sequence of one chunk.  Map k of the chunk uses workspace slot k.
 // prof = false: no per-stage events even when profiling is on (the
 // allocation-free entry point creates none).
+// compact: maps in the compact storage of Sec. IV-C ((L-1)(2L-1)+1 samples, the
+// south pole once), expanded or contracted by the phi stages.
 hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, int precision, void* const* ptrs,
-                     void* ws, int Lws, hipStream_t st, bool prof = true)
+                     void* ws, int Lws, hipStream_t st, bool prof = true, bool compact = false)
 {
+    const int pole_in = compact ? 1 : 0;    // a map read as the forward's input: expand the pole sample
+    const int pole_out = compact ? 1 : 0;   // a map written by the inverse: keep the pole sample
+    const int pole_adj = compact ? 2 : 0;   // the adjoints of those two
     const bool mix = precision != MW_FP64;
     const int s = c.s, real = c.real;
     const double phi_sc = TWO_PI / (double)p.N1;
@@ -325,7 +330,7 @@ hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, 
     switch (op) {
     case Op::Forward: {
         const mw::Batch B1 = batch_of(c, user_in, w0), B2 = batch_of(c, w0, w1), B3 = batch_of(c, w1, user_out);
-        go(0, [&] { return mw::launch_phi_forward(p, B1, real, phi_sc, st); });
+        go(0, [&] { return mw::launch_phi_forward(p, B1, real, phi_sc, pole_in, st); });
         go(1, [&] { return mw::launch_theta_forward(p, B2, mix, real, st); });
         if (mix) {
             const mw::MixBatch M = mix_of(c, w1, user_out);
@@ -359,10 +364,10 @@ hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, 
         if (inv) {
             // real maps: orders m >= 0 only, negative orders by conjugate symmetry
             go(4, [&] { return mw::launch_theta_inverse(p, B3, real, st); });
-            go(5, [&] { return mw::launch_phi_inverse(p, B4, real ? 2 : 0, 1.0, st); });
+            go(5, [&] { return mw::launch_phi_inverse(p, B4, real ? 2 : 0, 1.0, pole_out, st); });
         } else {
             go(8, [&] { return mw::launch_theta_forward_adjoint(p, B3, st); });
-            go(8, [&] { return mw::launch_phi_inverse(p, B4, real, phi_sc, st); });
+            go(8, [&] { return mw::launch_phi_inverse(p, B4, real, phi_sc, pole_adj, st); });
         }
         break;
     }
@@ -371,7 +376,7 @@ hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, 
         // contraction (the conjugate transpose of the inverse's); with real = 1
         // the real-map coefficient expansion is adjoined last.
         const mw::Batch B1 = batch_of(c, user_in, w0), B2 = batch_of(c, w0, w1), B3 = batch_of(c, w1, user_out);
-        go(8, [&] { return mw::launch_phi_forward(p, B1, real, 1.0, st); });
+        go(8, [&] { return mw::launch_phi_forward(p, B1, real, 1.0, pole_adj, st); });
         go(8, [&] { return mw::launch_theta_inverse_adjoint(p, B2, mix, st); });
         if (mix) {
             const mw::MixBatch M = mix_of(c, w1, user_out);
@@ -406,7 +411,7 @@ size_t chunks_ws(const std::vector<Chunk>& ch, int Lws)
 size_t call_ws(const std::vector<Chunk>& ch, int Lws) { return (ch.size() > 1 ? 2 : 1) * chunks_ws(ch, Lws); }
 
 int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
-        void* const* ptrs, int32_t precision, void* stream)
+        void* const* ptrs, int32_t precision, void* stream, bool compact = false)
 {
     int rc = validate(L, spin, reality, batch, ptrs, precision, true);
     if (rc) return rc;
@@ -452,7 +457,7 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     for (size_t i = 0; i < chunks.size() && e == hipSuccess; ++i) {
         hipStream_t cs = lanes ? d.lane[i & 1] : st;
         void* cws = lanes ? (void*)((char*)ws + (i & 1) * half) : ws;
-        e = run_chunk(op, chunks[i], *plans[i], spins[i], precision, ptrs, cws, Lws, cs);
+        e = run_chunk(op, chunks[i], *plans[i], spins[i], precision, ptrs, cws, Lws, cs, true, compact);
     }
     if (lanes) {
         // join both chunk streams back into the caller's stream, also after a failed launch
@@ -638,6 +643,30 @@ int mw_integrate(const int32_t* L, const int32_t* spin, const int32_t* reality, 
     if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     g_last_error.clear();
     return MW_OK;
+}
+
+int mw_forward_compact(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                       void* const* ptrs, int32_t precision, void* stream)
+{
+    return run(Op::Forward, L, spin, reality, batch, ptrs, precision, stream, true);
+}
+
+int mw_inverse_compact(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                       void* const* ptrs, int32_t precision, void* stream)
+{
+    return run(Op::Inverse, L, spin, reality, batch, ptrs, precision, stream, true);
+}
+
+int mw_forward_adjoint_compact(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                               void* const* ptrs, int32_t precision, void* stream)
+{
+    return run(Op::ForwardAdjoint, L, spin, reality, batch, ptrs, precision, stream, true);
+}
+
+int mw_inverse_adjoint_compact(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
+                               void* const* ptrs, int32_t precision, void* stream)
+{
+    return run(Op::InverseAdjoint, L, spin, reality, batch, ptrs, precision, stream, true);
 }
 
 int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,

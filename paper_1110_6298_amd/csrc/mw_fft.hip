@@ -445,14 +445,29 @@ __device__ __forceinline__ int xcd_column(int ncol)
     return (b & 7) * per + (b >> 3);
 }
 
+// e^{i s phi_p} = e^{2 pi i s p/N1}, the angle reduced exactly modulo N1.
+__device__ __forceinline__ double2 spin_phase(int s, int pp, int N1)
+{
+    int r = (int)(((long long)s * pp) % N1);
+    if (r < 0) r += N1;
+    double sn, cs;
+    sincospi(2.0 * (double)r / (double)N1, &sn, &cs);
+    return make_double2(cs, sn);
+}
+
 // ---------------------------------------------------------------------------
 // Forward phi stage (Sec. IV-D): G_m(theta_t) = sc sum_p f(t, p) e^{-i m phi_p}, with
 // sc = 2pi/N1 for the forward transform and sc = 1 for the adjoint of the inverse.
 // Output order-major, G[m + L-1][t], so that the theta stage reads each order's
 // column as one contiguous row; rings are dealt to XCDs in contiguous ranges,
 // so the L2 of one XCD merges the partial lines that neighbouring rings write.
+// pole: how the south-pole ring t = L-1 is read (Sec. IV-C counts it as one
+// sample): 0 = a full ring of the map; 1 = compact storage, the ring being the
+// one stored sample C = f(pi, 0) times e^{i s phi_p} (the form of every
+// band-limited spin-s map at theta = pi, where only m = s survives);
+// 2 = C at p = 0 and zeros elsewhere (the adjoint of keeping only p = 0).
 template <int REAL, int RB, bool SP>
-__global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
+__global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc, int pole)
 {
     extern __shared__ double2 A[];
     const void* __restrict__ map = B.in[blockIdx.y];
@@ -460,6 +475,8 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
     const int L = p.L, N1 = p.N1;
     const int t = xcd_column(L);
     if (t >= L) return;
+    const bool pring = pole != 0 && t == L - 1;
+    const int s = B.s[blockIdx.y];
     // twiddle bases of all FFTs below, read before the first pass (it needs none)
     const FftTw<RB> T = plan_twiddles<RB, SP>(p);
     // the ring's samples, chirped and zero-padded, read by the first pass; the
@@ -467,8 +484,9 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc)
     // the stride-L stores of G were measured slower)
     bluestein_any<RB, SP>(A, p, T, [&](int j) {
         if (j >= N1) return make_double2(0.0, 0.0);
-        const double2 a = REAL ? make_double2(((const double*)map)[(size_t)t * N1 + j], 0.0)
-                               : ((const double2*)map)[(size_t)t * N1 + j];
+        const size_t at = (size_t)t * N1 + (pring ? 0 : j);
+        double2 a = REAL ? make_double2(((const double*)map)[at], 0.0) : ((const double2*)map)[at];
+        if (pring) a = (pole == 1) ? cmul(a, spin_phase(s, j, N1)) : (j == 0 ? a : make_double2(0.0, 0.0));
         return cmul(a, p.chirp[j]);
     });
     staged_loop(
@@ -807,8 +825,11 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
 // (whose phi step is the conjugate transpose of the forward's).  REAL = 1 stores
 // Re f; REAL = 2 (real scalar maps) reads the orders m >= 0 only, takes
 // F_{-m} = conj(F_m) and stores f, which is then real.
+// pole: how the south-pole ring t = L-1 is stored: 0 = in full; 1 = compact
+// storage, its sample p = 0 only; 2 = the single value sum_p e^{-i s phi_p} f(L-1, p)
+// at p = 0 (the adjoint of the compact expansion C -> C e^{i s phi_p}).
 template <int REAL, int RB, bool SP>
-__global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
+__global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc, int pole)
 {
     extern __shared__ double2 A[];
     const double2* __restrict__ Ft = (const double2*)B.in[blockIdx.y];
@@ -825,11 +846,38 @@ __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc)
         const bool neg = REAL == 2 && m < 0;
         return cmul(neg ? a : cconj(a), p.chirp[j]);
     };
-    auto put = [&](int k, double2 v) {   // output k < N1 (v before the chirp)
+    auto value = [&](int k, double2 v) {   // output k < N1 (v before the chirp)
         const double2 out = cscale(cconj(cmul(v, p.chirp[k])), sc);
+        return REAL ? make_double2(out.x, 0.0) : out;
+    };
+    auto put = [&](int k, double2 v) {
+        const double2 out = value(k, v);
         if (REAL) ((double*)map)[(size_t)t * N1 + k] = out.x;
         else ((double2*)map)[(size_t)t * N1 + k] = out;
     };
+    if (pole != 0 && t == L - 1) {   // the pole ring of compact storage
+        bluestein_any<RB, SP>(A, p, T, ld);
+        if (pole == 1) {
+            if (threadIdx.x == 0) put(0, A[Pr<RB>(0)]);
+            return;
+        }
+        // sum_p e^{-i s phi_p} f_p: per-thread partial sums, then thread 0 adds
+        // them in thread order (fixed order)
+        const int s = B.s[blockIdx.y];
+        double2 acc = make_double2(0.0, 0.0);
+        for (int k = threadIdx.x; k < N1; k += blockDim.x)
+            acc = cadd(acc, cmul(value(k, A[Pr<RB>(k)]), cconj(spin_phase(s, k, N1))));
+        __syncthreads();
+        A[threadIdx.x] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double2 tot = A[0];
+            for (int i = 1; i < (int)blockDim.x; ++i) tot = cadd(tot, A[i]);
+            if (REAL) ((double*)map)[(size_t)t * N1] = tot.x;
+            else ((double2*)map)[(size_t)t * N1] = tot;
+        }
+        return;
+    }
     if constexpr (SP) {
         bluestein_split<RB>(A, p, T, ld, [&](int j) { return cmul(ld(j), p.tw[j]); });
         for (int k = threadIdx.x; k < N1; k += blockDim.x) put(k, A[Pr<RB>(k)]);
@@ -916,11 +964,11 @@ template <int RB, bool SP> struct ThFA { static auto fn() { return k_theta_forwa
 
 }  // namespace
 
-hipError_t launch_phi_forward(const Plan& p, const Batch& B, int real, double sc, hipStream_t st)
+hipError_t launch_phi_forward(const Plan& p, const Batch& B, int real, double sc, int pole, hipStream_t st)
 {
     const dim3 grid(xcd_grid(p.L), B.n);
-    if (real) return fft_launch<PhiF<1>::K>(p, grid, st, p, B, sc);
-    return fft_launch<PhiF<0>::K>(p, grid, st, p, B, sc);
+    if (real) return fft_launch<PhiF<1>::K>(p, grid, st, p, B, sc, pole);
+    return fft_launch<PhiF<0>::K>(p, grid, st, p, B, sc, pole);
 }
 
 hipError_t launch_theta_forward(const Plan& p, const Batch& B, int out32, int half, hipStream_t st)
@@ -952,12 +1000,12 @@ hipError_t launch_theta_inverse(const Plan& p, const Batch& B, int half, hipStre
     return fft_launch<ThI<0>::K>(p, dim3(xcd_grid(p.N1), B.n), st, p, B);
 }
 
-hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc, hipStream_t st)
+hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc, int pole, hipStream_t st)
 {
     const dim3 grid(xcd_grid(p.L), B.n);   // rings dealt to XCDs in contiguous ranges
-    if (real == 2) return fft_launch<PhiI<2>::K>(p, grid, st, p, B, sc);
-    if (real) return fft_launch<PhiI<1>::K>(p, grid, st, p, B, sc);
-    return fft_launch<PhiI<0>::K>(p, grid, st, p, B, sc);
+    if (real == 2) return fft_launch<PhiI<2>::K>(p, grid, st, p, B, sc, pole);
+    if (real) return fft_launch<PhiI<1>::K>(p, grid, st, p, B, sc, pole);
+    return fft_launch<PhiI<0>::K>(p, grid, st, p, B, sc, pole);
 }
 
 }  // namespace mw

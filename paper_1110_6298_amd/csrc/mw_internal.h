@@ -146,7 +146,9 @@ void free_spin_table(SpinTable& t);
 
 // Kernel launchers (enqueue only); each runs the maps of B (one plan) in one launch.
 // sc: 2 pi/N1 for the forward transform, 1 for the adjoint of the inverse.
-hipError_t launch_phi_forward(const Plan& p, const Batch& B, int real, double sc, hipStream_t st);
+// pole (compact storage of the south-pole ring, Sec. IV-C): 0 = full ring;
+// 1 = expand the stored sample C to C e^{i s phi_p}; 2 = C at p = 0, zeros elsewhere.
+hipError_t launch_phi_forward(const Plan& p, const Batch& B, int real, double sc, int pole, hipStream_t st);
 // Forward theta stage.  Output: Hp records (Re H_{m,n}, Im H_{m,n}, Re H_{-m,n}, Im H_{-m,n})
 // at [(m * Lp + n) * 4], m < L, n < Lp (pad rows zero); with out32 = 1 FP32 H at
 // [(m*4 + comp)*Lp + n] with the parity signs folded (the mixed contraction's layout).
@@ -171,7 +173,9 @@ hipError_t launch_theta_inverse(const Plan& p, const Batch& B, int half, hipStre
 // sc: 1 for the inverse transform, 2 pi/N1 for the adjoint of the forward.
 // real: 0 complex output; 1 the real part of the full synthesis; 2 a real map
 // synthesised from the orders m >= 0 with F_{-m} = conj(F_m).
-hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc, hipStream_t st);
+// pole: 0 = full pole ring; 1 = its sample p = 0 only (compact storage);
+// 2 = sum_p e^{-i s phi_p} f(L-1, p) at p = 0 (adjoint of the compact expansion).
+hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc, int pole, hipStream_t st);
 // Adjoint of the real-map coefficient expansion: y_{l,m} += (-1)^m conj(y_{l,-m}),
 // y_{l,-m} = 0 for m > 0 (in place on the L^2 layout of B.out).
 hipError_t launch_real_fold(int L, const Batch& B, hipStream_t st);

@@ -48,6 +48,8 @@ def _raw(name, Ls, spins, reals, batch=None, ptrs=True, prec=0):
 
 
 @pytest.mark.parametrize("name", ["mw_forward", "mw_forward_noalloc", "mw_inverse", "mw_forward_adjoint",
+                                  "mw_forward_compact", "mw_inverse_compact", "mw_forward_adjoint_compact",
+                                  "mw_inverse_adjoint_compact",
                                   "mw_inverse_adjoint"])
 @pytest.mark.parametrize("Ls,spins,reals,batch,ptrs,prec", [
     ([0], [0], [0], None, True, 0),          # L < 1

@@ -382,3 +382,30 @@ def test_quadrature_exact_for_band_limited_spin(orc, L, s):
     for nphi in (L, 2 * L - 1):
         f = _synth_on(flm, L, s, theta, 2 * np.pi * np.arange(nphi) / nphi)
         assert abs(orc.integrate(f, L, s) - ref) < 1e-13 * np.abs(flm).max(), nphi
+
+
+# --------------------------------------------------------------------------
+# Compact storage (Sec. IV-C): N_MW samples, the pole once
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("L,s", [(2, 0), (5, 2), (7, -3), (9, 1)])
+def test_compact_storage_is_exact(orc, L, s):
+    flm = mwsynth.flm_gaussian(L, s, seed=970 + L)
+    xc = orc.inverse_compact(flm, L, s)
+    assert xc.size == brute.n_samples(L)["MW"]
+    # the pole ring of the brute-force synthesis is C e^{i s phi_p} with the stored C
+    x = brute.synthesis(flm, L, s)
+    assert rel_inf(orc.expand_pole(xc, L, s), x) < 1e-13
+    # the sampling theorem on N_MW samples: forward(inverse) = identity
+    assert rel_inf(orc.forward_compact(xc, L, s), flm) < 1e-13
+
+
+@pytest.mark.parametrize("L,s", [(4, 0), (6, 2), (8, -1)])
+def test_compact_adjoint_dot_products(orc, L, s):
+    rng = np.random.default_rng(990 + L)
+    n = brute.n_samples(L)["MW"]
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    y = mwsynth.zero_below_spin(mwsynth.flm_gaussian(L, 0, seed=991 + L), L, s)
+    lhs, rhs = np.vdot(y, orc.forward_compact(x, L, s)), np.vdot(orc.forward_adjoint_compact(y, L, s), x)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+    lhs, rhs = np.vdot(x, orc.inverse_compact(y, L, s)), np.vdot(orc.inverse_adjoint_compact(x, L, s), y)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
