@@ -5,6 +5,7 @@ for l >= 2 (seed 1002).  One step = one inverse (f_lm -> map) plus one forward
 (map -> f_lm) on data resident in HBM.  Prints ONE JSON line.
 """
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -54,17 +55,25 @@ def rel(a, b):
 
 def time_steps(torch, step, steps, warmup):
     """ms per step of `step` (enqueued on the current stream), timed with events
-    around `steps` calls after `warmup` untimed ones."""
+    around `steps` calls after `warmup` untimed ones.  Python's cyclic garbage
+    collector is run before and paused during the timed calls: a collection
+    pass over the interpreter's heap stalls the host for tens of ms, and with it
+    the GPU, which would otherwise be charged to the transforms."""
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
+    try:
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(steps):
+            step()
+        t1.record()
+        torch.cuda.synchronize()
+    finally:
+        gc.enable()
     return t0.elapsed_time(t1) / steps
 
 

@@ -169,6 +169,19 @@ int mw_forward_adjoint_compact(const int32_t* L, const int32_t* spin, const int3
 int mw_inverse_adjoint_compact(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
                                void* const* ptrs, int32_t precision, void* stream);
 
+/* Spin -s coefficients for free (Sec. IV-G): if a map f of spin s has
+ * coefficients sf_lm, its conjugate conj(f) is a map of spin -s with
+ * coefficients (-1)^{s+m} conj(sf_{l,-m}).  Under the paper's reality condition
+ * for spin signals, (sf)* = (-s)f, these are the spin -s coefficients of the
+ * same signal, so a spin-s transform yields the spin -s one without a second
+ * transform.  ptrs[2b] = spin[b] coefficients (complex128, L[b]^2 entries),
+ * ptrs[2b+1] = the spin -spin[b] coefficients (may be the same buffer: every
+ * pair (l, +-m) is read before it is written); entries with l < |spin[b]| are
+ * written as 0.  Exact (sign changes and conjugation only).  Validation:
+ * batch >= 1, 1 <= L[b] <= MW_LMAX, |spin[b]| < L[b], non-NULL pointers, else
+ * MW_EINVAL.  Enqueued on `stream`; allocates nothing. */
+int mw_spin_flip(const int32_t* L, const int32_t* spin, int32_t batch, void* const* ptrs, void* stream);
+
 /* Explicit quadrature (Sec. IV-F, Eq.(quadrature)): the weights
  *   q(theta_t) = (2 pi/L) [wt(theta_t) + (1 - delta_{t,L-1}) (-1)^s wt(theta_{2L-2-t})],
  *   wt(theta_t) = 1/(2L-1) sum_{m'=-(L-1)}^{L-1} w(-m') e^{i m' theta_t},

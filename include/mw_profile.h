@@ -36,9 +36,17 @@ const char* mw_profile_stage_name(int stage);
 
 /* Group size (maps sharing one set of Wigner recursions) that mw_prepare's
  * autotuner chose for mixed-precision calls with `nmaps` maps of band-limit L
- * and spin s on the current device; *G = 0 when that shape was not tuned
- * (calls then use the largest size the LDS allows, up to the map count). */
-int mw_profile_tuned_group(int L, int spin, int nmaps, int* G);
+ * and the given reality; *G = 0 when that shape was not tuned (calls then use
+ * the largest size the LDS allows, up to the map count). */
+int mw_profile_tuned_group(int L, int reality, int nmaps, int* G);
+
+/* The autotuner's cache: with the environment variable MW_TUNE_CACHE naming a
+ * file, mw_prepare reads its entries before tuning and appends what it tunes,
+ * one line "gfx950 L reality nmaps G" per shape; lines that do not parse, or
+ * name another architecture or an impossible value, are skipped (the shape is
+ * then tuned again).  This loads such a file now (host only, no GPU needed)
+ * and reports in *entries how many lines it took. */
+int mw_profile_tune_cache_load(const char* path, int* entries);
 
 /* Fourier-kernel layout of plans built from now on (a test hook): mode 0 (the
  * default) runs the N2-point transforms in LDS up to N2 = 8192 and splits them

@@ -18,7 +18,7 @@ import ctypes
 import os
 from typing import Sequence
 
-__all__ = ["forward", "inverse", "forward_compact", "inverse_compact", "compact_batch", "forward_noalloc", "forward_noalloc_batch", "quadrature_weights", "integrate",
+__all__ = ["forward", "inverse", "spin_flip", "spin_flip_batch", "forward_compact", "inverse_compact", "compact_batch", "forward_noalloc", "forward_noalloc_batch", "quadrature_weights", "integrate",
            "integrate_batch", "forward_adjoint", "inverse_adjoint", "forward_batch",
            "inverse_batch", "forward_adjoint_batch", "inverse_adjoint_batch", "prepare", "release",
            "workspace_size", "set_workspace", "library", "MWError", "FP64", "FP32C", "EXPORTS", "LIB_PATH"]
@@ -27,12 +27,12 @@ FP64, FP32C = 0, 1
 _PREC = {"fp64": FP64, "fp32c": FP32C, FP64: FP64, FP32C: FP32C}
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmw.so")
-EXPORTS = ("mw_forward", "mw_forward_noalloc", "mw_inverse", "mw_quadrature_weights", "mw_integrate",
+EXPORTS = ("mw_forward", "mw_forward_noalloc", "mw_inverse", "mw_quadrature_weights", "mw_integrate", "mw_spin_flip",
            "mw_forward_compact", "mw_inverse_compact", "mw_forward_adjoint_compact", "mw_inverse_adjoint_compact", "mw_forward_adjoint", "mw_inverse_adjoint",
            "mw_workspace_size", "mw_set_workspace", "mw_prepare", "mw_release", "mw_status_string",
            "mw_last_error", "mw_version")
 PROFILE_EXPORTS = ("mw_profile_enable", "mw_profile_read", "mw_profile_stage_name", "mw_profile_tuned_group",
-                   "mw_profile_split_fft")
+                   "mw_profile_split_fft", "mw_profile_tune_cache_load")
 NSTAGE = 9
 
 _lib = None
@@ -60,6 +60,8 @@ def library():
             fn = getattr(lib, name)
             fn.restype = ctypes.c_int
             fn.argtypes = [i32p, i32p, i32p, ctypes.c_int32, vpp, ctypes.c_int32, ctypes.c_void_p]
+        lib.mw_spin_flip.restype = ctypes.c_int
+        lib.mw_spin_flip.argtypes = [i32p, i32p, ctypes.c_int32, vpp, ctypes.c_void_p]
         lib.mw_quadrature_weights.restype = ctypes.c_int
         lib.mw_quadrature_weights.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
         lib.mw_integrate.restype = ctypes.c_int
@@ -87,6 +89,8 @@ def library():
         lib.mw_profile_stage_name.argtypes = [ctypes.c_int]
         lib.mw_profile_split_fft.restype = ctypes.c_int
         lib.mw_profile_split_fft.argtypes = [ctypes.c_int]
+        lib.mw_profile_tune_cache_load.restype = ctypes.c_int
+        lib.mw_profile_tune_cache_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
         lib.mw_profile_tuned_group.restype = ctypes.c_int
         lib.mw_profile_tuned_group.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                ctypes.POINTER(ctypes.c_int)]
@@ -257,6 +261,31 @@ def inverse_adjoint(g, L: int, spin: int = 0, reality: int = 0, precision=FP64, 
     return inverse_adjoint_batch([g], [L], [spin], [reality], precision, [out], stream)[0]
 
 
+def spin_flip_batch(coeffs, Ls, spins, outs=None, stream=None):
+    """Coefficients of the conjugate maps (spin -s) from spin-s coefficients:
+    (-1)^{s+m} conj(f_{l,-m}) (Sec. IV-G).  ``outs`` may be the inputs (in place)."""
+    import torch
+    n = len(coeffs)
+    outs = list(outs) if outs is not None else [None] * n
+    ptrs = []
+    for b in range(n):
+        L = int(Ls[b])
+        _check_tensor(coeffs[b], (L * L,), (torch.complex128,), "coeffs %d" % b)
+        if outs[b] is None:
+            outs[b] = torch.empty_like(coeffs[b])
+        _check_tensor(outs[b], (L * L,), (torch.complex128,), "output %d" % b)
+        ptrs += [coeffs[b].data_ptr(), outs[b].data_ptr()]
+    parr = (ctypes.c_void_p * (2 * n))(*[ctypes.c_void_p(int(p)) for p in ptrs])
+    _check(library().mw_spin_flip(_arr(Ls), _arr(spins), n, ctypes.cast(parr, ctypes.POINTER(ctypes.c_void_p)),
+                                  _stream_handle(stream)), "mw_spin_flip")
+    return outs
+
+
+def spin_flip(flm, L: int, spin: int, out=None, stream=None):
+    """Spin -s coefficients of the conjugate map of one coefficient vector."""
+    return spin_flip_batch([flm], [L], [spin], [out], stream)[0]
+
+
 GRID_QUADRATURE, GRID_TRANSFORM = 0, 1
 
 
@@ -350,11 +379,20 @@ def profile_read() -> dict:
     return {lib.mw_profile_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(NSTAGE) if cnt[i]}
 
 
-def tuned_group(L: int, spin: int, nmaps: int) -> int:
-    """Group size the autotuner chose for this mixed-precision shape (0 = not tuned)."""
+def tuned_group(L: int, reality: int, nmaps: int) -> int:
+    """Group size the autotuner chose for mixed-precision calls with ``nmaps``
+    maps of band-limit L and this reality (0 = not tuned)."""
     g = ctypes.c_int(0)
-    _check(library().mw_profile_tuned_group(L, spin, nmaps, ctypes.byref(g)), "mw_profile_tuned_group")
+    _check(library().mw_profile_tuned_group(L, reality, nmaps, ctypes.byref(g)), "mw_profile_tuned_group")
     return int(g.value)
+
+
+def tune_cache_load(path: str) -> int:
+    """Load autotuner entries ("gfx950 L reality nmaps G" lines) from a file now;
+    returns how many lines were taken (malformed ones are skipped)."""
+    n = ctypes.c_int(0)
+    _check(library().mw_profile_tune_cache_load(os.fsencode(path), ctypes.byref(n)), "mw_profile_tune_cache_load")
+    return int(n.value)
 
 
 def split_fft(mode: int) -> None:

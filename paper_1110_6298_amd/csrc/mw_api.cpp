@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -214,35 +215,36 @@ Regions slot(void* ws, int Lws, int L, int k)
     return r;
 }
 
-// Maps of one call with equal band-limit, spin and reality run together: every
-// stage is one launch over the chunk (blockIdx.y = map), and in mixed precision
-// the chunk's maps share the Wigner chains in groups of G.
+// Maps of one call with equal band-limit and reality run together: every
+// Fourier stage is one launch over the chunk (blockIdx.y = map, each map with
+// its own spin).  In FP64 a chunk also has one spin (the FP64 contractions run
+// one spin row); in mixed precision it may hold several spins, sorted by (|s|, s),
+// and its maps share the Wigner order chains in groups of up to G maps with at
+// most two different |s| (the spin rows run beside the shared chains).
 struct Chunk {
-    int L = 0, s = 0, real = 0, G = 1;
-    std::vector<int> maps;   // batch indices
+    int L = 0, s = 0, real = 0, G = 1;   // s: the spin of an FP64 chunk
+    std::vector<int> maps;    // batch indices
+    std::vector<int> spins;   // their spins
 };
 
-// Autotuned group size per (band-limit, spin, maps in the chunk), from mw_prepare.
+// Autotuned group size per (band-limit, reality, maps in the chunk), from mw_prepare.
 std::map<std::tuple<int, int, int>, int> g_tuned;
 
 int pow2_ceil(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : 4; }
 
-// Chunk capacity: at most MAXB maps, MIXG groups in mixed precision, and 8 GiB
-// of workspace.
-int chunk_cap(int L, int precision, int G)
+// Chunk capacity: at most MAXB maps and 8 GiB of workspace.
+int chunk_cap(int L)
 {
-    int cap = mw::MAXB;
-    if (precision != MW_FP64) cap = std::min(cap, G * mw::MIXG);
     const size_t lim = (size_t)8 << 30;
-    cap = std::min<size_t>(cap, std::max<size_t>(1, lim / ws_need(L)));
-    return std::max(cap, 1);
+    const size_t cap = std::min<size_t>(mw::MAXB, std::max<size_t>(1, lim / ws_need(L)));
+    return (int)std::max<size_t>(cap, 1);
 }
 
 // Group size of a mixed-precision chunk: the autotuned one for this shape, else
 // the largest the LDS allows, up to the map count.
-int group_size(int L, int s, int n)
+int group_size(int L, int real, int n)
 {
-    auto it = g_tuned.find(std::make_tuple(L, s, n));
+    auto it = g_tuned.find(std::make_tuple(L, real, n));
     if (it != g_tuned.end()) return it->second;
     return std::min(pow2_ceil(n), mw::mix_group_max());
 }
@@ -252,18 +254,29 @@ int group_size(int L, int s, int n)
 std::vector<Chunk> make_chunks(const int32_t* L, const int32_t* spin, const int32_t* reality, int batch,
                                int precision)
 {
-    std::map<std::tuple<int, int, int>, std::vector<int>> cls;
-    for (int b = 0; b < batch; ++b) cls[std::make_tuple(-L[b], spin[b], reality[b])].push_back(b);
+    const bool mix = precision != MW_FP64;
+    // class key: (-L, reality, spin) in FP64, (-L, reality) in mixed precision;
+    // members sorted by (|s|, s, index)
+    std::map<std::tuple<int, int, int>, std::vector<std::tuple<int, int, int>>> cls;
+    for (int b = 0; b < batch; ++b) {
+        const int as = spin[b] < 0 ? -spin[b] : spin[b];
+        cls[std::make_tuple(-L[b], reality[b], mix ? 0 : spin[b])].push_back(std::make_tuple(as, spin[b], b));
+    }
     std::vector<Chunk> out;
     for (auto& kv : cls) {
-        const int Lc = -std::get<0>(kv.first), sc = std::get<1>(kv.first), rc_ = std::get<2>(kv.first);
-        const auto& v = kv.second;
-        const int G = (precision == MW_FP64) ? 1 : group_size(Lc, sc, (int)v.size());
-        const int cap = chunk_cap(Lc, precision, G);
+        const int Lc = -std::get<0>(kv.first), rc_ = std::get<1>(kv.first);
+        auto v = kv.second;
+        std::sort(v.begin(), v.end());
+        const int G = mix ? group_size(Lc, rc_, (int)v.size()) : 1;
+        const int cap = chunk_cap(Lc);
         for (size_t i = 0; i < v.size(); i += cap) {
             Chunk c;
-            c.L = Lc; c.s = sc; c.real = rc_; c.G = G;
-            c.maps.assign(v.begin() + i, v.begin() + std::min(v.size(), i + (size_t)cap));
+            c.L = Lc; c.real = rc_; c.G = G;
+            for (size_t k = i; k < std::min(v.size(), i + (size_t)cap); ++k) {
+                c.maps.push_back(std::get<2>(v[k]));
+                c.spins.push_back(std::get<1>(v[k]));
+            }
+            c.s = c.spins[0];
             out.push_back(c);
         }
     }
@@ -279,37 +292,87 @@ mw::Batch batch_of(const Chunk& c, In in, Out out)
     for (int k = 0; k < B.n; ++k) {
         B.in[k] = in(k);
         B.out[k] = out(k);
-        B.s[k] = c.s;
+        B.s[k] = c.spins[k];
     }
     return B;
 }
 
-// Mixed contraction descriptor: groups of c.G consecutive maps of the chunk.
-template <class Src, class Dst>
-mw::MixBatch mix_of(const Chunk& c, Src src, Dst dst)
+// The distinct |s| of a chunk (ascending).
+std::vector<int> chunk_abs_spins(const Chunk& c)
 {
-    mw::MixBatch M{};
-    const int n = (int)c.maps.size();
-    M.ng = (n + c.G - 1) / c.G;
-    for (int g = 0; g < M.ng; ++g) {
-        mw::MixMaps& mm = M.g[g];
-        mm.n = std::min(c.G, n - g * c.G);
-        for (int k = 0; k < mm.n; ++k) {
-            const int i = g * c.G + k;
-            mm.src[k] = (const float*)src(i);
-            mm.dst[k] = (double2*)dst(i);
-            mm.L[k] = c.L;
-        }
+    std::vector<int> a;
+    for (int s : c.spins) {
+        const int v = s < 0 ? -s : s;
+        if (a.empty() || a.back() != v) a.push_back(v);
     }
-    return M;
+    return a;
 }
 
-// Launch sequence of one chunk.  Map k of the chunk uses workspace slot k.
-// prof = false: no per-stage events even when profiling is on (the
-// allocation-free entry point creates none).
+// One launch of a mixed contraction: up to MIXG groups with the same spin rows.
+struct MixLaunch {
+    mw::MixBatch M{};
+    int asmax = 0;   // the largest |s| of the spin rows (its spin table's work list runs the inverse)
+};
+
+// Groups of the chunk's maps (in chunk order, sorted by |s|): up to c.G maps
+// with at most two different |s|; groups with the same spin rows share launches.
+// stab(as) gives the spin table of |s| = as (inverse) or nullptr (forward).
+template <class Src, class Dst, class Tab>
+std::vector<MixLaunch> mix_of(const Chunk& c, Src src, Dst dst, Tab stab)
+{
+    // groups by their spin rows (as0, as1 or -1)
+    std::map<std::pair<int, int>, std::vector<mw::MixMaps>> byrows;
+    const int n = (int)c.maps.size();
+    for (int i = 0; i < n;) {
+        mw::MixMaps mm{};
+        int rows[mw::NSMAX] = {0, 0}, nr = 0, nm = 0;
+        while (i < n && nm < c.G) {
+            const int s = c.spins[i], as = s < 0 ? -s : s;
+            int j = 0;
+            while (j < nr && rows[j] != as) ++j;
+            if (j == nr) {
+                if (nr == mw::NSMAX) break;
+                rows[nr++] = as;
+            }
+            mm.src[nm] = (const float*)src(i);
+            mm.dst[nm] = (double2*)dst(i);
+            mm.L[nm] = c.L;
+            mm.meta |= (j << (4 + nm)) | ((s < 0 ? 1 : 0) << (8 + nm));
+            ++nm;
+            ++i;
+        }
+        mm.meta |= nm;
+        byrows[std::make_pair(rows[0], nr > 1 ? rows[1] : -1)].push_back(mm);
+    }
+    std::vector<MixLaunch> out;
+    for (auto& kv : byrows) {
+        const auto& gs = kv.second;
+        for (size_t k = 0; k < gs.size(); k += mw::MIXG) {
+            MixLaunch ml;
+            ml.M.ng = (int)std::min<size_t>(mw::MIXG, gs.size() - k);
+            for (int g = 0; g < ml.M.ng; ++g) ml.M.g[g] = gs[k + g];
+            ml.M.ns = kv.first.second >= 0 ? 2 : 1;
+            ml.M.as[0] = kv.first.first;
+            ml.M.as[1] = kv.first.second >= 0 ? kv.first.second : kv.first.first;
+            for (int j = 0; j < mw::NSMAX; ++j) {
+                const SpinTable* t = stab(ml.M.as[j]);
+                ml.M.stab[j] = t ? t->val : nullptr;
+                ml.M.stabk[j] = t ? t->k : nullptr;
+            }
+            ml.asmax = std::max(ml.M.as[0], ml.M.as[1]);
+            out.push_back(ml);
+        }
+    }
+    return out;
+}
+
+// Spin tables of one chunk, by |s|.
+using ChunkSpins = std::map<int, const SpinTable*>;
+
 // compact: maps in the compact storage of Sec. IV-C ((L-1)(2L-1)+1 samples, the
 // south pole once), expanded or contracted by the phi stages.
-hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, int precision, void* const* ptrs,
+// sps: the spin tables of the chunk's |s| (inverse and forward adjoint).
+hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const ChunkSpins& sps, int precision, void* const* ptrs,
                      void* ws, int Lws, hipStream_t st, bool prof = true, bool compact = false)
 {
     const int pole_in = compact ? 1 : 0;    // a map read as the forward's input: expand the pole sample
@@ -327,14 +390,23 @@ hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, 
     auto go = [&](int stage, auto launch) {
         if (e == hipSuccess) e = staged(stage, st, prof, launch);
     };
+    auto no_tab = [](int) -> const SpinTable* { return nullptr; };
+    auto tab = [&](int as) -> const SpinTable* {
+        auto it = sps.find(as);
+        return it == sps.end() ? nullptr : it->second;
+    };
+    // the mixed contractions of the chunk: one launch per set of spin rows
+    auto mix_forward = [&](int stage, auto src, auto dst) {
+        for (const MixLaunch& ml : mix_of(c, src, dst, no_tab))
+            go(stage, [&] { return mw::launch_contract_forward_mix(p, ml.M, c.G, ml.M.ns, st); });
+    };
     switch (op) {
     case Op::Forward: {
         const mw::Batch B1 = batch_of(c, user_in, w0), B2 = batch_of(c, w0, w1), B3 = batch_of(c, w1, user_out);
         go(0, [&] { return mw::launch_phi_forward(p, B1, real, phi_sc, pole_in, st); });
         go(1, [&] { return mw::launch_theta_forward(p, B2, mix, real, st); });
         if (mix) {
-            const mw::MixBatch M = mix_of(c, w1, user_out);
-            go(2, [&] { return mw::launch_contract_forward_mix(p, s, M, c.G, st); });
+            mix_forward(2, w1, user_out);
         } else {
             go(2, [&] {
                 return mw::launch_contract_forward(p, s, real, (const double*)w1(0), ws_need(Lws) / 8, B3, st);
@@ -351,11 +423,16 @@ hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, 
         const bool inv = op == Op::Inverse;
         const mw::Batch B1 = batch_of(c, user_in, w2), B2 = batch_of(c, w2, w0), B3 = batch_of(c, w0, w1),
                         B4 = batch_of(c, w1, user_out);
-        go(8, [&] { return mw::launch_inverse_stream(p, s, inv ? real : 0, B1, mix, st); });
+        go(8, [&] { return mw::launch_inverse_stream(p, inv ? real : 0, B1, mix, st); });
         if (mix) {
-            const mw::MixBatch M = mix_of(c, w2, w0);
-            go(inv ? 3 : 6, [&] { return mw::launch_contract_inverse_mix(p, *sp, s, M, c.G, st); });
+            for (const MixLaunch& ml : mix_of(c, w2, w0, tab)) {
+                const SpinTable* wsp = tab(ml.asmax);
+                if (!wsp) { e = hipErrorInvalidValue; break; }
+                go(inv ? 3 : 6, [&] { return mw::launch_contract_inverse_mix(p, *wsp, ml.M, c.G, ml.M.ns, st); });
+            }
         } else {
+            const SpinTable* sp = tab(s < 0 ? -s : s);
+            if (!sp) return hipErrorInvalidValue;
             go(inv ? 3 : 6, [&] {
                 return mw::launch_contract_inverse(p, *sp, s, inv ? real : 0, (const double*)w2(0), ws_need(Lws) / 8,
                                                    B2, st);
@@ -379,8 +456,7 @@ hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const SpinTable* sp, 
         go(8, [&] { return mw::launch_phi_forward(p, B1, real, 1.0, pole_adj, st); });
         go(8, [&] { return mw::launch_theta_inverse_adjoint(p, B2, mix, st); });
         if (mix) {
-            const mw::MixBatch M = mix_of(c, w1, user_out);
-            go(7, [&] { return mw::launch_contract_forward_mix(p, s, M, c.G, st); });
+            mix_forward(7, w1, user_out);
         } else {
             go(7, [&] {
                 return mw::launch_contract_forward(p, s, 0, (const double*)w1(0), ws_need(Lws) / 8, B3, st);
@@ -426,11 +502,16 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     // every plan, spin table and the workspace are resolved before anything is
     // enqueued, so that a failure leaves the stream (and a capture) untouched
     std::vector<const Plan*> plans(chunks.size(), nullptr);
-    std::vector<const SpinTable*> spins(chunks.size(), nullptr);
+    std::vector<ChunkSpins> spins(chunks.size());
     for (size_t i = 0; i < chunks.size(); ++i) {
         const Chunk& c = chunks[i];
         if ((rc = get_plan(d, c.L, may_alloc, &plans[i]))) return rc;
-        if (need_spin && (rc = get_spin(d, *plans[i], c.s < 0 ? -c.s : c.s, may_alloc, &spins[i]))) return rc;
+        if (!need_spin) continue;
+        for (int as : chunk_abs_spins(c)) {
+            const SpinTable* t = nullptr;
+            if ((rc = get_spin(d, *plans[i], as, may_alloc, &t))) return rc;
+            spins[i][as] = t;
+        }
     }
     const int Lws = batch_lmax(L, batch);
     const size_t need = call_ws(chunks, Lws);
@@ -472,42 +553,85 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     return MW_OK;
 }
 
-// Times the mixed forward contraction of one chunk per candidate group size on
-// zeroed workspace and keeps the fastest; results do not depend on the choice
-// (each map keeps its own accumulators over the shared chains).
+// ---- the group-size autotuner and its cache --------------------------------
+// Entries "gfx950 L real n G" (one per line; anything else is skipped), read
+// from and appended to the file named by MW_TUNE_CACHE when that is set.
+const char* tune_cache_path()
+{
+    const char* p = getenv("MW_TUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+
+int tune_cache_load(const char* path)
+{
+    FILE* f = fopen(path, "r");
+    if (!f) return 0;
+    char line[256];
+    int got = 0;
+    while (fgets(line, sizeof(line), f)) {
+        char arch[32];
+        int Lc, rc_, n, G;
+        char tail[8];
+        if (sscanf(line, "%31s %d %d %d %d %7s", arch, &Lc, &rc_, &n, &G, tail) != 5) continue;
+        if (strcmp(arch, "gfx950") != 0 || Lc < 1 || Lc > MW_LMAX || (rc_ != 0 && rc_ != 1) || n < 1 ||
+            (G != 1 && G != 2 && G != 4) || G > mw::mix_group_max())
+            continue;
+        g_tuned[std::make_tuple(Lc, rc_, n)] = G;
+        ++got;
+    }
+    fclose(f);
+    return got;
+}
+
+void tune_cache_append(const char* path, int Lc, int rc_, int n, int G)
+{
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "gfx950 %d %d %d %d\n", Lc, rc_, n, G);
+    fclose(f);
+}
+
+// Times the mixed forward contraction of each (L, reality) class of a call with
+// its own spins, per candidate group size, on zeroed workspace, and keeps the
+// fastest per map; results do not depend on the choice (each map keeps its own
+// accumulators over the shared chains).
 int autotune(DeviceState& d, const int32_t* L, const int32_t* spin, const int32_t* reality, int batch)
 {
-    std::map<std::tuple<int, int, int>, int> cnt;   // maps per (L, s, reality)
-    for (int b = 0; b < batch; ++b) ++cnt[std::make_tuple(L[b], spin[b], reality[b])];
+    const char* cache = tune_cache_path();
+    if (cache) tune_cache_load(cache);
+    const std::vector<Chunk> chunks = make_chunks(L, spin, reality, batch, MW_FP32C);
+    std::map<std::pair<int, int>, int> cnt;   // maps per (L, reality)
+    for (int b = 0; b < batch; ++b) ++cnt[std::make_pair(L[b], reality[b])];
     const int Lws = batch_lmax(L, batch);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(MW_EHIP, "hipEventCreate failed");
     int rc = MW_OK;
-    for (auto& kv : cnt) {
-        const int Lc = std::get<0>(kv.first), sc = std::get<1>(kv.first), n = kv.second;
-        const auto key = std::make_tuple(Lc, sc, n);
+    for (const Chunk& c0 : chunks) {
+        const int n = cnt[std::make_pair(c0.L, c0.real)];
+        const auto key = std::make_tuple(c0.L, c0.real, n);
         if (g_tuned.count(key)) continue;
         const Plan* p = nullptr;
-        if ((rc = get_plan(d, Lc, true, &p))) break;
+        if ((rc = get_plan(d, c0.L, true, &p))) break;
         const int gmax = std::min(pow2_ceil(n), mw::mix_group_max());
-        const int nt = std::min(n, chunk_cap(Lc, MW_FP32C, gmax));
+        const int nt = (int)c0.maps.size();
         void* ws = nullptr;
         if ((rc = get_ws(d, (size_t)nt * ws_need(Lws) + 256, true, &ws))) break;
-        for (int k = 0; k < nt; ++k) (void)hipMemset(slot(ws, Lws, Lc, k).W1, 0, ws_region(Lc, 1));
+        for (int k = 0; k < nt; ++k) (void)hipMemset(slot(ws, Lws, c0.L, k).W1, 0, ws_region(c0.L, 1));
         int best = 1;
         double best_t = 1e30;
         for (int G = 1; G <= gmax; G <<= 1) {
-            Chunk c;
-            c.L = Lc; c.s = sc; c.G = G;
-            const int nc = std::min(nt, G * mw::MIXG);
-            for (int k = 0; k < nc; ++k) c.maps.push_back(k);
-            const mw::MixBatch M = mix_of(c, [&](int k) { return (void*)slot(ws, Lws, Lc, k).W1; },
-                                          [&](int k) { return (void*)slot(ws, Lws, Lc, k).W0; });
+            Chunk c = c0;
+            c.G = G;
+            const std::vector<MixLaunch> ls =
+                mix_of(c, [&](int k) { return (void*)slot(ws, Lws, c.L, k).W1; },
+                       [&](int k) { return (void*)slot(ws, Lws, c.L, k).W0; }, [](int) -> const SpinTable* { return nullptr; });
             double t = 0;
-            for (int rep = 0; rep < 3; ++rep) {
+            for (int rep = 0; rep < 3 && !rc; ++rep) {
                 (void)hipEventRecord(e0, nullptr);
-                hipError_t e = mw::launch_contract_forward_mix(*p, sc, M, G, nullptr);
+                hipError_t e = hipSuccess;
+                for (const MixLaunch& ml : ls)
+                    if (e == hipSuccess) e = mw::launch_contract_forward_mix(*p, ml.M, G, ml.M.ns, nullptr);
                 (void)hipEventRecord(e1, nullptr);
                 if (e != hipSuccess) { rc = fail(MW_EHIP, "autotune launch failed"); break; }
                 (void)hipEventSynchronize(e1);
@@ -516,11 +640,12 @@ int autotune(DeviceState& d, const int32_t* L, const int32_t* spin, const int32_
                 if (rep > 0) t += ms;
             }
             if (rc) break;
-            const double per_map = t / nc;
+            const double per_map = t / nt;
             if (per_map < best_t * 0.97) { best_t = per_map; best = G; }
         }
         if (rc) break;
         g_tuned[key] = best;
+        if (cache) tune_cache_append(cache, c0.L, c0.real, n, best);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -569,7 +694,7 @@ int mw_forward_noalloc(const int32_t* L, const int32_t* spin, const int32_t* rea
     }
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < chunks.size() && e == hipSuccess; ++i)
-        e = run_chunk(Op::Forward, chunks[i], *plans[i], nullptr, precision, ptrs, d.scratch, Lws, st, false);
+        e = run_chunk(Op::Forward, chunks[i], *plans[i], ChunkSpins(), precision, ptrs, d.scratch, Lws, st, false);
     if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     g_last_error.clear();
     return MW_OK;
@@ -667,6 +792,38 @@ int mw_inverse_adjoint_compact(const int32_t* L, const int32_t* spin, const int3
                                void* const* ptrs, int32_t precision, void* stream)
 {
     return run(Op::InverseAdjoint, L, spin, reality, batch, ptrs, precision, stream, true);
+}
+
+int mw_spin_flip(const int32_t* L, const int32_t* spin, int32_t batch, void* const* ptrs, void* stream)
+{
+    if (batch < 1 || !L || !spin || !ptrs) return fail(MW_EINVAL, "batch >= 1 and non-NULL L, spin and ptrs required");
+    for (int b = 0; b < batch; ++b) {
+        if (L[b] < 1 || L[b] > MW_LMAX) return fail(MW_EINVAL, "map %d: L = %d outside [1, %d]", b, L[b], MW_LMAX);
+        if (spin[b] <= -L[b] || spin[b] >= L[b])
+            return fail(MW_EINVAL, "map %d: |spin| = %d must be < L = %d", b, spin[b], L[b]);
+        if (!ptrs[2 * b] || !ptrs[2 * b + 1]) return fail(MW_EINVAL, "map %d: NULL pointer", b);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    // maps of equal band-limit share a launch (at most MAXB per launch)
+    std::map<int, std::vector<int>> byL;
+    for (int b = 0; b < batch; ++b) byL[L[b]].push_back(b);
+    hipError_t e = hipSuccess;
+    for (auto& kv : byL) {
+        for (size_t i = 0; i < kv.second.size() && e == hipSuccess; i += mw::MAXB) {
+            mw::Batch B{};
+            B.n = (int)std::min<size_t>(mw::MAXB, kv.second.size() - i);
+            for (int k = 0; k < B.n; ++k) {
+                const int b = kv.second[i + k];
+                B.in[k] = ptrs[2 * b];
+                B.out[k] = ptrs[2 * b + 1];
+                B.s[k] = spin[b];
+            }
+            e = mw::launch_spin_flip(kv.first, B, st);
+        }
+    }
+    if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    g_last_error.clear();
+    return MW_OK;
 }
 
 int mw_workspace_size(const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
@@ -799,12 +956,20 @@ int mw_profile_split_fft(int mode)
     return MW_OK;
 }
 
-int mw_profile_tuned_group(int L, int spin, int nmaps, int* G)
+int mw_profile_tuned_group(int L, int reality, int nmaps, int* G)
 {
     if (!G) return fail(MW_EINVAL, "G must be non-NULL");
     std::lock_guard<std::mutex> lock(g_mu);
-    auto it = g_tuned.find(std::make_tuple(L, spin, nmaps));
+    auto it = g_tuned.find(std::make_tuple(L, reality, nmaps));
     *G = (it == g_tuned.end()) ? 0 : it->second;
+    return MW_OK;
+}
+
+int mw_profile_tune_cache_load(const char* path, int* entries)
+{
+    if (!path || !entries) return fail(MW_EINVAL, "path and entries must be non-NULL");
+    std::lock_guard<std::mutex> lock(g_mu);
+    *entries = tune_cache_load(path);
     return MW_OK;
 }
 

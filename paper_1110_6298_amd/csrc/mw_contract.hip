@@ -77,31 +77,42 @@ __device__ __forceinline__ double2 rpair(const double* __restrict__ Rt, int j)
 // ===========================================================================
 // Forward contraction
 // ===========================================================================
-template <int MT, bool EXT>
+// The spin rows |s_j| a chain group runs: one for the FP64 kernels, up to two
+// for mixed-precision groups whose maps have two different |s| (the order
+// chains Delta_{m,n} are the same for every spin and shared; Sec. V notes that
+// the Wigner values need not be recomputed per spin).
+template <int NS>
+struct SpinSet {
+    int a[NS];
+};
+
+template <int MT, bool EXT, int NS = 1>
 struct FwdLane {
     double dc[MT], dn[MT];         // D_{m,n} and D_{m,n+1}
-    double sc, sn;                 // spin row |s|
+    double sc[NS], sn[NS];         // spin rows |s_j|
     double2 ap[MT][2], am[MT][2];  // accumulators for +m / -m, split by parity of n
-    int k[MT], ks;                 // exponent levels (EXT)
+    int k[MT], ks[NS];             // exponent levels (EXT)
     double anext;                  // sqrt((l-n)(l+n+1)) of the current step
     double q, dq;                  // Q_n = (l+n)(l-n+1) and 2(n-1), exact in FP64
-    double start[MT], starts;
-    int startk[MT], startks;
+    double start[MT], starts[NS];
+    int startk[MT], startks[NS];
 };
 
 // Chain starts of step n (lanes whose degree l equals n start from the edge).
-template <int MT, bool EXT, bool INJ>
-__device__ __forceinline__ void fwd_inject(FwdLane<MT, EXT>& st, int n, int l, bool& anyscaled)
+template <int MT, bool EXT, bool INJ, int NS>
+__device__ __forceinline__ void fwd_inject(FwdLane<MT, EXT, NS>& st, int n, int l, bool& anyscaled)
 {
     if (INJ) {
         if (n == l) {
 #pragma unroll
             for (int c = 0; c < MT; ++c) { st.dc[c] = st.start[c]; if (EXT) st.k[c] = st.startk[c]; }
-            st.sc = st.starts;
-            if (EXT) st.ks = st.startks;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) { st.sc[j] = st.starts[j]; if (EXT) st.ks[j] = st.startks[j]; }
         }
         if (EXT) {
-            bool sc = st.ks > 0;
+            bool sc = false;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) sc |= st.ks[j] > 0;
 #pragma unroll
             for (int c = 0; c < MT; ++c) sc |= st.k[c] > 0;
             anyscaled = __any(sc);
@@ -111,8 +122,9 @@ __device__ __forceinline__ void fwd_inject(FwdLane<MT, EXT>& st, int n, int l, b
 
 // Recursion from step n to n-1 with ra = 1/sqrt(Q_n):
 //   D_{n-1} = -(2m D_n + a_{n+1} D_{n+1}) / a_n,  a_n = sqrt(Q_n); harmless at n = 0.
-template <int MT, bool EXT>
-__device__ __forceinline__ void fwd_advance(FwdLane<MT, EXT>& st, int mb, int as, double ra, bool& anyscaled)
+template <int MT, bool EXT, int NS>
+__device__ __forceinline__ void fwd_advance(FwdLane<MT, EXT, NS>& st, int mb, const SpinSet<NS>& as, double ra,
+                                            bool& anyscaled)
 {
     const double an = st.q * ra;
     const double nra = -ra;
@@ -123,10 +135,11 @@ __device__ __forceinline__ void fwd_advance(FwdLane<MT, EXT>& st, int mb, int as
         st.dn[c] = st.dc[c];
         st.dc[c] = d;
     }
-    {
-        const double d = fma(2.0 * (double)as, st.sc, st.anext * st.sn) * nra;
-        st.sn = st.sc;
-        st.sc = d;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const double d = fma(2.0 * (double)as.a[j], st.sc[j], st.anext * st.sn[j]) * nra;
+        st.sn[j] = st.sc[j];
+        st.sc[j] = d;
     }
     st.anext = an;
     st.q += st.dq;          // Q_{n-1} = Q_n + 2(n-1)
@@ -140,18 +153,21 @@ __device__ __forceinline__ void fwd_advance(FwdLane<MT, EXT>& st, int mb, int as
             }
             still |= st.k[c] > 0;
         }
-        if (st.ks > 0 && fabs(st.sc) > EXT_UP) { st.sc *= EXT_DOWN; st.sn *= EXT_DOWN; st.ks -= 1; }
-        still |= st.ks > 0;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            if (st.ks[j] > 0 && fabs(st.sc[j]) > EXT_UP) { st.sc[j] *= EXT_DOWN; st.sn[j] *= EXT_DOWN; st.ks[j] -= 1; }
+            still |= st.ks[j] > 0;
+        }
         anyscaled = __any(still);
     }
 }
 
-// Delta_{m_c,n} * Delta_{|s|,n} of the current step (0 while a chain is scaled).
-template <int MT, bool EXT>
-__device__ __forceinline__ double fwd_product(const FwdLane<MT, EXT>& st, int c)
+// Delta_{m_c,n} * Delta_{|s_j|,n} of the current step (0 while a chain is scaled).
+template <int MT, bool EXT, int NS>
+__device__ __forceinline__ double fwd_product(const FwdLane<MT, EXT, NS>& st, int c, int j = 0)
 {
-    double seff = st.sc;
-    if (EXT) seff = (st.ks == 0) ? seff : 0.0;
+    double seff = st.sc[j];
+    if (EXT) seff = (st.ks[j] == 0) ? seff : 0.0;
     double d = st.dc[c];
     if (EXT) d = (st.k[c] == 0) ? d : 0.0;
     return d * seff;
@@ -163,11 +179,11 @@ template <int MT, bool EXT, int PAR, bool INJ, bool RL>
 __device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int mb, int as,
                                          const Rec8 (&h)[MT], double ra, bool& anyscaled)
 {
-    fwd_inject<MT, EXT, INJ>(st, n, l, anyscaled);
+    fwd_inject<MT, EXT, INJ, 1>(st, n, l, anyscaled);
 #pragma unroll
     for (int c = 0; c < MT; ++c) {
         const double* hc = h[c].v + 4 * PAR;
-        const double pr = fwd_product<MT, EXT>(st, c);
+        const double pr = fwd_product<MT, EXT, 1>(st, c);
         st.ap[c][PAR].x = fma(pr, hc[0], st.ap[c][PAR].x);
         st.ap[c][PAR].y = fma(pr, hc[1], st.ap[c][PAR].y);
         if (!RL) {   // real maps: f_{l,-m} follows from f_{l,m}
@@ -175,7 +191,7 @@ __device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int
             st.am[c][PAR].y = fma(pr, hc[3], st.am[c][PAR].y);
         }
     }
-    fwd_advance<MT, EXT>(st, mb, as, ra, anyscaled);
+    fwd_advance<MT, EXT, 1>(st, mb, SpinSet<1>{{as}}, ra, anyscaled);
 }
 
 template <int MT>
@@ -288,9 +304,9 @@ struct FwdSeg { int ktop, kA, klo; bool active; };
 // every lane at its own n = l from the edge value; a lower segment runs n from
 // hi-1 down to lo, started from the checkpoint pair of the plane at n_c = hi, a
 // multiple of ckfg (every lane has l >= n_c there).
-template <int MT, bool EXT>
-__device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscaled, int w, int nseg, int lo, int hi,
-                                            int l0, int mb, int l, int L, int as, int ckfg,
+template <int MT, bool EXT, int NS>
+__device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT, NS>& st, bool& anyscaled, int w, int nseg, int lo, int hi,
+                                            int l0, int mb, int l, int L, const SpinSet<NS>& as, int ckfg,
                                             const double* __restrict__ edge, const int* __restrict__ edgek,
                                             const double2* __restrict__ ckf, const int2* __restrict__ ckfk)
 {
@@ -303,7 +319,9 @@ __device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscale
         st.dc[c] = 0.0; st.dn[c] = 0.0; st.k[c] = 0; st.start[c] = 0.0; st.startk[c] = 0;
         st.ap[c][0] = st.ap[c][1] = st.am[c][0] = st.am[c][1] = make_double2(0.0, 0.0);
     }
-    st.sc = 0.0; st.sn = 0.0; st.ks = 0; st.anext = 0.0; st.starts = 0.0; st.startks = 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) { st.sc[j] = 0.0; st.sn[j] = 0.0; st.ks[j] = 0; st.starts[j] = 0.0; st.startks[j] = 0; }
+    st.anext = 0.0;
     st.q = 0.0; st.dq = 0.0;
     anyscaled = EXT;
     FwdSeg g{0, 0, 0, false};
@@ -316,9 +334,13 @@ __device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscale
             st.start[c] = ok ? sgn(l - m) * edge[(size_t)m * L + l] : 0.0;
             st.startk[c] = (EXT && ok) ? edgek[(size_t)m * L + l] : 0;
         }
-        const bool oks = valid && as <= l;
-        st.starts = oks ? sgn(le - as) * edge[(size_t)as * L + le] : 0.0;
-        st.startks = (EXT && oks) ? edgek[(size_t)as * L + le] : 0;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int a = as.a[j];
+            const bool oks = valid && a <= l;
+            st.starts[j] = oks ? sgn(le - a) * edge[(size_t)a * L + le] : 0.0;
+            st.startks[j] = (EXT && oks) ? edgek[(size_t)a * L + le] : 0;
+        }
         const int ktop = nmax >> 1, ntop = 2 * ktop + 1;   // n = L (odd L) is a zero pad step
         st.q = (double)(le + ntop) * (double)(le - ntop + 1);
         st.dq = 2.0 * (double)(ntop - 1);
@@ -337,19 +359,25 @@ __device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT>& st, bool& anyscale
                 st.dc[c] = v.x; st.dn[c] = v.y; st.k[c] = kk;
             }
         }
-        if (valid && as <= l) {
-            const size_t i = base + tri_m(as, l, L);
-            double2 v = ckf[i];
-            int kk = 0;
-            if (EXT) { const int2 kv = ckfk[i]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
-            st.sc = v.x; st.sn = v.y; st.ks = kk;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int a = as.a[j];
+            if (valid && a <= l) {
+                const size_t i = base + tri_m(a, l, L);
+                double2 v = ckf[i];
+                int kk = 0;
+                if (EXT) { const int2 kv = ckfk[i]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
+                st.sc[j] = v.x; st.sn[j] = v.y; st.ks[j] = kk;
+            }
         }
         st.anext = sqrt(fmax(0.0, (double)(le + nc) * (double)(le - nc + 1)));
         const int ntop = nc - 1;
         st.q = (double)(le + ntop) * (double)(le - ntop + 1);
         st.dq = 2.0 * (double)(ntop - 1);
         if (EXT) {
-            bool sc = st.ks > 0;
+            bool sc = false;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) sc |= st.ks[j] > 0;
 #pragma unroll
             for (int c = 0; c < MT; ++c) sc |= st.k[c] > 0;
             anyscaled = __any(sc);
@@ -393,8 +421,8 @@ __device__ __forceinline__ void contract_forward_body(
     FwdLane<MT, EXT> st;
     if (item) {
         bool anyscaled;
-        const FwdSeg g =
-            fwd_setup<MT, EXT>(st, anyscaled, w, nseg, lo, hi, l0, mb, l, L, as, ckfg, edge, edgek, ckf, ckfk);
+        const FwdSeg g = fwd_setup<MT, EXT, 1>(st, anyscaled, w, nseg, lo, hi, l0, mb, l, L, SpinSet<1>{{as}}, ckfg,
+                                               edge, edgek, ckf, ckfk);
         if (g.active) fwd_segment<MT, EXT, RL>(st, g.ktop, g.kA, g.klo, l, le, mb, as, Hp, Rt, Lp, L, anyscaled);
     }
     if (bar) {
@@ -503,8 +531,9 @@ constexpr int STR_L = 32, STR_M = 8;
 // layout the mixed-precision inverse stages per order).
 template <int OUT32>
 __global__ __launch_bounds__(256) void k_inverse_stream(Batch B, const double* __restrict__ cl,
-                                                        const double2* __restrict__ lco, int L, int Lp, int s, int real)
+                                                        const double2* __restrict__ lco, int L, int Lp, int real)
 {
+    const int s = B.s[blockIdx.z];
     const double2* __restrict__ flm = (const double2*)B.in[blockIdx.z];
     void* __restrict__ fs = B.out[blockIdx.z];
     __shared__ double2 ta[STR_L][STR_M + 1], tb[STR_L][STR_M + 1];
@@ -544,6 +573,36 @@ __global__ __launch_bounds__(256) void k_inverse_stream(Batch B, const double* _
             *rec = make_double4(sp * a.x, sp * a.y, sm * b.x, sm * b.y);
         }
     }
+}
+
+// Coefficients of the conjugate map (Sec. IV-G): if f has spin s and
+// coefficients sf_lm, conj(f) has spin -s and coefficients
+// (-1)^{s+m} conj(sf_{l,-m}); under the reality condition sf* = -sf these are the
+// spin -s coefficients of the same signal, obtained without a transform.  One
+// thread per (l, m >= 0) reads both (l, +-m) before writing them, so out may
+// equal in; entries with l < |s| are set to 0.
+__global__ __launch_bounds__(256) void k_spin_flip(Batch B, int L)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;   // (l, m >= 0) in triangle order
+    const int b = blockIdx.y;
+    if (k >= L * (L + 1) / 2) return;
+    int l = (int)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
+    while ((l + 1) * (l + 2) / 2 <= k) ++l;
+    while (l * (l + 1) / 2 > k) --l;
+    const int m = k - l * (l + 1) / 2;
+    const int s = B.s[b];
+    const double2* __restrict__ in = (const double2*)B.in[b];
+    double2* __restrict__ out = (double2*)B.out[b];
+    const size_t c = (size_t)l * l + l;
+    double2 vp = make_double2(0.0, 0.0), vm = make_double2(0.0, 0.0);
+    if (l >= (s < 0 ? -s : s)) {
+        const double2 a = in[c + m], z = in[c - m];
+        const double sg = ((s + m) & 1) ? -1.0 : 1.0;   // (-1)^{s+m} = (-1)^{s-m}
+        vp = make_double2(sg * z.x, -sg * z.y);
+        vm = make_double2(sg * a.x, -sg * a.y);
+    }
+    out[c + m] = vp;
+    if (m > 0) out[c - m] = vm;
 }
 
 // Adjoint of the real-map coefficient expansion f_{l,-m} = (-1)^m conj(f_{l,m})
@@ -594,15 +653,23 @@ struct InvGeo { int lstart, lA, cs, ce, nseg; };
 // stream records and (Pu', h), and (Pu', h) of |s|) is 28 scalar registers, so
 // it is double-buffered step by step.
 // ===========================================================================
-template <bool EXT>
+template <bool EXT, int NS = 1>
 struct InvLane2 {
     double dc[2], dp[2];       // Delta^l_{n,m_c}, Delta^{l-1}_{n,m_c}
-    double sc, sp;             // Delta^l_{n,|s|}, Delta^{l-1}_{n,|s|}
+    double sc[NS], sp[NS];     // Delta^l_{n,|s_j|}, Delta^{l-1}_{n,|s_j|}
     double2 ap[2], am[2];
-    int k[2], ks;
+    int k[2], ks[NS];
     double q, dq, sprev;
-    double start[2], starts;
-    int startk[2], startks, lz[2], l0s;
+    double start[2], starts[NS];
+    int startk[2], startks[NS], lz[2], l0s[NS];
+};
+
+// Spin tables Delta^l_{n,|s_j|} (values, exponent levels) of the spin rows of a
+// chain group.
+template <int NS>
+struct SpinTabs {
+    const double* val[NS];
+    const int* k[NS];
 };
 
 struct InvS2 { double4 f0, f1; double2 c0, c1, cs; };   // one step l
@@ -614,15 +681,16 @@ struct InvS2 { double4 f0, f1; double2 c0, c1, cs; };   // one step l
 struct Inv2Rows {
     const char* f;   // stream records, 32 bytes per (m, l)
     const char* c;   // (Pu', h), 16 bytes per (m, l)
-    unsigned f0, f1, c0, c1, cs;   // byte offsets of the rows at l = 0
+    unsigned f0, f1, c0, c1, cs, cs2;   // byte offsets of the rows at l = 0 (cs2: a second spin row)
 };
 
 __device__ __forceinline__ Inv2Rows inv2_rows(const double* __restrict__ fs, const double2* __restrict__ lco, int m0,
-                                              int as, int Lp, int L)
+                                              int as, int Lp, int L, int as2 = -1)
 {
     const int m1 = min(m0 + 1, L - 1);   // order L (odd L) never starts; any row will do
     return Inv2Rows{(const char*)fs, (const char*)lco, (unsigned)(m0 * Lp) * 32u, (unsigned)(m1 * Lp) * 32u,
-                    (unsigned)(m0 * Lp) * 16u, (unsigned)(m1 * Lp) * 16u, (unsigned)(as * Lp) * 16u};
+                    (unsigned)(m0 * Lp) * 16u, (unsigned)(m1 * Lp) * 16u, (unsigned)(as * Lp) * 16u,
+                    (unsigned)((as2 < 0 ? as : as2) * Lp) * 16u};
 }
 
 __device__ __forceinline__ void inv2_load(InvS2& u, const Inv2Rows& w, int l)
@@ -657,25 +725,41 @@ __device__ __forceinline__ unsigned inv2_touch(const Inv2Rows& w, int l0, int le
 // products pr[c] = e^l_{n,m_c} e^l_{n,|s|} of this step (scaled chains, e = h Delta;
 // the coefficient records carry 1/(h_m h_|s|)), then the recursion to l+1.
 // (c0, c1, cs): (Pu', h) of the two orders and of |s| at l.
-template <bool EXT, bool INJ>
-__device__ __forceinline__ void inv2_core(InvLane2<EXT>& st, int l, int lstart, double nd, const double2& c0,
-                                          const double2& c1, const double2& cs, double rs, double (&pr)[2],
-                                          bool& anyscaled)
+template <bool EXT, int NS>
+__device__ __forceinline__ bool inv2_scaled(const InvLane2<EXT, NS>& st)
+{
+    bool any = st.k[0] > 0 || st.k[1] > 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) any |= st.ks[j] > 0;
+    return any;
+}
+
+template <bool EXT, bool INJ, int NS>
+__device__ __forceinline__ void inv2_core(InvLane2<EXT, NS>& st, int l, int lstart, double nd, const double2& c0,
+                                          const double2& c1, const double2 (&cs)[NS], double rs,
+                                          double (&pr)[2][NS], bool& anyscaled)
 {
     if (INJ) {
 #pragma unroll
         for (int c = 0; c < 2; ++c)
             if (l == st.lz[c]) { st.dc[c] = st.start[c]; if (EXT) st.k[c] = st.startk[c]; }
-        if (l == st.l0s && st.l0s > lstart) { st.sc = st.starts; if (EXT) st.ks = st.startks; }
-        if (EXT) anyscaled = __any(st.k[0] > 0 || st.k[1] > 0 || st.ks > 0);
+#pragma unroll
+        for (int j = 0; j < NS; ++j)
+            if (l == st.l0s[j] && st.l0s[j] > lstart) { st.sc[j] = st.starts[j]; if (EXT) st.ks[j] = st.startks[j]; }
+        if (EXT) anyscaled = __any(inv2_scaled(st));
     }
-    double sv = st.sc;
-    if (EXT) sv = (st.ks == 0) ? sv : 0.0;
+    double sv[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        sv[j] = st.sc[j];
+        if (EXT) sv[j] = (st.ks[j] == 0) ? sv[j] : 0.0;
+    }
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         double d = st.dc[c];
         if (EXT) d = (st.k[c] == 0) ? d : 0.0;
-        pr[c] = d * sv;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) pr[c][j] = d * sv[j];
     }
     // X_n(l) = n/sqrt((l+1)^2-n^2), Y_n(l) = sqrt(l^2-n^2)/sqrt((l+1)^2-n^2); harmless at l = L-1
     const double xn = nd * rs;
@@ -691,17 +775,20 @@ __device__ __forceinline__ void inv2_core(InvLane2<EXT>& st, int l, int lstart, 
         st.dp[c] = st.dc[c];
         st.dc[c] = dn;
     }
-    {
-        const double sn = fma(cs.x * xn, st.sc, yn * st.sp);
-        st.sp = st.sc;
-        st.sc = sn;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const double sn = fma(cs[j].x * xn, st.sc[j], yn * st.sp[j]);
+        st.sp[j] = st.sc[j];
+        st.sc[j] = sn;
     }
     if (EXT && anyscaled) {
 #pragma unroll
         for (int c = 0; c < 2; ++c)
             if (st.k[c] > 0 && fabs(st.dc[c]) > EXT_UP) { st.dc[c] *= EXT_DOWN; st.dp[c] *= EXT_DOWN; st.k[c] -= 1; }
-        if (st.ks > 0 && fabs(st.sc) > EXT_UP) { st.sc *= EXT_DOWN; st.sp *= EXT_DOWN; st.ks -= 1; }
-        anyscaled = __any(st.k[0] > 0 || st.k[1] > 0 || st.ks > 0);
+#pragma unroll
+        for (int j = 0; j < NS; ++j)
+            if (st.ks[j] > 0 && fabs(st.sc[j]) > EXT_UP) { st.sc[j] *= EXT_DOWN; st.sp[j] *= EXT_DOWN; st.ks[j] -= 1; }
+        anyscaled = __any(inv2_scaled(st));
     }
 }
 
@@ -709,16 +796,17 @@ template <bool EXT, bool INJ, bool RL>
 __device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, double nd, const InvS2& u, double rs,
                                           bool& anyscaled)
 {
-    double pr[2];
-    inv2_core<EXT, INJ>(st, l, lstart, nd, u.c0, u.c1, u.cs, rs, pr, anyscaled);
+    double pr[2][1];
+    const double2 cs[1] = {u.cs};
+    inv2_core<EXT, INJ, 1>(st, l, lstart, nd, u.c0, u.c1, cs, rs, pr, anyscaled);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const double4 f = c ? u.f1 : u.f0;
-        st.ap[c].x = fma(pr[c], f.x, st.ap[c].x);
-        st.ap[c].y = fma(pr[c], f.y, st.ap[c].y);
+        st.ap[c].x = fma(pr[c][0], f.x, st.ap[c].x);
+        st.ap[c].y = fma(pr[c][0], f.y, st.ap[c].y);
         if (!RL) {
-            st.am[c].x = fma(pr[c], f.z, st.am[c].x);
-            st.am[c].y = fma(pr[c], f.w, st.am[c].y);
+            st.am[c].x = fma(pr[c][0], f.z, st.am[c].x);
+            st.am[c].y = fma(pr[c][0], f.w, st.am[c].y);
         }
     }
 }
@@ -772,11 +860,11 @@ __device__ __forceinline__ void inv2_phase(InvLane2<EXT>& st, int jfrom, int jla
 
 // Start values are scaled by h_m(l) (the .y of the l-recursion table) at their
 // degree, so that the chains run as e = h Delta.
-template <bool EXT>
-__device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled, const InvGeo& geo, int w, int n,
-                                             int m0, int L, int Lp, int as, int ckg, const double2* __restrict__ lco,
-                                             const double* __restrict__ edge, const int* __restrict__ edgek,
-                                             const double* __restrict__ stab, const int* __restrict__ stabk,
+template <bool EXT, int NS>
+__device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT, NS>& st, bool& anyscaled, const InvGeo& geo, int w, int n,
+                                             int m0, int L, int Lp, const SpinSet<NS>& sset, int ckg,
+                                             const double2* __restrict__ lco, const double* __restrict__ edge,
+                                             const int* __restrict__ edgek, const SpinTabs<NS>& tabs,
                                              const double2* __restrict__ cki, const int2* __restrict__ ckik,
                                              const CkOff& ckoff)
 {
@@ -790,8 +878,11 @@ __device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled,
         st.ap[c] = st.am[c] = make_double2(0.0, 0.0);
         st.lz[c] = max(n, m0 + c);
     }
-    st.sc = 0.0; st.sp = 0.0; st.ks = 0; st.starts = 0.0; st.startks = 0;
-    st.l0s = max(n, as);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        st.sc[j] = 0.0; st.sp[j] = 0.0; st.ks[j] = 0; st.starts[j] = 0.0; st.startks[j] = 0;
+        st.l0s[j] = max(n, sset.a[j]);
+    }
     st.sprev = 0.0; st.q = 0.0; st.dq = 0.0;
     anyscaled = EXT;
     InvSeg g{0, 0, -1, false};
@@ -804,21 +895,27 @@ __device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled,
                 st.start[c] = edge[(size_t)m * L + n] * lco[(size_t)m * Lp + st.lz[c]].y;
                 if (EXT) st.startk[c] = edgek[(size_t)m * L + n];
             }
-            // spin chain: from the table at lstart when already running, else injected
-            if (st.l0s <= lstart) {
-                double v1 = stab[(size_t)lstart * L + n], v0 = 0.0;
-                int k1 = EXT ? stabk[(size_t)lstart * L + n] : 0, k0 = k1;
-                v1 *= lco[(size_t)as * Lp + lstart].y;
-                if (lstart >= 1) {
-                    v0 = stab[(size_t)(lstart - 1) * L + n] * lco[(size_t)as * Lp + lstart - 1].y;
-                    k0 = EXT ? stabk[(size_t)(lstart - 1) * L + n] : 0;
+            // spin chains: from the table at lstart when already running, else injected
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                const int as = sset.a[j];
+                const double* __restrict__ stab = tabs.val[j];
+                const int* __restrict__ stabk = tabs.k[j];
+                if (st.l0s[j] <= lstart) {
+                    double v1 = stab[(size_t)lstart * L + n], v0 = 0.0;
+                    int k1 = EXT ? stabk[(size_t)lstart * L + n] : 0, k0 = k1;
+                    v1 *= lco[(size_t)as * Lp + lstart].y;
+                    if (lstart >= 1) {
+                        v0 = stab[(size_t)(lstart - 1) * L + n] * lco[(size_t)as * Lp + lstart - 1].y;
+                        k0 = EXT ? stabk[(size_t)(lstart - 1) * L + n] : 0;
+                    }
+                    int kk;
+                    ck_level<EXT>(v0, v1, k0, k1, kk);
+                    st.sc[j] = v1; st.sp[j] = v0; st.ks[j] = kk;
+                } else if (st.l0s[j] < L) {
+                    st.starts[j] = stab[(size_t)st.l0s[j] * L + n] * lco[(size_t)as * Lp + st.l0s[j]].y;
+                    st.startks[j] = EXT ? stabk[(size_t)st.l0s[j] * L + n] : 0;
                 }
-                int kk;
-                ck_level<EXT>(v0, v1, k0, k1, kk);
-                st.sc = v1; st.sp = v0; st.ks = kk;
-            } else if (st.l0s < L) {
-                st.starts = stab[(size_t)st.l0s * L + n] * lco[(size_t)as * Lp + st.l0s].y;
-                st.startks = EXT ? stabk[(size_t)st.l0s * L + n] : 0;
             }
         }
         st.sprev = (lstart >= ne) ? sqrt((double)(lstart - ne) * (double)(lstart + ne)) : 0.0;
@@ -844,17 +941,23 @@ __device__ __forceinline__ InvSeg inv2_setup(InvLane2<EXT>& st, bool& anyscaled,
                 if (EXT) { const int2 kv = ckik[i]; ck_level<EXT>(v.x, v.y, kv.x, kv.y, kk); }
                 st.dp[c] = v.x; st.dc[c] = v.y; st.k[c] = kk;
             }
-            double v1 = stab[(size_t)cdeg * L + n] * lco[(size_t)as * Lp + cdeg].y;
-            double v0 = stab[(size_t)(cdeg - 1) * L + n] * lco[(size_t)as * Lp + cdeg - 1].y;
-            int k1 = EXT ? stabk[(size_t)cdeg * L + n] : 0, k0 = EXT ? stabk[(size_t)(cdeg - 1) * L + n] : 0;
-            int kk;
-            ck_level<EXT>(v0, v1, k0, k1, kk);
-            st.sc = v1; st.sp = v0; st.ks = kk;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                const int as = sset.a[j];
+                const double* __restrict__ stab = tabs.val[j];
+                const int* __restrict__ stabk = tabs.k[j];
+                double v1 = stab[(size_t)cdeg * L + n] * lco[(size_t)as * Lp + cdeg].y;
+                double v0 = stab[(size_t)(cdeg - 1) * L + n] * lco[(size_t)as * Lp + cdeg - 1].y;
+                int k1 = EXT ? stabk[(size_t)cdeg * L + n] : 0, k0 = EXT ? stabk[(size_t)(cdeg - 1) * L + n] : 0;
+                int kk;
+                ck_level<EXT>(v0, v1, k0, k1, kk);
+                st.sc[j] = v1; st.sp[j] = v0; st.ks[j] = kk;
+            }
         }
         st.sprev = sqrt(fmax(0.0, (double)(cdeg - ne) * (double)(cdeg + ne)));
         st.q = (double)(cdeg + 1 - ne) * (double)(cdeg + 1 + ne);
         st.dq = 2.0 * (double)cdeg + 3.0;
-        if (EXT) anyscaled = __any(st.k[0] > 0 || st.k[1] > 0 || st.ks > 0);
+        if (EXT) anyscaled = __any(inv2_scaled(st));
         const int jlast = min(geo.ce >> 1, jend + 1) - 1;
         g = InvSeg{cdeg >> 1, (cdeg >> 1) - 1, jlast, true};
     }
@@ -901,8 +1004,8 @@ __device__ __forceinline__ void contract_inverse2_body(
         const Inv2Rows rows = inv2_rows(fs, lco, m0, as, Lp, L);
         const unsigned touched = inv2_touch(rows, geo.cs, lend, lane);
         bool anyscaled;
-        const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, ckg, lco, edge, edgek, stab, stabk,
-                                         cki, ckik, ckoff);
+        const InvSeg g = inv2_setup<EXT, 1>(st, anyscaled, geo, w, n, m0, L, Lp, SpinSet<1>{{as}}, ckg, lco, edge,
+                                            edgek, SpinTabs<1>{{stab}, {stabk}}, cki, ckik, ckoff);
         asm volatile("" ::"v"(touched));
         if (g.active) {
             InvS2 uA, uB;
@@ -1022,7 +1125,7 @@ __device__ __forceinline__ void fwd_win_load(FwdWin<G>& r, const MixMaps& maps, 
         const int row = e >> 4, n = WIN * q + 2 * (e & 15);
         const int comp = row & 3, c = (row >> 2) & 1, b = row >> 3;
         r.v[t] = fv2{0.0f, 0.0f};
-        if (b < maps.n) {
+        if (b < mix_n(maps)) {
             const int Lb = maps.L[b], m = mb + c;
             // rows hold Lp_b entries, the pad n = L_b (odd L_b) zero
             if (m < Lb && n < Lb)
@@ -1041,29 +1144,39 @@ __device__ __forceinline__ void win_store(float* __restrict__ win, const fv2* v,
     }
 }
 
-template <bool EXT, bool INJ, int G>
-__device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT>& st, v4f (&acc)[2][G], int k, int l, int mb, int as,
+// Maps of a group take the products of their own spin row: sj[b] in [0, NS).
+template <bool EXT, bool INJ, int G, int NS>
+__device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT, NS>& st, v4f (&acc)[2][G], int k, int l, int mb,
+                                             const SpinSet<NS>& as, const MixMaps& maps,
                                              const float* __restrict__ win, int comp, const FwdR& r,
                                              bool& anyscaled)
 {
-    float k1[2], k0[2];
-    fwd_inject<2, EXT, INJ>(st, 2 * k + 1, l, anyscaled);
-    k1[0] = (float)fwd_product<2, EXT>(st, 0);
-    k1[1] = (float)fwd_product<2, EXT>(st, 1);
-    fwd_advance<2, EXT>(st, mb, as, r.hi.y * r.lo.x, anyscaled);
-    fwd_inject<2, EXT, INJ>(st, 2 * k, l, anyscaled);
-    k0[0] = (float)fwd_product<2, EXT>(st, 0);
-    k0[1] = (float)fwd_product<2, EXT>(st, 1);
-    fwd_advance<2, EXT>(st, mb, as, r.hi.x * r.lo.y, anyscaled);
+    float k1[2][NS], k0[2][NS];
+    fwd_inject<2, EXT, INJ, NS>(st, 2 * k + 1, l, anyscaled);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        k1[0][j] = (float)fwd_product<2, EXT, NS>(st, 0, j);
+        k1[1][j] = (float)fwd_product<2, EXT, NS>(st, 1, j);
+    }
+    fwd_advance<2, EXT, NS>(st, mb, as, r.hi.y * r.lo.x, anyscaled);
+    fwd_inject<2, EXT, INJ, NS>(st, 2 * k, l, anyscaled);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        k0[0][j] = (float)fwd_product<2, EXT, NS>(st, 0, j);
+        k0[1][j] = (float)fwd_product<2, EXT, NS>(st, 1, j);
+    }
+    fwd_advance<2, EXT, NS>(st, mb, as, r.hi.x * r.lo.y, anyscaled);
     const int off = 2 * k - WIN * (k / (WIN / 2));   // n = 2k within its window
 #pragma unroll
-    for (int b = 0; b < G; ++b)
+    for (int b = 0; b < G; ++b) {
+        const bool second = NS > 1 && mix_row(maps, b) != 0;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const fv2 a = *(const fv2*)(win + ((b * 2 + c) * 4 + comp) * WROW + off);   // n = 2k, 2k+1
-            acc[c][b] = mfma4(a.y, k1[c], acc[c][b]);
-            acc[c][b] = mfma4(a.x, k0[c], acc[c][b]);
+            acc[c][b] = mfma4(a.y, second ? k1[c][NS - 1] : k1[c][0], acc[c][b]);
+            acc[c][b] = mfma4(a.x, second ? k0[c][NS - 1] : k0[c][0], acc[c][b]);
         }
+    }
 }
 
 // Pairs k .. kto (descending; INJ: pairs with lane starts), window by window:
@@ -1071,9 +1184,9 @@ __device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT>& st, v4f (&acc)[2][
 // window q-1 requested; the pairs of a window then run two at a time with the
 // 1/sqrt factors alternating between the A and B register sets (A holds pair k
 // on entry and on return).
-template <bool EXT, bool INJ, int G>
-__device__ __forceinline__ void fwd_mix_run(FwdLane<2, EXT>& st, v4f (&acc)[2][G], const FwdSeg& g, int& k, int kto,
-                                            int l, int le, int mb, int as, const double* __restrict__ Rt,
+template <bool EXT, bool INJ, int G, int NS>
+__device__ __forceinline__ void fwd_mix_run(FwdLane<2, EXT, NS>& st, v4f (&acc)[2][G], const FwdSeg& g, int& k, int kto,
+                                            int l, int le, int mb, const SpinSet<NS>& as, const double* __restrict__ Rt,
                                             float* __restrict__ win, const MixMaps& maps, int lane, FwdWin<G>& nxt,
                                             FwdR& rA, bool& anyscaled)
 {
@@ -1088,22 +1201,22 @@ __device__ __forceinline__ void fwd_mix_run(FwdLane<2, EXT>& st, v4f (&acc)[2][G
         const int kw = max(kto, (k / PW) * PW);        // lowest pair of this window in range
         for (; k > kw; k -= 2) {
             rB = fwd_load_r(Rt, le, max(k - 1, 0));
-            fwd_mix_pair<EXT, INJ, G>(st, acc, k, l, mb, as, win, comp, rA, anyscaled);
+            fwd_mix_pair<EXT, INJ, G, NS>(st, acc, k, l, mb, as, maps, win, comp, rA, anyscaled);
             rA = fwd_load_r(Rt, le, max(k - 2, 0));
-            fwd_mix_pair<EXT, INJ, G>(st, acc, k - 1, l, mb, as, win, comp, rB, anyscaled);
+            fwd_mix_pair<EXT, INJ, G, NS>(st, acc, k - 1, l, mb, as, maps, win, comp, rB, anyscaled);
         }
         if (k == kw) {                                 // odd pair left in the window
             rB = fwd_load_r(Rt, le, max(k - 1, 0));
-            fwd_mix_pair<EXT, INJ, G>(st, acc, k, l, mb, as, win, comp, rA, anyscaled);
+            fwd_mix_pair<EXT, INJ, G, NS>(st, acc, k, l, mb, as, maps, win, comp, rA, anyscaled);
             rA = rB;
             --k;
         }
     }
 }
 
-template <bool EXT, int G>
-__device__ __forceinline__ void fwd_mix_segment(FwdLane<2, EXT>& st, v4f (&acc)[2][G], const FwdSeg& g, int l,
-                                                int le, int mb, int as, const double* __restrict__ Rt,
+template <bool EXT, int G, int NS>
+__device__ __forceinline__ void fwd_mix_segment(FwdLane<2, EXT, NS>& st, v4f (&acc)[2][G], const FwdSeg& g, int l,
+                                                int le, int mb, const SpinSet<NS>& as, const double* __restrict__ Rt,
                                                 float* __restrict__ win, const MixMaps& maps, int lane,
                                                 bool& anyscaled)
 {
@@ -1112,13 +1225,14 @@ __device__ __forceinline__ void fwd_mix_segment(FwdLane<2, EXT>& st, v4f (&acc)[
     fwd_win_load<G>(nxt, maps, mb, g.ktop / PW, lane);
     FwdR rA = fwd_load_r(Rt, le, g.ktop);
     int k = g.ktop;
-    fwd_mix_run<EXT, true, G>(st, acc, g, k, max(g.kA, g.klo), l, le, mb, as, Rt, win, maps, lane, nxt, rA,
-                              anyscaled);   // pairs with lane starts
-    fwd_mix_run<EXT, false, G>(st, acc, g, k, g.klo, l, le, mb, as, Rt, win, maps, lane, nxt, rA, anyscaled);
+    fwd_mix_run<EXT, true, G, NS>(st, acc, g, k, max(g.kA, g.klo), l, le, mb, as, Rt, win, maps, lane, nxt, rA,
+                                  anyscaled);   // pairs with lane starts
+    fwd_mix_run<EXT, false, G, NS>(st, acc, g, k, g.klo, l, le, mb, as, Rt, win, maps, lane, nxt, rA, anyscaled);
 }
 
-// Forward contraction of a group of up to G maps of one spin (band-limits
-// maps.L[b] <= L, the plan's).  maps.src[b]: H of map b in FP32 at
+// Forward contraction of a group of up to G maps with at most NS different |s|
+// (band-limits maps.L[b] <= L, the plan's; spin mix_spin(MB, maps, b), whose |s|
+// is the launch's spin row mix_row(maps, b)).  maps.src[b]: H of map b in FP32 at
 // [(m*4 + comp)*Lp_b + n], comp = (Re, Im) of sigma_+(n) H_{m,n} and of
 // sigma_-(n) H_{-m,n}, where sigma_+ = (-1)^n for s >= 0 (else 1) and sigma_- =
 // (-1)^n for s < 0 (else 1); maps.dst[b]: f_lm of map b.
@@ -1130,12 +1244,14 @@ __host__ __device__ constexpr int fwdm_slot_floats(int G)
 }
 
 // Wave budgets as for the mixed inverse: five waves per SIMD for one map (96
-// VGPRs, the accumulators in ordinary VGPRs), four for two, three for four.
-template <bool EXT, int G>
-__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(G == 1 ? 5 : (G == 4 ? 3 : 4)))) void k_contract_forward_mix(
+// VGPRs, the accumulators in ordinary VGPRs), four for two, three for four;
+// with a second spin row one wave less for one or two maps (no spills).
+template <bool EXT, int G, int NS>
+__global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(
+    NS == 1 ? (G == 1 ? 5 : (G == 4 ? 3 : 4)) : (G == 1 ? 4 : 3)))) void k_contract_forward_mix(
     MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
     const double* __restrict__ cl, const double2* __restrict__ ckf, const int2* __restrict__ ckfk,
-    const int4* __restrict__ work, int L, int s, int ckfg)
+    const int4* __restrict__ work, int L, int ckfg)
 {
     extern __shared__ double smem[];
     const MixMaps& maps = MB.g[blockIdx.y];
@@ -1149,23 +1265,25 @@ __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(G 
     const int lo = rows & 0xffff, hi = (int)((unsigned)rows >> 16);   // this segment's rows [lo, hi)
     const bool bar = (code >> 24) & 1;   // the same for every slot of the workgroup
     bool any = false;                    // does any map of the group have this (l0, mb) block?
-    for (int b = 0; b < maps.n; ++b) any |= (l0 < maps.L[b] && mb < maps.L[b]);
+    for (int b = 0; b < mix_n(maps); ++b) any |= (l0 < maps.L[b] && mb < maps.L[b]);
     const double* __restrict__ Rt = Rtg;               // 1/sqrt table, L1-resident
     float* region = (float*)smem + slot * fwdm_slot_floats(G);
     const int l = l0 + lane;
     const bool valid = item && l < L;
     const int le = valid ? l : L - 1;
-    const int as = s < 0 ? -s : s;
+    SpinSet<NS> as;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) as.a[j] = MB.as[j];
 
     v4f acc[2][G];
 #pragma unroll
     for (int b = 0; b < G; ++b) acc[0][b] = acc[1][b] = v4f{0.f, 0.f, 0.f, 0.f};
     if (item && any) {
-        FwdLane<2, EXT> st;
+        FwdLane<2, EXT, NS> st;
         bool anyscaled;
         const FwdSeg g =
-            fwd_setup<2, EXT>(st, anyscaled, w, nseg, lo, hi, l0, mb, l, L, as, ckfg, edge, edgek, ckf, ckfk);
-        if (g.active) fwd_mix_segment<EXT, G>(st, acc, g, l, le, mb, as, Rt, region, maps, lane, anyscaled);
+            fwd_setup<2, EXT, NS>(st, anyscaled, w, nseg, lo, hi, l0, mb, l, L, as, ckfg, edge, edgek, ckf, ckfk);
+        if (g.active) fwd_mix_segment<EXT, G, NS>(st, acc, g, l, le, mb, as, Rt, region, maps, lane, anyscaled);
     }
 
     double sum[2][G][4];
@@ -1202,10 +1320,11 @@ __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(G 
         return;
     }
     if (!valid) return;
-    const double base = sgn(s) * cl[l];
 #pragma unroll
     for (int b = 0; b < G; ++b) {
-        if (b >= maps.n || l >= maps.L[b]) continue;
+        if (b >= mix_n(maps) || l >= maps.L[b]) continue;
+        const int s = mix_spin(MB, maps, b);
+        const double base = sgn(s) * cl[l];
         double2* flm = maps.dst[b];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -1229,14 +1348,18 @@ __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(G 
 // FP32 and accumulated by v_mfma_f32_4x4x1_16b_f32 against the FP32 stream of
 // every map of the group (windows of WIN degrees in LDS, as in the one-order
 // kernel).  Work list: the packed segment list of the spin table.
-struct InvC2 { double4 c0, c1, cs; };   // pair (l, l+1): (Pu', h) of m0, of m0+1 and of |s|
+// pair (l, l+1): (Pu', h) of m0, of m0+1 and of the spin rows |s_j|
+template <int NS>
+struct InvC2 { double4 c0, c1, cs[NS]; };
 
-__device__ __forceinline__ void inv2m_load_c(InvC2& u, const Inv2Rows& w, int j)
+template <int NS>
+__device__ __forceinline__ void inv2m_load_c(InvC2<NS>& u, const Inv2Rows& w, int j)
 {
     const unsigned lc = (unsigned)(2 * j) * 16u;
     u.c0 = *(const double4*)(w.c + (w.c0 + lc));
     u.c1 = *(const double4*)(w.c + (w.c1 + lc));
-    u.cs = *(const double4*)(w.c + (w.cs + lc));
+    u.cs[0] = *(const double4*)(w.c + (w.cs + lc));
+    if constexpr (NS > 1) u.cs[NS - 1] = *(const double4*)(w.c + (w.cs2 + lc));
 }
 
 // Window q of the group: rows r = (b*2 + c)*4 + comp (map b, order m0+c, stream
@@ -1254,7 +1377,7 @@ __device__ __forceinline__ void inv2m_win_load(InvWin2<G>& r, const MixMaps& map
         const int comp = row & 3, c = (row >> 2) & 1, b = row >> 3;
         const int m = m0 + c;
         r.v[t] = fv2{0.0f, 0.0f};
-        if (b < maps.n) {
+        if (b < mix_n(maps)) {
             const int Lb = maps.L[b];
             if (m < Lb && l < Lb)
                 r.v[t] = *(const fv2*)(maps.src[b] + ((size_t)m * 4 + comp) * (size_t)(Lb + (Lb & 1)) + l);
@@ -1262,26 +1385,35 @@ __device__ __forceinline__ void inv2m_win_load(InvWin2<G>& r, const MixMaps& map
     }
 }
 
-template <bool EXT, bool INJ, int G>
-__device__ __forceinline__ void inv2m_pair(InvLane2<EXT>& st, v4f (&acc)[2][G], int j, int lstart, double nd,
-                                           const InvC2& u, const InvR& r, const float* __restrict__ win, int comp,
-                                           bool& anyscaled)
+template <bool EXT, bool INJ, int G, int NS>
+__device__ __forceinline__ void inv2m_pair(InvLane2<EXT, NS>& st, v4f (&acc)[2][G], int j, int lstart, double nd,
+                                           const InvC2<NS>& u, const InvR& r, const MixMaps& maps,
+                                           const float* __restrict__ win, int comp, bool& anyscaled)
 {
     const int l = 2 * j;
-    double p0[2], p1[2];
-    inv2_core<EXT, INJ>(st, l, lstart, nd, make_double2(u.c0.x, u.c0.y), make_double2(u.c1.x, u.c1.y),
-                        make_double2(u.cs.x, u.cs.y), r.a.x * r.b.x, p0, anyscaled);
-    inv2_core<EXT, INJ>(st, l + 1, lstart, nd, make_double2(u.c0.z, u.c0.w), make_double2(u.c1.z, u.c1.w),
-                        make_double2(u.cs.z, u.cs.w), r.a.y * r.b.y, p1, anyscaled);
+    double p0[2][NS], p1[2][NS];
+    double2 cs0[NS], cs1[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        cs0[q] = make_double2(u.cs[q].x, u.cs[q].y);
+        cs1[q] = make_double2(u.cs[q].z, u.cs[q].w);
+    }
+    inv2_core<EXT, INJ, NS>(st, l, lstart, nd, make_double2(u.c0.x, u.c0.y), make_double2(u.c1.x, u.c1.y), cs0,
+                            r.a.x * r.b.x, p0, anyscaled);
+    inv2_core<EXT, INJ, NS>(st, l + 1, lstart, nd, make_double2(u.c0.z, u.c0.w), make_double2(u.c1.z, u.c1.w), cs1,
+                            r.a.y * r.b.y, p1, anyscaled);
     const int off = l - WIN * (j / (WIN / 2));   // degree l within its window
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        const float k0 = (float)p0[c], k1 = (float)p1[c];
+        float k0[NS], k1[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) { k0[q] = (float)p0[c][q]; k1[q] = (float)p1[c][q]; }
 #pragma unroll
         for (int b = 0; b < G; ++b) {
+            const bool second = NS > 1 && mix_row(maps, b) != 0;
             const fv2 a = *(const fv2*)(win + ((b * 2 + c) * 4 + comp) * WROW + off);   // degrees l, l+1
-            acc[c][b] = mfma4(a.x, k0, acc[c][b]);
-            acc[c][b] = mfma4(a.y, k1, acc[c][b]);
+            acc[c][b] = mfma4(a.x, second ? k0[NS - 1] : k0[0], acc[c][b]);
+            acc[c][b] = mfma4(a.y, second ? k1[NS - 1] : k1[0], acc[c][b]);
         }
     }
 }
@@ -1291,16 +1423,16 @@ __device__ __forceinline__ void inv2m_pair(InvLane2<EXT>& st, v4f (&acc)[2][G], 
 // window q+1 requested; the pairs of a window then run two at a time with the
 // uniform data and 1/sqrt factors alternating between the A and B register sets
 // (A holds pair j on entry and on return).
-template <bool EXT, bool INJ, int G>
-__device__ __forceinline__ void inv2m_run(InvLane2<EXT>& st, v4f (&acc)[2][G], const InvSeg& g, int& j, int jto,
+template <bool EXT, bool INJ, int G, int NS>
+__device__ __forceinline__ void inv2m_run(InvLane2<EXT, NS>& st, v4f (&acc)[2][G], const InvSeg& g, int& j, int jto,
                                           int jend, int lstart, int ne, double nd, int m0, const Inv2Rows& rows,
                                           const double* __restrict__ Rt, float* __restrict__ win,
-                                          const MixMaps& maps, int lane, InvWin2<G>& nxt, InvC2& uA, InvR& rA,
+                                          const MixMaps& maps, int lane, InvWin2<G>& nxt, InvC2<NS>& uA, InvR& rA,
                                           bool& anyscaled)
 {
     constexpr int PW = WIN / 2;   // pairs per window
     const int comp = lane & 3;
-    InvC2 uB;
+    InvC2<NS> uB;
     InvR rB;
     while (j <= jto) {
         if (j == g.jfrom || (j % PW) == 0) {          // entering window j / PW
@@ -1312,17 +1444,17 @@ __device__ __forceinline__ void inv2m_run(InvLane2<EXT>& st, v4f (&acc)[2][G], c
             wait_scalar(uA.c0.x);
             inv2m_load_c(uB, rows, min(j + 1, jend));
             rB = inv_load_r(Rt, ne, min(j + 1, jend));
-            inv2m_pair<EXT, INJ, G>(st, acc, j, lstart, nd, uA, rA, win, comp, anyscaled);
+            inv2m_pair<EXT, INJ, G, NS>(st, acc, j, lstart, nd, uA, rA, maps, win, comp, anyscaled);
             wait_scalar(uB.c0.x);
             inv2m_load_c(uA, rows, min(j + 2, jend));
             rA = inv_load_r(Rt, ne, min(j + 2, jend));
-            inv2m_pair<EXT, INJ, G>(st, acc, j + 1, lstart, nd, uB, rB, win, comp, anyscaled);
+            inv2m_pair<EXT, INJ, G, NS>(st, acc, j + 1, lstart, nd, uB, rB, maps, win, comp, anyscaled);
         }
         if (j == jw) {                                 // odd pair left in the window
             wait_scalar(uA.c0.x);
             inv2m_load_c(uB, rows, min(j + 1, jend));
             rB = inv_load_r(Rt, ne, min(j + 1, jend));
-            inv2m_pair<EXT, INJ, G>(st, acc, j, lstart, nd, uA, rA, win, comp, anyscaled);
+            inv2m_pair<EXT, INJ, G, NS>(st, acc, j, lstart, nd, uA, rA, maps, win, comp, anyscaled);
             uA = uB;
             rA = rB;
             ++j;
@@ -1330,8 +1462,8 @@ __device__ __forceinline__ void inv2m_run(InvLane2<EXT>& st, v4f (&acc)[2][G], c
     }
 }
 
-template <bool EXT, int G>
-__device__ __forceinline__ void inv2m_segment(InvLane2<EXT>& st, v4f (&acc)[2][G], const InvSeg& g, int jend,
+template <bool EXT, int G, int NS>
+__device__ __forceinline__ void inv2m_segment(InvLane2<EXT, NS>& st, v4f (&acc)[2][G], const InvSeg& g, int jend,
                                               int lstart, int ne, double nd, int m0, const Inv2Rows& rows,
                                               const double* __restrict__ Rt, float* __restrict__ win,
                                               const MixMaps& maps, int lane, bool& anyscaled)
@@ -1339,13 +1471,13 @@ __device__ __forceinline__ void inv2m_segment(InvLane2<EXT>& st, v4f (&acc)[2][G
     constexpr int PW = WIN / 2;
     InvWin2<G> nxt;
     inv2m_win_load<G>(nxt, maps, m0, g.jfrom / PW, lane);
-    InvC2 uA;
-    inv2m_load_c(uA, rows, g.jfrom);
+    InvC2<NS> uA;
+    inv2m_load_c<NS>(uA, rows, g.jfrom);
     InvR rA = inv_load_r(Rt, ne, g.jfrom);
     int j = g.jfrom;
-    inv2m_run<EXT, true, G>(st, acc, g, j, min(g.jA, g.jlast), jend, lstart, ne, nd, m0, rows, Rt, win, maps, lane,
+    inv2m_run<EXT, true, G, NS>(st, acc, g, j, min(g.jA, g.jlast), jend, lstart, ne, nd, m0, rows, Rt, win, maps, lane,
                             nxt, uA, rA, anyscaled);   // pairs with chain starts
-    inv2m_run<EXT, false, G>(st, acc, g, j, g.jlast, jend, lstart, ne, nd, m0, rows, Rt, win, maps, lane, nxt, uA,
+    inv2m_run<EXT, false, G, NS>(st, acc, g, j, g.jlast, jend, lstart, ne, nd, m0, rows, Rt, win, maps, lane, nxt, uA,
                              rA, anyscaled);
 }
 
@@ -1358,12 +1490,16 @@ __host__ __device__ constexpr int inv2m_slot_floats(int G)
 
 // Groups of four maps hold three waves per SIMD (136 VGPRs beside the 32 AGPRs of
 // their accumulators); left alone the allocator can take two more and drop to two.
-template <bool EXT, int G>
+// Groups whose maps have two different |s| (NS = 2) run both spin rows beside
+// the shared order chains, started from the launch's spin tables (MB.stab);
+// the work list is that of the larger |s| (its first segment reaches past every
+// chain start of both spin rows).  Each map's records carry the scale of its
+// own spin row.
+template <bool EXT, int G, int NS>
 __global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(G == 4 ? 3 : 4))) void k_contract_inverse2_mix(
     MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
-    const double2* __restrict__ lco, const double* __restrict__ stab, const int* __restrict__ stabk,
-    const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work,
-    int L, int Lp, int s, int ckg)
+    const double2* __restrict__ lco, const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff,
+    const int4* __restrict__ work, int L, int Lp, int ckg)
 {
     extern __shared__ double smem[];
     const MixMaps& maps = MB.g[blockIdx.y];
@@ -1376,10 +1512,19 @@ __global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(G
     const int w = code & 0xff, nseg = (code >> 8) & 0xff, lead = (code >> 16) & 0xff;
     const bool bar = (code >> 24) & 1;   // the same for every slot of the workgroup
     bool any = false;                    // does any map of the group have this (n0, m0) block?
-    for (int b = 0; b < maps.n; ++b) any |= (n0 < maps.L[b] && m0 < maps.L[b]);
+    for (int b = 0; b < mix_n(maps); ++b) any |= (n0 < maps.L[b] && m0 < maps.L[b]);
     const double* __restrict__ Rt = Rtg;               // 1/sqrt table, L1-resident
     float* region = (float*)smem + slot * inv2m_slot_floats(G);
-    const int as = s < 0 ? -s : s;
+    SpinSet<NS> sset;
+    SpinTabs<NS> tj;
+    int asmax = 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        sset.a[j] = MB.as[j];
+        asmax = max(asmax, MB.as[j]);
+        tj.val[j] = MB.stab[j];
+        tj.k[j] = MB.stabk[j];
+    }
     const int n = n0 + lane;
     const bool valid = item && n < L;
     const int ne = valid ? n : L - 1;
@@ -1394,17 +1539,18 @@ __global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(G
     if (item && any) {
         InvGeo geo;
         geo.lstart = max(n0, m0) & ~1;
-        geo.lA = max(max(n0 + 64, m0 + 2), as + 1);   // every chain start of both orders lies below lA
+        geo.lA = max(max(n0 + 64, m0 + 2), asmax + 1);   // every chain start lies below lA
         geo.cs = bounds & 0xffff;
         geo.ce = (int)((unsigned)bounds >> 16);
         geo.nseg = nseg;
-        InvLane2<EXT> st;
+        InvLane2<EXT, NS> st;
         bool anyscaled;
-        const InvSeg g = inv2_setup<EXT>(st, anyscaled, geo, w, n, m0, L, Lp, as, ckg, lco, edge, edgek, stab, stabk,
-                                         cki, ckik, ckoff);
+        const InvSeg g = inv2_setup<EXT, NS>(st, anyscaled, geo, w, n, m0, L, Lp, sset, ckg, lco, edge, edgek, tj, cki,
+                                             ckik, ckoff);
         if (g.active)
-            inv2m_segment<EXT, G>(st, acc, g, jend, geo.lstart, ne, nd, m0, inv2_rows(nullptr, lco, m0, as, Lp, L),
-                                  Rt, region, maps, lane, anyscaled);
+            inv2m_segment<EXT, G, NS>(st, acc, g, jend, geo.lstart, ne, nd, m0,
+                                      inv2_rows(nullptr, lco, m0, sset.a[0], Lp, L, sset.a[NS - 1]), Rt, region, maps,
+                                      lane, anyscaled);
     }
 
     double sum[2][G][4];
@@ -1441,14 +1587,15 @@ __global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(G
         return;
     }
     if (!valid) return;
-    const double fsp = sgn(s) * ((s >= 0) ? sgn(n) : 1.0);
-    const double fsm = sgn(s) * ((s < 0) ? sgn(n) : 1.0);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const int m = m0 + c;
 #pragma unroll
         for (int b = 0; b < G; ++b) {
-            if (b >= maps.n) continue;
+            if (b >= mix_n(maps)) continue;
+            const int s = mix_spin(MB, maps, b);
+            const double fsp = sgn(s) * ((s >= 0) ? sgn(n) : 1.0);
+            const double fsm = sgn(s) * ((s < 0) ? sgn(n) : 1.0);
             const int Lb = maps.L[b];
             if (n >= Lb || m >= Lb) continue;
             double2* F = maps.dst[b];
@@ -1486,6 +1633,13 @@ hipError_t launch_contract_forward(const Plan& p, int s, int real, const double*
     return real ? fwd_go<false, true>(p, s, in0, stride, B, st) : fwd_go<false, false>(p, s, in0, stride, B, st);
 }
 
+hipError_t launch_spin_flip(int L, const Batch& B, hipStream_t st)
+{
+    const int n = L * (L + 1) / 2;
+    hipLaunchKernelGGL(k_spin_flip, dim3((n + 255) / 256, B.n), dim3(256), 0, st, B, L);
+    return hipGetLastError();
+}
+
 hipError_t launch_real_fold(int L, const Batch& B, hipStream_t st)
 {
     const dim3 grid((L + 255) / 256, L, B.n);
@@ -1493,11 +1647,11 @@ hipError_t launch_real_fold(int L, const Batch& B, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_inverse_stream(const Plan& p, int s, int real, const Batch& B, int out32, hipStream_t st)
+hipError_t launch_inverse_stream(const Plan& p, int real, const Batch& B, int out32, hipStream_t st)
 {
     const dim3 grid((p.Lp + STR_L - 1) / STR_L, (p.L + STR_M - 1) / STR_M, B.n);
-    if (out32) hipLaunchKernelGGL(k_inverse_stream<1>, grid, dim3(256), 0, st, B, p.cl, p.lco, p.L, p.Lp, s, real);
-    else hipLaunchKernelGGL(k_inverse_stream<0>, grid, dim3(256), 0, st, B, p.cl, p.lco, p.L, p.Lp, s, real);
+    if (out32) hipLaunchKernelGGL(k_inverse_stream<1>, grid, dim3(256), 0, st, B, p.cl, p.lco, p.L, p.Lp, real);
+    else hipLaunchKernelGGL(k_inverse_stream<0>, grid, dim3(256), 0, st, B, p.cl, p.lco, p.L, p.Lp, real);
     return hipGetLastError();
 }
 
@@ -1539,29 +1693,44 @@ hipError_t mix_attr(K kernel, size_t bytes)
     return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <bool EXT, int G>
-hipError_t fwd_mix_go(const Plan& p, int s, const MixBatch& maps, hipStream_t st)
+template <bool EXT, int G, int NS>
+hipError_t fwd_mix_go(const Plan& p, const MixBatch& maps, hipStream_t st)
 {
     const size_t lds = mix_lds_forward(G);
-    hipError_t e = mix_attr(k_contract_forward_mix<EXT, G>, lds);
+    hipError_t e = mix_attr(k_contract_forward_mix<EXT, G, NS>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_contract_forward_mix<EXT, G>), dim3(p.nworkf4, maps.ng), dim3(64 * SEG_MAX), lds, st,
-                       maps, p.rtab, p.edge, p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, s, p.ckfg);
+    hipLaunchKernelGGL((k_contract_forward_mix<EXT, G, NS>), dim3(p.nworkf4, maps.ng), dim3(64 * SEG_MAX), lds, st,
+                       maps, p.rtab, p.edge, p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, p.ckfg);
     return hipGetLastError();
 }
 
-template <bool EXT, int G>
-hipError_t inv_mix_go(const Plan& p, const SpinTable& sp, int s, const MixBatch& maps, hipStream_t st)
+template <bool EXT, int G, int NS>
+hipError_t inv_mix_go(const Plan& p, const SpinTable& wsp, const MixBatch& maps, hipStream_t st)
 {
     CkOff off;
     for (int j = 0; j < CKI_MAX; ++j) off.off[j] = p.cki_off[j];
     const size_t lds = (size_t)SEGI_MAX * inv2m_slot_floats(G) * sizeof(float);
-    hipError_t e = mix_attr(k_contract_inverse2_mix<EXT, G>, lds);
+    hipError_t e = mix_attr(k_contract_inverse2_mix<EXT, G, NS>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_contract_inverse2_mix<EXT, G>), dim3(sp.nwinv, maps.ng), dim3(64 * SEGI_MAX), lds, st,
-                       maps, p.rtab, p.edge, p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s,
-                       p.ckg);
+    hipLaunchKernelGGL((k_contract_inverse2_mix<EXT, G, NS>), dim3(wsp.nwinv, maps.ng), dim3(64 * SEGI_MAX), lds, st,
+                       maps, p.rtab, p.edge, p.edgek, p.lco, p.cki, p.ckik, off, wsp.winv, p.L, p.Lp, p.ckg);
     return hipGetLastError();
+}
+
+template <bool EXT, int NS>
+hipError_t fwd_mix_g(const Plan& p, const MixBatch& maps, int G, hipStream_t st)
+{
+    if (G == 1) return fwd_mix_go<EXT, 1, NS>(p, maps, st);
+    if (G == 2) return fwd_mix_go<EXT, 2, NS>(p, maps, st);
+    return fwd_mix_go<EXT, 4, NS>(p, maps, st);
+}
+
+template <bool EXT, int NS>
+hipError_t inv_mix_g(const Plan& p, const SpinTable& wsp, const MixBatch& maps, int G, hipStream_t st)
+{
+    if (G == 1) return inv_mix_go<EXT, 1, NS>(p, wsp, maps, st);
+    if (G == 2) return inv_mix_go<EXT, 2, NS>(p, wsp, maps, st);
+    return inv_mix_go<EXT, 4, NS>(p, wsp, maps, st);
 }
 
 }  // namespace
@@ -1574,39 +1743,34 @@ int mix_group_max()
     return 1;
 }
 
-bool mix_ok(const MixBatch& maps, int G)
+// Groups of one launch: 1..G maps each; ns in [1, NS] spin rows, every map's
+// row below ns.
+bool mix_ok(const MixBatch& maps, int G, int NS)
 {
-    if (maps.ng < 1 || maps.ng > MIXG || G > GMAX) return false;
-    for (int g = 0; g < maps.ng; ++g)
-        if (maps.g[g].n < 1 || maps.g[g].n > G) return false;
+    if (maps.ng < 1 || maps.ng > MIXG || G > GMAX || NS < 1 || NS > NSMAX || maps.ns < 1 || maps.ns > NS)
+        return false;
+    for (int g = 0; g < maps.ng; ++g) {
+        const MixMaps& m = maps.g[g];
+        if (mix_n(m) < 1 || mix_n(m) > G) return false;
+        for (int b = 0; b < mix_n(m); ++b)
+            if (mix_row(m, b) >= maps.ns) return false;
+    }
     return true;
 }
 
-hipError_t launch_contract_forward_mix(const Plan& p, int s, const MixBatch& maps, int G, hipStream_t st)
+hipError_t launch_contract_forward_mix(const Plan& p, const MixBatch& maps, int G, int NS, hipStream_t st)
 {
-    if (!mix_ok(maps, G)) return hipErrorInvalidValue;
-    if (p.ext) {
-        if (G == 1) return fwd_mix_go<true, 1>(p, s, maps, st);
-        if (G == 2) return fwd_mix_go<true, 2>(p, s, maps, st);
-        return fwd_mix_go<true, 4>(p, s, maps, st);
-    }
-    if (G == 1) return fwd_mix_go<false, 1>(p, s, maps, st);
-    if (G == 2) return fwd_mix_go<false, 2>(p, s, maps, st);
-    return fwd_mix_go<false, 4>(p, s, maps, st);
+    if (!mix_ok(maps, G, NS)) return hipErrorInvalidValue;
+    if (p.ext) return NS == 2 ? fwd_mix_g<true, 2>(p, maps, G, st) : fwd_mix_g<true, 1>(p, maps, G, st);
+    return NS == 2 ? fwd_mix_g<false, 2>(p, maps, G, st) : fwd_mix_g<false, 1>(p, maps, G, st);
 }
 
-hipError_t launch_contract_inverse_mix(const Plan& p, const SpinTable& sp, int s, const MixBatch& maps, int G,
+hipError_t launch_contract_inverse_mix(const Plan& p, const SpinTable& wsp, const MixBatch& maps, int G, int NS,
                                        hipStream_t st)
 {
-    if (!mix_ok(maps, G)) return hipErrorInvalidValue;
-    if (p.ext) {
-        if (G == 1) return inv_mix_go<true, 1>(p, sp, s, maps, st);
-        if (G == 2) return inv_mix_go<true, 2>(p, sp, s, maps, st);
-        return inv_mix_go<true, 4>(p, sp, s, maps, st);
-    }
-    if (G == 1) return inv_mix_go<false, 1>(p, sp, s, maps, st);
-    if (G == 2) return inv_mix_go<false, 2>(p, sp, s, maps, st);
-    return inv_mix_go<false, 4>(p, sp, s, maps, st);
+    if (!mix_ok(maps, G, NS)) return hipErrorInvalidValue;
+    if (p.ext) return NS == 2 ? inv_mix_g<true, 2>(p, wsp, maps, G, st) : inv_mix_g<true, 1>(p, wsp, maps, G, st);
+    return NS == 2 ? inv_mix_g<false, 2>(p, wsp, maps, G, st) : inv_mix_g<false, 1>(p, wsp, maps, G, st);
 }
 
 }  // namespace mw

@@ -108,22 +108,40 @@ struct SpinTable {
 // Chains per lane in the contraction kernels (work-list granularity in m).
 constexpr int MT_FWD = 2;
 
-// Mixed-precision contraction: a group of up to GMAX maps of one spin shares the
-// FP64 chains.  src/dst are per-map device pointers (FP32 staged H or stream;
-// f_lm or F), L the per-map band-limits (<= the plan's).
+// Mixed-precision contraction: a group of up to GMAX maps shares the FP64 order
+// chains; its maps have at most NSMAX different |s|, the spin rows of the launch
+// (MixBatch::as, the same for all its groups).  src/dst are per-map device
+// pointers (FP32 staged H or stream; f_lm or F), L the per-map band-limits
+// (<= the plan's); meta packs the map count (bits 0-2), for each map b the row of
+// its |s| (bit 4+b) and the sign of its spin (bit 8+b).  Passed by value (the
+// launch's kernel arguments stay under 1 KB).
 constexpr int GMAX = 4;
+constexpr int NSMAX = 2;
 struct MixMaps {
     const float* src[GMAX];
     double2* dst[GMAX];
     int L[GMAX];
-    int n;
+    int meta;
 };
-// Groups of one mixed launch (blockIdx.y = group).
+__host__ __device__ inline int mix_n(const MixMaps& m) { return m.meta & 7; }
+__host__ __device__ inline int mix_row(const MixMaps& m, int b) { return (m.meta >> (4 + b)) & 1; }
+__host__ __device__ inline bool mix_neg(const MixMaps& m, int b) { return (m.meta >> (8 + b)) & 1; }
+// Groups of one mixed launch (blockIdx.y = group), with their spin rows |s_j|,
+// j < ns, and (inverse only) the spin tables Delta^l_{n,|s_j|} of those rows.
 constexpr int MIXG = 8;
 struct MixBatch {
     MixMaps g[MIXG];
     int ng;
+    int ns;
+    int as[NSMAX];
+    const double* stab[NSMAX];
+    const int* stabk[NSMAX];
 };
+__host__ __device__ inline int mix_spin(const MixBatch& B, const MixMaps& m, int b)
+{
+    const int a = B.as[mix_row(m, b)];
+    return mix_neg(m, b) ? -a : a;
+}
 
 // Maps of one batched launch (blockIdx.y, or z for 3-D grids, = map): per-map
 // input and output device pointers and spins; all maps of a launch share the
@@ -164,8 +182,9 @@ hipError_t launch_theta_forward_adjoint(const Plan& p, const Batch& B, hipStream
 // inverse writes only the orders m >= 0 of F.
 hipError_t launch_contract_forward(const Plan& p, int s, int real, const double* in0, size_t stride, const Batch& B,
                                    hipStream_t st);
-// Inverse coefficient stream (L x Lp x 4 doubles, or FP32 at [(m*4+comp)*Lp + l]).
-hipError_t launch_inverse_stream(const Plan& p, int s, int real, const Batch& B, int out32, hipStream_t st);
+// Inverse coefficient stream (L x Lp x 4 doubles, or FP32 at [(m*4+comp)*Lp + l]),
+// each map with its own spin B.s[k].
+hipError_t launch_inverse_stream(const Plan& p, int real, const Batch& B, int out32, hipStream_t st);
 hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, int real, const double* in0,
                                    size_t stride, const Batch& B, hipStream_t st);
 // half = 1: real scalar maps, only the orders m >= 0 (for launch_phi_inverse with real = 2).
@@ -179,11 +198,16 @@ hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc
 // Adjoint of the real-map coefficient expansion: y_{l,m} += (-1)^m conj(y_{l,-m}),
 // y_{l,-m} = 0 for m > 0 (in place on the L^2 layout of B.out).
 hipError_t launch_real_fold(int L, const Batch& B, hipStream_t st);
+// Coefficients of the conjugate maps (spin -s) of the maps of B (spin B.s[k]):
+// out_{l,m} = (-1)^{s+m} conj(in_{l,-m}); out may equal in.
+hipError_t launch_spin_flip(int L, const Batch& B, hipStream_t st);
 // Largest group size (1, 2 or 4) whose staging fits the LDS (independent of L).
 int mix_group_max();
-// Mixed-precision contractions of up to MIXG groups (each maps.n <= G <= GMAX, G in {1,2,4}).
-hipError_t launch_contract_forward_mix(const Plan& p, int s, const MixBatch& maps, int G, hipStream_t st);
-hipError_t launch_contract_inverse_mix(const Plan& p, const SpinTable& sp, int s, const MixBatch& maps, int G,
+// Mixed-precision contractions of up to MIXG groups (each maps.n <= G <= GMAX, G
+// in {1,2,4}; each with at most NS <= NSMAX spin rows).  The inverse runs the work
+// list of wsp, the spin table of the largest |s| of the launch's groups.
+hipError_t launch_contract_forward_mix(const Plan& p, const MixBatch& maps, int G, int NS, hipStream_t st);
+hipError_t launch_contract_inverse_mix(const Plan& p, const SpinTable& wsp, const MixBatch& maps, int G, int NS,
                                        hipStream_t st);
 
 // Explicit quadrature (mw_quad.hip): the weights q(theta_t), t < L, into q

@@ -248,3 +248,24 @@ def rel_per_degree(got, ref, L):
 # are dominated by the low-degree content of the data, so the bound is wider
 # than the global one.
 PER_DEGREE_TOL = 1e-3
+
+
+def test_mixed_groups_across_spins(orc, tc, mw):
+    """One mixed-precision call with maps of several spins at one band-limit:
+    groups of four share the order chains with two spin rows ({0, 1} and {2, 3}
+    here).  Every map against the oracle; the forward also bitwise against
+    single calls (its work list does not depend on the spin)."""
+    L = 128
+    spins = [0, 2, -2, 3, 0, 1, -1, 2]
+    n = len(spins)
+    flm = [mwsynth.flm_gaussian(L, s, seed=21000 + i, decay=1.0) for i, s in enumerate(spins)]
+    mw.prepare([L] * n, spins, precision=FP32C)
+    maps = [host(tc, t) for t in mw.inverse_batch([dev(tc, f) for f in flm], [L] * n, spins, precision=FP32C)]
+    grids = [mwsynth.grid_gaussian(L, seed=21100 + i) for i in range(n)]
+    fw = [host(tc, t) for t in mw.forward_batch([dev(tc, g) for g in grids], [L] * n, spins, precision=FP32C)]
+    for i, s in enumerate(spins):
+        print("  map %d spin %d" % (i, s), flush=True)
+        assert rel(maps[i], orc.inverse(flm[i], L, s)) < TOL, i
+        assert rel(fw[i], orc.forward(grids[i], L, s)) < TOL, i
+        single = host(tc, mw.forward(dev(tc, grids[i]), L, s, precision=FP32C))
+        assert np.array_equal(fw[i], single), i

@@ -409,3 +409,21 @@ def test_compact_adjoint_dot_products(orc, L, s):
     assert abs(lhs - rhs) < 1e-13 * abs(lhs)
     lhs, rhs = np.vdot(x, orc.inverse_compact(y, L, s)), np.vdot(orc.inverse_adjoint_compact(x, L, s), y)
     assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+# --------------------------------------------------------------------------
+# Spin -s coefficients of the conjugate map (Sec. IV-G)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("L,s", [(6, 0), (7, 2), (8, -3)])
+def test_conjugate_map_has_flipped_coefficients(orc, L, s):
+    # conj(sY_lm) = (-1)^{s+m} (-s)Y_{l,-m}, so conj(f) of spin -s has coefficients
+    # (-1)^{s+m} conj(f_{l,-m}); checked on brute-force synthesis and on the
+    # oracle's forward of a grid that is not band-limited (the algorithm commutes
+    # with conjugation as well)
+    flm = mwsynth.flm_gaussian(L, s, seed=1300 + L)
+    l, m = mwsynth.lm_arrays(L)
+    flip = (-1.0) ** (s + m) * np.conj(flm[l * l + l - m])
+    assert rel_inf(np.conj(brute.synthesis(flm, L, s)), brute.synthesis(flip, L, -s)) < 1e-13
+    x = mwsynth.grid_gaussian(L, seed=1310 + L)
+    a, b = orc.forward(x, L, s), orc.forward(np.conj(x), L, -s)
+    assert rel_inf(b, (-1.0) ** (s + m) * np.conj(a[l * l + l - m])) < 1e-13
