@@ -38,6 +38,14 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+PEAK_FP32_MFMA = 157.3e12   # dense FP32 matrix-core peak
+
+
+def contraction_term_flops(L, s, real=False):
+    """The contraction part of contraction_flops: 4 flop per folded term."""
+    return 4.0 * sum(((l + 1) if real else (2 * l + 1)) * (l + 1) for l in range(abs(s), L))
+
+
 def contraction_flops(L, s, real=False):
     """Algorithmic flops of one contraction launch: 4 per folded term (l, m, m'>=0)
     (complex H times the real product Delta*Delta), plus 5 per Wigner
@@ -51,6 +59,19 @@ def contraction_flops(L, s, real=False):
 def rel(a, b):
     import numpy as np
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def rel_per_degree(got, ref, L):
+    """Per-degree relative error of coefficient vectors: the largest over l of
+    max_m |got - ref| / max_m |ref| (degrees whose reference is zero skipped)."""
+    import numpy as np
+    worst = 0.0
+    for l in range(L):
+        sl = slice(l * l, (l + 1) * (l + 1))
+        den = float(np.abs(ref[sl]).max())
+        if den > 0:
+            worst = max(worst, float(np.abs(got[sl] - ref[sl]).max()) / den)
+    return worst
 
 
 def time_steps(torch, step, steps, warmup):
@@ -125,7 +146,26 @@ def batched_workload(torch, mw, dev, steps, warmup, precision, graph=False):
         ref = maps[b]["flm"]
         got = back[b].cpu().numpy()
         err = max(err, rel(got, ref))
-    return ms, len(maps), err
+    # one step with libmw's per-launch events: the summed time of each stage and
+    # the contraction roofline over the whole batch (algorithmic flops of every
+    # map's two contractions over the two contraction stages' summed time)
+    roof = None
+    if not graph:
+        torch.cuda.synchronize()
+        mw.profile_enable(True)
+        step()
+        prof = mw.profile_read()
+        mw.profile_enable(False)
+        t_c = sum(prof[k][0] for k in ("contract_forward", "contract_inverse") if k in prof) * 1e-3
+        fl = sum(contraction_flops(L, sp, real=bool(r)) for L, sp, r in zip(Ls, ss, rs)) * 2
+        terms = sum(contraction_term_flops(L, sp, real=bool(r)) for L, sp, r in zip(Ls, ss, rs)) * 2
+        roof = {"stages_ms": {k: v[0] for k, v in prof.items()},
+                "contraction": {"bound": "alu", "achieved": fl / t_c / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                                "unit": "TFLOP/s", "frac": fl / t_c / PEAK_FP64_VALU}}
+        if precision != mw.FP64:
+            roof["contraction"]["mfma"] = {"achieved": terms / t_c / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                                           "unit": "TFLOP/s", "frac": terms / t_c / PEAK_FP32_MFMA}
+    return ms, len(maps), err, roof
 
 
 def large_workload(torch, mw, dev, steps, warmup):
@@ -147,12 +187,15 @@ def large_workload(torch, mw, dev, steps, warmup):
 
         ms = time_steps(torch, step, steps, warmup)
         pk = kernel_profile(mw, step, steps)
-        err = rel(back.cpu().numpy(), flm_h)
+        back_h = back.cpu().numpy()
+        err = rel(back_h, flm_h)
+        err_deg = rel_per_degree(back_h, flm_h, L)
         flops = contraction_flops(L, 0, real=True)
         dom = "contract_forward" if pk.get("contract_forward", 0) >= pk.get("contract_inverse", 0) \
             else "contract_inverse"
         ach = flops / (pk[dom] * 1e-3)
         out[name] = {"round_trips_per_s": 1e3 / ms, "ms_per_step": ms, "round_trip_rel_err": err,
+                     "round_trip_rel_err_per_degree": err_deg,
                      "kernels": {k: {"avg_us": 1e3 * v} for k, v in pk.items()}}
         if prec == mw.FP64:
             out[name]["roofline"] = {"kernel": dom, "bound": "alu", "achieved": ach / 1e12,
@@ -175,6 +218,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle baseline sample (whole round trips)")
+    ap.add_argument("--cpu-1core", action="store_true",
+                    help="also time one oracle round trip on one host core (about 100 s at L=512)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed work, negate a float64 buffer of this many MiB once "
                          "(a plain read+write kernel of known size, for HBM counter calibration)")
@@ -251,6 +296,7 @@ def main():
                                "f_lm ~ (N+iN)/(l+1), seed 1002" % (s, L), "L": L, "spin": s,
                    "precision": "fp64", "maps_per_step": 1},
         "round_trip_rel_err": rel(back_h, flm_h),
+        "round_trip_rel_err_per_degree": rel_per_degree(back_h, flm_h, L),
         "wall_ms_per_step": 1e3 * wall / args.steps,
         "kernels": kernels,
         "dominant_kernel": dom,
@@ -262,8 +308,19 @@ def main():
                   "stated_max_rel_err": 1e-6,
                   "rel_err_vs_fp64": {"inverse_map": rel(x32_h, x_h), "forward_coeffs": rel(back32_h, back_h)},
                   "round_trip_rel_err": rel(back32_h, flm_h),
+                  "round_trip_rel_err_per_degree": rel_per_degree(back32_h, flm_h, L),
                   "kernels": {k: {"avg_us": 1e3 * v} for k, v in per_kernel_mixed.items()}},
     }
+    # mixed path: the chains stay FP64 (VALU-bound), the contraction's products
+    # run on the FP32 matrix cores; both rates for the dominant mixed kernel
+    dom_m = "contract_forward" if per_kernel_mixed.get("contract_forward", 0) >= \
+        per_kernel_mixed.get("contract_inverse", 0) else "contract_inverse"
+    t_m = per_kernel_mixed[dom_m] * 1e-3
+    result["mixed"]["roofline"] = {
+        "kernel": dom_m, "bound": "alu", "achieved": flops / t_m / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+        "unit": "TFLOP/s", "frac": flops / t_m / PEAK_FP64_VALU, "flops_per_launch": flops,
+        "mfma": {"achieved": contraction_term_flops(L, s) / t_m / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                 "unit": "TFLOP/s", "frac": contraction_term_flops(L, s) / t_m / PEAK_FP32_MFMA}}
     tr = TRAFFIC.get((dom_c, L, s))
     if tr is not None and tr["source_sha256"] == kernel_source_hash():
         result["roofline"]["traffic"] = tr["bytes"]
@@ -272,9 +329,11 @@ def main():
         batched = {}
         for name, prec, graph in (("fp64", mw.FP64, False), ("fp32c", mw.FP32C, False),
                                   ("fp64_graph", mw.FP64, True), ("fp32c_graph", mw.FP32C, True)):
-            ms_b, nmaps, err_b = batched_workload(torch, mw, dev, args.batch_steps, 2, prec, graph)
+            ms_b, nmaps, err_b, roof = batched_workload(torch, mw, dev, args.batch_steps, 2, prec, graph)
             batched[name] = {"maps_round_trips_per_s": nmaps * 1e3 / ms_b, "ms_per_step": ms_b,
                              "round_trip_rel_err": err_b}
+            if roof is not None:
+                batched[name]["profile"] = roof
         batched["workload"] = ("256 maps, L uniform on {128,256,512}, spin uniform on {0,2}, 128 with real-map "
                                "coefficient symmetry (s=0 ones on the real path), f_lm ~ N(0,1)/(l+1), seed 1003; "
                                "one step = batched inverse + batched forward")
@@ -299,9 +358,19 @@ def main():
                                   "kind": "oracle",
                                   "sample": "%d full round trips (inverse + forward) of the same L=%d s=%d map, "
                                             "%.1f s" % (count, L, s, dt)}
-        result["max_rel_err_vs_oracle"] = {"inverse_map": rel(x_h, xo), "forward_coeffs": rel(back_h, fo)}
+        if args.cpu_1core:
+            oracle.set_threads(1)
+            t = time.perf_counter()
+            oracle.forward(oracle.inverse(flm_h, L, s), L, s)
+            dt1 = time.perf_counter() - t
+            oracle.set_threads(result["cpu_baseline"]["cores"])
+            result["cpu_baseline_1core"] = {"value": 1.0 / dt1, "unit": "round trips/s", "cores": 1,
+                                            "kind": "oracle", "sample": "1 round trip, %.1f s" % dt1}
+        result["max_rel_err_vs_oracle"] = {"inverse_map": rel(x_h, xo), "forward_coeffs": rel(back_h, fo),
+                                           "forward_coeffs_per_degree": rel_per_degree(back_h, fo, L)}
         result["mixed"]["max_rel_err_vs_oracle"] = {"inverse_map": rel(x32_h, xo),
-                                                    "forward_coeffs": rel(back32_h, fo)}
+                                                    "forward_coeffs": rel(back32_h, fo),
+                                                    "forward_coeffs_per_degree": rel_per_degree(back32_h, fo, L)}
     print(json.dumps(result))
 
 

@@ -82,3 +82,23 @@ def test_workspace_size_is_host_only():
     assert mw.workspace_size([64, 512], [0, 2]) == 2 * mw.workspace_size([512], [2])
     with pytest.raises(mw.MWError):
         mw.workspace_size([0], [0])
+
+
+def test_tune_cache_parser(tmp_path):
+    """The autotuner's cache file: valid lines are taken, malformed ones and other
+    architectures or impossible values skipped (host only)."""
+    p = tmp_path / "tune.txt"
+    p.write_text("gfx950 300 0 12 2\n"
+                 "gfx950 301 1 5 4\n"
+                 "garbage line\n"
+                 "gfx942 302 0 3 2\n"          # another architecture
+                 "gfx950 303 0 3 3\n"          # G not a power of two
+                 "gfx950 99999 0 3 2\n"        # L out of range
+                 "gfx950 304 2 3 2\n"          # reality not 0/1
+                 "gfx950 305 0 3 2 extra\n")   # trailing token
+    assert mw.tune_cache_load(str(p)) == 2
+    assert mw.tuned_group(300, 0, 12) == 2
+    assert mw.tuned_group(301, 1, 5) == 4
+    assert mw.tuned_group(302, 0, 3) == 0
+    assert mw.tuned_group(303, 0, 3) == 0
+    assert mw.tune_cache_load(str(tmp_path / "missing.txt")) == 0
