@@ -418,6 +418,18 @@ __device__ __forceinline__ void bluestein_split(double2* x, const Plan& p, const
     __syncthreads();
 }
 
+// Kernels compiled for one transform length: LOGN = log2 of the length held in
+// LDS (N2, or N2/2 on a split plan), -1 for any length.  With a fixed length the
+// pass count, strides and guards of every transform are compile-time constants.
+template <int LOGN, bool SP>
+__device__ __forceinline__ void fix_length(Plan& p)
+{
+    if constexpr (LOGN > 0) {
+        p.logN2 = LOGN + (SP ? 1 : 0);
+        p.N2 = 1 << p.logN2;
+    }
+}
+
 // Twiddle bases of a kernel's FFTs: length N2, or NH = N2/2 on a split plan.
 template <int RB, bool SP>
 __device__ __forceinline__ FftTw<RB> plan_twiddles(const Plan& p)
@@ -466,9 +478,10 @@ __device__ __forceinline__ double2 spin_phase(int s, int pp, int N1)
 // one stored sample C = f(pi, 0) times e^{i s phi_p} (the form of every
 // band-limited spin-s map at theta = pi, where only m = s survives);
 // 2 = C at p = 0 and zeros elsewhere (the adjoint of keeping only p = 0).
-template <int REAL, int RB, bool SP>
+template <int REAL, int RB, bool SP, int LOGN>
 __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc, int pole)
 {
+    fix_length<LOGN, SP>(p);
     extern __shared__ double2 A[];
     const void* __restrict__ map = B.in[blockIdx.y];
     double2* __restrict__ G = (double2*)B.out[blockIdx.y];
@@ -522,9 +535,10 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc,
 // not overlap and fold onto one half grid, and the fold of the output is split
 // in the same way: H_n = P_n + w^n O_n - (-1)^{m+s} w^{NH-n} O_{NH-n} with
 // P_n = E_n + (-1)^{m+s} E_{NH-n} from the even pass (P_0 = E_0, H_0 = P_0 + O_0).
-template <int ADJ_INV, int OUT32, int HALF, int RB, bool SP>
+template <int ADJ_INV, int OUT32, int HALF, int RB, bool SP, int LOGN>
 __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
 {
+    fix_length<LOGN, SP>(p);
     extern __shared__ double2 A[];
     const int s = B.s[blockIdx.y];
     const double2* __restrict__ G = (const double2*)B.in[blockIdx.y];
@@ -664,6 +678,172 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
     }
 }
 
+// Forward theta stage for a pair of orders with extensions of opposite parity
+// (Sec. IV-B..IV-D): the order a with (-1)^{m_a+s} = +1 extends its column
+// symmetrically about theta = pi, the order b antisymmetrically, so the DFT of
+// their sum splits into a symmetric part (a's F_{m'}) and an antisymmetric part
+// (b's F_{m'}, without b's pole sample, whose DFT is symmetric and is added
+// separately).  The fold H_n = G_n + (-1)^{m+s} G_{-n} of a symmetric or
+// antisymmetric F keeps only the even part w_e of the weights, so one
+// correlation with w_e serves both orders:  Y = 2 pi sum_k F_k w_e(k - n),
+//   H^a_0 = Y_0,  H^a_n = Y_n + Y_{-n},  H^b_n = Y_n - Y_{-n}  (n >= 1),
+// and b's pole sample P = G^b(theta_{L-1}) and the odd weights w(+-1) enter
+// only H^b_0 = 2 pi^2 i (F_1 - F_{-1})/2 + P sum_{|k|<L} w_e(k)/N1 and
+// H^b_{L-1} += -i pi (-1)^L P/N1.  One Bluestein DFT and one correlation per
+// two orders instead of two of each.  Pairs: (m, -m-1), m = 0..L-2, and L-1
+// alone; real maps (HALF): (2c, 2c+1), only the orders m >= 0.
+template <int OUT32, int HALF, int RB, int LOGN>
+__global__ __launch_bounds__(512) void k_theta_forward_pair(Plan p, Batch B)
+{
+    fix_length<LOGN, false>(p);
+    extern __shared__ double2 A[];
+    __shared__ double2 f1[2];   // F_{+1} and F_{-1} of the packed column
+    const int s = B.s[blockIdx.y];
+    const double2* __restrict__ G = (const double2*)B.in[blockIdx.y];
+    void* __restrict__ Hout = B.out[blockIdx.y];
+    const int L = p.L, N1 = p.N1, N2 = p.N2;
+    const int npair = HALF ? (L + 1) >> 1 : L;
+    const int c = xcd_column(npair);
+    if (c >= npair) return;
+    const int m1 = HALF ? 2 * c : c, m2 = HALF ? 2 * c + 1 : -(c + 1);
+    const bool has2 = HALF ? (m2 < L) : (c < L - 1);
+    const bool m1sym = ((m1 + s) & 1) == 0;
+    const int ma = m1sym ? m1 : m2, mb = m1sym ? m2 : m1;
+    const bool hasa = m1sym || has2, hasb = !m1sym || has2;
+    const double2* __restrict__ Ga = G + (size_t)(ma + L - 1) * L;
+    const double2* __restrict__ Gb = G + (size_t)(mb + L - 1) * L;
+    const FftTw<RB> T = plan_twiddles<RB, false>(p);
+    // the packed extended column, chirped and zero-padded
+    auto ld = [&](int j) {
+        if (j >= N1) return make_double2(0.0, 0.0);
+        double2 v = make_double2(0.0, 0.0);
+        if (j < L) {
+            if (hasa) v = Ga[j];
+            if (hasb && j != L - 1) v = cadd(v, Gb[j]);
+        } else {
+            const int t = 2 * L - 2 - j;
+            if (hasa) v = Ga[t];
+            if (hasb) v = csub(v, Gb[t]);
+        }
+        return cmul(v, p.chirp[j]);
+    };
+    const double scale = p.thsc;
+    block_fft<-1, RB>(A, N2, p.logN2, T, p.bhat, PlainStore(), ld);
+    block_fft<+1, RB>(A, N2, p.logN2, T, nullptr, [&](int k, double2 v) {
+        if (k < N1) {
+            const double2 f = cscale(cmul(v, p.thwc[k]), scale);
+            A[Pr<RB>(k < L ? k : k + (N2 - N1))] = f;
+            if (k == 1) f1[0] = f;
+            if (k == N1 - 1) f1[1] = f;
+        } else {
+            A[Pr<RB>(k - N1 + L)] = make_double2(0.0, 0.0);
+        }
+    });
+    block_fft<+1, RB>(A, N2, p.logN2, T, p.whate);
+    block_fft<-1, RB>(A, N2, p.logN2, T);
+    // b's pole sample and the odd-weight term of H^b_0 (L >= 2: with L = 1 the
+    // only order is 0 and the pair has no b unless s is odd; then F_{+-1} = 0)
+    const double2 P = hasb ? Gb[L - 1] : make_double2(0.0, 0.0);
+    const double2 b1 = (L >= 2) ? cscale(csub(f1[0], f1[1]), 0.5) : make_double2(0.0, 0.0);
+    const double PI2 = 9.8696044010893586188;   // pi^2
+    const double sgnL = (L & 1) ? -1.0 : 1.0;
+    auto put = [&](int m, int n, double2 v) {
+        const double sig = ((m + s) & 1) ? -1.0 : 1.0;
+        const int am = m < 0 ? -m : m;
+        // the -m half: H_{-m,n} itself, or (-1)^{m+s} conj(H_{m,n}) for a real map
+        const double2 vm = HALF ? cscale(cconj(v), sig) : v;
+        const bool pos = m >= 0, neg = HALF || m <= 0;
+        if (OUT32) {
+            float* h = (float*)Hout + (size_t)am * 4 * p.Lp + n;
+            const double par = (n & 1) ? -1.0 : 1.0;
+            if (pos) {
+                const double sg = (s >= 0) ? par : 1.0;
+                h[0] = (float)(sg * v.x);
+                h[(size_t)p.Lp] = (float)(sg * v.y);
+            }
+            if (neg) {
+                const double sg = (s < 0) ? par : 1.0;
+                h[2 * (size_t)p.Lp] = (float)(sg * vm.x);
+                h[3 * (size_t)p.Lp] = (float)(sg * vm.y);
+            }
+        } else {
+            double* rec = (double*)Hout + ((size_t)am * p.Lp + n) * 4;
+            if (pos) { rec[0] = v.x; rec[1] = v.y; }
+            if (neg) { rec[2] = vm.x; rec[3] = vm.y; }
+        }
+    };
+    for (int n = threadIdx.x; n < p.Lp; n += blockDim.x) {
+        double2 ha = make_double2(0.0, 0.0), hb = make_double2(0.0, 0.0);
+        if (n == 0) {
+            ha = A[Pr<RB>(0)];
+            // 2 pi (i pi/2)(F_1 - F_{-1}) + P sum w_e / N1
+            hb = cadd(make_double2(-2.0 * PI2 * b1.y, 2.0 * PI2 * b1.x), cscale(P, p.wsum_e / (double)N1));
+        } else if (n < L) {
+            const double2 yp = A[Pr<RB>(n)], ym = A[Pr<RB>(N2 - n)];
+            ha = cadd(yp, ym);
+            hb = csub(yp, ym);
+            if (n == L - 1) {   // -i pi (-1)^L P / N1
+                const double f = 3.14159265358979323846 * sgnL / (double)N1;
+                hb = cadd(hb, make_double2(f * P.y, -f * P.x));
+            }
+        }
+        if (hasa) put(ma, n, ha);
+        if (hasb) put(mb, n, hb);
+    }
+}
+
+// Inverse theta stage for a pair of orders of opposite parity (Eq.(Fmt)): the
+// unfolded F_{m,m'} of order a is symmetric in m' and that of order b
+// antisymmetric (Eq.(Fmm_sym1); its m' = 0 entry vanishes), so
+// F_a(theta) + F_b(theta) over the whole period gives both orders:
+// F_a(theta_t) = (x_t + x_{2L-2-t})/2 and F_b(theta_t) = (x_t - x_{2L-2-t})/2
+// for t < L-1 (theta_{2L-2-t} = 2 pi - theta_t), F_a = x_{L-1} and F_b = 0 at the
+// pole.  One Bluestein DFT per two orders.  Pairs as in k_theta_forward_pair.
+template <int HALF, int RB, int LOGN>
+__global__ __launch_bounds__(512) void k_theta_inverse_pair(Plan p, Batch B)
+{
+    fix_length<LOGN, false>(p);
+    extern __shared__ double2 A[];
+    const int s = B.s[blockIdx.y];
+    const double2* __restrict__ F = (const double2*)B.in[blockIdx.y];
+    double2* __restrict__ Ft = (double2*)B.out[blockIdx.y];
+    const int L = p.L, N1 = p.N1;
+    const int npair = HALF ? (L + 1) >> 1 : L;
+    const int c = xcd_column(npair);
+    if (c >= npair) return;
+    const int m1 = HALF ? 2 * c : c, m2 = HALF ? 2 * c + 1 : -(c + 1);
+    const bool has2 = HALF ? (m2 < L) : (c < L - 1);
+    const bool m1sym = ((m1 + s) & 1) == 0;
+    const int ma = m1sym ? m1 : m2, mb = m1sym ? m2 : m1;
+    const bool hasa = m1sym || has2, hasb = !m1sym || has2;
+    const int ia = ma + L - 1, ib = mb + L - 1;
+    const double2* __restrict__ Fa = F + (size_t)ia * L;
+    const double2* __restrict__ Fb = F + (size_t)ib * L;
+    const FftTw<RB> T = plan_twiddles<RB, false>(p);
+    bluestein_core<RB>(A, p, T, [&](int j) {   // conj of the packed unfolded F times e^{-i m' pi/N1} chirp_j
+        if (j >= N1) return make_double2(0.0, 0.0);
+        const int mp = (j <= L - 1) ? j : j - N1;
+        const int n = mp < 0 ? -mp : mp;
+        double2 f = make_double2(0.0, 0.0);
+        if (hasa) f = Fa[n];
+        if (hasb && n > 0) f = (mp < 0) ? csub(f, Fb[n]) : cadd(f, Fb[n]);
+        return cmul(cconj(f), p.thwc[j]);
+    });
+    staged_loop(
+        L, [&](int t) { return Pair2{p.chirp[t], p.chirp[2 * L - 2 - t]}; },
+        [&](int t, const Pair2& cp) {
+            const double2 x = cconj(cmul(A[Pr<RB>(t)], cp.a));
+            if (t == L - 1) {
+                if (hasa) Ft[(size_t)t * N1 + ia] = x;
+                if (hasb) Ft[(size_t)t * N1 + ib] = make_double2(0.0, 0.0);
+            } else {
+                const double2 y = cconj(cmul(A[Pr<RB>(2 * L - 2 - t)], cp.b));
+                if (hasa) Ft[(size_t)t * N1 + ia] = cscale(cadd(x, y), 0.5);
+                if (hasb) Ft[(size_t)t * N1 + ib] = cscale(csub(x, y), 0.5);
+            }
+        });
+}
+
 // Theta step of the adjoint of the forward transform, for order m: the
 // conjugate transposes of the forward's theta stages in reverse order.
 //   unfold   Y_{m,-n} = (-1)^{m+s} Y_{m,n}     (input: folded Y[m + L-1][n], n >= 0)
@@ -677,9 +857,10 @@ __global__ __launch_bounds__(512) void k_theta_forward(Plan p, Batch B)
 // halves on the half grid (see k_theta_forward), its output at slot j of the half
 // grid being E_j + w^j O_j (m' = j >= 0) or E_j - w^j O_j (m' = j - NH < 0), and
 // the Bluestein step as bluestein_split on inputs held in registers.
-template <int RB, bool SP>
+template <int RB, bool SP, int LOGN>
 __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
 {
+    fix_length<LOGN, SP>(p);
     extern __shared__ double2 A[];
     const int s = B.s[blockIdx.y];
     const double2* __restrict__ Y = (const double2*)B.in[blockIdx.y];
@@ -787,9 +968,10 @@ __global__ __launch_bounds__(512) void k_theta_forward_adjoint(Plan p, Batch B)
 // Output Ft[t][m + L-1].
 // HALF = 1 (real scalar maps): only the orders m >= 0 run; the inverse phi stage
 // takes F_{-m}(theta) = conj(F_m(theta)).
-template <int HALF, int RB, bool SP>
+template <int HALF, int RB, bool SP, int LOGN>
 __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
 {
+    fix_length<LOGN, SP>(p);
     extern __shared__ double2 A[];
     const int s = B.s[blockIdx.y];
     const double2* __restrict__ F = (const double2*)B.in[blockIdx.y];
@@ -828,9 +1010,10 @@ __global__ __launch_bounds__(512) void k_theta_inverse(Plan p, Batch B)
 // pole: how the south-pole ring t = L-1 is stored: 0 = in full; 1 = compact
 // storage, its sample p = 0 only; 2 = the single value sum_p e^{-i s phi_p} f(L-1, p)
 // at p = 0 (the adjoint of the compact expansion C -> C e^{i s phi_p}).
-template <int REAL, int RB, bool SP>
+template <int REAL, int RB, bool SP, int LOGN>
 __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc, int pole)
 {
+    fix_length<LOGN, SP>(p);
     extern __shared__ double2 A[];
     const double2* __restrict__ Ft = (const double2*)B.in[blockIdx.y];
     void* __restrict__ map = B.out[blockIdx.y];
@@ -939,28 +1122,78 @@ hipError_t fft_go(K k, const Plan& p, int rb, dim3 grid, hipStream_t st, Args...
     return hipGetLastError();
 }
 
-// Launches kernel K<RB, SP> with the radix and split mode of the plan.
-template <template <int, bool> class KS, class... Args>
+// Launches kernel K<RB, SP, LOGN> with the radix and split mode of the plan,
+// compiled for its transform length when that is one of the common ones
+// (512 .. 8192 points in LDS: band-limits 65 .. 4096), else for any length.
+template <template <int, bool, int> class KS, class... Args>
 hipError_t fft_launch(const Plan& p, dim3 grid, hipStream_t st, Args... args)
 {
-    if (fft_split(p)) return fft_go(KS<16, true>::fn(), p, 16, grid, st, args...);
-    if (fft_radix(p) == 16) return fft_go(KS<16, false>::fn(), p, 16, grid, st, args...);
-    return fft_go(KS<8, false>::fn(), p, 8, grid, st, args...);
+    const int logn = fft_split(p) ? p.logN2 - 1 : p.logN2;
+    if (fft_split(p)) {
+        if (logn == 13) return fft_go(KS<16, true, 13>::fn(), p, 16, grid, st, args...);
+        return fft_go(KS<16, true, -1>::fn(), p, 16, grid, st, args...);
+    }
+    if (fft_radix(p) == 16) {
+        if (logn == 13) return fft_go(KS<16, false, 13>::fn(), p, 16, grid, st, args...);
+        return fft_go(KS<16, false, -1>::fn(), p, 16, grid, st, args...);
+    }
+    switch (logn) {
+        case 9: return fft_go(KS<8, false, 9>::fn(), p, 8, grid, st, args...);
+        case 10: return fft_go(KS<8, false, 10>::fn(), p, 8, grid, st, args...);
+        case 11: return fft_go(KS<8, false, 11>::fn(), p, 8, grid, st, args...);
+        case 12: return fft_go(KS<8, false, 12>::fn(), p, 8, grid, st, args...);
+        default: return fft_go(KS<8, false, -1>::fn(), p, 8, grid, st, args...);
+    }
 }
 
+// The same for kernels that exist only for split plans (KS<16, true, LOGN>) ...
+template <template <int, bool, int> class KS, class... Args>
+hipError_t fft_launch_split(const Plan& p, dim3 grid, hipStream_t st, Args... args)
+{
+    if (p.logN2 - 1 == 13) return fft_go(KS<16, true, 13>::fn(), p, 16, grid, st, args...);
+    return fft_go(KS<16, true, -1>::fn(), p, 16, grid, st, args...);
+}
+
+// ... and for those that exist only for unsplit plans (KS<RB, LOGN>).
+template <template <int, int> class KS, class... Args>
+hipError_t fft_launch_unsplit(const Plan& p, dim3 grid, hipStream_t st, Args... args)
+{
+    const int logn = p.logN2;
+    if (fft_radix(p) == 16) {
+        if (logn == 13) return fft_go(KS<16, 13>::fn(), p, 16, grid, st, args...);
+        return fft_go(KS<16, -1>::fn(), p, 16, grid, st, args...);
+    }
+    switch (logn) {
+        case 9: return fft_go(KS<8, 9>::fn(), p, 8, grid, st, args...);
+        case 10: return fft_go(KS<8, 10>::fn(), p, 8, grid, st, args...);
+        case 11: return fft_go(KS<8, 11>::fn(), p, 8, grid, st, args...);
+        case 12: return fft_go(KS<8, 12>::fn(), p, 8, grid, st, args...);
+        default: return fft_go(KS<8, -1>::fn(), p, 8, grid, st, args...);
+    }
+}
+
+template <int O, int H> struct ThFP {
+    template <int RB, int LN> struct K { static auto fn() { return k_theta_forward_pair<O, H, RB, LN>; } };
+};
+template <int H> struct ThIP {
+    template <int RB, int LN> struct K { static auto fn() { return k_theta_inverse_pair<H, RB, LN>; } };
+};
+
 template <int REAL> struct PhiF {
-    template <int RB, bool SP> struct K { static auto fn() { return k_phi_forward<REAL, RB, SP>; } };
+    template <int RB, bool SP, int LN> struct K { static auto fn() { return k_phi_forward<REAL, RB, SP, LN>; } };
 };
 template <int REAL> struct PhiI {
-    template <int RB, bool SP> struct K { static auto fn() { return k_phi_inverse<REAL, RB, SP>; } };
+    template <int RB, bool SP, int LN> struct K { static auto fn() { return k_phi_inverse<REAL, RB, SP, LN>; } };
 };
 template <int A, int O, int H> struct ThF {
-    template <int RB, bool SP> struct K { static auto fn() { return k_theta_forward<A, O, H, RB, SP>; } };
+    template <int RB, bool SP, int LN> struct K {
+        static auto fn() { return k_theta_forward<A, O, H, RB, SP, LN>; }
+    };
 };
 template <int H> struct ThI {
-    template <int RB, bool SP> struct K { static auto fn() { return k_theta_inverse<H, RB, SP>; } };
+    template <int RB, bool SP, int LN> struct K { static auto fn() { return k_theta_inverse<H, RB, SP, LN>; } };
 };
-template <int RB, bool SP> struct ThFA { static auto fn() { return k_theta_forward_adjoint<RB, SP>; } };
+template <int RB, bool SP, int LN> struct ThFA { static auto fn() { return k_theta_forward_adjoint<RB, SP, LN>; } };
 
 }  // namespace
 
@@ -973,13 +1206,22 @@ hipError_t launch_phi_forward(const Plan& p, const Batch& B, int real, double sc
 
 hipError_t launch_theta_forward(const Plan& p, const Batch& B, int out32, int half, hipStream_t st)
 {
+    if (!fft_split(p)) {   // pairs of orders of opposite extension parity
+        const dim3 grid(xcd_grid(half ? (p.L + 1) / 2 : p.L), B.n);
+        if (half) {
+            if (out32) return fft_launch_unsplit<ThFP<1, 1>::K>(p, grid, st, p, B);
+            return fft_launch_unsplit<ThFP<0, 1>::K>(p, grid, st, p, B);
+        }
+        if (out32) return fft_launch_unsplit<ThFP<1, 0>::K>(p, grid, st, p, B);
+        return fft_launch_unsplit<ThFP<0, 0>::K>(p, grid, st, p, B);
+    }
     const dim3 grid(xcd_grid(half ? p.L : p.N1), B.n);
     if (half) {
-        if (out32) return fft_launch<ThF<0, 1, 1>::K>(p, grid, st, p, B);
-        return fft_launch<ThF<0, 0, 1>::K>(p, grid, st, p, B);
+        if (out32) return fft_launch_split<ThF<0, 1, 1>::K>(p, grid, st, p, B);
+        return fft_launch_split<ThF<0, 0, 1>::K>(p, grid, st, p, B);
     }
-    if (out32) return fft_launch<ThF<0, 1, 0>::K>(p, grid, st, p, B);
-    return fft_launch<ThF<0, 0, 0>::K>(p, grid, st, p, B);
+    if (out32) return fft_launch_split<ThF<0, 1, 0>::K>(p, grid, st, p, B);
+    return fft_launch_split<ThF<0, 0, 0>::K>(p, grid, st, p, B);
 }
 
 hipError_t launch_theta_inverse_adjoint(const Plan& p, const Batch& B, int out32, hipStream_t st)
@@ -996,8 +1238,13 @@ hipError_t launch_theta_forward_adjoint(const Plan& p, const Batch& B, hipStream
 
 hipError_t launch_theta_inverse(const Plan& p, const Batch& B, int half, hipStream_t st)
 {
-    if (half) return fft_launch<ThI<1>::K>(p, dim3(xcd_grid(p.L), B.n), st, p, B);
-    return fft_launch<ThI<0>::K>(p, dim3(xcd_grid(p.N1), B.n), st, p, B);
+    if (!fft_split(p)) {   // pairs of orders of opposite extension parity
+        const dim3 grid(xcd_grid(half ? (p.L + 1) / 2 : p.L), B.n);
+        if (half) return fft_launch_unsplit<ThIP<1>::K>(p, grid, st, p, B);
+        return fft_launch_unsplit<ThIP<0>::K>(p, grid, st, p, B);
+    }
+    if (half) return fft_launch_split<ThI<1>::K>(p, dim3(xcd_grid(p.L), B.n), st, p, B);
+    return fft_launch_split<ThI<0>::K>(p, dim3(xcd_grid(p.N1), B.n), st, p, B);
 }
 
 hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc, int pole, hipStream_t st)

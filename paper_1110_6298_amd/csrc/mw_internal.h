@@ -58,6 +58,8 @@ struct Plan {
     double2* bhat = nullptr;    // FFT_N2 of the Bluestein kernel, divided by N2
     double2* what = nullptr;    // (2 pi/N2) * DFT_N2 of the theta weights w(k)
     double2* whatc = nullptr;   // conj(what), for the adjoint of the weight step
+    double2* whate = nullptr;   // (2 pi/N2) * DFT_N2 of the even part of the weights (frequency order)
+    double wsum_e = 0.0;        // sum of the even part of the weights over |k| <= L-1
     double2* thtw = nullptr;    // exp(-i m' pi/N1)/(2 pi N1) at slot k = m' mod N1
     double2* thwc = nullptr;    // exp(-i m' pi/N1) chirp_k at slot k = m' mod N1
     double thsc = 0.0;          // 1/(2 pi N1)

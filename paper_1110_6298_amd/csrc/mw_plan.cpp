@@ -303,6 +303,26 @@ int build_plan(int L, Plan& p, std::string& err)
     if ((rc = upload(wh, &p.what, p.bytes, err))) return rc;
     for (auto& v : wh) v.y = -v.y;   // conjugate spectrum, for the adjoint's correlation
     if ((rc = upload(wh, &p.whatc, p.bytes, err))) return rc;
+    {
+        // the even part w_e(k) = (w(k) + w(-k))/2 of the weights (2/(1-k^2) at even
+        // k, zero at odd k), for the paired theta stage, in frequency order, and the
+        // sum of w_e over |k| <= L-1
+        std::vector<cld> we(N2, cld(0, 0));
+        ld sum = 0.0L;
+        for (int k = -2 * (L - 1); k <= 2 * (L - 1); k += 2) {
+            const ld v = 2.0L / (1.0L - (ld)k * (ld)k);
+            we[((k % N2) + N2) % N2] += cld(v, 0);
+            if (k >= -(L - 1) && k <= L - 1) sum += v;
+        }
+        host_fft(we);
+        std::vector<double2> wes(N2);
+        for (int j = 0; j < N2; ++j) {
+            const cld v = we[j] * (2.0L * PI_L / (ld)N2);
+            wes[j] = make_double2((double)v.real(), (double)v.imag());
+        }
+        if ((rc = upload(wes, &p.whate, p.bytes, err))) return rc;
+        p.wsum_e = (double)sum;
+    }
 
     std::vector<double2> th(N1);
     for (int k = 0; k < N1; ++k) {
@@ -405,7 +425,7 @@ int build_plan(int L, Plan& p, std::string& err)
 
 void free_plan(Plan& p)
 {
-    void* ptrs[] = {p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.whatc, p.thtw, p.thwc,
+    void* ptrs[] = {p.rtab, p.edge, p.edgek, p.lco, p.cl, p.tw, p.chirp, p.bhat, p.what, p.whatc, p.whate, p.thtw, p.thwc,
                     p.workf4, p.ckf, p.ckfk, p.cki, p.ckik};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
