@@ -24,8 +24,8 @@ PEAK_FP64_VALU = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 # read for a plain copy of known size (profiles/traffic_roundtrip_L512_s2.md).
 # Valid only while the kernel and plan sources are unchanged: keyed by their SHA-256.
 TRAFFIC = {
-    ("contract_inverse", 512, 2): {"bytes": 29683724, "source_sha256": "894e192efbfc40adb1478cf0290886d096348bc352f9f9c7d85a6edb24c987f7"},
-    ("contract_forward", 512, 2): {"bytes": 29424079, "source_sha256": "894e192efbfc40adb1478cf0290886d096348bc352f9f9c7d85a6edb24c987f7"},
+    ("contract_inverse", 512, 2): {"bytes": 29669354, "source_sha256": "20179d153e5ae0e5a99a998fa40dcf00c6cc1b385fb063749a882387b4762374"},
+    ("contract_forward", 512, 2): {"bytes": 29424749, "source_sha256": "20179d153e5ae0e5a99a998fa40dcf00c6cc1b385fb063749a882387b4762374"},
 }
 KERNEL_SOURCES = ("paper_1110_6298_amd/csrc/mw_contract.hip", "paper_1110_6298_amd/csrc/mw_plan.cpp")
 
@@ -54,6 +54,11 @@ def contraction_flops(L, s, real=False):
     terms = sum(((l + 1) if real else (2 * l + 1)) * (l + 1) for l in range(abs(s), L))
     wedge = sum((l + 1) * (l + 2) // 2 for l in range(L))
     return 4.0 * terms + 5.0 * wedge
+
+
+def progress(msg):
+    """One progress line on stderr (the JSON result alone goes to stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def rel(a, b):
@@ -251,10 +256,12 @@ def main():
             mw.forward(xmap[prec], L, s, precision=prec, out=back[prec])
         return step
 
+    progress("L=%d s=%d FP64 round trips" % (L, s))
     wall0 = time.perf_counter()
     ms_step = time_steps(torch, stepper(mw.FP64), args.steps, args.warmup)
     wall = time.perf_counter() - wall0
     per_kernel = kernel_profile(mw, stepper(mw.FP64), args.steps)
+    progress("L=%d s=%d FP32C round trips" % (L, s))
     ms_mixed = time_steps(torch, stepper(mw.FP32C), args.steps, args.warmup)
     per_kernel_mixed = kernel_profile(mw, stepper(mw.FP32C), args.steps)
 
@@ -329,6 +336,7 @@ def main():
         batched = {}
         for name, prec, graph in (("fp64", mw.FP64, False), ("fp32c", mw.FP32C, False),
                                   ("fp64_graph", mw.FP64, True), ("fp32c_graph", mw.FP32C, True)):
+            progress("256-map batch, %s" % name)
             ms_b, nmaps, err_b, roof = batched_workload(torch, mw, dev, args.batch_steps, 2, prec, graph)
             batched[name] = {"maps_round_trips_per_s": nmaps * 1e3 / ms_b, "ms_per_step": ms_b,
                              "round_trip_rel_err": err_b}
@@ -340,10 +348,12 @@ def main():
         result["batched"] = batched
 
     if not args.no_large:
+        progress("L=2048 real map")
         result["large_l2048"] = large_workload(torch, mw, dev, 5, 1)
 
     if not args.no_cpu_baseline:
         import oracle
+        progress("oracle baseline on the host cores")
         oracle.build(force=False)
         t = time.perf_counter()
         count = 0
@@ -359,6 +369,7 @@ def main():
                                   "sample": "%d full round trips (inverse + forward) of the same L=%d s=%d map, "
                                             "%.1f s" % (count, L, s, dt)}
         if args.cpu_1core:
+            progress("oracle baseline on one host core")
             oracle.set_threads(1)
             t = time.perf_counter()
             oracle.forward(oracle.inverse(flm_h, L, s), L, s)
