@@ -57,6 +57,15 @@ int mw_profile_tune_cache_load(const char* path, int* entries);
  * Results agree with the unsplit kernels to rounding. */
 int mw_profile_split_fft(int mode);
 
+/* FP64 inverse contraction kernel (a test hook): mode 0 (the default) runs real
+ * maps at every band-limit, and complex maps from L = 1024, on the kernel that
+ * evaluates each Wigner chain Delta^l_{n,m} with n >= m once for the pairs
+ * (m, n) and (n, m) (the symmetry of Sec. III-C), and smaller complex maps on
+ * the kernel that runs every (n, m) chain; mode 1 runs every map on the first
+ * one, so that it can be compared with the oracle at small band-limits.  Takes
+ * effect for the calls that follow; results agree with the default to rounding. */
+int mw_profile_inverse_triangle(int mode);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,7 @@ EXPORTS = ("mw_forward", "mw_forward_noalloc", "mw_inverse", "mw_quadrature_weig
            "mw_workspace_size", "mw_set_workspace", "mw_prepare", "mw_release", "mw_status_string",
            "mw_last_error", "mw_version")
 PROFILE_EXPORTS = ("mw_profile_enable", "mw_profile_read", "mw_profile_stage_name", "mw_profile_tuned_group",
-                   "mw_profile_split_fft", "mw_profile_tune_cache_load")
+                   "mw_profile_split_fft", "mw_profile_inverse_triangle", "mw_profile_tune_cache_load")
 NSTAGE = 9
 
 _lib = None
@@ -89,6 +89,8 @@ def library():
         lib.mw_profile_stage_name.argtypes = [ctypes.c_int]
         lib.mw_profile_split_fft.restype = ctypes.c_int
         lib.mw_profile_split_fft.argtypes = [ctypes.c_int]
+        lib.mw_profile_inverse_triangle.restype = ctypes.c_int
+        lib.mw_profile_inverse_triangle.argtypes = [ctypes.c_int]
         lib.mw_profile_tune_cache_load.restype = ctypes.c_int
         lib.mw_profile_tune_cache_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
         lib.mw_profile_tuned_group.restype = ctypes.c_int
@@ -393,6 +395,13 @@ def tune_cache_load(path: str) -> int:
     n = ctypes.c_int(0)
     _check(library().mw_profile_tune_cache_load(os.fsencode(path), ctypes.byref(n)), "mw_profile_tune_cache_load")
     return int(n.value)
+
+
+def inverse_triangle(mode: int) -> None:
+    """Test hook: mode 1 runs every later FP64 inverse (and forward adjoint) on
+    the triangle contraction kernel, which by default runs real maps and complex
+    maps from L = 1024; mode 0 restores the default."""
+    _check(library().mw_profile_inverse_triangle(int(mode)), "mw_profile_inverse_triangle")
 
 
 def split_fft(mode: int) -> None:

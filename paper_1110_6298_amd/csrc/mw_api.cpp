@@ -433,9 +433,11 @@ hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const ChunkSpins& sps
         } else {
             const SpinTable* sp = tab(s < 0 ? -s : s);
             if (!sp) return hipErrorInvalidValue;
+            // the FP64 kernel reads the stream from the workspace and f_lm itself
+            const mw::Batch B2f = batch_of(c, user_in, w0);
             go(inv ? 3 : 6, [&] {
                 return mw::launch_contract_inverse(p, *sp, s, inv ? real : 0, (const double*)w2(0), ws_need(Lws) / 8,
-                                                   B2, st);
+                                                   B2f, st);
             });
         }
         if (inv) {
@@ -953,6 +955,14 @@ int mw_profile_split_fft(int mode)
     if (mode != 0 && mode != 1) return fail(MW_EINVAL, "split mode must be 0 or 1");
     std::lock_guard<std::mutex> lock(g_mu);
     mw::g_split_min_n2 = mode ? 2048 : 16384;
+    return MW_OK;
+}
+
+int mw_profile_inverse_triangle(int mode)
+{
+    if (mode != 0 && mode != 1) return fail(MW_EINVAL, "triangle mode must be 0 or 1");
+    std::lock_guard<std::mutex> lock(g_mu);
+    mw::g_inv_tri_all = mode;
     return MW_OK;
 }
 

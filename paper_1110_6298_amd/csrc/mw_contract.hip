@@ -734,10 +734,11 @@ __device__ __forceinline__ bool inv2_scaled(const InvLane2<EXT, NS>& st)
     return any;
 }
 
+// dd: the chain values of this step as they enter the products (0 while scaled).
 template <bool EXT, bool INJ, int NS>
-__device__ __forceinline__ void inv2_core(InvLane2<EXT, NS>& st, int l, int lstart, double nd, const double2& c0,
-                                          const double2& c1, const double2 (&cs)[NS], double rs,
-                                          double (&pr)[2][NS], bool& anyscaled)
+__device__ __forceinline__ void inv2_core_d(InvLane2<EXT, NS>& st, int l, int lstart, double nd, const double2& c0,
+                                            const double2& c1, const double2 (&cs)[NS], double rs,
+                                            double (&pr)[2][NS], double (&dd)[2], bool& anyscaled)
 {
     if (INJ) {
 #pragma unroll
@@ -758,6 +759,7 @@ __device__ __forceinline__ void inv2_core(InvLane2<EXT, NS>& st, int l, int lsta
     for (int c = 0; c < 2; ++c) {
         double d = st.dc[c];
         if (EXT) d = (st.k[c] == 0) ? d : 0.0;
+        dd[c] = d;
 #pragma unroll
         for (int j = 0; j < NS; ++j) pr[c][j] = d * sv[j];
     }
@@ -790,6 +792,15 @@ __device__ __forceinline__ void inv2_core(InvLane2<EXT, NS>& st, int l, int lsta
             if (st.ks[j] > 0 && fabs(st.sc[j]) > EXT_UP) { st.sc[j] *= EXT_DOWN; st.sp[j] *= EXT_DOWN; st.ks[j] -= 1; }
         anyscaled = __any(inv2_scaled(st));
     }
+}
+
+template <bool EXT, bool INJ, int NS>
+__device__ __forceinline__ void inv2_core(InvLane2<EXT, NS>& st, int l, int lstart, double nd, const double2& c0,
+                                          const double2& c1, const double2 (&cs)[NS], double rs,
+                                          double (&pr)[2][NS], bool& anyscaled)
+{
+    double dd[2];
+    inv2_core_d<EXT, INJ, NS>(st, l, lstart, nd, c0, c1, cs, rs, pr, dd, anyscaled);
 }
 
 template <bool EXT, bool INJ, bool RL>
@@ -1081,6 +1092,266 @@ __global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(R
 }
 #undef MW_INVERSE2_ARGS
 #undef MW_INVERSE2_PASS
+
+// ===========================================================================
+// FP64 inverse contraction over the triangle n >= m.  By the symmetry
+// Delta^l_{m,n} = (-1)^{m+n} Delta^l_{n,m} (Sec. III-C), the chain Delta^l_{n,m}
+// of a lane n >= m serves two sums:
+//   normal      F_{+-m,n}: the stream record of order m (uniform over the wave)
+//               times the lane's spin chain Delta^l_{n,|s|}, as in the
+//               two-order kernel above;
+//   transposed  F_{+-n,m}: the lane's own coefficients f_{l,+-n}, read from
+//               f_lm (64 consecutive n of one degree are one contiguous run),
+//               times the uniform factor c_l Delta^l_{m,|s|} / h_m(l), which
+//               the spin table's lcos rows carry beside the chain factor of
+//               order m (the division undoes the chain's scale h_m).
+// With also Delta^l_{m,-n} = (-1)^{l+m} Delta^l_{m,n} and Delta^l_{m,-s} =
+// (-1)^{l+m} Delta^l_{m,|s|} for s >= 0, the transposed sums take the degree
+// signs of the normal ones (sp(l) on the +n sum, sm(l) on the -n sum: (-1)^l
+// and 1 for s >= 0, 1 and (-1)^l for s < 0; SNEG = s < 0 fixes them per step
+// parity at compile time) and the output signs (-1)^{s+n} (order +n) and
+// (-1)^{s+n+m} (order -n) for s >= 0, (-1)^{s+n+m} and (-1)^{s+n} for s < 0.
+// Lanes n < m of a group on the diagonal run no chain (their pairs are the
+// transposed sums of another group); lane n = m writes the normal sums only.
+// Only the groups with n0 + 63 >= m0 run (the spin table's wtri): about half
+// the chain steps of the square kernel, at four more FMAs per step and order
+// and two coalesced 16-byte reads per lane and step (one for real maps).
+// ===========================================================================
+template <bool EXT>
+struct InvLane3 {
+    InvLane2<EXT> b;
+    double2 at[2], atm[2];   // transposed sums: orders +n, -n at rows m0, m0+1
+};
+
+// f_{l,+n} and f_{l,-n} of the lane at byte offsets op = 16 (l^2 + l + n) and
+// op - 32 n of f_lm, through a buffer resource of L^2 records: offsets past the
+// end (degree L, or l^2 + l - n < 0 as an unsigned offset) read zeros.
+template <bool RL>
+__device__ __forceinline__ double4 f_load(__amdgpu_buffer_rsrc_t rs, unsigned op, unsigned n32)
+{
+    const double2 a = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, op, 0, 0));
+    if (RL) return make_double4(a.x, a.y, 0.0, 0.0);
+    const double2 b = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, op - n32, 0, 0));
+    return make_double4(a.x, a.y, b.x, b.y);
+}
+
+// PAR: parity of l (the transposed sums' degree signs).
+template <bool EXT, bool INJ, bool RL, bool SNEG, int PAR>
+__device__ __forceinline__ void inv3_step(InvLane3<EXT>& st, int l, int lstart, double nd, const InvS2& u,
+                                          const double4& g, double rs, bool& anyscaled)
+{
+    double pr[2][1], dd[2];
+    const double2 cs[1] = {u.cs};
+    inv2_core_d<EXT, INJ, 1>(st.b, l, lstart, nd, u.c0, u.c1, cs, rs, pr, dd, anyscaled);
+    constexpr double sgp = (PAR && !SNEG) ? -1.0 : 1.0;   // sp(l)
+    constexpr double sgm = (PAR && SNEG) ? -1.0 : 1.0;    // sm(l)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const double4 f = c ? u.f1 : u.f0;
+        st.b.ap[c].x = fma(pr[c][0], f.x, st.b.ap[c].x);
+        st.b.ap[c].y = fma(pr[c][0], f.y, st.b.ap[c].y);
+        if (!RL) {
+            st.b.am[c].x = fma(pr[c][0], f.z, st.b.am[c].x);
+            st.b.am[c].y = fma(pr[c][0], f.w, st.b.am[c].y);
+        }
+        const double pt = dd[c] * (c ? u.c1.y : u.c0.y);
+        st.at[c].x = fma(sgp * pt, g.x, st.at[c].x);
+        st.at[c].y = fma(sgp * pt, g.y, st.at[c].y);
+        if (!RL) {
+            st.atm[c].x = fma(sgm * pt, g.z, st.atm[c].x);
+            st.atm[c].y = fma(sgm * pt, g.w, st.atm[c].y);
+        }
+    }
+}
+
+// Pairs jfrom .. jlast as in inv2_phase; the lane's coefficients are loaded
+// one step ahead beside the uniform records (gA with uA, gB with uB).  op: the
+// lane's f_lm offset at degree 2 jfrom on entry, advanced by 32 (l+1) per step.
+template <bool EXT, bool INJ, bool RL, bool SNEG>
+__device__ __forceinline__ void inv3_phase(InvLane3<EXT>& st, int jfrom, int jlast, int lend, int lstart, int ne,
+                                           double nd, const Inv2Rows& rows, const double* __restrict__ Rt,
+                                           __amdgpu_buffer_rsrc_t frs, unsigned& op, unsigned n32, InvS2& uA,
+                                           InvS2& uB, double4& gA, double4& gB, InvR& r, bool& anyscaled)
+{
+    const int jr = lend >> 1;   // last pair whose factors exist
+    InvR rB;
+    auto half = [&](int l, const InvR& rc) {   // steps l (in A) and l+1 (in B)
+        wait_scalar(uA.f0.x);
+        __builtin_amdgcn_sched_barrier(0);
+        inv2_load(uB, rows, l + 1);
+        op += 32u * (unsigned)(l + 1);   // degree l+1
+        gB = f_load<RL>(frs, op, n32);
+        __builtin_amdgcn_sched_barrier(0);
+        inv3_step<EXT, INJ, RL, SNEG, 0>(st, l, lstart, nd, uA, gA, rc.a.x * rc.b.x, anyscaled);
+        wait_scalar(uB.f0.x);
+        __builtin_amdgcn_sched_barrier(0);
+        inv2_load(uA, rows, min(l + 2, lend));
+        op += 32u * (unsigned)(l + 2);   // degree l+2 (past lend: beyond f_lm, reads zeros)
+        gA = f_load<RL>(frs, op, n32);
+        __builtin_amdgcn_sched_barrier(0);
+        inv3_step<EXT, INJ, RL, SNEG, 1>(st, l + 1, lstart, nd, uB, gB, rc.a.y * rc.b.y, anyscaled);
+    };
+    for (int j = jfrom; j <= jlast; ++j) {
+        rB = inv_load_r(Rt, ne, min(j + 1, jr));
+        half(2 * j, r);
+        r = rB;
+    }
+}
+
+template <bool EXT, bool RL, bool SNEG>
+__device__ __forceinline__ void contract_inverse_tri_body(
+    const double* __restrict__ fs0, size_t fstride, const Batch& B, const double* __restrict__ Rtg,
+    const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
+    const double2* __restrict__ lcos, const double* __restrict__ stab, const int* __restrict__ stabk,
+    const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work, int L,
+    int Lp, int s, int ckg)
+{
+    // LDS: the partial sums of later segments, red[slot][c][acc][lane] with acc =
+    // ap, at (and am, atm for complex maps)
+    constexpr int NACC = RL ? 2 : 4;
+    __shared__ double2 red[SEGT_MAX * 2 * NACC * 64];
+    const double* __restrict__ Rt = Rtg;
+    const double* __restrict__ fs = fs0 + blockIdx.y * fstride;   // map blockIdx.y of the launch
+    const __amdgpu_buffer_rsrc_t frs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)B.in[blockIdx.y], (short)0, (int)((unsigned)L * (unsigned)L * 16u), 0x00020000);
+    double2* __restrict__ F = (double2*)B.out[blockIdx.y];
+    const int slot = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int4 d = work[(size_t)blockIdx.x * SEGT_MAX + slot];
+    const int n0 = uniform(d.x), m0 = uniform(d.y), code = uniform(d.z), bounds = uniform(d.w);
+    const bool item = n0 >= 0;
+    const int w = code & 0xff, nseg = (code >> 8) & 0xff, lead = (code >> 16) & 0xff;
+    const bool bar = (code >> 24) & 1;   // the same for every slot of the workgroup
+    const int n = n0 + lane;
+    const bool valid = item && n < L;
+    const int ne = valid ? n : L - 1;
+    const int as = s < 0 ? -s : s;
+    const double nd = (double)ne;
+    const int lend = Lp - 1;
+
+    InvLane3<EXT> st;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) st.at[c] = st.atm[c] = make_double2(0.0, 0.0);
+    if (item) {
+        InvGeo geo;
+        geo.lstart = max(n0, m0) & ~1;
+        geo.lA = max(max(n0 + 64, m0 + 2), as + 1);   // every chain start of both orders lies below lA
+        geo.cs = bounds & 0xffff;
+        geo.ce = (int)((unsigned)bounds >> 16);
+        geo.nseg = nseg;
+        // uniform rows: stream records of both orders; (Pu', spin factor) of
+        // both orders and (Pu', -) of |s|, all from lcos
+        const Inv2Rows rows = inv2_rows(fs, lcos, m0, as, Lp, L);
+        const unsigned touched = inv2_touch(rows, geo.cs, lend, lane);
+        bool anyscaled;
+        const InvSeg g = inv2_setup<EXT, 1>(st.b, anyscaled, geo, w, n, m0, L, Lp, SpinSet<1>{{as}}, ckg, lco, edge,
+                                            edgek, SpinTabs<1>{{stab}, {stabk}}, cki, ckik, ckoff);
+        // lanes n < m run no chain of order m
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            if (n < m0 + c) {
+                st.b.start[c] = 0.0; st.b.startk[c] = 0;
+                st.b.dc[c] = 0.0; st.b.dp[c] = 0.0; st.b.k[c] = 0;
+            }
+        if (EXT) anyscaled = __any(inv2_scaled(st.b));
+        asm volatile("" ::"v"(touched));
+        if (g.active) {
+            const unsigned l0 = 2u * (unsigned)g.jfrom, n32 = 32u * (unsigned)ne;
+            unsigned op = 16u * (l0 * l0 + l0 + (unsigned)ne);
+            InvS2 uA, uB;
+            double4 gA, gB;
+            inv2_load(uA, rows, 2 * g.jfrom);
+            gA = f_load<RL>(frs, op, n32);
+            InvR r = inv_load_r(Rt, ne, g.jfrom);
+            const int jA = min(g.jA, g.jlast);
+            if (g.jfrom <= jA)
+                inv3_phase<EXT, true, RL, SNEG>(st, g.jfrom, jA, lend, geo.lstart, ne, nd, rows, Rt, frs, op, n32, uA,
+                                                uB, gA, gB, r, anyscaled);
+            if (max(g.jfrom, jA + 1) <= g.jlast)
+                inv3_phase<EXT, false, RL, SNEG>(st, max(g.jfrom, jA + 1), g.jlast, lend, geo.lstart, ne, nd, rows, Rt,
+                                                 frs, op, n32, uA, uB, gA, gB, r, anyscaled);
+        }
+    }
+
+    if (bar) {
+        // every wave of the workgroup (empty slots too) meets at this one barrier
+        auto R = [&](int k, int c, int h) -> double2& { return red[((k * 2 + c) * NACC + h) * 64 + lane]; };
+        if (item && w > 0) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                R(slot, c, 0) = st.b.ap[c];
+                R(slot, c, 1) = st.at[c];
+                if (!RL) { R(slot, c, NACC - 2) = st.b.am[c]; R(slot, c, NACC - 1) = st.atm[c]; }
+            }
+        }
+        __syncthreads();
+        if (!item || w != 0) return;
+        for (int k = 1; k < nseg; ++k)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const double2 a = R(lead + k, c, 0), t = R(lead + k, c, 1);
+                st.b.ap[c].x += a.x; st.b.ap[c].y += a.y;
+                st.at[c].x += t.x; st.at[c].y += t.y;
+                if (!RL) {
+                    const double2 b = R(lead + k, c, NACC - 2), u = R(lead + k, c, NACC - 1);
+                    st.b.am[c].x += b.x; st.b.am[c].y += b.y;
+                    st.atm[c].x += u.x; st.atm[c].y += u.y;
+                }
+            }
+    } else if (!item) {
+        return;
+    }
+
+    if (!valid) return;
+    const double ss = sgn(s), sn = sgn(n);
+    const double fsp = ss * ((s >= 0) ? sn : 1.0);
+    const double fsm = ss * ((s < 0) ? sn : 1.0);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int m = m0 + c;
+        if (m >= L || n < m) continue;
+        const double2 op = mul_ipow(st.b.ap[c], ((-(m + s)) % 4 + 4) % 4);
+        F[(size_t)(L - 1 + m) * L + n] = make_double2(op.x * fsp, op.y * fsp);
+        if (!RL && m > 0) {
+            const double2 om = mul_ipow(st.b.am[c], ((m - s) % 4 + 4) % 4);
+            F[(size_t)(L - 1 - m) * L + n] = make_double2(om.x * fsm, om.y * fsm);
+        }
+        if (n == m) continue;
+        const double sgm = sgn(m);
+        const double tsp = ss * sn * ((s >= 0) ? 1.0 : sgm);
+        const double2 tp = mul_ipow(st.at[c], ((-(n + s)) % 4 + 4) % 4);
+        F[(size_t)(L - 1 + n) * L + m] = make_double2(tp.x * tsp, tp.y * tsp);
+        if (!RL) {
+            const double tsm = ss * sn * ((s >= 0) ? sgm : 1.0);
+            const double2 tm = mul_ipow(st.atm[c], ((n - s) % 4 + 4) % 4);
+            F[(size_t)(L - 1 - n) * L + m] = make_double2(tm.x * tsm, tm.y * tsm);
+        }
+    }
+}
+
+#define MW_INVTRI_ARGS                                                                                           \
+    const double* __restrict__ fs0, size_t fstride, Batch B, const double* __restrict__ Rtg,                    \
+        const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,         \
+        const double2* __restrict__ lcos, const double* __restrict__ stab, const int* __restrict__ stabk,       \
+        const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff,                            \
+        const int4* __restrict__ work, int L, int Lp, int s, int ckg
+#define MW_INVTRI_PASS fs0, fstride, B, Rtg, edge, edgek, lco, lcos, stab, stabk, cki, ckik, ckoff, work, L, Lp, s, ckg
+
+template <bool RL, bool SNEG>
+__global__ __launch_bounds__(64 * SEGT_MAX) __attribute__((amdgpu_waves_per_eu(RL ? 5 : 4))) void
+k_contract_inverse_tri(MW_INVTRI_ARGS)
+{
+    contract_inverse_tri_body<false, RL, SNEG>(MW_INVTRI_PASS);
+}
+
+template <bool RL, bool SNEG>
+__global__ __launch_bounds__(64 * SEGT_MAX) __attribute__((amdgpu_waves_per_eu(4))) void
+k_contract_inverse_tri_ext(MW_INVTRI_ARGS)
+{
+    contract_inverse_tri_body<true, RL, SNEG>(MW_INVTRI_PASS);
+}
+#undef MW_INVTRI_ARGS
+#undef MW_INVTRI_PASS
 
 // ===========================================================================
 // Mixed precision (MW_FP32C): the same FP64 chains; each step's products
@@ -1656,9 +1927,25 @@ hipError_t launch_inverse_stream(const Plan& p, int real, const Batch& B, int ou
 }
 
 namespace {
+template <bool EXT, bool RL, bool SNEG>
+hipError_t inv_tri_go(const Plan& p, const SpinTable& sp, int s, const double* in0, size_t stride, const Batch& B,
+                      hipStream_t st)
+{
+    CkOff off;
+    for (int j = 0; j < CKI_MAX; ++j) off.off[j] = p.cki_off[j];
+    const dim3 grid(sp.nwtri, B.n), block(64 * SEGT_MAX);
+    if (EXT)
+        hipLaunchKernelGGL((k_contract_inverse_tri_ext<RL, SNEG>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
+                           p.edgek, p.lco, sp.lcos, sp.val, sp.k, p.cki, p.ckik, off, sp.wtri, p.L, p.Lp, s, p.ckg);
+    else
+        hipLaunchKernelGGL((k_contract_inverse_tri<RL, SNEG>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
+                           p.edgek, p.lco, sp.lcos, sp.val, sp.k, p.cki, p.ckik, off, sp.wtri, p.L, p.Lp, s, p.ckg);
+    return hipGetLastError();
+}
+
 template <bool EXT, bool RL>
-hipError_t inv_go(const Plan& p, const SpinTable& sp, int s, const double* in0, size_t stride, const Batch& B,
-                  hipStream_t st)
+hipError_t inv_sq_go(const Plan& p, const SpinTable& sp, int s, const double* in0, size_t stride, const Batch& B,
+                     hipStream_t st)
 {
     CkOff off;
     for (int j = 0; j < CKI_MAX; ++j) off.off[j] = p.cki_off[j];
@@ -1671,14 +1958,32 @@ hipError_t inv_go(const Plan& p, const SpinTable& sp, int s, const double* in0, 
                            p.lco, sp.val, sp.k, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s, p.ckg);
     return hipGetLastError();
 }
+
+template <bool EXT>
+hipError_t inv_go(const Plan& p, const SpinTable& sp, int s, int real, const double* in0, size_t stride,
+                  const Batch& B, hipStream_t st)
+{
+    // real maps have s = 0
+    if (real) return inv_tri_go<EXT, true, false>(p, sp, s, in0, stride, B, st);
+    if (p.L >= INV_TRI_MIN_L || g_inv_tri_all)
+        return s < 0 ? inv_tri_go<EXT, false, true>(p, sp, s, in0, stride, B, st)
+                     : inv_tri_go<EXT, false, false>(p, sp, s, in0, stride, B, st);
+    return inv_sq_go<EXT, false>(p, sp, s, in0, stride, B, st);
+}
 }  // namespace
 
+int g_inv_tri_all = 0;
+
+// The triangle kernel runs real maps at every band-limit and complex maps from
+// L = INV_TRI_MIN_L: below, a complex map's two coefficient reads per lane and
+// step and its four waves per SIMD (against six for the square kernel) cost more
+// than the halved chain work saves (measured at L = 256 and 512, one map and
+// batches: 2-16% slower; equal at L = 1024, 17% faster at L = 2048).
 hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, int real, const double* in0,
                                    size_t stride, const Batch& B, hipStream_t st)
 {
-    if (p.ext)
-        return real ? inv_go<true, true>(p, sp, s, in0, stride, B, st) : inv_go<true, false>(p, sp, s, in0, stride, B, st);
-    return real ? inv_go<false, true>(p, sp, s, in0, stride, B, st) : inv_go<false, false>(p, sp, s, in0, stride, B, st);
+    if (p.ext) return inv_go<true>(p, sp, s, real, in0, stride, B, st);
+    return inv_go<false>(p, sp, s, real, in0, stride, B, st);
 }
 
 // ---- mixed precision launchers ------------------------------------------

@@ -21,6 +21,17 @@ constexpr int EXT_LIMIT = 900;
 // extra restarts cost more than the added waves hide.
 constexpr int SEG_MAX = 4;
 constexpr int SEGI_MAX = 4;
+// The FP64 inverse over the triangle n >= m (half the chains of the square
+// kernels) splits its chains into up to SEGT_MAX segments, one wave each.
+// Eight segments were measured slower than four at L = 512 (47 against 41 us):
+// more restarts and more waves than fit at once.
+constexpr int SEGT_MAX = 4;
+// Complex maps use the triangle kernel from this band-limit up (real maps at
+// every band-limit); below, the square kernels.
+constexpr int INV_TRI_MIN_L = 1024;
+// Test hook (mw_profile_inverse_triangle): 1 runs every FP64 inverse on the
+// triangle kernel.
+extern int g_inv_tri_all;
 // Checkpoint planes of the inverse: at most CKI_MAX - 1 of them.
 constexpr int CKI_MAX = 16;
 
@@ -98,12 +109,23 @@ struct Plan {
 // m0+1) whose nseg segments sit in slots lead .. lead+nseg-1 of the same
 // workgroup (cs of a later segment is a checkpoint plane); (-1, 0, barrier << 24,
 // 0) marks an empty slot.
+//
+// The FP64 inverse runs each chain Delta^l_{n,m} with n >= m once for the pairs
+// (m, n) and (n, m) (Delta^l_{m,n} = (-1)^{m-n} Delta^l_{n,m}); its work list
+// wtri holds only the chain groups that meet n >= m (n0 + 63 >= m0), in the
+// layout of winv.  lcos[m*Lp + l] = (Pu'_m(l), c_l Delta^l_{m,|s|} / h_m(l)),
+// c_l = sqrt((2l+1)/(4 pi)): the chain factor of order m and the factor of row
+// m in the transposed sums (zero where |Delta^l_{m,|s|}| is below 2^-900 or
+// l < max(m, |s|)).
 struct SpinTable {
     int L = 0, as = 0;
     double* val = nullptr;
     int* k = nullptr;
     int4* winv = nullptr;
     int nwinv = 0;   // workgroups
+    double2* lcos = nullptr;
+    int4* wtri = nullptr;
+    int nwtri = 0;   // workgroups
     size_t bytes = 0;
 };
 
@@ -187,6 +209,9 @@ hipError_t launch_contract_forward(const Plan& p, int s, int real, const double*
 // Inverse coefficient stream (L x Lp x 4 doubles, or FP32 at [(m*4+comp)*Lp + l]),
 // each map with its own spin B.s[k].
 hipError_t launch_inverse_stream(const Plan& p, int real, const Batch& B, int out32, hipStream_t st);
+// FP64 inverse contraction: map k reads the stream at in0 + k*stride (doubles)
+// and its coefficients f_lm at B.in[k] (the transposed sums), and writes F to
+// B.out[k].
 hipError_t launch_contract_inverse(const Plan& p, const SpinTable& sp, int s, int real, const double* in0,
                                    size_t stride, const Batch& B, hipStream_t st);
 // half = 1: real scalar maps, only the orders m >= 0 (for launch_phi_inverse with real = 2).

@@ -179,6 +179,38 @@ static void ck_grid(int L, int seg, int& g, int& n)
     n = (L - 1) / g + 1;
 }
 
+// l-recursion factors at beta = pi/2, split into an m part (this table) and an
+// n part formed in the kernel:
+//  Delta^{l+1} = Pu_m(l) X_n(l) Delta^l + Qu_m(l) Y_n(l) Delta^{l-1}
+//  Pu_m(l) = -(2l+1) m / (l sqrt((l+1)^2 - m^2)),  Qu_m(l) = -(l+1)/l sqrt((l^2-m^2)/((l+1)^2-m^2))
+// The inverse runs the chains scaled, e_l = h_m(l) Delta^l, with h_m(m) =
+// h_m(m+1) = 1 and h_m(l+1) = h_m(l-1) / Qu_m(l), so that the Delta^{l-1} term
+// has coefficient 1:  e_{l+1} = Pu'_m(l) X_n(l) e_l + Y_n(l) e_{l-1},
+// Pu'_m(l) = Pu_m(l) h_m(l+1) / h_m(l).  |Qu_m(l)| is close to 1 away from
+// l = m, so h stays in [1, 5] up to L = 2048.  Entry [m*Lp + l] holds
+// (Pu'_m(l), h_m(l)); h = 1 where the chain does not exist (l < m, l >= L).
+static std::vector<double2> lrec_factors(int L, int Lp)
+{
+    std::vector<double2> lco((size_t)L * Lp, make_double2(0.0, 1.0));
+    for (int m = 0; m < L; ++m) {
+        ld hprev = 1.0L, hcur = 1.0L;   // h_m(l-1), h_m(l) at l = m
+        for (int l = m; l < L; ++l) {
+            const ld a = (ld)(l + 1) * (l + 1) - (ld)m * m;
+            const ld pu = (l == 0) ? 0.0L : -(2.0L * l + 1.0L) * (ld)m / ((ld)l * sqrtl(a));
+            ld hnext = 1.0L;   // h_m(l+1)
+            if (l > m) {
+                const ld b = (ld)l * l - (ld)m * m;
+                const ld qu = -((ld)(l + 1) / (ld)l) * sqrtl(b / a);
+                hnext = hprev / qu;
+            }
+            lco[(size_t)m * Lp + l] = make_double2((double)(pu * hnext / hcur), (double)hcur);
+            hprev = hcur;
+            hcur = hnext;
+        }
+    }
+    return lco;
+}
+
 int build_plan(int L, Plan& p, std::string& err)
 {
     p = Plan();
@@ -219,33 +251,7 @@ int build_plan(int L, Plan& p, std::string& err)
         if ((rc = upload(sk2, &p.edgek, p.bytes, err))) return rc;
     }
 
-    // l-recursion factors at beta = pi/2, split into an m part (this table) and an
-    // n part formed in the kernel:
-    //  Delta^{l+1} = Pu_m(l) X_n(l) Delta^l + Qu_m(l) Y_n(l) Delta^{l-1}
-    //  Pu_m(l) = -(2l+1) m / (l sqrt((l+1)^2 - m^2)),  Qu_m(l) = -(l+1)/l sqrt((l^2-m^2)/((l+1)^2-m^2))
-    // The inverse runs the chains scaled, e_l = h_m(l) Delta^l, with h_m(m) =
-    // h_m(m+1) = 1 and h_m(l+1) = h_m(l-1) / Qu_m(l), so that the Delta^{l-1} term
-    // has coefficient 1:  e_{l+1} = Pu'_m(l) X_n(l) e_l + Y_n(l) e_{l-1},
-    // Pu'_m(l) = Pu_m(l) h_m(l+1) / h_m(l).  |Qu_m(l)| is close to 1 away from
-    // l = m, so h stays in [1, 5] up to L = 2048.  Entry [m*Lp + l] holds
-    // (Pu'_m(l), h_m(l)); h = 1 where the chain does not exist (l < m, l >= L).
-    std::vector<double2> lco((size_t)L * p.Lp, make_double2(0.0, 1.0));
-    for (int m = 0; m < L; ++m) {
-        ld hprev = 1.0L, hcur = 1.0L;   // h_m(l-1), h_m(l) at l = m
-        for (int l = m; l < L; ++l) {
-            const ld a = (ld)(l + 1) * (l + 1) - (ld)m * m;
-            const ld pu = (l == 0) ? 0.0L : -(2.0L * l + 1.0L) * (ld)m / ((ld)l * sqrtl(a));
-            ld hnext = 1.0L;   // h_m(l+1)
-            if (l > m) {
-                const ld b = (ld)l * l - (ld)m * m;
-                const ld qu = -((ld)(l + 1) / (ld)l) * sqrtl(b / a);
-                hnext = hprev / qu;
-            }
-            lco[(size_t)m * p.Lp + l] = make_double2((double)(pu * hnext / hcur), (double)hcur);
-            hprev = hcur;
-            hcur = hnext;
-        }
-    }
+    const std::vector<double2> lco = lrec_factors(L, p.Lp);
     if ((rc = upload(lco, &p.lco, p.bytes, err))) return rc;
 
     std::vector<double> cl(L);
@@ -448,7 +454,8 @@ void free_plan(Plan& p)
 // work: the group's steps summed over its segments, plus a start-up cost per
 // segment.
 // dw: the descriptor's last word for each segment (see the work-list layouts).
-struct SegItem { int a, b, nseg, len, work; int dw[SEGI_MAX > SEG_MAX ? SEGI_MAX : SEG_MAX]; };
+constexpr int SEG_CAP = SEGT_MAX > SEGI_MAX ? (SEGT_MAX > SEG_MAX ? SEGT_MAX : SEG_MAX) : (SEGI_MAX > SEG_MAX ? SEGI_MAX : SEG_MAX);
+struct SegItem { int a, b, nseg, len, work; int dw[SEG_CAP]; };
 
 // Workgroups per compute unit up to which a work list is laid out for the
 // round-robin placement (balance_cus) rather than longest first.  The FP64
@@ -458,6 +465,7 @@ struct SegItem { int a, b, nseg, len, work; int dw[SEGI_MAX > SEG_MAX ? SEGI_MAX
 // layout (their last workgroups start as others finish), measured at L = 512
 // with 203 inverse and 137 forward workgroups per XCD.
 constexpr int RESIDENT_INV = 7;
+constexpr int RESIDENT_TRI = 7;
 constexpr int RESIDENT_FWD = 5;
 
 // Order of the workgroups of one XCD when all of them are resident at once:
@@ -492,7 +500,7 @@ static void balance_cus(std::vector<G>& gs)
 
 static std::vector<int4> pack_segments(std::vector<std::vector<SegItem>>& items, int slots, int resident)
 {
-    struct Group { int used, len; long work; bool bar; int4 slot[SEGI_MAX > SEG_MAX ? SEGI_MAX : SEG_MAX]; };
+    struct Group { int used, len; long work; bool bar; int4 slot[SEG_CAP]; };
     std::vector<std::vector<Group>> per(items.size());
     for (size_t x = 0; x < items.size(); ++x) {
         std::vector<SegItem>& it = items[x];
@@ -567,7 +575,7 @@ static int split_chain(int l0, int end, int lmin, const std::vector<int>& cand, 
     int lo = 1, hi = end - l0;   // hi is always feasible (one segment)
     while (lo < hi) {
         const int mid = (lo + hi) / 2;
-        int b[(SEGI_MAX > SEG_MAX ? SEGI_MAX : SEG_MAX) + 1];
+        int b[(SEG_CAP) + 1];
         if (greedy(mid, b) > 0) hi = mid;
         else lo = mid + 1;
     }
@@ -597,6 +605,34 @@ static std::vector<int4> inverse_work(const Plan& p, int as)
             items[(m0 / 2) & 7].push_back(t);
         }
     return pack_segments(items, SEGI_MAX, RESIDENT_INV);
+}
+
+// The same groups restricted to those that meet n >= m (m0 <= n0 + 63), for the
+// FP64 inverse that runs each chain with n >= m once for (m, n) and (n, m).
+// Dealt to XCDs by chunks of four order pairs, back and forth: the uniform rows
+// of an order stay in one L2, a 128-byte line of F holds eight orders of one
+// row in the transposed outputs, and the alternating direction evens out the
+// work, which falls with m0.  (Contiguous runs of (n0, m0) per XCD, which keep
+// each lane's coefficient rows in one L2 instead, were slower: the uniform
+// rows of every order then meet in every L2.)
+static std::vector<int4> inverse_work_tri(const Plan& p, int as)
+{
+    const int L = p.L, Lp = p.Lp;
+    std::vector<int> cand;   // the checkpoint planes
+    for (int k = 1; k < p.nck; ++k) cand.push_back(k * p.ckg);
+    std::vector<std::vector<SegItem>> items(8);
+    for (int n0 = 0; n0 < L; n0 += 64)
+        for (int m0 = 0; m0 < L && m0 <= n0 + 63; m0 += 2) {
+            const int lstart = std::max(n0, m0) & ~1;
+            const int lA = std::max(std::max(n0 + 64, m0 + 2), as + 1);
+            int bnd[SEGT_MAX + 1];
+            const int nseg = split_chain(lstart, Lp, std::max(lA, lstart + 2), cand, SEGT_MAX, bnd);
+            SegItem t{n0, m0, nseg, Lp - lstart, Lp - lstart + 16 * nseg, {}};
+            for (int w = 0; w < nseg; ++w) t.dw[w] = bnd[w] | (bnd[w + 1] << 16);
+            const int chunk = m0 >> 3, pos = chunk & 7;
+            items[((chunk >> 3) & 1) ? 7 - pos : pos].push_back(t);
+        }
+    return pack_segments(items, SEGT_MAX, RESIDENT_TRI);
 }
 
 // FP64 forward contraction: group (l0, mb) runs the row recursions from nmax =
@@ -652,6 +688,10 @@ int build_spin_table(const Plan& p, int as, SpinTable& t, std::string& err)
     auto edge = [&](int l, int m) { return E[(size_t)l * (l + 1) / 2 + m]; };
     std::vector<double> val((size_t)L * L, 0.0);
     std::vector<int> kk((size_t)L * L, 0);
+    // (Pu'_m(l), c_l Delta^l_{m,|s|} / h_m(l)) for the FP64 inverse's transposed sums
+    std::vector<double2> lcos = lrec_factors(L, p.Lp);
+    for (double2& v : lcos) v.y = 0.0;
+    const std::vector<double2> hs = lrec_factors(L, p.Lp);
     for (int n = 0; n < L; ++n) {
         int l0 = std::max(n, as);
         if (l0 >= L) continue;
@@ -664,6 +704,9 @@ int build_spin_table(const Plan& p, int as, SpinTable& t, std::string& err)
             split_ext(a, x, k);
             val[(size_t)l * L + n] = (dcur < 0) ? -x : x;
             kk[(size_t)l * L + n] = k;
+            if (a > 0x1p-900L)
+                lcos[(size_t)n * p.Lp + l].y =
+                    (double)(sqrtl((2.0L * l + 1.0L) / (4.0L * PI_L)) * dcur / (ld)hs[(size_t)n * p.Lp + l].y);
             if (l + 1 >= L) break;
             ld dnext;
             if (l == 0) {
@@ -684,6 +727,10 @@ int build_spin_table(const Plan& p, int as, SpinTable& t, std::string& err)
     const std::vector<int4> w = inverse_work(p, as);
     t.nwinv = (int)(w.size() / SEGI_MAX);
     if ((rc = upload(w, &t.winv, t.bytes, err))) return rc;
+    if ((rc = upload(lcos, &t.lcos, t.bytes, err))) return rc;
+    const std::vector<int4> wt = inverse_work_tri(p, as);
+    t.nwtri = (int)(wt.size() / SEGT_MAX);
+    if ((rc = upload(wt, &t.wtri, t.bytes, err))) return rc;
     return 0;
 }
 
@@ -692,6 +739,8 @@ void free_spin_table(SpinTable& t)
     if (t.val) (void)hipFree(t.val);
     if (t.k) (void)hipFree(t.k);
     if (t.winv) (void)hipFree(t.winv);
+    if (t.lcos) (void)hipFree(t.lcos);
+    if (t.wtri) (void)hipFree(t.wtri);
     t = SpinTable();
 }
 

@@ -1,5 +1,5 @@
 // Host-only checks of the contraction work lists that the plan builder packs
-// (inverse_work, forward_work in mw_plan.cpp): every segment of every chain
+// (inverse_work, inverse_work_tri, forward_work in mw_plan.cpp): every segment of every chain
 // group appears exactly once, the segments of a group sit in consecutive slots
 // of one workgroup with a consistent lead slot, barrier flags match the groups
 // a workgroup holds, restart boundaries lie where checkpoints exist, and a list
@@ -45,7 +45,9 @@ static void check_balance(const char* tag, int L, const std::vector<int4>& w, in
           mx, total / 256, heaviest);
 }
 
-static void check_inverse(int L, int as)
+// tri: the list of the FP64 inverse over the triangle n >= m (inverse_work_tri,
+// SEGT_MAX slots, only the groups with m0 <= n0 + 63).
+static void check_inverse(int L, int as, bool tri)
 {
     Plan p;
     p.L = L;
@@ -54,15 +56,16 @@ static void check_inverse(int L, int as)
     ck_grid(L, p.segi, p.ckg, p.nck);
     CHECK(p.nck <= CKI_MAX && p.ckg % 2 == 0, "inverse L=%d: plane grid\n", L);
     auto plane = [&](int c) { return c > 0 && c < L && c % p.ckg == 0 && c / p.ckg < p.nck; };
-    const std::vector<int4> w = inverse_work(p, as);
-    CHECK(w.size() % SEGI_MAX == 0, "inverse L=%d: size\n", L);
+    const int S = tri ? SEGT_MAX : SEGI_MAX;
+    const std::vector<int4> w = tri ? inverse_work_tri(p, as) : inverse_work(p, as);
+    CHECK(w.size() % S == 0, "inverse L=%d: size\n", L);
     std::map<std::tuple<int, int, int>, int> seen;
     std::vector<long> steps(w.size(), 0);
-    for (size_t g = 0; g < w.size() / SEGI_MAX; ++g) {
-        const int4* s = &w[g * SEGI_MAX];
+    for (size_t g = 0; g < w.size() / S; ++g) {
+        const int4* s = &w[g * S];
         const int bar = (s[0].z >> 24) & 1;
         int anymulti = 0, items = 0;
-        for (int i = 0; i < SEGI_MAX; ++i) {
+        for (int i = 0; i < S; ++i) {
             CHECK(((s[i].z >> 24) & 1) == bar, "inverse L=%d s=%d: barrier flag differs within workgroup %zu\n", L,
                   as, g);
             if (s[i].x < 0) continue;
@@ -72,13 +75,14 @@ static void check_inverse(int L, int as)
             const int cs = s[i].w & 0xffff, ce = (int)((unsigned)s[i].w >> 16);
             anymulti |= nseg > 1;
             CHECK(n0 % 64 == 0 && n0 < L && m0 % 2 == 0 && m0 < L, "inverse L=%d: group (%d, %d)\n", L, n0, m0);
-            CHECK(lead + seg == i && lead + nseg <= SEGI_MAX, "inverse L=%d: slot layout\n", L);
-            for (int k = 0; k < nseg && lead + k < SEGI_MAX; ++k) {
+            CHECK(!tri || m0 <= n0 + 63, "inverse L=%d: group (%d, %d) above the triangle\n", L, n0, m0);
+            CHECK(lead + seg == i && lead + nseg <= S, "inverse L=%d: slot layout\n", L);
+            for (int k = 0; k < nseg && lead + k < S; ++k) {
                 const int4 o = s[lead + k];
                 CHECK(o.x == n0 && o.y == m0 && (o.z & 0xff) == k && ((o.z >> 8) & 0xff) == nseg,
                       "inverse L=%d: sibling segment\n", L);
                 // consecutive segments of the group meet at their common boundary
-                if (k + 1 < nseg && lead + k + 1 < SEGI_MAX)
+                if (k + 1 < nseg && lead + k + 1 < S)
                     CHECK(((unsigned)o.w >> 16) == (unsigned)(s[lead + k + 1].w & 0xffff),
                           "inverse L=%d: segments not contiguous\n", L);
             }
@@ -93,23 +97,23 @@ static void check_inverse(int L, int as)
             if (seg >= 1) CHECK(plane(cs) && cs >= lA, "inverse L=%d s=%d: restart degree %d\n", L, as, cs);
             if (seg == nseg - 1) CHECK(ce == p.Lp, "inverse L=%d: last segment end\n", L);
             CHECK(ce > cs && cs % 2 == 0 && ce % 2 == 0, "inverse L=%d: segment [%d, %d)\n", L, cs, ce);
-            CHECK(nseg >= 1 && nseg <= SEGI_MAX, "inverse L=%d: segment count\n", L);
-            steps[g * SEGI_MAX + i] = ce - cs;
+            CHECK(nseg >= 1 && nseg <= S, "inverse L=%d: segment count\n", L);
+            steps[g * S + i] = ce - cs;
             CHECK(seen[std::make_tuple(n0, m0, seg)]++ == 0, "inverse L=%d: duplicate segment\n", L);
         }
         CHECK(!items || bar == anymulti, "inverse L=%d: barrier flag of workgroup %zu\n", L, g);
     }
     // the chains of every group are covered from lstart to the last degree
     for (int n0 = 0; n0 < L; n0 += 64)
-        for (int m0 = 0; m0 < L; m0 += 2) {
+        for (int m0 = 0; m0 < L && (!tri || m0 <= n0 + 63); m0 += 2) {
             int nseg = -1;
-            for (int k = 0; k < SEGI_MAX; ++k)
+            for (int k = 0; k < S; ++k)
                 if (seen.count(std::make_tuple(n0, m0, k))) nseg = k + 1;
             CHECK(nseg >= 1, "inverse L=%d s=%d: group (%d, %d) missing\n", L, as, n0, m0);
             for (int k = 0; k < nseg; ++k)
                 CHECK(seen.count(std::make_tuple(n0, m0, k)) == 1, "inverse L=%d: segment gap\n", L);
         }
-    check_balance("inverse", L, w, SEGI_MAX, RESIDENT_INV, steps);
+    check_balance(tri ? "inverse (triangle)" : "inverse", L, w, S, tri ? RESIDENT_TRI : RESIDENT_INV, steps);
 }
 
 static void check_forward(int L)
@@ -185,8 +189,9 @@ int main()
         ++cases;
         for (int as : {0, 1, 2, 3, 7, 63, 64, 65, 100, 200, L - 1}) {
             if (as < 0 || as >= L) continue;
-            check_inverse(L, as);
-            ++cases;
+            check_inverse(L, as, false);
+            check_inverse(L, as, true);
+            cases += 2;
         }
     }
     printf("%ld work lists checked, %ld problems\n", cases, bad);
