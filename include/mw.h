@@ -233,12 +233,19 @@ int mw_set_workspace(void* dptr, size_t bytes, void* stream);
 /* Create the plan tables and workspace a call with these arguments needs, on the
  * current device, so that a later call (e.g. one under stream capture) performs
  * no allocation.  With precision MW_FP32C it also times the candidate group
- * sizes of the shared-recursion contraction for each (L, spin, reality) class of
- * the batch and keeps the fastest for later calls of the same shape (the
- * results do not depend on the choice).  Synchronises the device.
+ * sizes of the shared-recursion contraction for each (L, reality) class of the
+ * batch and keeps the fastest for later calls of the same shape (the results do
+ * not depend on the choice).  Synchronises the device.
  *
- * Batching: a call runs its maps in chunks of equal (L, spin, reality), each
- * stage of a chunk being one kernel launch over all its maps.  Several chunks
+ * Batching: an FP64 call runs its maps in chunks of equal (L, spin, reality); an
+ * MW_FP32C call in chunks of equal reality whose maps share the Wigner
+ * recursions in groups of up to four maps with at most two different |s| (Sec.
+ * V's remark that the Wigner values need not be recomputed): groups of one
+ * band-limit, except that the maps of a band-limit with fewer than four maps in
+ * the call join the last group of a larger one (its recursions run to its
+ * largest band-limit; each map masks the degrees beyond its own).  Each stage
+ * of a chunk is one kernel launch per band-limit over its maps (the
+ * contractions: one per group band-limit and set of spin rows).  Several chunks
  * alternate over two internal streams (created here or on the first such call)
  * that fork from and join back into the caller's stream; calls under
  * stream capture (hipGraph) record those launches with their arguments and

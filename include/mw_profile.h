@@ -35,9 +35,10 @@ int mw_profile_read(double* ms, int* count);
 const char* mw_profile_stage_name(int stage);
 
 /* Group size (maps sharing one set of Wigner recursions) that mw_prepare's
- * autotuner chose for mixed-precision calls with `nmaps` maps of band-limit L
- * and the given reality; *G = 0 when that shape was not tuned (calls then use
- * the largest size the LDS allows, up to the map count). */
+ * autotuner chose for the groups that start at band-limit L in mixed-precision
+ * calls with `nmaps` maps of band-limit <= L and the given reality; *G = 0 when
+ * that shape was not tuned (calls then use the largest size the LDS allows, up
+ * to that map count). */
 int mw_profile_tuned_group(int L, int reality, int nmaps, int* G);
 
 /* The autotuner's cache: with the environment variable MW_TUNE_CACHE naming a

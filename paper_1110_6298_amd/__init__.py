@@ -382,8 +382,9 @@ def profile_read() -> dict:
 
 
 def tuned_group(L: int, reality: int, nmaps: int) -> int:
-    """Group size the autotuner chose for mixed-precision calls with ``nmaps``
-    maps of band-limit L and this reality (0 = not tuned)."""
+    """Group size the autotuner chose for the groups that start at band-limit L in
+    mixed-precision calls with ``nmaps`` maps of band-limit <= L and this
+    reality (0 = not tuned)."""
     g = ctypes.c_int(0)
     _check(library().mw_profile_tuned_group(L, reality, nmaps, ctypes.byref(g)), "mw_profile_tuned_group")
     return int(g.value)

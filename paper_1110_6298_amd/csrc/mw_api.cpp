@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <set>
 #include <mutex>
 #include <tuple>
 #include <string>
@@ -215,19 +216,54 @@ Regions slot(void* ws, int Lws, int L, int k)
     return r;
 }
 
-// Maps of one call with equal band-limit and reality run together: every
-// Fourier stage is one launch over the chunk (blockIdx.y = map, each map with
-// its own spin).  In FP64 a chunk also has one spin (the FP64 contractions run
-// one spin row); in mixed precision it may hold several spins, sorted by (|s|, s),
-// and its maps share the Wigner order chains in groups of up to G maps with at
-// most two different |s| (the spin rows run beside the shared chains).
+// Maps of one call run in chunks.  In FP64 a chunk holds maps of one band-limit,
+// reality and spin (the FP64 contractions run one spin row).  In mixed precision
+// a chunk holds maps of one reality, sorted by (-L, |s|, s), whose maps share
+// the Wigner order chains in groups of up to G maps with at most two different
+// |s| (the spin rows run beside the shared chains, Sec. V's remark on several
+// spins); the maps of a band-limit with few maps in the call (`ride`) may join
+// the last group of a larger band-limit, whose chains run to that band-limit
+// (each map masks the degrees l >= L_b).  Every Fourier stage is one launch per
+// band-limit of the chunk (blockIdx.y = map, each map with its own spin).
 struct Chunk {
-    int L = 0, s = 0, real = 0, G = 1;   // s: the spin of an FP64 chunk
+    int L = 0, s = 0, real = 0;   // L: the largest band-limit; s: the spin of an FP64 chunk
     std::vector<int> maps;    // batch indices
     std::vector<int> spins;   // their spins
+    std::vector<int> Ls;      // their band-limits
+    std::map<int, int> G;     // mixed precision: group size of the groups that start at each band-limit
+    std::set<int> ride;       // band-limits whose maps may join a group that starts at a larger one
 };
 
-// Autotuned group size per (band-limit, reality, maps in the chunk), from mw_prepare.
+// End of the mixed group that starts at map i of a sequence of n maps sorted by
+// (-L, |s|): up to G[L_i] maps, each of band-limit L_i or in `ride`, with at
+// most two different |s|.  Lof(k), asof(k): band-limit and |s| of map k.
+template <class LF, class AF>
+size_t group_end(size_t n, size_t i, LF Lof, AF asof, const std::map<int, int>& G, const std::set<int>& ride)
+{
+    const int L0 = Lof(i), Gl = G.at(L0);
+    int rows[mw::NSMAX] = {-1, -1}, nr = 0;
+    size_t j = i;
+    while (j < n && (int)(j - i) < Gl && (Lof(j) == L0 || ride.count(Lof(j)))) {
+        const int as = asof(j);
+        if (rows[0] != as && rows[1] != as) {
+            if (nr == mw::NSMAX) break;
+            rows[nr++] = as;
+        }
+        ++j;
+    }
+    return j;
+}
+
+// The distinct band-limits of a chunk, in chunk order (descending).
+std::vector<int> chunk_ls(const Chunk& c)
+{
+    std::vector<int> a;
+    for (int L : c.Ls)
+        if (a.empty() || a.back() != L) a.push_back(L);
+    return a;
+}
+
+// Autotuned group size per (band-limit, reality, maps of that band-limit and reality), from mw_prepare.
 std::map<std::tuple<int, int, int>, int> g_tuned;
 
 int pow2_ceil(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : 4; }
@@ -255,31 +291,67 @@ std::vector<Chunk> make_chunks(const int32_t* L, const int32_t* spin, const int3
                                int precision)
 {
     const bool mix = precision != MW_FP64;
-    // class key: (-L, reality, spin) in FP64, (-L, reality) in mixed precision;
-    // members sorted by (|s|, s, index)
-    std::map<std::tuple<int, int, int>, std::vector<std::tuple<int, int, int>>> cls;
+    // class key: (-L, reality, spin) in FP64, (reality) in mixed precision;
+    // members sorted by (-L, |s|, s, index)
+    std::map<std::tuple<int, int, int>, std::vector<std::tuple<int, int, int, int>>> cls;
     for (int b = 0; b < batch; ++b) {
         const int as = spin[b] < 0 ? -spin[b] : spin[b];
-        cls[std::make_tuple(-L[b], reality[b], mix ? 0 : spin[b])].push_back(std::make_tuple(as, spin[b], b));
+        cls[std::make_tuple(mix ? 0 : -L[b], reality[b], mix ? 0 : spin[b])].push_back(
+            std::make_tuple(-L[b], as, spin[b], b));
     }
     std::vector<Chunk> out;
     for (auto& kv : cls) {
-        const int Lc = -std::get<0>(kv.first), rc_ = std::get<1>(kv.first);
+        const int rc_ = std::get<1>(kv.first);
         auto v = kv.second;
         std::sort(v.begin(), v.end());
-        const int G = mix ? group_size(Lc, rc_, (int)v.size()) : 1;
-        const int cap = chunk_cap(Lc);
-        for (size_t i = 0; i < v.size(); i += cap) {
+        // group size per band-limit L: the autotuned one for (L, reality, maps
+        // of band-limit <= L and that reality: those a group starting at L can
+        // take), else the largest the LDS allows
+        std::map<int, int> G;
+        for (const auto& t : v) G[-std::get<0>(t)] = 0;
+        for (auto& kl : G) {
+            int nle = 0;
+            for (const auto& t : v) nle += (-std::get<0>(t) <= kl.first) ? 1 : 0;
+            kl.second = mix ? group_size(kl.first, rc_, nle) : 1;
+        }
+        const int cap = chunk_cap(-std::get<0>(v[0]));
+        // Maps of a band-limit fewer than the largest group ride along in the
+        // last group of a larger band-limit (its chains reach their degrees
+        // already); band-limits with that many maps or more keep to their own
+        // groups, since a group of mixed band-limits costs an extra launch of
+        // every Fourier stage and saves at most one small group.
+        std::set<int> ride;
+        if (mix) {
+            std::map<int, int> nl;
+            for (const auto& t : v) ++nl[-std::get<0>(t)];
+            for (const auto& kl : nl)
+                if (kl.first != -std::get<0>(v[0]) && kl.second < mw::mix_group_max()) ride.insert(kl.first);
+        }
+        auto Lof = [&](size_t k) { return -std::get<0>(v[k]); };
+        auto asof = [&](size_t k) { return std::get<1>(v[k]); };
+        // whole groups, formed as mix_of forms them, go into chunks of equal
+        // group band-limit up to the capacity
+        size_t i = 0;
+        while (i < v.size()) {
             Chunk c;
-            c.L = Lc; c.real = rc_; c.G = G;
-            for (size_t k = i; k < std::min(v.size(), i + (size_t)cap); ++k) {
-                c.maps.push_back(std::get<2>(v[k]));
-                c.spins.push_back(std::get<1>(v[k]));
+            c.L = -std::get<0>(v[i]); c.real = rc_; c.G = G; c.ride = ride;
+            while (i < v.size() && -std::get<0>(v[i]) == c.L) {
+                const size_t j = mix ? group_end(v.size(), i, Lof, asof, G, ride) : i + 1;
+                if (!c.maps.empty() && c.maps.size() + (j - i) > (size_t)cap) break;
+                for (size_t k = i; k < j; ++k) {
+                    c.maps.push_back(std::get<3>(v[k]));
+                    c.spins.push_back(std::get<2>(v[k]));
+                    c.Ls.push_back(-std::get<0>(v[k]));
+                }
+                i = j;
             }
             c.s = c.spins[0];
             out.push_back(c);
         }
     }
+    // chunks of one band-limit run next to each other (the two chunk streams then
+    // overlap stages of similar sizes)
+    std::stable_sort(out.begin(), out.end(), [](const Chunk& a, const Chunk& b) { return a.L > b.L; });
     return out;
 }
 
@@ -297,65 +369,89 @@ mw::Batch batch_of(const Chunk& c, In in, Out out)
     return B;
 }
 
+// The same for the maps of band-limit L of the chunk (map k reads in(k) with k
+// the chunk's index): one stage launch of that band-limit.
+template <class In, class Out>
+mw::Batch batch_sub(const Chunk& c, int L, In in, Out out)
+{
+    mw::Batch B{};
+    for (int k = 0; k < (int)c.maps.size(); ++k) {
+        if (c.Ls[k] != L) continue;
+        B.in[B.n] = in(k);
+        B.out[B.n] = out(k);
+        B.s[B.n] = c.spins[k];
+        ++B.n;
+    }
+    return B;
+}
+
 // The distinct |s| of a chunk (ascending).
 std::vector<int> chunk_abs_spins(const Chunk& c)
 {
     std::vector<int> a;
-    for (int s : c.spins) {
-        const int v = s < 0 ? -s : s;
-        if (a.empty() || a.back() != v) a.push_back(v);
-    }
+    for (int s : c.spins) a.push_back(s < 0 ? -s : s);
+    std::sort(a.begin(), a.end());
+    a.erase(std::unique(a.begin(), a.end()), a.end());
     return a;
 }
 
-// One launch of a mixed contraction: up to MIXG groups with the same spin rows.
+// One launch of a mixed contraction: up to MIXG groups with the same spin rows
+// and the same largest band-limit L (the plan the launch runs).
 struct MixLaunch {
     mw::MixBatch M{};
+    int L = 0;
+    int G = 1;   // the group size limit of its groups (kernel instance)
     int asmax = 0;   // the largest |s| of the spin rows (its spin table's work list runs the inverse)
 };
 
-// Groups of the chunk's maps (in chunk order, sorted by |s|): up to c.G maps
-// with at most two different |s|; groups with the same spin rows share launches.
-// stab(as) gives the spin table of |s| = as (inverse) or nullptr (forward).
+// Groups of the chunk's maps (in chunk order, sorted by (-L, |s|)): up to
+// c.G[L] maps, L the band-limit of the group's first (largest) map, with at most
+// two different |s|; groups with the same spin rows and the same largest
+// band-limit share launches.  stab(L, as) gives the spin table of
+// band-limit L and |s| = as (inverse) or nullptr (forward).
 template <class Src, class Dst, class Tab>
 std::vector<MixLaunch> mix_of(const Chunk& c, Src src, Dst dst, Tab stab)
 {
-    // groups by their spin rows (as0, as1 or -1)
-    std::map<std::pair<int, int>, std::vector<mw::MixMaps>> byrows;
+    // groups by (largest L, spin rows (as0, as1 or -1))
+    std::map<std::tuple<int, int, int>, std::vector<mw::MixMaps>> byrows;
     const int n = (int)c.maps.size();
+    auto Lof = [&](size_t k) { return c.Ls[k]; };
+    auto asof = [&](size_t k) { return c.spins[k] < 0 ? -c.spins[k] : c.spins[k]; };
     for (int i = 0; i < n;) {
         mw::MixMaps mm{};
-        int rows[mw::NSMAX] = {0, 0}, nr = 0, nm = 0;
-        while (i < n && nm < c.G) {
+        int rows[mw::NSMAX] = {0, 0}, nr = 0, nm = 0, Lg = 0;
+        const int iend = (int)group_end((size_t)n, (size_t)i, Lof, asof, c.G, c.ride);
+        while (i < iend) {
             const int s = c.spins[i], as = s < 0 ? -s : s;
             int j = 0;
             while (j < nr && rows[j] != as) ++j;
-            if (j == nr) {
-                if (nr == mw::NSMAX) break;
-                rows[nr++] = as;
-            }
+            if (j == nr) rows[nr++] = as;
             mm.src[nm] = (const float*)src(i);
             mm.dst[nm] = (double2*)dst(i);
-            mm.L[nm] = c.L;
+            mm.L[nm] = c.Ls[i];
+            Lg = std::max(Lg, c.Ls[i]);
             mm.meta |= (j << (4 + nm)) | ((s < 0 ? 1 : 0) << (8 + nm));
             ++nm;
             ++i;
         }
         mm.meta |= nm;
-        byrows[std::make_pair(rows[0], nr > 1 ? rows[1] : -1)].push_back(mm);
+        byrows[std::make_tuple(-Lg, rows[0], nr > 1 ? rows[1] : -1)].push_back(mm);
     }
     std::vector<MixLaunch> out;
     for (auto& kv : byrows) {
         const auto& gs = kv.second;
+        const int Lg = -std::get<0>(kv.first), as0 = std::get<1>(kv.first), as1 = std::get<2>(kv.first);
         for (size_t k = 0; k < gs.size(); k += mw::MIXG) {
             MixLaunch ml;
+            ml.L = Lg;
+            ml.G = c.G.at(Lg);
             ml.M.ng = (int)std::min<size_t>(mw::MIXG, gs.size() - k);
             for (int g = 0; g < ml.M.ng; ++g) ml.M.g[g] = gs[k + g];
-            ml.M.ns = kv.first.second >= 0 ? 2 : 1;
-            ml.M.as[0] = kv.first.first;
-            ml.M.as[1] = kv.first.second >= 0 ? kv.first.second : kv.first.first;
+            ml.M.ns = as1 >= 0 ? 2 : 1;
+            ml.M.as[0] = as0;
+            ml.M.as[1] = as1 >= 0 ? as1 : as0;
             for (int j = 0; j < mw::NSMAX; ++j) {
-                const SpinTable* t = stab(ml.M.as[j]);
+                const SpinTable* t = stab(Lg, ml.M.as[j]);
                 ml.M.stab[j] = t ? t->val : nullptr;
                 ml.M.stabk[j] = t ? t->k : nullptr;
             }
@@ -366,50 +462,64 @@ std::vector<MixLaunch> mix_of(const Chunk& c, Src src, Dst dst, Tab stab)
     return out;
 }
 
-// Spin tables of one chunk, by |s|.
-using ChunkSpins = std::map<int, const SpinTable*>;
+// Plans of one chunk by band-limit; spin tables by (band-limit, |s|).
+using ChunkPlans = std::map<int, const Plan*>;
+using ChunkSpins = std::map<std::pair<int, int>, const SpinTable*>;
 
 // compact: maps in the compact storage of Sec. IV-C ((L-1)(2L-1)+1 samples, the
 // south pole once), expanded or contracted by the phi stages.
-// sps: the spin tables of the chunk's |s| (inverse and forward adjoint).
-hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const ChunkSpins& sps, int precision, void* const* ptrs,
-                     void* ws, int Lws, hipStream_t st, bool prof = true, bool compact = false)
+// plans: the plan of every band-limit of the chunk; sps: the spin tables of its
+// (band-limits, |s|) (inverse and forward adjoint).
+hipError_t run_chunk(Op op, const Chunk& c, const ChunkPlans& plans, const ChunkSpins& sps, int precision,
+                     void* const* ptrs, void* ws, int Lws, hipStream_t st, bool prof = true, bool compact = false)
 {
     const int pole_in = compact ? 1 : 0;    // a map read as the forward's input: expand the pole sample
     const int pole_out = compact ? 1 : 0;   // a map written by the inverse: keep the pole sample
     const int pole_adj = compact ? 2 : 0;   // the adjoints of those two
     const bool mix = precision != MW_FP64;
     const int s = c.s, real = c.real;
-    const double phi_sc = TWO_PI / (double)p.N1;
+    const std::vector<int> Ls = chunk_ls(c);
     auto user_in = [&](int k) { return (void*)ptrs[2 * c.maps[k]]; };
     auto user_out = [&](int k) { return (void*)ptrs[2 * c.maps[k] + 1]; };
-    auto w0 = [&](int k) { return (void*)slot(ws, Lws, c.L, k).W0; };
-    auto w1 = [&](int k) { return (void*)slot(ws, Lws, c.L, k).W1; };
-    auto w2 = [&](int k) { return (void*)slot(ws, Lws, c.L, k).W2; };
+    auto w0 = [&](int k) { return (void*)slot(ws, Lws, c.Ls[k], k).W0; };
+    auto w1 = [&](int k) { return (void*)slot(ws, Lws, c.Ls[k], k).W1; };
+    auto w2 = [&](int k) { return (void*)slot(ws, Lws, c.Ls[k], k).W2; };
     hipError_t e = hipSuccess;
     auto go = [&](int stage, auto launch) {
         if (e == hipSuccess) e = staged(stage, st, prof, launch);
     };
-    auto no_tab = [](int) -> const SpinTable* { return nullptr; };
-    auto tab = [&](int as) -> const SpinTable* {
-        auto it = sps.find(as);
+    // one launch of a stage per band-limit of the chunk: launch(plan, maps of that L)
+    auto per_l = [&](int stage, auto in, auto out, auto launch) {
+        for (int L : Ls) {
+            const Plan& p = *plans.at(L);
+            const mw::Batch B = batch_sub(c, L, in, out);
+            go(stage, [&] { return launch(p, B); });
+        }
+    };
+    auto no_tab = [](int, int) -> const SpinTable* { return nullptr; };
+    auto tab = [&](int L, int as) -> const SpinTable* {
+        auto it = sps.find(std::make_pair(L, as));
         return it == sps.end() ? nullptr : it->second;
     };
-    // the mixed contractions of the chunk: one launch per set of spin rows
+    // the mixed contractions of the chunk: one launch per (largest L, spin rows)
     auto mix_forward = [&](int stage, auto src, auto dst) {
         for (const MixLaunch& ml : mix_of(c, src, dst, no_tab))
-            go(stage, [&] { return mw::launch_contract_forward_mix(p, ml.M, c.G, ml.M.ns, st); });
+            go(stage, [&] { return mw::launch_contract_forward_mix(*plans.at(ml.L), ml.M, ml.G, ml.M.ns, st); });
     };
+    // FP64 chunks hold one band-limit
+    const Plan& p0 = *plans.at(c.L);
     switch (op) {
     case Op::Forward: {
-        const mw::Batch B1 = batch_of(c, user_in, w0), B2 = batch_of(c, w0, w1), B3 = batch_of(c, w1, user_out);
-        go(0, [&] { return mw::launch_phi_forward(p, B1, real, phi_sc, pole_in, st); });
-        go(1, [&] { return mw::launch_theta_forward(p, B2, mix, real, st); });
+        per_l(0, user_in, w0, [&](const Plan& p, const mw::Batch& B) {
+            return mw::launch_phi_forward(p, B, real, TWO_PI / (double)p.N1, pole_in, st);
+        });
+        per_l(1, w0, w1, [&](const Plan& p, const mw::Batch& B) { return mw::launch_theta_forward(p, B, mix, real, st); });
         if (mix) {
             mix_forward(2, w1, user_out);
         } else {
+            const mw::Batch B3 = batch_of(c, w1, user_out);
             go(2, [&] {
-                return mw::launch_contract_forward(p, s, real, (const double*)w1(0), ws_need(Lws) / 8, B3, st);
+                return mw::launch_contract_forward(p0, s, real, (const double*)w1(0), ws_need(Lws) / 8, B3, st);
             });
         }
         break;
@@ -421,32 +531,38 @@ hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const ChunkSpins& sps
         // coefficients as given (no real-map expansion), then the theta and phi
         // adjoints; with real = 1 it stores Re(A^H y).
         const bool inv = op == Op::Inverse;
-        const mw::Batch B1 = batch_of(c, user_in, w2), B2 = batch_of(c, w2, w0), B3 = batch_of(c, w0, w1),
-                        B4 = batch_of(c, w1, user_out);
-        go(8, [&] { return mw::launch_inverse_stream(p, inv ? real : 0, B1, mix, st); });
+        per_l(8, user_in, w2, [&](const Plan& p, const mw::Batch& B) {
+            return mw::launch_inverse_stream(p, inv ? real : 0, B, mix, st);
+        });
         if (mix) {
             for (const MixLaunch& ml : mix_of(c, w2, w0, tab)) {
-                const SpinTable* wsp = tab(ml.asmax);
+                const SpinTable* wsp = tab(ml.L, ml.asmax);
                 if (!wsp) { e = hipErrorInvalidValue; break; }
-                go(inv ? 3 : 6, [&] { return mw::launch_contract_inverse_mix(p, *wsp, ml.M, c.G, ml.M.ns, st); });
+                go(inv ? 3 : 6, [&] {
+                    return mw::launch_contract_inverse_mix(*plans.at(ml.L), *wsp, ml.M, ml.G, ml.M.ns, st);
+                });
             }
         } else {
-            const SpinTable* sp = tab(s < 0 ? -s : s);
+            const SpinTable* sp = tab(c.L, s < 0 ? -s : s);
             if (!sp) return hipErrorInvalidValue;
-            // the FP64 kernel reads the stream from the workspace and f_lm itself
-            const mw::Batch B2f = batch_of(c, user_in, w0);
+            // the FP64 kernels read the stream from the workspace and f_lm itself
+            const mw::Batch B2 = batch_of(c, user_in, w0);
             go(inv ? 3 : 6, [&] {
-                return mw::launch_contract_inverse(p, *sp, s, inv ? real : 0, (const double*)w2(0), ws_need(Lws) / 8,
-                                                   B2f, st);
+                return mw::launch_contract_inverse(p0, *sp, s, inv ? real : 0, (const double*)w2(0), ws_need(Lws) / 8,
+                                                   B2, st);
             });
         }
         if (inv) {
             // real maps: orders m >= 0 only, negative orders by conjugate symmetry
-            go(4, [&] { return mw::launch_theta_inverse(p, B3, real, st); });
-            go(5, [&] { return mw::launch_phi_inverse(p, B4, real ? 2 : 0, 1.0, pole_out, st); });
+            per_l(4, w0, w1, [&](const Plan& p, const mw::Batch& B) { return mw::launch_theta_inverse(p, B, real, st); });
+            per_l(5, w1, user_out, [&](const Plan& p, const mw::Batch& B) {
+                return mw::launch_phi_inverse(p, B, real ? 2 : 0, 1.0, pole_out, st);
+            });
         } else {
-            go(8, [&] { return mw::launch_theta_forward_adjoint(p, B3, st); });
-            go(8, [&] { return mw::launch_phi_inverse(p, B4, real, phi_sc, pole_adj, st); });
+            per_l(8, w0, w1, [&](const Plan& p, const mw::Batch& B) { return mw::launch_theta_forward_adjoint(p, B, st); });
+            per_l(8, w1, user_out, [&](const Plan& p, const mw::Batch& B) {
+                return mw::launch_phi_inverse(p, B, real, TWO_PI / (double)p.N1, pole_adj, st);
+            });
         }
         break;
     }
@@ -454,17 +570,22 @@ hipError_t run_chunk(Op op, const Chunk& c, const Plan& p, const ChunkSpins& sps
         // grid -> coefficients: phi and theta adjoints, then the forward's
         // contraction (the conjugate transpose of the inverse's); with real = 1
         // the real-map coefficient expansion is adjoined last.
-        const mw::Batch B1 = batch_of(c, user_in, w0), B2 = batch_of(c, w0, w1), B3 = batch_of(c, w1, user_out);
-        go(8, [&] { return mw::launch_phi_forward(p, B1, real, 1.0, pole_adj, st); });
-        go(8, [&] { return mw::launch_theta_inverse_adjoint(p, B2, mix, st); });
+        per_l(8, user_in, w0, [&](const Plan& p, const mw::Batch& B) {
+            return mw::launch_phi_forward(p, B, real, 1.0, pole_adj, st);
+        });
+        per_l(8, w0, w1, [&](const Plan& p, const mw::Batch& B) {
+            return mw::launch_theta_inverse_adjoint(p, B, mix, st);
+        });
         if (mix) {
             mix_forward(7, w1, user_out);
         } else {
+            const mw::Batch B3 = batch_of(c, w1, user_out);
             go(7, [&] {
-                return mw::launch_contract_forward(p, s, 0, (const double*)w1(0), ws_need(Lws) / 8, B3, st);
+                return mw::launch_contract_forward(p0, s, 0, (const double*)w1(0), ws_need(Lws) / 8, B3, st);
             });
         }
-        if (real) go(8, [&] { return mw::launch_real_fold(p.L, B3, st); });
+        if (real)
+            per_l(8, w1, user_out, [&](const Plan& p, const mw::Batch& B) { return mw::launch_real_fold(p.L, B, st); });
         break;
     }
     }
@@ -488,6 +609,27 @@ size_t chunks_ws(const std::vector<Chunk>& ch, int Lws)
 // Workspace of a call: one half per chunk stream when it has several chunks.
 size_t call_ws(const std::vector<Chunk>& ch, int Lws) { return (ch.size() > 1 ? 2 : 1) * chunks_ws(ch, Lws); }
 
+// The plans of a chunk's band-limits and, with spins, the spin tables of every
+// (band-limit, |s|) of the chunk (a mixed group's chains run to its largest
+// band-limit with the rows of all its spins).
+int resolve_chunk(DeviceState& d, const Chunk& c, bool spins, bool may_alloc, ChunkPlans& plans, ChunkSpins& tabs)
+{
+    int rc;
+    for (int Lc : chunk_ls(c)) {
+        const Plan* p = nullptr;
+        if ((rc = get_plan(d, Lc, may_alloc, &p))) return rc;
+        plans[Lc] = p;
+        if (!spins) continue;
+        for (int as : chunk_abs_spins(c)) {
+            if (as >= Lc) continue;   // no map of band-limit Lc has this spin (|s| < L)
+            const SpinTable* t = nullptr;
+            if ((rc = get_spin(d, *p, as, may_alloc, &t))) return rc;
+            tabs[std::make_pair(Lc, as)] = t;
+        }
+    }
+    return MW_OK;
+}
+
 int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, int32_t batch,
         void* const* ptrs, int32_t precision, void* stream, bool compact = false)
 {
@@ -503,18 +645,10 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     const std::vector<Chunk> chunks = make_chunks(L, spin, reality, batch, precision);
     // every plan, spin table and the workspace are resolved before anything is
     // enqueued, so that a failure leaves the stream (and a capture) untouched
-    std::vector<const Plan*> plans(chunks.size(), nullptr);
+    std::vector<ChunkPlans> plans(chunks.size());
     std::vector<ChunkSpins> spins(chunks.size());
-    for (size_t i = 0; i < chunks.size(); ++i) {
-        const Chunk& c = chunks[i];
-        if ((rc = get_plan(d, c.L, may_alloc, &plans[i]))) return rc;
-        if (!need_spin) continue;
-        for (int as : chunk_abs_spins(c)) {
-            const SpinTable* t = nullptr;
-            if ((rc = get_spin(d, *plans[i], as, may_alloc, &t))) return rc;
-            spins[i][as] = t;
-        }
-    }
+    for (size_t i = 0; i < chunks.size(); ++i)
+        if ((rc = resolve_chunk(d, chunks[i], need_spin, may_alloc, plans[i], spins[i]))) return rc;
     const int Lws = batch_lmax(L, batch);
     const size_t need = call_ws(chunks, Lws);
     void* ws = nullptr;
@@ -540,7 +674,7 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     for (size_t i = 0; i < chunks.size() && e == hipSuccess; ++i) {
         hipStream_t cs = lanes ? d.lane[i & 1] : st;
         void* cws = lanes ? (void*)((char*)ws + (i & 1) * half) : ws;
-        e = run_chunk(op, chunks[i], *plans[i], spins[i], precision, ptrs, cws, Lws, cs, true, compact);
+        e = run_chunk(op, chunks[i], plans[i], spins[i], precision, ptrs, cws, Lws, cs, true, compact);
     }
     if (lanes) {
         // join both chunk streams back into the caller's stream, also after a failed launch
@@ -593,53 +727,75 @@ void tune_cache_append(const char* path, int Lc, int rc_, int n, int G)
     fclose(f);
 }
 
-// Times the mixed forward contraction of each (L, reality) class of a call with
-// its own spins, per candidate group size, on zeroed workspace, and keeps the
-// fastest per map; results do not depend on the choice (each map keeps its own
-// accumulators over the shared chains).
+// Times the mixed forward contraction of the maps of each (L, reality) of a call
+// (up to one chunk's worth, with their own spins), per candidate group size, on
+// zeroed workspace, and keeps the fastest per map for the key (L, reality, maps
+// of band-limit <= L and that reality), the group size of the groups that start
+// at L in make_chunks; results do not depend on the choice (each map keeps its
+// own accumulators over the shared chains).
 int autotune(DeviceState& d, const int32_t* L, const int32_t* spin, const int32_t* reality, int batch)
 {
     const char* cache = tune_cache_path();
     if (cache) tune_cache_load(cache);
-    const std::vector<Chunk> chunks = make_chunks(L, spin, reality, batch, MW_FP32C);
-    std::map<std::pair<int, int>, int> cnt;   // maps per (L, reality)
-    for (int b = 0; b < batch; ++b) ++cnt[std::make_pair(L[b], reality[b])];
+    // the maps of each (L, reality), sorted by (|s|, s) as in a chunk
+    std::map<std::pair<int, int>, std::vector<std::tuple<int, int, int>>> cls;
+    for (int b = 0; b < batch; ++b) {
+        const int as = spin[b] < 0 ? -spin[b] : spin[b];
+        cls[std::make_pair(L[b], reality[b])].push_back(std::make_tuple(as, spin[b], b));
+    }
     const int Lws = batch_lmax(L, batch);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(MW_EHIP, "hipEventCreate failed");
     int rc = MW_OK;
-    for (const Chunk& c0 : chunks) {
-        const int n = cnt[std::make_pair(c0.L, c0.real)];
-        const auto key = std::make_tuple(c0.L, c0.real, n);
+    for (auto& kv : cls) {
+        const int Lc = kv.first.first, rc_ = kv.first.second;
+        int n = 0;   // maps of band-limit <= Lc and this reality
+        for (int b = 0; b < batch; ++b) n += (reality[b] == rc_ && L[b] <= Lc) ? 1 : 0;
+        const auto key = std::make_tuple(Lc, rc_, n);
         if (g_tuned.count(key)) continue;
-        const Plan* p = nullptr;
-        if ((rc = get_plan(d, c0.L, true, &p))) break;
+        auto v = kv.second;
+        std::sort(v.begin(), v.end());
+        Chunk c0;
+        c0.L = Lc; c0.real = rc_;
+        for (int k = 0; k < std::min(n, chunk_cap(Lc)); ++k) {
+            c0.maps.push_back(std::get<2>(v[k]));
+            c0.spins.push_back(std::get<1>(v[k]));
+            c0.Ls.push_back(Lc);
+        }
+        c0.s = c0.spins[0];
+        ChunkPlans plans;
+        ChunkSpins none;
+        if ((rc = resolve_chunk(d, c0, false, true, plans, none))) break;
         const int gmax = std::min(pow2_ceil(n), mw::mix_group_max());
         const int nt = (int)c0.maps.size();
         void* ws = nullptr;
         if ((rc = get_ws(d, (size_t)nt * ws_need(Lws) + 256, true, &ws))) break;
-        for (int k = 0; k < nt; ++k) (void)hipMemset(slot(ws, Lws, c0.L, k).W1, 0, ws_region(c0.L, 1));
-        int best = 1;
+        for (int k = 0; k < nt; ++k) (void)hipMemset(slot(ws, Lws, Lc, k).W1, 0, ws_region(Lc, 1));
+        // from the largest size down: a smaller group must be 3% faster per map
+        // in the forward contraction to be chosen (the inverse, not timed here,
+        // gains from larger groups as well)
+        int best = gmax;
         double best_t = 1e30;
-        for (int G = 1; G <= gmax; G <<= 1) {
+        for (int G = gmax; G >= 1; G >>= 1) {
             Chunk c = c0;
-            c.G = G;
+            c.G[Lc] = G;
             const std::vector<MixLaunch> ls =
-                mix_of(c, [&](int k) { return (void*)slot(ws, Lws, c.L, k).W1; },
-                       [&](int k) { return (void*)slot(ws, Lws, c.L, k).W0; }, [](int) -> const SpinTable* { return nullptr; });
-            double t = 0;
-            for (int rep = 0; rep < 3 && !rc; ++rep) {
+                mix_of(c, [&](int k) { return (void*)slot(ws, Lws, Lc, k).W1; },
+                       [&](int k) { return (void*)slot(ws, Lws, Lc, k).W0; },
+                       [](int, int) -> const SpinTable* { return nullptr; });
+            double t = 1e30;   // the fastest of four timed repetitions (after one warm-up)
+            for (int rep = 0; rep < 5 && !rc; ++rep) {
                 (void)hipEventRecord(e0, nullptr);
                 hipError_t e = hipSuccess;
                 for (const MixLaunch& ml : ls)
-                    if (e == hipSuccess) e = mw::launch_contract_forward_mix(*p, ml.M, G, ml.M.ns, nullptr);
+                    if (e == hipSuccess) e = mw::launch_contract_forward_mix(*plans.at(Lc), ml.M, G, ml.M.ns, nullptr);
                 (void)hipEventRecord(e1, nullptr);
                 if (e != hipSuccess) { rc = fail(MW_EHIP, "autotune launch failed"); break; }
                 (void)hipEventSynchronize(e1);
                 float ms = 0;
                 (void)hipEventElapsedTime(&ms, e0, e1);
-                if (rep > 0) t += ms;
+                if (rep > 0) t = std::min(t, (double)ms);
             }
             if (rc) break;
             const double per_map = t / nt;
@@ -647,7 +803,7 @@ int autotune(DeviceState& d, const int32_t* L, const int32_t* spin, const int32_
         }
         if (rc) break;
         g_tuned[key] = best;
-        if (cache) tune_cache_append(cache, c0.L, c0.real, n, best);
+        if (cache) tune_cache_append(cache, Lc, rc_, n, best);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -675,11 +831,11 @@ int mw_forward_noalloc(const int32_t* L, const int32_t* spin, const int32_t* rea
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceState& d = g_dev[dev];
     const std::vector<Chunk> chunks = make_chunks(L, spin, reality, batch, precision);
-    std::vector<const Plan*> plans(chunks.size(), nullptr);
+    std::vector<ChunkPlans> plans(chunks.size());
+    ChunkSpins none;
     for (size_t i = 0; i < chunks.size(); ++i)
-        if ((rc = get_plan(d, chunks[i].L, false, &plans[i])))
-            return fail(MW_ENOMEM, "mw_forward_noalloc: plan for L=%d not prepared (call mw_prepare first)",
-                        chunks[i].L);
+        if ((rc = resolve_chunk(d, chunks[i], false, false, plans[i], none)))
+            return fail(MW_ENOMEM, "mw_forward_noalloc: a plan of this call is not prepared (call mw_prepare first)");
     // the chunks run one after another on the caller's stream, all in the one
     // set of workspace slots
     const int Lws = batch_lmax(L, batch);
@@ -696,7 +852,7 @@ int mw_forward_noalloc(const int32_t* L, const int32_t* spin, const int32_t* rea
     }
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < chunks.size() && e == hipSuccess; ++i)
-        e = run_chunk(Op::Forward, chunks[i], *plans[i], ChunkSpins(), precision, ptrs, d.scratch, Lws, st, false);
+        e = run_chunk(Op::Forward, chunks[i], plans[i], none, precision, ptrs, d.scratch, Lws, st, false);
     if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     g_last_error.clear();
     return MW_OK;
@@ -858,8 +1014,13 @@ int mw_prepare(const int32_t* L, const int32_t* spin, const int32_t* reality, in
         if ((rc = get_plan(d, L[b], true, &p))) return rc;
         if ((rc = get_spin(d, *p, as, true, &sp))) return rc;
     }
-    if (precision != MW_FP64 && (rc = autotune(d, L, spin, reality, batch))) return rc;
     const std::vector<Chunk> chunks = make_chunks(L, spin, reality, batch, precision);
+    for (const Chunk& c : chunks) {
+        ChunkPlans plans;
+        ChunkSpins tabs;
+        if ((rc = resolve_chunk(d, c, true, true, plans, tabs))) return rc;
+    }
+    if (precision != MW_FP64 && (rc = autotune(d, L, spin, reality, batch))) return rc;
     void* ws = nullptr;
     if ((rc = get_ws(d, call_ws(chunks, batch_lmax(L, batch)), true, &ws))) return rc;
     if (chunks.size() > 1 && !make_lanes(d)) return fail(MW_EHIP, "chunk stream creation failed");

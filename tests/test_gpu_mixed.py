@@ -269,3 +269,37 @@ def test_mixed_groups_across_spins(orc, tc, mw):
         assert rel(fw[i], orc.forward(grids[i], L, s)) < TOL, i
         single = host(tc, mw.forward(dev(tc, grids[i]), L, s, precision=FP32C))
         assert np.array_equal(fw[i], single), i
+
+
+def test_mixed_group_across_band_limits(orc, tc, mw):
+    """Maps of L = 512, 256 and 128 (one spin) in one mixed-precision call form one
+    group: its Wigner order chains run once, to L = 512, and each map masks the
+    degrees l >= L_b (one contraction launch per direction).  Every map against
+    the oracle (sampled orders at L = 512) and against its own single call."""
+    specs = [(128, 2, 0), (512, 2, 0), (256, 2, 0)]
+    Ls = [a for a, _, _ in specs]
+    ss = [b for _, b, _ in specs]
+    flm = [mwsynth.flm_gaussian(L, s, seed=22000 + L, decay=1.0) for L, s, _ in specs]
+    grids = [mwsynth.grid_gaussian(L, seed=22100 + L) for L, _, _ in specs]
+    # no mw_prepare: an untuned shape takes the largest group (four maps here)
+    assert mw.tuned_group(512, 0, 3) in (0, 4)
+    mw.profile_enable(True)
+    maps = [host(tc, t) for t in mw.inverse_batch([dev(tc, f) for f in flm], Ls, ss, precision=FP32C)]
+    fw = [host(tc, t) for t in mw.forward_batch([dev(tc, g) for g in grids], Ls, ss, precision=FP32C)]
+    prof = mw.profile_read()
+    mw.profile_enable(False)
+    print("  launches: %s" % {k: v[1] for k, v in prof.items()}, flush=True)
+    assert prof["contract_inverse"][1] == 1 and prof["contract_forward"][1] == 1
+    for i, (L, s, _) in enumerate(specs):
+        print("  map L=%d" % L, flush=True)
+        if L == 512:
+            orders = [0, 1, 2, 7, -1, -3, 255, -170, 510, 511, -511]
+            e_inv = rel(_ring_orders(maps[i], L, orders), orc.inverse_orders(flm[i], L, s, orders))
+            e_fwd = rel(_rows(fw[i], L, orders), orc.forward_orders(grids[i].astype(np.complex128), L, s, orders))
+        else:
+            e_inv = rel(maps[i], orc.inverse(flm[i], L, s))
+            e_fwd = rel(fw[i], orc.forward(grids[i], L, s))
+        print("    inverse %.3e forward %.3e" % (e_inv, e_fwd), flush=True)
+        assert e_inv < TOL and e_fwd < TOL
+        assert rel(maps[i], host(tc, mw.inverse(dev(tc, flm[i]), L, s, precision=FP32C))) < TOL
+        assert rel(fw[i], host(tc, mw.forward(dev(tc, grids[i]), L, s, precision=FP32C))) < TOL
