@@ -266,7 +266,7 @@ std::vector<int> chunk_ls(const Chunk& c)
 // Autotuned group size per (band-limit, reality, maps of that band-limit and reality), from mw_prepare.
 std::map<std::tuple<int, int, int>, int> g_tuned;
 
-int pow2_ceil(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : 4; }
+int pow2_ceil(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : 8; }
 
 // Chunk capacity: at most MAXB maps and 8 GiB of workspace.
 int chunk_cap(int L)
@@ -430,7 +430,7 @@ std::vector<MixLaunch> mix_of(const Chunk& c, Src src, Dst dst, Tab stab)
             mm.dst[nm] = (double2*)dst(i);
             mm.L[nm] = c.Ls[i];
             Lg = std::max(Lg, c.Ls[i]);
-            mm.meta |= (j << (4 + nm)) | ((s < 0 ? 1 : 0) << (8 + nm));
+            mm.meta |= (j << (4 + nm)) | ((s < 0 ? 1 : 0) << (12 + nm));
             ++nm;
             ++i;
         }
@@ -710,7 +710,7 @@ int tune_cache_load(const char* path)
         char tail[8];
         if (sscanf(line, "%31s %d %d %d %d %7s", arch, &Lc, &rc_, &n, &G, tail) != 5) continue;
         if (strcmp(arch, "gfx950") != 0 || Lc < 1 || Lc > MW_LMAX || (rc_ != 0 && rc_ != 1) || n < 1 ||
-            (G != 1 && G != 2 && G != 4) || G > mw::mix_group_max())
+            (G != 1 && G != 2 && G != 4 && G != 8) || G > mw::mix_group_max())
             continue;
         g_tuned[std::make_tuple(Lc, rc_, n)] = G;
         ++got;

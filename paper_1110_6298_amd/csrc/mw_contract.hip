@@ -1519,7 +1519,7 @@ __host__ __device__ constexpr int fwdm_slot_floats(int G)
 // with a second spin row one wave less for one or two maps (no spills).
 template <bool EXT, int G, int NS>
 __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(
-    NS == 1 ? (G == 1 ? 5 : (G == 4 ? 3 : 4)) : (G == 1 ? 4 : 3)))) void k_contract_forward_mix(
+    G == 8 ? 2 : (NS == 1 ? (G == 1 ? 5 : (G == 4 ? 3 : 4)) : (G == 1 ? 4 : 3))))) void k_contract_forward_mix(
     MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
     const double* __restrict__ cl, const double2* __restrict__ ckf, const int2* __restrict__ ckfk,
     const int4* __restrict__ work, int L, int ckfg)
@@ -1557,13 +1557,6 @@ __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(
         if (g.active) fwd_mix_segment<EXT, G, NS>(st, acc, g, l, le, mb, as, Rt, region, maps, lane, anyscaled);
     }
 
-    double sum[2][G][4];
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int b = 0; b < G; ++b)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) sum[c][b][v] = (double)acc[c][b][v];
     if (bar) {
         // every wave of the workgroup (empty slots too) meets at this one barrier;
         // a wave's partial sums overwrite its own window, which it no longer reads
@@ -1576,21 +1569,13 @@ __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(
         }
         __syncthreads();
         if (!item || w != 0) return;
-        for (int k = 1; k < nseg; ++k) {
-            const v4f* red = (const v4f*)((const float*)smem + (lead + k) * fwdm_slot_floats(G));
-#pragma unroll
-            for (int c = 0; c < 2; ++c)
-#pragma unroll
-                for (int b = 0; b < G; ++b) {
-                    const v4f v = red[(c * G + b) * 64 + lane];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) sum[c][b][q] += (double)v[q];
-                }
-        }
     } else if (!item) {
         return;
     }
     if (!valid) return;
+    // one (map, order) at a time: its FP32 sums in FP64, plus those of the later
+    // segments in segment order
+    const int nadd = bar ? nseg : 1;
 #pragma unroll
     for (int b = 0; b < G; ++b) {
         if (b >= mix_n(maps) || l >= maps.L[b]) continue;
@@ -1601,12 +1586,20 @@ __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(
         for (int c = 0; c < 2; ++c) {
             const int m = mb + c;
             if (m > l || m >= maps.L[b]) continue;
+            double sum[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sum[q] = (double)acc[c][b][q];
+            for (int k = 1; k < nadd; ++k) {
+                const v4f v = ((const v4f*)((const float*)smem + (lead + k) * fwdm_slot_floats(G)))[(c * G + b) * 64 + lane];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sum[q] += (double)v[q];
+            }
             const double fp = (s >= 0) ? sgn(m + l + s) : sgn(m + s);
             const double fm = (s >= 0) ? sgn(m + s) : sgn(l + m + s);
-            const double2 op = mul_ipow(make_double2(sum[c][b][0], sum[c][b][1]), ((m + s) % 4 + 4) % 4);
+            const double2 op = mul_ipow(make_double2(sum[0], sum[1]), ((m + s) % 4 + 4) % 4);
             flm[(size_t)l * l + l + m] = make_double2(op.x * base * fp, op.y * base * fp);
             if (m > 0) {
-                const double2 om = mul_ipow(make_double2(sum[c][b][2], sum[c][b][3]), ((-m + s) % 4 + 4) % 4);
+                const double2 om = mul_ipow(make_double2(sum[2], sum[3]), ((-m + s) % 4 + 4) % 4);
                 flm[(size_t)l * l + l - m] = make_double2(om.x * base * fm, om.y * base * fm);
             }
         }
@@ -1767,7 +1760,7 @@ __host__ __device__ constexpr int inv2m_slot_floats(int G)
 // chain start of both spin rows).  Each map's records carry the scale of its
 // own spin row.
 template <bool EXT, int G, int NS>
-__global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(G == 4 ? 3 : 4))) void k_contract_inverse2_mix(
+__global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(G == 8 ? 2 : (G == 4 ? 3 : 4)))) void k_contract_inverse2_mix(
     MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
     const double2* __restrict__ lco, const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff,
     const int4* __restrict__ work, int L, int Lp, int ckg)
@@ -1824,13 +1817,6 @@ __global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(G
                                       lane, anyscaled);
     }
 
-    double sum[2][G][4];
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int b = 0; b < G; ++b)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) sum[c][b][v] = (double)acc[c][b][v];
     if (bar) {
         // every wave of the workgroup (empty slots too) meets at this one barrier;
         // a wave's partial sums overwrite its own window, which it no longer reads
@@ -1843,21 +1829,13 @@ __global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(G
         }
         __syncthreads();
         if (!item || w != 0) return;
-        for (int k = 1; k < nseg; ++k) {
-            const v4f* red = (const v4f*)((const float*)smem + (lead + k) * inv2m_slot_floats(G));
-#pragma unroll
-            for (int c = 0; c < 2; ++c)
-#pragma unroll
-                for (int b = 0; b < G; ++b) {
-                    const v4f v = red[(c * G + b) * 64 + lane];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) sum[c][b][q] += (double)v[q];
-                }
-        }
     } else if (!item) {
         return;
     }
     if (!valid) return;
+    // one (order, map) at a time: its FP32 sums in FP64, plus those of the later
+    // segments in segment order
+    const int nadd = bar ? nseg : 1;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const int m = m0 + c;
@@ -1869,11 +1847,19 @@ __global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(G
             const double fsm = sgn(s) * ((s < 0) ? sgn(n) : 1.0);
             const int Lb = maps.L[b];
             if (n >= Lb || m >= Lb) continue;
+            double sum[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sum[q] = (double)acc[c][b][q];
+            for (int k = 1; k < nadd; ++k) {
+                const v4f v = ((const v4f*)((const float*)smem + (lead + k) * inv2m_slot_floats(G)))[(c * G + b) * 64 + lane];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sum[q] += (double)v[q];
+            }
             double2* F = maps.dst[b];
-            const double2 op = mul_ipow(make_double2(sum[c][b][0], sum[c][b][1]), ((-(m + s)) % 4 + 4) % 4);
+            const double2 op = mul_ipow(make_double2(sum[0], sum[1]), ((-(m + s)) % 4 + 4) % 4);
             F[(size_t)(Lb - 1 + m) * Lb + n] = make_double2(op.x * fsp, op.y * fsp);
             if (m > 0) {
-                const double2 om = mul_ipow(make_double2(sum[c][b][2], sum[c][b][3]), ((m - s) % 4 + 4) % 4);
+                const double2 om = mul_ipow(make_double2(sum[2], sum[3]), ((m - s) % 4 + 4) % 4);
                 F[(size_t)(Lb - 1 - m) * Lb + n] = make_double2(om.x * fsm, om.y * fsm);
             }
         }
@@ -2027,7 +2013,8 @@ hipError_t fwd_mix_g(const Plan& p, const MixBatch& maps, int G, hipStream_t st)
 {
     if (G == 1) return fwd_mix_go<EXT, 1, NS>(p, maps, st);
     if (G == 2) return fwd_mix_go<EXT, 2, NS>(p, maps, st);
-    return fwd_mix_go<EXT, 4, NS>(p, maps, st);
+    if (G == 4) return fwd_mix_go<EXT, 4, NS>(p, maps, st);
+    return fwd_mix_go<EXT, 8, NS>(p, maps, st);
 }
 
 template <bool EXT, int NS>
@@ -2035,7 +2022,8 @@ hipError_t inv_mix_g(const Plan& p, const SpinTable& wsp, const MixBatch& maps, 
 {
     if (G == 1) return inv_mix_go<EXT, 1, NS>(p, wsp, maps, st);
     if (G == 2) return inv_mix_go<EXT, 2, NS>(p, wsp, maps, st);
-    return inv_mix_go<EXT, 4, NS>(p, wsp, maps, st);
+    if (G == 4) return inv_mix_go<EXT, 4, NS>(p, wsp, maps, st);
+    return inv_mix_go<EXT, 8, NS>(p, wsp, maps, st);
 }
 
 }  // namespace

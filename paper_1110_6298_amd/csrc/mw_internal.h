@@ -136,10 +136,10 @@ constexpr int MT_FWD = 2;
 // chains; its maps have at most NSMAX different |s|, the spin rows of the launch
 // (MixBatch::as, the same for all its groups).  src/dst are per-map device
 // pointers (FP32 staged H or stream; f_lm or F), L the per-map band-limits
-// (<= the plan's); meta packs the map count (bits 0-2), for each map b the row of
-// its |s| (bit 4+b) and the sign of its spin (bit 8+b).  Passed by value (the
-// launch's kernel arguments stay under 1 KB).
-constexpr int GMAX = 4;
+// (<= the plan's); meta packs the map count (bits 0-3), for each map b the row of
+// its |s| (bit 4+b) and the sign of its spin (bit 12+b).  Passed by value (the
+// launch's kernel arguments stay under 1.5 KB).
+constexpr int GMAX = 8;
 constexpr int NSMAX = 2;
 struct MixMaps {
     const float* src[GMAX];
@@ -147,9 +147,9 @@ struct MixMaps {
     int L[GMAX];
     int meta;
 };
-__host__ __device__ inline int mix_n(const MixMaps& m) { return m.meta & 7; }
+__host__ __device__ inline int mix_n(const MixMaps& m) { return m.meta & 15; }
 __host__ __device__ inline int mix_row(const MixMaps& m, int b) { return (m.meta >> (4 + b)) & 1; }
-__host__ __device__ inline bool mix_neg(const MixMaps& m, int b) { return (m.meta >> (8 + b)) & 1; }
+__host__ __device__ inline bool mix_neg(const MixMaps& m, int b) { return (m.meta >> (12 + b)) & 1; }
 // Groups of one mixed launch (blockIdx.y = group), with their spin rows |s_j|,
 // j < ns, and (inverse only) the spin tables Delta^l_{n,|s_j|} of those rows.
 constexpr int MIXG = 8;
@@ -231,7 +231,7 @@ hipError_t launch_spin_flip(int L, const Batch& B, hipStream_t st);
 // Largest group size (1, 2 or 4) whose staging fits the LDS (independent of L).
 int mix_group_max();
 // Mixed-precision contractions of up to MIXG groups (each maps.n <= G <= GMAX, G
-// in {1,2,4}; each with at most NS <= NSMAX spin rows).  The inverse runs the work
+// in {1,2,4,8}; each with at most NS <= NSMAX spin rows).  The inverse runs the work
 // list of wsp, the spin table of the largest |s| of the launch's groups.
 hipError_t launch_contract_forward_mix(const Plan& p, const MixBatch& maps, int G, int NS, hipStream_t st);
 hipError_t launch_contract_inverse_mix(const Plan& p, const SpinTable& wsp, const MixBatch& maps, int G, int NS,
