@@ -510,6 +510,43 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc,
         });
 }
 
+// Forward phi stage of a real map for the rings t1 = 2c and t2 = 2c+1 together:
+// the spectrum of a real ring is Hermitian (Sec. IV-G), so one DFT X of
+// x_p = f(t1, p) + i f(t2, p) gives both, G1_m = (X_m + conj(X_{-m}))/2 and
+// G2_m = (X_m - conj(X_{-m}))/(2i).  Half the transforms of k_phi_forward for
+// real maps; full rings only (pole = 0).  Output as k_phi_forward.
+template <int RB, int LOGN>
+__global__ __launch_bounds__(512) void k_phi_forward_real2(Plan p, Batch B, double sc)
+{
+    fix_length<LOGN, false>(p);
+    extern __shared__ double2 A[];
+    const double* __restrict__ map = (const double*)B.in[blockIdx.y];
+    double2* __restrict__ G = (double2*)B.out[blockIdx.y];
+    const int L = p.L, N1 = p.N1;
+    const int npair = (L + 1) >> 1;
+    const int c = xcd_column(npair);
+    if (c >= npair) return;
+    const int t1 = 2 * c, t2 = 2 * c + 1;
+    const bool has2 = t2 < L;
+    const FftTw<RB> T = plan_twiddles<RB, false>(p);
+    bluestein_any<RB, false>(A, p, T, [&](int j) {
+        if (j >= N1) return make_double2(0.0, 0.0);
+        const double a = map[(size_t)t1 * N1 + j];
+        const double b = has2 ? map[(size_t)t2 * N1 + j] : 0.0;
+        return cmul(make_double2(a, b), p.chirp[j]);
+    });
+    const double h = 0.5 * sc;
+    for (int k = threadIdx.x; k < N1; k += blockDim.x) {
+        const int kn = (k == 0) ? 0 : N1 - k;
+        const double2 x = cmul(A[Pr<RB>(k)], p.chirp[k]);        // X_k
+        const double2 y = cconj(cmul(A[Pr<RB>(kn)], p.chirp[kn]));   // conj(X_{-k})
+        const int m = (k <= L - 1) ? k : k - N1;
+        double2* __restrict__ row = G + (size_t)(m + L - 1) * L;
+        row[t1] = make_double2(h * (x.x + y.x), h * (x.y + y.y));
+        if (has2) row[t2] = make_double2(h * (x.y - y.y), -h * (x.x - y.x));   // (x - y)/(2i)
+    }
+}
+
 // Forward theta stage for order m (Sec. IV-B..IV-D):
 //   extension  Gext(theta_t) = (-1)^{m+s} G_m(theta_{2L-2-t}) for t >= L,
 //   F_{m m'} = 1/(2 pi N1) sum_t Gext(theta_t) e^{-i m' theta_t},
@@ -1071,6 +1108,48 @@ __global__ __launch_bounds__(512) void k_phi_inverse(Plan p, Batch B, double sc,
     }
 }
 
+// Inverse phi stage of a real map (orders m >= 0 stored, F_{-m} = conj(F_m),
+// Sec. IV-G) for the rings t1 = 2c and t2 = 2c+1 together: one inverse DFT of
+// Y_m = F1_m + i F2_m (each F extended to m < 0 by conjugation) gives
+// f(t1, p) + i f(t2, p), both real.  Half the transforms of k_phi_inverse<2>;
+// full rings only (pole = 0).
+template <int RB, int LOGN>
+__global__ __launch_bounds__(512) void k_phi_inverse_real2(Plan p, Batch B, double sc)
+{
+    fix_length<LOGN, false>(p);
+    extern __shared__ double2 A[];
+    const double2* __restrict__ Ft = (const double2*)B.in[blockIdx.y];
+    double* __restrict__ map = (double*)B.out[blockIdx.y];
+    const int L = p.L, N1 = p.N1;
+    const int npair = (L + 1) >> 1;
+    const int c = xcd_column(npair);
+    if (c >= npair) return;
+    const int t1 = 2 * c, t2 = 2 * c + 1;
+    const bool has2 = t2 < L;
+    const FftTw<RB> T = plan_twiddles<RB, false>(p);
+    // conj(Y_m) chirp_j: with F1 = (a1, b1), F2 = (a2, b2) at |m|,
+    // conj(F1) - i conj(F2) = (a1 - b2, -b1 - a2) for m >= 0 and
+    // F1 - i F2 = (a1 + b2, b1 - a2) for m < 0.  At m = 0 only the real parts
+    // enter, as in k_phi_inverse<2>, which stores the real part of the
+    // synthesis: f = Re F_0 + 2 sum_{m>0} Re(F_m e^{i m phi}) for any input.
+    bluestein_core<RB>(A, p, T, [&](int j) {
+        if (j >= N1) return make_double2(0.0, 0.0);
+        const int m = (j <= L - 1) ? j : j - N1;
+        const int am = m < 0 ? -m : m;
+        double2 f1 = Ft[(size_t)t1 * N1 + am + L - 1];
+        double2 f2 = has2 ? Ft[(size_t)t2 * N1 + am + L - 1] : make_double2(0.0, 0.0);
+        if (am == 0) { f1.y = 0.0; f2.y = 0.0; }
+        const double2 y = (m >= 0) ? make_double2(f1.x - f2.y, -f1.y - f2.x) : make_double2(f1.x + f2.y, f1.y - f2.x);
+        return cmul(y, p.chirp[j]);
+    }, [&](int k, double2 v) {   // outputs k < N1: conj(v chirp_k) sc = f(t1, k) + i f(t2, k)
+        if (k < N1) {
+            const double2 o = cconj(cmul(v, p.chirp[k]));
+            map[(size_t)t1 * N1 + k] = sc * o.x;
+            if (has2) map[(size_t)t2 * N1 + k] = sc * o.y;
+        }
+    });
+}
+
 // Main radix of the FFTs for a plan.  It depends on the band-limit only, so a
 // map's result does not depend on the batch it runs in.  Radix 8 runs twice the
 // threads per transform of radix 16 for the same work; both keep a workgroup
@@ -1179,6 +1258,8 @@ template <int H> struct ThIP {
     template <int RB, int LN> struct K { static auto fn() { return k_theta_inverse_pair<H, RB, LN>; } };
 };
 
+template <int RB, int LN> struct PhiF2 { static auto fn() { return k_phi_forward_real2<RB, LN>; } };
+template <int RB, int LN> struct PhiI2 { static auto fn() { return k_phi_inverse_real2<RB, LN>; } };
 template <int REAL> struct PhiF {
     template <int RB, bool SP, int LN> struct K { static auto fn() { return k_phi_forward<REAL, RB, SP, LN>; } };
 };
@@ -1199,6 +1280,8 @@ template <int RB, bool SP, int LN> struct ThFA { static auto fn() { return k_the
 
 hipError_t launch_phi_forward(const Plan& p, const Batch& B, int real, double sc, int pole, hipStream_t st)
 {
+    if (real && pole == 0 && !fft_split(p))   // two real rings per transform
+        return fft_launch_unsplit<PhiF2>(p, dim3(xcd_grid((p.L + 1) / 2), B.n), st, p, B, sc);
     const dim3 grid(xcd_grid(p.L), B.n);
     if (real) return fft_launch<PhiF<1>::K>(p, grid, st, p, B, sc, pole);
     return fft_launch<PhiF<0>::K>(p, grid, st, p, B, sc, pole);
@@ -1249,6 +1332,8 @@ hipError_t launch_theta_inverse(const Plan& p, const Batch& B, int half, hipStre
 
 hipError_t launch_phi_inverse(const Plan& p, const Batch& B, int real, double sc, int pole, hipStream_t st)
 {
+    if (real == 2 && pole == 0 && !fft_split(p))   // two real rings per transform
+        return fft_launch_unsplit<PhiI2>(p, dim3(xcd_grid((p.L + 1) / 2), B.n), st, p, B, sc);
     const dim3 grid(xcd_grid(p.L), B.n);   // rings dealt to XCDs in contiguous ranges
     if (real == 2) return fft_launch<PhiI<2>::K>(p, grid, st, p, B, sc, pole);
     if (real) return fft_launch<PhiI<1>::K>(p, grid, st, p, B, sc, pole);
