@@ -735,25 +735,33 @@ __device__ __forceinline__ bool inv2_scaled(const InvLane2<EXT, NS>& st)
 }
 
 // dd: the chain values of this step as they enter the products (0 while scaled).
-template <bool EXT, bool INJ, int NS>
+// SPT (one spin row): the spin value e^l_{n,|s|} of this step is svt, read from
+// the spin table's scaled rows, instead of a third chain.
+template <bool EXT, bool INJ, int NS, bool SPT = false>
 __device__ __forceinline__ void inv2_core_d(InvLane2<EXT, NS>& st, int l, int lstart, double nd, const double2& c0,
                                             const double2& c1, const double2 (&cs)[NS], double rs,
-                                            double (&pr)[2][NS], double (&dd)[2], bool& anyscaled)
+                                            double (&pr)[2][NS], double (&dd)[2], bool& anyscaled, double svt = 0.0)
 {
     if (INJ) {
 #pragma unroll
         for (int c = 0; c < 2; ++c)
             if (l == st.lz[c]) { st.dc[c] = st.start[c]; if (EXT) st.k[c] = st.startk[c]; }
+        if constexpr (!SPT) {
 #pragma unroll
-        for (int j = 0; j < NS; ++j)
-            if (l == st.l0s[j] && st.l0s[j] > lstart) { st.sc[j] = st.starts[j]; if (EXT) st.ks[j] = st.startks[j]; }
+            for (int j = 0; j < NS; ++j)
+                if (l == st.l0s[j] && st.l0s[j] > lstart) { st.sc[j] = st.starts[j]; if (EXT) st.ks[j] = st.startks[j]; }
+        }
         if (EXT) anyscaled = __any(inv2_scaled(st));
     }
     double sv[NS];
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
-        sv[j] = st.sc[j];
-        if (EXT) sv[j] = (st.ks[j] == 0) ? sv[j] : 0.0;
+        if constexpr (SPT) {
+            sv[j] = svt;
+        } else {
+            sv[j] = st.sc[j];
+            if (EXT) sv[j] = (st.ks[j] == 0) ? sv[j] : 0.0;
+        }
     }
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -777,19 +785,23 @@ __device__ __forceinline__ void inv2_core_d(InvLane2<EXT, NS>& st, int l, int ls
         st.dp[c] = st.dc[c];
         st.dc[c] = dn;
     }
+    if constexpr (!SPT) {
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-        const double sn = fma(cs[j].x * xn, st.sc[j], yn * st.sp[j]);
-        st.sp[j] = st.sc[j];
-        st.sc[j] = sn;
+        for (int j = 0; j < NS; ++j) {
+            const double sn = fma(cs[j].x * xn, st.sc[j], yn * st.sp[j]);
+            st.sp[j] = st.sc[j];
+            st.sc[j] = sn;
+        }
     }
     if (EXT && anyscaled) {
 #pragma unroll
         for (int c = 0; c < 2; ++c)
             if (st.k[c] > 0 && fabs(st.dc[c]) > EXT_UP) { st.dc[c] *= EXT_DOWN; st.dp[c] *= EXT_DOWN; st.k[c] -= 1; }
+        if constexpr (!SPT) {
 #pragma unroll
-        for (int j = 0; j < NS; ++j)
-            if (st.ks[j] > 0 && fabs(st.sc[j]) > EXT_UP) { st.sc[j] *= EXT_DOWN; st.sp[j] *= EXT_DOWN; st.ks[j] -= 1; }
+            for (int j = 0; j < NS; ++j)
+                if (st.ks[j] > 0 && fabs(st.sc[j]) > EXT_UP) { st.sc[j] *= EXT_DOWN; st.sp[j] *= EXT_DOWN; st.ks[j] -= 1; }
+        }
         anyscaled = __any(inv2_scaled(st));
     }
 }
@@ -805,11 +817,11 @@ __device__ __forceinline__ void inv2_core(InvLane2<EXT, NS>& st, int l, int lsta
 
 template <bool EXT, bool INJ, bool RL>
 __device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, double nd, const InvS2& u, double rs,
-                                          bool& anyscaled)
+                                          double sv, bool& anyscaled)
 {
-    double pr[2][1];
+    double pr[2][1], dd[2];
     const double2 cs[1] = {u.cs};
-    inv2_core<EXT, INJ, 1>(st, l, lstart, nd, u.c0, u.c1, cs, rs, pr, anyscaled);
+    inv2_core_d<EXT, INJ, 1, true>(st, l, lstart, nd, u.c0, u.c1, cs, rs, pr, dd, anyscaled, sv);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const double4 f = c ? u.f1 : u.f0;
@@ -826,10 +838,14 @@ __device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, 
 // The 1/sqrt factors alternate between two register sets over pairs (two pairs
 // per iteration, an odd last pair peeled); r holds those of pair jfrom on entry
 // and of pair jlast+1 on return.
+// The spin values of the lane come from the scaled spin rows sv[l*L + n]
+// (svb: the lane's row base), loaded one step ahead beside the uniform records
+// (svA with uA, svB with uB).
 template <bool EXT, bool INJ, bool RL>
 __device__ __forceinline__ void inv2_phase(InvLane2<EXT>& st, int jfrom, int jlast, int lend, int lstart, int ne,
-                                           double nd, const Inv2Rows& rows, const double* __restrict__ Rt, InvS2& uA,
-                                           InvS2& uB, InvR& r, bool& anyscaled)
+                                           double nd, const Inv2Rows& rows, const double* __restrict__ Rt,
+                                           const double* __restrict__ svb, int L, InvS2& uA, InvS2& uB, double& svA,
+                                           double& svB, InvR& r, bool& anyscaled)
 {
     const int jr = lend >> 1;   // last pair whose factors exist
     InvR rB;
@@ -837,13 +853,16 @@ __device__ __forceinline__ void inv2_phase(InvLane2<EXT>& st, int jfrom, int jla
         wait_scalar(uA.f0.x);
         __builtin_amdgcn_sched_barrier(0);
         inv2_load(uB, rows, l + 1);
+        svB = svb[(size_t)(l + 1) * L];
         __builtin_amdgcn_sched_barrier(0);
-        inv2_step<EXT, INJ, RL>(st, l, lstart, nd, uA, rc.a.x * rc.b.x, anyscaled);
+        inv2_step<EXT, INJ, RL>(st, l, lstart, nd, uA, rc.a.x * rc.b.x, svA, anyscaled);
         wait_scalar(uB.f0.x);
         __builtin_amdgcn_sched_barrier(0);
-        inv2_load(uA, rows, min(l + 2, lend));
+        const int l2 = min(l + 2, lend);
+        inv2_load(uA, rows, l2);
+        svA = svb[(size_t)l2 * L];
         __builtin_amdgcn_sched_barrier(0);
-        inv2_step<EXT, INJ, RL>(st, l + 1, lstart, nd, uB, rc.a.y * rc.b.y, anyscaled);
+        inv2_step<EXT, INJ, RL>(st, l + 1, lstart, nd, uB, rc.a.y * rc.b.y, svB, anyscaled);
     };
     if constexpr (EXT) {
         // the exponent-extended variant keeps one pair per iteration: unrolled,
@@ -979,8 +998,9 @@ template <bool EXT, bool RL>
 __device__ __forceinline__ void contract_inverse2_body(
     const double* __restrict__ fs0, size_t fstride, const Batch& B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
-    const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,
-    const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work, int L, int Lp, int s, int ckg)
+    const double* __restrict__ stab, const int* __restrict__ stabk, const double* __restrict__ svt,
+    const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work,
+    int L, int Lp, int s, int ckg)
 {
     // LDS: the partial sums of later segments, red[slot][c][2][lane].  The 1/sqrt
     // table is read from global memory (L1-resident), so the LDS of a workgroup
@@ -1017,17 +1037,22 @@ __device__ __forceinline__ void contract_inverse2_body(
         bool anyscaled;
         const InvSeg g = inv2_setup<EXT, 1>(st, anyscaled, geo, w, n, m0, L, Lp, SpinSet<1>{{as}}, ckg, lco, edge,
                                             edgek, SpinTabs<1>{{stab}, {stabk}}, cki, ckik, ckoff);
+        st.ks[0] = 0;   // the spin values come from the scaled rows, not a chain
+        if (EXT) anyscaled = __any(inv2_scaled(st));
         asm volatile("" ::"v"(touched));
         if (g.active) {
+            const double* __restrict__ svb = svt + ne;
             InvS2 uA, uB;
             inv2_load(uA, rows, 2 * g.jfrom);
+            double svA = svb[(size_t)(2 * g.jfrom) * L], svB;
             InvR r = inv_load_r(Rt, ne, g.jfrom);
             const int jA = min(g.jA, g.jlast);
             if (g.jfrom <= jA)
-                inv2_phase<EXT, true, RL>(st, g.jfrom, jA, lend, geo.lstart, ne, nd, rows, Rt, uA, uB, r, anyscaled);
+                inv2_phase<EXT, true, RL>(st, g.jfrom, jA, lend, geo.lstart, ne, nd, rows, Rt, svb, L, uA, uB, svA, svB,
+                                          r, anyscaled);
             if (max(g.jfrom, jA + 1) <= g.jlast)
-                inv2_phase<EXT, false, RL>(st, max(g.jfrom, jA + 1), g.jlast, lend, geo.lstart, ne, nd, rows, Rt, uA,
-                                           uB, r, anyscaled);
+                inv2_phase<EXT, false, RL>(st, max(g.jfrom, jA + 1), g.jlast, lend, geo.lstart, ne, nd, rows, Rt, svb,
+                                           L, uA, uB, svA, svB, r, anyscaled);
         }
     }
 
@@ -1070,10 +1095,10 @@ __device__ __forceinline__ void contract_inverse2_body(
 #define MW_INVERSE2_ARGS                                                                                         \
     const double* __restrict__ fs0, size_t fstride, Batch B, const double* __restrict__ Rtg,                    \
         const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,         \
-        const double* __restrict__ stab, const int* __restrict__ stabk, const double2* __restrict__ cki,        \
-        const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work, int L, int Lp, int s,         \
-        int ckg
-#define MW_INVERSE2_PASS fs0, fstride, B, Rtg, edge, edgek, lco, stab, stabk, cki, ckik, ckoff, work, L, Lp, s, ckg
+        const double* __restrict__ stab, const int* __restrict__ stabk, const double* __restrict__ svt,         \
+        const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff,                            \
+        const int4* __restrict__ work, int L, int Lp, int s, int ckg
+#define MW_INVERSE2_PASS fs0, fstride, B, Rtg, edge, edgek, lco, stab, stabk, svt, cki, ckik, ckoff, work, L, Lp, s, ckg
 
 // Register budgets: a real map keeps no -m sums, which leaves room for one more
 // wave per SIMD (seven plain, six exponent-extended) without spills in the loops.
@@ -1938,10 +1963,10 @@ hipError_t inv_sq_go(const Plan& p, const SpinTable& sp, int s, const double* in
     const dim3 grid(sp.nwinv, B.n), block(64 * SEGI_MAX);
     if (EXT)
         hipLaunchKernelGGL((k_contract_inverse2_ext<RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
-                           p.edgek, p.lco, sp.val, sp.k, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s, p.ckg);
+                           p.edgek, p.lco, sp.val, sp.k, sp.sval, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s, p.ckg);
     else
         hipLaunchKernelGGL((k_contract_inverse2<RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge, p.edgek,
-                           p.lco, sp.val, sp.k, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s, p.ckg);
+                           p.lco, sp.val, sp.k, sp.sval, p.cki, p.ckik, off, sp.winv, p.L, p.Lp, s, p.ckg);
     return hipGetLastError();
 }
 

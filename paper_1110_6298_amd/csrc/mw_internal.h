@@ -124,6 +124,7 @@ struct SpinTable {
     int4* winv = nullptr;
     int nwinv = 0;   // workgroups
     double2* lcos = nullptr;
+    double* sval = nullptr;   // h_|s|(l) Delta^l_{n,|s|} at [l*L + n], l < Lp (the FP64 inverses' spin values)
     int4* wtri = nullptr;
     int nwtri = 0;   // workgroups
     size_t bytes = 0;

@@ -692,6 +692,9 @@ int build_spin_table(const Plan& p, int as, SpinTable& t, std::string& err)
     std::vector<double2> lcos = lrec_factors(L, p.Lp);
     for (double2& v : lcos) v.y = 0.0;
     const std::vector<double2> hs = lrec_factors(L, p.Lp);
+    // the scaled spin values h_|s|(l) Delta^l_{n,|s|} (zero below 2^-900 and in
+    // the pad row l = L of an odd L), the FP64 inverses' spin rows
+    std::vector<double> sval((size_t)p.Lp * L, 0.0);
     for (int n = 0; n < L; ++n) {
         int l0 = std::max(n, as);
         if (l0 >= L) continue;
@@ -704,6 +707,7 @@ int build_spin_table(const Plan& p, int as, SpinTable& t, std::string& err)
             split_ext(a, x, k);
             val[(size_t)l * L + n] = (dcur < 0) ? -x : x;
             kk[(size_t)l * L + n] = k;
+            if (a > 0x1p-900L) sval[(size_t)l * L + n] = (double)(dcur * (ld)hs[(size_t)as * p.Lp + l].y);
             if (a > 0x1p-900L)
                 lcos[(size_t)n * p.Lp + l].y =
                     (double)(sqrtl((2.0L * l + 1.0L) / (4.0L * PI_L)) * dcur / (ld)hs[(size_t)n * p.Lp + l].y);
@@ -728,6 +732,7 @@ int build_spin_table(const Plan& p, int as, SpinTable& t, std::string& err)
     t.nwinv = (int)(w.size() / SEGI_MAX);
     if ((rc = upload(w, &t.winv, t.bytes, err))) return rc;
     if ((rc = upload(lcos, &t.lcos, t.bytes, err))) return rc;
+    if ((rc = upload(sval, &t.sval, t.bytes, err))) return rc;
     const std::vector<int4> wt = inverse_work_tri(p, as);
     t.nwtri = (int)(wt.size() / SEGT_MAX);
     if ((rc = upload(wt, &t.wtri, t.bytes, err))) return rc;
@@ -740,6 +745,7 @@ void free_spin_table(SpinTable& t)
     if (t.k) (void)hipFree(t.k);
     if (t.winv) (void)hipFree(t.winv);
     if (t.lcos) (void)hipFree(t.lcos);
+    if (t.sval) (void)hipFree(t.sval);
     if (t.wtri) (void)hipFree(t.wtri);
     t = SpinTable();
 }
