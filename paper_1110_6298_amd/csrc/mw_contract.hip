@@ -1161,13 +1161,13 @@ __device__ __forceinline__ double4 f_load(__amdgpu_buffer_rsrc_t rs, unsigned op
 }
 
 // PAR: parity of l (the transposed sums' degree signs).
-template <bool EXT, bool INJ, bool RL, bool SNEG, int PAR>
+template <bool EXT, bool INJ, bool RL, bool SNEG, bool SPT, int PAR>
 __device__ __forceinline__ void inv3_step(InvLane3<EXT>& st, int l, int lstart, double nd, const InvS2& u,
-                                          const double4& g, double rs, bool& anyscaled)
+                                          const double4& g, double rs, double sv, bool& anyscaled)
 {
     double pr[2][1], dd[2];
     const double2 cs[1] = {u.cs};
-    inv2_core_d<EXT, INJ, 1>(st.b, l, lstart, nd, u.c0, u.c1, cs, rs, pr, dd, anyscaled);
+    inv2_core_d<EXT, INJ, 1, SPT>(st.b, l, lstart, nd, u.c0, u.c1, cs, rs, pr, dd, anyscaled, sv);
     constexpr double sgp = (PAR && !SNEG) ? -1.0 : 1.0;   // sp(l)
     constexpr double sgm = (PAR && SNEG) ? -1.0 : 1.0;    // sm(l)
 #pragma unroll
@@ -1189,14 +1189,16 @@ __device__ __forceinline__ void inv3_step(InvLane3<EXT>& st, int l, int lstart, 
     }
 }
 
-// Pairs jfrom .. jlast as in inv2_phase; the lane's coefficients are loaded
-// one step ahead beside the uniform records (gA with uA, gB with uB).  op: the
-// lane's f_lm offset at degree 2 jfrom on entry, advanced by 32 (l+1) per step.
-template <bool EXT, bool INJ, bool RL, bool SNEG>
+// Pairs jfrom .. jlast as in inv2_phase; the lane's coefficients (and with SPT
+// its spin values, else a third chain) are loaded one step ahead beside the
+// uniform records (gA, svA with uA; gB, svB with uB).  op: the lane's f_lm
+// offset at degree 2 jfrom on entry, advanced by 32 (l+1) per step.
+template <bool EXT, bool INJ, bool RL, bool SNEG, bool SPT>
 __device__ __forceinline__ void inv3_phase(InvLane3<EXT>& st, int jfrom, int jlast, int lend, int lstart, int ne,
                                            double nd, const Inv2Rows& rows, const double* __restrict__ Rt,
-                                           __amdgpu_buffer_rsrc_t frs, unsigned& op, unsigned n32, InvS2& uA,
-                                           InvS2& uB, double4& gA, double4& gB, InvR& r, bool& anyscaled)
+                                           __amdgpu_buffer_rsrc_t frs, unsigned& op, unsigned n32,
+                                           const double* __restrict__ svb, int L, InvS2& uA, InvS2& uB, double4& gA,
+                                           double4& gB, double& svA, double& svB, InvR& r, bool& anyscaled)
 {
     const int jr = lend >> 1;   // last pair whose factors exist
     InvR rB;
@@ -1206,15 +1208,18 @@ __device__ __forceinline__ void inv3_phase(InvLane3<EXT>& st, int jfrom, int jla
         inv2_load(uB, rows, l + 1);
         op += 32u * (unsigned)(l + 1);   // degree l+1
         gB = f_load<RL>(frs, op, n32);
+        if (SPT) svB = svb[(size_t)(l + 1) * L];
         __builtin_amdgcn_sched_barrier(0);
-        inv3_step<EXT, INJ, RL, SNEG, 0>(st, l, lstart, nd, uA, gA, rc.a.x * rc.b.x, anyscaled);
+        inv3_step<EXT, INJ, RL, SNEG, SPT, 0>(st, l, lstart, nd, uA, gA, rc.a.x * rc.b.x, svA, anyscaled);
         wait_scalar(uB.f0.x);
         __builtin_amdgcn_sched_barrier(0);
-        inv2_load(uA, rows, min(l + 2, lend));
+        const int l2 = min(l + 2, lend);
+        inv2_load(uA, rows, l2);
         op += 32u * (unsigned)(l + 2);   // degree l+2 (past lend: beyond f_lm, reads zeros)
         gA = f_load<RL>(frs, op, n32);
+        if (SPT) svA = svb[(size_t)l2 * L];
         __builtin_amdgcn_sched_barrier(0);
-        inv3_step<EXT, INJ, RL, SNEG, 1>(st, l + 1, lstart, nd, uB, gB, rc.a.y * rc.b.y, anyscaled);
+        inv3_step<EXT, INJ, RL, SNEG, SPT, 1>(st, l + 1, lstart, nd, uB, gB, rc.a.y * rc.b.y, svB, anyscaled);
     };
     for (int j = jfrom; j <= jlast; ++j) {
         rB = inv_load_r(Rt, ne, min(j + 1, jr));
@@ -1223,13 +1228,13 @@ __device__ __forceinline__ void inv3_phase(InvLane3<EXT>& st, int jfrom, int jla
     }
 }
 
-template <bool EXT, bool RL, bool SNEG>
+template <bool EXT, bool RL, bool SNEG, bool SPT>
 __device__ __forceinline__ void contract_inverse_tri_body(
     const double* __restrict__ fs0, size_t fstride, const Batch& B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,
     const double2* __restrict__ lcos, const double* __restrict__ stab, const int* __restrict__ stabk,
-    const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff, const int4* __restrict__ work, int L,
-    int Lp, int s, int ckg)
+    const double* __restrict__ svt, const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff,
+    const int4* __restrict__ work, int L, int Lp, int s, int ckg)
 {
     // LDS: the partial sums of later segments, red[slot][c][acc][lane] with acc =
     // ap, at (and am, atm for complex maps)
@@ -1278,23 +1283,26 @@ __device__ __forceinline__ void contract_inverse_tri_body(
                 st.b.start[c] = 0.0; st.b.startk[c] = 0;
                 st.b.dc[c] = 0.0; st.b.dp[c] = 0.0; st.b.k[c] = 0;
             }
+        if (SPT) st.b.ks[0] = 0;   // the spin values come from the scaled rows, not a chain
         if (EXT) anyscaled = __any(inv2_scaled(st.b));
         asm volatile("" ::"v"(touched));
         if (g.active) {
             const unsigned l0 = 2u * (unsigned)g.jfrom, n32 = 32u * (unsigned)ne;
             unsigned op = 16u * (l0 * l0 + l0 + (unsigned)ne);
+            const double* __restrict__ svb = svt + ne;
             InvS2 uA, uB;
             double4 gA, gB;
             inv2_load(uA, rows, 2 * g.jfrom);
             gA = f_load<RL>(frs, op, n32);
+            double svA = SPT ? svb[(size_t)l0 * L] : 0.0, svB = 0.0;
             InvR r = inv_load_r(Rt, ne, g.jfrom);
             const int jA = min(g.jA, g.jlast);
             if (g.jfrom <= jA)
-                inv3_phase<EXT, true, RL, SNEG>(st, g.jfrom, jA, lend, geo.lstart, ne, nd, rows, Rt, frs, op, n32, uA,
-                                                uB, gA, gB, r, anyscaled);
+                inv3_phase<EXT, true, RL, SNEG, SPT>(st, g.jfrom, jA, lend, geo.lstart, ne, nd, rows, Rt, frs, op, n32,
+                                                     svb, L, uA, uB, gA, gB, svA, svB, r, anyscaled);
             if (max(g.jfrom, jA + 1) <= g.jlast)
-                inv3_phase<EXT, false, RL, SNEG>(st, max(g.jfrom, jA + 1), g.jlast, lend, geo.lstart, ne, nd, rows, Rt,
-                                                 frs, op, n32, uA, uB, gA, gB, r, anyscaled);
+                inv3_phase<EXT, false, RL, SNEG, SPT>(st, max(g.jfrom, jA + 1), g.jlast, lend, geo.lstart, ne, nd, rows,
+                                                      Rt, frs, op, n32, svb, L, uA, uB, gA, gB, svA, svB, r, anyscaled);
         }
     }
 
@@ -1358,22 +1366,23 @@ __device__ __forceinline__ void contract_inverse_tri_body(
     const double* __restrict__ fs0, size_t fstride, Batch B, const double* __restrict__ Rtg,                    \
         const double* __restrict__ edge, const int* __restrict__ edgek, const double2* __restrict__ lco,         \
         const double2* __restrict__ lcos, const double* __restrict__ stab, const int* __restrict__ stabk,       \
-        const double2* __restrict__ cki, const int2* __restrict__ ckik, CkOff ckoff,                            \
-        const int4* __restrict__ work, int L, int Lp, int s, int ckg
-#define MW_INVTRI_PASS fs0, fstride, B, Rtg, edge, edgek, lco, lcos, stab, stabk, cki, ckik, ckoff, work, L, Lp, s, ckg
+        const double* __restrict__ svt, const double2* __restrict__ cki, const int2* __restrict__ ckik,         \
+        CkOff ckoff, const int4* __restrict__ work, int L, int Lp, int s, int ckg
+#define MW_INVTRI_PASS \
+    fs0, fstride, B, Rtg, edge, edgek, lco, lcos, stab, stabk, svt, cki, ckik, ckoff, work, L, Lp, s, ckg
 
-template <bool RL, bool SNEG>
+template <bool RL, bool SNEG, bool SPT>
 __global__ __launch_bounds__(64 * SEGT_MAX) __attribute__((amdgpu_waves_per_eu(RL ? 5 : 4))) void
 k_contract_inverse_tri(MW_INVTRI_ARGS)
 {
-    contract_inverse_tri_body<false, RL, SNEG>(MW_INVTRI_PASS);
+    contract_inverse_tri_body<false, RL, SNEG, SPT>(MW_INVTRI_PASS);
 }
 
-template <bool RL, bool SNEG>
+template <bool RL, bool SNEG, bool SPT>
 __global__ __launch_bounds__(64 * SEGT_MAX) __attribute__((amdgpu_waves_per_eu(4))) void
 k_contract_inverse_tri_ext(MW_INVTRI_ARGS)
 {
-    contract_inverse_tri_body<true, RL, SNEG>(MW_INVTRI_PASS);
+    contract_inverse_tri_body<true, RL, SNEG, SPT>(MW_INVTRI_PASS);
 }
 #undef MW_INVTRI_ARGS
 #undef MW_INVTRI_PASS
@@ -1938,7 +1947,7 @@ hipError_t launch_inverse_stream(const Plan& p, int real, const Batch& B, int ou
 }
 
 namespace {
-template <bool EXT, bool RL, bool SNEG>
+template <bool EXT, bool RL, bool SNEG, bool SPT = false>
 hipError_t inv_tri_go(const Plan& p, const SpinTable& sp, int s, const double* in0, size_t stride, const Batch& B,
                       hipStream_t st)
 {
@@ -1946,11 +1955,13 @@ hipError_t inv_tri_go(const Plan& p, const SpinTable& sp, int s, const double* i
     for (int j = 0; j < CKI_MAX; ++j) off.off[j] = p.cki_off[j];
     const dim3 grid(sp.nwtri, B.n), block(64 * SEGT_MAX);
     if (EXT)
-        hipLaunchKernelGGL((k_contract_inverse_tri_ext<RL, SNEG>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
-                           p.edgek, p.lco, sp.lcos, sp.val, sp.k, p.cki, p.ckik, off, sp.wtri, p.L, p.Lp, s, p.ckg);
+        hipLaunchKernelGGL((k_contract_inverse_tri_ext<RL, SNEG, SPT>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
+                           p.edgek, p.lco, sp.lcos, sp.val, sp.k, sp.sval, p.cki, p.ckik, off, sp.wtri, p.L, p.Lp, s,
+                           p.ckg);
     else
-        hipLaunchKernelGGL((k_contract_inverse_tri<RL, SNEG>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
-                           p.edgek, p.lco, sp.lcos, sp.val, sp.k, p.cki, p.ckik, off, sp.wtri, p.L, p.Lp, s, p.ckg);
+        hipLaunchKernelGGL((k_contract_inverse_tri<RL, SNEG, SPT>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
+                           p.edgek, p.lco, sp.lcos, sp.val, sp.k, sp.sval, p.cki, p.ckik, off, sp.wtri, p.L, p.Lp, s,
+                           p.ckg);
     return hipGetLastError();
 }
 
@@ -1974,8 +1985,14 @@ template <bool EXT>
 hipError_t inv_go(const Plan& p, const SpinTable& sp, int s, int real, const double* in0, size_t stride,
                   const Batch& B, hipStream_t st)
 {
-    // real maps have s = 0
-    if (real) return inv_tri_go<EXT, true, false>(p, sp, s, in0, stride, B, st);
+    // real maps have s = 0; from L = INV_TRI_SPT_MIN_L their spin values come from
+    // the scaled spin rows (below, and for complex maps, the extra per-lane read
+    // cost more than the chain it replaces: real L = 320..896 8-13% slower,
+    // complex L = 1024 and 2048 6-10% slower; real L = 1024 6% and 2048 12% faster)
+    if (real) {
+        if (p.L >= INV_TRI_SPT_MIN_L) return inv_tri_go<EXT, true, false, true>(p, sp, s, in0, stride, B, st);
+        return inv_tri_go<EXT, true, false>(p, sp, s, in0, stride, B, st);
+    }
     if (p.L >= INV_TRI_MIN_L || g_inv_tri_all)
         return s < 0 ? inv_tri_go<EXT, false, true>(p, sp, s, in0, stride, B, st)
                      : inv_tri_go<EXT, false, false>(p, sp, s, in0, stride, B, st);

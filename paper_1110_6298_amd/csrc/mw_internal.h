@@ -29,6 +29,9 @@ constexpr int SEGT_MAX = 4;
 // Complex maps use the triangle kernel from this band-limit up (real maps at
 // every band-limit); below, the square kernels.
 constexpr int INV_TRI_MIN_L = 1024;
+// Real maps from this band-limit up read their spin values from the scaled spin
+// rows in the triangle kernel (below, they run a third chain).
+constexpr int INV_TRI_SPT_MIN_L = 1024;
 // Test hook (mw_profile_inverse_triangle): 1 runs every FP64 inverse on the
 // triangle kernel.
 extern int g_inv_tri_all;
