@@ -517,9 +517,11 @@ hipError_t run_chunk(Op op, const Chunk& c, const ChunkPlans& plans, const Chunk
         if (mix) {
             mix_forward(2, w1, user_out);
         } else {
+            const SpinTable* sp = tab(c.L, s < 0 ? -s : s);
+            if (!sp) return hipErrorInvalidValue;
             const mw::Batch B3 = batch_of(c, w1, user_out);
             go(2, [&] {
-                return mw::launch_contract_forward(p0, s, real, (const double*)w1(0), ws_need(Lws) / 8, B3, st);
+                return mw::launch_contract_forward(p0, *sp, s, real, (const double*)w1(0), ws_need(Lws) / 8, B3, st);
             });
         }
         break;
@@ -579,9 +581,11 @@ hipError_t run_chunk(Op op, const Chunk& c, const ChunkPlans& plans, const Chunk
         if (mix) {
             mix_forward(7, w1, user_out);
         } else {
+            const SpinTable* sp = tab(c.L, s < 0 ? -s : s);
+            if (!sp) return hipErrorInvalidValue;
             const mw::Batch B3 = batch_of(c, w1, user_out);
             go(7, [&] {
-                return mw::launch_contract_forward(p0, s, 0, (const double*)w1(0), ws_need(Lws) / 8, B3, st);
+                return mw::launch_contract_forward(p0, *sp, s, 0, (const double*)w1(0), ws_need(Lws) / 8, B3, st);
             });
         }
         if (real)
@@ -639,7 +643,9 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");
     const bool may_alloc = !capturing(st);
-    const bool need_spin = (op == Op::Inverse || op == Op::ForwardAdjoint);
+    // spin tables: every FP64 contraction reads its spin row from one; the mixed
+    // inverses start their spin rows from them
+    const bool need_spin = precision == MW_FP64 || op == Op::Inverse || op == Op::ForwardAdjoint;
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceState& d = g_dev[dev];
     const std::vector<Chunk> chunks = make_chunks(L, spin, reality, batch, precision);
@@ -832,10 +838,11 @@ int mw_forward_noalloc(const int32_t* L, const int32_t* spin, const int32_t* rea
     DeviceState& d = g_dev[dev];
     const std::vector<Chunk> chunks = make_chunks(L, spin, reality, batch, precision);
     std::vector<ChunkPlans> plans(chunks.size());
-    ChunkSpins none;
+    std::vector<ChunkSpins> tabs(chunks.size());
     for (size_t i = 0; i < chunks.size(); ++i)
-        if ((rc = resolve_chunk(d, chunks[i], false, false, plans[i], none)))
-            return fail(MW_ENOMEM, "mw_forward_noalloc: a plan of this call is not prepared (call mw_prepare first)");
+        if ((rc = resolve_chunk(d, chunks[i], precision == MW_FP64, false, plans[i], tabs[i])))
+            return fail(MW_ENOMEM, "mw_forward_noalloc: a plan or spin table of this call is not prepared (call "
+                                   "mw_prepare first)");
     // the chunks run one after another on the caller's stream, all in the one
     // set of workspace slots
     const int Lws = batch_lmax(L, batch);
@@ -852,7 +859,7 @@ int mw_forward_noalloc(const int32_t* L, const int32_t* spin, const int32_t* rea
     }
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < chunks.size() && e == hipSuccess; ++i)
-        e = run_chunk(Op::Forward, chunks[i], plans[i], none, precision, ptrs, d.scratch, Lws, st, false);
+        e = run_chunk(Op::Forward, chunks[i], plans[i], tabs[i], precision, ptrs, d.scratch, Lws, st, false);
     if (e != hipSuccess) return fail(MW_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     g_last_error.clear();
     return MW_OK;

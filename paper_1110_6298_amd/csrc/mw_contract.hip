@@ -99,15 +99,17 @@ struct FwdLane {
 };
 
 // Chain starts of step n (lanes whose degree l equals n start from the edge).
-template <int MT, bool EXT, bool INJ, int NS>
+template <int MT, bool EXT, bool INJ, int NS, bool SPT = false>
 __device__ __forceinline__ void fwd_inject(FwdLane<MT, EXT, NS>& st, int n, int l, bool& anyscaled)
 {
     if (INJ) {
         if (n == l) {
 #pragma unroll
             for (int c = 0; c < MT; ++c) { st.dc[c] = st.start[c]; if (EXT) st.k[c] = st.startk[c]; }
+            if constexpr (!SPT) {
 #pragma unroll
-            for (int j = 0; j < NS; ++j) { st.sc[j] = st.starts[j]; if (EXT) st.ks[j] = st.startks[j]; }
+                for (int j = 0; j < NS; ++j) { st.sc[j] = st.starts[j]; if (EXT) st.ks[j] = st.startks[j]; }
+            }
         }
         if (EXT) {
             bool sc = false;
@@ -122,7 +124,7 @@ __device__ __forceinline__ void fwd_inject(FwdLane<MT, EXT, NS>& st, int n, int 
 
 // Recursion from step n to n-1 with ra = 1/sqrt(Q_n):
 //   D_{n-1} = -(2m D_n + a_{n+1} D_{n+1}) / a_n,  a_n = sqrt(Q_n); harmless at n = 0.
-template <int MT, bool EXT, int NS>
+template <int MT, bool EXT, int NS, bool SPT = false>
 __device__ __forceinline__ void fwd_advance(FwdLane<MT, EXT, NS>& st, int mb, const SpinSet<NS>& as, double ra,
                                             bool& anyscaled)
 {
@@ -135,11 +137,13 @@ __device__ __forceinline__ void fwd_advance(FwdLane<MT, EXT, NS>& st, int mb, co
         st.dn[c] = st.dc[c];
         st.dc[c] = d;
     }
+    if constexpr (!SPT) {
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-        const double d = fma(2.0 * (double)as.a[j], st.sc[j], st.anext * st.sn[j]) * nra;
-        st.sn[j] = st.sc[j];
-        st.sc[j] = d;
+        for (int j = 0; j < NS; ++j) {
+            const double d = fma(2.0 * (double)as.a[j], st.sc[j], st.anext * st.sn[j]) * nra;
+            st.sn[j] = st.sc[j];
+            st.sc[j] = d;
+        }
     }
     st.anext = an;
     st.q += st.dq;          // Q_{n-1} = Q_n + 2(n-1)
@@ -153,10 +157,12 @@ __device__ __forceinline__ void fwd_advance(FwdLane<MT, EXT, NS>& st, int mb, co
             }
             still |= st.k[c] > 0;
         }
+        if constexpr (!SPT) {
 #pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            if (st.ks[j] > 0 && fabs(st.sc[j]) > EXT_UP) { st.sc[j] *= EXT_DOWN; st.sn[j] *= EXT_DOWN; st.ks[j] -= 1; }
-            still |= st.ks[j] > 0;
+            for (int j = 0; j < NS; ++j) {
+                if (st.ks[j] > 0 && fabs(st.sc[j]) > EXT_UP) { st.sc[j] *= EXT_DOWN; st.sn[j] *= EXT_DOWN; st.ks[j] -= 1; }
+                still |= st.ks[j] > 0;
+            }
         }
         anyscaled = __any(still);
     }
@@ -174,16 +180,24 @@ __device__ __forceinline__ double fwd_product(const FwdLane<MT, EXT, NS>& st, in
 }
 
 // One step n: contributions of D_{.,n} (h = the four doubles of H at n for
-// each chain), then the recursion to n-1.
-template <int MT, bool EXT, int PAR, bool INJ, bool RL>
+// each chain), then the recursion to n-1.  The spin row's value Delta^l_{|s|,n}
+// at this step is sv, read from the spin table's transposed rows.
+template <int MT, bool EXT, int PAR, bool INJ, bool RL, bool SPT>
 __device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int mb, int as,
-                                         const Rec8 (&h)[MT], double ra, bool& anyscaled)
+                                         const Rec8 (&h)[MT], double ra, double sv, bool& anyscaled)
 {
-    fwd_inject<MT, EXT, INJ, 1>(st, n, l, anyscaled);
+    fwd_inject<MT, EXT, INJ, 1, SPT>(st, n, l, anyscaled);
 #pragma unroll
     for (int c = 0; c < MT; ++c) {
         const double* hc = h[c].v + 4 * PAR;
-        const double pr = fwd_product<MT, EXT, 1>(st, c);
+        double pr;
+        if constexpr (SPT) {
+            double d = st.dc[c];
+            if (EXT) d = (st.k[c] == 0) ? d : 0.0;
+            pr = d * sv;
+        } else {
+            pr = fwd_product<MT, EXT, 1>(st, c);
+        }
         st.ap[c][PAR].x = fma(pr, hc[0], st.ap[c][PAR].x);
         st.ap[c][PAR].y = fma(pr, hc[1], st.ap[c][PAR].y);
         if (!RL) {   // real maps: f_{l,-m} follows from f_{l,m}
@@ -191,7 +205,7 @@ __device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int
             st.am[c][PAR].y = fma(pr, hc[3], st.am[c][PAR].y);
         }
     }
-    fwd_advance<MT, EXT, 1>(st, mb, SpinSet<1>{{as}}, ra, anyscaled);
+    fwd_advance<MT, EXT, 1, SPT>(st, mb, SpinSet<1>{{as}}, ra, anyscaled);
 }
 
 template <int MT>
@@ -217,21 +231,33 @@ __device__ __forceinline__ FwdR fwd_load_r(const double* __restrict__ Rt, int le
     return r;
 }
 
-template <int MT, bool EXT, bool INJ, bool RL>
+// The spin values of the pair's steps: sv.x at n = 2k+1, sv.y at n = 2k.
+template <int MT, bool EXT, bool INJ, bool RL, bool SPT>
 __device__ __forceinline__ void fwd_pair(FwdLane<MT, EXT>& st, int k, int l, int mb, int as,
-                                         const Rec8 (&h)[MT], const FwdR& r, bool& anyscaled)
+                                         const Rec8 (&h)[MT], const FwdR& r, const double2& sv, bool& anyscaled)
 {
     // n = 2k+1: 1/sqrt(l+n) = hi.y, 1/sqrt(l-n+1) = lo.x;  n = 2k: hi.x, lo.y
-    fwd_step<MT, EXT, 1, INJ, RL>(st, 2 * k + 1, l, mb, as, h, r.hi.y * r.lo.x, anyscaled);
-    fwd_step<MT, EXT, 0, INJ, RL>(st, 2 * k, l, mb, as, h, r.hi.x * r.lo.y, anyscaled);
+    fwd_step<MT, EXT, 1, INJ, RL, SPT>(st, 2 * k + 1, l, mb, as, h, r.hi.y * r.lo.x, sv.x, anyscaled);
+    fwd_step<MT, EXT, 0, INJ, RL, SPT>(st, 2 * k, l, mb, as, h, r.hi.x * r.lo.y, sv.y, anyscaled);
+}
+
+// SPT: the spin values Delta^l_{|s|,n} of the lane for the pair k (rows 2k+1,
+// 2k) from the transposed spin rows (svl: the lane's column, row stride L);
+// without, the spin row runs as a third chain.
+template <bool SPT>
+__device__ __forceinline__ double2 fwd_load_sv(const double* __restrict__ svl, int L, int k)
+{
+    if (!SPT) return make_double2(0.0, 0.0);
+    return make_double2(svl[(size_t)(2 * k + 1) * L], svl[(size_t)(2 * k) * L]);
 }
 
 // Pairs kfrom, kfrom-1, ..., kto+1 (an even count); on entry A holds pair kfrom,
 // on exit A holds pair kto (pair 0 when kto < 0).
-template <int MT, bool EXT, bool INJ, bool RL>
+template <int MT, bool EXT, bool INJ, bool RL, bool SPT>
 __device__ __forceinline__ void fwd_phase(FwdLane<MT, EXT>& st, int kfrom, int kto, int l, int le, int mb,
                                           int as, const double* __restrict__ Hp, const double* __restrict__ Rt,
-                                          int Lp, int L, Rec8 (&hA)[MT], Rec8 (&hB)[MT], FwdR& rA, FwdR& rB,
+                                          const double* __restrict__ svl, int Lp, int L, Rec8 (&hA)[MT],
+                                          Rec8 (&hB)[MT], FwdR& rA, FwdR& rB, double2& sA, double2& sB,
                                           bool& anyscaled)
 {
     for (int k = kfrom; k > kto; k -= 2) {
@@ -239,48 +265,53 @@ __device__ __forceinline__ void fwd_phase(FwdLane<MT, EXT>& st, int kfrom, int k
         __builtin_amdgcn_sched_barrier(0);
         fwd_load_h<MT>(hB, Hp, mb, Lp, L, k - 1);
         rB = fwd_load_r(Rt, le, k - 1);
+        sB = fwd_load_sv<SPT>(svl, L, k - 1);
         __builtin_amdgcn_sched_barrier(0);
-        fwd_pair<MT, EXT, INJ, RL>(st, k, l, mb, as, hA, rA, anyscaled);
+        fwd_pair<MT, EXT, INJ, RL, SPT>(st, k, l, mb, as, hA, rA, sA, anyscaled);
         wait_scalar(hB[0].v[0]);
         __builtin_amdgcn_sched_barrier(0);
         const int k2 = max(k - 2, 0);
         fwd_load_h<MT>(hA, Hp, mb, Lp, L, k2);
         rA = fwd_load_r(Rt, le, k2);
+        sA = fwd_load_sv<SPT>(svl, L, k2);
         __builtin_amdgcn_sched_barrier(0);
-        fwd_pair<MT, EXT, INJ, RL>(st, k - 1, l, mb, as, hB, rB, anyscaled);
+        fwd_pair<MT, EXT, INJ, RL, SPT>(st, k - 1, l, mb, as, hB, rB, sB, anyscaled);
     }
 }
 
 // Pairs ktop .. klo of one segment; pairs >= kA (kA in [klo, ktop+1]) contain
 // lane starts.  Phase loops cover even pair counts; a leftover pair is peeled.
-template <int MT, bool EXT, bool RL>
+template <int MT, bool EXT, bool RL, bool SPT>
 __device__ __forceinline__ void fwd_segment(FwdLane<MT, EXT>& st, int ktop, int kA, int klo, int l, int le, int mb,
                                             int as, const double* __restrict__ Hp, const double* __restrict__ Rt,
-                                            int Lp, int L, bool& anyscaled)
+                                            const double* __restrict__ svl, int Lp, int L, bool& anyscaled)
 {
     Rec8 hA[MT], hB[MT];
     FwdR rA, rB;
+    double2 sA, sB;
     fwd_load_h<MT>(hA, Hp, mb, Lp, L, ktop);
     rA = fwd_load_r(Rt, le, ktop);
+    sA = fwd_load_sv<SPT>(svl, L, ktop);
     int cntA = ktop - kA + 1;
     if ((cntA & 1) && kA > klo) { --kA; ++cntA; }
     if (cntA > 0) {
         const int klastA = (cntA & 1) ? kA + 1 : kA;
-        fwd_phase<MT, EXT, true, RL>(st, ktop, klastA - 1, l, le, mb, as, Hp, Rt, Lp, L, hA, hB, rA, rB, anyscaled);
+        fwd_phase<MT, EXT, true, RL, SPT>(st, ktop, klastA - 1, l, le, mb, as, Hp, Rt, svl, Lp, L, hA, hB, rA, rB, sA,
+                                          sB, anyscaled);
         if (cntA & 1) {            // kA = klo, in A
             wait_scalar(hA[0].v[0]);
-            fwd_pair<MT, EXT, true, RL>(st, kA, l, mb, as, hA, rA, anyscaled);
+            fwd_pair<MT, EXT, true, RL, SPT>(st, kA, l, mb, as, hA, rA, sA, anyscaled);
             return;
         }
     }
     const int cntB = kA - klo;     // pairs kA-1 .. klo, A holds kA-1
     if (cntB > 0) {
         const int klastB = (cntB & 1) ? klo + 1 : klo;
-        fwd_phase<MT, EXT, false, RL>(st, kA - 1, klastB - 1, l, le, mb, as, Hp, Rt, Lp, L, hA, hB, rA, rB,
-                                     anyscaled);
+        fwd_phase<MT, EXT, false, RL, SPT>(st, kA - 1, klastB - 1, l, le, mb, as, Hp, Rt, svl, Lp, L, hA, hB, rA, rB,
+                                           sA, sB, anyscaled);
         if (cntB & 1) {
             wait_scalar(hA[0].v[0]);
-            fwd_pair<MT, EXT, false, RL>(st, klo, l, mb, as, hA, rA, anyscaled);
+            fwd_pair<MT, EXT, false, RL, SPT>(st, klo, l, mb, as, hA, rA, sA, anyscaled);
         }
     }
 }
@@ -390,12 +421,12 @@ __device__ __forceinline__ FwdSeg fwd_setup(FwdLane<MT, EXT, NS>& st, bool& anys
 // FP64 forward contraction.  One workgroup per chain group (64 degrees l0..,
 // MT orders mb..); wave w runs segment w of the row recursions.  Partial sums
 // are added in LDS in segment order.
-template <int MT, bool EXT, bool RL>
+template <int MT, bool EXT, bool RL, bool SPT>
 __device__ __forceinline__ void contract_forward_body(
     const double* __restrict__ Hp0, size_t hstride, const Batch& B, const double* __restrict__ Rtg,
     const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,
-    const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int4* __restrict__ work, int L, int Lp,
-    int s, int ckfg)
+    const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const double* __restrict__ svf,
+    const int4* __restrict__ work, int L, int Lp, int s, int ckfg)
 {
     // LDS: the partial sums of upper segments, red[slot][c][k][lane].  The
     // 1/sqrt table is read from global memory (L1-resident), so the LDS of a
@@ -423,7 +454,17 @@ __device__ __forceinline__ void contract_forward_body(
         bool anyscaled;
         const FwdSeg g = fwd_setup<MT, EXT, 1>(st, anyscaled, w, nseg, lo, hi, l0, mb, l, L, SpinSet<1>{{as}}, ckfg,
                                                edge, edgek, ckf, ckfk);
-        if (g.active) fwd_segment<MT, EXT, RL>(st, g.ktop, g.kA, g.klo, l, le, mb, as, Hp, Rt, Lp, L, anyscaled);
+        if (SPT) {   // the spin row's values come from the transposed spin rows, not a chain
+            st.ks[0] = 0;
+            if (EXT) {
+                bool sc = false;
+#pragma unroll
+                for (int c = 0; c < MT; ++c) sc |= st.k[c] > 0;
+                anyscaled = __any(sc);
+            }
+        }
+        if (g.active)
+            fwd_segment<MT, EXT, RL, SPT>(st, g.ktop, g.kA, g.klo, l, le, mb, as, Hp, Rt, svf + le, Lp, L, anyscaled);
     }
     if (bar) {
         // every wave of the workgroup (empty slots too) meets at this one barrier
@@ -495,22 +536,22 @@ __device__ __forceinline__ void contract_forward_body(
 #define MW_FORWARD_ARGS                                                                                          \
     const double* __restrict__ Hp0, size_t hstride, Batch B, const double* __restrict__ Rtg,                    \
         const double* __restrict__ edge, const int* __restrict__ edgek, const double* __restrict__ cl,           \
-        const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const int4* __restrict__ work, int L,    \
-        int Lp, int s, int ckfg
-#define MW_FORWARD_PASS Hp0, hstride, B, Rtg, edge, edgek, cl, ckf, ckfk, work, L, Lp, s, ckfg
+        const double2* __restrict__ ckf, const int2* __restrict__ ckfk, const double* __restrict__ svf,          \
+        const int4* __restrict__ work, int L, int Lp, int s, int ckfg
+#define MW_FORWARD_PASS Hp0, hstride, B, Rtg, edge, edgek, cl, ckf, ckfk, svf, work, L, Lp, s, ckfg
 
-template <int MT, bool RL>
+template <int MT, bool RL, bool SPT>
 __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(4))) void k_contract_forward(
     MW_FORWARD_ARGS)
 {
-    contract_forward_body<MT, false, RL>(MW_FORWARD_PASS);
+    contract_forward_body<MT, false, RL, SPT>(MW_FORWARD_PASS);
 }
 
-template <int MT, bool RL>
+template <int MT, bool RL, bool SPT>
 __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(4))) void k_contract_forward_ext(
     MW_FORWARD_ARGS)
 {
-    contract_forward_body<MT, true, RL>(MW_FORWARD_PASS);
+    contract_forward_body<MT, true, RL, SPT>(MW_FORWARD_PASS);
 }
 #undef MW_FORWARD_ARGS
 #undef MW_FORWARD_PASS
@@ -1903,25 +1944,41 @@ __global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(G
 }  // namespace
 
 namespace {
-template <bool EXT, bool RL>
-hipError_t fwd_go(const Plan& p, int s, const double* in0, size_t stride, const Batch& B, hipStream_t st)
+template <bool EXT, bool RL, bool SPT>
+hipError_t fwd_go(const Plan& p, const SpinTable& sp, int s, const double* in0, size_t stride, const Batch& B,
+                  hipStream_t st)
 {
     const dim3 grid(p.nworkf4, B.n), block(64 * SEG_MAX);
     if (EXT)
-        hipLaunchKernelGGL((k_contract_forward_ext<MT_FWD, RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
-                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, p.Lp, s, p.ckfg);
+        hipLaunchKernelGGL((k_contract_forward_ext<MT_FWD, RL, SPT>), grid, block, 0, st, in0, stride, B, p.rtab,
+                           p.edge, p.edgek, p.cl, p.ckf, p.ckfk, sp.svalf, p.workf4, p.L, p.Lp, s, p.ckfg);
     else
-        hipLaunchKernelGGL((k_contract_forward<MT_FWD, RL>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
-                           p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, p.Lp, s, p.ckfg);
+        hipLaunchKernelGGL((k_contract_forward<MT_FWD, RL, SPT>), grid, block, 0, st, in0, stride, B, p.rtab, p.edge,
+                           p.edgek, p.cl, p.ckf, p.ckfk, sp.svalf, p.workf4, p.L, p.Lp, s, p.ckfg);
     return hipGetLastError();
+}
+
+template <bool EXT, bool SPT>
+hipError_t fwd_go_r(const Plan& p, const SpinTable& sp, int s, int real, const double* in0, size_t stride,
+                    const Batch& B, hipStream_t st)
+{
+    return real ? fwd_go<EXT, true, SPT>(p, sp, s, in0, stride, B, st)
+                : fwd_go<EXT, false, SPT>(p, sp, s, in0, stride, B, st);
 }
 }  // namespace
 
-hipError_t launch_contract_forward(const Plan& p, int s, int real, const double* in0, size_t stride, const Batch& B,
-                                   hipStream_t st)
+// From L = FWD_SPT_MIN_L the spin row's values come from the spin table's
+// transposed rows; below, the third chain is faster (measured at L = 256 and
+// 512: 6-25% slower with the table, at L = 1024 and 2048 5-7% faster).
+hipError_t launch_contract_forward(const Plan& p, const SpinTable& sp, int s, int real, const double* in0,
+                                   size_t stride, const Batch& B, hipStream_t st)
 {
-    if (p.ext) return real ? fwd_go<true, true>(p, s, in0, stride, B, st) : fwd_go<true, false>(p, s, in0, stride, B, st);
-    return real ? fwd_go<false, true>(p, s, in0, stride, B, st) : fwd_go<false, false>(p, s, in0, stride, B, st);
+    const bool spt = p.L >= FWD_SPT_MIN_L;
+    if (p.ext)
+        return spt ? fwd_go_r<true, true>(p, sp, s, real, in0, stride, B, st)
+                   : fwd_go_r<true, false>(p, sp, s, real, in0, stride, B, st);
+    return spt ? fwd_go_r<false, true>(p, sp, s, real, in0, stride, B, st)
+               : fwd_go_r<false, false>(p, sp, s, real, in0, stride, B, st);
 }
 
 hipError_t launch_spin_flip(int L, const Batch& B, hipStream_t st)

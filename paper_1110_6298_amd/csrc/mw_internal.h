@@ -32,6 +32,8 @@ constexpr int INV_TRI_MIN_L = 1024;
 // Real maps from this band-limit up read their spin values from the scaled spin
 // rows in the triangle kernel (below, they run a third chain).
 constexpr int INV_TRI_SPT_MIN_L = 1024;
+// The FP64 forward reads its spin row from the spin table from this band-limit up.
+constexpr int FWD_SPT_MIN_L = 1024;
 // Test hook (mw_profile_inverse_triangle): 1 runs every FP64 inverse on the
 // triangle kernel.
 extern int g_inv_tri_all;
@@ -128,6 +130,7 @@ struct SpinTable {
     int nwinv = 0;   // workgroups
     double2* lcos = nullptr;
     double* sval = nullptr;   // h_|s|(l) Delta^l_{n,|s|} at [l*L + n], l < Lp (the FP64 inverses' spin values)
+    double* svalf = nullptr;  // Delta^l_{|s|,n} at [n*L + l], n < Lp (the FP64 forward's spin values)
     int4* wtri = nullptr;
     int nwtri = 0;   // workgroups
     size_t bytes = 0;
@@ -208,8 +211,8 @@ hipError_t launch_theta_forward_adjoint(const Plan& p, const Batch& B, hipStream
 // chunk's workspace slots are equally spaced) and writes B.out[k].  real = 1
 // (real scalar maps): the forward writes f_{l,-m} = (-1)^m conj(f_{l,m}) and the
 // inverse writes only the orders m >= 0 of F.
-hipError_t launch_contract_forward(const Plan& p, int s, int real, const double* in0, size_t stride, const Batch& B,
-                                   hipStream_t st);
+hipError_t launch_contract_forward(const Plan& p, const SpinTable& sp, int s, int real, const double* in0,
+                                   size_t stride, const Batch& B, hipStream_t st);
 // Inverse coefficient stream (L x Lp x 4 doubles, or FP32 at [(m*4+comp)*Lp + l]),
 // each map with its own spin B.s[k].
 hipError_t launch_inverse_stream(const Plan& p, int real, const Batch& B, int out32, hipStream_t st);

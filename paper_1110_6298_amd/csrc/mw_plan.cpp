@@ -695,6 +695,9 @@ int build_spin_table(const Plan& p, int as, SpinTable& t, std::string& err)
     // the scaled spin values h_|s|(l) Delta^l_{n,|s|} (zero below 2^-900 and in
     // the pad row l = L of an odd L), the FP64 inverses' spin rows
     std::vector<double> sval((size_t)p.Lp * L, 0.0);
+    // the forward's spin values Delta^l_{|s|,n} = (-1)^{n+|s|} Delta^l_{n,|s|},
+    // transposed (64 consecutive l of one row n are one read)
+    std::vector<double> svalf((size_t)p.Lp * L, 0.0);
     for (int n = 0; n < L; ++n) {
         int l0 = std::max(n, as);
         if (l0 >= L) continue;
@@ -707,7 +710,10 @@ int build_spin_table(const Plan& p, int as, SpinTable& t, std::string& err)
             split_ext(a, x, k);
             val[(size_t)l * L + n] = (dcur < 0) ? -x : x;
             kk[(size_t)l * L + n] = k;
-            if (a > 0x1p-900L) sval[(size_t)l * L + n] = (double)(dcur * (ld)hs[(size_t)as * p.Lp + l].y);
+            if (a > 0x1p-900L) {
+                sval[(size_t)l * L + n] = (double)(dcur * (ld)hs[(size_t)as * p.Lp + l].y);
+                svalf[(size_t)n * L + l] = (double)(((n + as) & 1) ? -dcur : dcur);
+            }
             if (a > 0x1p-900L)
                 lcos[(size_t)n * p.Lp + l].y =
                     (double)(sqrtl((2.0L * l + 1.0L) / (4.0L * PI_L)) * dcur / (ld)hs[(size_t)n * p.Lp + l].y);
@@ -733,6 +739,7 @@ int build_spin_table(const Plan& p, int as, SpinTable& t, std::string& err)
     if ((rc = upload(w, &t.winv, t.bytes, err))) return rc;
     if ((rc = upload(lcos, &t.lcos, t.bytes, err))) return rc;
     if ((rc = upload(sval, &t.sval, t.bytes, err))) return rc;
+    if ((rc = upload(svalf, &t.svalf, t.bytes, err))) return rc;
     const std::vector<int4> wt = inverse_work_tri(p, as);
     t.nwtri = (int)(wt.size() / SEGT_MAX);
     if ((rc = upload(wt, &t.wtri, t.bytes, err))) return rc;
@@ -746,6 +753,7 @@ void free_spin_table(SpinTable& t)
     if (t.winv) (void)hipFree(t.winv);
     if (t.lcos) (void)hipFree(t.lcos);
     if (t.sval) (void)hipFree(t.sval);
+    if (t.svalf) (void)hipFree(t.svalf);
     if (t.wtri) (void)hipFree(t.wtri);
     t = SpinTable();
 }
