@@ -454,6 +454,7 @@ std::vector<MixLaunch> mix_of(const Chunk& c, Src src, Dst dst, Tab stab)
                 const SpinTable* t = stab(Lg, ml.M.as[j]);
                 ml.M.stab[j] = t ? t->val : nullptr;
                 ml.M.stabk[j] = t ? t->k : nullptr;
+                ml.M.ssv[j] = t ? t->sval : nullptr;
             }
             ml.asmax = std::max(ml.M.as[0], ml.M.as[1]);
             out.push_back(ml);

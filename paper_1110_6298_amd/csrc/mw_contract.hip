@@ -776,12 +776,13 @@ __device__ __forceinline__ bool inv2_scaled(const InvLane2<EXT, NS>& st)
 }
 
 // dd: the chain values of this step as they enter the products (0 while scaled).
-// SPT (one spin row): the spin value e^l_{n,|s|} of this step is svt, read from
-// the spin table's scaled rows, instead of a third chain.
+// SPT: the spin values e^l_{n,|s_j|} of this step are svt[j], read from the
+// spin tables' scaled rows, instead of chains.
 template <bool EXT, bool INJ, int NS, bool SPT = false>
 __device__ __forceinline__ void inv2_core_d(InvLane2<EXT, NS>& st, int l, int lstart, double nd, const double2& c0,
                                             const double2& c1, const double2 (&cs)[NS], double rs,
-                                            double (&pr)[2][NS], double (&dd)[2], bool& anyscaled, double svt = 0.0)
+                                            double (&pr)[2][NS], double (&dd)[2], bool& anyscaled,
+                                            const double* svt = nullptr)
 {
     if (INJ) {
 #pragma unroll
@@ -798,7 +799,7 @@ __device__ __forceinline__ void inv2_core_d(InvLane2<EXT, NS>& st, int l, int ls
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
         if constexpr (SPT) {
-            sv[j] = svt;
+            sv[j] = svt[j];
         } else {
             sv[j] = st.sc[j];
             if (EXT) sv[j] = (st.ks[j] == 0) ? sv[j] : 0.0;
@@ -862,7 +863,7 @@ __device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, 
 {
     double pr[2][1], dd[2];
     const double2 cs[1] = {u.cs};
-    inv2_core_d<EXT, INJ, 1, true>(st, l, lstart, nd, u.c0, u.c1, cs, rs, pr, dd, anyscaled, sv);
+    inv2_core_d<EXT, INJ, 1, true>(st, l, lstart, nd, u.c0, u.c1, cs, rs, pr, dd, anyscaled, &sv);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const double4 f = c ? u.f1 : u.f0;
@@ -1208,7 +1209,7 @@ __device__ __forceinline__ void inv3_step(InvLane3<EXT>& st, int l, int lstart, 
 {
     double pr[2][1], dd[2];
     const double2 cs[1] = {u.cs};
-    inv2_core_d<EXT, INJ, 1, SPT>(st.b, l, lstart, nd, u.c0, u.c1, cs, rs, pr, dd, anyscaled, sv);
+    inv2_core_d<EXT, INJ, 1, SPT>(st.b, l, lstart, nd, u.c0, u.c1, cs, rs, pr, dd, anyscaled, &sv);
     constexpr double sgp = (PAR && !SNEG) ? -1.0 : 1.0;   // sp(l)
     constexpr double sgm = (PAR && SNEG) ? -1.0 : 1.0;    // sm(l)
 #pragma unroll
@@ -1724,23 +1725,38 @@ __device__ __forceinline__ void inv2m_win_load(InvWin2<G>& r, const MixMaps& map
     }
 }
 
+// Spin values of a pair (degrees 2j, 2j+1) of the lane, one double2 per spin
+// row, from the scaled spin rows (row stride L).
+template <int NS>
+struct SvPair { double2 v[NS]; };
+
+template <int NS>
+__device__ __forceinline__ void inv2m_load_sv(SvPair<NS>& sv, const double* const (&svl)[NS], int L, int j)
+{
+#pragma unroll
+    for (int q = 0; q < NS; ++q) sv.v[q] = make_double2(svl[q][(size_t)(2 * j) * L], svl[q][(size_t)(2 * j + 1) * L]);
+}
+
 template <bool EXT, bool INJ, int G, int NS>
 __device__ __forceinline__ void inv2m_pair(InvLane2<EXT, NS>& st, v4f (&acc)[2][G], int j, int lstart, double nd,
-                                           const InvC2<NS>& u, const InvR& r, const MixMaps& maps,
-                                           const float* __restrict__ win, int comp, bool& anyscaled)
+                                           const InvC2<NS>& u, const InvR& r, const SvPair<NS>& sp,
+                                           const MixMaps& maps, const float* __restrict__ win, int comp,
+                                           bool& anyscaled)
 {
     const int l = 2 * j;
-    double p0[2][NS], p1[2][NS];
+    double p0[2][NS], p1[2][NS], dd[2], s0[NS], s1[NS];
     double2 cs0[NS], cs1[NS];
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         cs0[q] = make_double2(u.cs[q].x, u.cs[q].y);
         cs1[q] = make_double2(u.cs[q].z, u.cs[q].w);
+        s0[q] = sp.v[q].x;
+        s1[q] = sp.v[q].y;
     }
-    inv2_core<EXT, INJ, NS>(st, l, lstart, nd, make_double2(u.c0.x, u.c0.y), make_double2(u.c1.x, u.c1.y), cs0,
-                            r.a.x * r.b.x, p0, anyscaled);
-    inv2_core<EXT, INJ, NS>(st, l + 1, lstart, nd, make_double2(u.c0.z, u.c0.w), make_double2(u.c1.z, u.c1.w), cs1,
-                            r.a.y * r.b.y, p1, anyscaled);
+    inv2_core_d<EXT, INJ, NS, true>(st, l, lstart, nd, make_double2(u.c0.x, u.c0.y), make_double2(u.c1.x, u.c1.y),
+                                    cs0, r.a.x * r.b.x, p0, dd, anyscaled, s0);
+    inv2_core_d<EXT, INJ, NS, true>(st, l + 1, lstart, nd, make_double2(u.c0.z, u.c0.w), make_double2(u.c1.z, u.c1.w),
+                                    cs1, r.a.y * r.b.y, p1, dd, anyscaled, s1);
     const int off = l - WIN * (j / (WIN / 2));   // degree l within its window
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -1765,14 +1781,15 @@ __device__ __forceinline__ void inv2m_pair(InvLane2<EXT, NS>& st, v4f (&acc)[2][
 template <bool EXT, bool INJ, int G, int NS>
 __device__ __forceinline__ void inv2m_run(InvLane2<EXT, NS>& st, v4f (&acc)[2][G], const InvSeg& g, int& j, int jto,
                                           int jend, int lstart, int ne, double nd, int m0, const Inv2Rows& rows,
-                                          const double* __restrict__ Rt, float* __restrict__ win,
-                                          const MixMaps& maps, int lane, InvWin2<G>& nxt, InvC2<NS>& uA, InvR& rA,
-                                          bool& anyscaled)
+                                          const double* __restrict__ Rt, const double* const (&svl)[NS], int L,
+                                          float* __restrict__ win, const MixMaps& maps, int lane, InvWin2<G>& nxt,
+                                          InvC2<NS>& uA, InvR& rA, SvPair<NS>& sA, bool& anyscaled)
 {
     constexpr int PW = WIN / 2;   // pairs per window
     const int comp = lane & 3;
     InvC2<NS> uB;
     InvR rB;
+    SvPair<NS> sB;
     while (j <= jto) {
         if (j == g.jfrom || (j % PW) == 0) {          // entering window j / PW
             win_store<2 * G>(win, nxt.v, lane);
@@ -1783,19 +1800,23 @@ __device__ __forceinline__ void inv2m_run(InvLane2<EXT, NS>& st, v4f (&acc)[2][G
             wait_scalar(uA.c0.x);
             inv2m_load_c(uB, rows, min(j + 1, jend));
             rB = inv_load_r(Rt, ne, min(j + 1, jend));
-            inv2m_pair<EXT, INJ, G, NS>(st, acc, j, lstart, nd, uA, rA, maps, win, comp, anyscaled);
+            inv2m_load_sv(sB, svl, L, min(j + 1, jend));
+            inv2m_pair<EXT, INJ, G, NS>(st, acc, j, lstart, nd, uA, rA, sA, maps, win, comp, anyscaled);
             wait_scalar(uB.c0.x);
             inv2m_load_c(uA, rows, min(j + 2, jend));
             rA = inv_load_r(Rt, ne, min(j + 2, jend));
-            inv2m_pair<EXT, INJ, G, NS>(st, acc, j + 1, lstart, nd, uB, rB, maps, win, comp, anyscaled);
+            inv2m_load_sv(sA, svl, L, min(j + 2, jend));
+            inv2m_pair<EXT, INJ, G, NS>(st, acc, j + 1, lstart, nd, uB, rB, sB, maps, win, comp, anyscaled);
         }
         if (j == jw) {                                 // odd pair left in the window
             wait_scalar(uA.c0.x);
             inv2m_load_c(uB, rows, min(j + 1, jend));
             rB = inv_load_r(Rt, ne, min(j + 1, jend));
-            inv2m_pair<EXT, INJ, G, NS>(st, acc, j, lstart, nd, uA, rA, maps, win, comp, anyscaled);
+            inv2m_load_sv(sB, svl, L, min(j + 1, jend));
+            inv2m_pair<EXT, INJ, G, NS>(st, acc, j, lstart, nd, uA, rA, sA, maps, win, comp, anyscaled);
             uA = uB;
             rA = rB;
+            sA = sB;
             ++j;
         }
     }
@@ -1804,8 +1825,9 @@ __device__ __forceinline__ void inv2m_run(InvLane2<EXT, NS>& st, v4f (&acc)[2][G
 template <bool EXT, int G, int NS>
 __device__ __forceinline__ void inv2m_segment(InvLane2<EXT, NS>& st, v4f (&acc)[2][G], const InvSeg& g, int jend,
                                               int lstart, int ne, double nd, int m0, const Inv2Rows& rows,
-                                              const double* __restrict__ Rt, float* __restrict__ win,
-                                              const MixMaps& maps, int lane, bool& anyscaled)
+                                              const double* __restrict__ Rt, const double* const (&svl)[NS], int L,
+                                              float* __restrict__ win, const MixMaps& maps, int lane,
+                                              bool& anyscaled)
 {
     constexpr int PW = WIN / 2;
     InvWin2<G> nxt;
@@ -1813,11 +1835,13 @@ __device__ __forceinline__ void inv2m_segment(InvLane2<EXT, NS>& st, v4f (&acc)[
     InvC2<NS> uA;
     inv2m_load_c<NS>(uA, rows, g.jfrom);
     InvR rA = inv_load_r(Rt, ne, g.jfrom);
+    SvPair<NS> sA;
+    inv2m_load_sv(sA, svl, L, g.jfrom);
     int j = g.jfrom;
-    inv2m_run<EXT, true, G, NS>(st, acc, g, j, min(g.jA, g.jlast), jend, lstart, ne, nd, m0, rows, Rt, win, maps, lane,
-                            nxt, uA, rA, anyscaled);   // pairs with chain starts
-    inv2m_run<EXT, false, G, NS>(st, acc, g, j, g.jlast, jend, lstart, ne, nd, m0, rows, Rt, win, maps, lane, nxt, uA,
-                             rA, anyscaled);
+    inv2m_run<EXT, true, G, NS>(st, acc, g, j, min(g.jA, g.jlast), jend, lstart, ne, nd, m0, rows, Rt, svl, L, win,
+                                maps, lane, nxt, uA, rA, sA, anyscaled);   // pairs with chain starts
+    inv2m_run<EXT, false, G, NS>(st, acc, g, j, g.jlast, jend, lstart, ne, nd, m0, rows, Rt, svl, L, win, maps, lane,
+                                 nxt, uA, rA, sA, anyscaled);
 }
 
 // LDS floats per wave slot: its window, later its partial sums (a v4f per
@@ -1886,10 +1910,15 @@ __global__ __launch_bounds__(64 * SEGI_MAX) __attribute__((amdgpu_waves_per_eu(G
         bool anyscaled;
         const InvSeg g = inv2_setup<EXT, NS>(st, anyscaled, geo, w, n, m0, L, Lp, sset, ckg, lco, edge, edgek, tj, cki,
                                              ckik, ckoff);
+        // the spin values come from the scaled spin rows, not chains
+        const double* svl[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) { st.ks[q] = 0; svl[q] = MB.ssv[q] + ne; }
+        if (EXT) anyscaled = __any(inv2_scaled(st));
         if (g.active)
             inv2m_segment<EXT, G, NS>(st, acc, g, jend, geo.lstart, ne, nd, m0,
-                                      inv2_rows(nullptr, lco, m0, sset.a[0], Lp, L, sset.a[NS - 1]), Rt, region, maps,
-                                      lane, anyscaled);
+                                      inv2_rows(nullptr, lco, m0, sset.a[0], Lp, L, sset.a[NS - 1]), Rt, svl, L,
+                                      region, maps, lane, anyscaled);
     }
 
     if (bar) {

@@ -167,6 +167,7 @@ struct MixBatch {
     int as[NSMAX];
     const double* stab[NSMAX];
     const int* stabk[NSMAX];
+    const double* ssv[NSMAX];   // inverse: the scaled spin rows of those tables (SpinTable::sval)
 };
 __host__ __device__ inline int mix_spin(const MixBatch& B, const MixMaps& m, int b)
 {
