@@ -455,6 +455,7 @@ std::vector<MixLaunch> mix_of(const Chunk& c, Src src, Dst dst, Tab stab)
                 ml.M.stab[j] = t ? t->val : nullptr;
                 ml.M.stabk[j] = t ? t->k : nullptr;
                 ml.M.ssv[j] = t ? t->sval : nullptr;
+                ml.M.ssvf[j] = t ? t->svalf : nullptr;
             }
             ml.asmax = std::max(ml.M.as[0], ml.M.as[1]);
             out.push_back(ml);
@@ -497,14 +498,13 @@ hipError_t run_chunk(Op op, const Chunk& c, const ChunkPlans& plans, const Chunk
             go(stage, [&] { return launch(p, B); });
         }
     };
-    auto no_tab = [](int, int) -> const SpinTable* { return nullptr; };
     auto tab = [&](int L, int as) -> const SpinTable* {
         auto it = sps.find(std::make_pair(L, as));
         return it == sps.end() ? nullptr : it->second;
     };
     // the mixed contractions of the chunk: one launch per (largest L, spin rows)
     auto mix_forward = [&](int stage, auto src, auto dst) {
-        for (const MixLaunch& ml : mix_of(c, src, dst, no_tab))
+        for (const MixLaunch& ml : mix_of(c, src, dst, tab))
             go(stage, [&] { return mw::launch_contract_forward_mix(*plans.at(ml.L), ml.M, ml.G, ml.M.ns, st); });
     };
     // FP64 chunks hold one band-limit
@@ -644,9 +644,6 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");
     const bool may_alloc = !capturing(st);
-    // spin tables: every FP64 contraction reads its spin row from one; the mixed
-    // inverses start their spin rows from them
-    const bool need_spin = precision == MW_FP64 || op == Op::Inverse || op == Op::ForwardAdjoint;
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceState& d = g_dev[dev];
     const std::vector<Chunk> chunks = make_chunks(L, spin, reality, batch, precision);
@@ -655,7 +652,7 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     std::vector<ChunkPlans> plans(chunks.size());
     std::vector<ChunkSpins> spins(chunks.size());
     for (size_t i = 0; i < chunks.size(); ++i)
-        if ((rc = resolve_chunk(d, chunks[i], need_spin, may_alloc, plans[i], spins[i]))) return rc;
+        if ((rc = resolve_chunk(d, chunks[i], true, may_alloc, plans[i], spins[i]))) return rc;
     const int Lws = batch_lmax(L, batch);
     const size_t need = call_ws(chunks, Lws);
     void* ws = nullptr;
@@ -772,8 +769,8 @@ int autotune(DeviceState& d, const int32_t* L, const int32_t* spin, const int32_
         }
         c0.s = c0.spins[0];
         ChunkPlans plans;
-        ChunkSpins none;
-        if ((rc = resolve_chunk(d, c0, false, true, plans, none))) break;
+        ChunkSpins tabs;   // the timed launches read the same spin tables as a call
+        if ((rc = resolve_chunk(d, c0, true, true, plans, tabs))) break;
         const int gmax = std::min(pow2_ceil(n), mw::mix_group_max());
         const int nt = (int)c0.maps.size();
         void* ws = nullptr;
@@ -790,7 +787,10 @@ int autotune(DeviceState& d, const int32_t* L, const int32_t* spin, const int32_
             const std::vector<MixLaunch> ls =
                 mix_of(c, [&](int k) { return (void*)slot(ws, Lws, Lc, k).W1; },
                        [&](int k) { return (void*)slot(ws, Lws, Lc, k).W0; },
-                       [](int, int) -> const SpinTable* { return nullptr; });
+                       [&](int Lt, int as) -> const SpinTable* {
+                           auto it = tabs.find(std::make_pair(Lt, as));
+                           return it == tabs.end() ? nullptr : it->second;
+                       });
             double t = 1e30;   // the fastest of four timed repetitions (after one warm-up)
             for (int rep = 0; rep < 5 && !rc; ++rep) {
                 (void)hipEventRecord(e0, nullptr);
@@ -841,7 +841,7 @@ int mw_forward_noalloc(const int32_t* L, const int32_t* spin, const int32_t* rea
     std::vector<ChunkPlans> plans(chunks.size());
     std::vector<ChunkSpins> tabs(chunks.size());
     for (size_t i = 0; i < chunks.size(); ++i)
-        if ((rc = resolve_chunk(d, chunks[i], precision == MW_FP64, false, plans[i], tabs[i])))
+        if ((rc = resolve_chunk(d, chunks[i], true, false, plans[i], tabs[i])))
             return fail(MW_ENOMEM, "mw_forward_noalloc: a plan or spin table of this call is not prepared (call "
                                    "mw_prepare first)");
     // the chunks run one after another on the caller's stream, all in the one

@@ -1492,27 +1492,60 @@ __device__ __forceinline__ void win_store(float* __restrict__ win, const fv2* v,
 }
 
 // Maps of a group take the products of their own spin row: sj[b] in [0, NS).
-template <bool EXT, bool INJ, int G, int NS>
+// SPT: the spin rows' values of the pair (rows 2k+1, 2k) come from the spin
+// tables' transposed rows (sv.v[j] = (row 2k+1, row 2k)), not chains.
+template <int NS>
+struct SvPairF { double2 v[NS]; };
+
+template <bool SPT, int NS>
+__device__ __forceinline__ void fwd_mix_load_sv(SvPairF<NS>& sv, const double* const (&svl)[NS], int L, int k)
+{
+    if constexpr (SPT) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j)
+            sv.v[j] = make_double2(svl[j][(size_t)(2 * k + 1) * L], svl[j][(size_t)(2 * k) * L]);
+    }
+}
+
+template <bool EXT, int NS>
+__device__ __forceinline__ double fwd_chain_value(const FwdLane<2, EXT, NS>& st, int c)
+{
+    double d = st.dc[c];
+    if (EXT) d = (st.k[c] == 0) ? d : 0.0;
+    return d;
+}
+
+template <bool EXT, bool INJ, int G, int NS, bool SPT>
 __device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT, NS>& st, v4f (&acc)[2][G], int k, int l, int mb,
                                              const SpinSet<NS>& as, const MixMaps& maps,
                                              const float* __restrict__ win, int comp, const FwdR& r,
-                                             bool& anyscaled)
+                                             const SvPairF<NS>& sv, bool& anyscaled)
 {
     float k1[2][NS], k0[2][NS];
-    fwd_inject<2, EXT, INJ, NS>(st, 2 * k + 1, l, anyscaled);
+    fwd_inject<2, EXT, INJ, NS, SPT>(st, 2 * k + 1, l, anyscaled);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
-        k1[0][j] = (float)fwd_product<2, EXT, NS>(st, 0, j);
-        k1[1][j] = (float)fwd_product<2, EXT, NS>(st, 1, j);
+        if constexpr (SPT) {
+            k1[0][j] = (float)(fwd_chain_value<EXT, NS>(st, 0) * sv.v[j].x);
+            k1[1][j] = (float)(fwd_chain_value<EXT, NS>(st, 1) * sv.v[j].x);
+        } else {
+            k1[0][j] = (float)fwd_product<2, EXT, NS>(st, 0, j);
+            k1[1][j] = (float)fwd_product<2, EXT, NS>(st, 1, j);
+        }
     }
-    fwd_advance<2, EXT, NS>(st, mb, as, r.hi.y * r.lo.x, anyscaled);
-    fwd_inject<2, EXT, INJ, NS>(st, 2 * k, l, anyscaled);
+    fwd_advance<2, EXT, NS, SPT>(st, mb, as, r.hi.y * r.lo.x, anyscaled);
+    fwd_inject<2, EXT, INJ, NS, SPT>(st, 2 * k, l, anyscaled);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
-        k0[0][j] = (float)fwd_product<2, EXT, NS>(st, 0, j);
-        k0[1][j] = (float)fwd_product<2, EXT, NS>(st, 1, j);
+        if constexpr (SPT) {
+            k0[0][j] = (float)(fwd_chain_value<EXT, NS>(st, 0) * sv.v[j].y);
+            k0[1][j] = (float)(fwd_chain_value<EXT, NS>(st, 1) * sv.v[j].y);
+        } else {
+            k0[0][j] = (float)fwd_product<2, EXT, NS>(st, 0, j);
+            k0[1][j] = (float)fwd_product<2, EXT, NS>(st, 1, j);
+        }
     }
-    fwd_advance<2, EXT, NS>(st, mb, as, r.hi.x * r.lo.y, anyscaled);
+    fwd_advance<2, EXT, NS, SPT>(st, mb, as, r.hi.x * r.lo.y, anyscaled);
     const int off = 2 * k - WIN * (k / (WIN / 2));   // n = 2k within its window
 #pragma unroll
     for (int b = 0; b < G; ++b) {
@@ -1531,15 +1564,17 @@ __device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT, NS>& st, v4f (&acc)
 // window q-1 requested; the pairs of a window then run two at a time with the
 // 1/sqrt factors alternating between the A and B register sets (A holds pair k
 // on entry and on return).
-template <bool EXT, bool INJ, int G, int NS>
+template <bool EXT, bool INJ, int G, int NS, bool SPT>
 __device__ __forceinline__ void fwd_mix_run(FwdLane<2, EXT, NS>& st, v4f (&acc)[2][G], const FwdSeg& g, int& k, int kto,
                                             int l, int le, int mb, const SpinSet<NS>& as, const double* __restrict__ Rt,
-                                            float* __restrict__ win, const MixMaps& maps, int lane, FwdWin<G>& nxt,
-                                            FwdR& rA, bool& anyscaled)
+                                            const double* const (&svl)[NS], int L, float* __restrict__ win,
+                                            const MixMaps& maps, int lane, FwdWin<G>& nxt, FwdR& rA, SvPairF<NS>& sA,
+                                            bool& anyscaled)
 {
     constexpr int PW = WIN / 2;   // pairs per window
     const int comp = lane & 3;
     FwdR rB;
+    SvPairF<NS> sB;
     while (k >= kto) {
         if (k == g.ktop || (k % PW) == PW - 1) {       // entering window k / PW
             win_store<2 * G>(win, nxt.v, lane);
@@ -1548,33 +1583,40 @@ __device__ __forceinline__ void fwd_mix_run(FwdLane<2, EXT, NS>& st, v4f (&acc)[
         const int kw = max(kto, (k / PW) * PW);        // lowest pair of this window in range
         for (; k > kw; k -= 2) {
             rB = fwd_load_r(Rt, le, max(k - 1, 0));
-            fwd_mix_pair<EXT, INJ, G, NS>(st, acc, k, l, mb, as, maps, win, comp, rA, anyscaled);
+            fwd_mix_load_sv<SPT>(sB, svl, L, max(k - 1, 0));
+            fwd_mix_pair<EXT, INJ, G, NS, SPT>(st, acc, k, l, mb, as, maps, win, comp, rA, sA, anyscaled);
             rA = fwd_load_r(Rt, le, max(k - 2, 0));
-            fwd_mix_pair<EXT, INJ, G, NS>(st, acc, k - 1, l, mb, as, maps, win, comp, rB, anyscaled);
+            fwd_mix_load_sv<SPT>(sA, svl, L, max(k - 2, 0));
+            fwd_mix_pair<EXT, INJ, G, NS, SPT>(st, acc, k - 1, l, mb, as, maps, win, comp, rB, sB, anyscaled);
         }
         if (k == kw) {                                 // odd pair left in the window
             rB = fwd_load_r(Rt, le, max(k - 1, 0));
-            fwd_mix_pair<EXT, INJ, G, NS>(st, acc, k, l, mb, as, maps, win, comp, rA, anyscaled);
+            fwd_mix_load_sv<SPT>(sB, svl, L, max(k - 1, 0));
+            fwd_mix_pair<EXT, INJ, G, NS, SPT>(st, acc, k, l, mb, as, maps, win, comp, rA, sA, anyscaled);
             rA = rB;
+            sA = sB;
             --k;
         }
     }
 }
 
-template <bool EXT, int G, int NS>
+template <bool EXT, int G, int NS, bool SPT>
 __device__ __forceinline__ void fwd_mix_segment(FwdLane<2, EXT, NS>& st, v4f (&acc)[2][G], const FwdSeg& g, int l,
                                                 int le, int mb, const SpinSet<NS>& as, const double* __restrict__ Rt,
-                                                float* __restrict__ win, const MixMaps& maps, int lane,
-                                                bool& anyscaled)
+                                                const double* const (&svl)[NS], int L, float* __restrict__ win,
+                                                const MixMaps& maps, int lane, bool& anyscaled)
 {
     constexpr int PW = WIN / 2;
     FwdWin<G> nxt;
     fwd_win_load<G>(nxt, maps, mb, g.ktop / PW, lane);
     FwdR rA = fwd_load_r(Rt, le, g.ktop);
+    SvPairF<NS> sA;
+    fwd_mix_load_sv<SPT>(sA, svl, L, g.ktop);
     int k = g.ktop;
-    fwd_mix_run<EXT, true, G, NS>(st, acc, g, k, max(g.kA, g.klo), l, le, mb, as, Rt, win, maps, lane, nxt, rA,
-                                  anyscaled);   // pairs with lane starts
-    fwd_mix_run<EXT, false, G, NS>(st, acc, g, k, g.klo, l, le, mb, as, Rt, win, maps, lane, nxt, rA, anyscaled);
+    fwd_mix_run<EXT, true, G, NS, SPT>(st, acc, g, k, max(g.kA, g.klo), l, le, mb, as, Rt, svl, L, win, maps, lane,
+                                       nxt, rA, sA, anyscaled);   // pairs with lane starts
+    fwd_mix_run<EXT, false, G, NS, SPT>(st, acc, g, k, g.klo, l, le, mb, as, Rt, svl, L, win, maps, lane, nxt, rA, sA,
+                                        anyscaled);
 }
 
 // Forward contraction of a group of up to G maps with at most NS different |s|
@@ -1593,7 +1635,7 @@ __host__ __device__ constexpr int fwdm_slot_floats(int G)
 // Wave budgets as for the mixed inverse: five waves per SIMD for one map (96
 // VGPRs, the accumulators in ordinary VGPRs), four for two, three for four;
 // with a second spin row one wave less for one or two maps (no spills).
-template <bool EXT, int G, int NS>
+template <bool EXT, int G, int NS, bool SPT>
 __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(
     G == 8 ? 2 : (NS == 1 ? (G == 1 ? 5 : (G == 4 ? 3 : 4)) : (G == 1 ? 4 : 3))))) void k_contract_forward_mix(
     MixBatch MB, const double* __restrict__ Rtg, const double* __restrict__ edge, const int* __restrict__ edgek,
@@ -1630,7 +1672,16 @@ __global__ __launch_bounds__(64 * SEG_MAX) __attribute__((amdgpu_waves_per_eu(
         bool anyscaled;
         const FwdSeg g =
             fwd_setup<2, EXT, NS>(st, anyscaled, w, nseg, lo, hi, l0, mb, l, L, as, ckfg, edge, edgek, ckf, ckfk);
-        if (g.active) fwd_mix_segment<EXT, G, NS>(st, acc, g, l, le, mb, as, Rt, region, maps, lane, anyscaled);
+        const double* svl[NS];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) svl[j] = SPT ? MB.ssvf[j] + le : nullptr;
+        if (SPT) {   // the spin rows' values come from the tables' transposed rows, not chains
+#pragma unroll
+            for (int j = 0; j < NS; ++j) st.ks[j] = 0;
+            if (EXT) anyscaled = __any(st.k[0] > 0 || st.k[1] > 0);
+        }
+        if (g.active)
+            fwd_mix_segment<EXT, G, NS, SPT>(st, acc, g, l, le, mb, as, Rt, svl, L, region, maps, lane, anyscaled);
     }
 
     if (bar) {
@@ -2112,15 +2163,25 @@ hipError_t mix_attr(K kernel, size_t bytes)
     return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+template <bool EXT, int G, int NS, bool SPT>
+hipError_t fwd_mix_go2(const Plan& p, const MixBatch& maps, hipStream_t st)
+{
+    const size_t lds = mix_lds_forward(G);
+    hipError_t e = mix_attr(k_contract_forward_mix<EXT, G, NS, SPT>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_contract_forward_mix<EXT, G, NS, SPT>), dim3(p.nworkf4, maps.ng), dim3(64 * SEG_MAX), lds,
+                       st, maps, p.rtab, p.edge, p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, p.ckfg);
+    return hipGetLastError();
+}
+
+// From L = FWD_SPT_MIN_L (the launch carrying its spin tables) the spin rows'
+// values come from the tables, as in the FP64 forward.
 template <bool EXT, int G, int NS>
 hipError_t fwd_mix_go(const Plan& p, const MixBatch& maps, hipStream_t st)
 {
-    const size_t lds = mix_lds_forward(G);
-    hipError_t e = mix_attr(k_contract_forward_mix<EXT, G, NS>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_contract_forward_mix<EXT, G, NS>), dim3(p.nworkf4, maps.ng), dim3(64 * SEG_MAX), lds, st,
-                       maps, p.rtab, p.edge, p.edgek, p.cl, p.ckf, p.ckfk, p.workf4, p.L, p.ckfg);
-    return hipGetLastError();
+    bool spt = p.L >= FWD_SPT_MIN_L;
+    for (int j = 0; j < NS; ++j) spt = spt && maps.ssvf[j] != nullptr;
+    return spt ? fwd_mix_go2<EXT, G, NS, true>(p, maps, st) : fwd_mix_go2<EXT, G, NS, false>(p, maps, st);
 }
 
 template <bool EXT, int G, int NS>

@@ -168,6 +168,7 @@ struct MixBatch {
     const double* stab[NSMAX];
     const int* stabk[NSMAX];
     const double* ssv[NSMAX];   // inverse: the scaled spin rows of those tables (SpinTable::sval)
+    const double* ssvf[NSMAX];  // forward: their transposed rows (SpinTable::svalf), or null
 };
 __host__ __device__ inline int mix_spin(const MixBatch& B, const MixMaps& m, int b)
 {
