@@ -534,10 +534,14 @@ hipError_t run_chunk(Op op, const Chunk& c, const ChunkPlans& plans, const Chunk
         // coefficients as given (no real-map expansion), then the theta and phi
         // adjoints; with real = 1 it stores Re(A^H y).
         const bool inv = op == Op::Inverse;
+        // A lone real map runs the FP64 inverse contraction in either precision:
+        // its triangle kernel (one chain per pair (m, n), (n, m), orders m >= 0
+        // only) has no mixed form, and a group of one shares no chain.
+        const bool mixc = mix && !(inv && real && c.maps.size() == 1);
         per_l(8, user_in, w2, [&](const Plan& p, const mw::Batch& B) {
-            return mw::launch_inverse_stream(p, inv ? real : 0, B, mix, st);
+            return mw::launch_inverse_stream(p, inv ? real : 0, B, mixc, st);
         });
-        if (mix) {
+        if (mixc) {
             for (const MixLaunch& ml : mix_of(c, w2, w0, tab)) {
                 const SpinTable* wsp = tab(ml.L, ml.asmax);
                 if (!wsp) { e = hipErrorInvalidValue; break; }

@@ -96,8 +96,15 @@ def test_mixed_real_maps(orc, tc, mw):
     xref = np.real(orc.inverse(flm, L, 0))
     x = host(tc, mw.inverse(dev(tc, flm), L, 0, reality=1, precision=FP32C))
     assert x.dtype == np.float64 and rel(x, xref) < TOL
+    # a lone real map's inverse contraction is the FP64 one in either precision
+    assert np.array_equal(x, host(tc, mw.inverse(dev(tc, flm), L, 0, reality=1)))
     f = host(tc, mw.forward(dev(tc, xref), L, 0, reality=1, precision=FP32C))
     assert rel(f, orc.forward(xref.astype(np.complex128), L, 0)) < TOL
+    # two real maps run the mixed inverse kernel (a group shares the chains)
+    flm2 = mwsynth.make_real_symmetric(mwsynth.flm_gaussian(L, 0, seed=13001), L)
+    xs = mw.inverse_batch([dev(tc, flm), dev(tc, flm2)], [L, L], [0, 0], [1, 1], precision=FP32C)
+    assert rel(host(tc, xs[0]), xref) < TOL
+    assert rel(host(tc, xs[1]), np.real(orc.inverse(flm2, L, 0))) < TOL
 
 
 def test_mixed_batch_of_uneven_maps(orc, tc, mw):
@@ -181,7 +188,8 @@ def test_mixed_groups_at_batch_sizes(orc, tc, mw, L, s, real):
     """Four maps of one class in one call (one group of four sharing the chains,
     several chain segments restarted from checkpoint planes at these L): two of
     them against the oracle on sampled orders, all four bitwise against single
-    calls (per-map arithmetic does not depend on the group)."""
+    calls (per-map arithmetic does not depend on the group; a real map's inverse
+    goes in with a copy of itself, since alone it takes the FP64 contraction)."""
     print("mixed groups L=%d s=%d real=%d" % (L, s, real), flush=True)
     n = 4
     flm = []
@@ -192,7 +200,11 @@ def test_mixed_groups_at_batch_sizes(orc, tc, mw, L, s, real):
     maps_h = [host(tc, t) for t in maps]
     orders = [0, 1, 7, L // 2, L - 1] + ([] if real else [-1, -(L // 3), -(L - 1)])
     for i in range(n):
-        single = host(tc, mw.inverse(dev(tc, flm[i]), L, s, real, precision=FP32C))
+        if real:
+            pair = mw.inverse_batch([dev(tc, flm[i])] * 2, [L] * 2, [s] * 2, [real] * 2, precision=FP32C)
+            single = host(tc, pair[0])
+        else:
+            single = host(tc, mw.inverse(dev(tc, flm[i]), L, s, real, precision=FP32C))
         assert np.array_equal(maps_h[i], single), i
     for i in range(2):
         e = rel(_ring_orders(maps_h[i], L, orders), orc.inverse_orders(flm[i], L, s, orders))
@@ -214,14 +226,20 @@ def test_mixed_groups_at_batch_sizes(orc, tc, mw, L, s, real):
 def test_mixed_inverse_large_l_sampled(orc, tc, mw):
     """L = 2048 real scalar map (C_l = (l+1)^-2): the exponent-extended mixed
     inverse on sampled orders of its rings' phi-spectra against the oracle, and
-    the per-degree error of the mixed round trip against the input."""
+    the per-degree error of the mixed round trip against the input. The map
+    goes in twice in one call, so that the mixed inverse kernel runs (a lone
+    real map takes the FP64 one)."""
     w = mwsynth.workload_real_l2048()
     L, flm = w["L"], w["flm"]
-    x = host(tc, mw.inverse(dev(tc, flm), L, 0, reality=1, precision=FP32C))
+    xs = mw.inverse_batch([dev(tc, flm), dev(tc, flm)], [L, L], [0, 0], [1, 1], precision=FP32C)
     orders = [0, 1, 2, 700, 1024, 1500, 2046, 2047]
-    e = rel(_ring_orders(x, L, orders), orc.inverse_orders(flm, L, 0, orders))
-    print("FP32C L=2048 real inverse, sampled orders: %.3e" % e, flush=True)
-    assert e < TOL
+    ref = orc.inverse_orders(flm, L, 0, orders)
+    for k in range(2):
+        e = rel(_ring_orders(host(tc, xs[k]), L, orders), ref)
+        print("FP32C L=2048 real inverse (map %d of a pair), sampled orders: %.3e" % (k, e), flush=True)
+        assert e < TOL
+    x = host(tc, xs[0])
+    del xs
     back = host(tc, mw.forward(dev(tc, x), L, 0, reality=1, precision=FP32C))
     e_rt = rel(back, flm)
     e_deg = rel_per_degree(back, flm, L)
