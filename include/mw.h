@@ -239,11 +239,14 @@ int mw_set_workspace(void* dptr, size_t bytes, void* stream);
  *
  * Batching: an FP64 call runs its maps in chunks of equal (L, spin, reality); an
  * MW_FP32C call in chunks of equal reality whose maps share the Wigner
- * recursions in groups of up to four maps with at most two different |s| (Sec.
- * V's remark that the Wigner values need not be recomputed): groups of one
- * band-limit, except that the maps of a band-limit with fewer than four maps in
- * the call join the last group of a larger one (its recursions run to its
- * largest band-limit; each map masks the degrees beyond its own).  Each stage
+ * recursions in groups of up to eight maps (the size tuned here per band-limit
+ * and reality) with at most two different |s| (Sec. V's remark that the Wigner
+ * values need not be recomputed): groups of one band-limit, except that the
+ * maps of a band-limit with fewer maps in the call than the largest group join
+ * the last group of a larger one (its recursions run to its largest
+ * band-limit; each map masks the degrees beyond its own).  A real map alone in
+ * its chunk takes the FP64 inverse contraction (its result is then the FP64
+ * one, within the MW_FP32C bound a fortiori).  Each stage
  * of a chunk is one kernel launch per band-limit over its maps (the
  * contractions: one per group band-limit and set of spin rows).  Several chunks
  * alternate over two internal streams (created here or on the first such call)

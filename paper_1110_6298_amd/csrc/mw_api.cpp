@@ -471,7 +471,7 @@ using ChunkSpins = std::map<std::pair<int, int>, const SpinTable*>;
 // compact: maps in the compact storage of Sec. IV-C ((L-1)(2L-1)+1 samples, the
 // south pole once), expanded or contracted by the phi stages.
 // plans: the plan of every band-limit of the chunk; sps: the spin tables of its
-// (band-limits, |s|) (inverse and forward adjoint).
+// (band-limits, |s|).
 hipError_t run_chunk(Op op, const Chunk& c, const ChunkPlans& plans, const ChunkSpins& sps, int precision,
                      void* const* ptrs, void* ws, int Lws, hipStream_t st, bool prof = true, bool compact = false)
 {
@@ -618,17 +618,16 @@ size_t chunks_ws(const std::vector<Chunk>& ch, int Lws)
 // Workspace of a call: one half per chunk stream when it has several chunks.
 size_t call_ws(const std::vector<Chunk>& ch, int Lws) { return (ch.size() > 1 ? 2 : 1) * chunks_ws(ch, Lws); }
 
-// The plans of a chunk's band-limits and, with spins, the spin tables of every
-// (band-limit, |s|) of the chunk (a mixed group's chains run to its largest
-// band-limit with the rows of all its spins).
-int resolve_chunk(DeviceState& d, const Chunk& c, bool spins, bool may_alloc, ChunkPlans& plans, ChunkSpins& tabs)
+// The plans of a chunk's band-limits and the spin tables of every (band-limit,
+// |s|) of the chunk (a mixed group's chains run to its largest band-limit with
+// the rows of all its spins).
+int resolve_chunk(DeviceState& d, const Chunk& c, bool may_alloc, ChunkPlans& plans, ChunkSpins& tabs)
 {
     int rc;
     for (int Lc : chunk_ls(c)) {
         const Plan* p = nullptr;
         if ((rc = get_plan(d, Lc, may_alloc, &p))) return rc;
         plans[Lc] = p;
-        if (!spins) continue;
         for (int as : chunk_abs_spins(c)) {
             if (as >= Lc) continue;   // no map of band-limit Lc has this spin (|s| < L)
             const SpinTable* t = nullptr;
@@ -656,7 +655,7 @@ int run(Op op, const int32_t* L, const int32_t* spin, const int32_t* reality, in
     std::vector<ChunkPlans> plans(chunks.size());
     std::vector<ChunkSpins> spins(chunks.size());
     for (size_t i = 0; i < chunks.size(); ++i)
-        if ((rc = resolve_chunk(d, chunks[i], true, may_alloc, plans[i], spins[i]))) return rc;
+        if ((rc = resolve_chunk(d, chunks[i], may_alloc, plans[i], spins[i]))) return rc;
     const int Lws = batch_lmax(L, batch);
     const size_t need = call_ws(chunks, Lws);
     void* ws = nullptr;
@@ -774,7 +773,7 @@ int autotune(DeviceState& d, const int32_t* L, const int32_t* spin, const int32_
         c0.s = c0.spins[0];
         ChunkPlans plans;
         ChunkSpins tabs;   // the timed launches read the same spin tables as a call
-        if ((rc = resolve_chunk(d, c0, true, true, plans, tabs))) break;
+        if ((rc = resolve_chunk(d, c0, true, plans, tabs))) break;
         const int gmax = std::min(pow2_ceil(n), mw::mix_group_max());
         const int nt = (int)c0.maps.size();
         void* ws = nullptr;
@@ -845,7 +844,7 @@ int mw_forward_noalloc(const int32_t* L, const int32_t* spin, const int32_t* rea
     std::vector<ChunkPlans> plans(chunks.size());
     std::vector<ChunkSpins> tabs(chunks.size());
     for (size_t i = 0; i < chunks.size(); ++i)
-        if ((rc = resolve_chunk(d, chunks[i], true, false, plans[i], tabs[i])))
+        if ((rc = resolve_chunk(d, chunks[i], false, plans[i], tabs[i])))
             return fail(MW_ENOMEM, "mw_forward_noalloc: a plan or spin table of this call is not prepared (call "
                                    "mw_prepare first)");
     // the chunks run one after another on the caller's stream, all in the one
@@ -1030,7 +1029,7 @@ int mw_prepare(const int32_t* L, const int32_t* spin, const int32_t* reality, in
     for (const Chunk& c : chunks) {
         ChunkPlans plans;
         ChunkSpins tabs;
-        if ((rc = resolve_chunk(d, c, true, true, plans, tabs))) return rc;
+        if ((rc = resolve_chunk(d, c, true, plans, tabs))) return rc;
     }
     if (precision != MW_FP64 && (rc = autotune(d, L, spin, reality, batch))) return rc;
     void* ws = nullptr;
