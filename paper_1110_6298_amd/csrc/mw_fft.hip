@@ -311,6 +311,15 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const Fft
         const int NB = N >> lr;
         double2 u[RB];
         const int k = i & (p - 1);
+        // with no final radix-2/4/8 pass, the last main pass applies post, its
+        // factors read ahead of the pass (as in last_pass)
+        const bool fold_post = plain && post && r == 0 && s == np - 1;
+        double2 pv[RB];
+        if (RB == 8 && fold_post && i < NB) {
+            const int j = ((i - k) << lr) + k;
+#pragma unroll
+            for (int t = 0; t < RB; ++t) pv[t] = post[j + t * p];
+        }
         if (i < NB) {
             if constexpr (reg_ld) {
                 if (s == 0) {
@@ -341,6 +350,9 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const Fft
             if (!plain && r == 0 && s == np - 1) {   // the last pass: outputs through st
 #pragma unroll
                 for (int t = 0; t < RB; ++t) st(j + t * p, u[t]);
+            } else if (fold_post) {
+#pragma unroll
+                for (int t = 0; t < RB; ++t) x[Pr<RB>(j + t * p)] = cmul(u[t], RB == 8 ? pv[t] : post[j + t * p]);
             } else {
 #pragma unroll
                 for (int t = 0; t < RB; ++t) x[Pr<RB>(j + t * p)] = u[t];
@@ -353,14 +365,6 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const Fft
     else if (r == 2) last_pass<DIR, 4, RB>(x, N, p, T.wl, post, st);
     else if constexpr (RB == 16) {
         if (r == 3) last_pass<DIR, 8, RB>(x, N, p, T.wl, post, st);
-        else if (plain && post) {
-            for (int j = threadIdx.x; j < N; j += blockDim.x) x[Pr<RB>(j)] = cmul(x[Pr<RB>(j)], post[j]);
-            __syncthreads();
-        }
-    }
-    else if (plain && post) {
-        for (int j = threadIdx.x; j < N; j += blockDim.x) x[Pr<RB>(j)] = cmul(x[Pr<RB>(j)], post[j]);
-        __syncthreads();
     }
 }
 
