@@ -65,6 +65,36 @@ __device__ __forceinline__ void staged_loop(int n, Ld ld, Use use)
     }
 }
 
+// The same loop with its global values read ahead: read_ahead<Q>(n, ld) issues
+// the loads ld(j) of every j = threadIdx.x + q*blockDim.x < n (q < Q, which must
+// cover n) at once, early in a kernel (before the transforms), and
+// use_ahead<Q>(n, a, use) later calls use(j, value), so that their latency
+// overlaps the transforms instead of following the last barrier.
+template <int Q, class V>
+struct Ahead { V v[Q]; };
+
+template <int Q, class Ld>
+__device__ __forceinline__ auto read_ahead(int n, Ld ld)
+{
+    Ahead<Q, decltype(ld(0))> a;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = threadIdx.x + q * blockDim.x;
+        if (j < n) a.v[q] = ld(j);
+    }
+    return a;
+}
+
+template <int Q, class V, class Use>
+__device__ __forceinline__ void use_ahead(int n, const Ahead<Q, V>& a, Use use)
+{
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = threadIdx.x + q * blockDim.x;
+        if (j < n) use(j, a.v[q]);
+    }
+}
+
 // In-place DFT of 4 values: a_k <- sum_j a_j w^{jk}, w = exp(DIR 2 pi i/4).
 template <int DIR>
 __device__ __forceinline__ void bf4(double2& a0, double2& a1, double2& a2, double2& a3)
@@ -496,6 +526,13 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc,
     const int s = B.s[blockIdx.y];
     // twiddle bases of all FFTs below, read before the first pass (it needs none)
     const FftTw<RB> T = plan_twiddles<RB, SP>(p);
+    // up to N2 = 1024: the output chirp factors read ahead (N1 < N2/2 =
+    // (RB/2) blockDim.x); measured neutral at N2 = 2048, and at 4096 their
+    // registers cost the workgroup its second slot on a compute unit
+    constexpr bool AH = RB == 8 && LOGN > 0 && LOGN <= 10;
+    constexpr int QA = AH ? RB / 2 : 1;
+    Ahead<QA, double2> ca;
+    if constexpr (AH) ca = read_ahead<QA>(N1, [&](int k) { return p.chirp[k]; });
     // the ring's samples, chirped and zero-padded, read by the first pass; the
     // outputs are stored from LDS in batches (written straight from the last pass,
     // the stride-L stores of G were measured slower)
@@ -506,12 +543,12 @@ __global__ __launch_bounds__(512) void k_phi_forward(Plan p, Batch B, double sc,
         if (pring) a = (pole == 1) ? cmul(a, spin_phase(s, j, N1)) : (j == 0 ? a : make_double2(0.0, 0.0));
         return cmul(a, p.chirp[j]);
     });
-    staged_loop(
-        N1, [&](int k) { return p.chirp[k]; },
-        [&](int k, double2 c) {
-            const int m = (k <= L - 1) ? k : k - N1;
-            G[(size_t)(m + L - 1) * L + t] = cscale(cmul(A[Pr<RB>(k)], c), sc);
-        });
+    auto out = [&](int k, double2 c) {
+        const int m = (k <= L - 1) ? k : k - N1;
+        G[(size_t)(m + L - 1) * L + t] = cscale(cmul(A[Pr<RB>(k)], c), sc);
+    };
+    if constexpr (AH) use_ahead<QA>(N1, ca, out);
+    else staged_loop(N1, [&](int k) { return p.chirp[k]; }, out);
 }
 
 // Forward phi stage of a real map for the rings t1 = 2c and t2 = 2c+1 together:
@@ -754,6 +791,8 @@ __global__ __launch_bounds__(512) void k_theta_forward_pair(Plan p, Batch B)
     const double2* __restrict__ Ga = G + (size_t)(ma + L - 1) * L;
     const double2* __restrict__ Gb = G + (size_t)(mb + L - 1) * L;
     const FftTw<RB> T = plan_twiddles<RB, false>(p);
+    // b's pole sample (used by the fold below), read before the transforms
+    const double2 P = hasb ? Gb[L - 1] : make_double2(0.0, 0.0);
     // the packed extended column, chirped and zero-padded
     auto ld = [&](int j) {
         if (j >= N1) return make_double2(0.0, 0.0);
@@ -782,9 +821,8 @@ __global__ __launch_bounds__(512) void k_theta_forward_pair(Plan p, Batch B)
     });
     block_fft<+1, RB>(A, N2, p.logN2, T, p.whate);
     block_fft<-1, RB>(A, N2, p.logN2, T);
-    // b's pole sample and the odd-weight term of H^b_0 (L >= 2: with L = 1 the
-    // only order is 0 and the pair has no b unless s is odd; then F_{+-1} = 0)
-    const double2 P = hasb ? Gb[L - 1] : make_double2(0.0, 0.0);
+    // the odd-weight term of H^b_0 (L >= 2: with L = 1 the only order is 0 and
+    // the pair has no b unless s is odd; then F_{+-1} = 0)
     const double2 b1 = (L >= 2) ? cscale(csub(f1[0], f1[1]), 0.5) : make_double2(0.0, 0.0);
     const double PI2 = 9.8696044010893586188;   // pi^2
     const double sgnL = (L & 1) ? -1.0 : 1.0;
@@ -861,6 +899,13 @@ __global__ __launch_bounds__(512) void k_theta_inverse_pair(Plan p, Batch B)
     const double2* __restrict__ Fa = F + (size_t)ia * L;
     const double2* __restrict__ Fb = F + (size_t)ib * L;
     const FftTw<RB> T = plan_twiddles<RB, false>(p);
+    // up to N2 = 2048 (radix 8, at most 256 threads): the output chirp factors
+    // read ahead (L <= N2/4 = (RB/4) blockDim.x)
+    constexpr bool AH = RB == 8 && LOGN > 0 && LOGN <= 11;
+    constexpr int QA = AH ? RB / 4 : 1;
+    auto chirps = [&](int t) { return Pair2{p.chirp[t], p.chirp[2 * L - 2 - t]}; };
+    Ahead<QA, Pair2> ca;
+    if constexpr (AH) ca = read_ahead<QA>(L, chirps);
     bluestein_core<RB>(A, p, T, [&](int j) {   // conj of the packed unfolded F times e^{-i m' pi/N1} chirp_j
         if (j >= N1) return make_double2(0.0, 0.0);
         const int mp = (j <= L - 1) ? j : j - N1;
@@ -870,19 +915,19 @@ __global__ __launch_bounds__(512) void k_theta_inverse_pair(Plan p, Batch B)
         if (hasb && n > 0) f = (mp < 0) ? csub(f, Fb[n]) : cadd(f, Fb[n]);
         return cmul(cconj(f), p.thwc[j]);
     });
-    staged_loop(
-        L, [&](int t) { return Pair2{p.chirp[t], p.chirp[2 * L - 2 - t]}; },
-        [&](int t, const Pair2& cp) {
-            const double2 x = cconj(cmul(A[Pr<RB>(t)], cp.a));
-            if (t == L - 1) {
-                if (hasa) Ft[(size_t)t * N1 + ia] = x;
-                if (hasb) Ft[(size_t)t * N1 + ib] = make_double2(0.0, 0.0);
-            } else {
-                const double2 y = cconj(cmul(A[Pr<RB>(2 * L - 2 - t)], cp.b));
-                if (hasa) Ft[(size_t)t * N1 + ia] = cscale(cadd(x, y), 0.5);
-                if (hasb) Ft[(size_t)t * N1 + ib] = cscale(csub(x, y), 0.5);
-            }
-        });
+    auto out = [&](int t, const Pair2& cp) {
+        const double2 x = cconj(cmul(A[Pr<RB>(t)], cp.a));
+        if (t == L - 1) {
+            if (hasa) Ft[(size_t)t * N1 + ia] = x;
+            if (hasb) Ft[(size_t)t * N1 + ib] = make_double2(0.0, 0.0);
+        } else {
+            const double2 y = cconj(cmul(A[Pr<RB>(2 * L - 2 - t)], cp.b));
+            if (hasa) Ft[(size_t)t * N1 + ia] = cscale(cadd(x, y), 0.5);
+            if (hasb) Ft[(size_t)t * N1 + ib] = cscale(csub(x, y), 0.5);
+        }
+    };
+    if constexpr (AH) use_ahead<QA>(L, ca, out);
+    else staged_loop(L, chirps, out);
 }
 
 // Theta step of the adjoint of the forward transform, for order m: the
