@@ -124,7 +124,10 @@ __device__ __forceinline__ void fwd_inject(FwdLane<MT, EXT, NS>& st, int n, int 
 
 // Recursion from step n to n-1 with ra = 1/sqrt(Q_n):
 //   D_{n-1} = -(2m D_n + a_{n+1} D_{n+1}) / a_n,  a_n = sqrt(Q_n); harmless at n = 0.
-template <int MT, bool EXT, int NS, bool SPT = false>
+// CHK: the exponent-extended state is checked (rescaled chains); once no lane of
+// the wave holds a scaled chain and none can start one (past the chain starts),
+// the steps run without the checks.
+template <int MT, bool EXT, int NS, bool SPT = false, bool CHK = EXT>
 __device__ __forceinline__ void fwd_advance(FwdLane<MT, EXT, NS>& st, int mb, const SpinSet<NS>& as, double ra,
                                             bool& anyscaled)
 {
@@ -148,7 +151,7 @@ __device__ __forceinline__ void fwd_advance(FwdLane<MT, EXT, NS>& st, int mb, co
     st.anext = an;
     st.q += st.dq;          // Q_{n-1} = Q_n + 2(n-1)
     st.dq -= 2.0;
-    if (EXT && anyscaled) {
+    if (CHK && anyscaled) {
         bool still = false;
 #pragma unroll
         for (int c = 0; c < MT; ++c) {
@@ -169,20 +172,20 @@ __device__ __forceinline__ void fwd_advance(FwdLane<MT, EXT, NS>& st, int mb, co
 }
 
 // Delta_{m_c,n} * Delta_{|s_j|,n} of the current step (0 while a chain is scaled).
-template <int MT, bool EXT, int NS>
+template <int MT, bool EXT, int NS, bool CHK = EXT>
 __device__ __forceinline__ double fwd_product(const FwdLane<MT, EXT, NS>& st, int c, int j = 0)
 {
     double seff = st.sc[j];
-    if (EXT) seff = (st.ks[j] == 0) ? seff : 0.0;
+    if (CHK) seff = (st.ks[j] == 0) ? seff : 0.0;
     double d = st.dc[c];
-    if (EXT) d = (st.k[c] == 0) ? d : 0.0;
+    if (CHK) d = (st.k[c] == 0) ? d : 0.0;
     return d * seff;
 }
 
 // One step n: contributions of D_{.,n} (h = the four doubles of H at n for
 // each chain), then the recursion to n-1.  The spin row's value Delta^l_{|s|,n}
 // at this step is sv, read from the spin table's transposed rows.
-template <int MT, bool EXT, int PAR, bool INJ, bool RL, bool SPT>
+template <int MT, bool EXT, int PAR, bool INJ, bool RL, bool SPT, bool CHK = EXT>
 __device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int mb, int as,
                                          const Rec8 (&h)[MT], double ra, double sv, bool& anyscaled)
 {
@@ -193,10 +196,10 @@ __device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int
         double pr;
         if constexpr (SPT) {
             double d = st.dc[c];
-            if (EXT) d = (st.k[c] == 0) ? d : 0.0;
+            if (CHK) d = (st.k[c] == 0) ? d : 0.0;
             pr = d * sv;
         } else {
-            pr = fwd_product<MT, EXT, 1>(st, c);
+            pr = fwd_product<MT, EXT, 1, CHK>(st, c);
         }
         st.ap[c][PAR].x = fma(pr, hc[0], st.ap[c][PAR].x);
         st.ap[c][PAR].y = fma(pr, hc[1], st.ap[c][PAR].y);
@@ -205,7 +208,7 @@ __device__ __forceinline__ void fwd_step(FwdLane<MT, EXT>& st, int n, int l, int
             st.am[c][PAR].y = fma(pr, hc[3], st.am[c][PAR].y);
         }
     }
-    fwd_advance<MT, EXT, 1, SPT>(st, mb, SpinSet<1>{{as}}, ra, anyscaled);
+    fwd_advance<MT, EXT, 1, SPT, CHK>(st, mb, SpinSet<1>{{as}}, ra, anyscaled);
 }
 
 template <int MT>
@@ -232,13 +235,13 @@ __device__ __forceinline__ FwdR fwd_load_r(const double* __restrict__ Rt, int le
 }
 
 // The spin values of the pair's steps: sv.x at n = 2k+1, sv.y at n = 2k.
-template <int MT, bool EXT, bool INJ, bool RL, bool SPT>
+template <int MT, bool EXT, bool INJ, bool RL, bool SPT, bool CHK = EXT>
 __device__ __forceinline__ void fwd_pair(FwdLane<MT, EXT>& st, int k, int l, int mb, int as,
                                          const Rec8 (&h)[MT], const FwdR& r, const double2& sv, bool& anyscaled)
 {
     // n = 2k+1: 1/sqrt(l+n) = hi.y, 1/sqrt(l-n+1) = lo.x;  n = 2k: hi.x, lo.y
-    fwd_step<MT, EXT, 1, INJ, RL, SPT>(st, 2 * k + 1, l, mb, as, h, r.hi.y * r.lo.x, sv.x, anyscaled);
-    fwd_step<MT, EXT, 0, INJ, RL, SPT>(st, 2 * k, l, mb, as, h, r.hi.x * r.lo.y, sv.y, anyscaled);
+    fwd_step<MT, EXT, 1, INJ, RL, SPT, CHK>(st, 2 * k + 1, l, mb, as, h, r.hi.y * r.lo.x, sv.x, anyscaled);
+    fwd_step<MT, EXT, 0, INJ, RL, SPT, CHK>(st, 2 * k, l, mb, as, h, r.hi.x * r.lo.y, sv.y, anyscaled);
 }
 
 // SPT: the spin values Delta^l_{|s|,n} of the lane for the pair k (rows 2k+1,
@@ -260,14 +263,15 @@ __device__ __forceinline__ void fwd_phase(FwdLane<MT, EXT>& st, int kfrom, int k
                                           Rec8 (&hB)[MT], FwdR& rA, FwdR& rB, double2& sA, double2& sB,
                                           bool& anyscaled)
 {
-    for (int k = kfrom; k > kto; k -= 2) {
+    auto body = [&](int k, auto chk) {
+        constexpr bool C = decltype(chk)::value;
         wait_scalar(hA[0].v[0]);
         __builtin_amdgcn_sched_barrier(0);
         fwd_load_h<MT>(hB, Hp, mb, Lp, L, k - 1);
         rB = fwd_load_r(Rt, le, k - 1);
         sB = fwd_load_sv<SPT>(svl, L, k - 1);
         __builtin_amdgcn_sched_barrier(0);
-        fwd_pair<MT, EXT, INJ, RL, SPT>(st, k, l, mb, as, hA, rA, sA, anyscaled);
+        fwd_pair<MT, EXT, INJ, RL, SPT, C>(st, k, l, mb, as, hA, rA, sA, anyscaled);
         wait_scalar(hB[0].v[0]);
         __builtin_amdgcn_sched_barrier(0);
         const int k2 = max(k - 2, 0);
@@ -275,7 +279,16 @@ __device__ __forceinline__ void fwd_phase(FwdLane<MT, EXT>& st, int kfrom, int k
         rA = fwd_load_r(Rt, le, k2);
         sA = fwd_load_sv<SPT>(svl, L, k2);
         __builtin_amdgcn_sched_barrier(0);
-        fwd_pair<MT, EXT, INJ, RL, SPT>(st, k - 1, l, mb, as, hB, rB, sB, anyscaled);
+        fwd_pair<MT, EXT, INJ, RL, SPT, C>(st, k - 1, l, mb, as, hB, rB, sB, anyscaled);
+    };
+    int k = kfrom;
+    if constexpr (EXT && !INJ) {
+        // past the chain starts no chain becomes scaled again: once none is
+        // (anyscaled is uniform over the wave), the rest runs unchecked
+        for (; k > kto && anyscaled; k -= 2) body(k, std::true_type());
+        for (; k > kto; k -= 2) body(k, std::false_type());
+    } else {
+        for (; k > kto; k -= 2) body(k, std::integral_constant<bool, EXT>());
     }
 }
 
@@ -778,7 +791,9 @@ __device__ __forceinline__ bool inv2_scaled(const InvLane2<EXT, NS>& st)
 // dd: the chain values of this step as they enter the products (0 while scaled).
 // SPT: the spin values e^l_{n,|s_j|} of this step are svt[j], read from the
 // spin tables' scaled rows, instead of chains.
-template <bool EXT, bool INJ, int NS, bool SPT = false>
+// CHK: the exponent-extended state is checked; past the chain starts, once no
+// lane of the wave holds a scaled chain, the steps run without the checks.
+template <bool EXT, bool INJ, int NS, bool SPT = false, bool CHK = EXT>
 __device__ __forceinline__ void inv2_core_d(InvLane2<EXT, NS>& st, int l, int lstart, double nd, const double2& c0,
                                             const double2& c1, const double2 (&cs)[NS], double rs,
                                             double (&pr)[2][NS], double (&dd)[2], bool& anyscaled,
@@ -802,13 +817,13 @@ __device__ __forceinline__ void inv2_core_d(InvLane2<EXT, NS>& st, int l, int ls
             sv[j] = svt[j];
         } else {
             sv[j] = st.sc[j];
-            if (EXT) sv[j] = (st.ks[j] == 0) ? sv[j] : 0.0;
+            if (CHK) sv[j] = (st.ks[j] == 0) ? sv[j] : 0.0;
         }
     }
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         double d = st.dc[c];
-        if (EXT) d = (st.k[c] == 0) ? d : 0.0;
+        if (CHK) d = (st.k[c] == 0) ? d : 0.0;
         dd[c] = d;
 #pragma unroll
         for (int j = 0; j < NS; ++j) pr[c][j] = d * sv[j];
@@ -835,7 +850,7 @@ __device__ __forceinline__ void inv2_core_d(InvLane2<EXT, NS>& st, int l, int ls
             st.sc[j] = sn;
         }
     }
-    if (EXT && anyscaled) {
+    if (CHK && anyscaled) {
 #pragma unroll
         for (int c = 0; c < 2; ++c)
             if (st.k[c] > 0 && fabs(st.dc[c]) > EXT_UP) { st.dc[c] *= EXT_DOWN; st.dp[c] *= EXT_DOWN; st.k[c] -= 1; }
@@ -857,13 +872,13 @@ __device__ __forceinline__ void inv2_core(InvLane2<EXT, NS>& st, int l, int lsta
     inv2_core_d<EXT, INJ, NS>(st, l, lstart, nd, c0, c1, cs, rs, pr, dd, anyscaled);
 }
 
-template <bool EXT, bool INJ, bool RL>
+template <bool EXT, bool INJ, bool RL, bool CHK = EXT>
 __device__ __forceinline__ void inv2_step(InvLane2<EXT>& st, int l, int lstart, double nd, const InvS2& u, double rs,
                                           double sv, bool& anyscaled)
 {
     double pr[2][1], dd[2];
     const double2 cs[1] = {u.cs};
-    inv2_core_d<EXT, INJ, 1, true>(st, l, lstart, nd, u.c0, u.c1, cs, rs, pr, dd, anyscaled, &sv);
+    inv2_core_d<EXT, INJ, 1, true, CHK>(st, l, lstart, nd, u.c0, u.c1, cs, rs, pr, dd, anyscaled, &sv);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const double4 f = c ? u.f1 : u.f0;
@@ -891,27 +906,40 @@ __device__ __forceinline__ void inv2_phase(InvLane2<EXT>& st, int jfrom, int jla
 {
     const int jr = lend >> 1;   // last pair whose factors exist
     InvR rB;
-    auto half = [&](int l, const InvR& rc) {   // steps l (in A) and l+1 (in B)
+    auto halfc = [&](int l, const InvR& rc, auto chk) {   // steps l (in A) and l+1 (in B)
+        constexpr bool C = decltype(chk)::value;
         wait_scalar(uA.f0.x);
         __builtin_amdgcn_sched_barrier(0);
         inv2_load(uB, rows, l + 1);
         svB = svb[(size_t)(l + 1) * L];
         __builtin_amdgcn_sched_barrier(0);
-        inv2_step<EXT, INJ, RL>(st, l, lstart, nd, uA, rc.a.x * rc.b.x, svA, anyscaled);
+        inv2_step<EXT, INJ, RL, C>(st, l, lstart, nd, uA, rc.a.x * rc.b.x, svA, anyscaled);
         wait_scalar(uB.f0.x);
         __builtin_amdgcn_sched_barrier(0);
         const int l2 = min(l + 2, lend);
         inv2_load(uA, rows, l2);
         svA = svb[(size_t)l2 * L];
         __builtin_amdgcn_sched_barrier(0);
-        inv2_step<EXT, INJ, RL>(st, l + 1, lstart, nd, uB, rc.a.y * rc.b.y, svB, anyscaled);
+        inv2_step<EXT, INJ, RL, C>(st, l + 1, lstart, nd, uB, rc.a.y * rc.b.y, svB, anyscaled);
     };
+    auto half = [&](int l, const InvR& rc) { halfc(l, rc, std::integral_constant<bool, EXT>()); };
     if constexpr (EXT) {
         // the exponent-extended variant keeps one pair per iteration: unrolled,
-        // it needs more registers than its wave budget leaves
-        for (int j = jfrom; j <= jlast; ++j) {
+        // it needs more registers than its wave budget leaves.  Past the chain
+        // starts no chain becomes scaled again: once none is (anyscaled is
+        // uniform over the wave), the rest runs unchecked.
+        int j = jfrom;
+        if constexpr (!INJ) {
+            for (; j <= jlast && anyscaled; ++j) {
+                rB = inv_load_r(Rt, ne, min(j + 1, jr));
+                halfc(2 * j, r, std::true_type());
+                r = rB;
+            }
+        }
+        for (; j <= jlast; ++j) {
             rB = inv_load_r(Rt, ne, min(j + 1, jr));
-            half(2 * j, r);
+            if constexpr (INJ) halfc(2 * j, r, std::true_type());
+            else halfc(2 * j, r, std::false_type());
             r = rB;
         }
     } else {
@@ -1203,13 +1231,13 @@ __device__ __forceinline__ double4 f_load(__amdgpu_buffer_rsrc_t rs, unsigned op
 }
 
 // PAR: parity of l (the transposed sums' degree signs).
-template <bool EXT, bool INJ, bool RL, bool SNEG, bool SPT, int PAR>
+template <bool EXT, bool INJ, bool RL, bool SNEG, bool SPT, int PAR, bool CHK = EXT>
 __device__ __forceinline__ void inv3_step(InvLane3<EXT>& st, int l, int lstart, double nd, const InvS2& u,
                                           const double4& g, double rs, double sv, bool& anyscaled)
 {
     double pr[2][1], dd[2];
     const double2 cs[1] = {u.cs};
-    inv2_core_d<EXT, INJ, 1, SPT>(st.b, l, lstart, nd, u.c0, u.c1, cs, rs, pr, dd, anyscaled, &sv);
+    inv2_core_d<EXT, INJ, 1, SPT, CHK>(st.b, l, lstart, nd, u.c0, u.c1, cs, rs, pr, dd, anyscaled, &sv);
     constexpr double sgp = (PAR && !SNEG) ? -1.0 : 1.0;   // sp(l)
     constexpr double sgm = (PAR && SNEG) ? -1.0 : 1.0;    // sm(l)
 #pragma unroll
@@ -1244,7 +1272,8 @@ __device__ __forceinline__ void inv3_phase(InvLane3<EXT>& st, int jfrom, int jla
 {
     const int jr = lend >> 1;   // last pair whose factors exist
     InvR rB;
-    auto half = [&](int l, const InvR& rc) {   // steps l (in A) and l+1 (in B)
+    auto half = [&](int l, const InvR& rc, auto chk) {   // steps l (in A) and l+1 (in B)
+        constexpr bool C = decltype(chk)::value;
         wait_scalar(uA.f0.x);
         __builtin_amdgcn_sched_barrier(0);
         inv2_load(uB, rows, l + 1);
@@ -1252,7 +1281,7 @@ __device__ __forceinline__ void inv3_phase(InvLane3<EXT>& st, int jfrom, int jla
         gB = f_load<RL>(frs, op, n32);
         if (SPT) svB = svb[(size_t)(l + 1) * L];
         __builtin_amdgcn_sched_barrier(0);
-        inv3_step<EXT, INJ, RL, SNEG, SPT, 0>(st, l, lstart, nd, uA, gA, rc.a.x * rc.b.x, svA, anyscaled);
+        inv3_step<EXT, INJ, RL, SNEG, SPT, 0, C>(st, l, lstart, nd, uA, gA, rc.a.x * rc.b.x, svA, anyscaled);
         wait_scalar(uB.f0.x);
         __builtin_amdgcn_sched_barrier(0);
         const int l2 = min(l + 2, lend);
@@ -1261,12 +1290,28 @@ __device__ __forceinline__ void inv3_phase(InvLane3<EXT>& st, int jfrom, int jla
         gA = f_load<RL>(frs, op, n32);
         if (SPT) svA = svb[(size_t)l2 * L];
         __builtin_amdgcn_sched_barrier(0);
-        inv3_step<EXT, INJ, RL, SNEG, SPT, 1>(st, l + 1, lstart, nd, uB, gB, rc.a.y * rc.b.y, svB, anyscaled);
+        inv3_step<EXT, INJ, RL, SNEG, SPT, 1, C>(st, l + 1, lstart, nd, uB, gB, rc.a.y * rc.b.y, svB, anyscaled);
     };
-    for (int j = jfrom; j <= jlast; ++j) {
-        rB = inv_load_r(Rt, ne, min(j + 1, jr));
-        half(2 * j, r);
-        r = rB;
+    int j = jfrom;
+    if constexpr (EXT && !INJ) {
+        // past the chain starts: checked while a chain of the wave is scaled
+        // (anyscaled is uniform), unchecked after
+        for (; j <= jlast && anyscaled; ++j) {
+            rB = inv_load_r(Rt, ne, min(j + 1, jr));
+            half(2 * j, r, std::true_type());
+            r = rB;
+        }
+        for (; j <= jlast; ++j) {
+            rB = inv_load_r(Rt, ne, min(j + 1, jr));
+            half(2 * j, r, std::false_type());
+            r = rB;
+        }
+    } else {
+        for (; j <= jlast; ++j) {
+            rB = inv_load_r(Rt, ne, min(j + 1, jr));
+            half(2 * j, r, std::integral_constant<bool, EXT>());
+            r = rB;
+        }
     }
 }
 
@@ -1507,15 +1552,16 @@ __device__ __forceinline__ void fwd_mix_load_sv(SvPairF<NS>& sv, const double* c
     }
 }
 
-template <bool EXT, int NS>
+template <bool EXT, int NS, bool CHK = EXT>
 __device__ __forceinline__ double fwd_chain_value(const FwdLane<2, EXT, NS>& st, int c)
 {
     double d = st.dc[c];
-    if (EXT) d = (st.k[c] == 0) ? d : 0.0;
+    if (CHK) d = (st.k[c] == 0) ? d : 0.0;
     return d;
 }
 
-template <bool EXT, bool INJ, int G, int NS, bool SPT>
+// CHK: the exponent-extended state is checked (as in fwd_advance).
+template <bool EXT, bool INJ, int G, int NS, bool SPT, bool CHK = EXT>
 __device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT, NS>& st, v4f (&acc)[2][G], int k, int l, int mb,
                                              const SpinSet<NS>& as, const MixMaps& maps,
                                              const float* __restrict__ win, int comp, const FwdR& r,
@@ -1526,26 +1572,26 @@ __device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT, NS>& st, v4f (&acc)
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
         if constexpr (SPT) {
-            k1[0][j] = (float)(fwd_chain_value<EXT, NS>(st, 0) * sv.v[j].x);
-            k1[1][j] = (float)(fwd_chain_value<EXT, NS>(st, 1) * sv.v[j].x);
+            k1[0][j] = (float)(fwd_chain_value<EXT, NS, CHK>(st, 0) * sv.v[j].x);
+            k1[1][j] = (float)(fwd_chain_value<EXT, NS, CHK>(st, 1) * sv.v[j].x);
         } else {
-            k1[0][j] = (float)fwd_product<2, EXT, NS>(st, 0, j);
-            k1[1][j] = (float)fwd_product<2, EXT, NS>(st, 1, j);
+            k1[0][j] = (float)fwd_product<2, EXT, NS, CHK>(st, 0, j);
+            k1[1][j] = (float)fwd_product<2, EXT, NS, CHK>(st, 1, j);
         }
     }
-    fwd_advance<2, EXT, NS, SPT>(st, mb, as, r.hi.y * r.lo.x, anyscaled);
+    fwd_advance<2, EXT, NS, SPT, CHK>(st, mb, as, r.hi.y * r.lo.x, anyscaled);
     fwd_inject<2, EXT, INJ, NS, SPT>(st, 2 * k, l, anyscaled);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
         if constexpr (SPT) {
-            k0[0][j] = (float)(fwd_chain_value<EXT, NS>(st, 0) * sv.v[j].y);
-            k0[1][j] = (float)(fwd_chain_value<EXT, NS>(st, 1) * sv.v[j].y);
+            k0[0][j] = (float)(fwd_chain_value<EXT, NS, CHK>(st, 0) * sv.v[j].y);
+            k0[1][j] = (float)(fwd_chain_value<EXT, NS, CHK>(st, 1) * sv.v[j].y);
         } else {
-            k0[0][j] = (float)fwd_product<2, EXT, NS>(st, 0, j);
-            k0[1][j] = (float)fwd_product<2, EXT, NS>(st, 1, j);
+            k0[0][j] = (float)fwd_product<2, EXT, NS, CHK>(st, 0, j);
+            k0[1][j] = (float)fwd_product<2, EXT, NS, CHK>(st, 1, j);
         }
     }
-    fwd_advance<2, EXT, NS, SPT>(st, mb, as, r.hi.x * r.lo.y, anyscaled);
+    fwd_advance<2, EXT, NS, SPT, CHK>(st, mb, as, r.hi.x * r.lo.y, anyscaled);
     const int off = 2 * k - WIN * (k / (WIN / 2));   // n = 2k within its window
 #pragma unroll
     for (int b = 0; b < G; ++b) {
@@ -1563,8 +1609,10 @@ __device__ __forceinline__ void fwd_mix_pair(FwdLane<2, EXT, NS>& st, v4f (&acc)
 // on entering window q the window loaded one window earlier is stored to LDS and
 // window q-1 requested; the pairs of a window then run two at a time with the
 // 1/sqrt factors alternating between the A and B register sets (A holds pair k
-// on entry and on return).
-template <bool EXT, bool INJ, int G, int NS, bool SPT>
+// on entry and on return).  EXIT: return before entering a window once no chain
+// of the wave is scaled (k then names the next pair; the caller continues
+// unchecked, CHK = false).
+template <bool EXT, bool INJ, int G, int NS, bool SPT, bool CHK = EXT, bool EXIT = false>
 __device__ __forceinline__ void fwd_mix_run(FwdLane<2, EXT, NS>& st, v4f (&acc)[2][G], const FwdSeg& g, int& k, int kto,
                                             int l, int le, int mb, const SpinSet<NS>& as, const double* __restrict__ Rt,
                                             const double* const (&svl)[NS], int L, float* __restrict__ win,
@@ -1576,6 +1624,9 @@ __device__ __forceinline__ void fwd_mix_run(FwdLane<2, EXT, NS>& st, v4f (&acc)[
     FwdR rB;
     SvPairF<NS> sB;
     while (k >= kto) {
+        if constexpr (EXIT) {
+            if (!anyscaled) return;
+        }
         if (k == g.ktop || (k % PW) == PW - 1) {       // entering window k / PW
             win_store<2 * G>(win, nxt.v, lane);
             if (k / PW > g.klo / PW) fwd_win_load<G>(nxt, maps, mb, k / PW - 1, lane);
@@ -1584,15 +1635,15 @@ __device__ __forceinline__ void fwd_mix_run(FwdLane<2, EXT, NS>& st, v4f (&acc)[
         for (; k > kw; k -= 2) {
             rB = fwd_load_r(Rt, le, max(k - 1, 0));
             fwd_mix_load_sv<SPT>(sB, svl, L, max(k - 1, 0));
-            fwd_mix_pair<EXT, INJ, G, NS, SPT>(st, acc, k, l, mb, as, maps, win, comp, rA, sA, anyscaled);
+            fwd_mix_pair<EXT, INJ, G, NS, SPT, CHK>(st, acc, k, l, mb, as, maps, win, comp, rA, sA, anyscaled);
             rA = fwd_load_r(Rt, le, max(k - 2, 0));
             fwd_mix_load_sv<SPT>(sA, svl, L, max(k - 2, 0));
-            fwd_mix_pair<EXT, INJ, G, NS, SPT>(st, acc, k - 1, l, mb, as, maps, win, comp, rB, sB, anyscaled);
+            fwd_mix_pair<EXT, INJ, G, NS, SPT, CHK>(st, acc, k - 1, l, mb, as, maps, win, comp, rB, sB, anyscaled);
         }
         if (k == kw) {                                 // odd pair left in the window
             rB = fwd_load_r(Rt, le, max(k - 1, 0));
             fwd_mix_load_sv<SPT>(sB, svl, L, max(k - 1, 0));
-            fwd_mix_pair<EXT, INJ, G, NS, SPT>(st, acc, k, l, mb, as, maps, win, comp, rA, sA, anyscaled);
+            fwd_mix_pair<EXT, INJ, G, NS, SPT, CHK>(st, acc, k, l, mb, as, maps, win, comp, rA, sA, anyscaled);
             rA = rB;
             sA = sB;
             --k;
@@ -1615,8 +1666,17 @@ __device__ __forceinline__ void fwd_mix_segment(FwdLane<2, EXT, NS>& st, v4f (&a
     int k = g.ktop;
     fwd_mix_run<EXT, true, G, NS, SPT>(st, acc, g, k, max(g.kA, g.klo), l, le, mb, as, Rt, svl, L, win, maps, lane,
                                        nxt, rA, sA, anyscaled);   // pairs with lane starts
-    fwd_mix_run<EXT, false, G, NS, SPT>(st, acc, g, k, g.klo, l, le, mb, as, Rt, svl, L, win, maps, lane, nxt, rA, sA,
-                                        anyscaled);
+    if constexpr (EXT) {
+        // past the chain starts: checked while a chain of the wave is scaled,
+        // unchecked from the next window on
+        fwd_mix_run<EXT, false, G, NS, SPT, true, true>(st, acc, g, k, g.klo, l, le, mb, as, Rt, svl, L, win, maps,
+                                                        lane, nxt, rA, sA, anyscaled);
+        fwd_mix_run<EXT, false, G, NS, SPT, false>(st, acc, g, k, g.klo, l, le, mb, as, Rt, svl, L, win, maps, lane,
+                                                   nxt, rA, sA, anyscaled);
+    } else {
+        fwd_mix_run<EXT, false, G, NS, SPT>(st, acc, g, k, g.klo, l, le, mb, as, Rt, svl, L, win, maps, lane, nxt, rA,
+                                            sA, anyscaled);
+    }
 }
 
 // Forward contraction of a group of up to G maps with at most NS different |s|
@@ -1788,7 +1848,7 @@ __device__ __forceinline__ void inv2m_load_sv(SvPair<NS>& sv, const double* cons
     for (int q = 0; q < NS; ++q) sv.v[q] = make_double2(svl[q][(size_t)(2 * j) * L], svl[q][(size_t)(2 * j + 1) * L]);
 }
 
-template <bool EXT, bool INJ, int G, int NS>
+template <bool EXT, bool INJ, int G, int NS, bool CHK = EXT>
 __device__ __forceinline__ void inv2m_pair(InvLane2<EXT, NS>& st, v4f (&acc)[2][G], int j, int lstart, double nd,
                                            const InvC2<NS>& u, const InvR& r, const SvPair<NS>& sp,
                                            const MixMaps& maps, const float* __restrict__ win, int comp,
@@ -1804,10 +1864,10 @@ __device__ __forceinline__ void inv2m_pair(InvLane2<EXT, NS>& st, v4f (&acc)[2][
         s0[q] = sp.v[q].x;
         s1[q] = sp.v[q].y;
     }
-    inv2_core_d<EXT, INJ, NS, true>(st, l, lstart, nd, make_double2(u.c0.x, u.c0.y), make_double2(u.c1.x, u.c1.y),
-                                    cs0, r.a.x * r.b.x, p0, dd, anyscaled, s0);
-    inv2_core_d<EXT, INJ, NS, true>(st, l + 1, lstart, nd, make_double2(u.c0.z, u.c0.w), make_double2(u.c1.z, u.c1.w),
-                                    cs1, r.a.y * r.b.y, p1, dd, anyscaled, s1);
+    inv2_core_d<EXT, INJ, NS, true, CHK>(st, l, lstart, nd, make_double2(u.c0.x, u.c0.y),
+                                         make_double2(u.c1.x, u.c1.y), cs0, r.a.x * r.b.x, p0, dd, anyscaled, s0);
+    inv2_core_d<EXT, INJ, NS, true, CHK>(st, l + 1, lstart, nd, make_double2(u.c0.z, u.c0.w),
+                                         make_double2(u.c1.z, u.c1.w), cs1, r.a.y * r.b.y, p1, dd, anyscaled, s1);
     const int off = l - WIN * (j / (WIN / 2));   // degree l within its window
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -1828,8 +1888,9 @@ __device__ __forceinline__ void inv2m_pair(InvLane2<EXT, NS>& st, v4f (&acc)[2][
 // on entering window q the window loaded one window earlier is stored to LDS and
 // window q+1 requested; the pairs of a window then run two at a time with the
 // uniform data and 1/sqrt factors alternating between the A and B register sets
-// (A holds pair j on entry and on return).
-template <bool EXT, bool INJ, int G, int NS>
+// (A holds pair j on entry and on return).  EXIT: return before entering a
+// window once no chain of the wave is scaled (the caller continues unchecked).
+template <bool EXT, bool INJ, int G, int NS, bool CHK = EXT, bool EXIT = false>
 __device__ __forceinline__ void inv2m_run(InvLane2<EXT, NS>& st, v4f (&acc)[2][G], const InvSeg& g, int& j, int jto,
                                           int jend, int lstart, int ne, double nd, int m0, const Inv2Rows& rows,
                                           const double* __restrict__ Rt, const double* const (&svl)[NS], int L,
@@ -1842,6 +1903,9 @@ __device__ __forceinline__ void inv2m_run(InvLane2<EXT, NS>& st, v4f (&acc)[2][G
     InvR rB;
     SvPair<NS> sB;
     while (j <= jto) {
+        if constexpr (EXIT) {
+            if (!anyscaled) return;
+        }
         if (j == g.jfrom || (j % PW) == 0) {          // entering window j / PW
             win_store<2 * G>(win, nxt.v, lane);
             if (j / PW < g.jlast / PW) inv2m_win_load<G>(nxt, maps, m0, j / PW + 1, lane);
@@ -1852,19 +1916,19 @@ __device__ __forceinline__ void inv2m_run(InvLane2<EXT, NS>& st, v4f (&acc)[2][G
             inv2m_load_c(uB, rows, min(j + 1, jend));
             rB = inv_load_r(Rt, ne, min(j + 1, jend));
             inv2m_load_sv(sB, svl, L, min(j + 1, jend));
-            inv2m_pair<EXT, INJ, G, NS>(st, acc, j, lstart, nd, uA, rA, sA, maps, win, comp, anyscaled);
+            inv2m_pair<EXT, INJ, G, NS, CHK>(st, acc, j, lstart, nd, uA, rA, sA, maps, win, comp, anyscaled);
             wait_scalar(uB.c0.x);
             inv2m_load_c(uA, rows, min(j + 2, jend));
             rA = inv_load_r(Rt, ne, min(j + 2, jend));
             inv2m_load_sv(sA, svl, L, min(j + 2, jend));
-            inv2m_pair<EXT, INJ, G, NS>(st, acc, j + 1, lstart, nd, uB, rB, sB, maps, win, comp, anyscaled);
+            inv2m_pair<EXT, INJ, G, NS, CHK>(st, acc, j + 1, lstart, nd, uB, rB, sB, maps, win, comp, anyscaled);
         }
         if (j == jw) {                                 // odd pair left in the window
             wait_scalar(uA.c0.x);
             inv2m_load_c(uB, rows, min(j + 1, jend));
             rB = inv_load_r(Rt, ne, min(j + 1, jend));
             inv2m_load_sv(sB, svl, L, min(j + 1, jend));
-            inv2m_pair<EXT, INJ, G, NS>(st, acc, j, lstart, nd, uA, rA, sA, maps, win, comp, anyscaled);
+            inv2m_pair<EXT, INJ, G, NS, CHK>(st, acc, j, lstart, nd, uA, rA, sA, maps, win, comp, anyscaled);
             uA = uB;
             rA = rB;
             sA = sB;
@@ -1891,8 +1955,17 @@ __device__ __forceinline__ void inv2m_segment(InvLane2<EXT, NS>& st, v4f (&acc)[
     int j = g.jfrom;
     inv2m_run<EXT, true, G, NS>(st, acc, g, j, min(g.jA, g.jlast), jend, lstart, ne, nd, m0, rows, Rt, svl, L, win,
                                 maps, lane, nxt, uA, rA, sA, anyscaled);   // pairs with chain starts
-    inv2m_run<EXT, false, G, NS>(st, acc, g, j, g.jlast, jend, lstart, ne, nd, m0, rows, Rt, svl, L, win, maps, lane,
-                                 nxt, uA, rA, sA, anyscaled);
+    if constexpr (EXT) {
+        // past the chain starts: checked while a chain of the wave is scaled,
+        // unchecked from the next window on
+        inv2m_run<EXT, false, G, NS, true, true>(st, acc, g, j, g.jlast, jend, lstart, ne, nd, m0, rows, Rt, svl, L,
+                                                 win, maps, lane, nxt, uA, rA, sA, anyscaled);
+        inv2m_run<EXT, false, G, NS, false>(st, acc, g, j, g.jlast, jend, lstart, ne, nd, m0, rows, Rt, svl, L, win,
+                                            maps, lane, nxt, uA, rA, sA, anyscaled);
+    } else {
+        inv2m_run<EXT, false, G, NS>(st, acc, g, j, g.jlast, jend, lstart, ne, nd, m0, rows, Rt, svl, L, win, maps,
+                                     lane, nxt, uA, rA, sA, anyscaled);
+    }
 }
 
 // LDS floats per wave slot: its window, later its partial sums (a v4f per
