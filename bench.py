@@ -61,6 +61,60 @@ def progress(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def oracle_configs(oracle, mwsynth):
+    """The oracle on the host cores for the workloads other than the L=512 map:
+    whole round trips of the L=64 map for at least 5 s; for the 256-map batch one
+    round trip per (L, spin) class, scaled by the class counts; one round trip of
+    the L=2048 real map (inverse and forward timed apart); for the 32-map
+    gradient 2 A^H (A x - y), one map's forward and forward adjoint, times 32."""
+    out = {}
+    w = mwsynth.workload_scalar_l64()
+    t, n = time.perf_counter(), 0
+    while time.perf_counter() - t < 5.0:
+        oracle.forward(oracle.inverse(w["flm"], w["L"], w["s"]), w["L"], w["s"])
+        n += 1
+    dt = time.perf_counter() - t
+    out["scalar_l64"] = {"value": n / dt, "unit": "round trips/s", "sample": "%d round trips, %.1f s" % (n, dt)}
+    progress("oracle: L=64 done")
+    maps = mwsynth.workload_batch_mixed()
+    cls = {}
+    for m in maps:
+        cls.setdefault((m["L"], m["s"]), []).append(m)
+    total = 0.0
+    for (L, s), ms in sorted(cls.items()):
+        t = time.perf_counter()
+        oracle.forward(oracle.inverse(ms[0]["flm"], L, s), L, s)
+        dt = time.perf_counter() - t
+        total += dt * len(ms)
+        progress("oracle: batch class L=%d s=%d, %.2f s x %d maps" % (L, s, dt, len(ms)))
+    out["batch256"] = {"value": len(maps) / total, "unit": "map round trips/s",
+                       "sample": "one round trip per (L, spin) class (%d classes), scaled by the class counts: "
+                                 "%.0f s for the batch" % (len(cls), total)}
+    w = mwsynth.workload_real_l2048()
+    t = time.perf_counter()
+    x = oracle.inverse(w["flm"], w["L"], w["s"])
+    ti = time.perf_counter() - t
+    progress("oracle: L=2048 inverse %.1f s" % ti)
+    t = time.perf_counter()
+    oracle.forward(x, w["L"], w["s"])
+    tf = time.perf_counter() - t
+    progress("oracle: L=2048 forward %.1f s" % tf)
+    out["real_l2048"] = {"value": 1.0 / (ti + tf), "unit": "round trips/s",
+                         "sample": "1 round trip: inverse %.1f s, forward %.1f s" % (ti, tf)}
+    w = mwsynth.workload_grad_l256()
+    L, s = w["L"], w["s"]
+    t = time.perf_counter()
+    r = oracle.forward(w["x"][0], L, s) - w["y"]
+    oracle.forward_adjoint(2.0 * r, L, s)
+    dt = time.perf_counter() - t
+    out["grad_l256"] = {"value": 1.0 / (dt * w["x"].shape[0]), "unit": "gradients/s (all 32 maps)",
+                        "sample": "one map's forward and forward adjoint, %.2f s, times %d" % (dt, w["x"].shape[0])}
+    progress("oracle: gradient done")
+    for v in out.values():
+        v.update({"cores": oracle.max_threads(), "kind": "oracle"})
+    return out
+
+
 def rel(a, b):
     import numpy as np
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
@@ -225,6 +279,9 @@ def main():
                     help="minimum CPU time of the oracle baseline sample (whole round trips)")
     ap.add_argument("--cpu-1core", action="store_true",
                     help="also time one oracle round trip on one host core (about 100 s at L=512)")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="also time the oracle on the host cores for the other workloads (L=64 map, "
+                         "256-map batch, L=2048 real map, 32-map gradient; several minutes)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed work, negate a float64 buffer of this many MiB once "
                          "(a plain read+write kernel of known size, for HBM counter calibration)")
@@ -377,6 +434,8 @@ def main():
             oracle.set_threads(result["cpu_baseline"]["cores"])
             result["cpu_baseline_1core"] = {"value": 1.0 / dt1, "unit": "round trips/s", "cores": 1,
                                             "kind": "oracle", "sample": "1 round trip, %.1f s" % dt1}
+        if args.cpu_configs:
+            result["cpu_baseline_configs"] = oracle_configs(oracle, mwsynth)
         result["max_rel_err_vs_oracle"] = {"inverse_map": rel(x_h, xo), "forward_coeffs": rel(back_h, fo),
                                            "forward_coeffs_per_degree": rel_per_degree(back_h, fo, L)}
         result["mixed"]["max_rel_err_vs_oracle"] = {"inverse_map": rel(x32_h, xo),
