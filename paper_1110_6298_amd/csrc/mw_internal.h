@@ -32,7 +32,8 @@ constexpr int INV_TRI_MIN_L = 1024;
 // Real maps from this band-limit up read their spin values from the scaled spin
 // rows in the triangle kernel (below, they run a third chain).
 constexpr int INV_TRI_SPT_MIN_L = 1024;
-// The FP64 forward reads its spin row from the spin table from this band-limit up.
+// The forward contractions (FP64 and mixed) read their spin rows from the spin
+// tables from this band-limit up (below, they run them as chains).
 constexpr int FWD_SPT_MIN_L = 1024;
 // Test hook (mw_profile_inverse_triangle): 1 runs every FP64 inverse on the
 // triangle kernel.
