@@ -40,6 +40,19 @@ __device__ __forceinline__ int Pr(int i)
     else return i + i / RB;
 }
 
+// Entries b + t*S (t = 0, 1, ...) of a pass sit at x + Pr(b) + t*S whenever
+// pr_linear(S): for RB = 8, when S is a multiple of 64 (the step leaves the row's
+// low three bits, and so the XOR, unchanged, and does not touch the column
+// bits).  One swizzled base per thread then serves all RB accesses with
+// constant offsets.  (The padded RB = 16 layout is linear too for S a multiple
+// of 16, but there the extra live base registers cost the 512-thread kernels
+// more spills than the address arithmetic they save.)
+template <int RB>
+__device__ __forceinline__ bool pr_linear(int S)
+{
+    return RB == 8 && (S & 63) == 0;
+}
+
 // Block-wide loop over j = threadIdx.x + q*blockDim.x < n (n <= 16*blockDim.x):
 // the global loads ld(j) of eight consecutive q are all issued before any result
 // is used by use(j, value), so a thread waits for memory twice, not 16 times.
@@ -233,8 +246,14 @@ __device__ __forceinline__ void last_pass(double2* x, int N, int p, const double
         const int i = threadIdx.x + q * blockDim.x;
         if (i < NB) {
             const int k = i & (p - 1);
+            if (RB == 8 && pr_linear<RB>(NB)) {
+                const double2* xb = x + Pr<RB>(i);
 #pragma unroll
-            for (int t = 0; t < R; ++t) u[q * R + t] = x[Pr<RB>(i + t * NB)];
+                for (int t = 0; t < R; ++t) u[q * R + t] = xb[t * NB];
+            } else {
+#pragma unroll
+                for (int t = 0; t < R; ++t) u[q * R + t] = x[Pr<RB>(i + t * NB)];
+            }
             double2 w = wl[q];
             if (DIR > 0) w = cconj(w);
             (void)k;
@@ -260,6 +279,10 @@ __device__ __forceinline__ void last_pass(double2* x, int N, int p, const double
             if constexpr (!std::is_same_v<Store, PlainStore>) {
 #pragma unroll
                 for (int t = 0; t < R; ++t) st(j + t * p, u[q * R + t]);
+            } else if (RB == 8 && pr_linear<RB>(p)) {
+                double2* xb = x + Pr<RB>(j);
+#pragma unroll
+                for (int t = 0; t < R; ++t) xb[t * p] = post ? cmul(u[q * R + t], post[j + t * p]) : u[q * R + t];
             } else if (post) {
 #pragma unroll
                 for (int t = 0; t < R; ++t) x[Pr<RB>(j + t * p)] = cmul(u[q * R + t], post[j + t * p]);
@@ -312,6 +335,33 @@ __device__ __forceinline__ FftTw<RB> fft_twiddles(int N, int logN, const double2
     return T;
 }
 
+// The RB entries b + t*S of a thread's butterfly, read from or written to LDS
+// (constant offsets from one swizzled base where pr_linear(S)).
+template <int RB>
+__device__ __forceinline__ void lds_read(double2 (&u)[RB], const double2* x, int b, int S)
+{
+    if (pr_linear<RB>(S)) {
+        const double2* xb = x + Pr<RB>(b);
+#pragma unroll
+        for (int t = 0; t < RB; ++t) u[t] = xb[t * S];
+    } else {
+#pragma unroll
+        for (int t = 0; t < RB; ++t) u[t] = x[Pr<RB>(b + t * S)];
+    }
+}
+template <int RB>
+__device__ __forceinline__ void lds_write(double2* x, const double2 (&u)[RB], int b, int S)
+{
+    if (pr_linear<RB>(S)) {
+        double2* xb = x + Pr<RB>(b);
+#pragma unroll
+        for (int t = 0; t < RB; ++t) xb[t * S] = u[t];
+    } else {
+#pragma unroll
+        for (int t = 0; t < RB; ++t) x[Pr<RB>(b + t * S)] = u[t];
+    }
+}
+
 // Block-wide in-place FFT of length N = 2^logN (16 <= N <= 8192) held in LDS
 // at padded positions Pr<RB>(j): Stockham passes of radix RB (16 or 8), one
 // butterfly per thread in registers, then one radix-2/4/8 pass for the
@@ -355,6 +405,8 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const Fft
                 if (s == 0) {
 #pragma unroll
                     for (int t = 0; t < RB; ++t) u[t] = ld.f(t, i + t * NB);
+                } else if constexpr (RB == 8) {
+                    lds_read<RB>(u, x, i, NB);
                 } else {
 #pragma unroll
                     for (int t = 0; t < RB; ++t) u[t] = x[Pr<RB>(i + t * NB)];
@@ -362,6 +414,8 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const Fft
             } else if (!plain_ld && s == 0) {
 #pragma unroll
                 for (int t = 0; t < RB; ++t) u[t] = ld(i + t * NB);
+            } else if constexpr (RB == 8) {
+                lds_read<RB>(u, x, i, NB);
             } else {
 #pragma unroll
                 for (int t = 0; t < RB; ++t) u[t] = x[Pr<RB>(i + t * NB)];
@@ -380,9 +434,15 @@ __device__ __forceinline__ void block_fft(double2* x, int N, int logN, const Fft
             if (!plain && r == 0 && s == np - 1) {   // the last pass: outputs through st
 #pragma unroll
                 for (int t = 0; t < RB; ++t) st(j + t * p, u[t]);
+            } else if constexpr (RB == 8) {
+                if (fold_post) {
+#pragma unroll
+                    for (int t = 0; t < RB; ++t) u[t] = cmul(u[t], pv[t]);
+                }
+                lds_write<RB>(x, u, j, p);
             } else if (fold_post) {
 #pragma unroll
-                for (int t = 0; t < RB; ++t) x[Pr<RB>(j + t * p)] = cmul(u[t], RB == 8 ? pv[t] : post[j + t * p]);
+                for (int t = 0; t < RB; ++t) x[Pr<RB>(j + t * p)] = cmul(u[t], post[j + t * p]);
             } else {
 #pragma unroll
                 for (int t = 0; t < RB; ++t) x[Pr<RB>(j + t * p)] = u[t];
@@ -1266,6 +1326,8 @@ hipError_t fft_launch(const Plan& p, dim3 grid, hipStream_t st, Args... args)
         return fft_go(KS<16, false, -1>::fn(), p, 16, grid, st, args...);
     }
     switch (logn) {
+        case 7: return fft_go(KS<8, false, 7>::fn(), p, 8, grid, st, args...);
+        case 8: return fft_go(KS<8, false, 8>::fn(), p, 8, grid, st, args...);
         case 9: return fft_go(KS<8, false, 9>::fn(), p, 8, grid, st, args...);
         case 10: return fft_go(KS<8, false, 10>::fn(), p, 8, grid, st, args...);
         case 11: return fft_go(KS<8, false, 11>::fn(), p, 8, grid, st, args...);
@@ -1292,6 +1354,8 @@ hipError_t fft_launch_unsplit(const Plan& p, dim3 grid, hipStream_t st, Args... 
         return fft_go(KS<16, -1>::fn(), p, 16, grid, st, args...);
     }
     switch (logn) {
+        case 7: return fft_go(KS<8, 7>::fn(), p, 8, grid, st, args...);
+        case 8: return fft_go(KS<8, 8>::fn(), p, 8, grid, st, args...);
         case 9: return fft_go(KS<8, 9>::fn(), p, 8, grid, st, args...);
         case 10: return fft_go(KS<8, 10>::fn(), p, 8, grid, st, args...);
         case 11: return fft_go(KS<8, 11>::fn(), p, 8, grid, st, args...);
