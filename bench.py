@@ -24,8 +24,8 @@ PEAK_FP64_VALU = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 # read for a plain copy of known size (profiles/traffic_roundtrip_L512_s2.md).
 # Valid only while the kernel and plan sources are unchanged: keyed by their SHA-256.
 TRAFFIC = {
-    ("contract_inverse", 512, 2): {"bytes": 37802714, "source_sha256": "d19b76c4cae29154cb8c1342d4d175a4709746dbd6ea603e9d52b09c7452be47"},
-    ("contract_forward", 512, 2): {"bytes": 29428868, "source_sha256": "d19b76c4cae29154cb8c1342d4d175a4709746dbd6ea603e9d52b09c7452be47"},
+    ("contract_inverse", 512, 2): {"bytes": 37805630, "source_sha256": "d19b76c4cae29154cb8c1342d4d175a4709746dbd6ea603e9d52b09c7452be47"},
+    ("contract_forward", 512, 2): {"bytes": 29427290, "source_sha256": "d19b76c4cae29154cb8c1342d4d175a4709746dbd6ea603e9d52b09c7452be47"},
 }
 KERNEL_SOURCES = ("paper_1110_6298_amd/csrc/mw_contract.hip", "paper_1110_6298_amd/csrc/mw_plan.cpp")
 
